@@ -1,0 +1,252 @@
+"""Plain FP64 CPU oracle of the rotating-SAR imaging path.
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the product path may import, call or execute this
+module: only the test suite, the smoke check and the CPU-baseline leg of the benchmark do.
+It shares no code with the HIP implementation.
+
+Everything is numpy in float64 / complex128, written as the plain definitions of the paper's
+equations, vectorised over one axis at most (azimuth for whole images, pulses or taps for
+single pixels).  Notation follows the paper: N pulses per rotation, M fast-time samples,
+L FFT points, r rotation radius, f_c carrier, K chirp slope (called `slope` here to keep K for
+the tap count), F_s sampling rate, T_Start sampling start, k the wavenumber.
+
+Readings of the paper taken here (each also an explicit argument of the HIP entry points):
+  * The weight vector is applied conjugated, I = w^H y (eq. 43); the BPA coefficient applied
+    to pulse n is alpha_n exp(-j 2 k R_n), i.e. BPA's w is the steering vector of eq. 16.
+  * `round` in eq. 40 is floor(u + 1/2) (u >= 0), evaluated in float64.
+  * FFT rows outside the computed band [l_lo, l_lo + l_count) read as 0.
+  * Pulse indices wrap modulo N (the track is a closed circle, Sec. II-A).
+  * Output azimuth bins coincide with the pulse grid (A = N), so Algorithm 2's centre pulse
+    of pixel a is pulse a and a tap at offset o reads pulse (a + o) mod N.
+  * Outside the +-90 deg field of view alpha = 0 (eqs. 3-5, 8): alpha = max(R cos D - r, 0)/R_n.
+  * The residual Dirichlet phase after the range FFT (Remark 1) is not corrected.
+  * Per-pulse angle errors delta_n (data taken at phi_n + delta_n, eq. 37) and phase errors
+    psi_n enter the corrected sparse filter as s <- s exp(-j 2k (R^ - R_nom)) exp(-j psi_n).
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+TWO_PI = 2.0 * math.pi
+
+
+# ----------------------------------------------------------------------------- constants
+def wavenumber(geom) -> float:
+    """k = 2 pi (K T_Start + f_c) / c  (Sec. II-B after eq. 12, and Sec. III-D after eq. 38)."""
+    return TWO_PI * (geom.slope_hz_s * geom.t_start_s + geom.fc_hz) / geom.c_m_s
+
+
+def bins_per_metre(geom) -> float:
+    """beta such that the peak bin of a target at slant range R is round(beta R) (eq. 40):
+    beta = 2 K t_s L / c with t_s = 1/F_s."""
+    return 2.0 * geom.slope_hz_s * geom.n_fft / (geom.fs_hz * geom.c_m_s)
+
+
+def slant_range(r_t, r, dphi):
+    """Distance from a phase centre on the circle of radius r to a point at range r_t whose
+    azimuth differs by dphi (eq. 2)."""
+    return np.sqrt(r_t * r_t + r * r - 2.0 * r * r_t * np.cos(dphi))
+
+
+def visible_index_range(r_t: float, r: float, n: int) -> tuple[int, int]:
+    """[N_min, N_max] of the phase centres that see a target at (pi/2, R_t) (eqs. 4-5)."""
+    phi_v = math.acos(r / r_t)
+    step = TWO_PI / n
+    return math.ceil((math.pi / 2 - phi_v) / step), math.floor((math.pi / 2 + phi_v) / step)
+
+
+# ----------------------------------------------------------------------- range compression
+def range_compress(raw: np.ndarray, window: np.ndarray | None, n_fft: int) -> np.ndarray:
+    """Y[n, l] = sum_m h[m] y[n, m] exp(-j 2 pi l m / L), l = 0..L-1 (eq. 38), zero-padded when
+    L > M.  The window h is the input array (rectangular if None).  Uses the library FFT."""
+    y = raw.astype(np.complex128)
+    if window is not None:
+        y = y * window.astype(np.float64)[None, :]
+    return np.fft.fft(y, n=n_fft, axis=1)
+
+
+def range_compress_direct(raw: np.ndarray, window: np.ndarray | None, n_fft: int) -> np.ndarray:
+    """Literal DFT sum of eq. 38 (tiny sizes only)."""
+    n_p, m = raw.shape
+    h = np.ones(m) if window is None else window.astype(np.float64)
+    out = np.zeros((n_p, n_fft), dtype=np.complex128)
+    for n in range(n_p):
+        for l in range(n_fft):
+            acc = 0j
+            for mm in range(m):
+                acc += h[mm] * complex(raw[n, mm]) * complex(math.cos(-TWO_PI * l * mm / n_fft),
+                                                             math.sin(-TWO_PI * l * mm / n_fft))
+            out[n, l] = acc
+    return out
+
+
+# ----------------------------------------------------------------------------- sampling
+def _band(yb: np.ndarray, n: np.ndarray, l: np.ndarray) -> np.ndarray:
+    """Y_1D[n, l] read from the computed band; rows outside it read as 0."""
+    ok = (l >= 0) & (l < yb.shape[1])
+    lc = np.where(ok, l, 0)
+    return np.where(ok, yb[n, lc], 0.0)
+
+
+def sample(yb: np.ndarray, l_lo: int, n: np.ndarray, u: np.ndarray, interp: str):
+    """Range-compressed sample of pulse n at fractional bin u, and its derivative d/du.
+    nearest: Y[n, round(u)] (eq. 40 with round = floor(u + 1/2)); derivative 0.
+    linear:  (1-f) Y[n, i] + f Y[n, i+1], i = floor(u), f = u - i."""
+    if interp == "nearest":
+        l = np.floor(u + 0.5).astype(np.int64) - l_lo
+        return _band(yb, n, l), np.zeros(np.shape(u), dtype=np.complex128)
+    if interp == "linear":
+        fl = np.floor(u)
+        f = u - fl
+        i = fl.astype(np.int64) - l_lo
+        y0 = _band(yb, n, i)
+        y1 = _band(yb, n, i + 1)
+        return (1.0 - f) * y0 + f * y1, y1 - y0
+    raise ValueError(interp)
+
+
+# ----------------------------------------------------------------------- sparse filter (FFT+SAS)
+def _row_taps(geom, grid, row: int, o: int, n: np.ndarray, dphi, dpsi, yb, l_lo, interp):
+    """Sample s and its partial derivatives for range row `row`, tap offset o, pulses n."""
+    r = geom.radius_m
+    rr = grid.r0_m + row * grid.dr_m
+    beta = bins_per_metre(geom)
+    k = wavenumber(geom)
+    d0 = o * TWO_PI / geom.n_pulses
+    dl = np.zeros(n.shape) if dphi is None else dphi[n].astype(np.float64)
+    d = d0 + dl
+    r_hat = slant_range(rr, r, d)
+    s, dsdu = sample(yb, l_lo, n, beta * r_hat, interp)
+    corrected = dphi is not None or dpsi is not None
+    if corrected:
+        r_nom = slant_range(rr, r, d0)
+        ps = np.zeros(n.shape) if dpsi is None else dpsi[n].astype(np.float64)
+        rot = np.exp(-1j * 2.0 * k * (r_hat - r_nom)) * np.exp(-1j * ps)
+    else:
+        rot = np.ones(n.shape, dtype=np.complex128)
+    drdd = rr * r * np.sin(d) / r_hat
+    ds_ddelta = rot * (beta * dsdu - 1j * 2.0 * k * s) * drdd
+    return s * rot, ds_ddelta
+
+
+def sparse_filter(yb: np.ndarray, l_lo: int, geom, grid, offsets: np.ndarray, weights: np.ndarray,
+                  dphi=None, dpsi=None, interp: str = "nearest", rows=None) -> np.ndarray:
+    """Sparse-aperture azimuth filter over range-compressed data (Algorithm 2 with eq. 43):
+        I[r, a] = sum_k conj(w[r, k]) s[r, a, k],
+        s = Y_1D[n, u(R^)],  n = (a + o_k) mod N,  R^ = R(o_k 2 pi/N + delta_n)  (eq. 2),
+    u = beta R^ (eq. 40), with the delta/psi correction when either is given.
+    yb: [N, l_count] rows [l_lo, l_lo + l_count) of Y_1D.  Returns [n_rows, A] complex128."""
+    n_p = geom.n_pulses
+    assert grid.n_az == n_p
+    rows = range(grid.n_range) if rows is None else rows
+    a = np.arange(grid.n_az)
+    out = np.zeros((len(rows), grid.n_az), dtype=np.complex128)
+    for i, row in enumerate(rows):
+        for kk in range(offsets.shape[1]):
+            o = int(offsets[row, kk])
+            n = (a + o) % n_p
+            s, _ = _row_taps(geom, grid, row, o, n, dphi, dpsi, yb, l_lo, interp)
+            out[i] += np.conj(weights[row, kk]) * s
+    return out
+
+
+def sparse_filter_at(yb, l_lo, geom, grid, offsets, weights, rows, azs, dphi=None, dpsi=None,
+                     interp="nearest") -> np.ndarray:
+    """The same sum as sparse_filter, evaluated pixel by pixel at (rows[i], azs[i])."""
+    out = np.zeros(len(rows), dtype=np.complex128)
+    for i, (row, a) in enumerate(zip(rows, azs)):
+        acc = 0j
+        for kk in range(offsets.shape[1]):
+            o = int(offsets[row, kk])
+            n = np.array([(a + o) % geom.n_pulses])
+            s, _ = _row_taps(geom, grid, row, o, n, dphi, dpsi, yb, l_lo, interp)
+            acc += np.conj(weights[row, kk]) * s[0]
+        out[i] = acc
+    return out
+
+
+# ----------------------------------------------------------------------- full-aperture BPA
+def bp_terms(geom, grid, row: int, phi_a, pulse_angles):
+    """Visibility, slant range and pattern weight of every (pixel, pulse) pair of one range row:
+    D = phi_a - phi^_n, v = R cos D - r, visible iff v > 0 (eqs. 4-5),
+    R_n from eq. 2, alpha = v / R_n = cos(theta_n) (eqs. 3, 8, 15)."""
+    r = geom.radius_m
+    rr = grid.r0_m + row * grid.dr_m
+    d = np.subtract.outer(np.atleast_1d(phi_a), pulse_angles)
+    v = rr * np.cos(d) - r
+    rn = slant_range(rr, r, d)
+    vis = v > 0
+    alpha = np.where(vis, v / rn, 0.0)
+    return vis, rn, alpha
+
+
+def _angles(geom, pulse_angles):
+    if pulse_angles is None:
+        return geom.phi0_rad + TWO_PI * np.arange(geom.n_pulses) / geom.n_pulses
+    return np.asarray(pulse_angles, dtype=np.float64)
+
+
+def bp_full(yb, l_lo, geom, grid, pulse_angles=None, interp="nearest", rows=None) -> np.ndarray:
+    """Full-aperture back-projection over range-compressed data ("FFT+BPA", eq. 43 with the BPA
+    weights): I[r, a] = sum over visible n of alpha_n exp(-j 2 k R_n) Y_1D[n, u(R_n)],
+    phi_a = phi0 + 2 pi a / A, pulses at their given angles phi^_n."""
+    ang = _angles(geom, pulse_angles)
+    beta = bins_per_metre(geom)
+    k = wavenumber(geom)
+    rows = range(grid.n_range) if rows is None else rows
+    phi_a = geom.phi0_rad + TWO_PI * np.arange(grid.n_az) / grid.n_az
+    n_idx = np.arange(geom.n_pulses)
+    out = np.zeros((len(rows), grid.n_az), dtype=np.complex128)
+    for i, row in enumerate(rows):
+        vis, rn, alpha = bp_terms(geom, grid, row, phi_a, ang)          # [A, N]
+        s, _ = sample(yb, l_lo, np.broadcast_to(n_idx, rn.shape), beta * rn, interp)
+        term = alpha * np.exp(-1j * 2.0 * k * rn) * s
+        out[i] = np.where(vis, term, 0.0).sum(axis=1)
+    return out
+
+
+def bp_full_at(yb, l_lo, geom, grid, rows, azs, pulse_angles=None, interp="nearest") -> np.ndarray:
+    """bp_full evaluated pixel by pixel at (rows[i], azs[i])."""
+    ang = _angles(geom, pulse_angles)
+    beta = bins_per_metre(geom)
+    k = wavenumber(geom)
+    n_idx = np.arange(geom.n_pulses)
+    out = np.zeros(len(rows), dtype=np.complex128)
+    for i, (row, a) in enumerate(zip(rows, azs)):
+        phi_a = geom.phi0_rad + TWO_PI * a / grid.n_az
+        vis, rn, alpha = bp_terms(geom, grid, row, phi_a, ang)
+        s, _ = sample(yb, l_lo, n_idx, beta * rn[0], interp)
+        out[i] = np.where(vis[0], alpha[0] * np.exp(-1j * 2.0 * k * rn[0]) * s, 0.0).sum()
+    return out
+
+
+# ----------------------------------------------------------------------- adjoint
+def sparse_filter_grad(yb, l_lo, geom, grid, offsets, weights, grad_image, dphi=None, dpsi=None,
+                       interp="linear"):
+    """Exact derivatives of sparse_filter for a real loss, in the convention
+    g = dL/dRe(I) + j dL/dIm(I) (the same convention is returned for the complex weights):
+        grad_w[r, k]  = sum_a conj(g[r, a]) s[r, a, k]
+        grad_delta[n] = sum_{r,k} Re(conj(g) conj(w) ds/ddelta_n)
+        grad_psi[n]   = sum_{r,k} Im(conj(g) conj(w) s)
+    with a = (n - o_k) mod N, ds/ddelta = rot (beta dY/du - j 2k Y) R_r r sin(D)/R^.
+    The derivatives are those of the corrected model (delta = psi = 0 when not given)."""
+    n_p = geom.n_pulses
+    dphi = np.zeros(n_p) if dphi is None else dphi
+    dpsi = np.zeros(n_p) if dpsi is None else dpsi
+    a = np.arange(grid.n_az)
+    gw = np.zeros(weights.shape, dtype=np.complex128)
+    gd = np.zeros(n_p)
+    gp = np.zeros(n_p)
+    for row in range(grid.n_range):
+        g = grad_image[row].astype(np.complex128)
+        for kk in range(offsets.shape[1]):
+            o = int(offsets[row, kk])
+            n = (a + o) % n_p
+            s, dsd = _row_taps(geom, grid, row, o, n, dphi, dpsi, yb, l_lo, interp)
+            gw[row, kk] = np.sum(np.conj(g) * s)
+            z = np.conj(g) * np.conj(weights[row, kk])
+            gd[n] += np.real(z * dsd)       # n is a permutation of 0..N-1 for fixed o
+            gp[n] += np.imag(z * s)
+    return gw, gd, gp

@@ -1,0 +1,6 @@
+"""Seeded synthetic inputs shared by the oracle and the HIP path (no imaging arithmetic here)."""
+from .configs import (Geometry, PolarGrid, SceneSpec, SparseSpec, Workload, WORKLOADS, band_for,
+                      bin_size_m, calib, precision, radar, rotation, scaled, small)
+from .scene import (Inputs, Scene, hann, make_angles, make_inputs, make_scene, make_support,
+                    nominal_angles, phase_matched_weights, random_complex, rng_for, simulate_raw,
+                    taylor_taper)

@@ -1,0 +1,426 @@
+"""Pins of the FP64 oracle against facts fixed by the paper and by mathematics (CPU only).
+
+Each test checks the oracle against something other than itself: a value the paper prints,
+a closed form derived independently (Cartesian geometry and the physical beat frequency
+rather than the law-of-cosines/eq. 40 code paths the oracle uses), a brute-force sum on tiny
+inputs, an invariant, or a library special case.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from oracle import metrics
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# --------------------------------------------------------------------------- helpers
+def cart_range(geom, pulse_angle, r_t, phi_t):
+    """Distance between the phase centre at pulse_angle and the point (r_t, phi_t), in x/y."""
+    px, py = geom.radius_m * np.cos(pulse_angle), geom.radius_m * np.sin(pulse_angle)
+    tx, ty = r_t * np.cos(phi_t), r_t * np.sin(phi_t)
+    return np.hypot(tx - px, ty - py)
+
+
+def beat_bin(geom, rng_m):
+    """Fractional FFT bin of a target at slant range rng_m: beat frequency 2 R K / c over F_s/L."""
+    return (2.0 * rng_m * geom.slope_hz_s / geom.c_m_s) / geom.fs_hz * geom.n_fft
+
+
+def carrier_phase(geom, rng_m):
+    """2 pi tau (K T_Start + f_c), tau = 2R/c (the constant part of eq. 10's phase)."""
+    return 2.0 * math.pi * (2.0 * rng_m / geom.c_m_s) * (geom.slope_hz_s * geom.t_start_s + geom.fc_hz)
+
+
+def boresight_cos(geom, pulse_angle, r_t, phi_t):
+    """cos(theta): projection of the unit vector radar->target on the outward bore-sight."""
+    px, py = geom.radius_m * np.cos(pulse_angle), geom.radius_m * np.sin(pulse_angle)
+    tx, ty = r_t * np.cos(phi_t), r_t * np.sin(phi_t)
+    d = np.hypot(tx - px, ty - py)
+    return ((tx - px) * np.cos(pulse_angle) + (ty - py) * np.sin(pulse_angle)) / d
+
+
+def dirichlet(x, m):
+    """sum_{m'<m} exp(j 2 pi x m') in closed form."""
+    x = np.asarray(x, dtype=np.float64)
+    z = np.exp(2j * np.pi * x)
+    near = np.abs(1 - z) < 1e-14
+    return np.where(near, m, (1 - z ** m) / np.where(near, 1, 1 - z))
+
+
+def small_geom(n=64, m=64, r=0.25, t_start=0.0):
+    g = synth.radar(n, m, r)
+    import dataclasses
+    return dataclasses.replace(g, t_start_s=t_start)
+
+
+# --------------------------------------------------------------------------- P1
+def test_visibility_worked_example():
+    """381 effective phase centres for (pi/2, 2 m), r = 0.145 m, N = 800 (Sec. IV-D.1)."""
+    with open(os.path.join(GOLDEN, "visibility_worked_example.json")) as f:
+        gold = json.load(f)
+    r, n, rt = gold["radius_m"], gold["n_pulses"], gold["target_range_m"]
+    lo, hi = oracle.visible_index_range(rt, r, n)
+    assert hi - lo + 1 == gold["effective_phase_centres"]
+    # the back-projection's own visibility rule must select exactly those pulses
+    g = synth.Geometry(n, 225, 225, r, 60e9, 6.8e13, 4.5e6)
+    grid = synth.PolarGrid(1, n, rt, 0.0)
+    vis, _, alpha = oracle.bp_terms(g, grid, 0, gold["target_azimuth_rad"],
+                                    2 * np.pi * np.arange(n) / n)
+    idx = np.nonzero(vis[0])[0]
+    assert len(idx) == gold["effective_phase_centres"]
+    assert idx[0] == lo and idx[-1] == hi
+    # alpha is the cosine antenna pattern of eq. 8 at the bore-sight angle
+    ang = 2 * np.pi * idx / n
+    np.testing.assert_allclose(alpha[0, idx], boresight_cos(g, ang, rt, np.pi / 2), rtol=1e-12)
+
+
+# --------------------------------------------------------------------------- P2, P3
+@pytest.mark.parametrize("window", ["rect", "hann"])
+@pytest.mark.parametrize("m,l", [(64, 64), (48, 64), (256, 512)])
+def test_range_compress_tone_closed_form(window, m, l):
+    nu = np.array([0.1234567, 0.31, -0.2])[:, None]                   # cycles per sample
+    mm = np.arange(m)
+    raw = np.exp(2j * np.pi * nu * mm)
+    h = None if window == "rect" else 0.5 - 0.5 * np.cos(2 * np.pi * mm / (m - 1))
+    y = oracle.range_compress(raw, h, l)
+    x = nu - np.arange(l)[None, :] / l
+    if window == "rect":
+        ref = dirichlet(x, m)
+    else:  # h = 1/2 - 1/4 e^{+j2pi m/(M-1)} - 1/4 e^{-j2pi m/(M-1)}
+        s = 1.0 / (m - 1)
+        ref = 0.5 * dirichlet(x, m) - 0.25 * dirichlet(x + s, m) - 0.25 * dirichlet(x - s, m)
+    np.testing.assert_allclose(y, ref, rtol=0, atol=1e-9 * m)
+
+
+def test_range_compress_direct_sum_and_parseval():
+    raw = synth.random_complex((3, 12), seed=11).astype(np.complex128)
+    h = synth.hann(12)
+    np.testing.assert_allclose(oracle.range_compress(raw, h, 16),
+                               oracle.range_compress_direct(raw, h, 16), atol=1e-12)
+    y = oracle.range_compress(raw, None, 12)
+    np.testing.assert_allclose(np.sum(np.abs(y) ** 2, axis=1), 12 * np.sum(np.abs(raw) ** 2, axis=1),
+                               rtol=1e-12)
+
+
+def test_peak_bin_matches_beat_frequency():
+    """argmax |Y_1D| of a simulated target equals round(beta R) (eq. 40)."""
+    g = synth.radar(8, 512, 0.3)
+    beta = oracle.bins_per_metre(g)
+    rng = np.random.default_rng(5)
+    for r_t in rng.uniform(1.0, 15.0, 20):
+        sc = synth.Scene(np.array([r_t]), np.array([0.0]), np.array([1.0 + 0j]))
+        raw = synth.simulate_raw(g, sc, np.zeros(g.n_pulses))
+        y = oracle.range_compress(raw[:1], None, g.n_fft)
+        rn = r_t - g.radius_m
+        assert np.argmax(np.abs(y[0])) == int(np.floor(beta * rn + 0.5))
+        assert abs(beta * rn - beat_bin(g, rn)) < 1e-9
+
+
+# --------------------------------------------------------------------------- P4
+def _bin_exact_scene(g, grid, offsets, row, a0, l_lo, l_count, dtype=np.complex128):
+    """Y_1D with a unit response e^{j2kR} at exactly the bin of a point at pixel (row, a0)."""
+    yb = np.zeros((g.n_pulses, l_count), dtype=dtype)
+    r_t = grid.r0_m + row * grid.dr_m
+    phi_t = g.phi0_rad + 2 * np.pi * a0 / grid.n_az
+    for o in offsets[row]:
+        n = (a0 + int(o)) % g.n_pulses
+        ang = g.phi0_rad + 2 * np.pi * n / g.n_pulses
+        rn = cart_range(g, ang, r_t, phi_t)
+        lb = int(np.floor(beat_bin(g, rn) + 0.5)) - l_lo
+        assert 0 <= lb < l_count
+        yb[n, lb] = np.exp(1j * carrier_phase(g, rn))
+    return yb
+
+
+@pytest.mark.parametrize("t_start", [0.0, 3e-6])
+def test_sum_abs_weights_closed_form(t_start):
+    """Phase-matched weights on a bin-exact unit scatterer give I = sum_k |w_k| at its pixel and
+    strictly less everywhere else (triangle inequality)."""
+    g = small_geom(180, 128, 0.25, t_start)
+    w = synth.Workload("p4", 41, g, synth.PolarGrid(6, 180, 1.3, 0.11),
+                       synth.SceneSpec(0, "unit", 1, 2), synth.SparseSpec(24, 64, False))
+    offs = synth.make_support(w)
+    wts = synth.phase_matched_weights(g, w.grid, offs, synth.taylor_taper(64, 4, 30))
+    l_lo, l_count = synth.band_for(g, w.grid)
+    row, a0 = 3, 17
+    yb = _bin_exact_scene(g, w.grid, offs, row, a0, l_lo, l_count)
+    img = oracle.sparse_filter(yb, l_lo, g, w.grid, offs, wts)
+    peak = np.sum(np.abs(wts[row]))
+    assert abs(img[row, a0] - peak) < 1e-9 * peak
+    others = np.abs(img).copy()
+    others[row, a0] = 0
+    assert others.max() < peak * (1 - 1e-6)
+
+
+# --------------------------------------------------------------------------- P5
+def test_raw_domain_closed_form():
+    """O1 then O2 on a simulated scatterer equals sum_k conj(w_k) alpha_k e^{j2kR_k} H(u_k - l_k)
+    with H(x) = sum_m h[m] exp(j 2 pi x m / L) (eq. 39 at the selected bins)."""
+    g = small_geom(360, 256, 0.25, 2e-6)
+    grid = synth.PolarGrid(4, 360, 2.0, 0.05)
+    wl = synth.Workload("p5", 42, g, grid, synth.SceneSpec(0, "unit", 1, 2), synth.SparseSpec(32, 64, False))
+    offs = synth.make_support(wl)
+    wts = synth.phase_matched_weights(g, grid, offs, synth.taylor_taper(64, 4, 30))
+    row, a0 = 2, 100
+    r_t, phi_t = grid.r0_m + row * grid.dr_m, 2 * np.pi * a0 / 360
+    raw = synth.simulate_raw(g, synth.Scene(np.array([r_t]), np.array([phi_t]), np.array([1 + 0j])),
+                             2 * np.pi * np.arange(360) / 360)
+    h = synth.hann(g.n_fast).astype(np.float64)
+    l_lo, l_count = synth.band_for(g, grid)
+    y = oracle.range_compress(raw, h, g.n_fft)[:, l_lo:l_lo + l_count]
+    got = oracle.sparse_filter_at(y, l_lo, g, grid, offs, wts, [row], [a0])[0]
+    mm = np.arange(g.n_fast)
+    ref = 0j
+    for kk, o in enumerate(offs[row]):
+        ang = 2 * np.pi * ((a0 + o) % 360) / 360
+        rn = cart_range(g, ang, r_t, phi_t)
+        u = beat_bin(g, rn)
+        lsel = np.floor(u + 0.5)
+        al = max(boresight_cos(g, ang, r_t, phi_t), 0.0)
+        hx = np.sum(h * np.exp(2j * np.pi * (u - lsel) * mm / g.n_fft))
+        ref += np.conj(wts[row, kk]) * al * np.exp(1j * carrier_phase(g, rn)) * hx
+    # raw is stored in complex64: allow its rounding
+    assert abs(got - ref) < 2e-6 * abs(ref)
+
+
+# --------------------------------------------------------------------------- P6
+def test_rotation_invariance():
+    """Shifting the pulses one angular step circularly shifts the image one azimuth bin."""
+    w = synth.small()
+    x = synth.make_inputs(w)
+    g, grid = w.geometry, w.grid
+    y = oracle.range_compress(x.raw, x.window, g.n_fft)[:, x.l_lo:x.l_lo + x.l_count]
+    rows = [0, 40, 127]
+    i0 = oracle.sparse_filter(y, x.l_lo, g, grid, x.offsets, x.weights, rows=rows)
+    i1 = oracle.sparse_filter(np.roll(y, 1, axis=0), x.l_lo, g, grid, x.offsets, x.weights, rows=rows)
+    np.testing.assert_allclose(i1, np.roll(i0, 1, axis=1), rtol=0, atol=1e-12 * np.abs(i0).max())
+    # back-projection with jittered angles: pulse n of the shifted set sits one step further on
+    ang = synth.nominal_angles(g) + np.random.default_rng(3).normal(0, 1e-3, g.n_pulses)
+    b0 = oracle.bp_full(y, x.l_lo, g, grid, ang, rows=rows)
+    ang1 = np.roll(ang, 1) + 2 * np.pi / g.n_pulses
+    b1 = oracle.bp_full(np.roll(y, 1, axis=0), x.l_lo, g, grid, ang1, rows=rows)
+    np.testing.assert_allclose(b1, np.roll(b0, 1, axis=1), rtol=0, atol=1e-10 * np.abs(b0).max())
+
+
+# --------------------------------------------------------------------------- P7
+def test_bpa_equals_dense_sparse_filter():
+    """With nominal angles, BPA equals the sparse filter whose support is every visible pulse and
+    whose weights are the steering vector alpha e^{+j2kR} (eq. 16): two separately coded sums."""
+    g = small_geom(64, 64, 0.3)
+    grid = synth.PolarGrid(8, 64, 0.35, 0.2)
+    l_lo, l_count = synth.band_for(g, grid)
+    yb = synth.random_complex((64, l_count), seed=7).astype(np.complex128)
+    n = g.n_pulses
+    vis_sets = []
+    for row in range(grid.n_range):
+        r_t = grid.r0_m + row * grid.dr_m
+        o = np.arange(-n // 2, n // 2)
+        c = boresight_cos(g, 2 * np.pi * o / n, r_t, 0.0)
+        vis_sets.append(o[c > 0])
+    kmax = max(len(v) for v in vis_sets)
+    offs = np.zeros((grid.n_range, kmax), np.int32)
+    wts = np.zeros((grid.n_range, kmax), np.complex128)
+    for row, v in enumerate(vis_sets):
+        r_t = grid.r0_m + row * grid.dr_m
+        pad = [o for o in range(-n // 2, n // 2) if o not in set(v.tolist())][:kmax - len(v)]
+        offs[row] = np.concatenate([v, pad]).astype(np.int32)
+        ang = 2 * np.pi * v / n
+        rn = cart_range(g, ang, r_t, 0.0)
+        wts[row, :len(v)] = boresight_cos(g, ang, r_t, 0.0) * np.exp(1j * carrier_phase(g, rn))
+    for interp in ("nearest", "linear"):
+        a = oracle.sparse_filter(yb, l_lo, g, grid, offs, wts, interp=interp)
+        b = oracle.bp_full(yb, l_lo, g, grid, None, interp=interp)
+        assert np.abs(a - b).max() < 1e-11 * np.abs(b).max()
+
+
+# --------------------------------------------------------------------------- P8
+def test_time_domain_bpa_brute_force():
+    """Literal eq.-14 double sum (fast-time ramp at the selected bin) on tiny random data equals
+    range FFT + BPA (eqs. 38, 43)."""
+    g = small_geom(16, 16, 0.3)
+    grid = synth.PolarGrid(3, 16, 0.9, 0.45)
+    raw = synth.random_complex((16, 16), seed=21).astype(np.complex128)
+    y = oracle.range_compress(raw, None, 16)
+    got = oracle.bp_full(y, 0, g, grid)
+    ref = np.zeros_like(got)
+    for row in range(3):
+        r_t = grid.r0_m + row * grid.dr_m
+        for a in range(16):
+            phi_t = 2 * np.pi * a / 16
+            acc = 0j
+            for n in range(16):
+                ang = 2 * np.pi * n / 16
+                cth = boresight_cos(g, ang, r_t, phi_t)
+                if cth <= 0:
+                    continue
+                rn = cart_range(g, ang, r_t, phi_t)
+                lsel = math.floor(beat_bin(g, rn) + 0.5)
+                if not 0 <= lsel < 16:
+                    continue
+                for m in range(16):
+                    acc += cth * np.exp(-2j * np.pi * lsel * m / 16) * np.exp(-1j * carrier_phase(g, rn)) * raw[n, m]
+            ref[row, a] = acc
+    np.testing.assert_allclose(got, ref, atol=1e-10 * np.abs(ref).max())
+
+
+# --------------------------------------------------------------------------- P9
+def test_linearity():
+    w = synth.small()
+    x = synth.make_inputs(w)
+    g, grid = w.geometry, w.grid
+    y1 = synth.random_complex((g.n_pulses, x.l_count), 1).astype(np.complex128)
+    y2 = synth.random_complex((g.n_pulses, x.l_count), 2).astype(np.complex128)
+    rows = [5, 60]
+    f = lambda y, wt: oracle.sparse_filter(y, x.l_lo, g, grid, x.offsets, wt, rows=rows)
+    a, b = 0.3 - 1.2j, 2.0 + 0.5j
+    np.testing.assert_allclose(f(a * y1 + b * y2, x.weights), a * f(y1, x.weights) + b * f(y2, x.weights), atol=1e-10)
+    w2 = synth.random_complex(x.weights.shape, 3).astype(np.complex128)
+    np.testing.assert_allclose(f(y1, a * x.weights + w2), np.conj(a) * f(y1, x.weights) + f(y1, w2), atol=1e-10)
+
+
+# --------------------------------------------------------------------------- P10
+def _calib_case():
+    g = small_geom(96, 64, 0.25)
+    grid = synth.PolarGrid(6, 96, 0.8, 0.07)
+    wl = synth.Workload("p10", 43, g, grid, synth.SceneSpec(0, "unit", 1, 2), synth.SparseSpec(12, 32, False))
+    offs = synth.make_support(wl)
+    wts = synth.phase_matched_weights(g, grid, offs, synth.taylor_taper(32, 4, 30))
+    l_lo, l_count = synth.band_for(g, grid)
+    yb = synth.random_complex((96, l_count), 9).astype(np.complex128)
+    rng = np.random.default_rng(4)
+    dphi = rng.normal(0, 2e-3, 96)
+    dpsi = rng.normal(0, 0.1, 96)
+    return g, grid, offs, wts, l_lo, yb, dphi, dpsi
+
+
+@pytest.mark.parametrize("interp", ["nearest", "linear"])
+def test_adjoint_dot_product_weights(interp):
+    g, grid, offs, wts, l_lo, yb, dphi, dpsi = _calib_case()
+    gimg = synth.random_complex((grid.n_range, grid.n_az), 12).astype(np.complex128)
+    dw = synth.random_complex(wts.shape, 13).astype(np.complex128)
+    gw, _, _ = oracle.sparse_filter_grad(yb, l_lo, g, grid, offs, wts, gimg, dphi, dpsi, interp)
+    img_dw = oracle.sparse_filter(yb, l_lo, g, grid, offs, dw, dphi, dpsi, interp)
+    lhs = np.real(np.sum(np.conj(gimg) * img_dw))
+    rhs = np.real(np.sum(np.conj(dw) * gw))
+    assert abs(lhs - rhs) < 1e-12 * (abs(lhs) + 1)
+
+
+def test_adjoint_finite_differences_linear():
+    """Central differences (h = 1e-4) of L = Re<g, I> in delta, psi and w against the adjoint."""
+    g, grid, offs, wts, l_lo, yb, dphi, dpsi = _calib_case()
+    gimg = synth.random_complex((grid.n_range, grid.n_az), 14).astype(np.complex128)
+    f = lambda w_, d_, p_: np.real(np.sum(np.conj(gimg) *
+                                          oracle.sparse_filter(yb, l_lo, g, grid, offs, w_, d_, p_, "linear")))
+    gw, gd, gp = oracle.sparse_filter_grad(yb, l_lo, g, grid, offs, wts, gimg, dphi, dpsi, "linear")
+    h = 1e-4
+    fd_d, fd_p, an_d, an_p = [], [], [], []
+    for n in [0, 7, 33, 50, 95]:
+        e = np.zeros(96); e[n] = h
+        fd_d.append((f(wts, dphi + e, dpsi) - f(wts, dphi - e, dpsi)) / (2 * h)); an_d.append(gd[n])
+        fd_p.append((f(wts, dphi, dpsi + e) - f(wts, dphi, dpsi - e)) / (2 * h)); an_p.append(gp[n])
+    fd_d, an_d, fd_p, an_p = map(np.array, (fd_d, an_d, fd_p, an_p))
+    assert np.linalg.norm(fd_d - an_d) <= 1e-3 * np.linalg.norm(an_d)
+    assert np.linalg.norm(fd_p - an_p) <= 1e-3 * np.linalg.norm(an_p)
+    for (row, kk) in [(0, 0), (3, 5), (5, 11)]:
+        for unit in (1.0, 1j):
+            e = np.zeros_like(wts); e[row, kk] = h * unit
+            fd = (f(wts + e, dphi, dpsi) - f(wts - e, dphi, dpsi)) / (2 * h)
+            an = gw[row, kk].real if unit == 1.0 else gw[row, kk].imag
+            assert abs(fd - an) <= 1e-6 * (abs(an) + 1e-3)
+
+
+def test_calibration_loss_gradient_chain():
+    """Entropy + sidelobe loss: analytic dL/dI pulled back through the adjoint matches central
+    differences of the full loss in delta and w."""
+    g, grid, offs, wts, l_lo, yb, dphi, dpsi = _calib_case()
+    mask = metrics.box_mask((grid.n_range, grid.n_az), [2, 4], [10, 70])
+    loss = lambda w_, d_: metrics.calib_loss(
+        oracle.sparse_filter(yb, l_lo, g, grid, offs, w_, d_, dpsi, "linear"), mask)[0]
+    _, gimg = metrics.calib_loss(oracle.sparse_filter(yb, l_lo, g, grid, offs, wts, dphi, dpsi, "linear"), mask)
+    gw, gd, _ = oracle.sparse_filter_grad(yb, l_lo, g, grid, offs, wts, gimg, dphi, dpsi, "linear")
+    h = 1e-4
+    fd, an = [], []
+    for n in [3, 40, 77]:
+        def cd(step):
+            e = np.zeros(96); e[n] = step
+            return (loss(wts, dphi + e) - loss(wts, dphi - e)) / (2 * step)
+        # central differences at h and h/2 combined (Richardson) to cancel the O(h^2) term:
+        # at 77 GHz a 1e-4 rad step already turns the phase by 2 k r h ~ 0.08 rad
+        fd.append((4 * cd(h / 2) - cd(h)) / 3); an.append(gd[n])
+    assert np.linalg.norm(np.array(fd) - an) <= 1e-3 * np.linalg.norm(an)
+    e = np.zeros_like(wts); e[2, 3] = h
+    fdw = (loss(wts + e, dphi) - loss(wts - e, dphi)) / (2 * h)
+    assert abs(fdw - gw[2, 3].real) <= 1e-3 * abs(gw[2, 3].real) + 1e-9
+
+
+# --------------------------------------------------------------------------- P11
+def test_point_target_focus():
+    """A simulated point focuses on its own pixel (BPA and sparse filter)."""
+    g = synth.radar(3600, 512, 0.3)
+    # place row 200 so the nearest slant range R - r sits on a bin centre (u = 206): the taps'
+    # fractional bins then stay within [0, 0.2] and the residual phase of Remark 1 stays small
+    # (at half-bin offsets NEAREST selection splits the taps between two bins and defocuses)
+    row, a0 = 200, 1234
+    r_row = 206.0 / oracle.bins_per_metre(g) + g.radius_m
+    grid = synth.PolarGrid(400, 3600, r_row - row * 0.0375, 0.0375)
+    r_t, phi_t = grid.r0_m + row * grid.dr_m, 2 * np.pi * a0 / 3600
+    raw = synth.simulate_raw(g, synth.Scene(np.array([r_t]), np.array([phi_t]), np.array([1 + 0j])),
+                             synth.nominal_angles(g))
+    l_lo, l_count = synth.band_for(g, grid)
+    y = oracle.range_compress(raw, synth.hann(512), 512)[:, l_lo:l_lo + l_count]
+    wl = synth.Workload("p11", 44, g, grid, synth.SceneSpec(0, "unit", 1, 2), synth.SparseSpec(64, 256, False))
+    offs = synth.make_support(wl)
+    wts = synth.phase_matched_weights(g, grid, offs, synth.taylor_taper(256, 4, 30))
+    rr, aa = np.meshgrid(np.arange(row - 3, row + 4), np.arange(a0 - 3, a0 + 4), indexing="ij")
+    rr, aa = rr.ravel(), aa.ravel()
+    for img in (oracle.bp_full_at(y, l_lo, g, grid, rr, aa),
+                oracle.sparse_filter_at(y, l_lo, g, grid, offs, wts, rr, aa)):
+        i = np.argmax(np.abs(img))
+        assert (rr[i], aa[i]) == (row, a0)
+
+
+# --------------------------------------------------------------------------- metrics
+def test_entropy_closed_forms():
+    assert metrics.image_entropy(np.ones((4, 8))) == pytest.approx(math.log(32), abs=1e-12)
+    z = np.zeros((5, 5), complex); z[2, 3] = 3 - 4j
+    assert metrics.image_entropy(z) == 0.0
+
+
+def test_pslr_rect_sinc():
+    """A rectangular-aperture response has its first sidelobe at -13.26 dB."""
+    m = 64
+    cut = dirichlet(np.arange(-512, 512) / (16 * m), m)          # 16x oversampled Dirichlet
+    img = np.roll(cut, 512)[None, :]
+    val = metrics.pslr_db(img, [0], [0], half_window=200)[0]
+    assert val == pytest.approx(-13.26, abs=0.05)
+
+
+def test_calib_loss_gradient_fd():
+    rng = np.random.default_rng(2)
+    img = rng.standard_normal((4, 6)) + 1j * rng.standard_normal((4, 6))
+    mask = metrics.box_mask(img.shape, [1], [2], half=1)
+    l0, g = metrics.calib_loss(img, mask)
+    h = 1e-6
+    for (i, j) in [(0, 0), (1, 2), (3, 5)]:
+        for unit in (1, 1j):
+            e = np.zeros_like(img); e[i, j] = h * unit
+            fd = (metrics.calib_loss(img + e, mask)[0] - metrics.calib_loss(img - e, mask)[0]) / (2 * h)
+            an = g[i, j].real if unit == 1 else g[i, j].imag
+            assert fd == pytest.approx(an, rel=1e-5, abs=1e-8)
+
+
+# --------------------------------------------------------------------------- generator
+def test_generator_deterministic():
+    a = synth.make_inputs(synth.small())
+    b = synth.make_inputs(synth.small())
+    assert a.raw.tobytes() == b.raw.tobytes()
+    assert a.offsets.tobytes() == b.offsets.tobytes()
+    assert a.weights.tobytes() == b.weights.tobytes()
+    assert np.all(a.offsets >= -32) and np.all(a.offsets < 32)
+    assert np.allclose(np.linalg.norm(a.weights, axis=1), 1.0)
