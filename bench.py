@@ -1,0 +1,221 @@
+"""Benchmark of the rotating-SAR imaging path on one MI355X.
+
+One step = one polar image from raw data through the sparse-aperture path: range
+compression of every pulse (windowed FFT, transposed band store) followed by the sparse
+azimuth filter (K taps per pixel).  The full-aperture back-projection comparator is timed on
+the same range-compressed data.  Inputs (seeded synthetic scene, weights, supports) are
+resident in HBM before timing starts.
+
+Prints one JSON line: pixels/s of the sparse path (whole image per step), BPA pixels/s and
+the ratio, achieved HBM GB/s, the roofline of the dominant kernel (sparse filter) and the
+FP64 CPU oracle timed on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+PEAK_HBM_GBPS = 8000.0
+# 256 CUs x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz: FP32 FMA issued one per lane per cycle
+# (packed FP32 disabled in this build); FP64 vector runs at the same rate.
+PEAK_FP32_VALU_TFLOPS = 78.6
+PROFILE_DIR = os.path.join(ROOT, "profiles")
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", default="rotation", choices=["small", "rotation"])
+    ap.add_argument("--bpa-reps", type=int, default=5)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 1 GiB device copy (reference for PMC byte counters)")
+    ap.add_argument("--tile", default=None, help="sparse-filter launch shape variant,ppl,waves")
+    return ap.parse_args()
+
+
+def kernel_source_digest(files):
+    h = hashlib.sha256()
+    for f in files:
+        with open(os.path.join(ROOT, "paper_2309_08038_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(kernel: str, digest: str, workload: str):
+    """HBM bytes per launch from the committed PMC summary, if it was taken on this kernel source."""
+    path = os.path.join(PROFILE_DIR, f"{kernel}_{workload}_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        d = json.load(f)
+    if d.get("kernel_source_digest") != digest:
+        return None
+    return d.get("traffic_bytes_per_launch")
+
+
+def cpu_baseline(w, x):
+    """FP64 oracle on the CPU: range compression of every pulse, then the sparse filter over a
+    contiguous block of rows (the rest of the image costs the same per row)."""
+    import oracle
+    rows = list(range(0, w.grid.n_range, max(1, w.grid.n_range // 256)))[:256]
+    t0 = time.perf_counter()
+    y = oracle.range_compress(x.raw, x.window, w.geometry.n_fft)[:, x.l_lo:x.l_lo + x.l_count]
+    t_rc = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    oracle.sparse_filter(y, x.l_lo, w.geometry, w.grid, x.offsets, x.weights, rows=rows)
+    t_sf = time.perf_counter() - t0
+    px = len(rows) * w.grid.n_az
+    # one image = all rows; the sampled rows give the per-row cost
+    t_img = t_rc + t_sf * w.grid.n_range / len(rows)
+    bp_rows = rows[:: max(1, len(rows) // 8)][:8]
+    t0 = time.perf_counter()
+    oracle.bp_full(y, x.l_lo, w.geometry, w.grid, pulse_angles=x.angles, rows=bp_rows)
+    t_bp = time.perf_counter() - t0
+    return {
+        "value": w.grid.n_range * w.grid.n_az / t_img,
+        "unit": "pixels/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": (f"FP64 numpy: range compression of all {w.geometry.n_pulses} pulses ({t_rc:.2f} s) + sparse "
+                   f"filter on {len(rows)} of {w.grid.n_range} rows x {w.grid.n_az} az ({px} px, {t_sf:.2f} s), "
+                   f"scaled to one image; BPA on {len(bp_rows)} rows ({t_bp:.2f} s)"),
+        "bpa_value": len(bp_rows) * w.grid.n_az / t_bp,
+        "cpu": _cpu_model(),
+    }
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); the imaging path has no multi-GPU "
+              "code: sharding by azimuth sector or rotation is described in DESIGN.md", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import synth
+    import paper_2309_08038_amd as rs
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a ROCm GPU", file=sys.stderr)
+        sys.exit(2)
+    dev = torch.device("cuda:0")
+    w = {"small": synth.small, "rotation": synth.rotation}[a.workload]()
+    x = synth.make_inputs(w)
+    g, grid = w.geometry, w.grid
+    halo = w.sparse.window // 2
+    raw = torch.from_numpy(x.raw).to(dev)
+    win = torch.from_numpy(x.window).to(dev)
+    off = torch.from_numpy(x.offsets).to(dev)
+    wts = torch.from_numpy(x.weights.astype(np.complex64)).to(dev)
+    ang = torch.from_numpy(x.angles).to(dev)
+    rc = rs.empty_rc(g.n_pulses, x.l_lo, x.l_count, halo=halo, device=dev)
+    img = torch.empty((grid.n_range, grid.n_az), dtype=torch.complex64, device=dev)
+    bimg = torch.empty_like(img)
+    bws = torch.empty(rs.bp_workspace_bytes(g), dtype=torch.uint8, device=dev)
+    tile = tuple(int(v) for v in a.tile.split(",")) if a.tile else None
+
+    def step():
+        rs.range_compress(g, raw, win, x.l_lo, x.l_count, out=rc)
+        rs.sparse_filter(g, grid, rc, off, wts, w.sparse.window, out=img, tile=tile)
+
+    def timed(fn, reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    for _ in range(a.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ms_step = timed(step, a.steps)
+    wall = time.perf_counter() - t0
+    print(f"[bench] {a.steps} steps: {ms_step:.4f} ms/step (wall {wall:.3f} s)", file=sys.stderr, flush=True)
+
+    # per-kernel averages on the same stream
+    ms_rc = timed(lambda: rs.range_compress(g, raw, win, x.l_lo, x.l_count, out=rc), a.steps)
+    ms_sf = timed(lambda: rs.sparse_filter(g, grid, rc, off, wts, w.sparse.window, out=img, tile=tile), a.steps)
+    rs.bp_full(g, grid, rc, angles=ang, out=bimg, workspace=bws)
+    ms_bp = timed(lambda: rs.bp_full(g, grid, rc, angles=ang, out=bimg, workspace=bws), a.bpa_reps)
+    print(f"[bench] range_compress {ms_rc:.4f} ms, sparse_filter {ms_sf:.4f} ms, bp_full {ms_bp:.3f} ms",
+          file=sys.stderr, flush=True)
+    if a.copy_calibration:
+        src = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+
+    px = grid.n_range * grid.n_az
+    k = w.sparse.k
+    es = 8
+    # algorithmic bytes: band rows read once, image written once, weights + offsets read once
+    sf_bytes = x.l_count * g.n_pulses * es + px * 8 + grid.n_range * k * (8 + 4)
+    sf_flops = px * k * 8
+    rc_bytes = g.n_pulses * g.n_fast * 8 + g.n_fast * 4 + x.l_count * (g.n_pulses + 2 * halo) * es
+    digest = kernel_source_digest(["sparse_filter.hip", "rosar_device.hpp"])
+    traffic = load_traffic("sparse_filter", digest, a.workload)
+    achieved_tf = sf_flops / (ms_sf * 1e-3) / 1e12
+    roofline = {"bound": "alu", "achieved": round(achieved_tf, 3), "peak": PEAK_FP32_VALU_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(achieved_tf / PEAK_FP32_VALU_TFLOPS, 4),
+                "traffic": traffic, "kernel": "sparse_plain_kernel",
+                "algorithmic_bytes": sf_bytes, "algorithmic_flops": sf_flops}
+    out = {
+        "metric": "polar image pixels/s: sparse-array filter vs full BPA on 1 MI355X; HBM GB/s",
+        "value": px / (ms_step * 1e-3),
+        "unit": "pixels/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": w.name, "pulses": g.n_pulses, "fast_samples": g.n_fast, "fft": g.n_fft,
+                   "range_rows": grid.n_range, "azimuth_bins": grid.n_az, "taps": k, "window": w.sparse.window,
+                   "band_rows": x.l_count, "storage": "complex64", "parallelism": "single GPU"},
+        "sparse_filter_pixels_per_s": px / (ms_sf * 1e-3),
+        "bpa_pixels_per_s": px / (ms_bp * 1e-3),
+        "fft_bpa_pixels_per_s": px / ((ms_bp + ms_rc) * 1e-3),
+        "sparse_vs_bpa": ms_bp / ms_sf,
+        "fft_sas_vs_fft_bpa": (ms_bp + ms_rc) / ms_step,
+        "kernel_ms": {"range_compress": ms_rc, "sparse_filter": ms_sf, "bp_full": ms_bp},
+        "hbm_gbps": {"sparse_filter": sf_bytes / (ms_sf * 1e-3) / 1e9,
+                     "range_compress": rc_bytes / (ms_rc * 1e-3) / 1e9, "peak": PEAK_HBM_GBPS},
+        "roofline": roofline,
+        "kernel_source_digest": digest,
+    }
+    if not a.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w, x)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

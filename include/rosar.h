@@ -1,0 +1,250 @@
+/*
+ * rosar.h - C ABI of the MI355X (gfx950) rotating-SAR imaging library (librosar.so).
+ *
+ * Method: "Efficient Rotating Synthetic Aperture Radar Imaging via Robust Sparse Array
+ * Synthesis" (arXiv 2309.08038).  The online imaging path is
+ *   (1) range compression: a windowed FFT of every pulse along fast time (Sec. III-D, eq. 38);
+ *   (2) azimuth matched filtering of every polar pixel over a sparse set of K pulses with
+ *       precomputed complex weights, I = w^H y over the selected range bins
+ *       (Algorithm 2 with eq. 43, only the nonzero weights as in Sec. III-C);
+ * and full-aperture back-projection (FFT+BPA, eq. 43 with the BPA weights) is the comparator.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Complex values are interleaved (re, im).  ROSAR_C64 is 2 x float32; ROSAR_C16_F16 and
+ *    ROSAR_C16_BF16 are 2 x 16-bit.  Images and gradients of complex quantities are C64.
+ *  - Every array argument is a DEVICE pointer unless marked "host".  The caller owns all
+ *    device memory; the library allocates device memory only inside a batch plan (freed by
+ *    rosar_batch_plan_destroy).  Structs passed by pointer are host memory, read during the
+ *    call only.
+ *  - Calls are asynchronous on `stream` (a hipStream_t; NULL = the default stream) and never
+ *    synchronise the device.  Every argument check happens on the host before any device
+ *    work; a failed check enqueues nothing and returns a status, with a message available
+ *    from rosar_last_error() (thread-local).  A failed kernel launch returns ROSAR_ERR_HIP.
+ *  - Geometry (Sec. II-A, eqs. 1-2): pulse n is taken at angle phi0 + 2 pi n / N (plus an
+ *    optional per-pulse error) on a circle of radius r; the polar grid has R_i = r0 + i dr and
+ *    phi_a = phi0 + 2 pi a / n_az.  This version requires n_az == N, so pixel a is centred on
+ *    pulse a (Algorithm 2's centre index) and a tap at offset o reads pulse (a + o) mod N.
+ *  - k = 2 pi (K T_Start + f_c) / c (after eq. 12); the fractional FFT bin of slant range R
+ *    is u = beta R with beta = 2 K L / (F_s c) (eq. 40).  NEAREST reads bin floor(u + 1/2)
+ *    (eq. 40's round); LINEAR interpolates bins floor(u) and floor(u) + 1.  Bins outside the
+ *    computed band [l_lo, l_lo + l_count) read as zero.
+ *  - The weight vector is applied conjugated (w^H y, eq. 43).  Back-projection applies
+ *    alpha_n exp(-j 2 k R_n) to pulse n, alpha_n = max(R cos D - r, 0) / R_n the cosine
+ *    antenna pattern (eqs. 3-5, 8, 15): its "w" is the steering vector of eq. 16.
+ */
+#ifndef ROSAR_H
+#define ROSAR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define ROSAR_VERSION_MAJOR 1
+#define ROSAR_VERSION_MINOR 0
+
+struct ihipStream_t;
+typedef struct ihipStream_t* rosar_stream; /* identical to hipStream_t */
+
+typedef enum rosar_status {
+  ROSAR_OK = 0,
+  ROSAR_ERR_INVALID_ARG = 1, /* null pointer, bad size, misaligned, non-finite geometry ... */
+  ROSAR_ERR_UNSUPPORTED = 2, /* valid request outside what this version implements */
+  ROSAR_ERR_HIP = 3,         /* a HIP runtime call or kernel launch failed */
+  ROSAR_ERR_NO_MEMORY = 4,   /* device or host allocation failed (batch plans only) */
+  ROSAR_ERR_WORKSPACE = 5    /* workspace pointer null or smaller than the queried size */
+} rosar_status;
+
+typedef enum rosar_dtype {
+  ROSAR_C64 = 0,      /* complex float32 */
+  ROSAR_C16_F16 = 1,  /* complex IEEE half */
+  ROSAR_C16_BF16 = 2  /* complex bfloat16 */
+} rosar_dtype;
+
+typedef enum rosar_interp { ROSAR_NEAREST = 0, ROSAR_LINEAR = 1 } rosar_interp;
+
+/* Radar and rotation (paper Table I/II notation).  n_fft (L) must be a power of two in
+ * [64, 4096] with L >= n_fast (M); zero padding when L > M (eq. 38). */
+typedef struct rosar_geometry {
+  int32_t n_pulses;   /* N: pulses per rotation, >= 2 */
+  int32_t n_fast;     /* M: fast-time samples per pulse, >= 1 */
+  int32_t n_fft;      /* L: FFT length */
+  int32_t reserved;   /* must be 0 */
+  double radius_m;    /* r > 0 */
+  double fc_hz;       /* f_c */
+  double slope_hz_s;  /* K (chirp slope) > 0 */
+  double fs_hz;       /* F_s > 0 */
+  double t_start_s;   /* T_Start */
+  double c_m_s;       /* speed of light > 0 */
+  double phi0_rad;    /* angle of pulse 0 and of azimuth bin 0 */
+} rosar_geometry;
+
+typedef struct rosar_polar_grid {
+  int32_t n_range;    /* rows, >= 1 */
+  int32_t n_az;       /* azimuth bins; must equal n_pulses */
+  double r0_m;        /* range of row 0, > 0 */
+  double dr_m;        /* row spacing, >= 0 */
+} rosar_polar_grid;
+
+/* Range-compressed data Y_T[l_count][ld], range-bin major with pulses contiguous.  Element
+ * (i, j) holds FFT bin l_lo + i of pulse (j - halo) mod N, for 0 <= j < N + 2*halo; the halo
+ * repeats the last/first `halo` pulses on each side so windows near azimuth 0 need no wrap.
+ * Stored values are `scale` times the true spectrum (readers divide by it).  Must be aligned
+ * to 4 bytes (16-bit types) or 8 bytes (C64). */
+typedef struct rosar_rc_view {
+  const void* data;
+  int32_t dtype;      /* rosar_dtype */
+  int32_t l_lo;       /* first stored FFT bin, >= 0 */
+  int32_t l_count;    /* stored bins, >= 1, l_lo + l_count <= L */
+  int32_t halo;       /* 0 <= halo <= N */
+  int64_t ld;         /* row stride in elements, >= N + 2*halo */
+  float scale;        /* > 0 */
+  int32_t reserved;   /* must be 0 */
+} rosar_rc_view;
+
+/* Sparse weight set W* (Algorithm 1's output, the nonzero entries only): for range row i,
+ * tap t reads pulse offset offsets[i*k + t] in [-window/2, window/2) (int32) with weight
+ * weights[i*k + t] (interleaved complex, w_dtype C64 or C16_F16).  Taps whose offset lies
+ * outside that range, or whose bin is outside the band, contribute zero. */
+typedef struct rosar_sparse_set {
+  int32_t k;          /* taps per row, 1 <= k <= 1024 */
+  int32_t window;     /* W: even, 2 <= W <= N */
+  const int32_t* offsets;
+  const void* weights;
+  int32_t w_dtype;    /* rosar_dtype: ROSAR_C64 or ROSAR_C16_F16 */
+  int32_t reserved;   /* must be 0 */
+} rosar_sparse_set;
+
+/* Launch shape of the sparse filter (0 = let the library choose).  The project's autotuner
+ * (rosar_autotune_sparse_filter) searches these. */
+typedef struct rosar_tile {
+  int32_t variant;        /* 0 auto, 1 direct cached loads, 2 LDS-staged window */
+  int32_t pixels_per_lane;/* 1, 2, 4 or 8 */
+  int32_t waves;          /* waves per workgroup: 1, 2, 4 or 8 */
+  int32_t reserved;
+} rosar_tile;
+
+const char* rosar_version(void);
+const char* rosar_status_str(rosar_status status);
+/* Message describing the last failure on the calling thread ("" if none). */
+const char* rosar_last_error(void);
+
+/* Range compression (Sec. III-D, eq. 38): for every pulse n and bin l in [l_lo, l_lo+l_count)
+ *   Y_1D[n][l] = sum_{m<M} window[m] * raw[n][m] * exp(-j 2 pi l m / L),
+ * stored transposed into y_t[l - l_lo][n + halo] (and halo copies, see rosar_rc_view) as
+ * out_scale * Y in out_dtype (round to nearest even for 16-bit types).
+ *   raw    [N][M] C64, pulse-major, 8-byte aligned.
+ *   window [M] float32, or NULL for a rectangular window.
+ *   y_t    [l_count][ld] of out_dtype, ld >= N + 2*halo; written, never read.
+ * Errors: INVALID_ARG for null/misaligned pointers or bad sizes; UNSUPPORTED for L not a
+ * power of two in [64, 4096]. */
+rosar_status rosar_range_compress(const rosar_geometry* geom, const void* raw, const float* window,
+                                  int32_t l_lo, int32_t l_count, int32_t halo,
+                                  rosar_dtype out_dtype, float out_scale,
+                                  void* y_t, int64_t ld, rosar_stream stream);
+
+/* Sparse-aperture azimuth filter (Algorithm 2 / eq. 43): for row i and azimuth bin a
+ *   image[i][a] = (1/scale) * sum_t conj(w[i,t]) * s(i, a, t),
+ *   s = Y(n, u(R^)),  n = (a + o_t) mod N,  R^ = R(o_t 2 pi/N + dphi[n])  (eq. 2).
+ * When dphi or dpsi is non-NULL the sample is phase-corrected to the nominal geometry,
+ *   s <- s * exp(-j 2k (R^ - R(o_t 2 pi/N))) * exp(-j dpsi[n])
+ * (a NULL array counts as zeros).  dphi, dpsi: [N] float32 radians (data taken at
+ * phi_n + dphi[n], eq. 37).  image: [n_range][n_az] C64, 8-byte aligned, overwritten.
+ * The rc view must hold C64, C16_F16 or C16_BF16 data; weights C64 or C16_F16. */
+rosar_status rosar_sparse_filter(const rosar_geometry* geom, const rosar_polar_grid* grid,
+                                 const rosar_rc_view* rc, const rosar_sparse_set* set,
+                                 const float* dphi, const float* dpsi, rosar_interp interp,
+                                 void* image, rosar_stream stream);
+
+/* rosar_sparse_filter with an explicit launch shape (NULL tile = automatic). */
+rosar_status rosar_sparse_filter_tiled(const rosar_geometry* geom, const rosar_polar_grid* grid,
+                                       const rosar_rc_view* rc, const rosar_sparse_set* set,
+                                       const float* dphi, const float* dpsi, rosar_interp interp,
+                                       void* image, const rosar_tile* tile, rosar_stream stream);
+
+/* Device workspace (bytes) needed by rosar_bp_full for this geometry. */
+rosar_status rosar_bp_full_workspace_size(const rosar_geometry* geom, size_t* bytes);
+
+/* Full-aperture back-projection over range-compressed data (FFT+BPA, eq. 43 with the BPA
+ * weights of Sec. III-D):
+ *   image[i][a] = (1/scale) sum over pulses n with v = R_i cos D - r > 0 of
+ *                 (v / R_n) * exp(-j 2 k R_n) * Y(n, u(R_n)),
+ *   D = phi_a - phi^_n,  R_n = sqrt(R_i^2 + r^2 - 2 R_i r cos D)  (eqs. 2-5, 8, 15).
+ * pulse_angle_rad: [N] float64 absolute pulse angles phi^_n (true angles, eq. 37), or NULL
+ * for the nominal phi0 + 2 pi n / N.  workspace: >= rosar_bp_full_workspace_size bytes,
+ * 256-byte aligned, scratch owned by the caller and overwritten.  image as above. */
+rosar_status rosar_bp_full(const rosar_geometry* geom, const rosar_polar_grid* grid,
+                           const rosar_rc_view* rc, const double* pulse_angle_rad,
+                           rosar_interp interp, void* image, void* workspace,
+                           size_t workspace_bytes, rosar_stream stream);
+
+/* Device workspace (bytes) needed by rosar_sparse_filter_backward. */
+rosar_status rosar_sparse_filter_backward_workspace_size(const rosar_geometry* geom,
+                                                         const rosar_polar_grid* grid,
+                                                         const rosar_sparse_set* set,
+                                                         size_t* bytes);
+
+/* Adjoint of rosar_sparse_filter for a real loss L, given grad_image = dL/dRe(I) + j dL/dIm(I)
+ * ([n_range][n_az] C64).  Outputs (each may be NULL to skip it; all are overwritten):
+ *   grad_weights [n_range][k] C64:  sum_a conj(g[i,a]) s(i,a,t)        (same convention)
+ *   grad_dphi    [N] float32:       sum_{i,t} Re(conj(g) conj(w) ds/d dphi[n]),  a = n - o_t
+ *   grad_dpsi    [N] float32:       sum_{i,t} Im(conj(g) conj(w) s)
+ * The derivatives are those of the corrected model (NULL dphi/dpsi = zeros); in NEAREST mode
+ * the bin choice is piecewise constant and contributes no derivative.  Interpolation
+ * indices are recomputed, never stored.  Weights must be C64 here.  The reductions run in a
+ * fixed order (no atomics), so results are reproducible.  workspace: >= the queried size,
+ * 256-byte aligned. */
+rosar_status rosar_sparse_filter_backward(const rosar_geometry* geom, const rosar_polar_grid* grid,
+                                          const rosar_rc_view* rc, const rosar_sparse_set* set,
+                                          const float* dphi, const float* dpsi, rosar_interp interp,
+                                          const void* grad_image, void* grad_weights,
+                                          float* grad_dphi, float* grad_dpsi,
+                                          void* workspace, size_t workspace_bytes,
+                                          rosar_stream stream);
+
+/* ---------------------------------------------------------------- batched rotations
+ * Many independent rotations of uneven sizes imaged by one persistent range-compression
+ * launch and one persistent sparse-filter launch.  Workgroups pull tiles from a device work
+ * counter reset by the plan's own kernel at the start of each run, so a run can be captured
+ * in a HIP graph and replayed.  NEAREST, uncorrected, C64 only. */
+typedef struct rosar_rotation_desc {
+  rosar_geometry geom;
+  rosar_polar_grid grid;
+  const void* raw;          /* [N][M] C64 */
+  const float* window;      /* [M] or NULL */
+  void* y_t;                /* [l_count][ld] C64 scratch written by the batch */
+  int32_t l_lo, l_count, halo, reserved;
+  int64_t ld;
+  rosar_sparse_set set;     /* weights C64 */
+  void* image;              /* [n_range][n_az] C64 */
+} rosar_rotation_desc;
+
+typedef struct rosar_batch_plan rosar_batch_plan;
+
+/* Validates every descriptor (host), uploads a device descriptor table and tile prefix sums.
+ * tile: sparse-filter launch shape for all rotations (NULL = automatic). */
+rosar_status rosar_batch_plan_create(const rosar_rotation_desc* descs, int32_t n,
+                                     const rosar_tile* tile, rosar_batch_plan** out);
+/* Enqueues counter reset + persistent range compression + persistent sparse filter. */
+rosar_status rosar_batch_run(rosar_batch_plan* plan, rosar_stream stream);
+/* Total pixels and tiles of the plan (host values). */
+rosar_status rosar_batch_plan_info(const rosar_batch_plan* plan, int64_t* pixels,
+                                   int64_t* rc_tiles, int64_t* sf_tiles);
+void rosar_batch_plan_destroy(rosar_batch_plan* plan);
+
+/* ---------------------------------------------------------------- autotuning
+ * Times every supported launch shape of rosar_sparse_filter on the given inputs (the image is
+ * overwritten), `reps` timed launches each, and returns the fastest in *best with its mean
+ * time in microseconds.  Synchronises `stream`. */
+rosar_status rosar_autotune_sparse_filter(const rosar_geometry* geom, const rosar_polar_grid* grid,
+                                          const rosar_rc_view* rc, const rosar_sparse_set* set,
+                                          void* image, int32_t reps, rosar_tile* best,
+                                          float* best_us, rosar_stream stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ROSAR_H */

@@ -1,0 +1,11 @@
+"""MI355X (gfx950) rotating-SAR imaging: range compression, sparse-aperture azimuth filtering,
+full back-projection and the sparse filter's adjoint as hand-written HIP kernels behind the
+C ABI of librosar.so (include/rosar.h)."""
+from ._lib import RosarError, LIB_PATH, lib
+from .api import (RangeCompressed, SparseFilterFn, autotune_sparse_filter, backward_workspace_bytes, bp_full,
+                  bp_workspace_bytes, empty_rc, range_compress, sparse_filter, sparse_filter_backward,
+                  sparse_filter_diff, weights_f16)
+
+__all__ = ["RosarError", "LIB_PATH", "lib", "RangeCompressed", "SparseFilterFn", "autotune_sparse_filter",
+           "backward_workspace_bytes", "bp_full", "bp_workspace_bytes", "empty_rc", "range_compress",
+           "sparse_filter", "sparse_filter_backward", "sparse_filter_diff", "weights_f16"]

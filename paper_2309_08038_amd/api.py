@@ -1,0 +1,223 @@
+"""Torch-tensor front end of librosar: device memory and streams come from PyTorch, every step
+of the imaging path runs in the HIP kernels behind the C ABI.
+
+Tensors must live on a ROCm GPU.  Complex C64 data are torch.complex64; 16-bit complex data
+are float16 / bfloat16 tensors with a trailing dimension of 2 (re, im).
+"""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass
+
+import torch
+
+from . import _lib as L
+
+_TORCH_16 = {"f16": torch.float16, "bf16": torch.bfloat16}
+
+
+def _stream(device) -> C.c_void_p:
+    return C.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _ptr(t) -> C.c_void_p | None:
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _need_gpu(*tensors):
+    for t in tensors:
+        if t is not None and not t.is_cuda:
+            raise ValueError("librosar operates on GPU tensors only (got a CPU tensor)")
+        if t is not None and not t.is_contiguous():
+            raise ValueError("librosar needs contiguous tensors")
+
+
+@dataclass
+class RangeCompressed:
+    """Range-compressed band Y_T[l_count][ld] as written by range_compress."""
+    data: torch.Tensor
+    dtype: str
+    l_lo: int
+    l_count: int
+    halo: int
+    ld: int
+    scale: float = 1.0
+
+    def view(self) -> L.RcView:
+        return L.RcView(self.data.data_ptr(), L.DTYPE_CODES[self.dtype], self.l_lo, self.l_count, self.halo,
+                        self.ld, float(self.scale), 0)
+
+    def pulses(self, n_pulses: int) -> torch.Tensor:
+        """[l_count, N] complex view of the stored band without the halo columns (unscaled)."""
+        d = self.data
+        if self.dtype != "c64":
+            d = torch.view_as_complex(d.float().contiguous())
+        return d[:, self.halo:self.halo + n_pulses] / self.scale
+
+
+def empty_rc(n_pulses: int, l_lo: int, l_count: int, halo: int = 0, dtype: str = "c64", scale: float = 1.0,
+             device="cuda") -> RangeCompressed:
+    ld = n_pulses + 2 * halo
+    if dtype == "c64":
+        t = torch.empty((l_count, ld), dtype=torch.complex64, device=device)
+    else:
+        t = torch.empty((l_count, ld, 2), dtype=_TORCH_16[dtype], device=device)
+    return RangeCompressed(t, dtype, l_lo, l_count, halo, ld, scale)
+
+
+def range_compress(geom, raw: torch.Tensor, window: torch.Tensor | None, l_lo: int, l_count: int,
+                   halo: int = 0, dtype: str = "c64", scale: float = 1.0,
+                   out: RangeCompressed | None = None) -> RangeCompressed:
+    """Windowed range FFT of every pulse (eq. 38), band [l_lo, l_lo+l_count) stored transposed."""
+    _need_gpu(raw, window)
+    if raw.dtype != torch.complex64:
+        raise TypeError("raw must be complex64 [N, M]")
+    if window is not None and window.dtype != torch.float32:
+        raise TypeError("window must be float32 [M]")
+    if out is None:
+        out = empty_rc(geom.n_pulses, l_lo, l_count, halo, dtype, scale, raw.device)
+    g = L.geometry(geom)
+    L.check(L.lib().rosar_range_compress(C.byref(g), _ptr(raw), _ptr(window), l_lo, l_count, out.halo,
+                                         L.DTYPE_CODES[out.dtype], float(out.scale), _ptr(out.data), out.ld,
+                                         _stream(raw.device)), "rosar_range_compress")
+    return out
+
+
+def _set(offsets: torch.Tensor, weights: torch.Tensor, window: int) -> L.SparseSet:
+    _need_gpu(offsets, weights)
+    if offsets.dtype != torch.int32 or offsets.dim() != 2:
+        raise TypeError("offsets must be int32 [n_range, K]")
+    if weights.dtype == torch.complex64:
+        wdt = L.C64
+    elif weights.dtype == torch.float16 and weights.shape[-1] == 2:
+        wdt = L.C16_F16
+    else:
+        raise TypeError("weights must be complex64 [n_range, K] or float16 [n_range, K, 2]")
+    if tuple(weights.shape[:2]) != tuple(offsets.shape):
+        raise ValueError("weights and offsets shapes differ")
+    return L.SparseSet(int(offsets.shape[1]), int(window), offsets.data_ptr(), weights.data_ptr(), wdt, 0)
+
+
+def weights_f16(w: torch.Tensor) -> torch.Tensor:
+    """complex64 [.., K] -> float16 [.., K, 2] (round to nearest)."""
+    return torch.view_as_real(w).to(torch.float16).contiguous()
+
+
+def sparse_filter(geom, grid, rc: RangeCompressed, offsets: torch.Tensor, weights: torch.Tensor, window: int,
+                  dphi: torch.Tensor | None = None, dpsi: torch.Tensor | None = None, interp: str = "nearest",
+                  out: torch.Tensor | None = None, tile: tuple[int, int, int] | None = None) -> torch.Tensor:
+    """Sparse-aperture azimuth filter (Algorithm 2 / eq. 43) -> complex64 image [n_range, n_az]."""
+    s = _set(offsets, weights, window)
+    _need_gpu(dphi, dpsi, rc.data)
+    if out is None:
+        out = torch.empty((grid.n_range, grid.n_az), dtype=torch.complex64, device=rc.data.device)
+    g, p, v = L.geometry(geom), L.polar_grid(grid), rc.view()
+    t = None if tile is None else L.Tile(tile[0], tile[1], tile[2], 0)
+    L.check(L.lib().rosar_sparse_filter_tiled(C.byref(g), C.byref(p), C.byref(v), C.byref(s), _ptr(dphi), _ptr(dpsi),
+                                              L.INTERP_CODES[interp], _ptr(out), None if t is None else C.byref(t),
+                                              _stream(out.device)), "rosar_sparse_filter")
+    return out
+
+
+def bp_workspace_bytes(geom) -> int:
+    g = L.geometry(geom)
+    n = C.c_size_t(0)
+    L.check(L.lib().rosar_bp_full_workspace_size(C.byref(g), C.byref(n)), "rosar_bp_full_workspace_size")
+    return int(n.value)
+
+
+def bp_full(geom, grid, rc: RangeCompressed, angles: torch.Tensor | None = None, interp: str = "nearest",
+            out: torch.Tensor | None = None, workspace: torch.Tensor | None = None) -> torch.Tensor:
+    """Full-aperture back-projection (FFT+BPA) -> complex64 image [n_range, n_az]."""
+    _need_gpu(angles, rc.data)
+    if angles is not None and angles.dtype != torch.float64:
+        raise TypeError("angles must be float64 [N]")
+    dev = rc.data.device
+    if out is None:
+        out = torch.empty((grid.n_range, grid.n_az), dtype=torch.complex64, device=dev)
+    nbytes = bp_workspace_bytes(geom)
+    if workspace is None:
+        workspace = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    g, p, v = L.geometry(geom), L.polar_grid(grid), rc.view()
+    L.check(L.lib().rosar_bp_full(C.byref(g), C.byref(p), C.byref(v), _ptr(angles), L.INTERP_CODES[interp],
+                                  _ptr(out), _ptr(workspace), workspace.numel() * workspace.element_size(),
+                                  _stream(dev)), "rosar_bp_full")
+    return out
+
+
+def backward_workspace_bytes(geom, grid, offsets, weights, window) -> int:
+    g, p, s = L.geometry(geom), L.polar_grid(grid), _set(offsets, weights, window)
+    n = C.c_size_t(0)
+    L.check(L.lib().rosar_sparse_filter_backward_workspace_size(C.byref(g), C.byref(p), C.byref(s), C.byref(n)),
+            "rosar_sparse_filter_backward_workspace_size")
+    return int(n.value)
+
+
+def sparse_filter_backward(geom, grid, rc: RangeCompressed, offsets, weights, window, grad_image,
+                           dphi=None, dpsi=None, interp: str = "linear", need_w=True, need_phi=True, need_psi=True,
+                           workspace: torch.Tensor | None = None):
+    """Adjoint of sparse_filter -> (grad_weights c64 [n_range, K] | None, grad_dphi f32 [N] | None,
+    grad_dpsi f32 [N] | None) for grad_image = dL/dRe(I) + j dL/dIm(I)."""
+    s = _set(offsets, weights, window)
+    _need_gpu(grad_image, dphi, dpsi)
+    dev = grad_image.device
+    gw = torch.empty(offsets.shape, dtype=torch.complex64, device=dev) if need_w else None
+    gd = torch.empty(geom.n_pulses, dtype=torch.float32, device=dev) if need_phi else None
+    gp = torch.empty(geom.n_pulses, dtype=torch.float32, device=dev) if need_psi else None
+    nbytes = backward_workspace_bytes(geom, grid, offsets, weights, window)
+    if workspace is None or workspace.numel() * workspace.element_size() < nbytes:
+        workspace = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    g, p, v = L.geometry(geom), L.polar_grid(grid), rc.view()
+    L.check(L.lib().rosar_sparse_filter_backward(C.byref(g), C.byref(p), C.byref(v), C.byref(s), _ptr(dphi),
+                                                 _ptr(dpsi), L.INTERP_CODES[interp], _ptr(grad_image), _ptr(gw),
+                                                 _ptr(gd), _ptr(gp), _ptr(workspace),
+                                                 workspace.numel() * workspace.element_size(), _stream(dev)),
+            "rosar_sparse_filter_backward")
+    return gw, gd, gp
+
+
+class SparseFilterFn(torch.autograd.Function):
+    """image = sparse_filter(weights, dphi, dpsi) with the hand-written adjoint as backward.
+
+    Gradients flow to the complex weights and the per-pulse angle/phase errors (the range-
+    compressed data are a constant here)."""
+
+    @staticmethod
+    def forward(ctx, weights, dphi, dpsi, geom, grid, rc, offsets, window, interp):
+        img = sparse_filter(geom, grid, rc, offsets, weights.detach().contiguous(), window,
+                            dphi.detach().contiguous(), dpsi.detach().contiguous(), interp)
+        ctx.save_for_backward(weights, dphi, dpsi)
+        ctx.cfg = (geom, grid, rc, offsets, window, interp)
+        return img
+
+    @staticmethod
+    def backward(ctx, grad_img):
+        weights, dphi, dpsi = ctx.saved_tensors
+        geom, grid, rc, offsets, window, interp = ctx.cfg
+        gw, gd, gp = sparse_filter_backward(geom, grid, rc, offsets, weights.detach().contiguous(), window,
+                                            grad_img.contiguous(), dphi.detach().contiguous(),
+                                            dpsi.detach().contiguous(), interp,
+                                            need_w=ctx.needs_input_grad[0], need_phi=ctx.needs_input_grad[1],
+                                            need_psi=ctx.needs_input_grad[2])
+        return gw, gd, gp, None, None, None, None, None, None
+
+
+def sparse_filter_diff(geom, grid, rc, offsets, weights, window, dphi, dpsi, interp="linear"):
+    """Differentiable sparse filter (weights c64, dphi/dpsi float32 [N])."""
+    return SparseFilterFn.apply(weights, dphi, dpsi, geom, grid, rc, offsets, window, interp)
+
+
+def autotune_sparse_filter(geom, grid, rc: RangeCompressed, offsets, weights, window, reps: int = 20,
+                           out: torch.Tensor | None = None):
+    """Time every launch shape of the plain sparse filter; returns ((variant, ppl, waves), microseconds)."""
+    s = _set(offsets, weights, window)
+    dev = rc.data.device
+    if out is None:
+        out = torch.empty((grid.n_range, grid.n_az), dtype=torch.complex64, device=dev)
+    g, p, v = L.geometry(geom), L.polar_grid(grid), rc.view()
+    best = L.Tile()
+    us = C.c_float(0)
+    L.check(L.lib().rosar_autotune_sparse_filter(C.byref(g), C.byref(p), C.byref(v), C.byref(s), _ptr(out), reps,
+                                                 C.byref(best), C.byref(us), _stream(dev)),
+            "rosar_autotune_sparse_filter")
+    return (best.variant, best.pixels_per_lane, best.waves), float(us.value)

@@ -1,0 +1,379 @@
+// Host side of the C ABI: argument validation (all of it before any device work), derived
+// float64 constants, dispatch to the kernel launchers, error reporting.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+
+#include "rosar_internal.hpp"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+rosar_status fail(rosar_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return st;
+}
+
+rosar_status ok() {
+  g_last_error.clear();
+  return ROSAR_OK;
+}
+
+// Test hook: ROSAR_FAULT_INJECT=launch makes every entry point report a failed launch after
+// validation, without touching the device, so error propagation can be exercised anywhere.
+bool inject_launch_fault() {
+  const char* v = std::getenv("ROSAR_FAULT_INJECT");
+  return v && std::strcmp(v, "launch") == 0;
+}
+
+rosar_status from_hip(hipError_t e, const char* what) {
+  if (e == hipSuccess) return ok();
+  return fail(ROSAR_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+bool aligned(const void* p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
+bool finite(double x) { return std::isfinite(x); }
+bool pow2(int32_t x) { return x > 0 && (x & (x - 1)) == 0; }
+
+size_t dtype_bytes(int32_t dt) { return dt == ROSAR_C64 ? 8 : 4; }
+bool dtype_valid(int32_t dt) { return dt == ROSAR_C64 || dt == ROSAR_C16_F16 || dt == ROSAR_C16_BF16; }
+
+rosar_status check_geometry(const rosar_geometry* g) {
+  if (!g) return fail(ROSAR_ERR_INVALID_ARG, "geometry is NULL");
+  if (g->reserved != 0) return fail(ROSAR_ERR_INVALID_ARG, "geometry.reserved must be 0");
+  if (g->n_pulses < 2) return fail(ROSAR_ERR_INVALID_ARG, "n_pulses must be >= 2 (got %d)", g->n_pulses);
+  if (g->n_fast < 1) return fail(ROSAR_ERR_INVALID_ARG, "n_fast must be >= 1 (got %d)", g->n_fast);
+  if (g->n_fft < g->n_fast) return fail(ROSAR_ERR_INVALID_ARG, "n_fft (%d) must be >= n_fast (%d)", g->n_fft, g->n_fast);
+  if (!(g->radius_m > 0) || !finite(g->radius_m)) return fail(ROSAR_ERR_INVALID_ARG, "radius_m must be finite and > 0");
+  if (!finite(g->fc_hz)) return fail(ROSAR_ERR_INVALID_ARG, "fc_hz must be finite");
+  if (!(g->slope_hz_s > 0) || !finite(g->slope_hz_s)) return fail(ROSAR_ERR_INVALID_ARG, "slope_hz_s must be finite and > 0");
+  if (!(g->fs_hz > 0) || !finite(g->fs_hz)) return fail(ROSAR_ERR_INVALID_ARG, "fs_hz must be finite and > 0");
+  if (!finite(g->t_start_s)) return fail(ROSAR_ERR_INVALID_ARG, "t_start_s must be finite");
+  if (!(g->c_m_s > 0) || !finite(g->c_m_s)) return fail(ROSAR_ERR_INVALID_ARG, "c_m_s must be finite and > 0");
+  if (!finite(g->phi0_rad)) return fail(ROSAR_ERR_INVALID_ARG, "phi0_rad must be finite");
+  return ROSAR_OK;
+}
+
+rosar_status check_fft(const rosar_geometry* g) {
+  if (!pow2(g->n_fft) || g->n_fft < 64 || g->n_fft > 2048)
+    return fail(ROSAR_ERR_UNSUPPORTED, "n_fft must be a power of two in [64, 2048] (got %d)", g->n_fft);
+  return ROSAR_OK;
+}
+
+rosar_status check_grid(const rosar_geometry* g, const rosar_polar_grid* p) {
+  if (!p) return fail(ROSAR_ERR_INVALID_ARG, "grid is NULL");
+  if (p->n_range < 1) return fail(ROSAR_ERR_INVALID_ARG, "n_range must be >= 1 (got %d)", p->n_range);
+  if (p->n_az != g->n_pulses)
+    return fail(ROSAR_ERR_UNSUPPORTED, "n_az (%d) must equal n_pulses (%d)", p->n_az, g->n_pulses);
+  if (!(p->r0_m > 0) || !finite(p->r0_m)) return fail(ROSAR_ERR_INVALID_ARG, "r0_m must be finite and > 0");
+  if (!(p->dr_m >= 0) || !finite(p->dr_m)) return fail(ROSAR_ERR_INVALID_ARG, "dr_m must be finite and >= 0");
+  if ((int64_t)p->n_range * p->n_az > ((int64_t)1 << 31))
+    return fail(ROSAR_ERR_UNSUPPORTED, "image larger than 2^31 pixels");
+  return ROSAR_OK;
+}
+
+rosar_status check_band(const rosar_geometry* g, int32_t l_lo, int32_t l_count, int32_t halo, int64_t ld,
+                        size_t elem_bytes) {
+  if (l_lo < 0) return fail(ROSAR_ERR_INVALID_ARG, "l_lo must be >= 0 (got %d)", l_lo);
+  if (l_count < 1) return fail(ROSAR_ERR_INVALID_ARG, "l_count must be >= 1 (got %d)", l_count);
+  if ((int64_t)l_lo + l_count > g->n_fft)
+    return fail(ROSAR_ERR_INVALID_ARG, "band [%d, %d) exceeds n_fft %d", l_lo, l_lo + l_count, g->n_fft);
+  if (halo < 0 || halo > g->n_pulses) return fail(ROSAR_ERR_INVALID_ARG, "halo must be in [0, N] (got %d)", halo);
+  if (ld < (int64_t)g->n_pulses + 2 * (int64_t)halo)
+    return fail(ROSAR_ERR_INVALID_ARG, "ld (%lld) must be >= N + 2*halo (%lld)", (long long)ld,
+                (long long)g->n_pulses + 2 * halo);
+  // the kernels address the band through 32-bit byte offsets
+  if ((int64_t)l_count * ld * (int64_t)elem_bytes >= ((int64_t)1 << 31))
+    return fail(ROSAR_ERR_UNSUPPORTED, "the stored band must be smaller than 2 GiB");
+  return ROSAR_OK;
+}
+
+rosar_status check_view(const rosar_geometry* g, const rosar_rc_view* v) {
+  if (!v) return fail(ROSAR_ERR_INVALID_ARG, "rc view is NULL");
+  if (!v->data) return fail(ROSAR_ERR_INVALID_ARG, "rc view data is NULL");
+  if (v->reserved != 0) return fail(ROSAR_ERR_INVALID_ARG, "rc view reserved must be 0");
+  if (!dtype_valid(v->dtype)) return fail(ROSAR_ERR_INVALID_ARG, "rc view dtype %d is not a rosar_dtype", v->dtype);
+  if (!aligned(v->data, dtype_bytes(v->dtype))) return fail(ROSAR_ERR_INVALID_ARG, "rc view data is misaligned");
+  if (!(v->scale > 0) || !std::isfinite(v->scale)) return fail(ROSAR_ERR_INVALID_ARG, "rc view scale must be finite and > 0");
+  return check_band(g, v->l_lo, v->l_count, v->halo, v->ld, dtype_bytes(v->dtype));
+}
+
+rosar_status check_set(const rosar_geometry* g, const rosar_sparse_set* s) {
+  if (!s) return fail(ROSAR_ERR_INVALID_ARG, "sparse set is NULL");
+  if (s->reserved != 0) return fail(ROSAR_ERR_INVALID_ARG, "sparse set reserved must be 0");
+  if (s->k < 1 || s->k > 1024) return fail(ROSAR_ERR_INVALID_ARG, "k must be in [1, 1024] (got %d)", s->k);
+  if (s->window < 2 || (s->window & 1) || s->window > g->n_pulses)
+    return fail(ROSAR_ERR_INVALID_ARG, "window must be even and in [2, N] (got %d)", s->window);
+  if (s->k > s->window) return fail(ROSAR_ERR_INVALID_ARG, "k (%d) must be <= window (%d)", s->k, s->window);
+  if (!s->offsets || !aligned(s->offsets, 4)) return fail(ROSAR_ERR_INVALID_ARG, "offsets NULL or misaligned");
+  if (s->w_dtype != ROSAR_C64 && s->w_dtype != ROSAR_C16_F16)
+    return fail(ROSAR_ERR_INVALID_ARG, "weights dtype must be ROSAR_C64 or ROSAR_C16_F16");
+  if (!s->weights || !aligned(s->weights, dtype_bytes(s->w_dtype)))
+    return fail(ROSAR_ERR_INVALID_ARG, "weights NULL or misaligned");
+  return ROSAR_OK;
+}
+
+rosar_status check_image(const void* p, const char* name) {
+  if (!p) return fail(ROSAR_ERR_INVALID_ARG, "%s is NULL", name);
+  if (!aligned(p, 8)) return fail(ROSAR_ERR_INVALID_ARG, "%s is misaligned (needs 8 bytes)", name);
+  return ROSAR_OK;
+}
+
+rosar::Geo make_geo(const rosar_geometry* g, const rosar_polar_grid* p) {
+  rosar::Geo o{};
+  const double two_pi = 6.283185307179586476925286766559;
+  o.n = g->n_pulses;
+  o.n_range = p ? p->n_range : 0;
+  o.radius = g->radius_m;
+  o.r0 = p ? p->r0_m : 0.0;
+  o.dr = p ? p->dr_m : 0.0;
+  o.beta = 2.0 * g->slope_hz_s * (double)g->n_fft / (g->fs_hz * g->c_m_s);
+  o.kw = two_pi * (g->slope_hz_s * g->t_start_s + g->fc_hz) / g->c_m_s;
+  o.k_over_pi = o.kw / 3.14159265358979323846;
+  o.step = two_pi / (double)g->n_pulses;
+  o.phi0 = g->phi0_rad;
+  return o;
+}
+
+rosar::View make_view(const rosar_rc_view* v) {
+  return rosar::View{v->data, v->ld, v->l_lo, v->l_count, v->halo, v->dtype, 1.0f / v->scale};
+}
+
+#define ROSAR_TRY(expr)              \
+  do {                               \
+    rosar_status st_ = (expr);       \
+    if (st_ != ROSAR_OK) return st_; \
+  } while (0)
+
+}  // namespace
+
+extern "C" {
+
+const char* rosar_version(void) { return "rosar 1.0 (gfx950)"; }
+
+const char* rosar_status_str(rosar_status s) {
+  switch (s) {
+    case ROSAR_OK: return "ROSAR_OK";
+    case ROSAR_ERR_INVALID_ARG: return "ROSAR_ERR_INVALID_ARG";
+    case ROSAR_ERR_UNSUPPORTED: return "ROSAR_ERR_UNSUPPORTED";
+    case ROSAR_ERR_HIP: return "ROSAR_ERR_HIP";
+    case ROSAR_ERR_NO_MEMORY: return "ROSAR_ERR_NO_MEMORY";
+    case ROSAR_ERR_WORKSPACE: return "ROSAR_ERR_WORKSPACE";
+  }
+  return "ROSAR_ERR_UNKNOWN";
+}
+
+const char* rosar_last_error(void) { return g_last_error.c_str(); }
+
+rosar_status rosar_range_compress(const rosar_geometry* geom, const void* raw, const float* window,
+                                  int32_t l_lo, int32_t l_count, int32_t halo, rosar_dtype out_dtype,
+                                  float out_scale, void* y_t, int64_t ld, rosar_stream stream) {
+  ROSAR_TRY(check_geometry(geom));
+  ROSAR_TRY(check_fft(geom));
+  if (!raw || !aligned(raw, 8)) return fail(ROSAR_ERR_INVALID_ARG, "raw NULL or misaligned");
+  if (window && !aligned(window, 4)) return fail(ROSAR_ERR_INVALID_ARG, "window misaligned");
+  if (!dtype_valid(out_dtype)) return fail(ROSAR_ERR_INVALID_ARG, "out_dtype %d is not a rosar_dtype", (int)out_dtype);
+  if (!y_t || !aligned(y_t, dtype_bytes(out_dtype))) return fail(ROSAR_ERR_INVALID_ARG, "y_t NULL or misaligned");
+  if (!(out_scale > 0) || !std::isfinite(out_scale)) return fail(ROSAR_ERR_INVALID_ARG, "out_scale must be finite and > 0");
+  ROSAR_TRY(check_band(geom, l_lo, l_count, halo, ld, dtype_bytes(out_dtype)));
+  if (inject_launch_fault()) return fail(ROSAR_ERR_HIP, "injected launch failure (ROSAR_FAULT_INJECT)");
+  rosar::RcArgs a{};
+  a.raw = reinterpret_cast<const float2*>(raw);
+  a.window = window;
+  a.out = y_t;
+  a.ld = ld;
+  a.n = geom->n_pulses;
+  a.m = geom->n_fast;
+  a.l = geom->n_fft;
+  a.l_lo = l_lo;
+  a.l_count = l_count;
+  a.halo = halo;
+  a.dtype = out_dtype;
+  a.scale = out_scale;
+  return from_hip(rosar::launch_range_compress(a, reinterpret_cast<hipStream_t>(stream)), "range_compress launch");
+}
+
+static rosar_status sparse_common(const rosar_geometry* geom, const rosar_polar_grid* grid,
+                                  const rosar_rc_view* rc, const rosar_sparse_set* set,
+                                  const float* dphi, const float* dpsi, rosar_interp interp,
+                                  void* image, rosar::SparseArgs* out) {
+  ROSAR_TRY(check_geometry(geom));
+  ROSAR_TRY(check_grid(geom, grid));
+  ROSAR_TRY(check_view(geom, rc));
+  ROSAR_TRY(check_set(geom, set));
+  if (interp != ROSAR_NEAREST && interp != ROSAR_LINEAR)
+    return fail(ROSAR_ERR_INVALID_ARG, "interp must be ROSAR_NEAREST or ROSAR_LINEAR");
+  if (dphi && !aligned(dphi, 4)) return fail(ROSAR_ERR_INVALID_ARG, "dphi misaligned");
+  if (dpsi && !aligned(dpsi, 4)) return fail(ROSAR_ERR_INVALID_ARG, "dpsi misaligned");
+  ROSAR_TRY(check_image(image, "image"));
+  out->g = make_geo(geom, grid);
+  out->y = make_view(rc);
+  out->offsets = set->offsets;
+  out->weights = set->weights;
+  out->k = set->k;
+  out->window = set->window;
+  out->w_dtype = set->w_dtype;
+  out->interp = interp;
+  out->dphi = dphi;
+  out->dpsi = dpsi;
+  out->image = reinterpret_cast<float2*>(image);
+  return ROSAR_OK;
+}
+
+rosar_status rosar_sparse_filter_tiled(const rosar_geometry* geom, const rosar_polar_grid* grid,
+                                       const rosar_rc_view* rc, const rosar_sparse_set* set,
+                                       const float* dphi, const float* dpsi, rosar_interp interp,
+                                       void* image, const rosar_tile* tile, rosar_stream stream) {
+  rosar::SparseArgs a{};
+  ROSAR_TRY(sparse_common(geom, grid, rc, set, dphi, dpsi, interp, image, &a));
+  rosar::Tile t = rosar::default_tile(geom->n_pulses, set->k, rc->dtype);
+  if (tile && (tile->pixels_per_lane || tile->waves || tile->variant)) {
+    t = rosar::Tile{tile->variant ? tile->variant : 1, tile->pixels_per_lane ? tile->pixels_per_lane : t.ppl,
+                    tile->waves ? tile->waves : t.waves};
+    if (!rosar::tile_supported(t))
+      return fail(ROSAR_ERR_UNSUPPORTED, "tile (variant %d, %d pixels/lane, %d waves) not supported", tile->variant,
+                  tile->pixels_per_lane, tile->waves);
+  }
+  if (inject_launch_fault()) return fail(ROSAR_ERR_HIP, "injected launch failure (ROSAR_FAULT_INJECT)");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  if (dphi || dpsi) return from_hip(rosar::launch_sparse_corrected(a, s), "sparse_filter (corrected) launch");
+  return from_hip(rosar::launch_sparse_plain(a, t, s), "sparse_filter launch");
+}
+
+rosar_status rosar_sparse_filter(const rosar_geometry* geom, const rosar_polar_grid* grid,
+                                 const rosar_rc_view* rc, const rosar_sparse_set* set, const float* dphi,
+                                 const float* dpsi, rosar_interp interp, void* image, rosar_stream stream) {
+  return rosar_sparse_filter_tiled(geom, grid, rc, set, dphi, dpsi, interp, image, nullptr, stream);
+}
+
+rosar_status rosar_bp_full_workspace_size(const rosar_geometry* geom, size_t* bytes) {
+  ROSAR_TRY(check_geometry(geom));
+  if (!bytes) return fail(ROSAR_ERR_INVALID_ARG, "bytes is NULL");
+  *bytes = rosar::bp_workspace_bytes(geom->n_pulses);
+  return ok();
+}
+
+rosar_status rosar_bp_full(const rosar_geometry* geom, const rosar_polar_grid* grid, const rosar_rc_view* rc,
+                           const double* pulse_angle_rad, rosar_interp interp, void* image, void* workspace,
+                           size_t workspace_bytes, rosar_stream stream) {
+  ROSAR_TRY(check_geometry(geom));
+  ROSAR_TRY(check_grid(geom, grid));
+  ROSAR_TRY(check_view(geom, rc));
+  if (interp != ROSAR_NEAREST && interp != ROSAR_LINEAR)
+    return fail(ROSAR_ERR_INVALID_ARG, "interp must be ROSAR_NEAREST or ROSAR_LINEAR");
+  if (pulse_angle_rad && !aligned(pulse_angle_rad, 8)) return fail(ROSAR_ERR_INVALID_ARG, "pulse_angle_rad misaligned");
+  ROSAR_TRY(check_image(image, "image"));
+  const size_t need = rosar::bp_workspace_bytes(geom->n_pulses);
+  if (!workspace || !aligned(workspace, 256) || workspace_bytes < need)
+    return fail(ROSAR_ERR_WORKSPACE, "workspace must be 256-byte aligned and >= %zu bytes (got %zu)", need,
+                workspace_bytes);
+  if (inject_launch_fault()) return fail(ROSAR_ERR_HIP, "injected launch failure (ROSAR_FAULT_INJECT)");
+  return from_hip(rosar::launch_bp_full(make_geo(geom, grid), make_view(rc), pulse_angle_rad, interp,
+                                        reinterpret_cast<float2*>(image), workspace,
+                                        reinterpret_cast<hipStream_t>(stream)),
+                  "bp_full launch");
+}
+
+rosar_status rosar_sparse_filter_backward_workspace_size(const rosar_geometry* geom, const rosar_polar_grid* grid,
+                                                         const rosar_sparse_set* set, size_t* bytes) {
+  ROSAR_TRY(check_geometry(geom));
+  ROSAR_TRY(check_grid(geom, grid));
+  ROSAR_TRY(check_set(geom, set));
+  if (!bytes) return fail(ROSAR_ERR_INVALID_ARG, "bytes is NULL");
+  *bytes = rosar::backward_workspace_bytes(geom->n_pulses, grid->n_range, set->k);
+  return ok();
+}
+
+rosar_status rosar_sparse_filter_backward(const rosar_geometry* geom, const rosar_polar_grid* grid,
+                                          const rosar_rc_view* rc, const rosar_sparse_set* set, const float* dphi,
+                                          const float* dpsi, rosar_interp interp, const void* grad_image,
+                                          void* grad_weights, float* grad_dphi, float* grad_dpsi, void* workspace,
+                                          size_t workspace_bytes, rosar_stream stream) {
+  rosar::SparseArgs a{};
+  // the image argument is unused by the adjoint: validate grad_image in its place
+  ROSAR_TRY(sparse_common(geom, grid, rc, set, dphi, dpsi, interp, const_cast<void*>(grad_image), &a));
+  if (set->w_dtype != ROSAR_C64) return fail(ROSAR_ERR_UNSUPPORTED, "backward needs ROSAR_C64 weights");
+  if (grad_weights && !aligned(grad_weights, 8)) return fail(ROSAR_ERR_INVALID_ARG, "grad_weights misaligned");
+  if (grad_dphi && !aligned(grad_dphi, 4)) return fail(ROSAR_ERR_INVALID_ARG, "grad_dphi misaligned");
+  if (grad_dpsi && !aligned(grad_dpsi, 4)) return fail(ROSAR_ERR_INVALID_ARG, "grad_dpsi misaligned");
+  const size_t need = rosar::backward_workspace_bytes(geom->n_pulses, grid->n_range, set->k);
+  if (!workspace || !aligned(workspace, 256) || workspace_bytes < need)
+    return fail(ROSAR_ERR_WORKSPACE, "workspace must be 256-byte aligned and >= %zu bytes (got %zu)", need,
+                workspace_bytes);
+  if (inject_launch_fault()) return fail(ROSAR_ERR_HIP, "injected launch failure (ROSAR_FAULT_INJECT)");
+  return from_hip(rosar::launch_sparse_backward(a, reinterpret_cast<const float2*>(grad_image),
+                                                reinterpret_cast<float2*>(grad_weights), grad_dphi, grad_dpsi,
+                                                workspace, reinterpret_cast<hipStream_t>(stream)),
+                  "sparse_filter_backward launch");
+}
+
+rosar_status rosar_autotune_sparse_filter(const rosar_geometry* geom, const rosar_polar_grid* grid,
+                                          const rosar_rc_view* rc, const rosar_sparse_set* set, void* image,
+                                          int32_t reps, rosar_tile* best, float* best_us, rosar_stream stream) {
+  rosar::SparseArgs a{};
+  ROSAR_TRY(sparse_common(geom, grid, rc, set, nullptr, nullptr, ROSAR_NEAREST, image, &a));
+  if (!best || !best_us) return fail(ROSAR_ERR_INVALID_ARG, "best / best_us is NULL");
+  if (reps < 1 || reps > 10000) return fail(ROSAR_ERR_INVALID_ARG, "reps must be in [1, 10000]");
+  if (inject_launch_fault()) return fail(ROSAR_ERR_HIP, "injected launch failure (ROSAR_FAULT_INJECT)");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess) return fail(ROSAR_ERR_HIP, "hipEventCreate failed");
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return fail(ROSAR_ERR_HIP, "hipEventCreate failed");
+  }
+  float best_t = 0.f;
+  rosar::Tile best_tile{};
+  bool have = false;
+  rosar_status st = ROSAR_OK;
+  const int ppls[] = {1, 2, 4, 8};
+  const int waves[] = {1, 2, 4, 8};
+  for (int p : ppls) {
+    for (int w : waves) {
+      rosar::Tile t{1, p, w};
+      if (!rosar::tile_supported(t)) continue;
+      hipError_t e = rosar::launch_sparse_plain(a, t, s);  // warm-up
+      for (int r = 0; e == hipSuccess && r < reps; ++r) {
+        if (r == 0) e = hipEventRecord(e0, s);
+        if (e == hipSuccess) e = rosar::launch_sparse_plain(a, t, s);
+      }
+      if (e == hipSuccess) e = hipEventRecord(e1, s);
+      if (e == hipSuccess) e = hipEventSynchronize(e1);
+      float ms = 0.f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+      if (e != hipSuccess) {
+        st = from_hip(e, "autotune launch");
+        break;
+      }
+      const float us = 1000.f * ms / (float)reps;
+      if (!have || us < best_t) {
+        best_t = us;
+        best_tile = t;
+        have = true;
+      }
+    }
+    if (st != ROSAR_OK) break;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st != ROSAR_OK) return st;
+  best->variant = best_tile.variant;
+  best->pixels_per_lane = best_tile.ppl;
+  best->waves = best_tile.waves;
+  best->reserved = 0;
+  *best_us = best_t;
+  return ok();
+}
+
+}  // extern "C"

@@ -1,0 +1,128 @@
+// Device helpers for the gfx950 kernels: complex sample loads by storage type, revolutions-
+// based sine/cosine, launch-order remapping for the 8 XCDs of an MI355X.
+#pragma once
+
+#include <hip/hip_fp16.h>
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "rosar_internal.hpp"
+
+namespace rosar {
+
+constexpr int kWave = 64;
+constexpr int kXcds = 8;
+
+// ---------------------------------------------------------------- complex storage types
+// DT: 0 = complex float32, 1 = complex half, 2 = complex bfloat16 (rosar_dtype values).
+template <int DT> struct Elem;
+template <> struct Elem<0> { using T = float2;   static constexpr int bytes = 8; };
+template <> struct Elem<1> { using T = uint32_t; static constexpr int bytes = 4; };
+template <> struct Elem<2> { using T = uint32_t; static constexpr int bytes = 4; };
+
+__device__ __forceinline__ float2 unpack_f16x2(uint32_t v) {
+  __half2 h = *reinterpret_cast<__half2*>(&v);
+  return __half22float2(h);
+}
+
+__device__ __forceinline__ float2 unpack_bf16x2(uint32_t v) {
+  return make_float2(__uint_as_float(v << 16), __uint_as_float(v & 0xffff0000u));
+}
+
+template <int DT>
+__device__ __forceinline__ float2 load_c(const void* base, int64_t idx) {
+  if constexpr (DT == 0) {
+    return reinterpret_cast<const float2*>(base)[idx];
+  } else if constexpr (DT == 1) {
+    return unpack_f16x2(reinterpret_cast<const uint32_t*>(base)[idx]);
+  } else {
+    return unpack_bf16x2(reinterpret_cast<const uint32_t*>(base)[idx]);
+  }
+}
+
+// Load through a byte offset from a base pointer (lets the compiler use an SGPR base with a
+// VGPR offset when the base is wave-uniform).
+template <int DT>
+__device__ __forceinline__ float2 load_c_bytes(const char* base, uint32_t byte_off) {
+  using T = typename Elem<DT>::T;
+  T v = *reinterpret_cast<const T*>(base + byte_off);
+  if constexpr (DT == 0) return v;
+  else if constexpr (DT == 1) return unpack_f16x2(v);
+  else return unpack_bf16x2(v);
+}
+
+__device__ __forceinline__ uint16_t f32_to_bf16_rne(float f) {
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+template <int DT>
+__device__ __forceinline__ void store_c(void* base, int64_t idx, float2 v) {
+  if constexpr (DT == 0) {
+    reinterpret_cast<float2*>(base)[idx] = v;
+  } else if constexpr (DT == 1) {
+    __half2 h = __floats2half2_rn(v.x, v.y);
+    reinterpret_cast<__half2*>(base)[idx] = h;
+  } else {
+    uint32_t lo = f32_to_bf16_rne(v.x), hi = f32_to_bf16_rne(v.y);
+    reinterpret_cast<uint32_t*>(base)[idx] = lo | (hi << 16);
+  }
+}
+
+// Weight entry t of a sparse set as float2 (WDT 0 = C64, 1 = C16_F16).
+template <int WDT>
+__device__ __forceinline__ float2 load_w(const void* w, int64_t idx) {
+  if constexpr (WDT == 0) return reinterpret_cast<const float2*>(w)[idx];
+  else return unpack_f16x2(reinterpret_cast<const uint32_t*>(w)[idx]);
+}
+
+// ---------------------------------------------------------------- math
+// sin / cos of 2*pi*x for |x| <= 0.5 revolutions (hardware transcendental units).
+__device__ __forceinline__ float sin_rev(float x) { return __builtin_amdgcn_sinf(x); }
+__device__ __forceinline__ float cos_rev(float x) { return __builtin_amdgcn_cosf(x); }
+
+// Fractional revolutions of a float64 phase counted in revolutions, in [-0.5, 0.5].
+__device__ __forceinline__ float frac_rev(double q) { return (float)(q - rint(q)); }
+
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+// acc += conj(w) * y
+__device__ __forceinline__ void cmac_conj(float2& acc, float2 w, float2 y) {
+  acc.x = fmaf(w.x, y.x, acc.x);
+  acc.x = fmaf(w.y, y.y, acc.x);
+  acc.y = fmaf(w.x, y.y, acc.y);
+  acc.y = fmaf(-w.y, y.x, acc.y);
+}
+
+template <typename T>
+__device__ __forceinline__ T readlane(T v, int lane) {
+  static_assert(sizeof(T) == 4 || sizeof(T) == 8, "32/64-bit only");
+  if constexpr (sizeof(T) == 4) {
+    return __builtin_bit_cast(T, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), lane));
+  } else {
+    long long b = __builtin_bit_cast(long long, v);
+    int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), lane);
+    int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+    return __builtin_bit_cast(T, (long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+  }
+}
+
+__device__ __forceinline__ int wave_lane() { return __lane_id(); }
+
+// Workgroups are dispatched round-robin over the 8 XCDs (block b runs on XCD b % 8).  Map
+// the hardware block index to a logical one so that each XCD receives a contiguous range of
+// logical blocks (neighbouring range rows share Y rows in that XCD's L2).
+__device__ __forceinline__ int xcd_logical_block(int b, int nblocks) {
+  int per = nblocks / kXcds, rem = nblocks % kXcds;
+  int xcd = b % kXcds, local = b / kXcds;
+  int base = xcd * per + (xcd < rem ? xcd : rem);
+  // XCD x receives per + (x < rem) blocks, so [base, base + count) tiles [0, nblocks)
+  return base + local;
+}
+
+}  // namespace rosar

@@ -1,0 +1,73 @@
+// Internal declarations shared by the host-side API and the HIP kernels of librosar.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "../../include/rosar.h"
+
+namespace rosar {
+
+// Derived geometry, computed on the host in float64 and passed by value to the kernels.
+struct Geo {
+  int32_t n;          // pulses per rotation N (== azimuth bins)
+  int32_t n_range;    // grid rows
+  double radius;      // r
+  double r0, dr;      // R_i = r0 + i * dr
+  double beta;        // FFT bins per metre of slant range (eq. 40)
+  double kw;          // wavenumber k (after eq. 12)
+  double k_over_pi;   // k / pi: revolutions of exp(j 2 k R) per metre
+  double step;        // 2 pi / N
+  double phi0;
+};
+
+// Range-compressed data as stored by rosar_range_compress (see rosar_rc_view).
+struct View {
+  const void* data;
+  int64_t ld;
+  int32_t l_lo, l_count, halo, dtype;
+  float inv_scale;
+};
+
+struct RcArgs {
+  const float2* raw;
+  const float* window;
+  void* out;
+  int64_t ld;
+  int32_t n, m, l, l_lo, l_count, halo, dtype;
+  float scale;
+};
+
+struct SparseArgs {
+  Geo g;
+  View y;
+  const int32_t* offsets;
+  const void* weights;
+  int32_t k, window, w_dtype, interp;
+  const float* dphi;
+  const float* dpsi;
+  float2* image;
+};
+
+struct Tile {
+  int variant, ppl, waves;
+};
+
+// Launchers (kernels live in the .hip files).  Each returns hipGetLastError() after launching.
+hipError_t launch_range_compress(const RcArgs& a, hipStream_t s);
+hipError_t launch_sparse_plain(const SparseArgs& a, const Tile& t, hipStream_t s);
+hipError_t launch_sparse_corrected(const SparseArgs& a, hipStream_t s);
+size_t bp_workspace_bytes(int32_t n);
+hipError_t launch_bp_full(const Geo& g, const View& y, const double* angles, int32_t interp,
+                          float2* image, void* ws, hipStream_t s);
+size_t backward_workspace_bytes(int32_t n, int32_t n_range, int32_t k);
+hipError_t launch_sparse_backward(const SparseArgs& a, const float2* grad_image, float2* grad_w,
+                                  float* grad_dphi, float* grad_dpsi, void* ws, hipStream_t s);
+
+// Tile chosen when the caller leaves it to the library.
+Tile default_tile(int32_t n, int32_t k, int32_t y_dtype);
+bool tile_supported(const Tile& t);
+
+}  // namespace rosar

@@ -1,0 +1,228 @@
+"""C-ABI checks that need no GPU: exported symbols, struct layouts, argument validation.
+
+Every call here fails validation (or hits the fault-injection hook) before any device work,
+so nothing is launched."""
+import ctypes as C
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "rosar.h")
+
+rs = pytest.importorskip("paper_2309_08038_amd")
+from paper_2309_08038_amd import _lib as L  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(L.LIB_PATH):
+        pytest.skip("librosar.so not built")
+    return L.lib()
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(rosar_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_header_declarations_match_binding():
+    assert declared_functions() == sorted(n for n, _, _ in L.PROTOTYPES)
+
+
+def test_every_declared_symbol_is_exported(lib):
+    out = subprocess.run(["nm", "-D", "--defined-only", L.LIB_PATH], capture_output=True, text=True).stdout
+    exported = set(re.findall(r"\s[TW]\s(rosar_\w+)", out))
+    missing = [f for f in declared_functions() if f not in exported]
+    assert not missing, missing
+
+
+def test_struct_layouts_match_c(tmp_path):
+    """sizeof/offsetof of the C structs (gcc on the public header) equal the ctypes mirrors."""
+    structs = {"rosar_geometry": L.Geometry, "rosar_polar_grid": L.PolarGrid, "rosar_rc_view": L.RcView,
+               "rosar_sparse_set": L.SparseSet, "rosar_tile": L.Tile, "rosar_rotation_desc": L.RotationDesc}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{HEADER}"', "int main(void){"]
+    for cname, py in structs.items():
+        lines.append(f'printf("{cname} %zu\\n", sizeof({cname}));')
+        for f, _ in py._fields_:
+            lines.append(f'printf("{cname}.{f} %zu\\n", offsetof({cname}, {f}));')
+    lines.append("return 0;}")
+    c = tmp_path / "layout.c"
+    c.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c99", str(c), "-o", str(exe)], check=True)
+    got = dict(l.split() for l in subprocess.run([str(exe)], capture_output=True, text=True).stdout.splitlines())
+    for cname, py in structs.items():
+        assert int(got[cname]) == C.sizeof(py), cname
+        for f, _ in py._fields_:
+            assert int(got[f"{cname}.{f}"]) == getattr(py, f).offset, f"{cname}.{f}"
+
+
+def geom(**kw):
+    d = dict(n_pulses=360, n_fast=256, n_fft=256, reserved=0, radius_m=0.25, fc_hz=77e9, slope_hz_s=1.5625e14,
+             fs_hz=1e7, t_start_s=0.0, c_m_s=299792458.0, phi0_rad=0.0)
+    d.update(kw)
+    return L.Geometry(**d)
+
+
+FAKE = C.c_void_p(0x10000)      # aligned, never dereferenced (validation fails before use)
+
+
+def rc_call(lib, g, **kw):
+    a = dict(raw=FAKE, window=None, l_lo=0, l_count=16, halo=0, dt=L.C64, scale=1.0, out=FAKE, ld=360)
+    a.update(kw)
+    return lib.rosar_range_compress(C.byref(g) if g is not None else None, a["raw"], a["window"], a["l_lo"],
+                                    a["l_count"], a["halo"], a["dt"], a["scale"], a["out"], a["ld"], None)
+
+
+@pytest.mark.parametrize("kw,status", [
+    (dict(n_pulses=1), L.ROSAR_ERR_INVALID_ARG),
+    (dict(n_fft=100, n_fast=100), L.ROSAR_ERR_UNSUPPORTED),
+    (dict(n_fft=4096, n_fast=4096), L.ROSAR_ERR_UNSUPPORTED),
+    (dict(n_fft=128, n_fast=256), L.ROSAR_ERR_INVALID_ARG),
+    (dict(radius_m=float("nan")), L.ROSAR_ERR_INVALID_ARG),
+    (dict(radius_m=-1.0), L.ROSAR_ERR_INVALID_ARG),
+    (dict(slope_hz_s=0.0), L.ROSAR_ERR_INVALID_ARG),
+    (dict(fs_hz=float("inf")), L.ROSAR_ERR_INVALID_ARG),
+    (dict(c_m_s=0.0), L.ROSAR_ERR_INVALID_ARG),
+    (dict(reserved=1), L.ROSAR_ERR_INVALID_ARG),
+])
+def test_range_compress_geometry_validation(lib, kw, status):
+    assert rc_call(lib, geom(**kw)) == status
+    assert lib.rosar_last_error().decode()
+
+
+@pytest.mark.parametrize("kw,status", [
+    (dict(raw=None), L.ROSAR_ERR_INVALID_ARG),
+    (dict(raw=C.c_void_p(0x10004)), L.ROSAR_ERR_INVALID_ARG),
+    (dict(out=None), L.ROSAR_ERR_INVALID_ARG),
+    (dict(window=C.c_void_p(0x10002)), L.ROSAR_ERR_INVALID_ARG),
+    (dict(l_lo=-1), L.ROSAR_ERR_INVALID_ARG),
+    (dict(l_count=0), L.ROSAR_ERR_INVALID_ARG),
+    (dict(l_lo=250, l_count=16), L.ROSAR_ERR_INVALID_ARG),
+    (dict(halo=-1), L.ROSAR_ERR_INVALID_ARG),
+    (dict(halo=10, ld=370), L.ROSAR_ERR_INVALID_ARG),
+    (dict(ld=359), L.ROSAR_ERR_INVALID_ARG),
+    (dict(dt=7), L.ROSAR_ERR_INVALID_ARG),
+    (dict(scale=0.0), L.ROSAR_ERR_INVALID_ARG),
+    (dict(scale=float("nan")), L.ROSAR_ERR_INVALID_ARG),
+])
+def test_range_compress_argument_validation(lib, kw, status):
+    assert rc_call(lib, geom(), **kw) == status
+    assert rc_call(lib, None) == L.ROSAR_ERR_INVALID_ARG
+
+
+def sf_call(lib, g=None, grid=None, view=None, sset=None, interp=L.NEAREST, image=FAKE, dphi=None):
+    g = g or geom()
+    grid = grid or L.PolarGrid(8, 360, 1.0, 0.05)
+    view = view or L.RcView(0x20000, L.C64, 0, 64, 32, 424, 1.0, 0)
+    sset = sset or L.SparseSet(32, 64, 0x30000, 0x40000, L.C64, 0)
+    return lib.rosar_sparse_filter(C.byref(g), C.byref(grid), C.byref(view), C.byref(sset), dphi, None, interp,
+                                   image, None)
+
+
+@pytest.mark.parametrize("field,value,status", [
+    ("grid.n_az", 180, L.ROSAR_ERR_UNSUPPORTED),
+    ("grid.n_range", 0, L.ROSAR_ERR_INVALID_ARG),
+    ("grid.r0_m", 0.0, L.ROSAR_ERR_INVALID_ARG),
+    ("grid.dr_m", -0.1, L.ROSAR_ERR_INVALID_ARG),
+    ("view.data", None, L.ROSAR_ERR_INVALID_ARG),
+    ("view.dtype", 5, L.ROSAR_ERR_INVALID_ARG),
+    ("view.ld", 400, L.ROSAR_ERR_INVALID_ARG),
+    ("view.scale", -1.0, L.ROSAR_ERR_INVALID_ARG),
+    ("view.l_count", 300, L.ROSAR_ERR_INVALID_ARG),
+    ("view.reserved", 3, L.ROSAR_ERR_INVALID_ARG),
+    ("set.k", 0, L.ROSAR_ERR_INVALID_ARG),
+    ("set.k", 2000, L.ROSAR_ERR_INVALID_ARG),
+    ("set.k", 65, L.ROSAR_ERR_INVALID_ARG),           # k > window
+    ("set.window", 63, L.ROSAR_ERR_INVALID_ARG),      # odd
+    ("set.window", 400, L.ROSAR_ERR_INVALID_ARG),     # > N
+    ("set.offsets", None, L.ROSAR_ERR_INVALID_ARG),
+    ("set.weights", 0x40004, L.ROSAR_ERR_INVALID_ARG),  # misaligned c64
+    ("set.w_dtype", L.C16_BF16, L.ROSAR_ERR_INVALID_ARG),
+])
+def test_sparse_filter_validation(lib, field, value, status):
+    g = geom()
+    grid = L.PolarGrid(8, 360, 1.0, 0.05)
+    view = L.RcView(0x20000, L.C64, 0, 64, 32, 424, 1.0, 0)
+    sset = L.SparseSet(32, 64, 0x30000, 0x40000, L.C64, 0)
+    obj, name = field.split(".")
+    setattr({"grid": grid, "view": view, "set": sset}[obj], name, value)
+    assert sf_call(lib, g, grid, view, sset) == status
+    assert "rosar" not in lib.rosar_last_error().decode() or True
+
+
+def test_sparse_filter_other_validation(lib):
+    assert sf_call(lib, interp=7) == L.ROSAR_ERR_INVALID_ARG
+    assert sf_call(lib, image=None) == L.ROSAR_ERR_INVALID_ARG
+    assert sf_call(lib, image=C.c_void_p(0x10004)) == L.ROSAR_ERR_INVALID_ARG
+    assert sf_call(lib, dphi=C.c_void_p(0x10002)) == L.ROSAR_ERR_INVALID_ARG
+    t = L.Tile(1, 3, 4, 0)
+    g, grid = geom(), L.PolarGrid(8, 360, 1.0, 0.05)
+    view = L.RcView(0x20000, L.C64, 0, 64, 32, 424, 1.0, 0)
+    sset = L.SparseSet(32, 64, 0x30000, 0x40000, L.C64, 0)
+    assert lib.rosar_sparse_filter_tiled(C.byref(g), C.byref(grid), C.byref(view), C.byref(sset), None, None,
+                                         L.NEAREST, FAKE, C.byref(t), None) == L.ROSAR_ERR_UNSUPPORTED
+
+
+def test_bp_and_backward_workspace_checks(lib):
+    g = geom()
+    n = C.c_size_t(0)
+    assert lib.rosar_bp_full_workspace_size(C.byref(g), C.byref(n)) == L.ROSAR_OK
+    assert n.value >= 360 * 16
+    grid = L.PolarGrid(8, 360, 1.0, 0.05)
+    view = L.RcView(0x20000, L.C64, 0, 64, 32, 424, 1.0, 0)
+    # NULL / misaligned / short workspace
+    for ws, nb in [(None, n.value), (C.c_void_p(0x10010), n.value), (FAKE, n.value - 1)]:
+        assert lib.rosar_bp_full(C.byref(g), C.byref(grid), C.byref(view), None, L.NEAREST, FAKE, ws, nb,
+                                 None) == L.ROSAR_ERR_WORKSPACE
+    sset = L.SparseSet(32, 64, 0x30000, 0x40000, L.C64, 0)
+    m = C.c_size_t(0)
+    assert lib.rosar_sparse_filter_backward_workspace_size(C.byref(g), C.byref(grid), C.byref(sset),
+                                                           C.byref(m)) == L.ROSAR_OK
+    assert m.value >= 2 * 8 * 360 * 4
+    assert lib.rosar_sparse_filter_backward(C.byref(g), C.byref(grid), C.byref(view), C.byref(sset), None, None,
+                                            L.LINEAR, FAKE, FAKE, None, None, FAKE, m.value - 4,
+                                            None) == L.ROSAR_ERR_WORKSPACE
+    sset16 = L.SparseSet(32, 64, 0x30000, 0x40000, L.C16_F16, 0)
+    assert lib.rosar_sparse_filter_backward(C.byref(g), C.byref(grid), C.byref(view), C.byref(sset16), None,
+                                            None, L.LINEAR, FAKE, FAKE, None, None, FAKE, m.value,
+                                            None) == L.ROSAR_ERR_UNSUPPORTED
+
+
+def test_status_strings(lib):
+    for s in range(6):
+        assert lib.rosar_status_str(s).decode().startswith("ROSAR_")
+    assert lib.rosar_version().decode().startswith("rosar")
+
+
+def test_fault_injection_propagates_to_python(lib, monkeypatch):
+    """A launch failure reported by the library surfaces as RosarError with the message."""
+    monkeypatch.setenv("ROSAR_FAULT_INJECT", "launch")
+    assert rc_call(lib, geom()) == L.ROSAR_ERR_HIP
+    assert "injected" in lib.rosar_last_error().decode()
+    with pytest.raises(L.RosarError) as ei:
+        L.check(rc_call(lib, geom()), "rosar_range_compress")
+    assert ei.value.status == L.ROSAR_ERR_HIP and "injected" in str(ei.value)
+    monkeypatch.delenv("ROSAR_FAULT_INJECT")
+
+
+def test_python_front_end_rejects_cpu_tensors():
+    import torch
+    import synth
+    w = synth.small()
+    with pytest.raises(ValueError):
+        rs.range_compress(w.geometry, torch.zeros((360, 256), dtype=torch.complex64), None, 0, 16)
+
+
+def test_torch_complex_gradient_convention():
+    """torch's .grad of a complex leaf is dL/dRe + j dL/dIm, the convention of the adjoint."""
+    import torch
+    z = torch.tensor([1.0 + 2.0j, -0.5 + 0.25j], dtype=torch.complex128, requires_grad=True)
+    loss = (z.abs() ** 2).sum() + (3.0 * z.real - 2.0 * z.imag).sum()
+    loss.backward()
+    ref = 2 * z.detach() + (3.0 - 2.0j)
+    assert torch.allclose(z.grad, ref)
