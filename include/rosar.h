@@ -67,7 +67,7 @@ typedef enum rosar_dtype {
 typedef enum rosar_interp { ROSAR_NEAREST = 0, ROSAR_LINEAR = 1 } rosar_interp;
 
 /* Radar and rotation (paper Table I/II notation).  n_fft (L) must be a power of two in
- * [64, 4096] with L >= n_fast (M); zero padding when L > M (eq. 38). */
+ * [64, 2048] with L >= n_fast (M); zero padding when L > M (eq. 38). */
 typedef struct rosar_geometry {
   int32_t n_pulses;   /* N: pulses per rotation, >= 2 */
   int32_t n_fast;     /* M: fast-time samples per pulse, >= 1 */
@@ -121,7 +121,7 @@ typedef struct rosar_sparse_set {
 /* Launch shape of the sparse filter (0 = let the library choose).  The project's autotuner
  * (rosar_autotune_sparse_filter) searches these. */
 typedef struct rosar_tile {
-  int32_t variant;        /* 0 auto, 1 direct cached loads, 2 LDS-staged window */
+  int32_t variant;        /* 0 auto; 1 direct cached loads; 2 LDS-staged window; 3 LDS-staged window read as pixel pairs (2 and 3 fall back to 1 when the window does not fit in LDS) */
   int32_t pixels_per_lane;/* 1, 2, 4 or 8 */
   int32_t waves;          /* waves per workgroup: 1, 2, 4 or 8 */
   int32_t reserved;
@@ -140,7 +140,7 @@ const char* rosar_last_error(void);
  *   window [M] float32, or NULL for a rectangular window.
  *   y_t    [l_count][ld] of out_dtype, ld >= N + 2*halo; written, never read.
  * Errors: INVALID_ARG for null/misaligned pointers or bad sizes; UNSUPPORTED for L not a
- * power of two in [64, 4096]. */
+ * power of two in [64, 2048]. */
 rosar_status rosar_range_compress(const rosar_geometry* geom, const void* raw, const float* window,
                                   int32_t l_lo, int32_t l_count, int32_t halo,
                                   rosar_dtype out_dtype, float out_scale,

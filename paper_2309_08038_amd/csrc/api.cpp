@@ -339,9 +339,9 @@ rosar_status rosar_autotune_sparse_filter(const rosar_geometry* geom, const rosa
   rosar_status st = ROSAR_OK;
   const int ppls[] = {1, 2, 4, 8};
   const int waves[] = {1, 2, 4, 8};
-  for (int p : ppls) {
+  for (int v = 1; v <= 3 && st == ROSAR_OK; ++v) for (int p : ppls) {
     for (int w : waves) {
-      rosar::Tile t{1, p, w};
+      rosar::Tile t{v, p, w};
       if (!rosar::tile_supported(t)) continue;
       hipError_t e = rosar::launch_sparse_plain(a, t, s);  // warm-up
       for (int r = 0; e == hipSuccess && r < reps; ++r) {

@@ -83,7 +83,7 @@ def test_sparse_filter_small_end_to_end():
     assert rel_l2(img.cpu().numpy(), ref) <= TOL
 
 
-SHAPES = [(1, p, nw) for p in (1, 2, 4, 8) for nw in (1, 2, 4, 8) if not (p == 8 and nw == 8)]
+SHAPES = [(v, p, nw) for v in (1, 2, 3) for p in (1, 2, 4, 8) for nw in (1, 2, 4, 8) if not (p == 8 and nw == 8)]
 
 
 def test_sparse_filter_launch_shapes_bit_identical():
@@ -360,8 +360,10 @@ def test_reduced_precision_small(dtype):
     log(f"reduced precision small {dtype}")
     scale = 2.0 ** -4 if dtype == "f16" else 1.0
     rc, off, wts = upload(w, x, dtype=dtype, scale=scale, rs=rs)
-    img = rs.sparse_filter(w.geometry, w.grid, rc, off, rs.weights_f16(wts), w.sparse.window).cpu().numpy()
     ref = oracle.sparse_filter(oracle_band("small"), x.l_lo, w.geometry, w.grid, x.offsets, x.weights)
-    assert rel_l2(img, ref) <= 1e-2
+    for tile in (None, (1, 4, 4), (2, 8, 2)):
+        for wt in (wts, rs.weights_f16(wts)):
+            img = rs.sparse_filter(w.geometry, w.grid, rc, off, wt, w.sparse.window, tile=tile).cpu().numpy()
+            assert rel_l2(img, ref) <= 1e-2, (tile, wt.dtype)
     bpa = rs.bp_full(w.geometry, w.grid, rc).cpu().numpy()
     assert rel_l2(bpa, oracle.bp_full(oracle_band("small"), x.l_lo, w.geometry, w.grid)) <= 1e-2
