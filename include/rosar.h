@@ -224,8 +224,13 @@ typedef struct rosar_rotation_desc {
 
 typedef struct rosar_batch_plan rosar_batch_plan;
 
-/* Validates every descriptor (host), uploads a device descriptor table and tile prefix sums.
- * tile: sparse-filter launch shape for all rotations (NULL = automatic). */
+/* Validates every descriptor (host), uploads a device descriptor table and tile prefix sums
+ * (the plan owns that device memory until rosar_batch_plan_destroy).  tile: sparse-filter
+ * launch shape for all rotations (pixels_per_lane x waves in {1x4, 2x4, 4x4, 8x4, 2x2, 4x2,
+ * 8x2, 4x8}; NULL = 4x4).  Every descriptor obeys the rules of rosar_range_compress and
+ * rosar_sparse_filter (C64 data and weights); the halo should cover half the window (staging
+ * falls back to element copies otherwise).  y_t is written by the run (range compression) and
+ * read by its sparse filter; images are overwritten.  Errors name the offending rotation. */
 rosar_status rosar_batch_plan_create(const rosar_rotation_desc* descs, int32_t n,
                                      const rosar_tile* tile, rosar_batch_plan** out);
 /* Enqueues counter reset + persistent range compression + persistent sparse filter. */
@@ -234,6 +239,11 @@ rosar_status rosar_batch_run(rosar_batch_plan* plan, rosar_stream stream);
 rosar_status rosar_batch_plan_info(const rosar_batch_plan* plan, int64_t* pixels,
                                    int64_t* rc_tiles, int64_t* sf_tiles);
 void rosar_batch_plan_destroy(rosar_batch_plan* plan);
+/* Project autotuner for batches: builds a plan for every supported sparse-filter launch shape,
+ * times `reps` runs of each on `stream` (outputs are overwritten) and returns the fastest
+ * shape in *best with its mean run time in microseconds.  Synchronises `stream`. */
+rosar_status rosar_batch_autotune(const rosar_rotation_desc* descs, int32_t n, int32_t reps,
+                                  rosar_tile* best, float* best_us, rosar_stream stream);
 
 /* ---------------------------------------------------------------- autotuning
  * Times every supported launch shape of rosar_sparse_filter on the given inputs (the image is

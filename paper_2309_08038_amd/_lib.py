@@ -75,6 +75,8 @@ PROTOTYPES = [
     ("rosar_batch_run", C.c_int, [C.c_void_p, C.c_void_p]),
     ("rosar_batch_plan_info", C.c_int, [C.c_void_p, _P(C.c_int64), _P(C.c_int64), _P(C.c_int64)]),
     ("rosar_batch_plan_destroy", None, [C.c_void_p]),
+    ("rosar_batch_autotune", C.c_int, [_P(RotationDesc), C.c_int32, C.c_int32, _P(Tile), _P(C.c_float),
+                                      C.c_void_p]),
     ("rosar_autotune_sparse_filter", C.c_int, [_P(Geometry), _P(PolarGrid), _P(RcView), _P(SparseSet),
                                               C.c_void_p, C.c_int32, _P(Tile), _P(C.c_float), C.c_void_p]),
 ]

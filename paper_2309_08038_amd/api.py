@@ -221,3 +221,79 @@ def autotune_sparse_filter(geom, grid, rc: RangeCompressed, offsets, weights, wi
                                                  C.byref(best), C.byref(us), _stream(dev)),
             "rosar_autotune_sparse_filter")
     return (best.variant, best.pixels_per_lane, best.waves), float(us.value)
+
+
+@dataclass
+class Rotation:
+    """One rotation of a batch: inputs, the range-compressed scratch and the output image."""
+    geom: object
+    grid: object
+    raw: torch.Tensor
+    window: torch.Tensor | None
+    rc: RangeCompressed
+    offsets: torch.Tensor
+    weights: torch.Tensor
+    sparse_window: int
+    image: torch.Tensor
+
+    def desc(self) -> L.RotationDesc:
+        _need_gpu(self.raw, self.window, self.offsets, self.weights, self.image, self.rc.data)
+        if self.rc.dtype != "c64" or self.weights.dtype != torch.complex64:
+            raise TypeError("batched rotations use complex64 data and weights")
+        return L.RotationDesc(L.geometry(self.geom), L.polar_grid(self.grid), self.raw.data_ptr(),
+                              None if self.window is None else self.window.data_ptr(), self.rc.data.data_ptr(),
+                              self.rc.l_lo, self.rc.l_count, self.rc.halo, 0, self.rc.ld,
+                              _set(self.offsets, self.weights, self.sparse_window), self.image.data_ptr())
+
+
+def _descs(rotations):
+    arr = (L.RotationDesc * len(rotations))()
+    for i, r in enumerate(rotations):
+        arr[i] = r.desc()
+    return arr
+
+
+class BatchPlan:
+    """Persistent batched imaging of many rotations (range compression + sparse filter).
+
+    The plan keeps device pointers to the rotations' tensors: keep them alive and unmoved
+    while the plan is used."""
+
+    def __init__(self, rotations, tile: tuple[int, int] | None = None):
+        self.rotations = list(rotations)
+        self._descs = _descs(self.rotations)
+        t = None if tile is None else L.Tile(1, tile[0], tile[1], 0)
+        h = C.c_void_p()
+        L.check(L.lib().rosar_batch_plan_create(self._descs, len(self.rotations), None if t is None else C.byref(t),
+                                                C.byref(h)), "rosar_batch_plan_create")
+        self._h = h
+        self.device = self.rotations[0].raw.device
+
+    def run(self):
+        L.check(L.lib().rosar_batch_run(self._h, _stream(self.device)), "rosar_batch_run")
+
+    def info(self):
+        px, rc, sf = C.c_int64(), C.c_int64(), C.c_int64()
+        L.check(L.lib().rosar_batch_plan_info(self._h, C.byref(px), C.byref(rc), C.byref(sf)), "rosar_batch_plan_info")
+        return int(px.value), int(rc.value), int(sf.value)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            L.lib().rosar_batch_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def batch_autotune(rotations, reps: int = 3):
+    """Time every batch launch shape; returns ((pixels_per_lane, waves), microseconds per run)."""
+    descs = _descs(rotations)
+    best = L.Tile()
+    us = C.c_float(0)
+    L.check(L.lib().rosar_batch_autotune(descs, len(rotations), reps, C.byref(best), C.byref(us),
+                                         _stream(rotations[0].raw.device)), "rosar_batch_autotune")
+    return (best.pixels_per_lane, best.waves), float(us.value)

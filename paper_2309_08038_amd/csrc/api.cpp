@@ -158,6 +158,37 @@ rosar::View make_view(const rosar_rc_view* v) {
 
 }  // namespace
 
+namespace rosar {
+
+rosar_status set_error(rosar_status st, const std::string& msg) {
+  g_last_error = msg;
+  return st;
+}
+
+void clear_error() { g_last_error.clear(); }
+
+Geo geo_of(const rosar_geometry* g, const rosar_polar_grid* p) { return make_geo(g, p); }
+
+// A batched rotation: NEAREST, uncorrected, complex float32 data and weights.
+rosar_status validate_rotation(const rosar_rotation_desc& d, int index) {
+  rosar_status st = check_geometry(&d.geom);
+  if (st == ROSAR_OK) st = check_fft(&d.geom);
+  if (st == ROSAR_OK) st = check_grid(&d.geom, &d.grid);
+  if (st == ROSAR_OK && d.reserved != 0) st = fail(ROSAR_ERR_INVALID_ARG, "descriptor reserved must be 0");
+  if (st == ROSAR_OK && (!d.raw || !aligned(d.raw, 8))) st = fail(ROSAR_ERR_INVALID_ARG, "raw NULL or misaligned");
+  if (st == ROSAR_OK && d.window && !aligned(d.window, 4)) st = fail(ROSAR_ERR_INVALID_ARG, "window misaligned");
+  if (st == ROSAR_OK && (!d.y_t || !aligned(d.y_t, 8))) st = fail(ROSAR_ERR_INVALID_ARG, "y_t NULL or misaligned");
+  if (st == ROSAR_OK) st = check_band(&d.geom, d.l_lo, d.l_count, d.halo, d.ld, 8);
+  if (st == ROSAR_OK) st = check_set(&d.geom, &d.set);
+  if (st == ROSAR_OK && d.set.w_dtype != ROSAR_C64)
+    st = fail(ROSAR_ERR_UNSUPPORTED, "batched rotations need ROSAR_C64 weights");
+  if (st == ROSAR_OK) st = check_image(d.image, "image");
+  if (st != ROSAR_OK) g_last_error = "rotation " + std::to_string(index) + ": " + g_last_error;
+  return st;
+}
+
+}  // namespace rosar
+
 extern "C" {
 
 const char* rosar_version(void) { return "rosar 1.0 (gfx950)"; }

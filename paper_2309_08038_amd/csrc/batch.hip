@@ -1,37 +1,367 @@
-// Batched rotations: persistent range-compression and sparse-filter launches over many
-// rotations of uneven size (placeholder until the persistent kernels land).
-#include "rosar_device.hpp"
+// Batched rotations: many independent rotations of uneven pulse, sample and range-row counts
+// imaged by one persistent range-compression launch and one persistent sparse-filter launch.
+//
+// The plan uploads one descriptor per rotation (derived float64 geometry, band, pointers,
+// LDS layout) and the prefix sums of their tile counts.  Workgroups of each persistent kernel
+// take tile indices from a device counter; a tile index is mapped to its rotation by binary
+// search over the prefix sums and processed by the same block functions the single-rotation
+// kernels use (fft::rc_block, sparse::lds_tile), so a batched image equals the image of the
+// single-rotation call with the same launch shape, bit for bit.  The counters are reset by the
+// plan's own kernel at the start of every run: the three launches can be captured in a HIP
+// graph and replayed.  Every workgroup leaves its loop once the counter passes the tile total.
+#include <algorithm>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "fft_device.hpp"
+#include "sparse_device.hpp"
+
+namespace rosar {
+namespace {
+
+constexpr int kBatchP = 4;       // default sparse-filter shape of a batch: 4 pixels per lane,
+constexpr int kBatchWaves = 4;   // 4 waves (1024-pixel tiles)
+
+struct BatchRot {
+  RcArgs rc;                 // range compression of this rotation
+  Geo g;                     // sparse filter geometry
+  View y;
+  const int32_t* offsets;
+  const void* weights;
+  float2* image;
+  int32_t k, window;
+  int32_t rows_cap, stride, dma, tiles_per_row;
+  int32_t rc_tile0, sf_tile0;  // first global tile of this rotation in each kernel
+  int32_t rc_pw;               // pulses per range-compression tile
+};
+
+__device__ __forceinline__ int find_rotation(const BatchRot* rots, int nrot, int t, bool rc) {
+  int lo = 0, hi = nrot - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    const int t0 = rc ? rots[mid].rc_tile0 : rots[mid].sf_tile0;
+    if (t0 <= t) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+__global__ void batch_reset_kernel(int* counters) {
+  if (threadIdx.x < 2) counters[threadIdx.x] = 0;
+}
+
+__global__ __launch_bounds__(fft::kRcThreads) void batch_rc_kernel(const BatchRot* __restrict__ rots, int nrot,
+                                                                    int total, int* counter) {
+  extern __shared__ __align__(16) float2 lds[];
+  __shared__ int s_t;
+  for (;;) {
+    if (threadIdx.x == 0) s_t = atomicAdd(counter, 1);
+    __syncthreads();
+    const int t = s_t;
+    __syncthreads();
+    if (t >= total) break;
+    const int i = find_rotation(rots, nrot, t, true);
+    const RcArgs a = rots[i].rc;
+    const int n0 = (t - rots[i].rc_tile0) * rots[i].rc_pw;
+    switch (a.l) {
+      case 64: fft::rc_block<64, 2, 0>(a, n0, lds); break;
+      case 128: fft::rc_block<128, 2, 0>(a, n0, lds); break;
+      case 256: fft::rc_block<256, 2, 0>(a, n0, lds); break;
+      case 512: fft::rc_block<512, 2, 0>(a, n0, lds); break;
+      case 1024: fft::rc_block<1024, 2, 0>(a, n0, lds); break;
+      default: fft::rc_block<2048, 1, 0>(a, n0, lds); break;
+    }
+    __syncthreads();  // the next tile reuses the LDS
+  }
+}
+
+template <int P, int NW>
+__global__ __launch_bounds__(kWave* NW) void batch_sf_kernel(const BatchRot* __restrict__ rots, int nrot,
+                                                              int total, int* counter) {
+  extern __shared__ __align__(16) char smem[];
+  __shared__ int s_t;
+  __shared__ int s_unstaged;
+  for (;;) {
+    if (threadIdx.x == 0) s_t = atomicAdd(counter, 1);
+    __syncthreads();
+    const int t = s_t;
+    __syncthreads();
+    if (t >= total) break;
+    const int i = find_rotation(rots, nrot, t, false);
+    const BatchRot& R = rots[i];
+    const int local = t - R.sf_tile0;
+    const int row = local / R.tiles_per_row;
+    sparse::lds_tile<ROSAR_C64, ROSAR_C64, ROSAR_NEAREST, P, NW>(
+        R.g, R.y, R.k, R.window, row, local - row * R.tiles_per_row, R.rows_cap, R.stride, R.dma, R.offsets,
+        R.weights, reinterpret_cast<const char*>(R.y.data), R.image, smem, s_unstaged);
+    __syncthreads();  // the next tile reuses the LDS
+  }
+}
+
+template <int P, int NW>
+struct SfKernel {
+  static const void* fn() { return reinterpret_cast<const void*>(&batch_sf_kernel<P, NW>); }
+  static void launch(dim3 grid, size_t lds, hipStream_t s, const BatchRot* r, int n, int total, int* c) {
+    batch_sf_kernel<P, NW><<<grid, kWave * NW, lds, s>>>(r, n, total, c);
+  }
+};
+
+rosar_status bfail(rosar_status st, const std::string& m) { return set_error(st, m); }
+
+}  // namespace
+}  // namespace rosar
 
 struct rosar_batch_plan {
-  int32_t n;
+  int n = 0;
+  int device = -1;
+  int ppl = rosar::kBatchP, waves = rosar::kBatchWaves;
+  rosar::BatchRot* d_rots = nullptr;
+  int* d_counters = nullptr;
+  int rc_total = 0, sf_total = 0;
+  int64_t pixels = 0;
+  size_t rc_lds = 0, sf_lds = 0;
+  int rc_grid = 0, sf_grid = 0;
 };
+
+namespace rosar {
+
+namespace {
+
+template <int P, int NW>
+rosar_status plan_shape(const std::vector<BatchRot>& hv, rosar_batch_plan* pl, int cus) {
+  (void)hv;
+  int occ = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, SfKernel<P, NW>::fn(), kWave * NW, pl->sf_lds) !=
+      hipSuccess || occ < 1)
+    return bfail(ROSAR_ERR_HIP, "occupancy query for the batched sparse-filter kernel failed");
+  pl->sf_grid = cus * occ;
+  return ROSAR_OK;
+}
+
+template <int P, int NW>
+void run_shape(rosar_batch_plan* pl, hipStream_t s) {
+  SfKernel<P, NW>::launch(dim3(pl->sf_grid), pl->sf_lds, s, pl->d_rots, pl->n, pl->sf_total, pl->d_counters + 1);
+}
+
+#define ROSAR_BATCH_SHAPES(X) X(1, 4) X(2, 4) X(4, 4) X(8, 4) X(2, 2) X(4, 2) X(8, 2) X(4, 8)
+
+bool batch_shape_supported(int p, int nw) {
+#define ROSAR_CHECK(P, NW) if (p == P && nw == NW) return true;
+  ROSAR_BATCH_SHAPES(ROSAR_CHECK)
+#undef ROSAR_CHECK
+  return false;
+}
+
+}  // namespace
+}  // namespace rosar
 
 extern "C" {
 
 rosar_status rosar_batch_plan_create(const rosar_rotation_desc* descs, int32_t n, const rosar_tile* tile,
                                      rosar_batch_plan** out) {
-  (void)descs;
-  (void)n;
-  (void)tile;
-  if (out) *out = nullptr;
-  return ROSAR_ERR_UNSUPPORTED;
+  using namespace rosar;
+  clear_error();
+  if (!out) return bfail(ROSAR_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  if (!descs || n < 1 || n > 65536) return bfail(ROSAR_ERR_INVALID_ARG, "need 1..65536 rotation descriptors");
+  int p = kBatchP, nw = kBatchWaves;
+  if (tile && (tile->pixels_per_lane || tile->waves)) {
+    p = tile->pixels_per_lane ? tile->pixels_per_lane : p;
+    nw = tile->waves ? tile->waves : nw;
+  }
+  if (!batch_shape_supported(p, nw))
+    return bfail(ROSAR_ERR_UNSUPPORTED, "batch launch shape (" + std::to_string(p) + " pixels/lane, " +
+                                            std::to_string(nw) + " waves) not supported");
+  const int tpx = kWave * p * nw;
+  std::vector<BatchRot> hv(n);
+  int64_t rc_total = 0, sf_total = 0, pixels = 0;
+  size_t rc_lds = 0, sf_lds = 0;
+  for (int i = 0; i < n; ++i) {
+    const rosar_rotation_desc& d = descs[i];
+    const rosar_status st = validate_rotation(d, i);
+    if (st != ROSAR_OK) return st;
+    BatchRot& R = hv[i];
+    std::memset(&R, 0, sizeof(R));
+    R.rc.raw = reinterpret_cast<const float2*>(d.raw);
+    R.rc.window = d.window;
+    R.rc.out = d.y_t;
+    R.rc.ld = d.ld;
+    R.rc.n = d.geom.n_pulses;
+    R.rc.m = d.geom.n_fast;
+    R.rc.l = d.geom.n_fft;
+    R.rc.l_lo = d.l_lo;
+    R.rc.l_count = d.l_count;
+    R.rc.halo = d.halo;
+    R.rc.dtype = ROSAR_C64;
+    R.rc.scale = 1.0f;
+    R.rc_pw = fft::kRcWaves * fft::kRcPulsesPerWave(d.geom.n_fft);
+    R.g = geo_of(&d.geom, &d.grid);
+    R.y = View{d.y_t, d.ld, d.l_lo, d.l_count, d.halo, ROSAR_C64, 1.0f};
+    R.offsets = d.set.offsets;
+    R.weights = d.set.weights;
+    R.image = reinterpret_cast<float2*>(d.image);
+    R.k = d.set.k;
+    R.window = d.set.window;
+    // staged rows capped so that the window fits the LDS budget; capped taps go through the guard
+    const sparse::LdsLayout L = sparse::lds_layout_capped(R.g, R.y, R.k, R.window, ROSAR_NEAREST, tpx);
+    if (L.bytes > sparse::kLdsBudget)
+      return bfail(ROSAR_ERR_UNSUPPORTED, "rotation " + std::to_string(i) + ": window does not fit in LDS");
+    R.rows_cap = L.rows;
+    R.stride = L.stride;
+    R.dma = L.dma;
+    R.tiles_per_row = (R.g.n + tpx - 1) / tpx;
+    R.rc_tile0 = (int32_t)rc_total;
+    R.sf_tile0 = (int32_t)sf_total;
+    rc_total += (R.rc.n + R.rc_pw - 1) / R.rc_pw;
+    sf_total += (int64_t)R.tiles_per_row * R.g.n_range;
+    pixels += (int64_t)R.g.n * R.g.n_range;
+    rc_lds = std::max(rc_lds, (size_t)fft::rc_lds_elems(R.rc.l, fft::kRcPulsesPerWave(R.rc.l)) * sizeof(float2));
+    sf_lds = std::max(sf_lds, L.bytes);
+  }
+  if (rc_total >= INT32_MAX / 2 || sf_total >= INT32_MAX / 2)
+    return bfail(ROSAR_ERR_UNSUPPORTED, "too many tiles in one batch");
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) !=
+                                              hipSuccess)
+    return bfail(ROSAR_ERR_HIP, "cannot query the current device");
+  auto* pl = new (std::nothrow) rosar_batch_plan();
+  if (!pl) return bfail(ROSAR_ERR_NO_MEMORY, "host allocation failed");
+  pl->n = n;
+  pl->device = dev;
+  pl->ppl = p;
+  pl->waves = nw;
+  pl->rc_total = (int)rc_total;
+  pl->sf_total = (int)sf_total;
+  pl->pixels = pixels;
+  pl->rc_lds = rc_lds;
+  pl->sf_lds = sf_lds;
+  int occ = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, reinterpret_cast<const void*>(&batch_rc_kernel),
+                                                   fft::kRcThreads, rc_lds) != hipSuccess || occ < 1) {
+    delete pl;
+    return bfail(ROSAR_ERR_HIP, "occupancy query for the batched range-compression kernel failed");
+  }
+  pl->rc_grid = cus * occ;
+  rosar_status st = ROSAR_ERR_UNSUPPORTED;
+#define ROSAR_PLAN(P, NW) if (p == P && nw == NW) st = plan_shape<P, NW>(hv, pl, cus);
+  ROSAR_BATCH_SHAPES(ROSAR_PLAN)
+#undef ROSAR_PLAN
+  if (st != ROSAR_OK) {
+    delete pl;
+    return st;
+  }
+  if (hipMalloc(&pl->d_rots, sizeof(BatchRot) * n) != hipSuccess) {
+    delete pl;
+    return bfail(ROSAR_ERR_NO_MEMORY, "device allocation of the descriptor table failed");
+  }
+  if (hipMalloc(&pl->d_counters, 2 * sizeof(int)) != hipSuccess) {
+    (void)hipFree(pl->d_rots);
+    delete pl;
+    return bfail(ROSAR_ERR_NO_MEMORY, "device allocation of the work counters failed");
+  }
+  if (hipMemcpy(pl->d_rots, hv.data(), sizeof(BatchRot) * n, hipMemcpyHostToDevice) != hipSuccess) {
+    (void)hipFree(pl->d_rots);
+    (void)hipFree(pl->d_counters);
+    delete pl;
+    return bfail(ROSAR_ERR_HIP, "upload of the descriptor table failed");
+  }
+  *out = pl;
+  return ROSAR_OK;
 }
 
-rosar_status rosar_batch_run(rosar_batch_plan* plan, rosar_stream stream) {
-  (void)plan;
-  (void)stream;
-  return ROSAR_ERR_UNSUPPORTED;
+rosar_status rosar_batch_run(rosar_batch_plan* pl, rosar_stream stream) {
+  using namespace rosar;
+  clear_error();
+  if (!pl) return bfail(ROSAR_ERR_INVALID_ARG, "plan is NULL");
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev != pl->device)
+    return bfail(ROSAR_ERR_INVALID_ARG, "plan was created on another device");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  batch_reset_kernel<<<1, 64, 0, s>>>(pl->d_counters);
+  batch_rc_kernel<<<pl->rc_grid, fft::kRcThreads, pl->rc_lds, s>>>(pl->d_rots, pl->n, pl->rc_total,
+                                                                    pl->d_counters);
+#define ROSAR_RUN(P, NW) if (pl->ppl == P && pl->waves == NW) run_shape<P, NW>(pl, s);
+  ROSAR_BATCH_SHAPES(ROSAR_RUN)
+#undef ROSAR_RUN
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return bfail(ROSAR_ERR_HIP, std::string("batch launch: ") + hipGetErrorString(e));
+  return ROSAR_OK;
 }
 
-rosar_status rosar_batch_plan_info(const rosar_batch_plan* plan, int64_t* pixels, int64_t* rc_tiles,
+rosar_status rosar_batch_plan_info(const rosar_batch_plan* pl, int64_t* pixels, int64_t* rc_tiles,
                                    int64_t* sf_tiles) {
-  (void)plan;
-  (void)pixels;
-  (void)rc_tiles;
-  (void)sf_tiles;
-  return ROSAR_ERR_UNSUPPORTED;
+  using namespace rosar;
+  clear_error();
+  if (!pl) return bfail(ROSAR_ERR_INVALID_ARG, "plan is NULL");
+  if (pixels) *pixels = pl->pixels;
+  if (rc_tiles) *rc_tiles = pl->rc_total;
+  if (sf_tiles) *sf_tiles = pl->sf_total;
+  return ROSAR_OK;
 }
 
-void rosar_batch_plan_destroy(rosar_batch_plan* plan) { delete plan; }
+rosar_status rosar_batch_autotune(const rosar_rotation_desc* descs, int32_t n, int32_t reps, rosar_tile* best,
+                                  float* best_us, rosar_stream stream) {
+  using namespace rosar;
+  clear_error();
+  if (!best || !best_us) return bfail(ROSAR_ERR_INVALID_ARG, "best / best_us is NULL");
+  if (reps < 1 || reps > 1000) return bfail(ROSAR_ERR_INVALID_ARG, "reps must be in [1, 1000]");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess) return bfail(ROSAR_ERR_HIP, "hipEventCreate failed");
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return bfail(ROSAR_ERR_HIP, "hipEventCreate failed");
+  }
+  bool have = false;
+  float best_t = 0.f;
+  rosar_tile bt{};
+  rosar_status st = ROSAR_OK;
+  const int shapes[][2] = {{1, 4}, {2, 4}, {4, 4}, {8, 4}, {2, 2}, {4, 2}, {8, 2}, {4, 8}};
+  for (const auto& sh : shapes) {
+    rosar_tile t{1, sh[0], sh[1], 0};
+    rosar_batch_plan* pl = nullptr;
+    const rosar_status cs = rosar_batch_plan_create(descs, n, &t, &pl);
+    if (cs == ROSAR_ERR_UNSUPPORTED) continue;  // this shape cannot hold some window
+    if (cs != ROSAR_OK) {
+      st = cs;
+      break;
+    }
+    st = rosar_batch_run(pl, stream);  // warm-up
+    hipError_t e = st == ROSAR_OK ? hipEventRecord(e0, s) : hipSuccess;
+    for (int r = 0; st == ROSAR_OK && e == hipSuccess && r < reps; ++r) st = rosar_batch_run(pl, stream);
+    if (st == ROSAR_OK && e == hipSuccess) e = hipEventRecord(e1, s);
+    if (st == ROSAR_OK && e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0.f;
+    if (st == ROSAR_OK && e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    rosar_batch_plan_destroy(pl);
+    if (st != ROSAR_OK) break;
+    if (e != hipSuccess) {
+      st = bfail(ROSAR_ERR_HIP, std::string("batch autotune timing: ") + hipGetErrorString(e));
+      break;
+    }
+    const float us = 1000.f * ms / (float)reps;
+    if (!have || us < best_t) {
+      have = true;
+      best_t = us;
+      bt = t;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st != ROSAR_OK) return st;
+  if (!have) return bfail(ROSAR_ERR_UNSUPPORTED, "no batch launch shape holds these windows");
+  *best = bt;
+  *best_us = best_t;
+  clear_error();
+  return ROSAR_OK;
+}
+
+void rosar_batch_plan_destroy(rosar_batch_plan* pl) {
+  if (!pl) return;
+  (void)hipFree(pl->d_rots);
+  (void)hipFree(pl->d_counters);
+  delete pl;
+}
 
 }  // extern "C"

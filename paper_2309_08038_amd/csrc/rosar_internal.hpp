@@ -5,6 +5,7 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <string>
 
 #include "../../include/rosar.h"
 
@@ -65,6 +66,12 @@ hipError_t launch_bp_full(const Geo& g, const View& y, const double* angles, int
 size_t backward_workspace_bytes(int32_t n, int32_t n_range, int32_t k);
 hipError_t launch_sparse_backward(const SparseArgs& a, const float2* grad_image, float2* grad_w,
                                   float* grad_dphi, float* grad_dpsi, void* ws, hipStream_t s);
+
+// Thread-local error of the C ABI (rosar_last_error) and the per-rotation checks of batch plans.
+rosar_status set_error(rosar_status st, const std::string& msg);
+void clear_error();
+rosar_status validate_rotation(const rosar_rotation_desc& d, int index);
+Geo geo_of(const rosar_geometry* g, const rosar_polar_grid* p);
 
 // Tile chosen when the caller leaves it to the library.
 Tile default_tile(int32_t n, int32_t k, int32_t y_dtype);

@@ -4,3 +4,4 @@ from .configs import (Geometry, PolarGrid, SceneSpec, SparseSpec, Workload, WORK
 from .scene import (Inputs, Scene, hann, make_angles, make_inputs, make_scene, make_support,
                     nominal_angles, phase_matched_weights, random_complex, rng_for, simulate_raw,
                     taylor_taper)
+from .batch import batch_workloads, make_batch_inputs, scaled_batch
