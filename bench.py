@@ -42,6 +42,8 @@ def parse():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for PMC byte counters)")
     ap.add_argument("--tile", default=None, help="sparse-filter launch shape variant,ppl,waves")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the corrected-forward, adjoint, batch and precision timings")
     return ap.parse_args()
 
 
@@ -105,6 +107,103 @@ def _cpu_model():
     except OSError:
         pass
     return "unknown"
+
+
+def event_timer(torch):
+    def timed(fn, reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+    return timed
+
+
+def extras(torch, rs, synth, w, x, dev, rc, off, wts, timed, reps):
+    """Timings of the other rows of the path on the same rotation, plus the batched stream and
+    the precision workload."""
+    g, grid = w.geometry, w.grid
+    n = g.n_pulses
+    out = {}
+    # corrected forward (per-pulse angle and phase errors, LINEAR) and its adjoint
+    dphi = torch.zeros(n, dtype=torch.float32, device=dev)
+    dpsi = torch.zeros(n, dtype=torch.float32, device=dev)
+    img = torch.empty((grid.n_range, grid.n_az), dtype=torch.complex64, device=dev)
+    f = lambda: rs.sparse_filter(g, grid, rc, off, wts, w.sparse.window, dphi=dphi, dpsi=dpsi, interp="linear",
+                                 out=img)
+    f()
+    out["corrected_forward_us"] = 1000 * timed(f, reps)
+    gimg = torch.randn((grid.n_range, grid.n_az), dtype=torch.complex64, device=dev)
+    ws = torch.empty(rs.backward_workspace_bytes(g, grid, off, wts, w.sparse.window), dtype=torch.uint8, device=dev)
+    b = lambda: rs.sparse_filter_backward(g, grid, rc, off, wts, w.sparse.window, gimg, dphi, dpsi, "linear",
+                                          workspace=ws)
+    b()
+    out["adjoint_us"] = 1000 * timed(b, max(3, reps // 5))
+    print(f"[bench] corrected forward {out['corrected_forward_us']:.1f} us, adjoint {out['adjoint_us']:.1f} us",
+          file=sys.stderr, flush=True)
+
+    # batched stream: 64 rotations of uneven size, autotuned shape, replayed from a HIP graph
+    bws = synth.batch_workloads(64)
+    bxs = synth.make_batch_inputs(bws)
+    rots = []
+    for bw, bx in zip(bws, bxs):
+        brc = rs.empty_rc(bw.geometry.n_pulses, bx.l_lo, bx.l_count, halo=bw.sparse.window // 2, device=dev)
+        bimg = torch.empty((bw.grid.n_range, bw.grid.n_az), dtype=torch.complex64, device=dev)
+        rots.append(rs.Rotation(bw.geometry, bw.grid, torch.from_numpy(bx.raw).to(dev),
+                                torch.from_numpy(bx.window).to(dev), brc, torch.from_numpy(bx.offsets).to(dev),
+                                torch.from_numpy(bx.weights.astype(np.complex64)).to(dev), bw.sparse.window, bimg))
+    del bxs
+    shape, _ = rs.batch_autotune(rots, reps=2)
+    plan = rs.BatchPlan(rots, tile=shape)
+    px, rc_tiles, sf_tiles = plan.info()
+    st = torch.cuda.Stream()
+    st.wait_stream(torch.cuda.current_stream())
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(st):
+        plan.run()
+        torch.cuda.synchronize()
+        with torch.cuda.graph(graph, stream=st):
+            plan.run()
+    torch.cuda.current_stream().wait_stream(st)
+    graph.replay()
+    ms = timed(graph.replay, max(3, reps // 5))
+    out["batch"] = {"rotations": len(rots), "pixels": px, "range_tiles": rc_tiles, "filter_tiles": sf_tiles,
+                    "shape_pixels_per_lane_waves": list(shape), "ms_per_batch": ms,
+                    "pixels_per_s": px / (ms * 1e-3), "graph_replay": True}
+    print(f"[bench] batch of {len(rots)} rotations ({px / 1e6:.1f} Mpx): {ms:.3f} ms, shape {shape}",
+          file=sys.stderr, flush=True)
+    plan.close()
+    del rots, plan, graph
+    torch.cuda.empty_cache()
+
+    # precision workload: FP16 / BF16 range-compressed storage and FP16 weights vs complex64
+    pw = synth.precision()
+    px_ = synth.make_inputs(pw)
+    pg, pgrid = pw.geometry, pw.grid
+    praw = torch.from_numpy(px_.raw).to(dev)
+    pwin = torch.from_numpy(px_.window).to(dev)
+    poff = torch.from_numpy(px_.offsets).to(dev)
+    pwts = torch.from_numpy(px_.weights.astype(np.complex64)).to(dev)
+    pimg = torch.empty((pgrid.n_range, pgrid.n_az), dtype=torch.complex64, device=dev)
+    prec = {"workload": pw.name, "pulses": pg.n_pulses, "fast_samples": pg.n_fast, "range_rows": pgrid.n_range,
+            "azimuth_bins": pgrid.n_az, "taps": pw.sparse.k, "window": pw.sparse.window}
+    for dt, scale, wt in (("c64", 1.0, pwts), ("f16", 2.0 ** -6, rs.weights_f16(pwts)), ("bf16", 1.0, rs.weights_f16(pwts))):
+        prc = rs.range_compress(pg, praw, pwin, px_.l_lo, px_.l_count, halo=pw.sparse.window // 2, dtype=dt,
+                                scale=scale)
+        t_rc = timed(lambda: rs.range_compress(pg, praw, pwin, px_.l_lo, px_.l_count, dtype=dt, scale=scale,
+                                               out=prc), reps)
+        ff = lambda: rs.sparse_filter(pg, pgrid, prc, poff, wt, pw.sparse.window, out=pimg)
+        ff()
+        t_sf = timed(ff, reps)
+        prec[dt] = {"range_compress_us": 1000 * t_rc, "sparse_filter_us": 1000 * t_sf,
+                    "pixels_per_s": pgrid.n_range * pgrid.n_az / ((t_rc + t_sf) * 1e-3)}
+        print(f"[bench] precision {dt}: rc {1000 * t_rc:.1f} us, sf {1000 * t_sf:.1f} us", file=sys.stderr,
+              flush=True)
+    out["precision"] = prec
+    return out
 
 
 def main():
@@ -212,6 +311,8 @@ def main():
         "roofline": roofline,
         "kernel_source_digest": digest,
     }
+    if not a.no_extras:
+        out["rows"] = extras(torch, rs, synth, w, x, dev, rc, off, wts, timed, a.steps)
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, x)
     print(json.dumps(out))

@@ -64,31 +64,45 @@ def calib_loss(img: np.ndarray, mask: np.ndarray):
 
 
 def pslr_db(img: np.ndarray, rows, azs, half_window: int, exclude: np.ndarray | None = None,
-            search: int = 3) -> np.ndarray:
+            search: int = 3, lobes=None, return_lobes: bool = False, peaks=None):
     """Peak sidelobe ratio (dB) on the circular azimuth cut through each scatterer's peak.
 
     Peak: max |I| within +-search bins of the nominal pixel.  Main lobe: from the peak out to
-    the nearest local minimum on each side (the half main-lobe rule of Sec. IV-C).  Sidelobe:
+    the nearest local minimum on each side (the half main-lobe rule of Sec. IV-C), unless
+    `lobes` gives the extents (lo, hi) to use; `peaks` likewise fixes the peak pixels (pr, pa).
+    Taking both from a reference image compares two images over the same pixels.  Sidelobe:
     max |I|^2 within +-half_window bins of the peak outside the main lobe and outside `exclude`
-    (boxes of other scatterers).  Returns one value per scatterer (nan where undefined)."""
+    (boxes of other scatterers).  Returns one value per scatterer (nan where undefined), and
+    with return_lobes also the extents and the peak pixels."""
     n_r, n_a = img.shape
     mag = np.abs(img.astype(np.complex128)) ** 2
     out = np.full(len(rows), np.nan)
+    ext, pks = [], []
     for i, (r0, a0) in enumerate(zip(rows, azs)):
         if r0 < 0 or r0 >= n_r:
+            ext.append((0, 0))
+            pks.append((-1, -1))
             continue
-        rr = np.arange(max(r0 - search, 0), min(r0 + search + 1, n_r))
-        aa = (a0 + np.arange(-search, search + 1)) % n_a
-        sub = mag[np.ix_(rr, aa)]
-        ir, ia = np.unravel_index(np.argmax(sub), sub.shape)
-        pr, pa = rr[ir], aa[ia]
+        if peaks is not None:
+            pr, pa = peaks[i]
+        else:
+            rr = np.arange(max(r0 - search, 0), min(r0 + search + 1, n_r))
+            aa = (a0 + np.arange(-search, search + 1)) % n_a
+            sub = mag[np.ix_(rr, aa)]
+            ir, ia = np.unravel_index(np.argmax(sub), sub.shape)
+            pr, pa = int(rr[ir]), int(aa[ia])
+        pks.append((pr, pa))
         cut = mag[pr]
-        lo = 0
-        while lo < half_window and cut[(pa - lo - 1) % n_a] < cut[(pa - lo) % n_a]:
-            lo += 1
-        hi = 0
-        while hi < half_window and cut[(pa + hi + 1) % n_a] < cut[(pa + hi) % n_a]:
-            hi += 1
+        if lobes is not None:
+            lo, hi = lobes[i]
+        else:
+            lo = 0
+            while lo < half_window and cut[(pa - lo - 1) % n_a] < cut[(pa - lo) % n_a]:
+                lo += 1
+            hi = 0
+            while hi < half_window and cut[(pa + hi + 1) % n_a] < cut[(pa + hi) % n_a]:
+                hi += 1
+        ext.append((lo, hi))
         side = []
         for d in range(-half_window, half_window + 1):
             if -lo <= d <= hi:
@@ -99,4 +113,4 @@ def pslr_db(img: np.ndarray, rows, azs, half_window: int, exclude: np.ndarray | 
             side.append(cut[a])
         if side and cut[pa] > 0:
             out[i] = 10 * np.log10(max(side) / cut[pa])
-    return out
+    return (out, ext, pks) if return_lobes else out

@@ -397,8 +397,12 @@ def test_pslr_rect_sinc():
     m = 64
     cut = dirichlet(np.arange(-512, 512) / (16 * m), m)          # 16x oversampled Dirichlet
     img = np.roll(cut, 512)[None, :]
-    val = metrics.pslr_db(img, [0], [0], half_window=200)[0]
-    assert val == pytest.approx(-13.26, abs=0.05)
+    val, lobes, peaks = metrics.pslr_db(img, [0], [0], half_window=200, return_lobes=True)
+    assert val[0] == pytest.approx(-13.26, abs=0.05)
+    # first nulls of a 16x oversampled length-64 aperture: 16 bins either side of the peak
+    assert lobes[0] == (16, 16) and peaks[0] == (0, 0)
+    again = metrics.pslr_db(img * 3.0, [0], [0], 200, lobes=lobes, peaks=peaks)
+    assert again[0] == pytest.approx(val[0], abs=1e-9)
 
 
 def test_calib_loss_gradient_fd():
