@@ -277,7 +277,7 @@ def main():
     sf_bytes = x.l_count * g.n_pulses * es + px * 8 + grid.n_range * k * (8 + 4)
     sf_flops = px * k * 8
     rc_bytes = g.n_pulses * g.n_fast * 8 + g.n_fast * 4 + x.l_count * (g.n_pulses + 2 * halo) * es
-    digest = kernel_source_digest(["sparse_filter.hip", "rosar_device.hpp"])
+    digest = kernel_source_digest(["sparse_filter.hip", "sparse_device.hpp", "rosar_device.hpp"])
     traffic = load_traffic("sparse_filter", digest, a.workload)
     achieved_tf = sf_flops / (ms_sf * 1e-3) / 1e12
     roofline = {"bound": "alu", "achieved": round(achieved_tf, 3), "peak": PEAK_FP32_VALU_TFLOPS,
