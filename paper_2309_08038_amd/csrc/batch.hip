@@ -1,13 +1,18 @@
 // Batched rotations: many independent rotations of uneven pulse, sample and range-row counts
-// imaged by one persistent range-compression launch and one persistent sparse-filter launch.
+// imaged by one range-compression launch per FFT length present and one persistent
+// sparse-filter launch.
 //
 // The plan uploads one descriptor per rotation (derived float64 geometry, band, pointers,
-// LDS layout) and the prefix sums of their tile counts.  Workgroups of each persistent kernel
-// take tile indices from a device counter; a tile index is mapped to its rotation by binary
-// search over the prefix sums and processed by the same block functions the single-rotation
-// kernels use (fft::rc_block, sparse::lds_tile), so a batched image equals the image of the
-// single-rotation call with the same launch shape, bit for bit.  The counters are reset by the
-// plan's own kernel at the start of every run: the three launches can be captured in a HIP
+// LDS layout) and the prefix sums of their tile counts.  A tile index is mapped to its rotation
+// by binary search over the prefix sums and processed by the same block functions the
+// single-rotation kernels use (fft::rc_block, sparse::lds_tile), so a batched image equals the
+// image of the single-rotation call with the same launch shape, bit for bit.
+//
+// Range compression: the rotations are grouped by FFT length; each group is one launch with
+// one workgroup per 8-pulse tile, the exact LDS of its length and XCD-aware tile order (the
+// hardware dispatcher balanced these short tiles better than a work queue did).  Sparse filter:
+// a persistent launch whose workgroups take tile indices from a device counter, reset by the
+// plan's own kernel at the start of every run, so that the launches can be captured in a HIP
 // graph and replayed.  Every workgroup leaves its loop once the counter passes the tile total.
 #include <algorithm>
 #include <cstring>
@@ -21,27 +26,37 @@ namespace rosar {
 namespace {
 
 constexpr int kBatchP = 4;       // default sparse-filter shape of a batch: 4 pixels per lane,
-constexpr int kBatchWaves = 4;   // 4 waves (1024-pixel tiles)
+constexpr int kBatchWaves = 8;   // 8 waves (2048-pixel tiles)
+constexpr int kBatchRcWaves = 8; // range-compression workgroup: one pulse per wave, 8 waves
+constexpr int kRcLengths = 6;    // FFT lengths 64 .. 2048
+
+// Range compression of one rotation inside its FFT-length group.
+struct BatchRc {
+  RcArgs rc;
+  int32_t tile0;             // first tile of this rotation within its group
+  int32_t pad;
+};
 
 struct BatchRot {
-  RcArgs rc;                 // range compression of this rotation
   Geo g;                     // sparse filter geometry
   View y;
   const int32_t* offsets;
   const void* weights;
   float2* image;
+  double cos_hw;              // cos of the half-window angle (bounds the staged rows of a range row)
   int32_t k, window;
   int32_t rows_cap, stride, dma, tiles_per_row;
-  int32_t rc_tile0, sf_tile0;  // first global tile of this rotation in each kernel
-  int32_t rc_pw;               // pulses per range-compression tile
+  int32_t sf_tile0;          // first sparse-filter tile of this rotation
+  int32_t pad;
 };
 
-__device__ __forceinline__ int find_rotation(const BatchRot* rots, int nrot, int t, bool rc) {
-  int lo = 0, hi = nrot - 1;
+// Index of the last entry whose first tile is <= t (entries sorted by first tile).
+template <typename D>
+__device__ __forceinline__ int find_entry(const D* d, int nd, int t, int32_t D::*tile0) {
+  int lo = 0, hi = nd - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
-    const int t0 = rc ? rots[mid].rc_tile0 : rots[mid].sf_tile0;
-    if (t0 <= t) lo = mid;
+    if (d[mid].*tile0 <= t) lo = mid;
     else hi = mid - 1;
   }
   return lo;
@@ -51,29 +66,13 @@ __global__ void batch_reset_kernel(int* counters) {
   if (threadIdx.x < 2) counters[threadIdx.x] = 0;
 }
 
-__global__ __launch_bounds__(fft::kRcThreads) void batch_rc_kernel(const BatchRot* __restrict__ rots, int nrot,
-                                                                    int total, int* counter) {
-  extern __shared__ __align__(16) float2 lds[];
-  __shared__ int s_t;
-  for (;;) {
-    if (threadIdx.x == 0) s_t = atomicAdd(counter, 1);
-    __syncthreads();
-    const int t = s_t;
-    __syncthreads();
-    if (t >= total) break;
-    const int i = find_rotation(rots, nrot, t, true);
-    const RcArgs a = rots[i].rc;
-    const int n0 = (t - rots[i].rc_tile0) * rots[i].rc_pw;
-    switch (a.l) {
-      case 64: fft::rc_block<64, 2, 0>(a, n0, lds); break;
-      case 128: fft::rc_block<128, 2, 0>(a, n0, lds); break;
-      case 256: fft::rc_block<256, 2, 0>(a, n0, lds); break;
-      case 512: fft::rc_block<512, 2, 0>(a, n0, lds); break;
-      case 1024: fft::rc_block<1024, 2, 0>(a, n0, lds); break;
-      default: fft::rc_block<2048, 1, 0>(a, n0, lds); break;
-    }
-    __syncthreads();  // the next tile reuses the LDS
-  }
+template <int L>
+__global__ __launch_bounds__(kBatchRcWaves* kWave) void batch_rc_kernel(const BatchRc* __restrict__ group,
+                                                                         int nrot) {
+  __shared__ float2 lds[fft::rc_lds_elems(L, 1, kBatchRcWaves)];
+  const int t = xcd_logical_block(blockIdx.x, gridDim.x);
+  const int i = find_entry(group, nrot, t, &BatchRc::tile0);
+  fft::rc_block<L, 1, 0, kBatchRcWaves>(group[i].rc, (t - group[i].tile0) * kBatchRcWaves, lds);
 }
 
 template <int P, int NW>
@@ -88,12 +87,13 @@ __global__ __launch_bounds__(kWave* NW) void batch_sf_kernel(const BatchRot* __r
     const int t = s_t;
     __syncthreads();
     if (t >= total) break;
-    const int i = find_rotation(rots, nrot, t, false);
+    const int i = find_entry(rots, nrot, t, &BatchRot::sf_tile0);
     const BatchRot& R = rots[i];
     const int local = t - R.sf_tile0;
     const int row = local / R.tiles_per_row;
     sparse::lds_tile<ROSAR_C64, ROSAR_C64, ROSAR_NEAREST, P, NW>(
-        R.g, R.y, R.k, R.window, row, local - row * R.tiles_per_row, R.rows_cap, R.stride, R.dma, R.offsets,
+        R.g, R.y, R.k, R.window, row, local - row * R.tiles_per_row, R.rows_cap, R.cos_hw, R.stride, R.dma,
+        R.offsets,
         R.weights, reinterpret_cast<const char*>(R.y.data), R.image, smem, s_unstaged);
     __syncthreads();  // the next tile reuses the LDS
   }
@@ -117,11 +117,15 @@ struct rosar_batch_plan {
   int device = -1;
   int ppl = rosar::kBatchP, waves = rosar::kBatchWaves;
   rosar::BatchRot* d_rots = nullptr;
+  rosar::BatchRc* d_rc = nullptr;                 // grouped by FFT length
+  int rc_first[rosar::kRcLengths] = {};           // first entry of each length's group in d_rc
+  int rc_count[rosar::kRcLengths] = {};           // rotations in the group
+  int rc_tiles[rosar::kRcLengths] = {};           // tiles (8-pulse groups) of the group
   int* d_counters = nullptr;
   int rc_total = 0, sf_total = 0;
   int64_t pixels = 0;
-  size_t rc_lds = 0, sf_lds = 0;
-  int rc_grid = 0, sf_grid = 0;
+  size_t sf_lds = 0;
+  int sf_grid = 0;
 };
 
 namespace rosar {
@@ -175,27 +179,36 @@ rosar_status rosar_batch_plan_create(const rosar_rotation_desc* descs, int32_t n
                                             std::to_string(nw) + " waves) not supported");
   const int tpx = kWave * p * nw;
   std::vector<BatchRot> hv(n);
-  int64_t rc_total = 0, sf_total = 0, pixels = 0;
-  size_t rc_lds = 0, sf_lds = 0;
+  std::vector<BatchRc> rc_by_len[kRcLengths];
+  int64_t rc_tiles[kRcLengths] = {};
+  int64_t sf_total = 0, pixels = 0;
+  size_t sf_lds = 0;
   for (int i = 0; i < n; ++i) {
     const rosar_rotation_desc& d = descs[i];
     const rosar_status st = validate_rotation(d, i);
     if (st != ROSAR_OK) return st;
+    BatchRc C;
+    std::memset(&C, 0, sizeof(C));
+    C.rc.raw = reinterpret_cast<const float2*>(d.raw);
+    C.rc.window = d.window;
+    C.rc.out = d.y_t;
+    C.rc.ld = d.ld;
+    C.rc.n = d.geom.n_pulses;
+    C.rc.m = d.geom.n_fast;
+    C.rc.l = d.geom.n_fft;
+    C.rc.l_lo = d.l_lo;
+    C.rc.l_count = d.l_count;
+    C.rc.halo = d.halo;
+    C.rc.dtype = ROSAR_C64;
+    C.rc.scale = 1.0f;
+    int li = 0;
+    while ((64 << li) < C.rc.l) ++li;   // n_fft is a power of two in [64, 2048]
+    C.tile0 = (int32_t)rc_tiles[li];
+    rc_tiles[li] += (C.rc.n + kBatchRcWaves - 1) / kBatchRcWaves;
+    rc_by_len[li].push_back(C);
+
     BatchRot& R = hv[i];
     std::memset(&R, 0, sizeof(R));
-    R.rc.raw = reinterpret_cast<const float2*>(d.raw);
-    R.rc.window = d.window;
-    R.rc.out = d.y_t;
-    R.rc.ld = d.ld;
-    R.rc.n = d.geom.n_pulses;
-    R.rc.m = d.geom.n_fast;
-    R.rc.l = d.geom.n_fft;
-    R.rc.l_lo = d.l_lo;
-    R.rc.l_count = d.l_count;
-    R.rc.halo = d.halo;
-    R.rc.dtype = ROSAR_C64;
-    R.rc.scale = 1.0f;
-    R.rc_pw = fft::kRcWaves * fft::kRcPulsesPerWave(d.geom.n_fft);
     R.g = geo_of(&d.geom, &d.grid);
     R.y = View{d.y_t, d.ld, d.l_lo, d.l_count, d.halo, ROSAR_C64, 1.0f};
     R.offsets = d.set.offsets;
@@ -208,17 +221,17 @@ rosar_status rosar_batch_plan_create(const rosar_rotation_desc* descs, int32_t n
     if (L.bytes > sparse::kLdsBudget)
       return bfail(ROSAR_ERR_UNSUPPORTED, "rotation " + std::to_string(i) + ": window does not fit in LDS");
     R.rows_cap = L.rows;
+    R.cos_hw = L.cos_hw;
     R.stride = L.stride;
     R.dma = L.dma;
     R.tiles_per_row = (R.g.n + tpx - 1) / tpx;
-    R.rc_tile0 = (int32_t)rc_total;
     R.sf_tile0 = (int32_t)sf_total;
-    rc_total += (R.rc.n + R.rc_pw - 1) / R.rc_pw;
     sf_total += (int64_t)R.tiles_per_row * R.g.n_range;
     pixels += (int64_t)R.g.n * R.g.n_range;
-    rc_lds = std::max(rc_lds, (size_t)fft::rc_lds_elems(R.rc.l, fft::kRcPulsesPerWave(R.rc.l)) * sizeof(float2));
     sf_lds = std::max(sf_lds, L.bytes);
   }
+  int64_t rc_total = 0;
+  for (int li = 0; li < kRcLengths; ++li) rc_total += rc_tiles[li];
   if (rc_total >= INT32_MAX / 2 || sf_total >= INT32_MAX / 2)
     return bfail(ROSAR_ERR_UNSUPPORTED, "too many tiles in one batch");
   int dev = 0, cus = 0;
@@ -234,15 +247,22 @@ rosar_status rosar_batch_plan_create(const rosar_rotation_desc* descs, int32_t n
   pl->rc_total = (int)rc_total;
   pl->sf_total = (int)sf_total;
   pl->pixels = pixels;
-  pl->rc_lds = rc_lds;
   pl->sf_lds = sf_lds;
-  int occ = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, reinterpret_cast<const void*>(&batch_rc_kernel),
-                                                   fft::kRcThreads, rc_lds) != hipSuccess || occ < 1) {
-    delete pl;
-    return bfail(ROSAR_ERR_HIP, "occupancy query for the batched range-compression kernel failed");
+  std::vector<BatchRc> hrc;
+  hrc.reserve(n);
+  for (int li = 0; li < kRcLengths; ++li) {
+    pl->rc_first[li] = (int)hrc.size();
+    pl->rc_count[li] = (int)rc_by_len[li].size();
+    pl->rc_tiles[li] = (int)rc_tiles[li];
+    hrc.insert(hrc.end(), rc_by_len[li].begin(), rc_by_len[li].end());
   }
-  pl->rc_grid = cus * occ;
+  auto fail = [pl](rosar_status st, const std::string& m) {
+    (void)hipFree(pl->d_rots);
+    (void)hipFree(pl->d_rc);
+    (void)hipFree(pl->d_counters);
+    delete pl;
+    return bfail(st, m);
+  };
   rosar_status st = ROSAR_ERR_UNSUPPORTED;
 #define ROSAR_PLAN(P, NW) if (p == P && nw == NW) st = plan_shape<P, NW>(hv, pl, cus);
   ROSAR_BATCH_SHAPES(ROSAR_PLAN)
@@ -251,21 +271,13 @@ rosar_status rosar_batch_plan_create(const rosar_rotation_desc* descs, int32_t n
     delete pl;
     return st;
   }
-  if (hipMalloc(&pl->d_rots, sizeof(BatchRot) * n) != hipSuccess) {
-    delete pl;
-    return bfail(ROSAR_ERR_NO_MEMORY, "device allocation of the descriptor table failed");
-  }
-  if (hipMalloc(&pl->d_counters, 2 * sizeof(int)) != hipSuccess) {
-    (void)hipFree(pl->d_rots);
-    delete pl;
-    return bfail(ROSAR_ERR_NO_MEMORY, "device allocation of the work counters failed");
-  }
-  if (hipMemcpy(pl->d_rots, hv.data(), sizeof(BatchRot) * n, hipMemcpyHostToDevice) != hipSuccess) {
-    (void)hipFree(pl->d_rots);
-    (void)hipFree(pl->d_counters);
-    delete pl;
-    return bfail(ROSAR_ERR_HIP, "upload of the descriptor table failed");
-  }
+  if (hipMalloc(&pl->d_rots, sizeof(BatchRot) * n) != hipSuccess ||
+      hipMalloc(&pl->d_rc, sizeof(BatchRc) * n) != hipSuccess ||
+      hipMalloc(&pl->d_counters, 2 * sizeof(int)) != hipSuccess)
+    return fail(ROSAR_ERR_NO_MEMORY, "device allocation of the batch descriptors failed");
+  if (hipMemcpy(pl->d_rots, hv.data(), sizeof(BatchRot) * n, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(pl->d_rc, hrc.data(), sizeof(BatchRc) * n, hipMemcpyHostToDevice) != hipSuccess)
+    return fail(ROSAR_ERR_HIP, "upload of the batch descriptors failed");
   *out = pl;
   return ROSAR_OK;
 }
@@ -279,8 +291,19 @@ rosar_status rosar_batch_run(rosar_batch_plan* pl, rosar_stream stream) {
     return bfail(ROSAR_ERR_INVALID_ARG, "plan was created on another device");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   batch_reset_kernel<<<1, 64, 0, s>>>(pl->d_counters);
-  batch_rc_kernel<<<pl->rc_grid, fft::kRcThreads, pl->rc_lds, s>>>(pl->d_rots, pl->n, pl->rc_total,
-                                                                    pl->d_counters);
+  for (int li = 0; li < kRcLengths; ++li) {
+    if (!pl->rc_count[li]) continue;
+    const BatchRc* g = pl->d_rc + pl->rc_first[li];
+    const int nb = pl->rc_tiles[li], nr = pl->rc_count[li];
+    switch (li) {
+      case 0: batch_rc_kernel<64><<<nb, kBatchRcWaves * kWave, 0, s>>>(g, nr); break;
+      case 1: batch_rc_kernel<128><<<nb, kBatchRcWaves * kWave, 0, s>>>(g, nr); break;
+      case 2: batch_rc_kernel<256><<<nb, kBatchRcWaves * kWave, 0, s>>>(g, nr); break;
+      case 3: batch_rc_kernel<512><<<nb, kBatchRcWaves * kWave, 0, s>>>(g, nr); break;
+      case 4: batch_rc_kernel<1024><<<nb, kBatchRcWaves * kWave, 0, s>>>(g, nr); break;
+      default: batch_rc_kernel<2048><<<nb, kBatchRcWaves * kWave, 0, s>>>(g, nr); break;
+    }
+  }
 #define ROSAR_RUN(P, NW) if (pl->ppl == P && pl->waves == NW) run_shape<P, NW>(pl, s);
   ROSAR_BATCH_SHAPES(ROSAR_RUN)
 #undef ROSAR_RUN
@@ -360,6 +383,7 @@ rosar_status rosar_batch_autotune(const rosar_rotation_desc* descs, int32_t n, i
 void rosar_batch_plan_destroy(rosar_batch_plan* pl) {
   if (!pl) return;
   (void)hipFree(pl->d_rots);
+  (void)hipFree(pl->d_rc);
   (void)hipFree(pl->d_counters);
   delete pl;
 }

@@ -4,9 +4,11 @@
 // One wavefront transforms one pulse at a time with a Stockham autosort FFT (radix 8, then 4
 // or 2 for the remaining factor) in LDS; twiddles come from an LDS table of
 // exp(-j 2 pi t / L).  The first pass reads raw samples straight from HBM with the window and
-// zero padding applied.  A workgroup of 4 waves handles 4*PPW pulses, then writes the
-// transposed band with 4*PPW consecutive pulses per row segment, plus the circular halo
-// copies of the first/last `halo` pulses.
+// zero padding applied.  A workgroup of NW waves handles NW*PPW pulses, then writes the
+// transposed band with NW*PPW consecutive pulses per row segment, plus the circular halo
+// copies of the first/last `halo` pulses.  Each wave owns its pulses' LDS rows, so the passes
+// order their LDS accesses with wave-level fences; the workgroup synchronises only around the
+// twiddle table and before the transposed store.
 #pragma once
 
 #include "rosar_device.hpp"
@@ -15,8 +17,12 @@ namespace rosar {
 namespace fft {
 
 
-constexpr int kRcWaves = 4;
-constexpr int kRcThreads = kRcWaves * kWave;
+// Orders the LDS accesses of one wavefront (each wave owns its pulses' rows in LDS).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 
 constexpr int radix_of(int x) { return (x % 8 == 0) ? 8 : ((x % 4 == 0) ? 4 : 2); }
 constexpr int pass_count(int l) {
@@ -114,7 +120,7 @@ __device__ __forceinline__ void fft_pass(float2* buf, const float2* tw, int wave
       }
     }
   }
-  __syncthreads();
+  wave_sync();
 #pragma unroll
   for (int p = 0; p < PPW; ++p) {
     const int wp = wave * PPW + p;
@@ -134,7 +140,7 @@ __device__ __forceinline__ void fft_pass(float2* buf, const float2* tw, int wave
       }
     }
   }
-  __syncthreads();
+  wave_sync();
 }
 
 template <int L, int PPW, int PASS>
@@ -147,30 +153,32 @@ __device__ __forceinline__ void fft_all(float2* buf, const float2* tw, int wave,
 }
 
 
-constexpr int kRcPulsesPerWave(int l) { return l >= 2048 ? 1 : 2; }
+// LDS float2 needed by rc_block<L, PPW, NW>: twiddle table + NW*PPW padded pulse rows.
+constexpr int rc_lds_elems(int l, int ppw, int nw) { return l + nw * ppw * (l + 1); }
 
-// LDS floats2 needed by rc_block<L, PPW>: twiddle table + PW padded pulse rows.
-constexpr int rc_lds_elems(int l, int ppw) { return l + kRcWaves * ppw * (l + 1); }
-
-// Range-compress pulses [n0, n0 + 4*PPW) of one rotation: FFT each, store the band transposed.
-// `lds` holds rc_lds_elems(L, PPW) float2.  All threads of the workgroup must call it.
-template <int L, int PPW, int DT>
+// Range-compress pulses [n0, n0 + NW*PPW) of one rotation: FFT each (wave w owns pulses
+// n0 + w*PPW ...), then store the band transposed with NW*PPW consecutive pulses per row
+// segment.  `lds` holds rc_lds_elems(L, PPW, NW) float2.  All threads of the workgroup call it.
+template <int L, int PPW, int DT, int NW>
 __device__ __forceinline__ void rc_block(const RcArgs& a, int n0, float2* lds) {
-  constexpr int PW = kRcWaves * PPW;
+  constexpr int PW = NW * PPW;
   constexpr int LP = L + 1;
+  constexpr int NT = NW * kWave;
   float2* tw = lds;
   float2* buf = lds + L;
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
-  for (int t = tid; t < L; t += kRcThreads) {
+  for (int t = tid; t < L; t += NT) {
     float s, c;
     sincospif(-2.0f * (float)t / (float)L, &s, &c);
     tw[t] = make_float2(c, s);
   }
+  __syncthreads();
   fft_all<L, PPW, 0>(buf, tw, wave, lane, a, n0);
+  __syncthreads();
 
   // transposed store of the band: PW consecutive pulses form one contiguous row segment
   const int total = a.l_count * PW;
-  for (int i = tid; i < total; i += kRcThreads) {
+  for (int i = tid; i < total; i += NT) {
     const int pp = i % PW;
     const int lr = i / PW;
     const int n = n0 + pp;

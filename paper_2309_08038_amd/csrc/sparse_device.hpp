@@ -77,14 +77,22 @@ __device__ __forceinline__ void mac_packed(float2& acc, uint32_t w1, uint32_t w2
   }
 }
 
+typedef unsigned u32x2v __attribute__((ext_vector_type(2)));
+typedef __attribute__((address_space(3))) const volatile u32x2v lds_u32x2;
+typedef __attribute__((address_space(3))) const volatile uint32_t lds_u32;
+typedef __attribute__((address_space(3))) const char lds_char;
+
+// One sample of a lane from the staged rows.  The reads are volatile so that the compiler keeps
+// each one a single ds_read_b64 / ds_read_b32: fused into ds_read2st64 pairs (the P reads of a
+// tap are 64 samples apart) the loop measured about 25 % slower on gfx950.
 template <int DT>
 __device__ __forceinline__ void lds_sample(const char* smem, uint32_t byte_off, uint32_t& lo, uint32_t& hi) {
   if constexpr (DT == 0) {
-    const uint2 v = *reinterpret_cast<const uint2*>(smem + byte_off);
+    const u32x2v v = *(lds_u32x2*)((lds_char*)smem + byte_off);
     lo = v.x;
     hi = v.y;
   } else {
-    lo = *reinterpret_cast<const uint32_t*>(smem + byte_off);
+    lo = *(lds_u32*)((lds_char*)smem + byte_off);
     hi = 0;
   }
 }
@@ -139,7 +147,7 @@ __device__ __forceinline__ int bin_of(double u) {
 // reuse `smem` for another tile must place a barrier in between.
 template <int DT, int WDT, int INTERP, int P, int NW>
 __device__ __forceinline__ void lds_tile(const Geo& g, const View& y, int32_t k, int32_t window, int row,
-                                         int tile, int rows_cap, int stride, int use_dma,
+                                         int tile, int rows_cap, double cos_hw, int stride, int use_dma,
                                          const int32_t* __restrict__ offsets, const void* __restrict__ weights,
                                          const char* __restrict__ ydata, float2* __restrict__ image, char* smem,
                                          int& s_unstaged) {
@@ -155,7 +163,7 @@ __device__ __forceinline__ void lds_tile(const Geo& g, const View& y, int32_t k,
   char* stage = smem + ((ne * ((int)sizeof(TapEntry) + 8) + 15) & ~15);
 
   const int lane = threadIdx.x & (kWave - 1);
-  const int wave = threadIdx.x / kWave;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);   // wave-uniform
   const int n = g.n;
   const int a0 = tile * T;
   const int half_w = window / 2;
@@ -164,23 +172,37 @@ __device__ __forceinline__ void lds_tile(const Geo& g, const View& y, int32_t k,
   const double c1 = rr * rr + g.radius * g.radius;
   const double c2 = 2.0 * rr * g.radius;
 
-  // ---- staged window: bin rows [lfirst, lfirst + nrows) from the geometry alone (the nearest
-  // slant range of any tap is |R - r|, at offset 0), columns of pulses [a0 - W/2, a0 + T + W/2)
-  const int lfirst = max(bin_of<INTERP>(g.beta * fabs(rr - g.radius)) - y.l_lo, 0);
-  const int nrows = max(min(rows_cap, y.l_count - lfirst), 0);
+  // ---- staged window: bin rows [lfirst, lfirst + nrows) from the geometry of this row alone
+  // (the slant range of a tap grows with |offset|: |R - r| at offset 0, at most that of offset
+  // W/2, whose cosine is cos_hw), columns of pulses [a0 - W/2, a0 + T + W/2)
+  const double u_near = g.beta * fabs(rr - g.radius);
+  const double u_far = g.beta * sqrt(c1 - c2 * cos_hw);
+  const int lfirst = max(bin_of<INTERP>(u_near) - y.l_lo, 0);
+  const int lspan = bin_of<INTERP>(u_far) - y.l_lo + NSUB - lfirst;
+  const int nrows = max(min(min(rows_cap, lspan), y.l_count - lfirst), 0);
   int col0;   // stored column of staged column 0
   if (use_dma) {
-    // direct-to-LDS 16-byte loads from an even stored column (the halo covers the window)
+    // direct-to-LDS 16-byte loads from an even stored column (the halo covers the window);
+    // chunk (r, c) of the staged rows is wave (r * nchunk + c) mod NW's, all indices uniform.
+    // The last chunk of a row is partial: its lanes past the row end stay idle.  Columns past
+    // the stored rotation (clamped) feed padded pixels only.
     col0 = (a0 - half_w + y.halo) & ~(CPL - 1);
-    const int nchunk = stride / CHUNK;
-    const int64_t last = (int64_t)y.l_count * y.ld - CPL;   // clamp: columns past the stored
-    for (int j = wave; j < nrows * nchunk; j += NW) {        // rotation feed padded pixels only
-      const int r = j / nchunk;
-      const int ch = j - r * nchunk;
-      int64_t el = (int64_t)(lfirst + r) * y.ld + col0 + ch * CHUNK + lane * CPL;
-      el = min(el, last);
-      __builtin_amdgcn_global_load_lds((gbl_void_t*)(ydata + el * ES),
-                                       (lds_void_t*)(stage + (r * stride + ch * CHUNK) * ES), 16, 0, 0);
+    const int nchunk = (stride + CHUNK - 1) / CHUNK;
+    const int64_t last = (int64_t)y.l_count * y.ld - CPL;
+    const int lane_col = lane * CPL;
+    int r = 0, ch = wave;
+    while (ch >= nchunk) { ch -= nchunk; ++r; }
+    while (r < nrows) {
+      const int c = ch * CHUNK;
+      const int64_t el0 = (int64_t)(lfirst + r) * y.ld + col0 + c;
+      if (c + lane_col < stride) {
+        int64_t el = el0 + lane_col;
+        if (el0 + CHUNK - CPL > last) el = min(el, last);
+        __builtin_amdgcn_global_load_lds((gbl_void_t*)(ydata + el * ES),
+                                         (lds_void_t*)(stage + (r * stride + c) * ES), 16, 0, 0);
+      }
+      ch += NW;
+      while (ch >= nchunk) { ch -= nchunk; ++r; }
     }
   } else {
     // element-wise copy with the pulse index wrapped modulo N
@@ -307,7 +329,7 @@ __device__ __forceinline__ void lds_tile(const Geo& g, const View& y, int32_t k,
 
 
 // ---------------------------------------------------------------------------------- host side
-constexpr size_t kLdsBudget = 96 * 1024;
+constexpr size_t kLdsBudget = 78 * 1024;   // two workgroups per CU (160 KB of LDS), with room for static LDS
 
 // Upper bound on the FFT rows the taps of one range row touch: the slant range of a tap grows
 // with |offset| over the window (|D| <= pi), so the rows lie between those of offsets 0 and W/2.
@@ -329,6 +351,7 @@ inline int staged_rows_bound(const Geo& g, int n_range, int window, int interp, 
 struct LdsLayout {
   int rows, stride, dma;
   size_t bytes;
+  double cos_hw;   // cos((W/2) * 2 pi / N): bounds the slant range of a tap in the window
 };
 
 // LDS layout of lds_tile for tiles of `tile_px` pixels (direct-to-LDS staging needs the halo to
@@ -336,16 +359,17 @@ struct LdsLayout {
 inline LdsLayout lds_layout(const Geo& g, const View& y, int k, int window, int interp, int tile_px,
                             int rows_cap_limit) {
   const int es = y.dtype == ROSAR_C64 ? 8 : 4;
-  const int chunk = kWave * (16 / es);
+  const int cpl = 16 / es;
   const int nsub = interp == ROSAR_LINEAR ? 2 : 1;
   LdsLayout L{};
   L.rows = staged_rows_bound(g, g.n_range, window, interp, y.l_count);
   if (rows_cap_limit > 0 && L.rows > rows_cap_limit) L.rows = rows_cap_limit;
   L.dma = y.halo >= window / 2 && ((y.ld * es) % 16) == 0 && (reinterpret_cast<uintptr_t>(y.data) % 16) == 0;
-  const int cols = tile_px + window + 16 / es;
-  L.stride = L.dma ? (cols + chunk - 1) / chunk * chunk : cols;
+  const int cols = tile_px + window + cpl;
+  L.stride = L.dma ? (cols + cpl - 1) / cpl * cpl : cols;   // rows stay 16-byte aligned
   const size_t table = ((size_t)k * nsub * (sizeof(TapEntry) + 8) + 15) & ~(size_t)15;
   L.bytes = table + (size_t)L.rows * L.stride * es;
+  L.cos_hw = cos((window / 2) * g.step);
   return L;
 }
 

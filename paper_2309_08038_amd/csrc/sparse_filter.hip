@@ -297,7 +297,7 @@ __global__ __launch_bounds__(kCorrThreads) void sparse_corrected_kernel(
 template <int DT, int WDT, int INTERP, int P, int NW>
 __global__ __launch_bounds__(kWave* NW) void sparse_lds_kernel(Geo g, View y, int32_t k, int32_t window,
                                                                int tiles_per_row, int nblocks, int rows_cap,
-                                                               int stride, int use_dma,
+                                                               double cos_hw, int stride, int use_dma,
                                                                const int32_t* __restrict__ offsets,
                                                                const void* __restrict__ weights,
                                                                const char* __restrict__ ydata,
@@ -306,8 +306,8 @@ __global__ __launch_bounds__(kWave* NW) void sparse_lds_kernel(Geo g, View y, in
   __shared__ int s_unstaged;
   const int blk = xcd_logical_block(blockIdx.x, nblocks);
   const int row = blk / tiles_per_row;
-  sparse::lds_tile<DT, WDT, INTERP, P, NW>(g, y, k, window, row, blk - row * tiles_per_row, rows_cap, stride,
-                                           use_dma, offsets, weights, ydata, image, smem, s_unstaged);
+  sparse::lds_tile<DT, WDT, INTERP, P, NW>(g, y, k, window, row, blk - row * tiles_per_row, rows_cap,
+                                           cos_hw, stride, use_dma, offsets, weights, ydata, image, smem, s_unstaged);
 }
 
 template <int DT, int WDT, int INTERP, int P, int NW>
@@ -319,7 +319,7 @@ hipError_t launch_lds_t(const SparseArgs& a, hipStream_t s, bool* fits) {
   const int tiles = (a.g.n + T - 1) / T;
   const int nblocks = tiles * a.g.n_range;
   sparse_lds_kernel<DT, WDT, INTERP, P, NW><<<nblocks, kWave * NW, L.bytes, s>>>(
-      a.g, a.y, a.k, a.window, tiles, nblocks, L.rows, L.stride, L.dma, a.offsets, a.weights,
+      a.g, a.y, a.k, a.window, tiles, nblocks, L.rows, L.cos_hw, L.stride, L.dma, a.offsets, a.weights,
       reinterpret_cast<const char*>(a.y.data), a.image);
   return hipGetLastError();
 }
@@ -389,12 +389,11 @@ hipError_t launch_corr_dt(const SparseArgs& a, hipStream_t s) {
 
 Tile default_tile(int32_t n, int32_t k, int32_t y_dtype) {
   (void)k;
-  (void)y_dtype;
-  // LDS-staged window, eight pixels per lane, four waves: 2048-pixel tiles (short rotations:
-  // one pixel per lane)
-  Tile t{2, 8, 4};
-  if (n <= 1024) t = Tile{2, 1, 4};
-  return t;
+  // LDS-staged window of 2048-pixel tiles: complex64 samples four pixels per lane over eight
+  // waves, 16-bit samples eight pixels per lane over four waves (the faster shape of each on
+  // the 3600- and 7200-pulse workloads); short rotations one pixel per lane
+  if (n <= 1024) return Tile{2, 1, 4};
+  return y_dtype == ROSAR_C64 ? Tile{2, 4, 8} : Tile{2, 8, 4};
 }
 
 bool tile_supported(const Tile& t) {

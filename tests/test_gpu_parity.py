@@ -83,7 +83,7 @@ def test_sparse_filter_small_end_to_end():
     assert rel_l2(img.cpu().numpy(), ref) <= TOL
 
 
-SHAPES = [(v, p, nw) for v in (1, 2, 3) for p in (1, 2, 4, 8) for nw in (1, 2, 4, 8) if not (p == 8 and nw == 8)]
+SHAPES = [(v, p, nw) for v in (1, 2) for p in (1, 2, 4, 8) for nw in (1, 2, 4, 8) if not (p == 8 and nw == 8)]
 
 
 def test_sparse_filter_launch_shapes_bit_identical():
