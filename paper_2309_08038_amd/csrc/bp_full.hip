@@ -1,38 +1,58 @@
 // Full-aperture back-projection over range-compressed data (FFT+BPA, eq. 43 with the BPA
 // weights alpha_n exp(-j 2 k R_n)), the comparator of the sparse filter.
 //
-// Prep kernel (one workgroup): per-pulse float64 table (cos phi^_n, sin phi^_n) and the largest
-// deviation of any pulse angle from its nominal position, written to the caller's workspace.
-// Main kernel: a workgroup owns one range row and 256 consecutive azimuth bins (one per lane).
-// It walks the pulses that can be visible from any of its pixels: |a - n| steps up to
-// (acos(r/R) + max deviation) / (2 pi / N) + 1, or the whole rotation when that covers it.
-// Per (pixel, pulse), in float64: cos D = cos phi_a cos phi^_n + sin phi_a sin phi^_n (table
-// values arrive through scalar loads, the pulse being wave-uniform), visibility v = R cos D - r
-// (eqs. 4-5), R_n (eq. 2), the bin (eq. 40) and the phase 2 k R_n reduced to revolutions; then
-// in float32 alpha = v / R_n (eqs. 3, 8, 15), the hardware sine/cosine and the complex MAC.
+// Prep kernel (one workgroup): per pulse, the deviation d_n of its angle from the nominal
+// phi0 + 2 pi n / N (wrapped to (-pi, pi]) as (sin(d_n / 2), cos(d_n / 2)) in float32, and the
+// largest |d_n|, written to the caller's workspace.
+//
+// Main kernel: a workgroup owns one range row and kBpTile consecutive azimuth bins (kBpP per
+// lane, 64 apart).  It walks the pulse offsets o = n - a that can be visible from its row:
+// |o| up to (acos(r / R) + max |d|) / (2 pi / N) + 1, or every pulse once when that covers the
+// rotation.  With D0 = 2 pi o / N the angle between pixel a and pulse n is D = D0 + d_n (eqs.
+// 2-5 with the pixel centred on pulse a).  Per chunk of offsets the workgroup computes the
+// nominal geometry in float64 (R_nom = R(D0), beta R_nom of eq. 40, the phase 2 k R_nom in
+// revolutions) into LDS, and stages the pulse corrections of the columns the chunk touches.
+// Per (pixel, pulse) only the correction is evaluated, in float32 and without cancellation:
+//   R_n^2 - R_nom^2 = 4 R r sin(D0 + d/2) sin(d/2),  R_n - R_nom = (R_n^2 - R_nom^2)/(R_n + R_nom),
+// the bin is beta R_nom + beta (R_n - R_nom) in float64, the phase adds 2 k (R_n - R_nom), and
+// v = R cos D - r = (R^2 - r^2 - R_n^2) / (2 r) gives alpha = max(v, 0) / R_n (eqs. 3, 8, 15).
+// Neighbouring lanes read neighbouring columns of the same bin row: coalesced loads.
 #include "rosar_device.hpp"
 
 namespace rosar {
 namespace {
 
 constexpr int kBpThreads = 256;
-constexpr size_t kBpHeader = 256;  // bytes before the per-pulse table
+constexpr int kBpP = 2;                          // pixels per lane
+constexpr int kBpTile = kBpThreads * kBpP;       // pixels per workgroup
+constexpr int kBpChunk = kBpThreads;             // offsets per chunk (one per thread)
+constexpr size_t kBpHeader = 256;                // bytes before the per-pulse table
+
+// Nominal geometry of one offset o (no angle error), 32 bytes.
+struct alignas(16) BpTap {
+  double u;       // beta * R_nom (FFT bin, eq. 40)
+  float r2;       // R_nom^2
+  float rnom;     // R_nom
+  float sd, cd;   // sin, cos of D0 = 2 pi o / N
+  float ph;       // frac(k R_nom / pi): revolutions of exp(j 2 k R_nom)
+  int32_t pad;
+};
 
 __global__ __launch_bounds__(1024) void bp_prep_kernel(int32_t n, double phi0, double step,
                                                        const double* __restrict__ angles,
                                                        double* __restrict__ ws) {
   __shared__ double red[1024 / kWave];
-  double* table = ws + kBpHeader / sizeof(double);
+  float2* table = reinterpret_cast<float2*>(reinterpret_cast<char*>(ws) + kBpHeader);
   double dmax = 0.0;
   for (int i = threadIdx.x; i < n; i += blockDim.x) {
-    const double nominal = phi0 + step * i;
-    const double ang = angles ? angles[i] : nominal;
+    double d = 0.0;
+    if (angles) {
+      d = angles[i] - (phi0 + step * i);
+      d -= 6.283185307179586477 * rint(d * 0.15915494309189533577);
+    }
     double s, c;
-    sincos(ang, &s, &c);
-    table[2 * i] = c;
-    table[2 * i + 1] = s;
-    double d = ang - nominal;
-    d -= 6.283185307179586477 * rint(d * 0.15915494309189533577);
+    sincos(0.5 * d, &s, &c);
+    table[i] = make_float2((float)s, (float)c);
     dmax = fmax(dmax, fabs(d));
   }
   for (int off = kWave / 2; off > 0; off >>= 1) dmax = fmax(dmax, __shfl_xor(dmax, off));
@@ -50,82 +70,141 @@ __global__ __launch_bounds__(kBpThreads) void bp_kernel(Geo g, View y, int tiles
                                                        const double* __restrict__ ws,
                                                        const char* __restrict__ ydata,
                                                        float2* __restrict__ image) {
+  __shared__ BpTap s_tap[kBpChunk];
+  __shared__ float2 s_del[kBpChunk + kBpTile];   // pulse corrections of columns a0 + c0 + j
   const int blk = xcd_logical_block(blockIdx.x, nblocks);
   const int row = blk / tiles_per_row;
   const int tile = blk - row * tiles_per_row;
   const int n = g.n;
-  const int a0 = tile * kBpThreads;
-  const int a = a0 + threadIdx.x;
-  if (a0 + (int)(threadIdx.x & ~(kWave - 1)) >= n) return;
-  const int ac = min(a, n - 1);
-  const int a_last = min(a0 + kBpThreads, n) - 1;
+  const int a0 = tile * kBpTile;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wave = threadIdx.x / kWave;
+  const int i_wave = wave * kWave * kBpP;   // first pixel of this wave within the tile
 
   const double rr = g.r0 + row * g.dr;
   const double r = g.radius;
-  float2 acc = make_float2(0.f, 0.f);
-  if (rr > r) {
-    const double c1 = rr * rr + r * r;
-    const double c2 = 2.0 * rr * r;
-    const double* table = ws + kBpHeader / sizeof(double);
+  float2 acc[kBpP];
+#pragma unroll
+  for (int p = 0; p < kBpP; ++p) acc[p] = make_float2(0.f, 0.f);
+
+  if (rr > r) {   // otherwise no pulse sees the row (v <= R - r <= 0)
+    const float2* del = reinterpret_cast<const float2*>(reinterpret_cast<const char*>(ws) + kBpHeader);
     const double dmax = ws[0];
-    double sa, ca;
-    sincos(g.phi0 + g.step * ac, &sa, &ca);
-    // pulses that may be visible from some pixel of this block
     const double reach = (acos(r / rr) + dmax) / g.step;
     const int span = reach >= (double)n ? n : (int)reach + 1;
-    int first, count;
-    if (2 * span + (a_last - a0) + 1 >= n) {
-      first = 0;
-      count = n;
+    int o_lo, o_hi;   // inclusive offset range, each pulse at most once per pixel
+    if (2 * span + 1 >= n) {
+      o_lo = -(n / 2);
+      o_hi = o_lo + n - 1;
     } else {
-      first = a0 - span;
-      count = 2 * span + (a_last - a0) + 1;
+      o_lo = -span;
+      o_hi = span;
     }
-    const double kpi = g.k_over_pi;
-    for (int i = 0; i < count; ++i) {
-      int pn = first + i;
-      pn += (pn < 0) ? n : 0;
-      pn -= (pn >= n) ? n : 0;
-      const double cn = table[2 * pn];
-      const double sn = table[2 * pn + 1];
-      const double cosd = ca * cn + sa * sn;
-      const double v = rr * cosd - r;
-      if (v > 0.0) {
-        const double rn = sqrt(c1 - c2 * cosd);
-        const double u = g.beta * rn;
-        const int64_t col = pn + y.halo;
-        float2 smp;
-        if constexpr (INTERP == ROSAR_NEAREST) {
-          const int l = (int)floor(u + 0.5) - y.l_lo;
-          smp = (l >= 0 && l < y.l_count) ? load_c<DT>(ydata, l * y.ld + col) : make_float2(0.f, 0.f);
-        } else {
-          const double fl = floor(u);
-          const float f = (float)(u - fl);
-          const int l = (int)fl - y.l_lo;
-          const float2 y0 = (l >= 0 && l < y.l_count) ? load_c<DT>(ydata, l * y.ld + col) : make_float2(0.f, 0.f);
-          const float2 y1 = (l + 1 >= 0 && l + 1 < y.l_count) ? load_c<DT>(ydata, (l + 1) * y.ld + col)
-                                                               : make_float2(0.f, 0.f);
-          smp = make_float2(fmaf(f, y1.x - y0.x, y0.x), fmaf(f, y1.y - y0.y, y0.y));
-        }
-        const float alpha = (float)(v / rn);
-        const float fr = frac_rev(kpi * rn);
-        // coefficient alpha exp(-j 2 k R_n); acc += coef * smp
-        const float cr = alpha * cos_rev(fr);
-        const float ci = -alpha * sin_rev(fr);
-        acc.x = fmaf(cr, smp.x, acc.x);
-        acc.x = fmaf(-ci, smp.y, acc.x);
-        acc.y = fmaf(cr, smp.y, acc.y);
-        acc.y = fmaf(ci, smp.x, acc.y);
+    const double c1 = rr * rr + r * r;
+    const double c2 = 2.0 * rr * r;
+    const float c4 = (float)(2.0 * c2);         // 4 R r
+    const float k1 = (float)(rr * rr - r * r);  // R^2 - r^2
+    const float inv2r = (float)(0.5 / r);
+    const float kpi = (float)g.k_over_pi;
+    const float beta = (float)g.beta;
+    constexpr int ES = Elem<DT>::bytes;
+    // band rows as one buffer: a bin outside the band is an offset past its end (or a negative
+    // offset, i.e. above 2^31 as unsigned), which the range check turns into a zero sample
+    const __amdgpu_buffer_rsrc_t rsrc = make_rsrc(ydata, (uint32_t)((int64_t)y.l_count * y.ld * ES));
+    const int ld_es = (int)(y.ld * ES);
+    const double u_shift = INTERP == ROSAR_NEAREST ? 0.5 - y.l_lo : -(double)y.l_lo;
+    int acol[kBpP];   // pixel column, clamped into the rotation for padding lanes
+#pragma unroll
+    for (int p = 0; p < kBpP; ++p) acol[p] = min(a0 + i_wave + lane + kWave * p, n - 1);
+
+    for (int c0 = o_lo; c0 <= o_hi; c0 += kBpChunk) {
+      const int cnt = min(kBpChunk, o_hi - c0 + 1);
+      if ((int)threadIdx.x < cnt) {
+        const int o = c0 + (int)threadIdx.x;
+        double s, c;
+        sincos(o * g.step, &s, &c);
+        const double r2 = c1 - c2 * c;
+        const double rn = sqrt(r2);
+        const double ph = g.k_over_pi * rn;
+        BpTap t;
+        t.u = g.beta * rn + u_shift;   // band-relative bin (+ 1/2 for rounding to nearest)
+        t.r2 = (float)r2;
+        t.rnom = (float)rn;
+        t.sd = (float)s;
+        t.cd = (float)c;
+        t.ph = (float)(ph - floor(ph));
+        t.pad = 0;
+        s_tap[threadIdx.x] = t;
       }
+      for (int j = threadIdx.x; j < cnt - 1 + kBpTile; j += kBpThreads) {
+        int pn = (a0 + c0 + j) % n;
+        pn += pn < 0 ? n : 0;
+        s_del[j] = del[pn];
+      }
+      __syncthreads();
+      int pc[kBpP];   // pulse column of offset c0 for each pixel, in [0, N)
+#pragma unroll
+      for (int p = 0; p < kBpP; ++p) {
+        pc[p] = acol[p] + c0;
+        pc[p] += (pc[p] < 0) ? n : 0;
+        pc[p] -= (pc[p] >= n) ? n : 0;
+      }
+      for (int t = 0; t < cnt; ++t) {
+        const BpTap tp = s_tap[t];
+#pragma unroll
+        for (int p = 0; p < kBpP; ++p) {
+          const float2 dl = s_del[i_wave + lane + kWave * p + t];   // (sin(d/2), cos(d/2))
+          const float s_mid = fmaf(tp.sd, dl.y, tp.cd * dl.x);    // sin(D0 + d/2)
+          const float dd = c4 * s_mid * dl.x;                      // R_n^2 - R_nom^2
+          const float r2 = fmaxf(tp.r2 + dd, 1e-30f);
+          const float rs = __builtin_amdgcn_rsqf(r2);
+          const float rn = r2 * rs;
+          const float diff = dd * __builtin_amdgcn_rcpf(rn + tp.rnom);   // R_n - R_nom
+          const float alpha = fmaxf((k1 - r2) * inv2r, 0.f) * rs;
+          const double u = tp.u + (double)(beta * diff);
+          int pn = pc[p] + t;
+          pn -= (pn >= n) ? n : 0;
+          const int cb = (pn + y.halo) * ES;   // byte offset of the column within a row
+          // rows clamped to just outside either band edge: an out-of-band sample reads zero
+          float2 smp;
+          if constexpr (INTERP == ROSAR_NEAREST) {
+            const int l = min(max((int)floor(u), -1), y.l_count);
+            smp = buf_load<DT>(rsrc, (uint32_t)(__mul24(l, ld_es) + cb), 0u);
+          } else {
+            const double fl = floor(u);
+            const float f = (float)(u - fl);
+            const int l = min(max((int)fl, -2), y.l_count);
+            const uint32_t off0 = (uint32_t)(__mul24(l, ld_es) + cb);
+            const float2 y0 = buf_load<DT>(rsrc, off0, 0u);
+            const float2 y1 = buf_load<DT>(rsrc, off0 + (uint32_t)ld_es, 0u);
+            smp = make_float2(fmaf(f, y1.x - y0.x, y0.x), fmaf(f, y1.y - y0.y, y0.y));
+          }
+          float fr = tp.ph + kpi * diff;
+          fr -= floorf(fr);
+          // coefficient alpha exp(-j 2 k R_n); acc += coef * smp
+          const float cr = alpha * cos_rev(fr);
+          const float ci = -alpha * sin_rev(fr);
+          acc[p].x = fmaf(cr, smp.x, acc[p].x);
+          acc[p].x = fmaf(-ci, smp.y, acc[p].x);
+          acc[p].y = fmaf(cr, smp.y, acc[p].y);
+          acc[p].y = fmaf(ci, smp.x, acc[p].y);
+        }
+      }
+      __syncthreads();
     }
   }
-  if (a < n) image[(int64_t)row * n + a] = make_float2(acc.x * y.inv_scale, acc.y * y.inv_scale);
+  float2* out = image + (int64_t)row * n;
+#pragma unroll
+  for (int p = 0; p < kBpP; ++p) {
+    const int a = a0 + i_wave + lane + kWave * p;
+    if (a < n) out[a] = make_float2(acc[p].x * y.inv_scale, acc[p].y * y.inv_scale);
+  }
 }
 
 template <int DT>
 hipError_t launch_dt(const Geo& g, const View& y, int32_t interp, float2* image, const double* ws,
                      hipStream_t s) {
-  const int tiles = (g.n + kBpThreads - 1) / kBpThreads;
+  const int tiles = (g.n + kBpTile - 1) / kBpTile;
   const int nblocks = tiles * g.n_range;
   const char* yd = reinterpret_cast<const char*>(y.data);
   if (interp == ROSAR_LINEAR)
@@ -137,7 +216,7 @@ hipError_t launch_dt(const Geo& g, const View& y, int32_t interp, float2* image,
 
 }  // namespace
 
-size_t bp_workspace_bytes(int32_t n) { return kBpHeader + (size_t)n * 2 * sizeof(double); }
+size_t bp_workspace_bytes(int32_t n) { return kBpHeader + (size_t)n * sizeof(float2); }
 
 hipError_t launch_bp_full(const Geo& g, const View& y, const double* angles, int32_t interp,
                           float2* image, void* ws, hipStream_t s) {

@@ -114,6 +114,23 @@ __device__ __forceinline__ T readlane(T v, int lane) {
 
 __device__ __forceinline__ int wave_lane() { return __lane_id(); }
 
+// Raw buffer resource over `bytes` bytes (gfx9 family word 3).  Loads address
+// base + voffset + soffset; a load whose offset is not below `bytes` returns zero without a
+// memory access (the descriptor's range check).
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* p, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, 0x00020000);
+}
+
+template <int DT>
+__device__ __forceinline__ float2 buf_load(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+  if constexpr (DT == 0) {
+    return __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+  } else {
+    const uint32_t v = __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0);
+    return DT == 1 ? unpack_f16x2(v) : unpack_bf16x2(v);
+  }
+}
+
 // Workgroups are dispatched round-robin over the 8 XCDs (block b runs on XCD b % 8).  Map
 // the hardware block index to a logical one so that each XCD receives a contiguous range of
 // logical blocks (neighbouring range rows share Y rows in that XCD's L2).

@@ -141,105 +141,114 @@ __device__ __forceinline__ int bin_of(double u) {
   return INTERP == ROSAR_NEAREST ? (int)floor(u + 0.5) : (int)floor(u);
 }
 
-// One workgroup's tile: `row` x pixels [tile * T, tile * T + T) of a rotation.  All threads of
-// the workgroup call it; `smem` is the dynamic LDS (lds_bytes of the layout), `s_unstaged` a
-// workgroup-shared int.  Ends with every thread past its last LDS access, but callers that
-// reuse `smem` for another tile must place a barrier in between.
-template <int DT, int WDT, int INTERP, int P, int NW>
-__device__ __forceinline__ void lds_tile(const Geo& g, const View& y, int32_t k, int32_t window, int row,
-                                         int tile, int rows_cap, double cos_hw, int stride, int use_dma,
-                                         const int32_t* __restrict__ offsets, const void* __restrict__ weights,
-                                         const char* __restrict__ ydata, float2* __restrict__ image, char* smem,
-                                         int& s_unstaged) {
+// Bin rows [lfirst, lfirst + nrows) of the staged window of one range row, from the geometry
+// alone: the slant range of a tap grows with |offset| (|R - r| at offset 0, at most that of
+// offset W/2, whose cosine is cos_hw).  Uniform across the workgroup.
+struct RowSpan {
+  int lfirst, nrows;
+};
+
+template <int INTERP>
+__device__ __forceinline__ RowSpan row_span(const Geo& g, const View& y, int row, int rows_cap, double cos_hw) {
+  constexpr int NSUB = INTERP == ROSAR_LINEAR ? 2 : 1;
+  const double rr = g.r0 + row * g.dr;
+  const double u_near = g.beta * fabs(rr - g.radius);
+  const double u_far = g.beta * sqrt(rr * rr + g.radius * g.radius - 2.0 * rr * g.radius * cos_hw);
+  RowSpan sp;
+  sp.lfirst = max(bin_of<INTERP>(u_near) - y.l_lo, 0);
+  const int lspan = bin_of<INTERP>(u_far) - y.l_lo + NSUB - sp.lfirst;
+  sp.nrows = max(min(min(rows_cap, lspan), y.l_count - sp.lfirst), 0);
+  return sp;
+}
+
+// First stored column of the staged window of the tile starting at pixel a0 (direct-to-LDS
+// staging starts at an aligned column), and the LDS column of pixel a0 + i at offset o:
+// i + o + shift.
+template <int DT>
+__device__ __forceinline__ int stage_col0(const View& y, int a0, int half_w, int use_dma) {
+  constexpr int CPL = 16 / Elem<DT>::bytes;
+  const int c = a0 - half_w + y.halo;
+  return use_dma ? (c & ~(CPL - 1)) : c;
+}
+
+// Issue the direct-to-LDS 16-byte loads of the staged rows (all NW waves; chunk (r, c) of the
+// staged rows is wave (r * nchunk + c) mod NW's, all indices uniform).  The last chunk of a row
+// is partial: its lanes past the row end stay idle.  Columns past the stored rotation (clamped)
+// feed padded pixels only.  Completion: s_waitcnt vmcnt, then a barrier.
+template <int DT, int NW>
+__device__ __forceinline__ void stage_dma(const View& y, const char* __restrict__ ydata, char* stage, RowSpan sp,
+                                          int col0, int stride, int wave, int lane) {
+  constexpr int ES = Elem<DT>::bytes;
+  constexpr int CPL = 16 / ES;
+  constexpr int CHUNK = kWave * CPL;
+  const int nchunk = (stride + CHUNK - 1) / CHUNK;
+  const int64_t last = (int64_t)y.l_count * y.ld - CPL;
+  const int lane_col = lane * CPL;
+  int r = 0, ch = wave;
+  while (ch >= nchunk) { ch -= nchunk; ++r; }
+  while (r < sp.nrows) {
+    const int c = ch * CHUNK;
+    const int64_t el0 = (int64_t)(sp.lfirst + r) * y.ld + col0 + c;
+    if (c + lane_col < stride) {
+      int64_t el = el0 + lane_col;
+      if (el0 + CHUNK - CPL > last) el = min(el, last);
+      __builtin_amdgcn_global_load_lds((gbl_void_t*)(ydata + el * ES),
+                                       (lds_void_t*)(stage + (r * stride + c) * ES), 16, 0, 0);
+    }
+    ch += NW;
+    while (ch >= nchunk) { ch -= nchunk; ++r; }
+  }
+}
+
+// Element-wise staging with the pulse index wrapped modulo N (used when the halo does not cover
+// the window or rows are not 16-byte aligned).  Synchronous: the data is in LDS after a barrier.
+template <int DT, int NW>
+__device__ __forceinline__ void stage_copy(const View& y, const char* __restrict__ ydata, char* stage, RowSpan sp,
+                                           int n, int a0, int half_w, int cols, int stride) {
+  constexpr int ES = Elem<DT>::bytes;
+  constexpr int NT = kWave * NW;
+  using TE = typename Elem<DT>::T;
+  constexpr int SU = 8;
+  const int total = sp.nrows * cols;
+  for (int i0 = threadIdx.x; i0 < total; i0 += NT * SU) {
+    TE v[SU];
+    int dst[SU];
+#pragma unroll
+    for (int u = 0; u < SU; ++u) {
+      const int i = i0 + u * NT;
+      dst[u] = -1;
+      if (i < total) {
+        const int r = i / cols;
+        const int c = i - r * cols;
+        int pn = a0 - half_w + c;
+        pn %= n;
+        pn += pn < 0 ? n : 0;
+        v[u] = *reinterpret_cast<const TE*>(ydata + ((int64_t)(sp.lfirst + r) * y.ld + pn + y.halo) * ES);
+        dst[u] = (r * stride + c) * ES;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < SU; ++u)
+      if (dst[u] >= 0) *reinterpret_cast<TE*>(stage + dst[u]) = v[u];
+  }
+}
+
+// Tap table of one range row, taps t = t0, t0 + tstep, ... (float64 bins of eq. 2 / eq. 40,
+// weights packed for the storage type).  Entries whose bin row is outside the staged span are
+// marked for the guard loop; returns true (for this thread) if it wrote such an entry.
+template <int DT, int WDT, int INTERP>
+__device__ __forceinline__ bool build_taps(const Geo& g, const View& y, int k, int half_w, int row, RowSpan sp,
+                                           int stride, int shift, const int32_t* __restrict__ offsets,
+                                           const void* __restrict__ weights, TapEntry* table, uint2* side, int t0,
+                                           int tstep) {
   constexpr int ES = Elem<DT>::bytes;
   constexpr int NSUB = INTERP == ROSAR_LINEAR ? 2 : 1;
-  constexpr int NT = kWave * NW;
-  constexpr int T = kWave * P * NW;
-  constexpr int CPL = 16 / ES;            // columns per lane of one 16-byte direct-to-LDS load
-  constexpr int CHUNK = kWave * CPL;      // columns per wave-wide direct-to-LDS load
-  const int ne = k * NSUB;
-  TapEntry* table = reinterpret_cast<TapEntry*>(smem);
-  uint2* side = reinterpret_cast<uint2*>(smem + ne * (int)sizeof(TapEntry));
-  char* stage = smem + ((ne * ((int)sizeof(TapEntry) + 8) + 15) & ~15);
-
-  const int lane = threadIdx.x & (kWave - 1);
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);   // wave-uniform
-  const int n = g.n;
-  const int a0 = tile * T;
-  const int half_w = window / 2;
   const int64_t wrow = (int64_t)row * k;
   const double rr = g.r0 + row * g.dr;
   const double c1 = rr * rr + g.radius * g.radius;
   const double c2 = 2.0 * rr * g.radius;
-
-  // ---- staged window: bin rows [lfirst, lfirst + nrows) from the geometry of this row alone
-  // (the slant range of a tap grows with |offset|: |R - r| at offset 0, at most that of offset
-  // W/2, whose cosine is cos_hw), columns of pulses [a0 - W/2, a0 + T + W/2)
-  const double u_near = g.beta * fabs(rr - g.radius);
-  const double u_far = g.beta * sqrt(c1 - c2 * cos_hw);
-  const int lfirst = max(bin_of<INTERP>(u_near) - y.l_lo, 0);
-  const int lspan = bin_of<INTERP>(u_far) - y.l_lo + NSUB - lfirst;
-  const int nrows = max(min(min(rows_cap, lspan), y.l_count - lfirst), 0);
-  int col0;   // stored column of staged column 0
-  if (use_dma) {
-    // direct-to-LDS 16-byte loads from an even stored column (the halo covers the window);
-    // chunk (r, c) of the staged rows is wave (r * nchunk + c) mod NW's, all indices uniform.
-    // The last chunk of a row is partial: its lanes past the row end stay idle.  Columns past
-    // the stored rotation (clamped) feed padded pixels only.
-    col0 = (a0 - half_w + y.halo) & ~(CPL - 1);
-    const int nchunk = (stride + CHUNK - 1) / CHUNK;
-    const int64_t last = (int64_t)y.l_count * y.ld - CPL;
-    const int lane_col = lane * CPL;
-    int r = 0, ch = wave;
-    while (ch >= nchunk) { ch -= nchunk; ++r; }
-    while (r < nrows) {
-      const int c = ch * CHUNK;
-      const int64_t el0 = (int64_t)(lfirst + r) * y.ld + col0 + c;
-      if (c + lane_col < stride) {
-        int64_t el = el0 + lane_col;
-        if (el0 + CHUNK - CPL > last) el = min(el, last);
-        __builtin_amdgcn_global_load_lds((gbl_void_t*)(ydata + el * ES),
-                                         (lds_void_t*)(stage + (r * stride + c) * ES), 16, 0, 0);
-      }
-      ch += NW;
-      while (ch >= nchunk) { ch -= nchunk; ++r; }
-    }
-  } else {
-    // element-wise copy with the pulse index wrapped modulo N
-    col0 = a0 - half_w + y.halo;
-    using TE = typename Elem<DT>::T;
-    constexpr int SU = 8;
-    const int cols = T + window;
-    const int total = nrows * cols;
-    for (int i0 = threadIdx.x; i0 < total; i0 += NT * SU) {
-      TE v[SU];
-      int dst[SU];
-#pragma unroll
-      for (int u = 0; u < SU; ++u) {
-        const int i = i0 + u * NT;
-        dst[u] = -1;
-        if (i < total) {
-          const int r = i / cols;
-          const int c = i - r * cols;
-          int pn = a0 - half_w + c;
-          pn %= n;
-          pn += pn < 0 ? n : 0;
-          v[u] = *reinterpret_cast<const TE*>(ydata + ((int64_t)(lfirst + r) * y.ld + pn + y.halo) * ES);
-          dst[u] = (r * stride + c) * ES;
-        }
-      }
-#pragma unroll
-      for (int u = 0; u < SU; ++u)
-        if (dst[u] >= 0) *reinterpret_cast<TE*>(stage + dst[u]) = v[u];
-    }
-  }
-  // LDS column of pixel a0 + i at offset o: i + o + shift
-  const int shift = (a0 - half_w + y.halo) - col0 + half_w;
-
-  // ---- tap table (tap t by thread t): float64 bins (eq. 2 / eq. 40), packed weights
-  if (threadIdx.x == 0) s_unstaged = 0;
-  __syncthreads();
-  for (int t = threadIdx.x; t < k; t += NT) {
+  bool unstaged = false;
+  for (int t = t0; t < k; t += tstep) {
     const int o = offsets[wrow + t];
     const float2 w = load_w<WDT>(weights, wrow + t);
     const bool inwin = o >= -half_w && o < half_w;
@@ -254,33 +263,39 @@ __device__ __forceinline__ void lds_tile(const Geo& g, const View& y, int32_t k,
     for (int s = 0; s < NSUB; ++s) {
       const int ls = l + s;
       const bool ok = inwin && ls >= 0 && ls < y.l_count;
-      const bool staged = ok && ls >= lfirst && ls < lfirst + nrows;
+      const bool staged = ok && ls >= sp.lfirst && ls < sp.lfirst + sp.nrows;
       const float fs = INTERP == ROSAR_NEAREST ? 1.f : (s == 0 ? 1.f - f : f);
       uint32_t w1, w2;
       pack_weight<DT>(ok ? make_float2(w.x * fs, w.y * fs) : make_float2(0.f, 0.f), w1, w2);
       TapEntry e;
-      e.lds_off = staged ? ((ls - lfirst) * stride + o + shift) * ES : 0;
+      e.lds_off = staged ? ((ls - sp.lfirst) * stride + o + shift) * ES : 0;
       e.glob_row = (ok && !staged) ? (int)(ls * y.ld) : -1;
       e.w1 = staged ? w1 : 0u;
       e.w2 = staged ? w2 : 0u;
       table[t * NSUB + s] = e;
       side[t * NSUB + s] = make_uint2(w1, w2);
-      if (ok && !staged) s_unstaged = 1;
+      unstaged |= ok && !staged;
     }
   }
-  if (use_dma) __builtin_amdgcn_s_waitcnt(0);  // direct-to-LDS loads complete
-  __syncthreads();
+  return unstaged;
+}
 
-  const int a_wave = a0 + wave * kWave * P;
-  if (a_wave >= n) return;  // whole wave past the row end (no barrier below)
-  const uint32_t lane_base = (uint32_t)((wave * kWave * P + lane) * ES);
-  float2 acc[P];
+// The P pixel chunks of one wave (pixels a_wave + lane + 64 p) into acc: staged entries from
+// LDS, then the guard loop for entries outside the staged rows (if any).  a_wave < n.
+template <int DT, int INTERP, int P>
+__device__ __forceinline__ void wave_pixels(float2 (&acc)[P], const Geo& g, const View& y, int k, int row,
+                                            int a_wave, int lane, const TapEntry* table, const uint2* side,
+                                            const char* stage, uint32_t lane_base, int ne_staged, bool unstaged,
+                                            const int32_t* __restrict__ offsets, const char* __restrict__ ydata) {
+  constexpr int ES = Elem<DT>::bytes;
+  constexpr int NSUB = INTERP == ROSAR_LINEAR ? 2 : 1;
+  const int n = g.n;
+  const int ne = k * NSUB;
 #pragma unroll
   for (int p = 0; p < P; ++p) acc[p] = make_float2(0.f, 0.f);
 
   // pixel chunks of 64 this wave really has (the last wave of a row may be partial)
   const int pa = min(P, (n - a_wave + kWave - 1) / kWave);
-  const int ne_staged = nrows > 0 ? ne : 0;
   if (pa == P) {
     staged_taps<DT, P, P>(acc, table, stage, lane_base, ne_staged);
   } else {
@@ -294,8 +309,9 @@ __device__ __forceinline__ void lds_tile(const Geo& g, const View& y, int32_t k,
       default: if constexpr (P > 7) staged_taps<DT, P, 7>(acc, table, stage, lane_base, ne_staged); break;
     }
   }
-  if (s_unstaged) {
+  if (unstaged) {
     // guard: sampled entries outside the staged rows, straight from global memory
+    const int64_t wrow = (int64_t)row * k;
     for (int e2 = 0; e2 < ne; ++e2) {
       const TapEntry te = table[e2];
       if (__builtin_amdgcn_readfirstlane(te.glob_row) < 0) continue;
@@ -319,14 +335,70 @@ __device__ __forceinline__ void lds_tile(const Geo& g, const View& y, int32_t k,
       }
     }
   }
+}
+
+template <int P>
+__device__ __forceinline__ void store_pixels(const float2 (&acc)[P], float inv_scale, int n, int row, int a_wave,
+                                             int lane, float2* __restrict__ image) {
   float2* out = image + (int64_t)row * n;
 #pragma unroll
   for (int p = 0; p < P; ++p) {
     const int a = a_wave + lane + kWave * p;
-    if (a < n) out[a] = make_float2(acc[p].x * y.inv_scale, acc[p].y * y.inv_scale);
+    if (a < n) out[a] = make_float2(acc[p].x * inv_scale, acc[p].y * inv_scale);
   }
 }
 
+// Byte offsets of the tap table, its side copy and the staged rows in one LDS buffer.
+__host__ __device__ constexpr int table_bytes(int ne) { return ne * (int)sizeof(TapEntry); }
+__host__ __device__ constexpr int stage_offset(int ne) { return (ne * ((int)sizeof(TapEntry) + 8) + 15) & ~15; }
+
+// One workgroup's tile: `row` x pixels [tile * T, tile * T + T) of a rotation.  All threads of
+// the workgroup call it; `smem` is the dynamic LDS (lds_bytes of the layout), `s_unstaged` a
+// workgroup-shared int.  Staging is issued at entry, while the threads build the row's tap
+// table (tap t by thread t).  Ends with every thread past its last LDS access, but callers
+// that reuse `smem` for another tile must place a barrier in between.
+template <int DT, int WDT, int INTERP, int P, int NW>
+__device__ __forceinline__ void lds_tile(const Geo& g, const View& y, int32_t k, int32_t window, int row,
+                                         int tile, int rows_cap, double cos_hw, int stride, int use_dma,
+                                         const int32_t* __restrict__ offsets, const void* __restrict__ weights,
+                                         const char* __restrict__ ydata, float2* __restrict__ image, char* smem,
+                                         int& s_unstaged) {
+  constexpr int ES = Elem<DT>::bytes;
+  constexpr int NSUB = INTERP == ROSAR_LINEAR ? 2 : 1;
+  constexpr int NT = kWave * NW;
+  constexpr int T = kWave * P * NW;
+  const int ne = k * NSUB;
+  TapEntry* table = reinterpret_cast<TapEntry*>(smem);
+  uint2* side = reinterpret_cast<uint2*>(smem + table_bytes(ne));
+  char* stage = smem + stage_offset(ne);
+
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);   // wave-uniform
+  const int n = g.n;
+  const int a0 = tile * T;
+  const int half_w = window / 2;
+  const RowSpan sp = row_span<INTERP>(g, y, row, rows_cap, cos_hw);
+  const int col0 = stage_col0<DT>(y, a0, half_w, use_dma);
+  if (use_dma) stage_dma<DT, NW>(y, ydata, stage, sp, col0, stride, wave, lane);
+  else stage_copy<DT, NW>(y, ydata, stage, sp, n, a0, half_w, T + window, stride);
+  const int shift = (a0 - half_w + y.halo) - col0 + half_w;
+
+  if (threadIdx.x == 0) s_unstaged = 0;
+  __syncthreads();
+  if (build_taps<DT, WDT, INTERP>(g, y, k, half_w, row, sp, stride, shift, offsets, weights, table, side,
+                                  threadIdx.x, NT))
+    s_unstaged = 1;
+  if (use_dma) __builtin_amdgcn_s_waitcnt(0);  // direct-to-LDS loads complete
+  __syncthreads();
+
+  const int a_wave = a0 + wave * kWave * P;
+  if (a_wave >= n) return;  // whole wave past the row end (no barrier below)
+  const uint32_t lane_base = (uint32_t)((wave * kWave * P + lane) * ES);
+  float2 acc[P];
+  wave_pixels<DT, INTERP, P>(acc, g, y, k, row, a_wave, lane, table, side, stage, lane_base, sp.nrows > 0 ? ne : 0,
+                             s_unstaged != 0, offsets, ydata);
+  store_pixels<P>(acc, y.inv_scale, n, row, a_wave, lane, image);
+}
 
 // ---------------------------------------------------------------------------------- host side
 constexpr size_t kLdsBudget = 78 * 1024;   // two workgroups per CU (160 KB of LDS), with room for static LDS

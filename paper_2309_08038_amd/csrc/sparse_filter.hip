@@ -20,22 +20,6 @@
 namespace rosar {
 namespace {
 
-// Raw buffer resource over `bytes` bytes (gfx9 family word 3).  Loads address
-// base + voffset + soffset; every offset the kernels form stays inside the buffer.
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* p, uint32_t bytes) {
-  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, 0x00020000);
-}
-
-template <int DT>
-__device__ __forceinline__ float2 buf_load(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
-  if constexpr (DT == 0) {
-    return __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
-  } else {
-    const uint32_t v = __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0);
-    return DT == 1 ? unpack_f16x2(v) : unpack_bf16x2(v);
-  }
-}
-
 // U consecutive taps starting at tap tt of the current 64-tap chunk: loads first, then FMAs.
 // MASKED: sub-taps without a sample and taps at or beyond `cnt` contribute zero.
 template <int DT, int WDT, int INTERP, int P, int U, bool MASKED>

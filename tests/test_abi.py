@@ -172,7 +172,7 @@ def test_bp_and_backward_workspace_checks(lib):
     g = geom()
     n = C.c_size_t(0)
     assert lib.rosar_bp_full_workspace_size(C.byref(g), C.byref(n)) == L.ROSAR_OK
-    assert n.value >= 360 * 16
+    assert n.value >= 256 + 360 * 8   # header + (sin, cos) of half the angle error per pulse, float32
     grid = L.PolarGrid(8, 360, 1.0, 0.05)
     view = L.RcView(0x20000, L.C64, 0, 64, 32, 424, 1.0, 0)
     # NULL / misaligned / short workspace
