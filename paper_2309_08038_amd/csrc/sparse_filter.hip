@@ -10,11 +10,8 @@
 // range-compressed rows and 4P FMAs, with no per-lane address arithmetic.  LINEAR
 // interpolation is two sub-taps with real factors (1-f, f) folded into the weight.
 //
-// Corrected path (per-pulse angle error dphi and phase error psi).  The slant range now varies
-// per (pixel, tap) through dphi[n], so each pair evaluates the float64 geometry
-// cos(D0 + dphi) = cos D0 cos dphi - sin D0 sin dphi with per-column cos/sin tables staged in
-// LDS, a float64 square root, the bin, and the phase correction exp(-j 2k (R^ - R_nom) - j psi)
-// on the hardware sine/cosine after a float64 range reduction.
+// Corrected path (per-pulse angle error dphi and phase error psi): see
+// sparse_corrected_kernel.
 #include "sparse_device.hpp"
 
 namespace rosar {
@@ -174,108 +171,165 @@ __global__ __launch_bounds__(kWave* NW) void sparse_plain_kernel(
 }
 
 constexpr int kCorrThreads = 256;
-constexpr int kCorrMaxCols = 2048;  // LDS table columns (tile + window)
+constexpr int kCorrP = 4;                          // pixels per lane (64 apart)
+constexpr int kCorrTile = kCorrThreads * kCorrP;   // pixels per workgroup
+constexpr int kCorrChunk = kCorrThreads;           // taps per chunk (one per thread)
+constexpr int kCorrMaxCols = 4096;                 // largest per-pulse table held in LDS (T + W)
 
+// Nominal geometry and weight of one tap (no angle error), 48 bytes.
+struct alignas(16) CorrTap {
+  double u;       // band-relative bin beta * R_nom - l_lo (+ 1/2 for NEAREST)
+  float r2;       // R_nom^2
+  float rnom;     // R_nom
+  float sd, cd;   // sin, cos of D0 = 2 pi o / N
+  float wr, wi;   // weight (zero for an offset outside the window)
+  int32_t o;      // offset
+  int32_t pad;
+};
+
+// Corrected path: the angle error d_n and phase error psi_n of pulse n move the slant range of
+// every (pixel, tap) pair: R^ = R(D0 + d_n).  The workgroup (one row, kCorrTile pixels)
+// computes the taps' nominal geometry in float64 into LDS and stages, per column of pulses
+// [a0 - W/2, a0 + T + W/2), (sin(d/2), cos(d/2), psi / 2 pi).  Per pair only the correction is
+// evaluated, in float32 and without cancellation:
+//   R^2 - R_nom^2 = 4 R r sin(D0 + d/2) sin(d/2),  R^ - R_nom = (R^2 - R_nom^2) / (R^ + R_nom),
+// the bin is the float64 nominal bin plus beta (R^ - R_nom), the sample comes through buffer
+// loads (out-of-band rows read zero), and the phase factor exp(-j (2 k (R^ - R_nom) + psi))
+// runs on the hardware sine/cosine in revolutions.  TABLE = false (window too wide for the
+// LDS table) evaluates the per-pulse values for every pair from global memory.
 template <int DT, int WDT, int INTERP, bool TABLE>
 __global__ __launch_bounds__(kCorrThreads) void sparse_corrected_kernel(
     Geo g, View y, int32_t k, int32_t window, int tiles_per_row, int nblocks,
     const int32_t* __restrict__ offsets, const void* __restrict__ weights,
     const float* __restrict__ dphi, const float* __restrict__ dpsi,
     const char* __restrict__ ydata, float2* __restrict__ image) {
-  __shared__ double s_cos[TABLE ? kCorrMaxCols : 1];
-  __shared__ double s_sin[TABLE ? kCorrMaxCols : 1];
-  __shared__ float s_psi[TABLE ? kCorrMaxCols : 1];
-  const int lane = threadIdx.x & (kWave - 1);
+  constexpr int ES = Elem<DT>::bytes;
+  constexpr float kInv2Pi = 0.15915494309189533577f;
+  __shared__ CorrTap s_tap[kCorrChunk];
+  extern __shared__ float4 s_pul[];   // TABLE: kCorrTile + window entries
   const int blk = xcd_logical_block(blockIdx.x, nblocks);
   const int row = blk / tiles_per_row;
   const int tile = blk - row * tiles_per_row;
   const int n = g.n;
   const int half_w = window / 2;
-  const int a0 = tile * kCorrThreads;
-  const int a = a0 + threadIdx.x;
-  constexpr double kInv2Pi = 0.15915494309189533577;
+  const int a0 = tile * kCorrTile;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wave = threadIdx.x / kWave;
+  const int i_wave = wave * kWave * kCorrP;
 
   if constexpr (TABLE) {
-    // columns c <-> pulse (a0 - W/2 + c) mod N
-    const int ncol = kCorrThreads + window;
-    for (int c = threadIdx.x; c < ncol; c += kCorrThreads) {
-      int pn = a0 - half_w + c;
-      pn %= n;
-      if (pn < 0) pn += n;
-      const double d = dphi ? (double)dphi[pn] : 0.0;
-      double sd, cd;
-      sincos(d, &sd, &cd);
-      s_cos[c] = cd;
-      s_sin[c] = sd;
-      s_psi[c] = dpsi ? dpsi[pn] : 0.f;
+    for (int c = threadIdx.x; c < kCorrTile + window; c += kCorrThreads) {
+      int pn = (a0 - half_w + c) % n;
+      pn += pn < 0 ? n : 0;
+      float sh = 0.f, ch = 1.f;
+      if (dphi) sincosf(0.5f * dphi[pn], &sh, &ch);
+      s_pul[c] = make_float4(sh, ch, dpsi ? dpsi[pn] * kInv2Pi : 0.f, 0.f);
     }
-    __syncthreads();
   }
-  if (a0 + (threadIdx.x & ~(kWave - 1)) >= n) return;  // whole wave past the row end
-  const int ac = min(a, n - 1);
 
   const double rr = g.r0 + row * g.dr;
   const double c1 = rr * rr + g.radius * g.radius;
   const double c2 = 2.0 * rr * g.radius;
+  const float c4 = (float)(2.0 * c2);   // 4 R r
+  const float kpi = (float)g.k_over_pi;
+  const float beta = (float)g.beta;
+  const double u_shift = INTERP == ROSAR_NEAREST ? 0.5 - y.l_lo : -(double)y.l_lo;
+  const __amdgpu_buffer_rsrc_t rsrc = make_rsrc(ydata, (uint32_t)((int64_t)y.l_count * y.ld * ES));
+  const int ld_es = (int)(y.ld * ES);
+  const bool direct = y.halo >= half_w;   // the halo holds every column a + o (no wrap)
   const int64_t wrow = (int64_t)row * k;
-  float2 acc = make_float2(0.f, 0.f);
-
-  for (int c0 = 0; c0 < k; c0 += kWave) {
-    const int t = c0 + lane;
-    int ofs = 0;
-    double cd0 = 1.0, sd0 = 0.0, rnom = 0.0;
-    if (t < k) {
-      ofs = offsets[wrow + t];
-      sincos(ofs * g.step, &sd0, &cd0);
-      rnom = sqrt(c1 - c2 * cd0);
-    }
-    const int cnt = min(kWave, k - c0);
-    for (int tt = 0; tt < cnt; ++tt) {
-      const int o = readlane(ofs, tt);
-      if (o < -half_w || o >= half_w) continue;
-      const double cD0 = readlane(cd0, tt);
-      const double sD0 = readlane(sd0, tt);
-      const double rN = readlane(rnom, tt);
-      const float2 w = load_w<WDT>(weights, wrow + c0 + tt);
-      int pn = ac + o;
-      pn += (pn < 0) ? n : 0;
-      pn -= (pn >= n) ? n : 0;
-      double cd, sd;
-      float ps;
-      if constexpr (TABLE) {
-        const int c = ac - a0 + o + half_w;
-        cd = s_cos[c];
-        sd = s_sin[c];
-        ps = s_psi[c];
-      } else {
-        const double d = dphi ? (double)dphi[pn] : 0.0;
-        sincos(d, &sd, &cd);
-        ps = dpsi ? dpsi[pn] : 0.f;
-      }
-      const double cosd = cD0 * cd - sD0 * sd;
-      const double rh = sqrt(c1 - c2 * cosd);
-      const double u = g.beta * rh;
-      const int64_t col = pn + y.halo;
-      float2 smp;
-      if constexpr (INTERP == ROSAR_NEAREST) {
-        const int l = (int)floor(u + 0.5) - y.l_lo;
-        smp = (l >= 0 && l < y.l_count) ? load_c<DT>(ydata, l * y.ld + col) : make_float2(0.f, 0.f);
-      } else {
-        const double fl = floor(u);
-        const float f = (float)(u - fl);
-        const int l = (int)fl - y.l_lo;
-        const float2 y0 = (l >= 0 && l < y.l_count) ? load_c<DT>(ydata, l * y.ld + col) : make_float2(0.f, 0.f);
-        const float2 y1 = (l + 1 >= 0 && l + 1 < y.l_count) ? load_c<DT>(ydata, (l + 1) * y.ld + col)
-                                                             : make_float2(0.f, 0.f);
-        smp = make_float2(fmaf(f, y1.x - y0.x, y0.x), fmaf(f, y1.y - y0.y, y0.y));
-      }
-      // exp(-j (2k (R^ - R_nom) + psi)), phase counted in revolutions and reduced in float64
-      const float fr = frac_rev(g.k_over_pi * (rh - rN) + (double)ps * kInv2Pi);
-      const float2 rot = make_float2(cos_rev(fr), -sin_rev(fr));
-      cmac_conj(acc, w, cmul(smp, rot));
-    }
+  int acol[kCorrP];   // pixel column, clamped into the rotation for padding lanes
+  float2 acc[kCorrP];
+#pragma unroll
+  for (int p = 0; p < kCorrP; ++p) {
+    acol[p] = min(a0 + i_wave + lane + kWave * p, n - 1);
+    acc[p] = make_float2(0.f, 0.f);
   }
-  if (a < n) image[(int64_t)row * n + a] = make_float2(acc.x * y.inv_scale, acc.y * y.inv_scale);
+
+  for (int c0 = 0; c0 < k; c0 += kCorrChunk) {
+    const int cnt = min(kCorrChunk, k - c0);
+    if ((int)threadIdx.x < cnt) {
+      const int t = c0 + (int)threadIdx.x;
+      const int o = offsets[wrow + t];
+      const float2 w = load_w<WDT>(weights, wrow + t);
+      const bool inwin = o >= -half_w && o < half_w;
+      double sd, cd;
+      sincos(o * g.step, &sd, &cd);
+      const double r2 = c1 - c2 * cd;
+      const double rn = sqrt(r2);
+      CorrTap e;
+      e.u = g.beta * rn + u_shift;
+      e.r2 = (float)r2;
+      e.rnom = (float)rn;
+      e.sd = (float)sd;
+      e.cd = (float)cd;
+      e.wr = inwin ? w.x : 0.f;
+      e.wi = inwin ? w.y : 0.f;
+      e.o = inwin ? o : 0;
+      e.pad = 0;
+      s_tap[threadIdx.x] = e;
+    }
+    __syncthreads();
+    for (int t = 0; t < cnt; ++t) {
+      const CorrTap tp = s_tap[t];
+      const float2 w = make_float2(tp.wr, tp.wi);
+#pragma unroll
+      for (int p = 0; p < kCorrP; ++p) {
+        float sh, ch, pr;
+        int col = acol[p] + tp.o;
+        if constexpr (TABLE) {
+          const float4 q = s_pul[i_wave + lane + kWave * p + tp.o + half_w];
+          sh = q.x;
+          ch = q.y;
+          pr = q.z;
+        } else {
+          int pn = col;
+          pn += (pn < 0) ? n : 0;
+          pn -= (pn >= n) ? n : 0;
+          sh = 0.f;
+          ch = 1.f;
+          if (dphi) sincosf(0.5f * dphi[pn], &sh, &ch);
+          pr = dpsi ? dpsi[pn] * kInv2Pi : 0.f;
+        }
+        if (!direct) {
+          col += (col < 0) ? n : 0;
+          col -= (col >= n) ? n : 0;
+        }
+        const int cb = (col + y.halo) * ES;
+        const float s_mid = fmaf(tp.sd, ch, tp.cd * sh);   // sin(D0 + d/2)
+        const float dd = c4 * s_mid * sh;                    // R^2 - R_nom^2
+        const float r2 = fmaxf(tp.r2 + dd, 1e-30f);
+        const float rn = r2 * __builtin_amdgcn_rsqf(r2);
+        const float diff = dd * __builtin_amdgcn_rcpf(rn + tp.rnom);   // R^ - R_nom
+        const double u = tp.u + (double)(beta * diff);
+        float2 smp;
+        if constexpr (INTERP == ROSAR_NEAREST) {
+          const int l = min(max((int)floor(u), -1), y.l_count);
+          smp = buf_load<DT>(rsrc, (uint32_t)(__mul24(l, ld_es) + cb), 0u);
+        } else {
+          const double fl = floor(u);
+          const float f = (float)(u - fl);
+          const int l = min(max((int)fl, -2), y.l_count);
+          const uint32_t off0 = (uint32_t)(__mul24(l, ld_es) + cb);
+          const float2 y0 = buf_load<DT>(rsrc, off0, 0u);
+          const float2 y1 = buf_load<DT>(rsrc, off0 + (uint32_t)ld_es, 0u);
+          smp = make_float2(fmaf(f, y1.x - y0.x, y0.x), fmaf(f, y1.y - y0.y, y0.y));
+        }
+        // exp(-j (2 k (R^ - R_nom) + psi)) in revolutions
+        float fr = fmaf(kpi, diff, pr);
+        fr -= floorf(fr);
+        const float2 rot = make_float2(cos_rev(fr), -sin_rev(fr));
+        cmac_conj(acc[p], w, cmul(smp, rot));
+      }
+    }
+    __syncthreads();
+  }
+  float2* out = image + (int64_t)row * n;
+#pragma unroll
+  for (int p = 0; p < kCorrP; ++p) {
+    const int a = a0 + i_wave + lane + kWave * p;
+    if (a < n) out[a] = make_float2(acc[p].x * y.inv_scale, acc[p].y * y.inv_scale);
+  }
 }
 
 template <int DT, int WDT, int INTERP, int P, int NW>
@@ -348,11 +402,12 @@ hipError_t launch_plain_dt(const SparseArgs& a, const Tile& t, hipStream_t s) {
 
 template <int DT, int WDT, int INTERP>
 hipError_t launch_corr_t(const SparseArgs& a, hipStream_t s) {
-  const int tiles = (a.g.n + kCorrThreads - 1) / kCorrThreads;
+  const int tiles = (a.g.n + kCorrTile - 1) / kCorrTile;
   const int nblocks = tiles * a.g.n_range;
   const char* yd = reinterpret_cast<const char*>(a.y.data);
-  if (kCorrThreads + a.window <= kCorrMaxCols) {
-    sparse_corrected_kernel<DT, WDT, INTERP, true><<<nblocks, kCorrThreads, 0, s>>>(
+  if (kCorrTile + a.window <= kCorrMaxCols) {
+    const size_t lds = (size_t)(kCorrTile + a.window) * sizeof(float4);
+    sparse_corrected_kernel<DT, WDT, INTERP, true><<<nblocks, kCorrThreads, lds, s>>>(
         a.g, a.y, a.k, a.window, tiles, nblocks, a.offsets, a.weights, a.dphi, a.dpsi, yd, a.image);
   } else {
     sparse_corrected_kernel<DT, WDT, INTERP, false><<<nblocks, kCorrThreads, 0, s>>>(
