@@ -12,8 +12,13 @@
 // contribution to grad_dphi[n] accumulates in that thread).  For each tap the thread visits
 // pixel a = n - o_t, recomputes the sample and its derivative (indices are never stored), and
 // feeds conj(g) s into a per-tap partial reduced across the wavefront and then across the
-// waves in a fixed order.  Row partials of grad_dphi/grad_dpsi go to the workspace and a
-// second kernel sums them over rows, row by row, in a fixed order.
+// waves in a fixed order.  The taps' nominal geometry (float64 bin of R_nom, R_nom, sin/cos of
+// D0 = 2 pi o / N) and weights sit in an LDS table; per (pulse, tap) only the angle-error
+// correction is evaluated, in float32 without cancellation:
+//   R^2 - R_nom^2 = 4 R r sin(D0 + d/2) sin(d/2),   R^ - R_nom = (R^2 - R_nom^2)/(R^ + R_nom),
+// with the bin formed in float64 and the samples read through buffer loads (out-of-band rows
+// read zero).  Row partials of grad_dphi/grad_dpsi go to the workspace; a two-stage reduction
+// sums them over rows in a fixed order (groups of rows, then the groups).
 #include "rosar_device.hpp"
 
 namespace rosar {
@@ -23,6 +28,19 @@ constexpr int kBwThreads = 256;
 constexpr int kBwWaves = kBwThreads / kWave;
 constexpr int kBwPpt = 8;      // pulses per thread per pass
 constexpr int kBwMaxK = 1024;
+constexpr int kBwChunk = kBwThreads;   // taps per LDS table chunk
+constexpr int kRedGroups = 32;         // row groups of the first reduction stage
+
+// Nominal geometry and weight of one tap, 48 bytes.
+struct alignas(16) BwTap {
+  double u;       // band-relative bin beta * R_nom - l_lo (+ 1/2 for NEAREST)
+  float r2;       // R_nom^2
+  float rnom;     // R_nom
+  float sd, cd;   // sin, cos of D0
+  float wr, wi;   // weight
+  int32_t o;      // offset
+  int32_t valid;  // offset inside the window
+};
 
 __device__ __forceinline__ float2 wave_sum(float2 v) {
   for (int off = kWave / 2; off > 0; off >>= 1) {
@@ -39,7 +57,10 @@ __global__ __launch_bounds__(kBwThreads) void backward_row_kernel(
     const float* __restrict__ dphi, const float* __restrict__ dpsi,
     const float2* __restrict__ gimg, const char* __restrict__ ydata,
     float2* __restrict__ grad_w, float* __restrict__ part_d, float* __restrict__ part_p) {
+  constexpr int ES = Elem<DT>::bytes;
+  constexpr float kInv2Pi = 0.15915494309189533577f;
   __shared__ float2 s_gw[kBwWaves][kBwMaxK];
+  __shared__ BwTap s_tap[kBwChunk];
   const int lane = threadIdx.x & (kWave - 1);
   const int wave = threadIdx.x / kWave;
   const int row = xcd_logical_block(blockIdx.x, nblocks);
@@ -47,96 +68,115 @@ __global__ __launch_bounds__(kBwThreads) void backward_row_kernel(
   const int half_w = window / 2;
   for (int t = threadIdx.x; t < k; t += kBwThreads)
     for (int w = 0; w < kBwWaves; ++w) s_gw[w][t] = make_float2(0.f, 0.f);
-  __syncthreads();
 
   const double rr = g.r0 + row * g.dr;
   const double c1 = rr * rr + g.radius * g.radius;
   const double c2 = 2.0 * rr * g.radius;
-  const double rrr = rr * g.radius;
+  const float c4 = (float)(2.0 * c2);          // 4 R r
+  const float rrr = (float)(rr * g.radius);    // R r
   const float two_k = (float)(2.0 * g.kw);
+  const float kpi = (float)g.k_over_pi;
   const float beta = (float)g.beta;
   const float isc = y.inv_scale;
-  constexpr double kInv2Pi = 0.15915494309189533577;
+  const double u_shift = INTERP == ROSAR_NEAREST ? 0.5 - y.l_lo : -(double)y.l_lo;
+  const __amdgpu_buffer_rsrc_t rsrc = make_rsrc(ydata, (uint32_t)((int64_t)y.l_count * y.ld * ES));
+  const int ld_es = (int)(y.ld * ES);
   const int64_t wrow = (int64_t)row * k;
   const float2* grow = gimg + (int64_t)row * n;
 
   for (int base = 0; base < n; base += kBwThreads * kBwPpt) {
-    double cd[kBwPpt], sd[kBwPpt];
-    float ps[kBwPpt], gd[kBwPpt], gp[kBwPpt];
+    float sh[kBwPpt], ch[kBwPpt], pr[kBwPpt], gd[kBwPpt], gp[kBwPpt];
+    int cb[kBwPpt];   // byte offset of the pulse's column within a row
 #pragma unroll
     for (int j = 0; j < kBwPpt; ++j) {
-      const int pn = base + threadIdx.x + kBwThreads * j;
-      const double d = (pn < n && dphi) ? (double)dphi[pn] : 0.0;
-      sincos(d, &sd[j], &cd[j]);
-      ps[j] = (pn < n && dpsi) ? dpsi[pn] : 0.f;
+      const int pn = min(base + (int)threadIdx.x + kBwThreads * j, n - 1);
+      sh[j] = 0.f;
+      ch[j] = 1.f;
+      if (dphi) sincosf(0.5f * dphi[pn], &sh[j], &ch[j]);
+      pr[j] = dpsi ? dpsi[pn] * kInv2Pi : 0.f;
+      cb[j] = (pn + y.halo) * ES;
       gd[j] = 0.f;
       gp[j] = 0.f;
     }
-    for (int c0 = 0; c0 < k; c0 += kWave) {
-      const int t = c0 + lane;
-      int ofs = 0;
-      double cd0 = 1.0, sd0 = 0.0, rnom = 0.0;
-      if (t < k) {
-        ofs = offsets[wrow + t];
-        sincos(ofs * g.step, &sd0, &cd0);
-        rnom = sqrt(c1 - c2 * cd0);
+    for (int c0 = 0; c0 < k; c0 += kBwChunk) {
+      const int cnt = min(kBwChunk, k - c0);
+      __syncthreads();   // the previous chunk's table is no longer read
+      if ((int)threadIdx.x < cnt) {
+        const int t = c0 + (int)threadIdx.x;
+        const int o = offsets[wrow + t];
+        double sd, cd;
+        sincos(o * g.step, &sd, &cd);
+        const double r2 = c1 - c2 * cd;
+        const double rn = sqrt(r2);
+        const float2 w = weights[wrow + t];
+        BwTap e;
+        e.u = g.beta * rn + u_shift;
+        e.r2 = (float)r2;
+        e.rnom = (float)rn;
+        e.sd = (float)sd;
+        e.cd = (float)cd;
+        e.wr = w.x;
+        e.wi = w.y;
+        e.o = o;
+        e.valid = (o >= -half_w && o < half_w) ? 1 : 0;
+        s_tap[threadIdx.x] = e;
       }
-      const int cnt = min(kWave, k - c0);
+      __syncthreads();
       for (int tt = 0; tt < cnt; ++tt) {
-        const int o = readlane(ofs, tt);
-        if (o < -half_w || o >= half_w) continue;
-        const double cD0 = readlane(cd0, tt);
-        const double sD0 = readlane(sd0, tt);
-        const double rN = readlane(rnom, tt);
-        const float2 w = weights[wrow + c0 + tt];
+        const BwTap tp = s_tap[tt];
+        if (!tp.valid) continue;   // uniform
         float2 gw = make_float2(0.f, 0.f);
 #pragma unroll
         for (int j = 0; j < kBwPpt; ++j) {
-          const int pn = base + threadIdx.x + kBwThreads * j;
-          if (pn < n) {
-            int ap = pn - o;
-            ap += (ap < 0) ? n : 0;
-            ap -= (ap >= n) ? n : 0;
-            const float2 gv = grow[ap];
-            const double cosd = cD0 * cd[j] - sD0 * sd[j];
-            const double sind = sD0 * cd[j] + cD0 * sd[j];
-            const double rh = sqrt(c1 - c2 * cosd);
-            const double u = g.beta * rh;
-            const int64_t col = pn + y.halo;
-            float2 yv, dy = make_float2(0.f, 0.f);
-            if constexpr (INTERP == ROSAR_NEAREST) {
-              const int l = (int)floor(u + 0.5) - y.l_lo;
-              yv = (l >= 0 && l < y.l_count) ? load_c<DT>(ydata, l * y.ld + col) : make_float2(0.f, 0.f);
-            } else {
-              const double fl = floor(u);
-              const float f = (float)(u - fl);
-              const int l = (int)fl - y.l_lo;
-              const float2 y0 = (l >= 0 && l < y.l_count) ? load_c<DT>(ydata, l * y.ld + col) : make_float2(0.f, 0.f);
-              const float2 y1 = (l + 1 >= 0 && l + 1 < y.l_count) ? load_c<DT>(ydata, (l + 1) * y.ld + col)
-                                                                   : make_float2(0.f, 0.f);
-              dy = make_float2((y1.x - y0.x) * isc, (y1.y - y0.y) * isc);
-              yv = make_float2(fmaf(f, y1.x - y0.x, y0.x), fmaf(f, y1.y - y0.y, y0.y));
-            }
-            yv.x *= isc;
-            yv.y *= isc;
-            const float fr = frac_rev(g.k_over_pi * (rh - rN) + (double)ps[j] * kInv2Pi);
-            const float2 rot = make_float2(cos_rev(fr), -sin_rev(fr));
-            const float2 s = cmul(yv, rot);
-            // conj(g) s
-            gw.x = fmaf(gv.x, s.x, fmaf(gv.y, s.y, gw.x));
-            gw.y = fmaf(gv.x, s.y, fmaf(-gv.y, s.x, gw.y));
-            // ds/d dphi
-            const float dr = (float)(rrr * sind / rh);
-            const float2 inner = make_float2(beta * dy.x + two_k * yv.y, beta * dy.y - two_k * yv.x);
-            const float2 dsd = cmul(rot, inner);
-            // z = conj(g) conj(w) = conj(g w)
-            const float2 gw_ = cmul(gv, w);
-            const float2 z = make_float2(gw_.x, -gw_.y);
-            const float2 zd = cmul(z, dsd);
-            const float2 zs = cmul(z, s);
-            gd[j] = fmaf(zd.x, dr, gd[j]);
-            gp[j] += zs.y;
+          const int pn = base + (int)threadIdx.x + kBwThreads * j;
+          int ap = min(pn, n - 1) - tp.o;
+          ap += (ap < 0) ? n : 0;
+          ap -= (ap >= n) ? n : 0;
+          // pulses past N (last pass) take a zero gradient sample: they add nothing
+          const float2 gv = pn < n ? grow[ap] : make_float2(0.f, 0.f);
+          const float s_mid = fmaf(tp.sd, ch[j], tp.cd * sh[j]);   // sin(D0 + d/2)
+          const float dd = c4 * s_mid * sh[j];                      // R^2 - R_nom^2
+          const float r2 = fmaxf(tp.r2 + dd, 1e-30f);
+          const float rs = __builtin_amdgcn_rsqf(r2);
+          const float rh = r2 * rs;
+          const float diff = dd * __builtin_amdgcn_rcpf(rh + tp.rnom);   // R^ - R_nom
+          const double u = tp.u + (double)(beta * diff);
+          float2 yv, dy = make_float2(0.f, 0.f);
+          if constexpr (INTERP == ROSAR_NEAREST) {
+            const int l = min(max((int)floor(u), -1), y.l_count);
+            yv = buf_load<DT>(rsrc, (uint32_t)(__mul24(l, ld_es) + cb[j]), 0u);
+          } else {
+            const double fl = floor(u);
+            const float f = (float)(u - fl);
+            const int l = min(max((int)fl, -2), y.l_count);
+            const uint32_t off0 = (uint32_t)(__mul24(l, ld_es) + cb[j]);
+            const float2 y0 = buf_load<DT>(rsrc, off0, 0u);
+            const float2 y1 = buf_load<DT>(rsrc, off0 + (uint32_t)ld_es, 0u);
+            dy = make_float2((y1.x - y0.x) * isc, (y1.y - y0.y) * isc);
+            yv = make_float2(fmaf(f, y1.x - y0.x, y0.x), fmaf(f, y1.y - y0.y, y0.y));
           }
+          yv.x *= isc;
+          yv.y *= isc;
+          float fr = fmaf(kpi, diff, pr[j]);
+          fr -= floorf(fr);
+          const float2 rot = make_float2(cos_rev(fr), -sin_rev(fr));
+          const float2 s = cmul(yv, rot);
+          // conj(g) s
+          gw.x = fmaf(gv.x, s.x, fmaf(gv.y, s.y, gw.x));
+          gw.y = fmaf(gv.x, s.y, fmaf(-gv.y, s.x, gw.y));
+          // ds/d dphi = rot (beta dY/du - j 2k Y) R r sin(D) / R^,  D = D0 + d:
+          // sin D = sin D0 (1 - 2 sin^2(d/2)) + cos D0 2 sin(d/2) cos(d/2)
+          const float sind = fmaf(tp.sd, fmaf(-2.f * sh[j], sh[j], 1.f), tp.cd * 2.f * sh[j] * ch[j]);
+          const float dr = rrr * sind * rs;
+          const float2 inner = make_float2(beta * dy.x + two_k * yv.y, beta * dy.y - two_k * yv.x);
+          const float2 dsd = cmul(rot, inner);
+          // z = conj(g) conj(w) = conj(g w)
+          const float2 gw_ = cmul(gv, make_float2(tp.wr, tp.wi));
+          const float2 z = make_float2(gw_.x, -gw_.y);
+          const float2 zd = cmul(z, dsd);
+          const float2 zs = cmul(z, s);
+          gd[j] = fmaf(zd.x, dr, gd[j]);
+          gp[j] += zs.y;
         }
         gw = wave_sum(gw);
         if (lane == 0) {
@@ -164,17 +204,38 @@ __global__ __launch_bounds__(kBwThreads) void backward_row_kernel(
   }
 }
 
-__global__ __launch_bounds__(256) void backward_reduce_kernel(int32_t n, int32_t n_range,
-                                                              const float* __restrict__ part_d,
-                                                              const float* __restrict__ part_p,
-                                                              float* __restrict__ grad_dphi,
-                                                              float* __restrict__ grad_dpsi) {
+// Stage 1: group gy sums rows [gy * rows_per, min((gy + 1) * rows_per, n_range)) of the row
+// partials, row by row, into group partials.  Stage 2 adds the groups in order.
+__global__ __launch_bounds__(256) void backward_reduce_rows_kernel(int32_t n, int32_t n_range, int32_t rows_per,
+                                                                   const float* __restrict__ part_d,
+                                                                   const float* __restrict__ part_p,
+                                                                   float* __restrict__ grp_d,
+                                                                   float* __restrict__ grp_p) {
+  const int pn = blockIdx.x * blockDim.x + threadIdx.x;
+  const int gy = blockIdx.y;
+  if (pn >= n) return;
+  const int r0 = gy * rows_per;
+  const int r1 = min(r0 + rows_per, n_range);
+  float sd = 0.f, sp = 0.f;
+  for (int r = r0; r < r1; ++r) {
+    sd += part_d[(int64_t)r * n + pn];
+    sp += part_p[(int64_t)r * n + pn];
+  }
+  grp_d[(int64_t)gy * n + pn] = sd;
+  grp_p[(int64_t)gy * n + pn] = sp;
+}
+
+__global__ __launch_bounds__(256) void backward_reduce_groups_kernel(int32_t n, int32_t groups,
+                                                                     const float* __restrict__ grp_d,
+                                                                     const float* __restrict__ grp_p,
+                                                                     float* __restrict__ grad_dphi,
+                                                                     float* __restrict__ grad_dpsi) {
   const int pn = blockIdx.x * blockDim.x + threadIdx.x;
   if (pn >= n) return;
   float sd = 0.f, sp = 0.f;
-  for (int r = 0; r < n_range; ++r) {
-    sd += part_d[(int64_t)r * n + pn];
-    sp += part_p[(int64_t)r * n + pn];
+  for (int gy = 0; gy < groups; ++gy) {
+    sd += grp_d[(int64_t)gy * n + pn];
+    sp += grp_p[(int64_t)gy * n + pn];
   }
   if (grad_dphi) grad_dphi[pn] = sd;
   if (grad_dpsi) grad_dpsi[pn] = sp;
@@ -197,15 +258,19 @@ hipError_t launch_dt(const SparseArgs& a, const float2* gimg, float2* grad_w, fl
 
 }  // namespace
 
+// Row partials (2 x n_range x N floats) followed by the group partials (2 x kRedGroups x N).
 size_t backward_workspace_bytes(int32_t n, int32_t n_range, int32_t k) {
   (void)k;
-  return 2 * (size_t)n * (size_t)n_range * sizeof(float);
+  return 2 * (size_t)n * ((size_t)n_range + kRedGroups) * sizeof(float);
 }
 
 hipError_t launch_sparse_backward(const SparseArgs& a, const float2* grad_image, float2* grad_w,
                                   float* grad_dphi, float* grad_dpsi, void* ws, hipStream_t s) {
+  const int n = a.g.n, nr = a.g.n_range;
   float* pd = reinterpret_cast<float*>(ws);
-  float* pp = pd + (size_t)a.g.n * a.g.n_range;
+  float* pp = pd + (size_t)n * nr;
+  float* gd = pp + (size_t)n * nr;
+  float* gp = gd + (size_t)n * kRedGroups;
   hipError_t e;
   switch (a.y.dtype) {
     case ROSAR_C64: e = launch_dt<0>(a, grad_image, grad_w, pd, pp, s); break;
@@ -214,8 +279,11 @@ hipError_t launch_sparse_backward(const SparseArgs& a, const float2* grad_image,
   }
   if (e != hipSuccess) return e;
   if (grad_dphi || grad_dpsi) {
-    backward_reduce_kernel<<<(a.g.n + 255) / 256, 256, 0, s>>>(a.g.n, a.g.n_range, pd, pp, grad_dphi,
-                                                               grad_dpsi);
+    const int rows_per = (nr + kRedGroups - 1) / kRedGroups;
+    const int groups = (nr + rows_per - 1) / rows_per;
+    const dim3 grid1((n + 255) / 256, groups);
+    backward_reduce_rows_kernel<<<grid1, 256, 0, s>>>(n, nr, rows_per, pd, pp, gd, gp);
+    backward_reduce_groups_kernel<<<(n + 255) / 256, 256, 0, s>>>(n, groups, gd, gp, grad_dphi, grad_dpsi);
     e = hipGetLastError();
   }
   return e;
