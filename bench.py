@@ -109,16 +109,35 @@ def _cpu_model():
     return "unknown"
 
 
-def event_timer(torch):
-    def timed(fn, reps):
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        torch.cuda.synchronize()
-        e0.record()
-        for _ in range(reps):
+def graph_timer(torch):
+    """ms per call of fn, from HIP-graph replays: `inner` calls captured into one graph (no host
+    work per launch: a Python/ctypes call costs about as much as a short kernel), the graph
+    replayed `reps` times between two events recorded on the capture stream, which is the
+    stream the kernels run on.  `out()` returns the tensor fn writes: one replay must reproduce
+    the eager result bit for bit before anything is timed."""
+    def timed(fn, reps, inner=1, out=None):
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
             fn()
-        e1.record()
-        torch.cuda.synchronize()
-        return e0.elapsed_time(e1) / reps
+            torch.cuda.synchronize()
+            ref = out().clone() if out is not None else None
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g, stream=s):
+                for _ in range(inner):
+                    fn()
+            g.replay()
+            torch.cuda.synchronize()
+            if ref is not None and not torch.equal(out(), ref):
+                raise RuntimeError("graph replay differs from the eager result")
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(s)
+            for _ in range(reps):
+                g.replay()
+            e1.record(s)
+            torch.cuda.synchronize()
+        torch.cuda.current_stream().wait_stream(s)
+        return e0.elapsed_time(e1) / (reps * inner)
     return timed
 
 
@@ -135,13 +154,15 @@ def extras(torch, rs, synth, w, x, dev, rc, off, wts, timed, reps):
     f = lambda: rs.sparse_filter(g, grid, rc, off, wts, w.sparse.window, dphi=dphi, dpsi=dpsi, interp="linear",
                                  out=img)
     f()
-    out["corrected_forward_us"] = 1000 * timed(f, reps)
+    out["corrected_forward_us"] = 1000 * timed(f, max(3, reps // 5), inner=5, out=lambda: img)
     gimg = torch.randn((grid.n_range, grid.n_az), dtype=torch.complex64, device=dev)
     ws = torch.empty(rs.backward_workspace_bytes(g, grid, off, wts, w.sparse.window), dtype=torch.uint8, device=dev)
+    grads = (torch.empty(tuple(off.shape), dtype=torch.complex64, device=dev),
+             torch.empty(n, dtype=torch.float32, device=dev), torch.empty(n, dtype=torch.float32, device=dev))
     b = lambda: rs.sparse_filter_backward(g, grid, rc, off, wts, w.sparse.window, gimg, dphi, dpsi, "linear",
-                                          workspace=ws)
+                                          workspace=ws, out=grads)
     b()
-    out["adjoint_us"] = 1000 * timed(b, max(3, reps // 5))
+    out["adjoint_us"] = 1000 * timed(b, 3, inner=2, out=lambda: grads[0])
     print(f"[bench] corrected forward {out['corrected_forward_us']:.1f} us, adjoint {out['adjoint_us']:.1f} us",
           file=sys.stderr, flush=True)
 
@@ -169,7 +190,15 @@ def extras(torch, rs, synth, w, x, dev, rc, off, wts, timed, reps):
             plan.run()
     torch.cuda.current_stream().wait_stream(st)
     graph.replay()
-    ms = timed(graph.replay, max(3, reps // 5))
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    nrep = max(3, reps // 5)
+    e0.record()
+    for _ in range(nrep):
+        graph.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / nrep
     out["batch"] = {"rotations": len(rots), "pixels": px, "range_tiles": rc_tiles, "filter_tiles": sf_tiles,
                     "shape_pixels_per_lane_waves": list(shape), "ms_per_batch": ms,
                     "pixels_per_s": px / (ms * 1e-3), "graph_replay": True}
@@ -194,10 +223,10 @@ def extras(torch, rs, synth, w, x, dev, rc, off, wts, timed, reps):
         prc = rs.range_compress(pg, praw, pwin, px_.l_lo, px_.l_count, halo=pw.sparse.window // 2, dtype=dt,
                                 scale=scale)
         t_rc = timed(lambda: rs.range_compress(pg, praw, pwin, px_.l_lo, px_.l_count, dtype=dt, scale=scale,
-                                               out=prc), reps)
+                                               out=prc), max(3, reps // 10), inner=10, out=lambda: prc.data)
         ff = lambda: rs.sparse_filter(pg, pgrid, prc, poff, wt, pw.sparse.window, out=pimg)
         ff()
-        t_sf = timed(ff, reps)
+        t_sf = timed(ff, max(3, reps // 10), inner=10, out=lambda: pimg)
         prec[dt] = {"range_compress_us": 1000 * t_rc, "sparse_filter_us": 1000 * t_sf,
                     "pixels_per_s": pgrid.n_range * pgrid.n_az / ((t_rc + t_sf) * 1e-3)}
         print(f"[bench] precision {dt}: rc {1000 * t_rc:.1f} us, sf {1000 * t_sf:.1f} us", file=sys.stderr,
@@ -239,29 +268,25 @@ def main():
         rs.range_compress(g, raw, win, x.l_lo, x.l_count, out=rc)
         rs.sparse_filter(g, grid, rc, off, wts, w.sparse.window, out=img, tile=tile)
 
-    def timed(fn, reps):
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        torch.cuda.synchronize()
-        e0.record()
-        for _ in range(reps):
-            fn()
-        e1.record()
-        torch.cuda.synchronize()
-        return e0.elapsed_time(e1) / reps
-
+    timed = graph_timer(torch)
     for _ in range(a.warmup):
         step()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    ms_step = timed(step, a.steps)
+    # exactly `steps` steps: all of them captured in one graph, replayed once
+    ms_step = timed(step, 1, inner=a.steps, out=lambda: img)
     wall = time.perf_counter() - t0
     print(f"[bench] {a.steps} steps: {ms_step:.4f} ms/step (wall {wall:.3f} s)", file=sys.stderr, flush=True)
 
-    # per-kernel averages on the same stream
-    ms_rc = timed(lambda: rs.range_compress(g, raw, win, x.l_lo, x.l_count, out=rc), a.steps)
-    ms_sf = timed(lambda: rs.sparse_filter(g, grid, rc, off, wts, w.sparse.window, out=img, tile=tile), a.steps)
+    # per-kernel averages: 20 launches per graph
+    kreps = max(3, a.steps // 10)
+    ms_rc = timed(lambda: rs.range_compress(g, raw, win, x.l_lo, x.l_count, out=rc), kreps, inner=20,
+                  out=lambda: rc.data)
+    ms_sf = timed(lambda: rs.sparse_filter(g, grid, rc, off, wts, w.sparse.window, out=img, tile=tile), kreps,
+                  inner=20, out=lambda: img)
     rs.bp_full(g, grid, rc, angles=ang, out=bimg, workspace=bws)
-    ms_bp = timed(lambda: rs.bp_full(g, grid, rc, angles=ang, out=bimg, workspace=bws), a.bpa_reps)
+    ms_bp = timed(lambda: rs.bp_full(g, grid, rc, angles=ang, out=bimg, workspace=bws), a.bpa_reps,
+                  out=lambda: bimg)
     print(f"[bench] range_compress {ms_rc:.4f} ms, sparse_filter {ms_sf:.4f} ms, bp_full {ms_bp:.3f} ms",
           file=sys.stderr, flush=True)
     if a.copy_calibration:
@@ -282,7 +307,7 @@ def main():
     achieved_tf = sf_flops / (ms_sf * 1e-3) / 1e12
     roofline = {"bound": "alu", "achieved": round(achieved_tf, 3), "peak": PEAK_FP32_VALU_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(achieved_tf / PEAK_FP32_VALU_TFLOPS, 4),
-                "traffic": traffic, "kernel": "sparse_plain_kernel",
+                "traffic": traffic, "kernel": "sparse_lds_kernel (default launch shape)",
                 "algorithmic_bytes": sf_bytes, "algorithmic_flops": sf_flops}
     out = {
         "metric": "polar image pixels/s: sparse-array filter vs full BPA on 1 MI355X; HBM GB/s",
@@ -310,6 +335,8 @@ def main():
                      "range_compress": rc_bytes / (ms_rc * 1e-3) / 1e9, "peak": PEAK_HBM_GBPS},
         "roofline": roofline,
         "kernel_source_digest": digest,
+        "timing": "HIP-graph replays, events on the launch stream: the timed steps captured in one graph "
+                  "replayed once; 20 launches per graph for the per-kernel figures",
     }
     if not a.no_extras:
         out["rows"] = extras(torch, rs, synth, w, x, dev, rc, off, wts, timed, a.steps)

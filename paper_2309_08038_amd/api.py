@@ -155,15 +155,24 @@ def backward_workspace_bytes(geom, grid, offsets, weights, window) -> int:
 
 def sparse_filter_backward(geom, grid, rc: RangeCompressed, offsets, weights, window, grad_image,
                            dphi=None, dpsi=None, interp: str = "linear", need_w=True, need_phi=True, need_psi=True,
-                           workspace: torch.Tensor | None = None):
+                           workspace: torch.Tensor | None = None, out=None):
     """Adjoint of sparse_filter -> (grad_weights c64 [n_range, K] | None, grad_dphi f32 [N] | None,
-    grad_dpsi f32 [N] | None) for grad_image = dL/dRe(I) + j dL/dIm(I)."""
+    grad_dpsi f32 [N] | None) for grad_image = dL/dRe(I) + j dL/dIm(I).  `out` may supply the three
+    output tensors (entries None for gradients not wanted)."""
     s = _set(offsets, weights, window)
     _need_gpu(grad_image, dphi, dpsi)
     dev = grad_image.device
-    gw = torch.empty(offsets.shape, dtype=torch.complex64, device=dev) if need_w else None
-    gd = torch.empty(geom.n_pulses, dtype=torch.float32, device=dev) if need_phi else None
-    gp = torch.empty(geom.n_pulses, dtype=torch.float32, device=dev) if need_psi else None
+    if out is not None:
+        gw, gd, gp = out
+        for t, shape, dt in ((gw, tuple(offsets.shape), torch.complex64), (gd, (geom.n_pulses,), torch.float32),
+                             (gp, (geom.n_pulses,), torch.float32)):
+            if t is not None and (tuple(t.shape) != shape or t.dtype != dt or not t.is_contiguous()):
+                raise TypeError(f"output gradient must be a contiguous {dt} tensor of shape {shape}")
+        _need_gpu(gw, gd, gp)
+    else:
+        gw = torch.empty(offsets.shape, dtype=torch.complex64, device=dev) if need_w else None
+        gd = torch.empty(geom.n_pulses, dtype=torch.float32, device=dev) if need_phi else None
+        gp = torch.empty(geom.n_pulses, dtype=torch.float32, device=dev) if need_psi else None
     nbytes = backward_workspace_bytes(geom, grid, offsets, weights, window)
     if workspace is None or workspace.numel() * workspace.element_size() < nbytes:
         workspace = torch.empty(nbytes, dtype=torch.uint8, device=dev)
