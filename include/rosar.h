@@ -206,10 +206,11 @@ rosar_status rosar_sparse_filter_backward(const rosar_geometry* geom, const rosa
                                           rosar_stream stream);
 
 /* ---------------------------------------------------------------- batched rotations
- * Many independent rotations of uneven sizes imaged by one persistent range-compression
- * launch and one persistent sparse-filter launch.  Workgroups pull tiles from a device work
- * counter reset by the plan's own kernel at the start of each run, so a run can be captured
- * in a HIP graph and replayed.  NEAREST, uncorrected, C64 only. */
+ * Many independent rotations of uneven sizes imaged by one range-compression launch per FFT
+ * length present (one workgroup per 8-pulse tile) and one persistent sparse-filter launch
+ * whose workgroups pull tiles from a device work counter.  The counter is reset by the plan's
+ * own kernel at the start of each run, so a run can be captured in a HIP graph and replayed.
+ * NEAREST, uncorrected, C64 only. */
 typedef struct rosar_rotation_desc {
   rosar_geometry geom;
   rosar_polar_grid grid;
@@ -227,13 +228,14 @@ typedef struct rosar_batch_plan rosar_batch_plan;
 /* Validates every descriptor (host), uploads a device descriptor table and tile prefix sums
  * (the plan owns that device memory until rosar_batch_plan_destroy).  tile: sparse-filter
  * launch shape for all rotations (pixels_per_lane x waves in {1x4, 2x4, 4x4, 8x4, 2x2, 4x2,
- * 8x2, 4x8}; NULL = 4x4).  Every descriptor obeys the rules of rosar_range_compress and
+ * 8x2, 4x8}; NULL = 4x8).  Every descriptor obeys the rules of rosar_range_compress and
  * rosar_sparse_filter (C64 data and weights); the halo should cover half the window (staging
  * falls back to element copies otherwise).  y_t is written by the run (range compression) and
  * read by its sparse filter; images are overwritten.  Errors name the offending rotation. */
 rosar_status rosar_batch_plan_create(const rosar_rotation_desc* descs, int32_t n,
                                      const rosar_tile* tile, rosar_batch_plan** out);
-/* Enqueues counter reset + persistent range compression + persistent sparse filter. */
+/* Enqueues counter reset + range compression (one launch per FFT length) + persistent sparse
+ * filter. */
 rosar_status rosar_batch_run(rosar_batch_plan* plan, rosar_stream stream);
 /* Total pixels and tiles of the plan (host values). */
 rosar_status rosar_batch_plan_info(const rosar_batch_plan* plan, int64_t* pixels,
