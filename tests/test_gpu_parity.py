@@ -185,6 +185,30 @@ def test_sparse_filter_corrected(interp, which):
     assert rel_l2(img, ref) <= TOL
 
 
+@pytest.mark.parametrize("interp", ["nearest", "linear"])
+@pytest.mark.parametrize("halo_half", [False, True])
+def test_sparse_filter_corrected_wide_window(interp, halo_half):
+    """A window too wide for the corrected kernel's LDS pulse table (tile + W > 4096 columns):
+    the per-pulse angle/phase terms come from global memory for every pair.  With halo 0 the
+    pulse columns wrap modulo N explicitly."""
+    rs = need_gpu()
+    n, win = 3200, 3200
+    w = custom_workload("wide_window", 71, n, 64, 6, 0.6, 1.5, 16, win)
+    x = synth.make_inputs(w)
+    rng = np.random.default_rng(23)
+    dphi = rng.normal(0, 2e-3, n).astype(np.float32)
+    dpsi = rng.normal(0, 0.3, n).astype(np.float32)
+    log(f"sparse_filter corrected wide window {interp} halo_half={halo_half}")
+    yb = oracle.range_compress(x.raw, x.window, 64)[:, x.l_lo:x.l_lo + x.l_count]
+    ref = oracle.sparse_filter(yb, x.l_lo, w.geometry, w.grid, x.offsets, x.weights, dphi=dphi.astype(np.float64),
+                               dpsi=dpsi.astype(np.float64), interp=interp)
+    rc = rs.range_compress(w.geometry, to_dev(x.raw), to_dev(x.window), x.l_lo, x.l_count,
+                           halo=win // 2 if halo_half else 0)
+    img = rs.sparse_filter(w.geometry, w.grid, rc, to_dev(x.offsets), to_dev(x.weights.astype(np.complex64)),
+                           win, dphi=to_dev(dphi), dpsi=to_dev(dpsi), interp=interp).cpu().numpy()
+    assert rel_l2(img, ref) <= TOL
+
+
 def test_sparse_filter_rotation_invariance_bitwise():
     rs = need_gpu()
     w, x = inputs("small")
@@ -246,6 +270,40 @@ def test_bp_full_rotation_sampled():
     azs[:4] = [0, w.grid.n_az - 1, 0, w.grid.n_az - 1]
     ref = oracle.bp_full_at(oracle_band("rotation"), x.l_lo, w.geometry, w.grid, rows, azs, pulse_angles=x.angles)
     assert rel_l2(img[rows, azs], ref) <= TOL
+
+
+@pytest.mark.parametrize("interp", ["nearest", "linear"])
+def test_bp_full_narrow_band(interp):
+    """Bins outside a narrow stored band read zero (the clamped row lies past the band, where the
+    buffer range check returns zero), as in the oracle; with jittered angles."""
+    rs = need_gpu()
+    w, x = inputs("small")
+    y = oracle.range_compress(x.raw, x.window, w.geometry.n_fft)
+    lo, cnt = 40, 30
+    rng = np.random.default_rng(5)
+    ang = w.geometry.phi0_rad + 2 * np.pi * np.arange(w.geometry.n_pulses) / w.geometry.n_pulses
+    ang = ang + rng.normal(0, np.deg2rad(0.3), ang.size)
+    log(f"bp_full narrow band {interp}")
+    ref = oracle.bp_full(y[:, lo:lo + cnt], lo, w.geometry, w.grid, pulse_angles=ang, interp=interp)
+    rc = rs.range_compress(w.geometry, to_dev(x.raw), to_dev(x.window), lo, cnt, halo=0)
+    img = rs.bp_full(w.geometry, w.grid, rc, angles=to_dev(ang), interp=interp).cpu().numpy()
+    assert rel_l2(img, ref) <= TOL
+    assert np.count_nonzero(img) < img.size
+
+
+def test_bp_full_rows_inside_radius():
+    """Rows at or inside the rotation radius see no pulse (R cos D - r <= 0): exactly zero."""
+    rs = need_gpu()
+    w = custom_workload("inside_radius", 72, 120, 64, 24, 0.07, 1.22, 8, 16)   # no row within 2 cm of r
+    x = synth.make_inputs(w)
+    yb = oracle.range_compress(x.raw, x.window, 64)[:, x.l_lo:x.l_lo + x.l_count]
+    log("bp_full rows inside the radius")
+    ref = oracle.bp_full(yb, x.l_lo, w.geometry, w.grid)
+    rc = rs.range_compress(w.geometry, to_dev(x.raw), to_dev(x.window), x.l_lo, x.l_count, halo=8)
+    img = rs.bp_full(w.geometry, w.grid, rc).cpu().numpy()
+    assert rel_l2(img, ref) <= TOL
+    inside = w.grid.r0_m + np.arange(w.grid.n_range) * w.grid.dr_m <= w.geometry.radius_m
+    assert inside.any() and not np.any(img[inside])
 
 
 def test_bpa_equals_dense_sparse_filter_gpu():
