@@ -121,8 +121,9 @@ typedef struct rosar_sparse_set {
 /* Launch shape of the sparse filter (0 = let the library choose).  The project's autotuner
  * (rosar_autotune_sparse_filter) searches these. */
 typedef struct rosar_tile {
-  int32_t variant;        /* 0 auto; 1 direct cached loads; 2 LDS-staged window; 3 LDS-staged window read as pixel pairs (2 and 3 fall back to 1 when the window does not fit in LDS) */
-  int32_t pixels_per_lane;/* 1, 2, 4 or 8 */
+  int32_t variant;        /* 0 auto; 1 direct cached loads; 2 LDS-staged window (falls back
+                             to 1 when one staged row does not fit the LDS budget) */
+  int32_t pixels_per_lane;/* 1, 2, 4 or 8 (8 x 8 waves is not supported) */
   int32_t waves;          /* waves per workgroup: 1, 2, 4 or 8 */
   int32_t reserved;
 } rosar_tile;

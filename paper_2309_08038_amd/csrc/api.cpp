@@ -268,7 +268,7 @@ rosar_status rosar_sparse_filter_tiled(const rosar_geometry* geom, const rosar_p
                                        void* image, const rosar_tile* tile, rosar_stream stream) {
   rosar::SparseArgs a{};
   ROSAR_TRY(sparse_common(geom, grid, rc, set, dphi, dpsi, interp, image, &a));
-  rosar::Tile t = rosar::default_tile(geom->n_pulses, set->k, rc->dtype);
+  rosar::Tile t = rosar::default_tile(geom->n_pulses, rc->dtype);
   if (tile && (tile->pixels_per_lane || tile->waves || tile->variant)) {
     t = rosar::Tile{tile->variant ? tile->variant : 1, tile->pixels_per_lane ? tile->pixels_per_lane : t.ppl,
                     tile->waves ? tile->waves : t.waves};

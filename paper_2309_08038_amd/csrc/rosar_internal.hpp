@@ -74,7 +74,7 @@ rosar_status validate_rotation(const rosar_rotation_desc& d, int index);
 Geo geo_of(const rosar_geometry* g, const rosar_polar_grid* p);
 
 // Tile chosen when the caller leaves it to the library.
-Tile default_tile(int32_t n, int32_t k, int32_t y_dtype);
+Tile default_tile(int32_t n, int32_t y_dtype);
 bool tile_supported(const Tile& t);
 
 }  // namespace rosar

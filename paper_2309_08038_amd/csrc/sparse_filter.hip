@@ -2,13 +2,17 @@
 // azimuth a) is the conjugate-weighted sum of K range-compressed samples, one per selected
 // pulse a + o_t, each read at the FFT bin of that pulse's slant range (eq. 40).
 //
-// Plain path (no angle/phase correction).  Under the rotation symmetry the bin and weight of a
-// tap depend only on (row, offset), so a whole wavefront shares them: the tap table is built
-// once per wave in float64 (lane t owns tap t), then each tap's row offset is broadcast with
-// v_readlane into an SGPR and its weight comes through a scalar load.  Every lane owns P
-// pixels spaced one wavefront apart, so a tap costs P coalesced loads from the (L2-resident)
-// range-compressed rows and 4P FMAs, with no per-lane address arithmetic.  LINEAR
-// interpolation is two sub-taps with real factors (1-f, f) folded into the weight.
+// Plain path (no angle/phase correction), two launch variants:
+//  - LDS-staged (variant 2, the default; sparse::lds_tile): a workgroup stages the bin rows
+//    its row's taps can touch into LDS at entry and reads every sample from there.
+//  - Direct (variant 1, also the fallback when a window does not fit the LDS budget): under
+//    the rotation symmetry the bin and weight of a tap depend only on (row, offset), so a
+//    whole wavefront shares them: the tap table is built once per wave in float64 (lane t
+//    owns tap t), then each tap's row offset is broadcast with v_readlane into an SGPR and its
+//    weight comes through a scalar load.  Every lane owns P pixels spaced one wavefront apart,
+//    so a tap costs P coalesced buffer loads from the (L2-resident) range-compressed rows and
+//    4P FMAs, with no per-lane address arithmetic.
+// LINEAR interpolation is two sub-taps with real factors (1-f, f) folded into the weight.
 //
 // Corrected path (per-pulse angle error dphi and phase error psi): see
 // sparse_corrected_kernel.
@@ -426,8 +430,7 @@ hipError_t launch_corr_dt(const SparseArgs& a, hipStream_t s) {
 
 }  // namespace
 
-Tile default_tile(int32_t n, int32_t k, int32_t y_dtype) {
-  (void)k;
+Tile default_tile(int32_t n, int32_t y_dtype) {
   // LDS-staged window of 2048-pixel tiles: complex64 samples four pixels per lane over eight
   // waves, 16-bit samples eight pixels per lane over four waves (the faster shape of each on
   // the 3600- and 7200-pulse workloads); short rotations one pixel per lane
