@@ -1,14 +1,14 @@
 // Windowed range FFT of a group of pulses (Sec. III-D, eq. 38), shared by the single-rotation
-// range-compression kernel and the persistent batched kernel.
+// range-compression kernel and the batched kernel.
 //
 // One wavefront transforms one pulse at a time with a Stockham autosort FFT (radix 8, then 4
 // or 2 for the remaining factor) in LDS; twiddles come from an LDS table of
-// exp(-j 2 pi t / L).  The first pass reads raw samples straight from HBM with the window and
-// zero padding applied.  A workgroup of NW waves handles NW*PPW pulses, then writes the
-// transposed band with NW*PPW consecutive pulses per row segment, plus the circular halo
-// copies of the first/last `halo` pulses.  Each wave owns its pulses' LDS rows, so the passes
-// order their LDS accesses with wave-level fences; the workgroup synchronises only around the
-// twiddle table and before the transposed store.
+// exp(-j 2 pi t / L).  The first pass reads the raw samples straight from HBM (zero padding
+// past M) and applies the window from LDS.  A workgroup of NW waves handles NW*PPW pulses, then
+// writes the transposed band with NW*PPW consecutive pulses per row segment, plus the circular
+// halo copies of the first/last `halo` pulses.  Each wave owns its pulses' LDS rows, so the
+// passes order their LDS accesses with wave-level fences; the workgroup synchronises only
+// around the twiddle/window tables and before the transposed store.
 #pragma once
 
 #include "rosar_device.hpp"
@@ -85,47 +85,77 @@ __device__ __forceinline__ void dft(float2 (&v)[R]) {
   }
 }
 
-// One Stockham pass of radix R after `NS` points have been combined; in place on each pulse
-// row of `buf` (read phase, barrier, write phase, barrier).  The first pass (NS == 1) loads
-// the windowed, zero-padded raw samples from global memory instead of LDS.
+constexpr int pass_bpl(int l, int pass) { return (l / pass_radix(l, pass) + kWave - 1) / kWave; }
+
+template <int L, int PASS>
+struct PassShape {
+  static constexpr int R = pass_radix(L, PASS);
+  static constexpr int NS = pass_ns(L, PASS);
+  static constexpr int NB = L / R;                          // butterflies per pulse
+  static constexpr int BPL = (NB + kWave - 1) / kWave;      // butterflies per lane
+};
+
+// Operands of one Stockham pass of radix R (after NS points have been combined) for the PPW
+// pulses of a wave: from the pulse rows of `buf` in LDS, or for the first pass the raw samples
+// from global memory (zero padding past M, zero for pulses past N; the window is applied
+// separately, see apply_window).
 template <int L, int PPW, int PASS>
-__device__ __forceinline__ void fft_pass(float2* buf, const float2* tw, int wave, int lane,
-                                         const RcArgs& a, int n0) {
-  constexpr int R = pass_radix(L, PASS);
-  constexpr int NS = pass_ns(L, PASS);
-  constexpr int NB = L / R;
-  constexpr int BPL = (NB + kWave - 1) / kWave;
+__device__ __forceinline__ void pass_load(float2 (&v)[PPW][pass_bpl(L, PASS)][pass_radix(L, PASS)],
+                                          const float2* buf, int wave, int lane, const RcArgs& a, int n0) {
+  using S = PassShape<L, PASS>;
   constexpr int LP = L + 1;
-  float2 v[PPW][BPL][R];
 #pragma unroll
   for (int p = 0; p < PPW; ++p) {
     const int wp = wave * PPW + p;
     const int n = n0 + wp;
 #pragma unroll
-    for (int b = 0; b < BPL; ++b) {
+    for (int b = 0; b < S::BPL; ++b) {
       const int j = lane + kWave * b;
 #pragma unroll
-      for (int r = 0; r < R; ++r) {
-        const int idx = j + r * NB;
+      for (int r = 0; r < S::R; ++r) {
+        const int idx = j + r * S::NB;
         float2 x = make_float2(0.f, 0.f);
         if constexpr (PASS == 0) {
-          if (j < NB && n < a.n && idx < a.m) {
-            x = a.raw[(int64_t)n * a.m + idx];
-            if (a.window) { float h = a.window[idx]; x.x *= h; x.y *= h; }
-          }
+          if (j < S::NB && n < a.n && idx < a.m) x = a.raw[(int64_t)n * a.m + idx];
         } else {
-          if (j < NB) x = buf[wp * LP + idx];
+          if (j < S::NB) x = buf[wp * LP + idx];
         }
         v[p][b][r] = x;
       }
     }
   }
-  wave_sync();
+}
+
+// First-pass operands times the window staged in LDS (samples past M are zero already).
+template <int L, int PPW>
+__device__ __forceinline__ void apply_window(float2 (&v)[PPW][pass_bpl(L, 0)][pass_radix(L, 0)],
+                                             const float* win, int lane, int m) {
+  using S = PassShape<L, 0>;
+#pragma unroll
+  for (int p = 0; p < PPW; ++p)
+#pragma unroll
+    for (int b = 0; b < S::BPL; ++b)
+#pragma unroll
+      for (int r = 0; r < S::R; ++r) {
+        const int idx = lane + kWave * b + r * S::NB;
+        const float h = idx < m ? win[idx] : 0.f;
+        v[p][b][r].x *= h;
+        v[p][b][r].y *= h;
+      }
+}
+
+// Twiddles, radix-R DFT and the Stockham write of one pass (in place on the pulse rows).
+template <int L, int PPW, int PASS>
+__device__ __forceinline__ void pass_compute(float2 (&v)[PPW][pass_bpl(L, PASS)][pass_radix(L, PASS)],
+                                             float2* buf, const float2* tw, int wave, int lane) {
+  using S = PassShape<L, PASS>;
+  constexpr int R = S::R, NS = S::NS, NB = S::NB;
+  constexpr int LP = L + 1;
 #pragma unroll
   for (int p = 0; p < PPW; ++p) {
     const int wp = wave * PPW + p;
 #pragma unroll
-    for (int b = 0; b < BPL; ++b) {
+    for (int b = 0; b < S::BPL; ++b) {
       const int j = lane + kWave * b;
       if (j < NB) {
         const int k = j & (NS - 1);
@@ -143,22 +173,29 @@ __device__ __forceinline__ void fft_pass(float2* buf, const float2* tw, int wave
   wave_sync();
 }
 
+// Passes PASS.. of the FFT, each reading the previous pass's rows from LDS.
 template <int L, int PPW, int PASS>
-__device__ __forceinline__ void fft_all(float2* buf, const float2* tw, int wave, int lane,
-                                        const RcArgs& a, int n0) {
+__device__ __forceinline__ void fft_rest(float2* buf, const float2* tw, int wave, int lane, const RcArgs& a) {
   if constexpr (PASS < pass_count(L)) {
-    fft_pass<L, PPW, PASS>(buf, tw, wave, lane, a, n0);
-    fft_all<L, PPW, PASS + 1>(buf, tw, wave, lane, a, n0);
+    using S = PassShape<L, PASS>;
+    float2 v[PPW][S::BPL][S::R];
+    pass_load<L, PPW, PASS>(v, buf, wave, lane, a, 0);
+    wave_sync();
+    pass_compute<L, PPW, PASS>(v, buf, tw, wave, lane);
+    fft_rest<L, PPW, PASS + 1>(buf, tw, wave, lane, a);
   }
 }
 
 
-// LDS float2 needed by rc_block<L, PPW, NW>: twiddle table + NW*PPW padded pulse rows.
-constexpr int rc_lds_elems(int l, int ppw, int nw) { return l + nw * ppw * (l + 1); }
+// LDS float2 needed by rc_block<L, PPW, NW>: twiddle table, NW*PPW padded pulse rows and the
+// window (L floats).
+constexpr int rc_lds_elems(int l, int ppw, int nw) { return l + nw * ppw * (l + 1) + l / 2; }
 
 // Range-compress pulses [n0, n0 + NW*PPW) of one rotation: FFT each (wave w owns pulses
 // n0 + w*PPW ...), then store the band transposed with NW*PPW consecutive pulses per row
-// segment.  `lds` holds rc_lds_elems(L, PPW, NW) float2.  All threads of the workgroup call it.
+// segment.  The first pass's raw samples are requested before the workgroup builds the
+// twiddle table and stages the window, so their latency overlaps that work.  `lds` holds
+// rc_lds_elems(L, PPW, NW) float2.  All threads of the workgroup call it.
 template <int L, int PPW, int DT, int NW>
 __device__ __forceinline__ void rc_block(const RcArgs& a, int n0, float2* lds) {
   constexpr int PW = NW * PPW;
@@ -166,14 +203,21 @@ __device__ __forceinline__ void rc_block(const RcArgs& a, int n0, float2* lds) {
   constexpr int NT = NW * kWave;
   float2* tw = lds;
   float2* buf = lds + L;
+  float* win = reinterpret_cast<float*>(lds + L + PW * LP);
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
+  using S0 = PassShape<L, 0>;
+  float2 v[PPW][S0::BPL][S0::R];
+  pass_load<L, PPW, 0>(v, buf, wave, lane, a, n0);
   for (int t = tid; t < L; t += NT) {
     float s, c;
     sincospif(-2.0f * (float)t / (float)L, &s, &c);
     tw[t] = make_float2(c, s);
+    win[t] = t < a.m ? (a.window ? a.window[t] : 1.f) : 0.f;
   }
   __syncthreads();
-  fft_all<L, PPW, 0>(buf, tw, wave, lane, a, n0);
+  apply_window<L, PPW>(v, win, lane, a.m);
+  pass_compute<L, PPW, 0>(v, buf, tw, wave, lane);
+  fft_rest<L, PPW, 1>(buf, tw, wave, lane, a);
   __syncthreads();
 
   // transposed store of the band: PW consecutive pulses form one contiguous row segment
@@ -183,13 +227,13 @@ __device__ __forceinline__ void rc_block(const RcArgs& a, int n0, float2* lds) {
     const int lr = i / PW;
     const int n = n0 + pp;
     if (n >= a.n) continue;
-    float2 v = buf[pp * LP + a.l_lo + lr];
-    v.x *= a.scale;
-    v.y *= a.scale;
+    float2 v2 = buf[pp * LP + a.l_lo + lr];
+    v2.x *= a.scale;
+    v2.y *= a.scale;
     const int64_t row = (int64_t)lr * a.ld;
-    store_c<DT>(a.out, row + n + a.halo, v);
-    if (n < a.halo) store_c<DT>(a.out, row + n + a.halo + a.n, v);
-    if (n >= a.n - a.halo) store_c<DT>(a.out, row + n + a.halo - a.n, v);
+    store_c<DT>(a.out, row + n + a.halo, v2);
+    if (n < a.halo) store_c<DT>(a.out, row + n + a.halo + a.n, v2);
+    if (n >= a.n - a.halo) store_c<DT>(a.out, row + n + a.halo - a.n, v2);
   }
 }
 
