@@ -27,7 +27,6 @@ namespace {
 constexpr int kBwThreads = 256;
 constexpr int kBwWaves = kBwThreads / kWave;
 constexpr int kBwPpt = 8;      // pulses per thread per pass
-constexpr int kBwMaxK = 1024;
 constexpr int kBwChunk = kBwThreads;   // taps per LDS table chunk
 constexpr int kRedGroups = 32;         // row groups of the first reduction stage
 
@@ -59,7 +58,7 @@ __global__ __launch_bounds__(kBwThreads) void backward_row_kernel(
     float2* __restrict__ grad_w, float* __restrict__ part_d, float* __restrict__ part_p) {
   constexpr int ES = Elem<DT>::bytes;
   constexpr float kInv2Pi = 0.15915494309189533577f;
-  __shared__ float2 s_gw[kBwWaves][kBwMaxK];
+  extern __shared__ float2 s_gw[];   // [kBwWaves][k]: per-wave grad_w partials
   __shared__ BwTap s_tap[kBwChunk];
   const int lane = threadIdx.x & (kWave - 1);
   const int wave = threadIdx.x / kWave;
@@ -67,7 +66,7 @@ __global__ __launch_bounds__(kBwThreads) void backward_row_kernel(
   const int n = g.n;
   const int half_w = window / 2;
   for (int t = threadIdx.x; t < k; t += kBwThreads)
-    for (int w = 0; w < kBwWaves; ++w) s_gw[w][t] = make_float2(0.f, 0.f);
+    for (int w = 0; w < kBwWaves; ++w) s_gw[w * k + t] = make_float2(0.f, 0.f);
 
   const double rr = g.r0 + row * g.dr;
   const double c1 = rr * rr + g.radius * g.radius;
@@ -180,8 +179,8 @@ __global__ __launch_bounds__(kBwThreads) void backward_row_kernel(
         }
         gw = wave_sum(gw);
         if (lane == 0) {
-          float2 cur = s_gw[wave][c0 + tt];
-          s_gw[wave][c0 + tt] = make_float2(cur.x + gw.x, cur.y + gw.y);
+          float2 cur = s_gw[wave * k + c0 + tt];
+          s_gw[wave * k + c0 + tt] = make_float2(cur.x + gw.x, cur.y + gw.y);
         }
       }
     }
@@ -197,8 +196,8 @@ __global__ __launch_bounds__(kBwThreads) void backward_row_kernel(
   __syncthreads();
   if (grad_w) {
     for (int t = threadIdx.x; t < k; t += kBwThreads) {
-      float2 sum = s_gw[0][t];
-      for (int w = 1; w < kBwWaves; ++w) sum = make_float2(sum.x + s_gw[w][t].x, sum.y + s_gw[w][t].y);
+      float2 sum = s_gw[t];
+      for (int w = 1; w < kBwWaves; ++w) sum = make_float2(sum.x + s_gw[w * k + t].x, sum.y + s_gw[w * k + t].y);
       grad_w[wrow + t] = sum;
     }
   }
@@ -247,11 +246,12 @@ hipError_t launch_dt(const SparseArgs& a, const float2* gimg, float2* grad_w, fl
   const int nblocks = a.g.n_range;
   const char* yd = reinterpret_cast<const char*>(a.y.data);
   const float2* w = reinterpret_cast<const float2*>(a.weights);
+  const size_t lds = (size_t)kBwWaves * a.k * sizeof(float2);
   if (a.interp == ROSAR_LINEAR)
-    backward_row_kernel<DT, ROSAR_LINEAR><<<nblocks, kBwThreads, 0, s>>>(
+    backward_row_kernel<DT, ROSAR_LINEAR><<<nblocks, kBwThreads, lds, s>>>(
         a.g, a.y, a.k, a.window, nblocks, a.offsets, w, a.dphi, a.dpsi, gimg, yd, grad_w, pd, pp);
   else
-    backward_row_kernel<DT, ROSAR_NEAREST><<<nblocks, kBwThreads, 0, s>>>(
+    backward_row_kernel<DT, ROSAR_NEAREST><<<nblocks, kBwThreads, lds, s>>>(
         a.g, a.y, a.k, a.window, nblocks, a.offsets, w, a.dphi, a.dpsi, gimg, yd, grad_w, pd, pp);
   return hipGetLastError();
 }
