@@ -1,6 +1,6 @@
 // Batched rotations: many independent rotations of uneven pulse, sample and range-row counts
 // imaged by one range-compression launch per FFT length present and one persistent
-// sparse-filter launch.
+// sparse-filter launch per occupancy class.
 //
 // The plan uploads one descriptor per rotation (derived float64 geometry, band, pointers,
 // LDS layout) and the prefix sums of their tile counts.  A tile index is mapped to its rotation
@@ -11,10 +11,13 @@
 // Range compression: the rotations are grouped by FFT length; each group is one launch with
 // one workgroup per 8-pulse tile, the exact LDS of its length and XCD-aware tile order (the
 // hardware dispatcher balanced these short tiles better than a work queue did).  Sparse filter:
-// a persistent launch whose workgroups take tile indices from a device counter, reset by the
-// plan's own kernel at the start of every run, so that the launches can be captured in a HIP
-// graph and replayed.  Every workgroup leaves its loop once the counter passes the tile total.
+// the rotations are grouped by the occupancy their LDS layout allows, and each group is a
+// persistent launch sized for its widest window, whose workgroups take tile indices from the
+// group's device counter.  The counters are reset by the plan's own kernel at the start of
+// every run, so that the launches can be captured in a HIP graph and replayed.  Every
+// workgroup leaves its loop once its counter passes the group's tile total.
 #include <algorithm>
+#include <functional>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -29,6 +32,7 @@ constexpr int kBatchP = 4;       // default sparse-filter shape of a batch: 4 pi
 constexpr int kBatchWaves = 8;   // 8 waves (2048-pixel tiles)
 constexpr int kBatchRcWaves = 8; // range-compression workgroup: one pulse per wave, 8 waves
 constexpr int kRcLengths = 6;    // FFT lengths 64 .. 2048
+constexpr int kSfClasses = 8;    // sparse-filter launches: one per occupancy class
 
 // Range compression of one rotation inside its FFT-length group.
 struct BatchRc {
@@ -62,8 +66,8 @@ __device__ __forceinline__ int find_entry(const D* d, int nd, int t, int32_t D::
   return lo;
 }
 
-__global__ void batch_reset_kernel(int* counters) {
-  if (threadIdx.x < 2) counters[threadIdx.x] = 0;
+__global__ void batch_reset_kernel(int* counters, int n) {
+  if ((int)threadIdx.x < n) counters[threadIdx.x] = 0;
 }
 
 template <int L>
@@ -121,31 +125,73 @@ struct rosar_batch_plan {
   int rc_first[rosar::kRcLengths] = {};           // first entry of each length's group in d_rc
   int rc_count[rosar::kRcLengths] = {};           // rotations in the group
   int rc_tiles[rosar::kRcLengths] = {};           // tiles (8-pulse groups) of the group
-  int* d_counters = nullptr;
+  int* d_counters = nullptr;                      // one work counter per sparse-filter class
   int rc_total = 0, sf_total = 0;
   int64_t pixels = 0;
-  size_t sf_lds = 0;
-  int sf_grid = 0;
+  // sparse filter: rotations grouped by how many workgroups of their LDS layout fit on a CU;
+  // class c is d_rots[sf_first[c], sf_first[c] + sf_count[c]), one persistent launch each
+  int sf_classes = 0;
+  int sf_first[rosar::kSfClasses] = {}, sf_count[rosar::kSfClasses] = {};
+  int sf_tiles[rosar::kSfClasses] = {}, sf_grid[rosar::kSfClasses] = {};
+  size_t sf_lds[rosar::kSfClasses] = {};
 };
 
 namespace rosar {
 
 namespace {
 
+// Groups the rotations by the occupancy their LDS layout allows (rotations with small windows
+// should not run at the occupancy of the widest one), reorders hv class by class, numbers the
+// tiles within each class and sizes each class's persistent grid.
 template <int P, int NW>
-rosar_status plan_shape(const std::vector<BatchRot>& hv, rosar_batch_plan* pl, int cus) {
-  (void)hv;
-  int occ = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, SfKernel<P, NW>::fn(), kWave * NW, pl->sf_lds) !=
-      hipSuccess || occ < 1)
-    return bfail(ROSAR_ERR_HIP, "occupancy query for the batched sparse-filter kernel failed");
-  pl->sf_grid = cus * occ;
+rosar_status plan_shape(std::vector<BatchRot>& hv, const std::vector<size_t>& lds, rosar_batch_plan* pl, int cus) {
+  const int n = (int)hv.size();
+  std::vector<int> occ(n);
+  for (int i = 0; i < n; ++i) {
+    int o = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&o, SfKernel<P, NW>::fn(), kWave * NW, lds[i]) != hipSuccess ||
+        o < 1)
+      return bfail(ROSAR_ERR_HIP, "occupancy query for the batched sparse-filter kernel failed");
+    occ[i] = o;
+  }
+  std::vector<int> levels(occ.begin(), occ.end());
+  std::sort(levels.begin(), levels.end(), std::greater<int>());
+  levels.erase(std::unique(levels.begin(), levels.end()), levels.end());
+  while ((int)levels.size() > kSfClasses) levels.pop_back();   // merge the lowest levels
+  std::vector<BatchRot> sorted;
+  sorted.reserve(n);
+  pl->sf_classes = (int)levels.size();
+  for (int c = 0; c < pl->sf_classes; ++c) {
+    const bool last = c == pl->sf_classes - 1;
+    pl->sf_first[c] = (int)sorted.size();
+    int64_t tiles = 0;
+    size_t bytes = 0;
+    for (int i = 0; i < n; ++i) {
+      if (!(occ[i] == levels[c] || (last && occ[i] < levels[c]))) continue;
+      BatchRot R = hv[i];
+      R.sf_tile0 = (int32_t)tiles;
+      tiles += (int64_t)R.tiles_per_row * R.g.n_range;
+      bytes = std::max(bytes, lds[i]);
+      sorted.push_back(R);
+    }
+    pl->sf_count[c] = (int)sorted.size() - pl->sf_first[c];
+    pl->sf_tiles[c] = (int)tiles;
+    pl->sf_lds[c] = bytes;
+    int o = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&o, SfKernel<P, NW>::fn(), kWave * NW, bytes) != hipSuccess ||
+        o < 1)
+      return bfail(ROSAR_ERR_HIP, "occupancy query for the batched sparse-filter kernel failed");
+    pl->sf_grid[c] = (int)std::min<int64_t>((int64_t)cus * o, std::max<int64_t>(tiles, 1));
+  }
+  hv.swap(sorted);
   return ROSAR_OK;
 }
 
 template <int P, int NW>
 void run_shape(rosar_batch_plan* pl, hipStream_t s) {
-  SfKernel<P, NW>::launch(dim3(pl->sf_grid), pl->sf_lds, s, pl->d_rots, pl->n, pl->sf_total, pl->d_counters + 1);
+  for (int c = 0; c < pl->sf_classes; ++c)
+    SfKernel<P, NW>::launch(dim3(pl->sf_grid[c]), pl->sf_lds[c], s, pl->d_rots + pl->sf_first[c], pl->sf_count[c],
+                            pl->sf_tiles[c], pl->d_counters + c);
 }
 
 #define ROSAR_BATCH_SHAPES(X) X(1, 4) X(2, 4) X(4, 4) X(8, 4) X(2, 2) X(4, 2) X(8, 2) X(4, 8)
@@ -182,7 +228,7 @@ rosar_status rosar_batch_plan_create(const rosar_rotation_desc* descs, int32_t n
   std::vector<BatchRc> rc_by_len[kRcLengths];
   int64_t rc_tiles[kRcLengths] = {};
   int64_t sf_total = 0, pixels = 0;
-  size_t sf_lds = 0;
+  std::vector<size_t> sf_lds(n);
   for (int i = 0; i < n; ++i) {
     const rosar_rotation_desc& d = descs[i];
     const rosar_status st = validate_rotation(d, i);
@@ -225,10 +271,9 @@ rosar_status rosar_batch_plan_create(const rosar_rotation_desc* descs, int32_t n
     R.stride = L.stride;
     R.dma = L.dma;
     R.tiles_per_row = (R.g.n + tpx - 1) / tpx;
-    R.sf_tile0 = (int32_t)sf_total;
     sf_total += (int64_t)R.tiles_per_row * R.g.n_range;
     pixels += (int64_t)R.g.n * R.g.n_range;
-    sf_lds = std::max(sf_lds, L.bytes);
+    sf_lds[i] = L.bytes;
   }
   int64_t rc_total = 0;
   for (int li = 0; li < kRcLengths; ++li) rc_total += rc_tiles[li];
@@ -247,7 +292,6 @@ rosar_status rosar_batch_plan_create(const rosar_rotation_desc* descs, int32_t n
   pl->rc_total = (int)rc_total;
   pl->sf_total = (int)sf_total;
   pl->pixels = pixels;
-  pl->sf_lds = sf_lds;
   std::vector<BatchRc> hrc;
   hrc.reserve(n);
   for (int li = 0; li < kRcLengths; ++li) {
@@ -264,7 +308,7 @@ rosar_status rosar_batch_plan_create(const rosar_rotation_desc* descs, int32_t n
     return bfail(st, m);
   };
   rosar_status st = ROSAR_ERR_UNSUPPORTED;
-#define ROSAR_PLAN(P, NW) if (p == P && nw == NW) st = plan_shape<P, NW>(hv, pl, cus);
+#define ROSAR_PLAN(P, NW) if (p == P && nw == NW) st = plan_shape<P, NW>(hv, sf_lds, pl, cus);
   ROSAR_BATCH_SHAPES(ROSAR_PLAN)
 #undef ROSAR_PLAN
   if (st != ROSAR_OK) {
@@ -273,7 +317,7 @@ rosar_status rosar_batch_plan_create(const rosar_rotation_desc* descs, int32_t n
   }
   if (hipMalloc(&pl->d_rots, sizeof(BatchRot) * n) != hipSuccess ||
       hipMalloc(&pl->d_rc, sizeof(BatchRc) * n) != hipSuccess ||
-      hipMalloc(&pl->d_counters, 2 * sizeof(int)) != hipSuccess)
+      hipMalloc(&pl->d_counters, kSfClasses * sizeof(int)) != hipSuccess)
     return fail(ROSAR_ERR_NO_MEMORY, "device allocation of the batch descriptors failed");
   if (hipMemcpy(pl->d_rots, hv.data(), sizeof(BatchRot) * n, hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(pl->d_rc, hrc.data(), sizeof(BatchRc) * n, hipMemcpyHostToDevice) != hipSuccess)
@@ -290,7 +334,7 @@ rosar_status rosar_batch_run(rosar_batch_plan* pl, rosar_stream stream) {
   if (hipGetDevice(&dev) != hipSuccess || dev != pl->device)
     return bfail(ROSAR_ERR_INVALID_ARG, "plan was created on another device");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  batch_reset_kernel<<<1, 64, 0, s>>>(pl->d_counters);
+  batch_reset_kernel<<<1, 64, 0, s>>>(pl->d_counters, pl->sf_classes);
   for (int li = 0; li < kRcLengths; ++li) {
     if (!pl->rc_count[li]) continue;
     const BatchRc* g = pl->d_rc + pl->rc_first[li];
