@@ -208,10 +208,11 @@ rosar_status rosar_sparse_filter_backward(const rosar_geometry* geom, const rosa
 
 /* ---------------------------------------------------------------- batched rotations
  * Many independent rotations of uneven sizes imaged by one range-compression launch per FFT
- * length present (one workgroup per 8-pulse tile) and one persistent sparse-filter launch
- * whose workgroups pull tiles from a device work counter.  The counter is reset by the plan's
- * own kernel at the start of each run, so a run can be captured in a HIP graph and replayed.
- * NEAREST, uncorrected, C64 only. */
+ * length present (one workgroup per 8-pulse tile) and one persistent sparse-filter launch per
+ * occupancy class (rotations grouped by how many workgroups of their LDS layout fit on a CU),
+ * whose workgroups pull tiles from the class's device work counter.  The counters are reset by
+ * the plan's own kernel at the start of each run, so a run can be captured in a HIP graph and
+ * replayed.  NEAREST, uncorrected, C64 only. */
 typedef struct rosar_rotation_desc {
   rosar_geometry geom;
   rosar_polar_grid grid;
@@ -235,8 +236,8 @@ typedef struct rosar_batch_plan rosar_batch_plan;
  * read by its sparse filter; images are overwritten.  Errors name the offending rotation. */
 rosar_status rosar_batch_plan_create(const rosar_rotation_desc* descs, int32_t n,
                                      const rosar_tile* tile, rosar_batch_plan** out);
-/* Enqueues counter reset + range compression (one launch per FFT length) + persistent sparse
- * filter. */
+/* Enqueues counter reset + range compression (one launch per FFT length) + the persistent
+ * sparse-filter launches. */
 rosar_status rosar_batch_run(rosar_batch_plan* plan, rosar_stream stream);
 /* Total pixels and tiles of the plan (host values). */
 rosar_status rosar_batch_plan_info(const rosar_batch_plan* plan, int64_t* pixels,
