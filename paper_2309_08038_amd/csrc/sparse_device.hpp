@@ -78,7 +78,9 @@ __device__ __forceinline__ void mac_packed(float2& acc, uint32_t w1, uint32_t w2
 }
 
 typedef unsigned u32x2v __attribute__((ext_vector_type(2)));
+typedef unsigned u32x4v __attribute__((ext_vector_type(4)));
 typedef __attribute__((address_space(3))) const volatile u32x2v lds_u32x2;
+typedef __attribute__((address_space(3))) const volatile u32x4v lds_u32x4;
 typedef __attribute__((address_space(3))) const volatile uint32_t lds_u32;
 typedef __attribute__((address_space(3))) const char lds_char;
 
@@ -97,6 +99,18 @@ __device__ __forceinline__ void lds_sample(const char* smem, uint32_t byte_off, 
   }
 }
 
+// One tap-table entry as a single 16-byte broadcast LDS read (the compiler would otherwise
+// split it into the fields the loop uses, two instructions).
+__device__ __forceinline__ TapEntry lds_entry(const TapEntry* table, int e) {
+  const u32x4v v = *(lds_u32x4*)((lds_char*)reinterpret_cast<const char*>(table) + e * 16);
+  TapEntry t;
+  t.lds_off = (int)v.x;
+  t.glob_row = (int)v.y;
+  t.w1 = v.z;
+  t.w2 = v.w;
+  return t;
+}
+
 // Staged-entry loop for the first PA of the P pixel chunks of a lane (PA < P on a row's last,
 // partial wave).  Groups of U entries: table reads and samples first, then the FMAs.
 template <int DT, int P, int PA>
@@ -110,7 +124,7 @@ __device__ __forceinline__ void staged_taps(float2 (&acc)[P], const TapEntry* ta
     uint32_t ylo[U][PA], yhi[U][PA];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      te[u] = table[e + u];
+      te[u] = lds_entry(table, e + u);
       const uint32_t base = lane_base + (uint32_t)te[u].lds_off;
 #pragma unroll
       for (int p = 0; p < PA; ++p) lds_sample<DT>(stage, base + p * kWave * ES, ylo[u][p], yhi[u][p]);
@@ -121,7 +135,7 @@ __device__ __forceinline__ void staged_taps(float2 (&acc)[P], const TapEntry* ta
       for (int p = 0; p < PA; ++p) mac_packed<DT>(acc[p], te[u].w1, te[u].w2, ylo[u][p], yhi[u][p]);
   }
   for (; e < ne; ++e) {
-    const TapEntry te = table[e];
+    const TapEntry te = lds_entry(table, e);
     const uint32_t base = lane_base + (uint32_t)te.lds_off;
 #pragma unroll
     for (int p = 0; p < PA; ++p) {
