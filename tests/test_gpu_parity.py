@@ -368,6 +368,42 @@ def test_backward_small(interp):
     assert torch.equal(gw, gw2) and torch.equal(gd, gd2) and torch.equal(gp, gp2)
 
 
+@pytest.mark.parametrize("interp", ["nearest", "linear"])
+def test_max_taps_forward_corrected_and_adjoint(interp):
+    """K = 1024 (the ABI maximum) with W = N: several LDS tap chunks in the corrected forward and
+    in the adjoint, a tap table of 1024 entries in the plain filter."""
+    rs = need_gpu()
+    n = 1024
+    w = custom_workload("max_taps", 73, n, 64, 4, 0.6, 1.4, 1024, n)
+    x = synth.make_inputs(w)
+    yb = oracle.range_compress(x.raw, x.window, 64)[:, x.l_lo:x.l_lo + x.l_count]
+    rng = np.random.default_rng(29)
+    dphi = rng.normal(0, 2e-3, n).astype(np.float32)
+    dpsi = rng.normal(0, 0.2, n).astype(np.float32)
+    rc = rs.range_compress(w.geometry, to_dev(x.raw), to_dev(x.window), x.l_lo, x.l_count, halo=n // 2)
+    off, wts = to_dev(x.offsets), to_dev(x.weights.astype(np.complex64))
+    log(f"max taps plain {interp}")
+    ref = oracle.sparse_filter(yb, x.l_lo, w.geometry, w.grid, x.offsets, x.weights, interp=interp)
+    img = rs.sparse_filter(w.geometry, w.grid, rc, off, wts, n, interp=interp).cpu().numpy()
+    assert rel_l2(img, ref) <= TOL
+    log(f"max taps corrected {interp}")
+    ref = oracle.sparse_filter(yb, x.l_lo, w.geometry, w.grid, x.offsets, x.weights, dphi=dphi.astype(np.float64),
+                               dpsi=dpsi.astype(np.float64), interp=interp)
+    img = rs.sparse_filter(w.geometry, w.grid, rc, off, wts, n, dphi=to_dev(dphi), dpsi=to_dev(dpsi),
+                           interp=interp).cpu().numpy()
+    assert rel_l2(img, ref) <= TOL
+    log(f"max taps adjoint {interp}")
+    gimg = synth.random_complex((w.grid.n_range, n), seed=37)
+    gw_r, gd_r, gp_r = oracle.sparse_filter_grad(yb, x.l_lo, w.geometry, w.grid, x.offsets, x.weights,
+                                                 gimg.astype(np.complex128), dphi.astype(np.float64),
+                                                 dpsi.astype(np.float64), interp)
+    gw, gd, gp = rs.sparse_filter_backward(w.geometry, w.grid, rc, off, wts, n, to_dev(gimg), to_dev(dphi),
+                                           to_dev(dpsi), interp)
+    assert rel_l2(gw.cpu().numpy(), gw_r) <= 1e-3
+    assert rel_l2(gd.cpu().numpy(), gd_r) <= 1e-3
+    assert rel_l2(gp.cpu().numpy(), gp_r) <= 1e-3
+
+
 def test_calibration_gradient_rotation_subgrid():
     """Calibration workload: loss = entropy + sidelobe energy on a 64 x 360 sub-grid of the
     full-size image, gradients through the autograd Function vs the FP64 oracle gradient."""
