@@ -47,6 +47,8 @@ def parse():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for PMC byte counters)")
     ap.add_argument("--tile", default=None, help="sparse-filter launch shape variant,ppl,waves")
+    ap.add_argument("--single-call", action="store_true",
+                    help="time the steps with the single-call sparse filter instead of a plan")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the corrected-forward, adjoint, batch and precision timings")
     return ap.parse_args()
@@ -146,11 +148,12 @@ def graph_timer(torch):
     return timed
 
 
-def pipelined_steps(torch, rs, g, grid, x, raw, win, off, wts, window, tile, steps):
+def pipelined_steps(torch, rs, g, grid, x, raw, win, window, sf, steps):
     """`steps` FFT+SAS steps as one HIP graph on two streams: step i's range compression writes
     band buffer i mod 2 on stream B (after step i - 2's sparse filter has read that buffer), its
     sparse filter runs on stream A after it.  So the range compression of step i + 1 overlaps
-    the sparse filter of step i.  Returns (ms per step from one timed replay, last image)."""
+    the sparse filter of step i.  sf(rc, out) runs the sparse filter.  Returns (ms per step from
+    one timed replay, last image)."""
     dev = raw.device
     rcs = [rs.empty_rc(g.n_pulses, x.l_lo, x.l_count, halo=window // 2, device=dev) for _ in range(2)]
     imgs = [torch.empty((grid.n_range, grid.n_az), dtype=torch.complex64, device=dev) for _ in range(2)]
@@ -171,7 +174,7 @@ def pipelined_steps(torch, rs, g, grid, x, raw, win, off, wts, window, tile, ste
                 ev_rc[i].record(sb)
             with torch.cuda.stream(sa):
                 sa.wait_event(ev_rc[i])
-                rs.sparse_filter(g, grid, rcs[b], off, wts, window, out=imgs[b], tile=tile)
+                sf(rcs[b], imgs[b])
                 ev_sf[i].record(sa)
         sa.wait_stream(sb)
 
@@ -277,11 +280,17 @@ def extras(torch, rs, synth, w, x, dev, rc, off, wts, timed, reps):
                                                out=prc), max(3, reps // 10), inner=10, out=lambda: prc.data)
         ff = lambda: rs.sparse_filter(pg, pgrid, prc, poff, wt, pw.sparse.window, out=pimg)
         ff()
-        t_sf = timed(ff, max(3, reps // 10), inner=10, out=lambda: pimg)
+        t_single = timed(ff, max(3, reps // 10), inner=10, out=lambda: pimg)
+        pplan = rs.SparsePlan(pg, pgrid, prc, poff, wt, pw.sparse.window)
+        fp = lambda: pplan.run(prc, out=pimg)
+        fp()
+        t_sf = timed(fp, max(3, reps // 10), inner=10, out=lambda: pimg)
+        pplan.close()
         prec[dt] = {"range_compress_us": 1000 * t_rc, "sparse_filter_us": 1000 * t_sf,
+                    "sparse_filter_single_call_us": 1000 * t_single,
                     "pixels_per_s": pgrid.n_range * pgrid.n_az / ((t_rc + t_sf) * 1e-3)}
-        print(f"[bench] precision {dt}: rc {1000 * t_rc:.1f} us, sf {1000 * t_sf:.1f} us", file=sys.stderr,
-              flush=True)
+        print(f"[bench] precision {dt}: rc {1000 * t_rc:.1f} us, sf {1000 * t_sf:.1f} us planned / "
+              f"{1000 * t_single:.1f} us single call", file=sys.stderr, flush=True)
     out["precision"] = prec
     return out
 
@@ -314,10 +323,27 @@ def main():
     bimg = torch.empty_like(img)
     bws = torch.empty(rs.bp_workspace_bytes(g), dtype=torch.uint8, device=dev)
     tile = tuple(int(v) for v in a.tile.split(",")) if a.tile else None
+    # one filter design for every rotation: the tap tables of its range rows are built once,
+    # outside the timed steps (the plan equals the single call with the same shape bit for bit)
+    rs.range_compress(g, raw, win, x.l_lo, x.l_count, out=rc)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan = rs.SparsePlan(g, grid, rc, off, wts, w.sparse.window,
+                         tile=tile[1:] if tile is not None and tile[0] in (0, 2) else None)
+    torch.cuda.synchronize()
+    ms_plan = 1000 * (time.perf_counter() - t0)
+
+    def single(rc_, out_):
+        rs.sparse_filter(g, grid, rc_, off, wts, w.sparse.window, out=out_, tile=tile)
+
+    def planned(rc_, out_):
+        plan.run(rc_, out=out_)
+
+    sf = single if a.single_call else planned
 
     def step():
         rs.range_compress(g, raw, win, x.l_lo, x.l_count, out=rc)
-        rs.sparse_filter(g, grid, rc, off, wts, w.sparse.window, out=img, tile=tile)
+        sf(rc, img)
 
     timed = graph_timer(torch)
     for _ in range(a.warmup):
@@ -330,7 +356,7 @@ def main():
     # compression of step i + 1 on a second stream overlapping the sparse filter of step i
     # (double-buffered band); every step still runs its whole path over its input
     t0 = time.perf_counter()
-    ms_step, last = pipelined_steps(torch, rs, g, grid, x, raw, win, off, wts, w.sparse.window, tile, a.steps)
+    ms_step, last = pipelined_steps(torch, rs, g, grid, x, raw, win, w.sparse.window, sf, a.steps)
     wall = time.perf_counter() - t0
     if not torch.equal(last, ref):
         raise RuntimeError("pipelined steps differ from the serial result")
@@ -341,12 +367,17 @@ def main():
     kreps = max(3, a.steps // 10)
     ms_rc = timed(lambda: rs.range_compress(g, raw, win, x.l_lo, x.l_count, out=rc), kreps, inner=20,
                   out=lambda: rc.data)
-    ms_sf = timed(lambda: rs.sparse_filter(g, grid, rc, off, wts, w.sparse.window, out=img, tile=tile), kreps,
-                  inner=20, out=lambda: img)
+    ms_sf = timed(lambda: sf(rc, img), kreps, inner=20, out=lambda: img)
+    sf_ref = img.clone()
+    ms_sf_other = timed(lambda: (planned if a.single_call else single)(rc, img), kreps, inner=20, out=lambda: img)
+    if not torch.equal(img, sf_ref):
+        raise RuntimeError("planned and single-call sparse filters differ")
+    ms_sf_plan, ms_sf_single = (ms_sf_other, ms_sf) if a.single_call else (ms_sf, ms_sf_other)
     rs.bp_full(g, grid, rc, angles=ang, out=bimg, workspace=bws)
     ms_bp = timed(lambda: rs.bp_full(g, grid, rc, angles=ang, out=bimg, workspace=bws), a.bpa_reps,
                   out=lambda: bimg)
-    print(f"[bench] range_compress {ms_rc:.4f} ms, sparse_filter {ms_sf:.4f} ms, bp_full {ms_bp:.3f} ms",
+    print(f"[bench] range_compress {ms_rc:.4f} ms, sparse_filter {ms_sf_plan:.4f} ms planned / "
+          f"{ms_sf_single:.4f} ms single call (plan built in {ms_plan:.1f} ms), bp_full {ms_bp:.3f} ms",
           file=sys.stderr, flush=True)
     if a.copy_calibration:
         src = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
@@ -368,7 +399,9 @@ def main():
                 "unit": "TFLOP/s", "frac": round(achieved_tf / PEAK_FP32_VALU_TFLOPS, 4),
                 "peak_with_packed_fp32": PEAK_FP32_PACKED_TFLOPS,
                 "frac_of_packed_peak": round(achieved_tf / PEAK_FP32_PACKED_TFLOPS, 4),
-                "traffic": traffic, "kernel": "sparse_lds_kernel (default launch shape)",
+                "traffic": traffic,
+                "kernel": "sparse_lds_kernel (" + ("single call" if a.single_call else "planned tap tables")
+                          + ", default launch shape)",
                 "algorithmic_bytes": sf_bytes, "algorithmic_flops": sf_flops}
     out = {
         "metric": "polar image pixels/s: sparse-array filter vs full BPA on 1 MI355X; HBM GB/s",
@@ -392,7 +425,10 @@ def main():
         "fft_bpa_pixels_per_s": px / ((ms_bp + ms_rc) * 1e-3),
         "sparse_vs_bpa": ms_bp / ms_sf,
         "fft_sas_vs_fft_bpa": (ms_bp + ms_rc) / ms_step_serial,
-        "kernel_ms": {"range_compress": ms_rc, "sparse_filter": ms_sf, "bp_full": ms_bp},
+        "kernel_ms": {"range_compress": ms_rc, "sparse_filter": ms_sf, "sparse_filter_planned": ms_sf_plan,
+                      "sparse_filter_single_call": ms_sf_single, "bp_full": ms_bp},
+        "sparse_filter_mode": "single call" if a.single_call else "plan (tap tables built once per filter design)",
+        "plan_create_ms_wall": ms_plan,
         "hbm_gbps": {"sparse_filter": sf_bytes / (ms_sf * 1e-3) / 1e9,
                      "range_compress": rc_bytes / (ms_rc * 1e-3) / 1e9, "peak": PEAK_HBM_GBPS},
         "roofline": roofline,
@@ -400,7 +436,9 @@ def main():
         "timing": "HIP-graph replays, events on the launch stream.  value / ms_per_step: the timed steps "
                   "as one graph on two streams, the range compression of step i+1 overlapping the sparse "
                   "filter of step i (double-buffered band); ms_per_step_serial: the same steps on one "
-                  "stream; per-kernel figures: 20 launches per graph",
+                  "stream; per-kernel figures: 20 launches per graph.  The sparse filter runs from a plan "
+                  "whose per-row tap tables are built once per filter design before timing (plan_create_ms_wall); "
+                  "kernel_ms.sparse_filter_single_call is the entry point that builds them in every workgroup",
     }
     if not a.no_extras:
         out["rows"] = extras(torch, rs, synth, w, x, dev, rc, off, wts, timed, a.steps)

@@ -249,6 +249,39 @@ void rosar_batch_plan_destroy(rosar_batch_plan* plan);
 rosar_status rosar_batch_autotune(const rosar_rotation_desc* descs, int32_t n, int32_t reps,
                                   rosar_tile* best, float* best_us, rosar_stream stream);
 
+/* ---------------------------------------------------------------- sparse-filter plans
+ * One filter design applied to many rotations: the sparse weights of Sec. III-C are designed
+ * offline, only the range-compressed data change from rotation to rotation.  A plan evaluates,
+ * once, the tap table of every range row -- the float64 bin of each tap (eq. 2, eq. 40), its
+ * packed weight and its offset in the LDS-staged window -- into device memory it owns; each
+ * run then copies a row's table into LDS instead of building it.  A run computes the same
+ * image, bit for bit, as rosar_sparse_filter_tiled with the same launch shape (variant 2). */
+typedef struct rosar_sparse_plan rosar_sparse_plan;
+
+/* Validates the arguments as rosar_sparse_filter does and enqueues the table kernel on
+ * `stream` (the tables are ready in stream order).  rc fixes the band layout of every run
+ * (l_lo, l_count, halo, ld, dtype, scale); its data pointer must be valid and 16-byte aligned
+ * but is not read.  offsets and weights are read by the table kernel only: change them and
+ * create a new plan.  tile: NULL or {0 or 2, pixels_per_lane, waves} with pixels_per_lane x
+ * waves in {4x8, 8x4, 4x4, 2x8, 2x4, 8x2} (NULL = the rosar_sparse_filter default, or 2x4 where
+ * that default is 1 pixel per lane, i.e. n_az <= 1024).  No
+ * angle/phase errors (those change per rotation: use rosar_sparse_filter).
+ * Errors: INVALID_ARG as rosar_sparse_filter; UNSUPPORTED for another shape, or a layout the
+ * LDS-staged kernel cannot take (halo < W/2, rows not 16-byte aligned, one staged row over the
+ * LDS budget); NO_MEMORY if the table allocation ((K or 2K) x 24 bytes + 16 per row, rounded
+ * to 16) fails. */
+rosar_status rosar_sparse_plan_create(const rosar_geometry* geom, const rosar_polar_grid* grid,
+                                      const rosar_rc_view* rc, const rosar_sparse_set* set,
+                                      rosar_interp interp, const rosar_tile* tile, rosar_stream stream,
+                                      rosar_sparse_plan** out);
+/* Runs the plan: rc must have the layout of the plan (a different data pointer is the point);
+ * image [n_range][n_az] C64, 8-byte aligned, overwritten.  Asynchronous on `stream`; the plan
+ * must be used on the device it was created on.  Safe to capture in a HIP graph. */
+rosar_status rosar_sparse_plan_run(const rosar_sparse_plan* plan, const rosar_rc_view* rc, void* image,
+                                   rosar_stream stream);
+/* Frees the plan's tables (NULL is a no-op).  No run of the plan may be pending. */
+void rosar_sparse_plan_destroy(rosar_sparse_plan* plan);
+
 /* ---------------------------------------------------------------- autotuning
  * Times every supported launch shape of rosar_sparse_filter on the given inputs (the image is
  * overwritten), `reps` timed launches each, and returns the fastest in *best with its mean

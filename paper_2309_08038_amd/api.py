@@ -262,6 +262,49 @@ def _descs(rotations):
     return arr
 
 
+class SparsePlan:
+    """A sparse-filter plan: one filter design (geometry, grid, offsets, weights, band layout)
+    applied to the range-compressed data of many rotations.  The rows' tap tables are built once
+    on the device; each run() computes the image rosar_sparse_filter gives with the same launch
+    shape.  `layout` is a RangeCompressed whose band layout every run must share; the offsets
+    and weights are read when the plan is created."""
+
+    def __init__(self, geom, grid, layout: RangeCompressed, offsets, weights, window, interp: str = "nearest",
+                 tile: tuple[int, int] | None = None):
+        _need_gpu(layout.data)
+        s = _set(offsets, weights, window)
+        g, p, v = L.geometry(geom), L.polar_grid(grid), layout.view()
+        t = None if tile is None else L.Tile(2, tile[0], tile[1], 0)
+        h = C.c_void_p()
+        L.check(L.lib().rosar_sparse_plan_create(C.byref(g), C.byref(p), C.byref(v), C.byref(s),
+                                                 L.INTERP_CODES[interp], None if t is None else C.byref(t),
+                                                 _stream(layout.data.device), C.byref(h)), "rosar_sparse_plan_create")
+        self._h = h
+        self.grid = grid
+        self.device = layout.data.device
+        self._keep = (offsets, weights)
+
+    def run(self, rc: RangeCompressed, out: torch.Tensor | None = None) -> torch.Tensor:
+        _need_gpu(rc.data)
+        if out is None:
+            out = torch.empty((self.grid.n_range, self.grid.n_az), dtype=torch.complex64, device=rc.data.device)
+        v = rc.view()
+        L.check(L.lib().rosar_sparse_plan_run(self._h, C.byref(v), _ptr(out), _stream(rc.data.device)),
+                "rosar_sparse_plan_run")
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None):
+            L.lib().rosar_sparse_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 class BatchPlan:
     """Persistent batched imaging of many rotations (range compression + sparse filter).
 

@@ -269,6 +269,8 @@ rosar_status rosar_sparse_filter_tiled(const rosar_geometry* geom, const rosar_p
   rosar::SparseArgs a{};
   ROSAR_TRY(sparse_common(geom, grid, rc, set, dphi, dpsi, interp, image, &a));
   rosar::Tile t = rosar::default_tile(geom->n_pulses, rc->dtype);
+  // small images default to 1 pixel per lane, which has no planned instantiation: take 2 x 4
+  if (!rosar::plan_shape_supported(t.ppl, t.waves)) t = rosar::Tile{2, 2, 4};
   if (tile && (tile->pixels_per_lane || tile->waves || tile->variant)) {
     t = rosar::Tile{tile->variant ? tile->variant : 1, tile->pixels_per_lane ? tile->pixels_per_lane : t.ppl,
                     tile->waves ? tile->waves : t.waves};
@@ -347,6 +349,107 @@ rosar_status rosar_sparse_filter_backward(const rosar_geometry* geom, const rosa
                                                 reinterpret_cast<float2*>(grad_weights), grad_dphi, grad_dpsi,
                                                 workspace, reinterpret_cast<hipStream_t>(stream)),
                   "sparse_filter_backward launch");
+}
+
+}  // extern "C"
+
+struct rosar_sparse_plan {
+  rosar::SparseArgs a{};      // geometry, band layout (data NULL), set, interp
+  rosar::PlanLayout layout{};
+  rosar_rc_view view{};       // layout fields every run must match
+  char* tabs = nullptr;       // n_range row blocks of layout.row_bytes
+  int device = -1;
+};
+
+extern "C" {
+
+rosar_status rosar_sparse_plan_create(const rosar_geometry* geom, const rosar_polar_grid* grid,
+                                      const rosar_rc_view* rc, const rosar_sparse_set* set,
+                                      rosar_interp interp, const rosar_tile* tile, rosar_stream stream,
+                                      rosar_sparse_plan** out) {
+  rosar::clear_error();
+  if (!out) return fail(ROSAR_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  rosar::SparseArgs a{};
+  // the plan has no image yet: sparse_common's image check gets an aligned host placeholder
+  alignas(8) static double placeholder = 0.0;
+  ROSAR_TRY(sparse_common(geom, grid, rc, set, nullptr, nullptr, interp, &placeholder, &a));
+  if (!aligned(rc->data, 16)) return fail(ROSAR_ERR_INVALID_ARG, "rc view data must be 16-byte aligned");
+  rosar::Tile t = rosar::default_tile(geom->n_pulses, rc->dtype);
+  // small images default to 1 pixel per lane, which has no planned instantiation: take 2 x 4
+  if (!rosar::plan_shape_supported(t.ppl, t.waves)) t = rosar::Tile{2, 2, 4};
+  if (tile && (tile->pixels_per_lane || tile->waves || tile->variant)) {
+    if (tile->variant != 0 && tile->variant != 2)
+      return fail(ROSAR_ERR_UNSUPPORTED, "a plan runs the LDS-staged variant (2), not %d", tile->variant);
+    t.ppl = tile->pixels_per_lane ? tile->pixels_per_lane : t.ppl;
+    t.waves = tile->waves ? tile->waves : t.waves;
+  }
+  if (!rosar::plan_shape_supported(t.ppl, t.waves))
+    return fail(ROSAR_ERR_UNSUPPORTED, "plan launch shape %d pixels/lane x %d waves not supported", t.ppl, t.waves);
+  rosar::PlanLayout pl{};
+  if (!rosar::sparse_plan_layout(a, t.ppl, t.waves, &pl))
+    return fail(ROSAR_ERR_UNSUPPORTED,
+                "this band layout cannot use the LDS-staged kernel (halo < W/2, rows not 16-byte aligned, or a "
+                "staged row over the LDS budget)");
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return fail(ROSAR_ERR_HIP, "cannot query the current device");
+  auto* p = new (std::nothrow) rosar_sparse_plan();
+  if (!p) return fail(ROSAR_ERR_NO_MEMORY, "host allocation failed");
+  p->a = a;
+  p->a.y.data = nullptr;
+  p->a.image = nullptr;
+  p->layout = pl;
+  p->view = *rc;
+  p->view.data = nullptr;
+  p->device = dev;
+  const size_t bytes = (size_t)pl.row_bytes * (size_t)grid->n_range;
+  if (hipMalloc(&p->tabs, bytes) != hipSuccess) {
+    delete p;
+    return fail(ROSAR_ERR_NO_MEMORY, "device allocation of the tap tables (%zu bytes) failed", bytes);
+  }
+  if (inject_launch_fault()) {
+    (void)hipFree(p->tabs);
+    delete p;
+    return fail(ROSAR_ERR_HIP, "injected launch failure (ROSAR_FAULT_INJECT)");
+  }
+  a.y.data = rc->data;
+  const rosar_status st = from_hip(rosar::launch_tap_tables(a, pl, p->tabs, reinterpret_cast<hipStream_t>(stream)),
+                                   "tap table launch");
+  if (st != ROSAR_OK) {
+    (void)hipFree(p->tabs);
+    delete p;
+    return st;
+  }
+  *out = p;
+  return ROSAR_OK;
+}
+
+rosar_status rosar_sparse_plan_run(const rosar_sparse_plan* plan, const rosar_rc_view* rc, void* image,
+                                   rosar_stream stream) {
+  rosar::clear_error();
+  if (!plan) return fail(ROSAR_ERR_INVALID_ARG, "plan is NULL");
+  if (!rc) return fail(ROSAR_ERR_INVALID_ARG, "rc view is NULL");
+  const rosar_rc_view& v = plan->view;
+  if (rc->dtype != v.dtype || rc->l_lo != v.l_lo || rc->l_count != v.l_count || rc->halo != v.halo ||
+      rc->ld != v.ld || rc->scale != v.scale || rc->reserved != 0)
+    return fail(ROSAR_ERR_INVALID_ARG, "rc view layout differs from the plan's");
+  if (!rc->data || !aligned(rc->data, 16)) return fail(ROSAR_ERR_INVALID_ARG, "rc view data NULL or not 16-byte aligned");
+  ROSAR_TRY(check_image(image, "image"));
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev != plan->device)
+    return fail(ROSAR_ERR_INVALID_ARG, "plan was created on another device");
+  if (inject_launch_fault()) return fail(ROSAR_ERR_HIP, "injected launch failure (ROSAR_FAULT_INJECT)");
+  rosar::SparseArgs a = plan->a;
+  a.y.data = rc->data;
+  a.image = reinterpret_cast<float2*>(image);
+  return from_hip(rosar::launch_sparse_planned(a, plan->layout, plan->tabs, reinterpret_cast<hipStream_t>(stream)),
+                  "sparse plan launch");
+}
+
+void rosar_sparse_plan_destroy(rosar_sparse_plan* plan) {
+  if (!plan) return;
+  (void)hipFree(plan->tabs);
+  delete plan;
 }
 
 rosar_status rosar_autotune_sparse_filter(const rosar_geometry* geom, const rosar_polar_grid* grid,

@@ -73,6 +73,19 @@ void clear_error();
 rosar_status validate_rotation(const rosar_rotation_desc& d, int index);
 Geo geo_of(const rosar_geometry* g, const rosar_polar_grid* p);
 
+// Sparse-filter plans: the LDS layout a plan fixes, the kernel that writes every row's tap table
+// (row_bytes each) and the filter launch that copies them into LDS.
+struct PlanLayout {
+  int ppl, waves;
+  int rows_cap, stride, shift, row_bytes;
+  double cos_hw;
+  size_t lds_bytes;
+};
+bool plan_shape_supported(int ppl, int waves);
+bool sparse_plan_layout(const SparseArgs& a, int ppl, int waves, PlanLayout* out);
+hipError_t launch_tap_tables(const SparseArgs& a, const PlanLayout& pl, char* tabs, hipStream_t s);
+hipError_t launch_sparse_planned(const SparseArgs& a, const PlanLayout& pl, const char* tabs, hipStream_t s);
+
 // Tile chosen when the caller leaves it to the library.
 Tile default_tile(int32_t n, int32_t y_dtype);
 bool tile_supported(const Tile& t);

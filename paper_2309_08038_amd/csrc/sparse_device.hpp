@@ -366,22 +366,53 @@ __device__ __forceinline__ void store_pixels(const float2 (&acc)[P], float inv_s
 __host__ __device__ constexpr int table_bytes(int ne) { return ne * (int)sizeof(TapEntry); }
 __host__ __device__ constexpr int stage_offset(int ne) { return (ne * ((int)sizeof(TapEntry) + 8) + 15) & ~15; }
 
+// Precomputed tap tables (sparse-filter plans).  One block per range row, in the byte layout the
+// tile function stages: a 16-byte header (first staged bin row, staged row count, any entry
+// outside the staged rows), the tap table and its side copy of the weights.  The entries are
+// those build_taps makes inside the tile function, so both paths compute the same image.
+__host__ __device__ constexpr int row_table_bytes(int ne) { return 16 + stage_offset(ne); }
+
+template <int DT, int WDT, int INTERP>
+__global__ __launch_bounds__(256) void tap_table_kernel(Geo g, View y, int32_t k, int32_t window, int rows_cap,
+                                                        double cos_hw, int stride, int shift,
+                                                        const int32_t* __restrict__ offsets,
+                                                        const void* __restrict__ weights, char* __restrict__ tabs) {
+  constexpr int NSUB = INTERP == ROSAR_LINEAR ? 2 : 1;
+  const int row = blockIdx.x;
+  const int ne = k * NSUB;
+  char* blk = tabs + (size_t)row * row_table_bytes(ne);
+  const RowSpan sp = row_span<INTERP>(g, y, row, rows_cap, cos_hw);
+  __shared__ int s_any;
+  if (threadIdx.x == 0) s_any = 0;
+  __syncthreads();
+  if (build_taps<DT, WDT, INTERP>(g, y, k, window / 2, row, sp, stride, shift, offsets, weights,
+                                  reinterpret_cast<TapEntry*>(blk + 16),
+                                  reinterpret_cast<uint2*>(blk + 16 + table_bytes(ne)), threadIdx.x, blockDim.x))
+    s_any = 1;
+  __syncthreads();
+  if (threadIdx.x == 0) *reinterpret_cast<int4*>(blk) = make_int4(sp.lfirst, sp.nrows, s_any, 0);
+}
+
 // One workgroup's tile: `row` x pixels [tile * T, tile * T + T) of a rotation.  All threads of
 // the workgroup call it; `smem` is the dynamic LDS (lds_bytes of the layout), `s_unstaged` a
 // workgroup-shared int.  Staging is issued at entry, while the threads build the row's tap
-// table (tap t by thread t).  Ends with every thread past its last LDS access, but callers
-// that reuse `smem` for another tile must place a barrier in between.
-template <int DT, int WDT, int INTERP, int P, int NW>
+// table (tap t by thread t) -- or, with PRE, copy the row's precomputed table block from `tabs`
+// (tap_table_kernel; then `smem` holds 16 more bytes, the block header, in front).  Ends with
+// every thread past its last LDS access, but callers that reuse `smem` for another tile must
+// place a barrier in between.
+template <int DT, int WDT, int INTERP, int P, int NW, bool PRE = false>
 __device__ __forceinline__ void lds_tile(const Geo& g, const View& y, int32_t k, int32_t window, int row,
                                          int tile, int rows_cap, double cos_hw, int stride, int use_dma,
                                          const int32_t* __restrict__ offsets, const void* __restrict__ weights,
                                          const char* __restrict__ ydata, float2* __restrict__ image, char* smem,
-                                         int& s_unstaged) {
+                                         int& s_unstaged, const char* __restrict__ tabs = nullptr) {
   constexpr int ES = Elem<DT>::bytes;
   constexpr int NSUB = INTERP == ROSAR_LINEAR ? 2 : 1;
   constexpr int NT = kWave * NW;
   constexpr int T = kWave * P * NW;
   const int ne = k * NSUB;
+  char* const hdr = smem;
+  if constexpr (PRE) smem += 16;
   TapEntry* table = reinterpret_cast<TapEntry*>(smem);
   uint2* side = reinterpret_cast<uint2*>(smem + table_bytes(ne));
   char* stage = smem + stage_offset(ne);
@@ -397,13 +428,31 @@ __device__ __forceinline__ void lds_tile(const Geo& g, const View& y, int32_t k,
   else stage_copy<DT, NW>(y, ydata, stage, sp, n, a0, half_w, T + window, stride);
   const int shift = (a0 - half_w + y.halo) - col0 + half_w;
 
-  if (threadIdx.x == 0) s_unstaged = 0;
-  __syncthreads();
-  if (build_taps<DT, WDT, INTERP>(g, y, k, half_w, row, sp, stride, shift, offsets, weights, table, side,
-                                  threadIdx.x, NT))
-    s_unstaged = 1;
-  if (use_dma) __builtin_amdgcn_s_waitcnt(0);  // direct-to-LDS loads complete
-  __syncthreads();
+  if constexpr (PRE) {
+    // the row's table block (header, entries, weights) straight into LDS, 16 bytes a lane
+    const char* src = tabs + (size_t)row * row_table_bytes(ne);
+    const int n16 = row_table_bytes(ne) / 16;
+    for (int c = wave * kWave; c < n16; c += NT) {
+      if (c + lane < n16)
+        __builtin_amdgcn_global_load_lds((gbl_void_t*)(src + (size_t)(c + lane) * 16), (lds_void_t*)(hdr + c * 16),
+                                         16, 0, 0);
+    }
+    (void)offsets;
+    (void)weights;
+    (void)shift;
+    __builtin_amdgcn_s_waitcnt(0);  // direct-to-LDS loads complete
+    __syncthreads();
+    if (threadIdx.x == 0) s_unstaged = reinterpret_cast<const int*>(hdr)[2];
+    __syncthreads();
+  } else {
+    if (threadIdx.x == 0) s_unstaged = 0;
+    __syncthreads();
+    if (build_taps<DT, WDT, INTERP>(g, y, k, half_w, row, sp, stride, shift, offsets, weights, table, side,
+                                    threadIdx.x, NT))
+      s_unstaged = 1;
+    if (use_dma) __builtin_amdgcn_s_waitcnt(0);  // direct-to-LDS loads complete
+    __syncthreads();
+  }
 
   const int a_wave = a0 + wave * kWave * P;
   if (a_wave >= n) return;  // whole wave past the row end (no barrier below)

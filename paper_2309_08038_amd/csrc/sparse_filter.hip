@@ -336,20 +336,23 @@ __global__ __launch_bounds__(kCorrThreads) void sparse_corrected_kernel(
   }
 }
 
-template <int DT, int WDT, int INTERP, int P, int NW>
+// PRE: the rows' tap tables come precomputed from `tabs` (sparse-filter plans).
+template <int DT, int WDT, int INTERP, int P, int NW, bool PRE>
 __global__ __launch_bounds__(kWave* NW) void sparse_lds_kernel(Geo g, View y, int32_t k, int32_t window,
                                                                int tiles_per_row, int nblocks, int rows_cap,
                                                                double cos_hw, int stride, int use_dma,
                                                                const int32_t* __restrict__ offsets,
                                                                const void* __restrict__ weights,
                                                                const char* __restrict__ ydata,
-                                                               float2* __restrict__ image) {
+                                                               float2* __restrict__ image,
+                                                               const char* __restrict__ tabs) {
   extern __shared__ __align__(16) char smem[];
   __shared__ int s_unstaged;
   const int blk = xcd_logical_block(blockIdx.x, nblocks);
   const int row = blk / tiles_per_row;
-  sparse::lds_tile<DT, WDT, INTERP, P, NW>(g, y, k, window, row, blk - row * tiles_per_row, rows_cap,
-                                           cos_hw, stride, use_dma, offsets, weights, ydata, image, smem, s_unstaged);
+  sparse::lds_tile<DT, WDT, INTERP, P, NW, PRE>(g, y, k, window, row, blk - row * tiles_per_row, rows_cap, cos_hw,
+                                                stride, use_dma, offsets, weights, ydata, image, smem, s_unstaged,
+                                                tabs);
 }
 
 template <int DT, int WDT, int INTERP, int P, int NW>
@@ -360,9 +363,9 @@ hipError_t launch_lds_t(const SparseArgs& a, hipStream_t s, bool* fits) {
   if (!*fits) return hipSuccess;
   const int tiles = (a.g.n + T - 1) / T;
   const int nblocks = tiles * a.g.n_range;
-  sparse_lds_kernel<DT, WDT, INTERP, P, NW><<<nblocks, kWave * NW, L.bytes, s>>>(
+  sparse_lds_kernel<DT, WDT, INTERP, P, NW, false><<<nblocks, kWave * NW, L.bytes, s>>>(
       a.g, a.y, a.k, a.window, tiles, nblocks, L.rows, L.cos_hw, L.stride, L.dma, a.offsets, a.weights,
-      reinterpret_cast<const char*>(a.y.data), a.image);
+      reinterpret_cast<const char*>(a.y.data), a.image, nullptr);
   return hipGetLastError();
 }
 
@@ -428,7 +431,97 @@ hipError_t launch_corr_dt(const SparseArgs& a, hipStream_t s) {
   return lin ? launch_corr_t<DT, 1, ROSAR_LINEAR>(a, s) : launch_corr_t<DT, 1, ROSAR_NEAREST>(a, s);
 }
 
+// ---------------------------------------------------------------- sparse-filter plans
+#define ROSAR_PLAN_SHAPES(X) X(4, 8) X(8, 4) X(4, 4) X(2, 8) X(2, 4) X(8, 2)
+
+template <int DT, int WDT, int INTERP, int P, int NW>
+hipError_t launch_planned_t(const SparseArgs& a, const PlanLayout& pl, const char* tabs, hipStream_t s) {
+  constexpr int T = kWave * P * NW;
+  const int tiles = (a.g.n + T - 1) / T;
+  const int nblocks = tiles * a.g.n_range;
+  sparse_lds_kernel<DT, WDT, INTERP, P, NW, true><<<nblocks, kWave * NW, pl.lds_bytes, s>>>(
+      a.g, a.y, a.k, a.window, tiles, nblocks, pl.rows_cap, pl.cos_hw, pl.stride, 1, a.offsets, a.weights,
+      reinterpret_cast<const char*>(a.y.data), a.image, tabs);
+  return hipGetLastError();
+}
+
+template <int DT, int WDT, int INTERP>
+hipError_t launch_planned_shape(const SparseArgs& a, const PlanLayout& pl, const char* tabs, hipStream_t s) {
+#define ROSAR_PSHAPE(P, NW) \
+  if (pl.ppl == P && pl.waves == NW) return launch_planned_t<DT, WDT, INTERP, P, NW>(a, pl, tabs, s);
+  ROSAR_PLAN_SHAPES(ROSAR_PSHAPE)
+#undef ROSAR_PSHAPE
+  return hipErrorInvalidValue;
+}
+
+template <int DT>
+hipError_t launch_planned_dt(const SparseArgs& a, const PlanLayout& pl, const char* tabs, hipStream_t s) {
+  const bool lin = a.interp == ROSAR_LINEAR;
+  if (a.w_dtype == ROSAR_C64)
+    return lin ? launch_planned_shape<DT, 0, ROSAR_LINEAR>(a, pl, tabs, s)
+               : launch_planned_shape<DT, 0, ROSAR_NEAREST>(a, pl, tabs, s);
+  return lin ? launch_planned_shape<DT, 1, ROSAR_LINEAR>(a, pl, tabs, s)
+             : launch_planned_shape<DT, 1, ROSAR_NEAREST>(a, pl, tabs, s);
+}
+
+template <int DT, int WDT, int INTERP>
+hipError_t launch_tables_t(const SparseArgs& a, const PlanLayout& pl, char* tabs, hipStream_t s) {
+  sparse::tap_table_kernel<DT, WDT, INTERP><<<a.g.n_range, 256, 0, s>>>(
+      a.g, a.y, a.k, a.window, pl.rows_cap, pl.cos_hw, pl.stride, pl.shift, a.offsets, a.weights, tabs);
+  return hipGetLastError();
+}
+
+template <int DT>
+hipError_t launch_tables_dt(const SparseArgs& a, const PlanLayout& pl, char* tabs, hipStream_t s) {
+  const bool lin = a.interp == ROSAR_LINEAR;
+  if (a.w_dtype == ROSAR_C64)
+    return lin ? launch_tables_t<DT, 0, ROSAR_LINEAR>(a, pl, tabs, s) : launch_tables_t<DT, 0, ROSAR_NEAREST>(a, pl, tabs, s);
+  return lin ? launch_tables_t<DT, 1, ROSAR_LINEAR>(a, pl, tabs, s) : launch_tables_t<DT, 1, ROSAR_NEAREST>(a, pl, tabs, s);
+}
+
 }  // namespace
+
+bool plan_shape_supported(int ppl, int waves) {
+#define ROSAR_PCHECK(P, NW) if (ppl == P && waves == NW) return true;
+  ROSAR_PLAN_SHAPES(ROSAR_PCHECK)
+#undef ROSAR_PCHECK
+  return false;
+}
+
+bool sparse_plan_layout(const SparseArgs& a, int ppl, int waves, PlanLayout* out) {
+  const int T = kWave * ppl * waves;
+  const sparse::LdsLayout L = sparse::lds_layout_capped(a.g, a.y, a.k, a.window, a.interp, T);
+  if (!L.dma || L.bytes > sparse::kLdsBudget) return false;
+  const int es = a.y.dtype == ROSAR_C64 ? 8 : 4;
+  const int cpl = 16 / es;
+  const int half_w = a.window / 2;
+  const int nsub = a.interp == ROSAR_LINEAR ? 2 : 1;
+  out->ppl = ppl;
+  out->waves = waves;
+  out->rows_cap = L.rows;
+  out->stride = L.stride;
+  out->cos_hw = L.cos_hw;
+  out->shift = ((a.y.halo - half_w) & (cpl - 1)) + half_w;   // tiles start at multiples of cpl
+  out->lds_bytes = L.bytes + 16;
+  out->row_bytes = sparse::row_table_bytes(a.k * nsub);
+  return true;
+}
+
+hipError_t launch_tap_tables(const SparseArgs& a, const PlanLayout& pl, char* tabs, hipStream_t s) {
+  switch (a.y.dtype) {
+    case ROSAR_C64: return launch_tables_dt<0>(a, pl, tabs, s);
+    case ROSAR_C16_F16: return launch_tables_dt<1>(a, pl, tabs, s);
+    default: return launch_tables_dt<2>(a, pl, tabs, s);
+  }
+}
+
+hipError_t launch_sparse_planned(const SparseArgs& a, const PlanLayout& pl, const char* tabs, hipStream_t s) {
+  switch (a.y.dtype) {
+    case ROSAR_C64: return launch_planned_dt<0>(a, pl, tabs, s);
+    case ROSAR_C16_F16: return launch_planned_dt<1>(a, pl, tabs, s);
+    default: return launch_planned_dt<2>(a, pl, tabs, s);
+  }
+}
 
 Tile default_tile(int32_t n, int32_t y_dtype) {
   // LDS-staged window of 2048-pixel tiles: complex64 samples four pixels per lane over eight

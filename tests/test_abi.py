@@ -228,3 +228,37 @@ def test_torch_complex_gradient_convention():
     loss.backward()
     ref = 2 * z.detach() + (3.0 - 2.0j)
     assert torch.allclose(z.grad, ref)
+
+
+def plan_create(lib, g=None, grid=None, view=None, sset=None, interp=L.NEAREST, tile=None, out=True):
+    g = g or geom()
+    grid = grid or L.PolarGrid(8, 360, 1.0, 0.05)
+    view = view or L.RcView(0x20000, L.C64, 0, 64, 32, 424, 1.0, 0)
+    sset = sset or L.SparseSet(32, 64, 0x30000, 0x40000, L.C64, 0)
+    h = C.c_void_p(0x1234)
+    st = lib.rosar_sparse_plan_create(C.byref(g), C.byref(grid), C.byref(view), C.byref(sset), interp,
+                                      C.byref(tile) if tile is not None else None, None,
+                                      C.byref(h) if out else None)
+    return st, h
+
+
+def test_sparse_plan_validation(lib):
+    st, _ = plan_create(lib, out=False)
+    assert st == L.ROSAR_ERR_INVALID_ARG
+    # the single-call checks apply unchanged (here: k > window), and *out is cleared on failure
+    st, h = plan_create(lib, sset=L.SparseSet(65, 64, 0x30000, 0x40000, L.C64, 0))
+    assert st == L.ROSAR_ERR_INVALID_ARG and h.value is None
+    # band data must be 16-byte aligned for the direct-to-LDS staging
+    st, _ = plan_create(lib, view=L.RcView(0x20008, L.C64, 0, 64, 32, 424, 1.0, 0))
+    assert st == L.ROSAR_ERR_INVALID_ARG and "16-byte" in lib.rosar_last_error().decode()
+    # a plan runs the staged kernel only: variant 1 and shapes outside the instantiated set are refused
+    for t in (L.Tile(1, 4, 8, 0), L.Tile(2, 1, 1, 0), L.Tile(2, 8, 8, 0), L.Tile(2, 3, 4, 0)):
+        st, _ = plan_create(lib, tile=t)
+        assert st == L.ROSAR_ERR_UNSUPPORTED, (t.variant, t.pixels_per_lane, t.waves)
+        assert lib.rosar_last_error().decode() != ""
+    # halo below W/2: the staged kernel would need the guard loop for every edge column
+    st, _ = plan_create(lib, view=L.RcView(0x20000, L.C64, 0, 64, 16, 392, 1.0, 0))
+    assert st == L.ROSAR_ERR_UNSUPPORTED and "halo" in lib.rosar_last_error().decode()
+    view = L.RcView(0x20000, L.C64, 0, 64, 32, 424, 1.0, 0)
+    assert lib.rosar_sparse_plan_run(None, C.byref(view), FAKE, None) == L.ROSAR_ERR_INVALID_ARG
+    lib.rosar_sparse_plan_destroy(None)   # no-op

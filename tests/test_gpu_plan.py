@@ -1,0 +1,168 @@
+"""GPU tests of sparse-filter plans (one filter design, tap tables built once per range row):
+a plan's run equals rosar_sparse_filter_tiled with the same launch shape bit for bit, for every
+planned shape, both interpolations and all storage types; it follows the oracle; it is reusable
+across rotations and replays correctly from a captured HIP graph."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_common import custom_workload, inputs, log, need_gpu, oracle_band, rel_l2, to_dev, torch
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-4
+PLAN_SHAPES = [(4, 8), (8, 4), (4, 4), (2, 8), (2, 4), (8, 2)]
+
+
+def upload(rs, w, x, dtype="c64", scale=1.0):
+    g = w.geometry
+    rc = rs.range_compress(g, to_dev(x.raw), to_dev(x.window), x.l_lo, x.l_count, halo=w.sparse.window // 2,
+                           dtype=dtype, scale=scale)
+    return rc, to_dev(x.offsets), to_dev(x.weights.astype(np.complex64))
+
+
+@pytest.mark.parametrize("interp", ["nearest", "linear"])
+def test_plan_shapes_bit_identical_to_single_call(interp):
+    rs = need_gpu()
+    w, x = inputs("small")
+    rc, off, wts = upload(rs, w, x)
+    ref = oracle.sparse_filter(oracle_band("small"), x.l_lo, w.geometry, w.grid, x.offsets, x.weights,
+                               interp=interp)
+    for shape in PLAN_SHAPES + [None]:
+        log(f"plan small shape={shape} interp={interp}")
+        plan = rs.SparsePlan(w.geometry, w.grid, rc, off, wts, w.sparse.window, interp=interp, tile=shape)
+        img = plan.run(rc).cpu()
+        t = (2,) + (shape if shape is not None else (2, 4))
+        single = rs.sparse_filter(w.geometry, w.grid, rc, off, wts, w.sparse.window, interp=interp, tile=t).cpu()
+        assert torch.equal(img, single), shape
+        assert rel_l2(img.numpy(), ref) <= TOL, shape
+        plan.close()
+
+
+def test_plan_reused_across_rotations():
+    """One plan, two rotations' data: the second image is the first rotated by one azimuth bin."""
+    rs = need_gpu()
+    w, x = inputs("small")
+    rc0, off, wts = upload(rs, w, x)
+    x1 = synth.Inputs(**{**x.__dict__, "raw": np.roll(x.raw, 1, axis=0)})
+    rc1, _, _ = upload(rs, w, x1)
+    log("plan reused across rotations")
+    plan = rs.SparsePlan(w.geometry, w.grid, rc0, off, wts, w.sparse.window)
+    i0 = plan.run(rc0).cpu()
+    out = torch.empty_like(i0, device=rc1.data.device)
+    i1 = plan.run(rc1, out=out).cpu()
+    assert torch.equal(i1, torch.roll(i0, 1, dims=1))
+    plan.close()
+
+
+@pytest.mark.parametrize("dtype", ["f16", "bf16"])
+def test_plan_reduced_precision(dtype):
+    rs = need_gpu()
+    w, x = inputs("small")
+    scale = 2.0 ** -4 if dtype == "f16" else 1.0
+    rc, off, wts = upload(rs, w, x, dtype=dtype, scale=scale)
+    ref = oracle.sparse_filter(oracle_band("small"), x.l_lo, w.geometry, w.grid, x.offsets, x.weights)
+    for shape in ((8, 4), (4, 4), (8, 2)):
+        for wt in (wts, rs.weights_f16(wts)):
+            log(f"plan {dtype} shape={shape} weights={wt.dtype}")
+            plan = rs.SparsePlan(w.geometry, w.grid, rc, off, wt, w.sparse.window, tile=shape)
+            img = plan.run(rc).cpu()
+            single = rs.sparse_filter(w.geometry, w.grid, rc, off, wt, w.sparse.window, tile=(2,) + shape).cpu()
+            assert torch.equal(img, single), (shape, wt.dtype)
+            assert rel_l2(img.numpy(), ref) <= 1e-2, (shape, wt.dtype)
+            plan.close()
+
+
+EDGE = [
+    # name, N, M, rows, r0, r1, K, W
+    ("ragged_n_k5", 100, 128, 9, 0.6, 2.5, 5, 16),
+    ("k100_gt_wave", 300, 256, 6, 0.8, 4.0, 100, 128),
+    ("k1", 64, 64, 3, 0.5, 1.2, 1, 2),
+    ("w_equals_n", 96, 64, 4, 0.5, 1.0, 40, 96),
+    ("many_rows", 128, 64, 300, 0.4, 1.4, 12, 32),
+]
+
+
+@pytest.mark.parametrize("case", EDGE, ids=[c[0] for c in EDGE])
+@pytest.mark.parametrize("interp", ["nearest", "linear"])
+def test_plan_edge_cases(case, interp):
+    rs = need_gpu()
+    name, n, m, rg, r0, r1, k, win = case
+    w = custom_workload(name, 60 + len(name), n, m, rg, r0, r1, k, win)
+    x = synth.make_inputs(w)
+    log(f"plan edge {name} interp={interp}")
+    yb = oracle.range_compress(x.raw, x.window, m)[:, x.l_lo:x.l_lo + x.l_count]
+    ref = oracle.sparse_filter(yb, x.l_lo, w.geometry, w.grid, x.offsets, x.weights, interp=interp)
+    rc, off, wts = upload(rs, w, x)
+    plan = rs.SparsePlan(w.geometry, w.grid, rc, off, wts, win, interp=interp)
+    img = plan.run(rc).cpu()
+    single = rs.sparse_filter(w.geometry, w.grid, rc, off, wts, win, interp=interp, tile=(2, 2, 4)).cpu()
+    assert torch.equal(img, single)
+    assert rel_l2(img.numpy(), ref) <= TOL
+    plan.close()
+
+
+def test_plan_rotation_size():
+    """Rotation workload (1024 x 3600, K = 64 of 256): bit-identical to the default single call,
+    oracle parity on sampled pixels."""
+    rs = need_gpu()
+    w, x = inputs("rotation")
+    rc, off, wts = upload(rs, w, x)
+    log("plan rotation size")
+    plan = rs.SparsePlan(w.geometry, w.grid, rc, off, wts, w.sparse.window)
+    img = plan.run(rc).cpu()
+    single = rs.sparse_filter(w.geometry, w.grid, rc, off, wts, w.sparse.window).cpu()
+    assert torch.equal(img, single)
+    rng = np.random.default_rng(7)
+    rows = rng.integers(0, w.grid.n_range, 300)
+    azs = rng.integers(0, w.grid.n_az, 300)
+    ref = oracle.sparse_filter_at(oracle_band("rotation"), x.l_lo, w.geometry, w.grid, x.offsets, x.weights,
+                                  rows, azs)
+    assert rel_l2(img.numpy()[rows, azs], ref) <= TOL
+    plan.close()
+
+
+def test_plan_layout_mismatch_rejected():
+    rs = need_gpu()
+    w, x = inputs("small")
+    rc, off, wts = upload(rs, w, x)
+    plan = rs.SparsePlan(w.geometry, w.grid, rc, off, wts, w.sparse.window)
+    other = rs.range_compress(w.geometry, to_dev(x.raw), to_dev(x.window), x.l_lo, x.l_count,
+                              halo=w.sparse.window // 2 + 2)
+    log("plan layout mismatch")
+    with pytest.raises(rs.RosarError) as ei:
+        plan.run(other)
+    assert "layout" in str(ei.value)
+    plan.close()
+
+
+def test_plan_graph_replay():
+    rs = need_gpu()
+    w, x = inputs("small")
+    rc, off, wts = upload(rs, w, x)
+    plan = rs.SparsePlan(w.geometry, w.grid, rc, off, wts, w.sparse.window, tile=(4, 4))
+    log("plan graph: eager reference")
+    img = plan.run(rc)
+    torch.cuda.synchronize()
+    ref = img.clone()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(s):
+        plan.run(rc, out=img)             # warm-up on the capture stream
+        torch.cuda.synchronize()
+        with torch.cuda.graph(graph, stream=s):
+            plan.run(rc, out=img)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    for rep in range(3):
+        log(f"plan graph: replay {rep}")
+        img.zero_()
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(img, ref), rep
+        plan.run(rc, out=img)             # eager work between replays
+        torch.cuda.synchronize()
+    plan.close()
