@@ -326,10 +326,13 @@ def main():
     # one filter design for every rotation: the tap tables of its range rows are built once,
     # outside the timed steps (the plan equals the single call with the same shape bit for bit)
     rs.range_compress(g, raw, win, x.l_lo, x.l_count, out=rc)
+    if tile is not None and tile[0] in (0, 2):
+        plan_shape = tile[1:]
+    else:   # the plan autotuner's choice for this layout (times every plan shape on the GPU)
+        plan_shape, _ = rs.sparse_plan_autotune(g, grid, rc, off, wts, w.sparse.window, reps=10, out=img)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    plan = rs.SparsePlan(g, grid, rc, off, wts, w.sparse.window,
-                         tile=tile[1:] if tile is not None and tile[0] in (0, 2) else None)
+    plan = rs.SparsePlan(g, grid, rc, off, wts, w.sparse.window, tile=plan_shape)
     torch.cuda.synchronize()
     ms_plan = 1000 * (time.perf_counter() - t0)
 
@@ -429,6 +432,7 @@ def main():
                       "sparse_filter_single_call": ms_sf_single, "bp_full": ms_bp},
         "sparse_filter_mode": "single call" if a.single_call else "plan (tap tables built once per filter design)",
         "plan_create_ms_wall": ms_plan,
+        "plan_shape_pixels_per_lane_waves": list(plan_shape),
         "hbm_gbps": {"sparse_filter": sf_bytes / (ms_sf * 1e-3) / 1e9,
                      "range_compress": rc_bytes / (ms_rc * 1e-3) / 1e9, "peak": PEAK_HBM_GBPS},
         "roofline": roofline,

@@ -281,6 +281,17 @@ rosar_status rosar_sparse_plan_run(const rosar_sparse_plan* plan, const rosar_rc
                                    rosar_stream stream);
 /* Frees the plan's tables (NULL is a no-op).  No run of the plan may be pending. */
 void rosar_sparse_plan_destroy(rosar_sparse_plan* plan);
+/* Project autotuner for plans: for every plan launch shape the layout admits, builds the tap
+ * tables (in a temporary device buffer) and times `reps` runs on `stream` (image overwritten);
+ * returns the fastest shape as {2, pixels_per_lane, waves} in *best, for
+ * rosar_sparse_plan_create, with its mean run time in microseconds.  Arguments as
+ * rosar_sparse_plan_create plus the image of rosar_sparse_filter.  Synchronises `stream`.
+ * Errors: as rosar_sparse_plan_create; INVALID_ARG for NULL best/best_us or reps outside
+ * [1, 10000]. */
+rosar_status rosar_sparse_plan_autotune(const rosar_geometry* geom, const rosar_polar_grid* grid,
+                                        const rosar_rc_view* rc, const rosar_sparse_set* set,
+                                        rosar_interp interp, void* image, int32_t reps, rosar_tile* best,
+                                        float* best_us, rosar_stream stream);
 
 /* ---------------------------------------------------------------- autotuning
  * Times every supported launch shape of rosar_sparse_filter on the given inputs (the image is

@@ -262,6 +262,24 @@ def _descs(rotations):
     return arr
 
 
+def sparse_plan_autotune(geom, grid, rc: RangeCompressed, offsets, weights, window, interp: str = "nearest",
+                         reps: int = 20, out: torch.Tensor | None = None):
+    """Time every plan launch shape on `rc`; returns ((pixels_per_lane, waves), microseconds),
+    the shape to pass as SparsePlan(tile=...)."""
+    _need_gpu(rc.data)
+    s = _set(offsets, weights, window)
+    dev = rc.data.device
+    if out is None:
+        out = torch.empty((grid.n_range, grid.n_az), dtype=torch.complex64, device=dev)
+    g, p, v = L.geometry(geom), L.polar_grid(grid), rc.view()
+    best = L.Tile()
+    us = C.c_float(0)
+    L.check(L.lib().rosar_sparse_plan_autotune(C.byref(g), C.byref(p), C.byref(v), C.byref(s),
+                                               L.INTERP_CODES[interp], _ptr(out), reps, C.byref(best), C.byref(us),
+                                               _stream(dev)), "rosar_sparse_plan_autotune")
+    return (best.pixels_per_lane, best.waves), float(us.value)
+
+
 class SparsePlan:
     """A sparse-filter plan: one filter design (geometry, grid, offsets, weights, band layout)
     applied to the range-compressed data of many rotations.  The rows' tap tables are built once

@@ -150,6 +150,20 @@ rosar::View make_view(const rosar_rc_view* v) {
   return rosar::View{v->data, v->ld, v->l_lo, v->l_count, v->halo, v->dtype, 1.0f / v->scale};
 }
 
+// Mean time in microseconds of `reps` back-to-back launches on `s`, after one untimed warm-up.
+template <class F>
+hipError_t time_launches(F&& launch, int reps, hipStream_t s, hipEvent_t e0, hipEvent_t e1, float* us) {
+  hipError_t e = launch();
+  if (e == hipSuccess) e = hipEventRecord(e0, s);
+  for (int r = 0; e == hipSuccess && r < reps; ++r) e = launch();
+  if (e == hipSuccess) e = hipEventRecord(e1, s);
+  if (e == hipSuccess) e = hipEventSynchronize(e1);
+  float ms = 0.f;
+  if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+  *us = 1000.f * ms / (float)reps;
+  return e;
+}
+
 #define ROSAR_TRY(expr)              \
   do {                               \
     rosar_status st_ = (expr);       \
@@ -452,6 +466,70 @@ void rosar_sparse_plan_destroy(rosar_sparse_plan* plan) {
   delete plan;
 }
 
+rosar_status rosar_sparse_plan_autotune(const rosar_geometry* geom, const rosar_polar_grid* grid,
+                                        const rosar_rc_view* rc, const rosar_sparse_set* set, rosar_interp interp,
+                                        void* image, int32_t reps, rosar_tile* best, float* best_us,
+                                        rosar_stream stream) {
+  rosar::SparseArgs a{};
+  ROSAR_TRY(sparse_common(geom, grid, rc, set, nullptr, nullptr, interp, image, &a));
+  if (!aligned(rc->data, 16)) return fail(ROSAR_ERR_INVALID_ARG, "rc view data must be 16-byte aligned");
+  if (!best || !best_us) return fail(ROSAR_ERR_INVALID_ARG, "best / best_us is NULL");
+  if (reps < 1 || reps > 10000) return fail(ROSAR_ERR_INVALID_ARG, "reps must be in [1, 10000]");
+  int shapes[16][2];
+  int n_shapes = 0;
+  for (int p : {1, 2, 4, 8})
+    for (int w : {1, 2, 4, 8})
+      if (rosar::plan_shape_supported(p, w)) {
+        shapes[n_shapes][0] = p;
+        shapes[n_shapes][1] = w;
+        ++n_shapes;
+      }
+  bool any = false;
+  rosar::PlanLayout pl{};
+  for (int i = 0; i < n_shapes; ++i) any = any || rosar::sparse_plan_layout(a, shapes[i][0], shapes[i][1], &pl);
+  if (!any)
+    return fail(ROSAR_ERR_UNSUPPORTED,
+                "this band layout cannot use the LDS-staged kernel (halo < W/2, rows not 16-byte aligned, or a "
+                "staged row over the LDS budget)");
+  if (inject_launch_fault()) return fail(ROSAR_ERR_HIP, "injected launch failure (ROSAR_FAULT_INJECT)");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  char* tabs = nullptr;   // row blocks do not depend on the shape: one buffer serves every shape
+  const size_t bytes = (size_t)pl.row_bytes * (size_t)grid->n_range;
+  if (hipMalloc(&tabs, bytes) != hipSuccess)
+    return fail(ROSAR_ERR_NO_MEMORY, "device allocation of the tap tables (%zu bytes) failed", bytes);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  float best_t = 0.f;
+  rosar::Tile best_tile{};
+  bool have = false;
+  for (int i = 0; i < n_shapes; ++i) {
+    const int* sh = shapes[i];
+    if (e != hipSuccess) break;
+    if (!rosar::sparse_plan_layout(a, sh[0], sh[1], &pl)) continue;
+    e = rosar::launch_tap_tables(a, pl, tabs, s);
+    float us = 0.f;
+    if (e == hipSuccess)
+      e = time_launches([&] { return rosar::launch_sparse_planned(a, pl, tabs, s); }, reps, s, e0, e1, &us);
+    if (e == hipSuccess && (!have || us < best_t)) {
+      best_t = us;
+      best_tile = rosar::Tile{2, sh[0], sh[1]};
+      have = true;
+    }
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(s);   // no run may still read the tables
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  (void)hipFree(tabs);
+  if (e != hipSuccess) return from_hip(e, "plan autotune");
+  best->variant = best_tile.variant;
+  best->pixels_per_lane = best_tile.ppl;
+  best->waves = best_tile.waves;
+  best->reserved = 0;
+  *best_us = best_t;
+  return ok();
+}
+
 rosar_status rosar_autotune_sparse_filter(const rosar_geometry* geom, const rosar_polar_grid* grid,
                                           const rosar_rc_view* rc, const rosar_sparse_set* set, void* image,
                                           int32_t reps, rosar_tile* best, float* best_us, rosar_stream stream) {
@@ -473,24 +551,16 @@ rosar_status rosar_autotune_sparse_filter(const rosar_geometry* geom, const rosa
   rosar_status st = ROSAR_OK;
   const int ppls[] = {1, 2, 4, 8};
   const int waves[] = {1, 2, 4, 8};
-  for (int v = 1; v <= 3 && st == ROSAR_OK; ++v) for (int p : ppls) {
+  for (int v = 1; v <= 2 && st == ROSAR_OK; ++v) for (int p : ppls) {
     for (int w : waves) {
       rosar::Tile t{v, p, w};
       if (!rosar::tile_supported(t)) continue;
-      hipError_t e = rosar::launch_sparse_plain(a, t, s);  // warm-up
-      for (int r = 0; e == hipSuccess && r < reps; ++r) {
-        if (r == 0) e = hipEventRecord(e0, s);
-        if (e == hipSuccess) e = rosar::launch_sparse_plain(a, t, s);
-      }
-      if (e == hipSuccess) e = hipEventRecord(e1, s);
-      if (e == hipSuccess) e = hipEventSynchronize(e1);
-      float ms = 0.f;
-      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+      float us = 0.f;
+      const hipError_t e = time_launches([&] { return rosar::launch_sparse_plain(a, t, s); }, reps, s, e0, e1, &us);
       if (e != hipSuccess) {
         st = from_hip(e, "autotune launch");
         break;
       }
-      const float us = 1000.f * ms / (float)reps;
       if (!have || us < best_t) {
         best_t = us;
         best_tile = t;

@@ -262,3 +262,24 @@ def test_sparse_plan_validation(lib):
     view = L.RcView(0x20000, L.C64, 0, 64, 32, 424, 1.0, 0)
     assert lib.rosar_sparse_plan_run(None, C.byref(view), FAKE, None) == L.ROSAR_ERR_INVALID_ARG
     lib.rosar_sparse_plan_destroy(None)   # no-op
+
+
+def test_sparse_plan_autotune_validation(lib):
+    g, grid = geom(), L.PolarGrid(8, 360, 1.0, 0.05)
+    sset = L.SparseSet(32, 64, 0x30000, 0x40000, L.C64, 0)
+    best, us = L.Tile(), C.c_float(0)
+
+    def call(view=None, reps=5, b=True, u=True, image=FAKE):
+        view = view or L.RcView(0x20000, L.C64, 0, 64, 32, 424, 1.0, 0)
+        return lib.rosar_sparse_plan_autotune(C.byref(g), C.byref(grid), C.byref(view), C.byref(sset), L.NEAREST,
+                                              image, reps, C.byref(best) if b else None,
+                                              C.byref(us) if u else None, None)
+
+    assert call(b=False) == L.ROSAR_ERR_INVALID_ARG
+    assert call(u=False) == L.ROSAR_ERR_INVALID_ARG
+    assert call(reps=0) == L.ROSAR_ERR_INVALID_ARG
+    assert call(reps=10001) == L.ROSAR_ERR_INVALID_ARG
+    assert call(image=None) == L.ROSAR_ERR_INVALID_ARG
+    assert call(view=L.RcView(0x20008, L.C64, 0, 64, 32, 424, 1.0, 0)) == L.ROSAR_ERR_INVALID_ARG
+    assert call(view=L.RcView(0x20000, L.C64, 0, 64, 16, 392, 1.0, 0)) == L.ROSAR_ERR_UNSUPPORTED
+    assert lib.rosar_last_error().decode() != ""

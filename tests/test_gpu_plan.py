@@ -123,6 +123,22 @@ def test_plan_rotation_size():
     plan.close()
 
 
+@pytest.mark.parametrize("dtype", ["c64", "bf16"])
+def test_plan_autotune(dtype):
+    """The autotuner returns a plan shape; a plan of that shape equals the single call."""
+    rs = need_gpu()
+    w, x = inputs("rotation")
+    rc, off, wts = upload(rs, w, x, dtype=dtype)
+    log(f"plan autotune {dtype}")
+    shape, us = rs.sparse_plan_autotune(w.geometry, w.grid, rc, off, wts, w.sparse.window, reps=3)
+    assert shape in PLAN_SHAPES and 0.0 < us < 1e5
+    plan = rs.SparsePlan(w.geometry, w.grid, rc, off, wts, w.sparse.window, tile=shape)
+    img = plan.run(rc).cpu()
+    single = rs.sparse_filter(w.geometry, w.grid, rc, off, wts, w.sparse.window, tile=(2,) + shape).cpu()
+    assert torch.equal(img, single)
+    plan.close()
+
+
 def test_plan_layout_mismatch_rejected():
     rs = need_gpu()
     w, x = inputs("small")
