@@ -105,6 +105,60 @@ def cpu_baseline(w, x):
     }
 
 
+_POOL = {}
+
+
+def _pool_init(d):
+    from multiprocessing import shared_memory
+    _POOL.update(d)
+    _POOL["shm"] = shared_memory.SharedMemory(name=d["shm_name"])
+    _POOL["y"] = np.ndarray(d["y_shape"], dtype=np.complex128, buffer=_POOL["shm"].buf)
+
+
+def _pool_rc(chunk):
+    import oracle
+    d = _POOL
+    d["y"][chunk[0]:chunk[1]] = oracle.range_compress(d["raw"][chunk[0]:chunk[1]], d["window"],
+                                                      d["n_fft"])[:, d["l_lo"]:d["l_hi"]]
+    return 0
+
+
+def _pool_sf(rows):
+    import oracle
+    d = _POOL
+    return oracle.sparse_filter(d["y"], d["l_lo"], d["geom"], d["grid"], d["offsets"], d["weights"], rows=rows)
+
+
+def cpu_baseline_all_cores(w, x):
+    """The same FP64 oracle over a pool of spawned worker processes (fresh interpreters that
+    never touch the GPU; at most 8): range compression by pulse chunks into a shared band, then
+    the sparse filter of every range row by row chunks: the whole image, no extrapolation.  The
+    inputs reach the workers before the clock starts."""
+    import multiprocessing as mp
+    from multiprocessing import shared_memory
+    cores = min(8, len(os.sched_getaffinity(0)))
+    g = w.geometry
+    shape = (g.n_pulses, x.l_count)
+    shm = shared_memory.SharedMemory(create=True, size=int(np.prod(shape)) * 16)
+    try:
+        d = dict(raw=x.raw, window=x.window, n_fft=g.n_fft, l_lo=x.l_lo, l_hi=x.l_lo + x.l_count, geom=g,
+                 grid=w.grid, offsets=x.offsets, weights=x.weights, shm_name=shm.name, y_shape=shape)
+        with mp.get_context("spawn").Pool(cores, initializer=_pool_init, initargs=(d,)) as pool:
+            pool.map(abs, range(4 * cores))   # workers up and initialised
+            t0 = time.perf_counter()
+            step = -(-g.n_pulses // (4 * cores))
+            pool.map(_pool_rc, [(i, min(i + step, g.n_pulses)) for i in range(0, g.n_pulses, step)])
+            rstep = -(-w.grid.n_range // (4 * cores))
+            pool.map(_pool_sf, [list(range(i, min(i + rstep, w.grid.n_range)))
+                                for i in range(0, w.grid.n_range, rstep)])
+            t = time.perf_counter() - t0
+    finally:
+        shm.close()
+        shm.unlink()
+    return {"value": w.grid.n_range * w.grid.n_az / t, "unit": "pixels/s", "cores": cores, "kind": "oracle",
+            "sample": f"whole image ({w.grid.n_range} x {w.grid.n_az}) over {cores} worker processes: {t:.2f} s"}
+
+
 def _cpu_model():
     try:
         with open("/proc/cpuinfo") as f:
@@ -114,6 +168,58 @@ def _cpu_model():
     except OSError:
         pass
     return "unknown"
+
+
+def step_latency(torch, step, reps, flush_bytes):
+    """Median ms of one step replayed from a graph, warm (inputs left in the caches by the
+    previous replay) and cold (a write of `flush_bytes`, more than the 256 MB Infinity Cache,
+    between replays)."""
+    scratch = torch.empty(flush_bytes, dtype=torch.uint8, device="cuda")
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    out = {}
+    with torch.cuda.stream(s):
+        step()
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=s):
+            step()
+        for _ in range(3):
+            g.replay()
+        torch.cuda.synchronize()
+        for mode in ("warm", "cold"):
+            ts = []
+            for i in range(reps):
+                if mode == "cold":
+                    scratch.fill_(i & 0xFF)
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(s)
+                g.replay()
+                e1.record(s)
+                torch.cuda.synchronize()
+                ts.append(e0.elapsed_time(e1))
+            out[mode] = float(np.median(ts))
+    torch.cuda.current_stream().wait_stream(s)
+    del scratch
+    return out
+
+
+def copy_bandwidth(torch, nbytes=1 << 30, reps=5):
+    """Achievable HBM bandwidth: a plain device-to-device copy of `nbytes` (read + write)."""
+    src = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del src, dst
+    torch.cuda.empty_cache()
+    return 2 * nbytes / (ms * 1e-3) / 1e9
 
 
 def graph_timer(torch):
@@ -366,6 +472,11 @@ def main():
     print(f"[bench] {a.steps} steps: {ms_step:.4f} ms/step pipelined, {ms_step_serial:.4f} ms/step serial "
           f"(wall {wall:.3f} s)", file=sys.stderr, flush=True)
 
+    lat = step_latency(torch, step, max(20, a.steps), 512 << 20)
+    copy_gbps = copy_bandwidth(torch)
+    print(f"[bench] one step from a graph: {lat['warm']:.4f} ms warm, {lat['cold']:.4f} ms cold; "
+          f"plain copy {copy_gbps:.0f} GB/s", file=sys.stderr, flush=True)
+
     # per-kernel averages: 20 launches per graph
     kreps = max(3, a.steps // 10)
     ms_rc = timed(lambda: rs.range_compress(g, raw, win, x.l_lo, x.l_count, out=rc), kreps, inner=20,
@@ -434,7 +545,10 @@ def main():
         "plan_create_ms_wall": ms_plan,
         "plan_shape_pixels_per_lane_waves": list(plan_shape),
         "hbm_gbps": {"sparse_filter": sf_bytes / (ms_sf * 1e-3) / 1e9,
-                     "range_compress": rc_bytes / (ms_rc * 1e-3) / 1e9, "peak": PEAK_HBM_GBPS},
+                     "range_compress": rc_bytes / (ms_rc * 1e-3) / 1e9, "peak": PEAK_HBM_GBPS,
+                     "plain_copy_achievable": copy_gbps},
+        "single_step_ms": {"warm": lat["warm"], "cold": lat["cold"],
+                           "note": "median of one-step graph replays; cold = 512 MiB written between replays"},
         "roofline": roofline,
         "kernel_source_digest": digest,
         "timing": "HIP-graph replays, events on the launch stream.  value / ms_per_step: the timed steps "
@@ -448,6 +562,7 @@ def main():
         out["rows"] = extras(torch, rs, synth, w, x, dev, rc, off, wts, timed, a.steps)
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, x)
+        out["cpu_baseline"]["all_cores"] = cpu_baseline_all_cores(w, x)
     print(json.dumps(out))
 
 
