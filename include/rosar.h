@@ -255,7 +255,17 @@ rosar_status rosar_batch_autotune(const rosar_rotation_desc* descs, int32_t n, i
  * once, the tap table of every range row -- the float64 bin of each tap (eq. 2, eq. 40), its
  * packed weight and its offset in the LDS-staged window -- into device memory it owns; each
  * run then copies a row's table into LDS instead of building it.  A run computes the same
- * image, bit for bit, as rosar_sparse_filter_tiled with the same launch shape (variant 2). */
+ * image, bit for bit, as rosar_sparse_filter_tiled with the same launch shape (variant 2).
+ *
+ * Variant 3 evaluates the same sum as an azimuth fast convolution.  Under the rotation symmetry
+ * the taps of a range row that read bin row l form a sparse kernel over azimuth offsets, and
+ * the row of the image is the sum over l of the circular correlation of band row l with it.
+ * A run takes the DFT of every band row over the N pulses, and per range row the DFT of each
+ * sparse kernel, multiplies and accumulates, and transforms back (mixed-radix FFTs of length N
+ * in LDS, float32).  It equals the direct sum up to float32 rounding, not bit for bit.  It
+ * needs N = 2^a 3^b 5^c <= 8192 and the taps of a range row on at most 32 bin rows.  The plan
+ * owns the band-row spectra (l_count x N x 8 bytes), a twiddle table and per-row tap lists, so
+ * runs of one such plan must not overlap (runs on one stream are ordered). */
 typedef struct rosar_sparse_plan rosar_sparse_plan;
 
 /* Validates the arguments as rosar_sparse_filter does and enqueues the table kernel on
@@ -264,11 +274,13 @@ typedef struct rosar_sparse_plan rosar_sparse_plan;
  * but is not read.  offsets and weights are read by the table kernel only: change them and
  * create a new plan.  tile: NULL or {0 or 2, pixels_per_lane, waves} with pixels_per_lane x
  * waves in {4x8, 8x4, 4x4, 2x8, 2x4, 8x2} (NULL = the rosar_sparse_filter default, or 2x4 where
- * that default is 1 pixel per lane, i.e. n_az <= 1024).  No
+ * that default is 1 pixel per lane, i.e. n_az <= 1024), or {3, 0, 0} for the azimuth fast
+ * convolution (which uploads its twiddle table and synchronises `stream`).  No
  * angle/phase errors (those change per rotation: use rosar_sparse_filter).
- * Errors: INVALID_ARG as rosar_sparse_filter; UNSUPPORTED for another shape, or a layout the
+ * Errors: INVALID_ARG as rosar_sparse_filter; UNSUPPORTED for another shape, a layout the
  * LDS-staged kernel cannot take (halo < W/2, rows not 16-byte aligned, one staged row over the
- * LDS budget); NO_MEMORY if the table allocation ((K or 2K) x 24 bytes + 16 per row, rounded
+ * LDS budget), or for variant 3 an N with another prime factor, N > 8192 or more than 32 bin
+ * rows per range row; NO_MEMORY if the table allocation ((K or 2K) x 24 bytes + 16 per row, rounded
  * to 16) fails. */
 rosar_status rosar_sparse_plan_create(const rosar_geometry* geom, const rosar_polar_grid* grid,
                                       const rosar_rc_view* rc, const rosar_sparse_set* set,
@@ -283,7 +295,8 @@ rosar_status rosar_sparse_plan_run(const rosar_sparse_plan* plan, const rosar_rc
 void rosar_sparse_plan_destroy(rosar_sparse_plan* plan);
 /* Project autotuner for plans: for every plan launch shape the layout admits, builds the tap
  * tables (in a temporary device buffer) and times `reps` runs on `stream` (image overwritten);
- * returns the fastest shape as {2, pixels_per_lane, waves} in *best, for
+ * times the azimuth fast convolution too where the layout admits it, and returns the fastest
+ * as {2, pixels_per_lane, waves} or {3, 0, 0} in *best, for
  * rosar_sparse_plan_create, with its mean run time in microseconds.  Arguments as
  * rosar_sparse_plan_create plus the image of rosar_sparse_filter.  Synchronises `stream`.
  * Errors: as rosar_sparse_plan_create; INVALID_ARG for NULL best/best_us or reps outside

@@ -264,8 +264,9 @@ def _descs(rotations):
 
 def sparse_plan_autotune(geom, grid, rc: RangeCompressed, offsets, weights, window, interp: str = "nearest",
                          reps: int = 20, out: torch.Tensor | None = None):
-    """Time every plan launch shape on `rc`; returns ((pixels_per_lane, waves), microseconds),
-    the shape to pass as SparsePlan(tile=...)."""
+    """Time every plan launch shape on `rc`, and the azimuth fast convolution where the layout
+    admits it; returns (tile, microseconds) with tile = (pixels_per_lane, waves) or "fastconv",
+    to pass as SparsePlan(tile=...)."""
     _need_gpu(rc.data)
     s = _set(offsets, weights, window)
     dev = rc.data.device
@@ -277,22 +278,31 @@ def sparse_plan_autotune(geom, grid, rc: RangeCompressed, offsets, weights, wind
     L.check(L.lib().rosar_sparse_plan_autotune(C.byref(g), C.byref(p), C.byref(v), C.byref(s),
                                                L.INTERP_CODES[interp], _ptr(out), reps, C.byref(best), C.byref(us),
                                                _stream(dev)), "rosar_sparse_plan_autotune")
+    if best.variant == 3:
+        return "fastconv", float(us.value)
     return (best.pixels_per_lane, best.waves), float(us.value)
 
 
 class SparsePlan:
     """A sparse-filter plan: one filter design (geometry, grid, offsets, weights, band layout)
-    applied to the range-compressed data of many rotations.  The rows' tap tables are built once
-    on the device; each run() computes the image rosar_sparse_filter gives with the same launch
-    shape.  `layout` is a RangeCompressed whose band layout every run must share; the offsets
-    and weights are read when the plan is created."""
+    applied to the range-compressed data of many rotations.  `layout` is a RangeCompressed whose
+    band layout every run must share; the offsets and weights are read when the plan is created.
+
+    tile = (pixels_per_lane, waves) or None: the rows' tap tables are built once on the device
+    and each run() computes the image rosar_sparse_filter gives with that launch shape, bit for
+    bit.  tile = "fastconv": the same sum as an azimuth fast convolution (FFTs of the band rows
+    and of each row's sparse kernels); equal to the direct sum up to float32 rounding.  Runs of
+    one fast-convolution plan share its spectrum buffer: do not overlap them."""
 
     def __init__(self, geom, grid, layout: RangeCompressed, offsets, weights, window, interp: str = "nearest",
-                 tile: tuple[int, int] | None = None):
+                 tile: tuple[int, int] | str | None = None):
         _need_gpu(layout.data)
         s = _set(offsets, weights, window)
         g, p, v = L.geometry(geom), L.polar_grid(grid), layout.view()
-        t = None if tile is None else L.Tile(2, tile[0], tile[1], 0)
+        if tile == "fastconv":
+            t = L.Tile(3, 0, 0, 0)
+        else:
+            t = None if tile is None else L.Tile(2, tile[0], tile[1], 0)
         h = C.c_void_p()
         L.check(L.lib().rosar_sparse_plan_create(C.byref(g), C.byref(p), C.byref(v), C.byref(s),
                                                  L.INTERP_CODES[interp], None if t is None else C.byref(t),

@@ -369,11 +369,54 @@ rosar_status rosar_sparse_filter_backward(const rosar_geometry* geom, const rosa
 
 struct rosar_sparse_plan {
   rosar::SparseArgs a{};      // geometry, band layout (data NULL), set, interp
+  int variant = 2;            // 2: LDS-staged direct sum; 3: azimuth fast convolution
   rosar::PlanLayout layout{};
+  rosar::FcLayout fc{};
   rosar_rc_view view{};       // layout fields every run must match
-  char* tabs = nullptr;       // n_range row blocks of layout.row_bytes
+  char* tabs = nullptr;       // n_range row blocks (layout.row_bytes or fc.row_bytes)
+  float2* tw = nullptr;       // fast convolution: twiddle table [N]
+  float2* spec = nullptr;     // fast convolution: band-row spectra [l_count][N]
   int device = -1;
 };
+
+namespace {
+
+void free_plan(rosar_sparse_plan* p) {
+  if (!p) return;
+  (void)hipFree(p->tabs);
+  (void)hipFree(p->tw);
+  (void)hipFree(p->spec);
+  delete p;
+}
+
+// Device memory of a fast-convolution plan: tables (+ a flag word), twiddles, spectra; the
+// twiddles uploaded, the tables built on `s`.  Fails with UNSUPPORTED if a range row's taps
+// span more bin rows than the row mask holds (reported by the table kernel).
+rosar_status fc_prepare(const rosar::SparseArgs& a, const rosar::FcLayout& fc, hipStream_t s, char** tabs, float2** tw,
+                        float2** spec) {
+  const size_t tab_bytes = (size_t)fc.row_bytes * (size_t)a.g.n_range;
+  const size_t tw_bytes = (size_t)a.g.n * sizeof(float2);
+  if (hipMalloc(tabs, tab_bytes + 256) != hipSuccess || hipMalloc(tw, tw_bytes) != hipSuccess ||
+      hipMalloc(spec, rosar::fc_spectrum_bytes(a)) != hipSuccess)
+    return fail(ROSAR_ERR_NO_MEMORY, "device allocation of the fast-convolution plan failed");
+  float2* host_tw = static_cast<float2*>(malloc(tw_bytes));
+  if (!host_tw) return fail(ROSAR_ERR_NO_MEMORY, "host allocation failed");
+  rosar::fc_twiddles(a.g.n, host_tw);
+  int* bad = reinterpret_cast<int*>(*tabs + tab_bytes);
+  int bad_host = 0;
+  hipError_t e = hipMemcpyAsync(*tw, host_tw, tw_bytes, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(bad, &bad_host, sizeof(int), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = rosar::launch_fc_tables(a, fc, *tabs, bad, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(&bad_host, bad, sizeof(int), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  free(host_tw);
+  if (e != hipSuccess) return from_hip(e, "fast-convolution plan set-up");
+  if (bad_host)
+    return fail(ROSAR_ERR_UNSUPPORTED, "a range row's taps span more bin rows than the fast convolution handles (32)");
+  return ROSAR_OK;
+}
+
+}  // namespace
 
 extern "C" {
 
@@ -392,9 +435,39 @@ rosar_status rosar_sparse_plan_create(const rosar_geometry* geom, const rosar_po
   rosar::Tile t = rosar::default_tile(geom->n_pulses, rc->dtype);
   // small images default to 1 pixel per lane, which has no planned instantiation: take 2 x 4
   if (!rosar::plan_shape_supported(t.ppl, t.waves)) t = rosar::Tile{2, 2, 4};
+  if (tile && tile->variant == 3) {
+    rosar::FcLayout fc{};
+    if (!rosar::fc_layout(a, &fc))
+      return fail(ROSAR_ERR_UNSUPPORTED,
+                  "the azimuth fast convolution needs N = 2^a 3^b 5^c <= 8192 and at most 32 bin rows per range row");
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) return fail(ROSAR_ERR_HIP, "cannot query the current device");
+    auto* p = new (std::nothrow) rosar_sparse_plan();
+    if (!p) return fail(ROSAR_ERR_NO_MEMORY, "host allocation failed");
+    p->a = a;
+    p->variant = 3;
+    p->fc = fc;
+    p->view = *rc;
+    p->view.data = nullptr;
+    p->device = dev;
+    if (inject_launch_fault()) {
+      free_plan(p);
+      return fail(ROSAR_ERR_HIP, "injected launch failure (ROSAR_FAULT_INJECT)");
+    }
+    const rosar_status st = fc_prepare(a, fc, reinterpret_cast<hipStream_t>(stream), &p->tabs, &p->tw, &p->spec);
+    if (st != ROSAR_OK) {
+      free_plan(p);
+      return st;
+    }
+    p->a.y.data = nullptr;
+    p->a.image = nullptr;
+    *out = p;
+    return ROSAR_OK;
+  }
   if (tile && (tile->pixels_per_lane || tile->waves || tile->variant)) {
     if (tile->variant != 0 && tile->variant != 2)
-      return fail(ROSAR_ERR_UNSUPPORTED, "a plan runs the LDS-staged variant (2), not %d", tile->variant);
+      return fail(ROSAR_ERR_UNSUPPORTED, "a plan runs the LDS-staged variant (2) or the fast convolution (3), not %d",
+                  tile->variant);
     t.ppl = tile->pixels_per_lane ? tile->pixels_per_lane : t.ppl;
     t.waves = tile->waves ? tile->waves : t.waves;
   }
@@ -456,15 +529,13 @@ rosar_status rosar_sparse_plan_run(const rosar_sparse_plan* plan, const rosar_rc
   rosar::SparseArgs a = plan->a;
   a.y.data = rc->data;
   a.image = reinterpret_cast<float2*>(image);
-  return from_hip(rosar::launch_sparse_planned(a, plan->layout, plan->tabs, reinterpret_cast<hipStream_t>(stream)),
-                  "sparse plan launch");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  if (plan->variant == 3)
+    return from_hip(rosar::launch_fc_run(a, plan->fc, plan->tabs, plan->tw, plan->spec, s), "fast convolution launch");
+  return from_hip(rosar::launch_sparse_planned(a, plan->layout, plan->tabs, s), "sparse plan launch");
 }
 
-void rosar_sparse_plan_destroy(rosar_sparse_plan* plan) {
-  if (!plan) return;
-  (void)hipFree(plan->tabs);
-  delete plan;
-}
+void rosar_sparse_plan_destroy(rosar_sparse_plan* plan) { free_plan(plan); }
 
 rosar_status rosar_sparse_plan_autotune(const rosar_geometry* geom, const rosar_polar_grid* grid,
                                         const rosar_rc_view* rc, const rosar_sparse_set* set, rosar_interp interp,
@@ -518,10 +589,35 @@ rosar_status rosar_sparse_plan_autotune(const rosar_geometry* geom, const rosar_
     }
   }
   if (e == hipSuccess) e = hipStreamSynchronize(s);   // no run may still read the tables
+  (void)hipFree(tabs);
+  rosar_status st = e == hipSuccess ? ROSAR_OK : from_hip(e, "plan autotune");
+  rosar::FcLayout fc{};
+  if (st == ROSAR_OK && rosar::fc_layout(a, &fc)) {   // the azimuth fast convolution
+    char* ftabs = nullptr;
+    float2* tw = nullptr;
+    float2* spec = nullptr;
+    const rosar_status fst = fc_prepare(a, fc, s, &ftabs, &tw, &spec);
+    if (fst == ROSAR_OK) {
+      float us = 0.f;
+      e = time_launches([&] { return rosar::launch_fc_run(a, fc, ftabs, tw, spec, s); }, reps, s, e0, e1, &us);
+      if (e == hipSuccess) e = hipStreamSynchronize(s);
+      if (e != hipSuccess) {
+        st = from_hip(e, "plan autotune");
+      } else if (!have || us < best_t) {
+        best_t = us;
+        best_tile = rosar::Tile{3, 0, 0};
+        have = true;
+      }
+    } else if (fst != ROSAR_ERR_UNSUPPORTED) {
+      st = fst;
+    }
+    (void)hipFree(ftabs);
+    (void)hipFree(tw);
+    (void)hipFree(spec);
+  }
   if (e0) (void)hipEventDestroy(e0);
   if (e1) (void)hipEventDestroy(e1);
-  (void)hipFree(tabs);
-  if (e != hipSuccess) return from_hip(e, "plan autotune");
+  if (st != ROSAR_OK) return st;
   best->variant = best_tile.variant;
   best->pixels_per_lane = best_tile.ppl;
   best->waves = best_tile.waves;

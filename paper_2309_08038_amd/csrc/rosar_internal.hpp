@@ -86,6 +86,28 @@ bool sparse_plan_layout(const SparseArgs& a, int ppl, int waves, PlanLayout* out
 hipError_t launch_tap_tables(const SparseArgs& a, const PlanLayout& pl, char* tabs, hipStream_t s);
 hipError_t launch_sparse_planned(const SparseArgs& a, const PlanLayout& pl, const char* tabs, hipStream_t s);
 
+// Azimuth fast convolution (plans of variant 3): the radix sequence of the azimuth FFT length,
+// the per-row tap-list layout, the table kernel and the two kernels of a run (band-row spectra,
+// then one workgroup per range row).
+constexpr int kFftMaxPasses = 16;
+struct FftFactors {
+  int32_t n, n_pass;
+  int32_t radix[kFftMaxPasses];
+};
+struct FcLayout {
+  FftFactors f;
+  int ne, row_bytes;   // entries per row (K or 2K) and bytes of a row's block
+  int rows_cap;        // bin rows one range row may touch (at most 32)
+  double cos_hw;
+  size_t lds_bytes;
+};
+bool fc_layout(const SparseArgs& a, FcLayout* out);
+size_t fc_spectrum_bytes(const SparseArgs& a);
+void fc_twiddles(int n, float2* host_tw);
+hipError_t launch_fc_tables(const SparseArgs& a, const FcLayout& L, char* tabs, int* bad, hipStream_t s);
+hipError_t launch_fc_run(const SparseArgs& a, const FcLayout& L, const char* tabs, const float2* tw, float2* spec,
+                         hipStream_t s);
+
 // Tile chosen when the caller leaves it to the library.
 Tile default_tile(int32_t n, int32_t y_dtype);
 bool tile_supported(const Tile& t);

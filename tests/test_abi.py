@@ -283,3 +283,14 @@ def test_sparse_plan_autotune_validation(lib):
     assert call(view=L.RcView(0x20008, L.C64, 0, 64, 32, 424, 1.0, 0)) == L.ROSAR_ERR_INVALID_ARG
     assert call(view=L.RcView(0x20000, L.C64, 0, 64, 16, 392, 1.0, 0)) == L.ROSAR_ERR_UNSUPPORTED
     assert lib.rosar_last_error().decode() != ""
+
+
+def test_fastconv_plan_rejections(lib):
+    """The azimuth fast convolution needs N = 2^a 3^b 5^c <= 8192 (checked before any device work)."""
+    for n in (98, 9000, 7 * 64):
+        g = geom(n_pulses=n)
+        grid = L.PolarGrid(8, n, 1.0, 0.05)
+        view = L.RcView(0x20000, L.C64, 0, 64, 32, n + 64, 1.0, 0)
+        st, _ = plan_create(lib, g=g, grid=grid, view=view, tile=L.Tile(3, 0, 0, 0))
+        assert st == L.ROSAR_ERR_UNSUPPORTED, n
+        assert "2^a 3^b 5^c" in lib.rosar_last_error().decode()

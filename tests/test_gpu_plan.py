@@ -131,11 +131,16 @@ def test_plan_autotune(dtype):
     rc, off, wts = upload(rs, w, x, dtype=dtype)
     log(f"plan autotune {dtype}")
     shape, us = rs.sparse_plan_autotune(w.geometry, w.grid, rc, off, wts, w.sparse.window, reps=3)
-    assert shape in PLAN_SHAPES and 0.0 < us < 1e5
+    log(f"plan autotune {dtype}: {shape} {us:.1f} us")
+    assert (shape in PLAN_SHAPES or shape == "fastconv") and 0.0 < us < 1e5
     plan = rs.SparsePlan(w.geometry, w.grid, rc, off, wts, w.sparse.window, tile=shape)
     img = plan.run(rc).cpu()
-    single = rs.sparse_filter(w.geometry, w.grid, rc, off, wts, w.sparse.window, tile=(2,) + shape).cpu()
-    assert torch.equal(img, single)
+    if shape == "fastconv":
+        single = rs.sparse_filter(w.geometry, w.grid, rc, off, wts, w.sparse.window).cpu()
+        assert rel_l2(img.numpy(), single.numpy()) <= 1e-5
+    else:
+        single = rs.sparse_filter(w.geometry, w.grid, rc, off, wts, w.sparse.window, tile=(2,) + shape).cpu()
+        assert torch.equal(img, single)
     plan.close()
 
 
@@ -180,5 +185,112 @@ def test_plan_graph_replay():
         torch.cuda.synchronize()
         assert torch.equal(img, ref), rep
         plan.run(rc, out=img)             # eager work between replays
+        torch.cuda.synchronize()
+    plan.close()
+
+
+# ------------------------------------------------------------------ azimuth fast convolution
+# Same sum as the direct filter, evaluated with FFTs along azimuth: equal to the oracle within
+# the float32 bar (1e-4 relative L2), and to the direct filter within 1e-5.
+
+@pytest.mark.parametrize("interp", ["nearest", "linear"])
+def test_fastconv_small(interp):
+    rs = need_gpu()
+    w, x = inputs("small")
+    rc, off, wts = upload(rs, w, x)
+    ref = oracle.sparse_filter(oracle_band("small"), x.l_lo, w.geometry, w.grid, x.offsets, x.weights,
+                               interp=interp)
+    log(f"fastconv small interp={interp}")
+    plan = rs.SparsePlan(w.geometry, w.grid, rc, off, wts, w.sparse.window, interp=interp, tile="fastconv")
+    img = plan.run(rc).cpu().numpy()
+    assert rel_l2(img, ref) <= TOL
+    direct = rs.sparse_filter(w.geometry, w.grid, rc, off, wts, w.sparse.window, interp=interp).cpu().numpy()
+    assert rel_l2(img, direct) <= 1e-5
+    plan.close()
+
+
+@pytest.mark.parametrize("case", EDGE, ids=[c[0] for c in EDGE])
+@pytest.mark.parametrize("interp", ["nearest", "linear"])
+def test_fastconv_edge_cases(case, interp):
+    rs = need_gpu()
+    name, n, m, rg, r0, r1, k, win = case
+    w = custom_workload(name, 60 + len(name), n, m, rg, r0, r1, k, win)
+    x = synth.make_inputs(w)
+    log(f"fastconv edge {name} interp={interp}")
+    yb = oracle.range_compress(x.raw, x.window, m)[:, x.l_lo:x.l_lo + x.l_count]
+    ref = oracle.sparse_filter(yb, x.l_lo, w.geometry, w.grid, x.offsets, x.weights, interp=interp)
+    rc, off, wts = upload(rs, w, x)
+    plan = rs.SparsePlan(w.geometry, w.grid, rc, off, wts, win, interp=interp, tile="fastconv")
+    img = plan.run(rc).cpu().numpy()
+    assert rel_l2(img, ref) <= TOL
+    plan.close()
+
+
+def test_fastconv_rotation_size():
+    """Rotation workload (N = 3600 = 2^4 3^2 5^2): oracle parity on sampled pixels and the whole
+    image against the direct filter."""
+    rs = need_gpu()
+    w, x = inputs("rotation")
+    rc, off, wts = upload(rs, w, x)
+    log("fastconv rotation size")
+    plan = rs.SparsePlan(w.geometry, w.grid, rc, off, wts, w.sparse.window, tile="fastconv")
+    img = plan.run(rc).cpu().numpy()
+    direct = rs.sparse_filter(w.geometry, w.grid, rc, off, wts, w.sparse.window).cpu().numpy()
+    assert rel_l2(img, direct) <= 1e-5
+    rng = np.random.default_rng(11)
+    rows = rng.integers(0, w.grid.n_range, 300)
+    azs = rng.integers(0, w.grid.n_az, 300)
+    ref = oracle.sparse_filter_at(oracle_band("rotation"), x.l_lo, w.geometry, w.grid, x.offsets, x.weights,
+                                  rows, azs)
+    assert rel_l2(img[rows, azs], ref) <= TOL
+    plan.close()
+
+
+@pytest.mark.parametrize("dtype", ["f16", "bf16"])
+def test_fastconv_reduced_precision(dtype):
+    rs = need_gpu()
+    w, x = inputs("small")
+    scale = 2.0 ** -4 if dtype == "f16" else 1.0
+    rc, off, wts = upload(rs, w, x, dtype=dtype, scale=scale)
+    ref = oracle.sparse_filter(oracle_band("small"), x.l_lo, w.geometry, w.grid, x.offsets, x.weights)
+    for wt in (wts, rs.weights_f16(wts)):
+        log(f"fastconv {dtype} weights={wt.dtype}")
+        plan = rs.SparsePlan(w.geometry, w.grid, rc, off, wt, w.sparse.window, tile="fastconv")
+        img = plan.run(rc).cpu().numpy()
+        assert rel_l2(img, ref) <= 1e-2, wt.dtype
+        # the direct 16-bit path also rounds the weights to the storage type (v_dot2 operands);
+        # the fast convolution applies them in float32, so it is at least as close to the oracle
+        direct = rs.sparse_filter(w.geometry, w.grid, rc, off, wt, w.sparse.window).cpu().numpy()
+        assert rel_l2(img, ref) <= rel_l2(direct, ref) + 1e-5, wt.dtype
+        plan.close()
+
+
+def test_fastconv_graph_replay():
+    rs = need_gpu()
+    w, x = inputs("small")
+    rc, off, wts = upload(rs, w, x)
+    plan = rs.SparsePlan(w.geometry, w.grid, rc, off, wts, w.sparse.window, tile="fastconv")
+    log("fastconv graph: eager reference")
+    img = plan.run(rc)
+    torch.cuda.synchronize()
+    ref = img.clone()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(s):
+        plan.run(rc, out=img)
+        torch.cuda.synchronize()
+        with torch.cuda.graph(graph, stream=s):
+            plan.run(rc, out=img)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    for rep in range(3):
+        log(f"fastconv graph: replay {rep}")
+        img.zero_()
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(img, ref), rep
+        plan.run(rc, out=img)
         torch.cuda.synchronize()
     plan.close()
