@@ -8,6 +8,8 @@
 #include <cstdlib>
 #include <cstring>
 #include <string>
+#include <vector>
+#include <algorithm>
 
 #include "rosar_internal.hpp"
 
@@ -376,6 +378,7 @@ struct rosar_sparse_plan {
   char* tabs = nullptr;       // n_range row blocks (layout.row_bytes or fc.row_bytes)
   float2* tw = nullptr;       // fast convolution: twiddle table [N]
   float2* spec = nullptr;     // fast convolution: band-row spectra [l_count][N]
+  float2* gspec = nullptr;    // fast convolution: kernel spectra [pairs][N]
   int device = -1;
 };
 
@@ -386,33 +389,57 @@ void free_plan(rosar_sparse_plan* p) {
   (void)hipFree(p->tabs);
   (void)hipFree(p->tw);
   (void)hipFree(p->spec);
+  (void)hipFree(p->gspec);
   delete p;
 }
 
-// Device memory of a fast-convolution plan: tables (+ a flag word), twiddles, spectra; the
-// twiddles uploaded, the tables built on `s`.  Fails with UNSUPPORTED if a range row's taps
-// span more bin rows than the row mask holds (reported by the table kernel).
+// Device memory of a fast-convolution plan: tables (+ a flag word), twiddles, band-row spectra
+// and the kernel spectra of every (range row, bin row) pair.  Uploads the twiddles, builds the
+// tap lists, numbers the pairs on the host (row by row, bin rows in mask order; the header's
+// last word gets the row's first pair) and builds their spectra, all on `s`, which it
+// synchronises.  UNSUPPORTED if a range row's taps span more bin rows than the row mask holds.
 rosar_status fc_prepare(const rosar::SparseArgs& a, const rosar::FcLayout& fc, hipStream_t s, char** tabs, float2** tw,
-                        float2** spec) {
-  const size_t tab_bytes = (size_t)fc.row_bytes * (size_t)a.g.n_range;
+                        float2** spec, float2** gspec) {
+  const int n_range = a.g.n_range;
+  const size_t tab_bytes = (size_t)fc.row_bytes * (size_t)n_range;
   const size_t tw_bytes = (size_t)a.g.n * sizeof(float2);
   if (hipMalloc(tabs, tab_bytes + 256) != hipSuccess || hipMalloc(tw, tw_bytes) != hipSuccess ||
       hipMalloc(spec, rosar::fc_spectrum_bytes(a)) != hipSuccess)
     return fail(ROSAR_ERR_NO_MEMORY, "device allocation of the fast-convolution plan failed");
-  float2* host_tw = static_cast<float2*>(malloc(tw_bytes));
-  if (!host_tw) return fail(ROSAR_ERR_NO_MEMORY, "host allocation failed");
-  rosar::fc_twiddles(a.g.n, host_tw);
+  std::vector<float2> host_tw(a.g.n);
+  rosar::fc_twiddles(a.g.n, host_tw.data());
   int* bad = reinterpret_cast<int*>(*tabs + tab_bytes);
   int bad_host = 0;
-  hipError_t e = hipMemcpyAsync(*tw, host_tw, tw_bytes, hipMemcpyHostToDevice, s);
+  std::vector<int4> hdr(n_range);
+  hipError_t e = hipMemcpyAsync(*tw, host_tw.data(), tw_bytes, hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = hipMemcpyAsync(bad, &bad_host, sizeof(int), hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = rosar::launch_fc_tables(a, fc, *tabs, bad, s);
   if (e == hipSuccess) e = hipMemcpyAsync(&bad_host, bad, sizeof(int), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess)
+    e = hipMemcpy2DAsync(hdr.data(), sizeof(int4), *tabs, fc.row_bytes, sizeof(int4), n_range, hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
-  free(host_tw);
   if (e != hipSuccess) return from_hip(e, "fast-convolution plan set-up");
   if (bad_host)
     return fail(ROSAR_ERR_UNSUPPORTED, "a range row's taps span more bin rows than the fast convolution handles (32)");
+  std::vector<int2> pairs;
+  for (int r = 0; r < n_range; ++r) {
+    hdr[r].w = (int)pairs.size();
+    for (unsigned m = (unsigned)hdr[r].y; m; m &= m - 1u) pairs.push_back(make_int2(r, __builtin_ctz(m)));
+  }
+  const size_t n_pairs = pairs.size();
+  int2* d_pairs = nullptr;
+  if (hipMalloc(gspec, std::max<size_t>(n_pairs, 1) * tw_bytes) != hipSuccess ||
+      hipMalloc(&d_pairs, std::max<size_t>(n_pairs, 1) * sizeof(int2)) != hipSuccess) {
+    (void)hipFree(d_pairs);
+    return fail(ROSAR_ERR_NO_MEMORY, "device allocation of the kernel spectra (%zu pairs) failed", n_pairs);
+  }
+  e = hipMemcpy2DAsync(*tabs, fc.row_bytes, hdr.data(), sizeof(int4), sizeof(int4), n_range, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess && n_pairs)
+    e = hipMemcpyAsync(d_pairs, pairs.data(), n_pairs * sizeof(int2), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = rosar::launch_fc_kernel_spectra(fc, *tabs, d_pairs, (int)n_pairs, *tw, *gspec, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  (void)hipFree(d_pairs);
+  if (e != hipSuccess) return from_hip(e, "fast-convolution kernel spectra");
   return ROSAR_OK;
 }
 
@@ -454,7 +481,8 @@ rosar_status rosar_sparse_plan_create(const rosar_geometry* geom, const rosar_po
       free_plan(p);
       return fail(ROSAR_ERR_HIP, "injected launch failure (ROSAR_FAULT_INJECT)");
     }
-    const rosar_status st = fc_prepare(a, fc, reinterpret_cast<hipStream_t>(stream), &p->tabs, &p->tw, &p->spec);
+    const rosar_status st =
+        fc_prepare(a, fc, reinterpret_cast<hipStream_t>(stream), &p->tabs, &p->tw, &p->spec, &p->gspec);
     if (st != ROSAR_OK) {
       free_plan(p);
       return st;
@@ -531,7 +559,8 @@ rosar_status rosar_sparse_plan_run(const rosar_sparse_plan* plan, const rosar_rc
   a.image = reinterpret_cast<float2*>(image);
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   if (plan->variant == 3)
-    return from_hip(rosar::launch_fc_run(a, plan->fc, plan->tabs, plan->tw, plan->spec, s), "fast convolution launch");
+    return from_hip(rosar::launch_fc_run(a, plan->fc, plan->tabs, plan->tw, plan->spec, plan->gspec, s),
+                    "fast convolution launch");
   return from_hip(rosar::launch_sparse_planned(a, plan->layout, plan->tabs, s), "sparse plan launch");
 }
 
@@ -596,10 +625,11 @@ rosar_status rosar_sparse_plan_autotune(const rosar_geometry* geom, const rosar_
     char* ftabs = nullptr;
     float2* tw = nullptr;
     float2* spec = nullptr;
-    const rosar_status fst = fc_prepare(a, fc, s, &ftabs, &tw, &spec);
+    float2* gspec = nullptr;
+    const rosar_status fst = fc_prepare(a, fc, s, &ftabs, &tw, &spec, &gspec);
     if (fst == ROSAR_OK) {
       float us = 0.f;
-      e = time_launches([&] { return rosar::launch_fc_run(a, fc, ftabs, tw, spec, s); }, reps, s, e0, e1, &us);
+      e = time_launches([&] { return rosar::launch_fc_run(a, fc, ftabs, tw, spec, gspec, s); }, reps, s, e0, e1, &us);
       if (e == hipSuccess) e = hipStreamSynchronize(s);
       if (e != hipSuccess) {
         st = from_hip(e, "plan autotune");
@@ -614,6 +644,7 @@ rosar_status rosar_sparse_plan_autotune(const rosar_geometry* geom, const rosar_
     (void)hipFree(ftabs);
     (void)hipFree(tw);
     (void)hipFree(spec);
+    (void)hipFree(gspec);
   }
   if (e0) (void)hipEventDestroy(e0);
   if (e1) (void)hipEventDestroy(e1);

@@ -6,11 +6,12 @@
 // a circular correlation along azimuth.  With Yhat_l the DFT of band row l and
 // G_{r,l}[m] = sum_o g_{r,l}[o] exp(+j 2 pi o m / N),
 //   I[r, .] = IDFT( sum_l G_{r,l} * Yhat_l ).
-// A run computes Yhat for every band row (one workgroup per row), then one workgroup per range
-// row scatters each sparse kernel into LDS, transforms it, accumulates the products with the
-// band spectra in registers, and transforms the sum back.  The bins come from the same float64
-// expression (eq. 2, eq. 40) as the direct filter's tap tables, in a table kernel run once per
-// plan.
+// The sparse kernels, hence the G_{r,l}, depend on the filter design alone: a plan builds the
+// tap lists (the bins come from the same float64 expression, eq. 2 and eq. 40, as the direct
+// filter's tap tables) and then G for every (range row, bin row) pair, one workgroup per pair
+// scattering the kernel into LDS and transforming it.  A run computes Yhat for every band row
+// (one workgroup per row), then one workgroup per range row accumulates the products G * Yhat
+// in registers and transforms the sum back.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -27,8 +28,9 @@ using mfft::kFftThreads;
 constexpr int kFcMaxRows = 32;   // bin rows one range row may touch (a 32-bit mask)
 constexpr int kFcMaxQ = (kFftMaxN + kFftThreads - 1) / kFftThreads;
 
-// Row block: int4 header {lfirst, bin mask, ne, 0}, then ne entries
-// int4 {azimuth index (o mod N), bin row - lfirst (-1: no contribution), coef.x, coef.y}.
+// Row block: int4 header {lfirst, bin mask, ne, first pair}, then ne entries
+// int4 {azimuth index (o mod N), bin row - lfirst (-1: no contribution), coef.x, coef.y}.  The
+// first pair index (the row's G spectra, one per mask bit in bit order) is filled in by the host.
 template <int WDT, int INTERP>
 __global__ __launch_bounds__(256) void fc_table_kernel(Geo g, View y, int32_t k, int32_t window, int rows_cap,
                                                        double cos_hw, const int32_t* __restrict__ offsets,
@@ -98,53 +100,68 @@ __global__ __launch_bounds__(kFftThreads) void fc_spectrum_kernel(View y, FftFac
   for (int i = tid; i < n; i += kFftThreads) out[i] = buf[i];
 }
 
+// G of one (range row, bin row) pair: the row's entries on that bin row scattered into a
+// zeroed LDS row (entries that share an azimuth index add up, as in the direct sum), then the
+// unnormalised inverse-direction transform.
+__global__ __launch_bounds__(kFftThreads) void fc_kernel_spectra_kernel(FftFactors f, const char* __restrict__ tabs,
+                                                                        int row_bytes, const int2* __restrict__ pairs,
+                                                                        const float2* __restrict__ tw,
+                                                                        float2* __restrict__ gspec) {
+  extern __shared__ float2 buf[];
+  const int p = blockIdx.x;
+  const int n = f.n;
+  const int tid = threadIdx.x;
+  const int2 pr = pairs[p];
+  const int4* blk = reinterpret_cast<const int4*>(tabs + (size_t)pr.x * row_bytes);
+  const int ne = blk[0].z;
+  float* bufs = reinterpret_cast<float*>(buf);
+  for (int i = tid; i < n; i += kFftThreads) buf[i] = make_float2(0.f, 0.f);
+  __syncthreads();
+  for (int e = tid; e < ne; e += kFftThreads) {
+    const int4 t = blk[1 + e];
+    if (t.y == pr.y) {
+      atomicAdd(&bufs[2 * t.x], __int_as_float(t.z));
+      atomicAdd(&bufs[2 * t.x + 1], __int_as_float(t.w));
+    }
+  }
+  __syncthreads();
+  mfft::block_fft<+1>(buf, f, tw, tid);
+  float2* out = gspec + (size_t)p * n;
+  for (int i = tid; i < n; i += kFftThreads) out[i] = buf[i];
+}
+
 // One range row: I[r, .] = IDFT(sum over the row's bin rows of G_{r,l} * Yhat_l).
 __global__ __launch_bounds__(kFftThreads) void fc_rows_kernel(FftFactors f, int n_range, const char* __restrict__ tabs,
                                                               int row_bytes, const float2* __restrict__ tw,
-                                                              const float2* __restrict__ spec, float inv_scale,
+                                                              const float2* __restrict__ spec,
+                                                              const float2* __restrict__ gspec, float inv_scale,
                                                               float2* __restrict__ image) {
   extern __shared__ float2 buf[];
   const int row = xcd_logical_block(blockIdx.x, n_range);
   const int n = f.n;
   const int tid = threadIdx.x;
-  const int4* blk = reinterpret_cast<const int4*>(tabs + (size_t)row * row_bytes);
-  const int4 hdr = blk[0];
+  const int4 hdr = reinterpret_cast<const int4*>(tabs + (size_t)row * row_bytes)[0];
   const int lfirst = hdr.x;
   unsigned mask = (unsigned)hdr.y;
-  const int ne = hdr.z;
-  float* bufs = reinterpret_cast<float*>(buf);
+  const float2* gp = gspec + (size_t)hdr.w * n;
 
   float2 acc[kFcMaxQ];
 #pragma unroll
   for (int q = 0; q < kFcMaxQ; ++q) acc[q] = make_float2(0.f, 0.f);
-
   while (mask) {
     const int rel = __builtin_ctz(mask);
     mask &= mask - 1u;
-    // sparse kernel of bin row lfirst + rel, scattered into a zeroed row (entries that share an
-    // azimuth index add up, as in the direct sum)
-    for (int i = tid; i < n; i += kFftThreads) buf[i] = make_float2(0.f, 0.f);
-    __syncthreads();
-    for (int e = tid; e < ne; e += kFftThreads) {
-      const int4 t = blk[1 + e];
-      if (t.y == rel) {
-        atomicAdd(&bufs[2 * t.x], __int_as_float(t.z));
-        atomicAdd(&bufs[2 * t.x + 1], __int_as_float(t.w));
-      }
-    }
-    __syncthreads();
-    mfft::block_fft<+1>(buf, f, tw, tid);
     const float2* sp = spec + (size_t)(lfirst + rel) * n;
 #pragma unroll
     for (int q = 0; q < kFcMaxQ; ++q) {
       const int i = tid + q * kFftThreads;
       if (i < n) {
-        const float2 gv = buf[i], yv = sp[i];
+        const float2 gv = gp[i], yv = sp[i];
         acc[q].x = fmaf(gv.x, yv.x, fmaf(-gv.y, yv.y, acc[q].x));
         acc[q].y = fmaf(gv.x, yv.y, fmaf(gv.y, yv.x, acc[q].y));
       }
     }
-    // the next zeroing writes only this thread's own indices: no barrier needed here
+    gp += n;
   }
 #pragma unroll
   for (int q = 0; q < kFcMaxQ; ++q) {
@@ -210,8 +227,15 @@ hipError_t launch_fc_tables(const SparseArgs& a, const FcLayout& L, char* tabs, 
   return lin ? launch_tables_t<1, ROSAR_LINEAR>(a, L, tabs, bad, s) : launch_tables_t<1, ROSAR_NEAREST>(a, L, tabs, bad, s);
 }
 
+hipError_t launch_fc_kernel_spectra(const FcLayout& L, const char* tabs, const int2* pairs, int n_pairs,
+                                   const float2* tw, float2* gspec, hipStream_t s) {
+  if (n_pairs == 0) return hipSuccess;
+  fc_kernel_spectra_kernel<<<n_pairs, kFftThreads, L.lds_bytes, s>>>(L.f, tabs, L.row_bytes, pairs, tw, gspec);
+  return hipGetLastError();
+}
+
 hipError_t launch_fc_run(const SparseArgs& a, const FcLayout& L, const char* tabs, const float2* tw, float2* spec,
-                         hipStream_t s) {
+                         const float2* gspec, hipStream_t s) {
   switch (a.y.dtype) {
     case ROSAR_C64: fc_spectrum_kernel<0><<<a.y.l_count, kFftThreads, L.lds_bytes, s>>>(a.y, L.f, tw, spec); break;
     case ROSAR_C16_F16: fc_spectrum_kernel<1><<<a.y.l_count, kFftThreads, L.lds_bytes, s>>>(a.y, L.f, tw, spec); break;
@@ -220,7 +244,7 @@ hipError_t launch_fc_run(const SparseArgs& a, const FcLayout& L, const char* tab
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   fc_rows_kernel<<<a.g.n_range, kFftThreads, L.lds_bytes, s>>>(L.f, a.g.n_range, tabs, L.row_bytes, tw, spec,
-                                                                a.y.inv_scale, a.image);
+                                                                gspec, a.y.inv_scale, a.image);
   return hipGetLastError();
 }
 

@@ -87,8 +87,9 @@ hipError_t launch_tap_tables(const SparseArgs& a, const PlanLayout& pl, char* ta
 hipError_t launch_sparse_planned(const SparseArgs& a, const PlanLayout& pl, const char* tabs, hipStream_t s);
 
 // Azimuth fast convolution (plans of variant 3): the radix sequence of the azimuth FFT length,
-// the per-row tap-list layout, the table kernel and the two kernels of a run (band-row spectra,
-// then one workgroup per range row).
+// the per-row tap-list layout, the plan's kernels (tap lists, then the spectrum of every (range
+// row, bin row) pair's sparse kernel) and the two kernels of a run (band-row spectra, then one
+// workgroup per range row).
 constexpr int kFftMaxPasses = 16;
 struct FftFactors {
   int32_t n, n_pass;
@@ -105,8 +106,10 @@ bool fc_layout(const SparseArgs& a, FcLayout* out);
 size_t fc_spectrum_bytes(const SparseArgs& a);
 void fc_twiddles(int n, float2* host_tw);
 hipError_t launch_fc_tables(const SparseArgs& a, const FcLayout& L, char* tabs, int* bad, hipStream_t s);
+hipError_t launch_fc_kernel_spectra(const FcLayout& L, const char* tabs, const int2* pairs, int n_pairs,
+                                   const float2* tw, float2* gspec, hipStream_t s);
 hipError_t launch_fc_run(const SparseArgs& a, const FcLayout& L, const char* tabs, const float2* tw, float2* spec,
-                         hipStream_t s);
+                         const float2* gspec, hipStream_t s);
 
 // Tile chosen when the caller leaves it to the library.
 Tile default_tile(int32_t n, int32_t y_dtype);
