@@ -326,6 +326,24 @@ def extras(torch, rs, synth, w, x, dev, rc, off, wts, timed, reps):
     print(f"[bench] corrected forward {out['corrected_forward_us']:.1f} us, adjoint {out['adjoint_us']:.1f} us",
           file=sys.stderr, flush=True)
 
+    # sparse-plan variants on the same rotation: the direct sum with LINEAR sampling, and the
+    # azimuth fast convolution (same sum through FFTs along azimuth) for both samplings
+    fc = {}
+    for interp in ("nearest", "linear"):
+        for name, tile in (("fastconv", "fastconv"), ("direct", None)):
+            if name == "direct" and interp == "nearest":
+                continue   # the headline figure
+            if tile is None:
+                tile, _ = rs.sparse_plan_autotune(g, grid, rc, off, wts, w.sparse.window, interp=interp, reps=5,
+                                                  out=img, methods="direct")
+            p = rs.SparsePlan(g, grid, rc, off, wts, w.sparse.window, interp=interp, tile=tile)
+            fp = lambda: p.run(rc, out=img)
+            fp()
+            fc[f"{name}_{interp}_us"] = 1000 * timed(fp, max(3, reps // 10), inner=10, out=lambda: img)
+            p.close()
+    out["plan_variants"] = fc
+    print("[bench] plan variants: " + ", ".join(f"{k} {v:.1f}" for k, v in fc.items()), file=sys.stderr, flush=True)
+
     # batched stream: 64 rotations of uneven size, autotuned shape, replayed from a HIP graph
     bws = synth.batch_workloads(64)
     bxs = synth.make_batch_inputs(bws)
@@ -435,7 +453,8 @@ def main():
     if tile is not None and tile[0] in (0, 2):
         plan_shape = tile[1:]
     else:   # the plan autotuner's choice for this layout (times every plan shape on the GPU)
-        plan_shape, _ = rs.sparse_plan_autotune(g, grid, rc, off, wts, w.sparse.window, reps=10, out=img)
+        plan_shape, _ = rs.sparse_plan_autotune(g, grid, rc, off, wts, w.sparse.window, reps=10, out=img,
+                                                methods="direct")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     plan = rs.SparsePlan(g, grid, rc, off, wts, w.sparse.window, tile=plan_shape)

@@ -298,13 +298,16 @@ void rosar_sparse_plan_destroy(rosar_sparse_plan* plan);
  * times the azimuth fast convolution too where the layout admits it, and returns the fastest
  * as {2, pixels_per_lane, waves} or {3, 0, 0} in *best, for
  * rosar_sparse_plan_create, with its mean run time in microseconds.  Arguments as
- * rosar_sparse_plan_create plus the image of rosar_sparse_filter.  Synchronises `stream`.
- * Errors: as rosar_sparse_plan_create; INVALID_ARG for NULL best/best_us or reps outside
- * [1, 10000]. */
+ * rosar_sparse_plan_create plus the image of rosar_sparse_filter; `variants` restricts the
+ * candidates to a mask of ROSAR_PLAN_DIRECT (the LDS-staged shapes) and ROSAR_PLAN_FASTCONV
+ * (0 = both).  Synchronises `stream`.
+ * Errors: as rosar_sparse_plan_create (UNSUPPORTED if no candidate admits the layout);
+ * INVALID_ARG for NULL best/best_us, reps outside [1, 10000] or unknown variant bits. */
+enum { ROSAR_PLAN_DIRECT = 1, ROSAR_PLAN_FASTCONV = 2 };
 rosar_status rosar_sparse_plan_autotune(const rosar_geometry* geom, const rosar_polar_grid* grid,
                                         const rosar_rc_view* rc, const rosar_sparse_set* set,
-                                        rosar_interp interp, void* image, int32_t reps, rosar_tile* best,
-                                        float* best_us, rosar_stream stream);
+                                        rosar_interp interp, void* image, int32_t variants, int32_t reps,
+                                        rosar_tile* best, float* best_us, rosar_stream stream);
 
 /* ---------------------------------------------------------------- autotuning
  * Times every supported launch shape of rosar_sparse_filter on the given inputs (the image is

@@ -263,10 +263,11 @@ def _descs(rotations):
 
 
 def sparse_plan_autotune(geom, grid, rc: RangeCompressed, offsets, weights, window, interp: str = "nearest",
-                         reps: int = 20, out: torch.Tensor | None = None):
+                         reps: int = 20, out: torch.Tensor | None = None, methods: str = "all"):
     """Time every plan launch shape on `rc`, and the azimuth fast convolution where the layout
     admits it; returns (tile, microseconds) with tile = (pixels_per_lane, waves) or "fastconv",
-    to pass as SparsePlan(tile=...)."""
+    to pass as SparsePlan(tile=...).  methods: "all", "direct" or "fastconv"."""
+    variants = {"all": 0, "direct": L.PLAN_DIRECT, "fastconv": L.PLAN_FASTCONV}[methods]
     _need_gpu(rc.data)
     s = _set(offsets, weights, window)
     dev = rc.data.device
@@ -276,7 +277,8 @@ def sparse_plan_autotune(geom, grid, rc: RangeCompressed, offsets, weights, wind
     best = L.Tile()
     us = C.c_float(0)
     L.check(L.lib().rosar_sparse_plan_autotune(C.byref(g), C.byref(p), C.byref(v), C.byref(s),
-                                               L.INTERP_CODES[interp], _ptr(out), reps, C.byref(best), C.byref(us),
+                                               L.INTERP_CODES[interp], _ptr(out), variants, reps, C.byref(best),
+                                               C.byref(us),
                                                _stream(dev)), "rosar_sparse_plan_autotune")
     if best.variant == 3:
         return "fastconv", float(us.value)

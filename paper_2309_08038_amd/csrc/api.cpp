@@ -402,11 +402,12 @@ rosar_status fc_prepare(const rosar::SparseArgs& a, const rosar::FcLayout& fc, h
                         float2** spec, float2** gspec) {
   const int n_range = a.g.n_range;
   const size_t tab_bytes = (size_t)fc.row_bytes * (size_t)n_range;
-  const size_t tw_bytes = (size_t)a.g.n * sizeof(float2);
+  const size_t tw_bytes = (size_t)rosar::fc_twiddle_count(a.g.n) * sizeof(float2);
+  const size_t row_spec_bytes = (size_t)a.g.n * sizeof(float2);
   if (hipMalloc(tabs, tab_bytes + 256) != hipSuccess || hipMalloc(tw, tw_bytes) != hipSuccess ||
       hipMalloc(spec, rosar::fc_spectrum_bytes(a)) != hipSuccess)
     return fail(ROSAR_ERR_NO_MEMORY, "device allocation of the fast-convolution plan failed");
-  std::vector<float2> host_tw(a.g.n);
+  std::vector<float2> host_tw(rosar::fc_twiddle_count(a.g.n));
   rosar::fc_twiddles(a.g.n, host_tw.data());
   int* bad = reinterpret_cast<int*>(*tabs + tab_bytes);
   int bad_host = 0;
@@ -428,7 +429,7 @@ rosar_status fc_prepare(const rosar::SparseArgs& a, const rosar::FcLayout& fc, h
   }
   const size_t n_pairs = pairs.size();
   int2* d_pairs = nullptr;
-  if (hipMalloc(gspec, std::max<size_t>(n_pairs, 1) * tw_bytes) != hipSuccess ||
+  if (hipMalloc(gspec, std::max<size_t>(n_pairs, 1) * row_spec_bytes) != hipSuccess ||
       hipMalloc(&d_pairs, std::max<size_t>(n_pairs, 1) * sizeof(int2)) != hipSuccess) {
     (void)hipFree(d_pairs);
     return fail(ROSAR_ERR_NO_MEMORY, "device allocation of the kernel spectra (%zu pairs) failed", n_pairs);
@@ -568,33 +569,38 @@ void rosar_sparse_plan_destroy(rosar_sparse_plan* plan) { free_plan(plan); }
 
 rosar_status rosar_sparse_plan_autotune(const rosar_geometry* geom, const rosar_polar_grid* grid,
                                         const rosar_rc_view* rc, const rosar_sparse_set* set, rosar_interp interp,
-                                        void* image, int32_t reps, rosar_tile* best, float* best_us,
-                                        rosar_stream stream) {
+                                        void* image, int32_t variants, int32_t reps, rosar_tile* best,
+                                        float* best_us, rosar_stream stream) {
   rosar::SparseArgs a{};
   ROSAR_TRY(sparse_common(geom, grid, rc, set, nullptr, nullptr, interp, image, &a));
   if (!aligned(rc->data, 16)) return fail(ROSAR_ERR_INVALID_ARG, "rc view data must be 16-byte aligned");
   if (!best || !best_us) return fail(ROSAR_ERR_INVALID_ARG, "best / best_us is NULL");
   if (reps < 1 || reps > 10000) return fail(ROSAR_ERR_INVALID_ARG, "reps must be in [1, 10000]");
+  if (variants != 0 && (variants & ~(ROSAR_PLAN_DIRECT | ROSAR_PLAN_FASTCONV)) != 0)
+    return fail(ROSAR_ERR_INVALID_ARG, "variants must be 0 or a mask of ROSAR_PLAN_DIRECT / ROSAR_PLAN_FASTCONV");
+  const bool try_direct = variants == 0 || (variants & ROSAR_PLAN_DIRECT);
+  const bool try_fc = variants == 0 || (variants & ROSAR_PLAN_FASTCONV);
   int shapes[16][2];
   int n_shapes = 0;
   for (int p : {1, 2, 4, 8})
     for (int w : {1, 2, 4, 8})
-      if (rosar::plan_shape_supported(p, w)) {
+      if (try_direct && rosar::plan_shape_supported(p, w)) {
         shapes[n_shapes][0] = p;
         shapes[n_shapes][1] = w;
         ++n_shapes;
       }
   bool any = false;
   rosar::PlanLayout pl{};
+  rosar::FcLayout fc{};
   for (int i = 0; i < n_shapes; ++i) any = any || rosar::sparse_plan_layout(a, shapes[i][0], shapes[i][1], &pl);
-  if (!any)
-    return fail(ROSAR_ERR_UNSUPPORTED,
-                "this band layout cannot use the LDS-staged kernel (halo < W/2, rows not 16-byte aligned, or a "
-                "staged row over the LDS budget)");
+  const bool fc_ok = try_fc && rosar::fc_layout(a, &fc);
+  if (!any && !fc_ok)
+    return fail(ROSAR_ERR_UNSUPPORTED, "no plan variant admits this layout (direct: halo >= W/2, 16-byte aligned rows, "
+                                       "a staged row within the LDS budget; fast convolution: N = 2^a 3^b 5^c <= 8192)");
   if (inject_launch_fault()) return fail(ROSAR_ERR_HIP, "injected launch failure (ROSAR_FAULT_INJECT)");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   char* tabs = nullptr;   // row blocks do not depend on the shape: one buffer serves every shape
-  const size_t bytes = (size_t)pl.row_bytes * (size_t)grid->n_range;
+  const size_t bytes = any ? (size_t)pl.row_bytes * (size_t)grid->n_range : 256;
   if (hipMalloc(&tabs, bytes) != hipSuccess)
     return fail(ROSAR_ERR_NO_MEMORY, "device allocation of the tap tables (%zu bytes) failed", bytes);
   hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -620,8 +626,7 @@ rosar_status rosar_sparse_plan_autotune(const rosar_geometry* geom, const rosar_
   if (e == hipSuccess) e = hipStreamSynchronize(s);   // no run may still read the tables
   (void)hipFree(tabs);
   rosar_status st = e == hipSuccess ? ROSAR_OK : from_hip(e, "plan autotune");
-  rosar::FcLayout fc{};
-  if (st == ROSAR_OK && rosar::fc_layout(a, &fc)) {   // the azimuth fast convolution
+  if (st == ROSAR_OK && fc_ok) {   // the azimuth fast convolution
     char* ftabs = nullptr;
     float2* tw = nullptr;
     float2* spec = nullptr;

@@ -89,13 +89,15 @@ template <int DT>
 __global__ __launch_bounds__(kFftThreads) void fc_spectrum_kernel(View y, FftFactors f, const float2* __restrict__ tw,
                                                                   float2* __restrict__ spec) {
   extern __shared__ float2 buf[];
+  __shared__ mfft::Twiddles s_tw;
   const int l = blockIdx.x;
   const int n = f.n;
   const int tid = threadIdx.x;
   const int64_t row = (int64_t)l * y.ld + y.halo;
+  mfft::load_twiddles(s_tw, tw, n, tid);
   for (int i = tid; i < n; i += kFftThreads) buf[i] = load_c<DT>(y.data, row + i);
   __syncthreads();
-  mfft::block_fft<-1>(buf, f, tw, tid);
+  mfft::block_fft<-1>(buf, f, s_tw, tid);
   float2* out = spec + (size_t)l * n;
   for (int i = tid; i < n; i += kFftThreads) out[i] = buf[i];
 }
@@ -108,10 +110,12 @@ __global__ __launch_bounds__(kFftThreads) void fc_kernel_spectra_kernel(FftFacto
                                                                         const float2* __restrict__ tw,
                                                                         float2* __restrict__ gspec) {
   extern __shared__ float2 buf[];
+  __shared__ mfft::Twiddles s_tw;
   const int p = blockIdx.x;
   const int n = f.n;
   const int tid = threadIdx.x;
   const int2 pr = pairs[p];
+  mfft::load_twiddles(s_tw, tw, n, tid);
   const int4* blk = reinterpret_cast<const int4*>(tabs + (size_t)pr.x * row_bytes);
   const int ne = blk[0].z;
   float* bufs = reinterpret_cast<float*>(buf);
@@ -125,7 +129,7 @@ __global__ __launch_bounds__(kFftThreads) void fc_kernel_spectra_kernel(FftFacto
     }
   }
   __syncthreads();
-  mfft::block_fft<+1>(buf, f, tw, tid);
+  mfft::block_fft<+1>(buf, f, s_tw, tid);
   float2* out = gspec + (size_t)p * n;
   for (int i = tid; i < n; i += kFftThreads) out[i] = buf[i];
 }
@@ -137,9 +141,11 @@ __global__ __launch_bounds__(kFftThreads) void fc_rows_kernel(FftFactors f, int 
                                                               const float2* __restrict__ gspec, float inv_scale,
                                                               float2* __restrict__ image) {
   extern __shared__ float2 buf[];
+  __shared__ mfft::Twiddles s_tw;
   const int row = xcd_logical_block(blockIdx.x, n_range);
   const int n = f.n;
   const int tid = threadIdx.x;
+  mfft::load_twiddles(s_tw, tw, n, tid);
   const int4 hdr = reinterpret_cast<const int4*>(tabs + (size_t)row * row_bytes)[0];
   const int lfirst = hdr.x;
   unsigned mask = (unsigned)hdr.y;
@@ -169,7 +175,7 @@ __global__ __launch_bounds__(kFftThreads) void fc_rows_kernel(FftFactors f, int 
     if (i < n) buf[i] = acc[q];
   }
   __syncthreads();
-  mfft::block_fft<+1>(buf, f, tw, tid);
+  mfft::block_fft<+1>(buf, f, s_tw, tid);
   const float s = inv_scale / (float)n;
   float2* out = image + (size_t)row * n;
   for (int i = tid; i < n; i += kFftThreads) out[i] = make_float2(buf[i].x * s, buf[i].y * s);
@@ -212,11 +218,15 @@ bool fc_layout(const SparseArgs& a, FcLayout* out) {
 
 size_t fc_spectrum_bytes(const SparseArgs& a) { return (size_t)a.y.l_count * (size_t)a.g.n * sizeof(float2); }
 
+int fc_twiddle_count(int n) { return mfft::twiddle_count(n); }
+
 void fc_twiddles(int n, float2* host_tw) {
   const double two_pi = 6.283185307179586476925286766559;
-  for (int t = 0; t < n; ++t) {
+  const int cnt = mfft::twiddle_count(n);
+  for (int i = 0; i < cnt; ++i) {
+    const int t = i < mfft::kTwLo ? i : (i - mfft::kTwLo) * mfft::kTwLo;
     const double ang = two_pi * (double)t / (double)n;
-    host_tw[t] = make_float2((float)std::cos(ang), (float)-std::sin(ang));
+    host_tw[i] = make_float2((float)std::cos(ang), (float)-std::sin(ang));
   }
 }
 

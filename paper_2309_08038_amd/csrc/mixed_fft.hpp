@@ -1,8 +1,10 @@
 // Workgroup-wide complex FFT of one row held in LDS, any length N = 2^a 3^b 5^c up to
 // kFftMaxN: Stockham autosort passes of radix 8, 4, 2, 5 and 3.  Each pass reads its
 // butterflies' inputs into registers, synchronises, and writes the outputs back into the same
-// LDS buffer, so one N-element buffer suffices.  Twiddles come from a float32 table
-// tw[t] = exp(-j 2 pi t / N) evaluated in float64 on the host.
+// LDS buffer, so one N-element buffer suffices.  A twiddle exp(-j 2 pi t / N) is the product of
+// two entries of small LDS tables, lo[t mod 64] = exp(-j 2 pi (t mod 64) / N) and
+// hi[t / 64] = exp(-j 2 pi 64 (t / 64) / N), both evaluated in float64 on the host: 1.5 KB of
+// LDS instead of an N-entry table, and no global-memory latency inside a pass.
 //
 // DIR = -1: X[m] = sum_n x[n] exp(-j 2 pi n m / N) (forward); DIR = +1: the same with +j
 // (unnormalised inverse).
@@ -18,6 +20,26 @@ constexpr int kFftMaxN = 8192;
 
 // Radix sequence of one length (host-built; the product of radix[0..n_pass) is n).
 using Factors = FftFactors;
+
+constexpr int kTwLo = 64;
+constexpr int kTwHi = kFftMaxN / kTwLo;
+
+// The twiddle tables in LDS (global layout: kTwLo lo entries, then ceil(N / 64) hi entries).
+struct Twiddles {
+  float2 lo[kTwLo];
+  float2 hi[kTwHi];
+};
+
+__host__ __device__ constexpr int twiddle_count(int n) { return kTwLo + (n + kTwLo - 1) / kTwLo; }
+
+// Copies the tables into LDS; the caller synchronises before the first pass.
+__device__ __forceinline__ void load_twiddles(Twiddles& t, const float2* __restrict__ tw, int n, int tid) {
+  const int cnt = twiddle_count(n);
+  for (int i = tid; i < cnt; i += kFftThreads) {
+    if (i < kTwLo) t.lo[i] = tw[i];
+    else t.hi[i - kTwLo] = tw[i];
+  }
+}
 
 // j * z for DIR = +1, -j * z for DIR = -1.
 template <int DIR>
@@ -89,10 +111,13 @@ __device__ __forceinline__ void dft(float2 (&v)[R]) {
 // j reads buf[j + i n/R], applies the twiddles exp(DIR j 2 pi i k / (ns R)) with k = j mod ns,
 // and writes buf[(j - k) R + k + i ns].  All threads of the block call it.
 template <int R, int DIR>
-__device__ __forceinline__ void fft_pass(float2* buf, int n, int ns, const float2* __restrict__ tw, int tid) {
+__device__ __forceinline__ void fft_pass(float2* buf, int n, int ns, const Twiddles& tw, int tid) {
   constexpr int MAXB = (kFftMaxN / R + kFftThreads - 1) / kFftThreads;
   const int nb = n / R;
   const int tstep = n / (ns * R);
+  // j / ns as a multiply-high for ns >= 2 (magic = ceil(2^32 / ns) < 2^32): exact for
+  // j, ns <= 8192 since j * (magic * ns - 2^32) < 2^32.  ns == 1 gives k = 0.
+  const uint32_t magic = ns > 1 ? (uint32_t)((0x100000000ull + (uint64_t)ns - 1) / (uint64_t)ns) : 0u;
   float2 v[MAXB][R];
 #pragma unroll
   for (int b = 0; b < MAXB; ++b) {
@@ -107,11 +132,12 @@ __device__ __forceinline__ void fft_pass(float2* buf, int n, int ns, const float
   for (int b = 0; b < MAXB; ++b) {
     const int j = tid + b * kFftThreads;
     if (j < nb) {
-      const int k = j % ns;
+      const int k = ns > 1 ? j - (int)__umulhi((uint32_t)j, magic) * ns : 0;
       if (k != 0) {
 #pragma unroll
         for (int i = 1; i < R; ++i) {
-          float2 w = tw[i * k * tstep];
+          const int t = i * k * tstep;
+          float2 w = cmul(tw.hi[t >> 6], tw.lo[t & (kTwLo - 1)]);
           if (DIR > 0) w.y = -w.y;
           v[b][i] = cmul(v[b][i], w);
         }
@@ -128,7 +154,7 @@ __device__ __forceinline__ void fft_pass(float2* buf, int n, int ns, const float
 // The whole transform; `buf` holds the row on entry and the result on exit (block-uniform
 // arguments; the caller synchronises before, the last pass synchronises after).
 template <int DIR>
-__device__ __forceinline__ void block_fft(float2* buf, const Factors& f, const float2* __restrict__ tw, int tid) {
+__device__ __forceinline__ void block_fft(float2* buf, const Factors& f, const Twiddles& tw, int tid) {
   int ns = 1;
   for (int p = 0; p < f.n_pass; ++p) {
     switch (f.radix[p]) {

@@ -104,7 +104,8 @@ struct FcLayout {
 };
 bool fc_layout(const SparseArgs& a, FcLayout* out);
 size_t fc_spectrum_bytes(const SparseArgs& a);
-void fc_twiddles(int n, float2* host_tw);
+int fc_twiddle_count(int n);
+void fc_twiddles(int n, float2* host_tw);   // fc_twiddle_count(n) entries
 hipError_t launch_fc_tables(const SparseArgs& a, const FcLayout& L, char* tabs, int* bad, hipStream_t s);
 hipError_t launch_fc_kernel_spectra(const FcLayout& L, const char* tabs, const int2* pairs, int n_pairs,
                                    const float2* tw, float2* gspec, hipStream_t s);

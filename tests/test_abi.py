@@ -269,10 +269,10 @@ def test_sparse_plan_autotune_validation(lib):
     sset = L.SparseSet(32, 64, 0x30000, 0x40000, L.C64, 0)
     best, us = L.Tile(), C.c_float(0)
 
-    def call(view=None, reps=5, b=True, u=True, image=FAKE):
+    def call(view=None, reps=5, b=True, u=True, image=FAKE, variants=0):
         view = view or L.RcView(0x20000, L.C64, 0, 64, 32, 424, 1.0, 0)
         return lib.rosar_sparse_plan_autotune(C.byref(g), C.byref(grid), C.byref(view), C.byref(sset), L.NEAREST,
-                                              image, reps, C.byref(best) if b else None,
+                                              image, variants, reps, C.byref(best) if b else None,
                                               C.byref(us) if u else None, None)
 
     assert call(b=False) == L.ROSAR_ERR_INVALID_ARG
@@ -281,7 +281,11 @@ def test_sparse_plan_autotune_validation(lib):
     assert call(reps=10001) == L.ROSAR_ERR_INVALID_ARG
     assert call(image=None) == L.ROSAR_ERR_INVALID_ARG
     assert call(view=L.RcView(0x20008, L.C64, 0, 64, 32, 424, 1.0, 0)) == L.ROSAR_ERR_INVALID_ARG
-    assert call(view=L.RcView(0x20000, L.C64, 0, 64, 16, 392, 1.0, 0)) == L.ROSAR_ERR_UNSUPPORTED
+    assert call(variants=4) == L.ROSAR_ERR_INVALID_ARG
+    # halo < W/2 rules out the direct shapes; the fast convolution (N = 360) is still a candidate
+    # unless excluded
+    assert call(view=L.RcView(0x20000, L.C64, 0, 64, 16, 392, 1.0, 0), variants=L.PLAN_DIRECT) == \
+        L.ROSAR_ERR_UNSUPPORTED
     assert lib.rosar_last_error().decode() != ""
 
 
