@@ -62,8 +62,9 @@ def kernel_source_digest(files):
     return h.hexdigest()[:16]
 
 
-def load_traffic(kernel: str, digest: str, workload: str):
-    """HBM bytes per launch from the committed PMC summary, if it was taken on this kernel source."""
+def load_traffic(kernel: str, digest: str, workload: str, shape: str):
+    """HBM bytes per launch of the planned sparse filter with launch shape `shape` ("PxNW") from
+    the committed PMC summary, if it was taken on this kernel source and that shape."""
     path = os.path.join(PROFILE_DIR, f"{kernel}_{workload}_traffic.json")
     if not os.path.exists(path):
         return None
@@ -71,7 +72,8 @@ def load_traffic(kernel: str, digest: str, workload: str):
         d = json.load(f)
     if d.get("kernel_source_digest") != digest:
         return None
-    return d.get("traffic_bytes_per_launch")
+    entry = d.get("by_shape", {}).get(shape)
+    return entry.get("traffic_bytes_per_launch") if entry else None
 
 
 def cpu_baseline(w, x):
@@ -450,11 +452,23 @@ def main():
     # one filter design for every rotation: the tap tables of its range rows are built once,
     # outside the timed steps (the plan equals the single call with the same shape bit for bit)
     rs.range_compress(g, raw, win, x.l_lo, x.l_count, out=rc)
+    timed = graph_timer(torch)
+    shape_us = {}
     if tile is not None and tile[0] in (0, 2):
         plan_shape = tile[1:]
-    else:   # the plan autotuner's choice for this layout (times every plan shape on the GPU)
-        plan_shape, _ = rs.sparse_plan_autotune(g, grid, rc, off, wts, w.sparse.window, reps=10, out=img,
+    else:
+        # every direct plan shape timed the way the figures below are (graph replays of 20
+        # launches, best of 3); the library autotuner's own pick is recorded beside it
+        tuner_pick, _ = rs.sparse_plan_autotune(g, grid, rc, off, wts, w.sparse.window, reps=10, out=img,
                                                 methods="direct")
+        for cand in ((4, 8), (8, 4), (4, 4), (2, 8), (2, 4), (8, 2)):
+            cp = rs.SparsePlan(g, grid, rc, off, wts, w.sparse.window, tile=cand)
+            fc_ = lambda: cp.run(rc, out=img)
+            shape_us[f"{cand[0]}x{cand[1]}"] = 1000 * min(timed(fc_, 3, inner=20, out=lambda: img) for _ in range(3))
+            cp.close()
+        best = min(shape_us, key=shape_us.get)
+        plan_shape = tuple(int(v) for v in best.split("x"))
+        shape_us["library_autotuner_pick"] = f"{tuner_pick[0]}x{tuner_pick[1]}"
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     plan = rs.SparsePlan(g, grid, rc, off, wts, w.sparse.window, tile=plan_shape)
@@ -473,7 +487,6 @@ def main():
         rs.range_compress(g, raw, win, x.l_lo, x.l_count, out=rc)
         sf(rc, img)
 
-    timed = graph_timer(torch)
     for _ in range(a.warmup):
         step()
     torch.cuda.synchronize()
@@ -526,15 +539,17 @@ def main():
     sf_flops = px * k * 8
     rc_bytes = g.n_pulses * g.n_fast * 8 + g.n_fast * 4 + x.l_count * (g.n_pulses + 2 * halo) * es
     digest = kernel_source_digest(["sparse_filter.hip", "sparse_device.hpp", "rosar_device.hpp"])
-    traffic = load_traffic("sparse_filter", digest, a.workload)
+    traffic = None if a.single_call else load_traffic("sparse_filter", digest, a.workload,
+                                                       f"{plan_shape[0]}x{plan_shape[1]}")
     achieved_tf = sf_flops / (ms_sf * 1e-3) / 1e12
     roofline = {"bound": "alu", "achieved": round(achieved_tf, 3), "peak": PEAK_FP32_VALU_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(achieved_tf / PEAK_FP32_VALU_TFLOPS, 4),
                 "peak_with_packed_fp32": PEAK_FP32_PACKED_TFLOPS,
                 "frac_of_packed_peak": round(achieved_tf / PEAK_FP32_PACKED_TFLOPS, 4),
                 "traffic": traffic,
-                "kernel": "sparse_lds_kernel (" + ("single call" if a.single_call else "planned tap tables")
-                          + ", default launch shape)",
+                "kernel": ("sparse_lds_kernel (single call, default launch shape)" if a.single_call else
+                           f"sparse_lds_kernel<0, 0, 0, {plan_shape[0]}, {plan_shape[1]}, true> (planned tap "
+                           "tables, autotuned shape)"),
                 "algorithmic_bytes": sf_bytes, "algorithmic_flops": sf_flops}
     out = {
         "metric": "polar image pixels/s: sparse-array filter vs full BPA on 1 MI355X; HBM GB/s",
@@ -563,6 +578,7 @@ def main():
         "sparse_filter_mode": "single call" if a.single_call else "plan (tap tables built once per filter design)",
         "plan_create_ms_wall": ms_plan,
         "plan_shape_pixels_per_lane_waves": list(plan_shape),
+        "plan_shape_candidates_us": shape_us,
         "hbm_gbps": {"sparse_filter": sf_bytes / (ms_sf * 1e-3) / 1e9,
                      "range_compress": rc_bytes / (ms_rc * 1e-3) / 1e9, "peak": PEAK_HBM_GBPS,
                      "plain_copy_achievable": copy_gbps},
