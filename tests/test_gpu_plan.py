@@ -294,3 +294,38 @@ def test_fastconv_graph_replay():
         plan.run(rc, out=img)
         torch.cuda.synchronize()
     plan.close()
+
+
+@pytest.mark.parametrize("variant", ["fastconv-nearest", "fastconv-linear", "direct-linear", "direct-nearest"])
+def test_plan_runs_deterministic(variant):
+    """Rotation size: repeated eager runs and graph replays of one plan give identical bits."""
+    rs = need_gpu()
+    w, x = inputs("rotation")
+    rc, off, wts = upload(rs, w, x)
+    method, interp = variant.split("-")
+    tile = "fastconv" if method == "fastconv" else (4, 4)
+    plan = rs.SparsePlan(w.geometry, w.grid, rc, off, wts, w.sparse.window, interp=interp, tile=tile)
+    log(f"plan determinism {variant}: eager runs")
+    img = plan.run(rc)
+    torch.cuda.synchronize()
+    ref = img.clone()
+    for i in range(5):
+        plan.run(rc, out=img)
+        torch.cuda.synchronize()
+        assert torch.equal(img, ref), ("eager", i)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(graph, stream=s):
+            for _ in range(4):
+                plan.run(rc, out=img)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    for rep in range(3):
+        log(f"plan determinism {variant}: replay {rep}")
+        img.zero_()
+        graph.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(img, ref), ("replay", rep)
+    plan.close()
