@@ -88,11 +88,11 @@ __global__ __launch_bounds__(256) void fc_table_kernel(Geo g, View y, int32_t k,
 template <int DT>
 __global__ __launch_bounds__(kFftThreads) void fc_spectrum_kernel(View y, FftFactors f, const float2* __restrict__ tw,
                                                                   float2* __restrict__ spec) {
-  extern __shared__ float2 buf[];
-  __shared__ mfft::Twiddles s_tw;
+  extern __shared__ float2 buf[];   // [n] row, then the twiddle tables (all dynamic LDS)
   const int l = blockIdx.x;
   const int n = f.n;
   const int tid = threadIdx.x;
+  mfft::Twiddles& s_tw = *reinterpret_cast<mfft::Twiddles*>(buf + n);
   const int64_t row = (int64_t)l * y.ld + y.halo;
   mfft::load_twiddles(s_tw, tw, n, tid);
   for (int i = tid; i < n; i += kFftThreads) buf[i] = load_c<DT>(y.data, row + i);
@@ -109,11 +109,11 @@ __global__ __launch_bounds__(kFftThreads) void fc_kernel_spectra_kernel(FftFacto
                                                                         int row_bytes, const int2* __restrict__ pairs,
                                                                         const float2* __restrict__ tw,
                                                                         float2* __restrict__ gspec) {
-  extern __shared__ float2 buf[];
-  __shared__ mfft::Twiddles s_tw;
+  extern __shared__ float2 buf[];   // [n] row, then the twiddle tables (all dynamic LDS)
   const int p = blockIdx.x;
   const int n = f.n;
   const int tid = threadIdx.x;
+  mfft::Twiddles& s_tw = *reinterpret_cast<mfft::Twiddles*>(buf + n);
   const int2 pr = pairs[p];
   mfft::load_twiddles(s_tw, tw, n, tid);
   const int4* blk = reinterpret_cast<const int4*>(tabs + (size_t)pr.x * row_bytes);
@@ -140,11 +140,11 @@ __global__ __launch_bounds__(kFftThreads) void fc_rows_kernel(FftFactors f, int 
                                                               const float2* __restrict__ spec,
                                                               const float2* __restrict__ gspec, float inv_scale,
                                                               float2* __restrict__ image) {
-  extern __shared__ float2 buf[];
-  __shared__ mfft::Twiddles s_tw;
+  extern __shared__ float2 buf[];   // [n] row, then the twiddle tables (all dynamic LDS)
   const int row = xcd_logical_block(blockIdx.x, n_range);
   const int n = f.n;
   const int tid = threadIdx.x;
+  mfft::Twiddles& s_tw = *reinterpret_cast<mfft::Twiddles*>(buf + n);
   mfft::load_twiddles(s_tw, tw, n, tid);
   const int4 hdr = reinterpret_cast<const int4*>(tabs + (size_t)row * row_bytes)[0];
   const int lfirst = hdr.x;
@@ -212,7 +212,7 @@ bool fc_layout(const SparseArgs& a, FcLayout* out) {
   out->row_bytes = 16 * (1 + out->ne);
   out->rows_cap = kFcMaxRows;
   out->cos_hw = cos((a.window / 2) * a.g.step);
-  out->lds_bytes = (size_t)n * sizeof(float2);
+  out->lds_bytes = (size_t)n * sizeof(float2) + sizeof(mfft::Twiddles);
   return true;
 }
 
