@@ -167,6 +167,53 @@ def sparse_filter_at(yb, l_lo, geom, grid, offsets, weights, rows, azs, dphi=Non
     return out
 
 
+def sparse_filter_adjoint_band(l_count: int, l_lo: int, geom, grid, offsets, weights, grad_image, dphi=None,
+                               dpsi=None, interp: str = "nearest") -> np.ndarray:
+    """Adjoint of sparse_filter with respect to the range-compressed band: sparse_filter is
+    linear in Y, I[r, a] = sum_k conj(w[r, k]) rot c_l Y_1D[n, l] over the bins l the sample of
+    tap k reads with interpolation weights c_l (eq. 40; 1 for NEAREST, 1 - f and f for LINEAR),
+    n = (a + o_k) mod N, rot the delta/psi correction (1 without).  For a real loss with
+    g = dL/dRe(I) + j dL/dIm(I) the gradient with respect to Y is
+        grad_Y[n, l] = sum over (r, a, k) reading (n, l) of w[r, k] conj(rot) c_l g[r, a],
+    i.e. A^H g for the linear map A.  Bins outside the band get nothing.  Returns
+    [N, l_count] complex128 in the layout of the band argument of sparse_filter."""
+    n_p = geom.n_pulses
+    r = geom.radius_m
+    beta = bins_per_metre(geom)
+    k = wavenumber(geom)
+    a = np.arange(grid.n_az)
+    out = np.zeros((n_p, l_count), dtype=np.complex128)
+    for row in range(grid.n_range):
+        rr = grid.r0_m + row * grid.dr_m
+        g = grad_image[row].astype(np.complex128)
+        for kk in range(offsets.shape[1]):
+            o = int(offsets[row, kk])
+            n = (a + o) % n_p
+            d0 = o * TWO_PI / n_p
+            d = d0 + (0.0 if dphi is None else dphi[n].astype(np.float64))
+            r_hat = slant_range(rr, r, d)
+            u = beta * r_hat
+            rot = np.ones(n.shape, dtype=np.complex128)
+            if dphi is not None or dpsi is not None:
+                ps = np.zeros(n.shape) if dpsi is None else dpsi[n].astype(np.float64)
+                rot = np.exp(-1j * 2.0 * k * (r_hat - slant_range(rr, r, d0))) * np.exp(-1j * ps)
+            if interp == "nearest":
+                parts = [(np.floor(u + 0.5).astype(np.int64) - l_lo, np.ones(n.shape))]
+            elif interp == "linear":
+                fl = np.floor(u)
+                f = u - fl
+                i = fl.astype(np.int64) - l_lo
+                parts = [(i, 1.0 - f), (i + 1, f)]
+            else:
+                raise ValueError(interp)
+            contrib = weights[row, kk] * np.conj(rot) * g
+            for l, c in parts:
+                ok = (l >= 0) & (l < l_count)
+                # n is a permutation of 0..N-1 for a fixed tap, so the fancy-index add is exact
+                out[n[ok], l[ok]] += c[ok] * contrib[ok]
+    return out
+
+
 # ----------------------------------------------------------------------- full-aperture BPA
 def bp_terms(geom, grid, row: int, phi_a, pulse_angles):
     """Visibility, slant range and pattern weight of every (pixel, pulse) pair of one range row:

@@ -311,6 +311,45 @@ def test_adjoint_dot_product_weights(interp):
     assert abs(lhs - rhs) < 1e-12 * (abs(lhs) + 1)
 
 
+@pytest.mark.parametrize("interp", ["nearest", "linear"])
+@pytest.mark.parametrize("corrected", [False, True])
+def test_adjoint_band_identity(interp, corrected):
+    """<g, A Y> = <A^H g, Y> as complex numbers, A = sparse_filter as a linear map of the band."""
+    g, grid, offs, wts, l_lo, yb, dphi, dpsi = _calib_case()
+    if not corrected:
+        dphi = dpsi = None
+    gimg = synth.random_complex((grid.n_range, grid.n_az), 14).astype(np.complex128)
+    img = oracle.sparse_filter(yb, l_lo, g, grid, offs, wts, dphi, dpsi, interp)
+    gy = oracle.sparse_filter_adjoint_band(yb.shape[1], l_lo, g, grid, offs, wts, gimg, dphi, dpsi, interp)
+    lhs = np.sum(np.conj(gimg) * img)
+    rhs = np.sum(np.conj(gy) * yb)
+    assert abs(lhs - rhs) < 1e-12 * (abs(lhs) + 1)
+
+
+@pytest.mark.parametrize("interp", ["nearest", "linear"])
+def test_adjoint_band_brute_force(interp):
+    """Tiny case: the matrix of sparse_filter built column by column from unit band inputs;
+    the adjoint equals conj(A)^T g."""
+    geom = small_geom(16, 32, 0.25)
+    grid = synth.PolarGrid(3, 16, 0.9, 0.11)
+    wl = synth.Workload("adj", 44, geom, grid, synth.SceneSpec(0, "unit", 1, 2), synth.SparseSpec(5, 8, False))
+    offs = synth.make_support(wl)
+    wts = synth.random_complex((grid.n_range, 5), 21).astype(np.complex128)
+    l_lo, l_count = synth.band_for(geom, grid)
+    cols = []
+    for n in range(16):
+        for l in range(l_count):
+            e = np.zeros((16, l_count), dtype=np.complex128)
+            e[n, l] = 1.0
+            cols.append(oracle.sparse_filter(e, l_lo, geom, grid, offs, wts, interp=interp).ravel())
+    a = np.stack(cols, axis=1)                      # [pixels, N * l_count]
+    gimg = synth.random_complex((grid.n_range, grid.n_az), 22).astype(np.complex128)
+    want = (np.conj(a).T @ gimg.ravel()).reshape(16, l_count)
+    got = oracle.sparse_filter_adjoint_band(l_count, l_lo, geom, grid, offs, wts, gimg, interp=interp)
+    np.testing.assert_allclose(got, want, atol=1e-12)
+    assert np.count_nonzero(np.abs(want) > 1e-9) > 10   # the case is not degenerate
+
+
 def test_adjoint_finite_differences_linear():
     """Central differences (h = 1e-4) of L = Re<g, I> in delta, psi and w against the adjoint."""
     g, grid, offs, wts, l_lo, yb, dphi, dpsi = _calib_case()
