@@ -206,6 +206,28 @@ rosar_status rosar_sparse_filter_backward(const rosar_geometry* geom, const rosa
                                           void* workspace, size_t workspace_bytes,
                                           rosar_stream stream);
 
+/* ---------------------------------------------------------------- adjoint w.r.t. the band
+ * The plain sparse filter (Algorithm 2 with eq. 43, no angle or phase errors) is linear in the
+ * range-compressed band: I[r, a] = sum_k conj(w[r, k]) c Y[l_k, (a + o_k) mod N], c = 1 for
+ * NEAREST and 1 - f, f on the two bins of a LINEAR tap (eq. 40).  For a real loss with
+ * grad_image = dL/dRe(I) + j dL/dIm(I) this computes the gradient with respect to the band,
+ *   grad_band[l][n] = sum over taps (r, k) on bin row l_lo + l of
+ *                     w[r, k] c grad_image[r][(n - o_k) mod N],
+ * i.e. A^H grad_image.  rc gives the band layout (l_lo, l_count; its data is not read);
+ * grad_image [n_range][n_az] C64; grad_band [l_count][n_pulses] C64 (dense, no halo), 8-byte
+ * aligned, overwritten.  The workspace (size from the query, 256-byte aligned, caller-owned)
+ * holds the per-row tap lists.  Deterministic (fixed summation order, no atomics on the output).
+ * Errors: as rosar_sparse_filter; UNSUPPORTED if a range row's taps span more than 32 bin rows;
+ * ROSAR_ERR_WORKSPACE for a NULL, misaligned or short workspace. */
+rosar_status rosar_sparse_filter_adjoint_band_workspace_size(const rosar_geometry* geom,
+                                                             const rosar_polar_grid* grid, const rosar_rc_view* rc,
+                                                             const rosar_sparse_set* set, rosar_interp interp,
+                                                             size_t* bytes);
+rosar_status rosar_sparse_filter_adjoint_band(const rosar_geometry* geom, const rosar_polar_grid* grid,
+                                              const rosar_rc_view* rc, const rosar_sparse_set* set,
+                                              rosar_interp interp, const void* grad_image, void* grad_band,
+                                              void* workspace, size_t workspace_bytes, rosar_stream stream);
+
 /* ---------------------------------------------------------------- batched rotations
  * Many independent rotations of uneven sizes imaged by one range-compression launch per FFT
  * length present (one workgroup per 8-pulse tile) and one persistent sparse-filter launch per

@@ -190,7 +190,7 @@ def sparse_filter_adjoint_band(l_count: int, l_lo: int, geom, grid, offsets, wei
             o = int(offsets[row, kk])
             n = (a + o) % n_p
             d0 = o * TWO_PI / n_p
-            d = d0 + (0.0 if dphi is None else dphi[n].astype(np.float64))
+            d = d0 + (np.zeros(n.shape) if dphi is None else dphi[n].astype(np.float64))
             r_hat = slant_range(rr, r, d)
             u = beta * r_hat
             rot = np.ones(n.shape, dtype=np.complex128)

@@ -285,6 +285,31 @@ def sparse_plan_autotune(geom, grid, rc: RangeCompressed, offsets, weights, wind
     return (best.pixels_per_lane, best.waves), float(us.value)
 
 
+def sparse_filter_adjoint_band(geom, grid, layout: RangeCompressed, offsets, weights, window, grad_image,
+                               interp: str = "nearest", out: torch.Tensor | None = None,
+                               workspace: torch.Tensor | None = None) -> torch.Tensor:
+    """Gradient of a real loss with respect to the band read by the plain sparse filter,
+    A^H grad_image (grad_image = dL/dRe(I) + j dL/dIm(I)).  `layout` gives the band rows; returns
+    [l_count, n_pulses] complex64 (the band without its halo copies)."""
+    _need_gpu(grad_image)
+    s = _set(offsets, weights, window)
+    g, p, v = L.geometry(geom), L.polar_grid(grid), layout.view()
+    dev = grad_image.device
+    if out is None:
+        out = torch.empty((layout.l_count, geom.n_pulses), dtype=torch.complex64, device=dev)
+    need = C.c_size_t(0)
+    L.check(L.lib().rosar_sparse_filter_adjoint_band_workspace_size(C.byref(g), C.byref(p), C.byref(v), C.byref(s),
+                                                                    L.INTERP_CODES[interp], C.byref(need)),
+            "rosar_sparse_filter_adjoint_band_workspace_size")
+    if workspace is None:
+        workspace = torch.empty(int(need.value), dtype=torch.uint8, device=dev)
+    L.check(L.lib().rosar_sparse_filter_adjoint_band(C.byref(g), C.byref(p), C.byref(v), C.byref(s),
+                                                     L.INTERP_CODES[interp], _ptr(grad_image.contiguous()), _ptr(out),
+                                                     _ptr(workspace), workspace.numel(), _stream(dev)),
+            "rosar_sparse_filter_adjoint_band")
+    return out
+
+
 class SparsePlan:
     """A sparse-filter plan: one filter design (geometry, grid, offsets, weights, band layout)
     applied to the range-compressed data of many rotations.  `layout` is a RangeCompressed whose

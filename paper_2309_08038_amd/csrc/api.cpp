@@ -344,6 +344,43 @@ rosar_status rosar_sparse_filter_backward_workspace_size(const rosar_geometry* g
   return ok();
 }
 
+rosar_status rosar_sparse_filter_adjoint_band_workspace_size(const rosar_geometry* geom,
+                                                             const rosar_polar_grid* grid, const rosar_rc_view* rc,
+                                                             const rosar_sparse_set* set, rosar_interp interp,
+                                                             size_t* bytes) {
+  rosar::SparseArgs a{};
+  alignas(8) static double placeholder = 0.0;   // no image is involved in the size query
+  ROSAR_TRY(sparse_common(geom, grid, rc, set, nullptr, nullptr, interp, &placeholder, &a));
+  if (!bytes) return fail(ROSAR_ERR_INVALID_ARG, "bytes is NULL");
+  rosar::FcLayout L{};
+  if (!rosar::fc_tap_layout(a, &L))
+    return fail(ROSAR_ERR_UNSUPPORTED, "a range row's taps span more than 32 bin rows");
+  *bytes = rosar::adjoint_band_workspace_bytes(L, grid->n_range);
+  return ok();
+}
+
+rosar_status rosar_sparse_filter_adjoint_band(const rosar_geometry* geom, const rosar_polar_grid* grid,
+                                              const rosar_rc_view* rc, const rosar_sparse_set* set, rosar_interp interp,
+                                              const void* grad_image, void* grad_band, void* workspace,
+                                              size_t workspace_bytes, rosar_stream stream) {
+  rosar::SparseArgs a{};
+  // validate grad_image in the image's place
+  ROSAR_TRY(sparse_common(geom, grid, rc, set, nullptr, nullptr, interp, const_cast<void*>(grad_image), &a));
+  ROSAR_TRY(check_image(grad_band, "grad_band"));
+  rosar::FcLayout L{};
+  if (!rosar::fc_tap_layout(a, &L))
+    return fail(ROSAR_ERR_UNSUPPORTED, "a range row's taps span more than 32 bin rows");
+  const size_t need = rosar::adjoint_band_workspace_bytes(L, grid->n_range);
+  if (!workspace || !aligned(workspace, 256) || workspace_bytes < need)
+    return fail(ROSAR_ERR_WORKSPACE, "workspace must be 256-byte aligned and >= %zu bytes (got %zu)", need,
+                workspace_bytes);
+  if (inject_launch_fault()) return fail(ROSAR_ERR_HIP, "injected launch failure (ROSAR_FAULT_INJECT)");
+  return from_hip(rosar::launch_adjoint_band(a, L, static_cast<const float2*>(grad_image),
+                                             static_cast<float2*>(grad_band), workspace,
+                                             reinterpret_cast<hipStream_t>(stream)),
+                  "adjoint band launch");
+}
+
 rosar_status rosar_sparse_filter_backward(const rosar_geometry* geom, const rosar_polar_grid* grid,
                                           const rosar_rc_view* rc, const rosar_sparse_set* set, const float* dphi,
                                           const float* dpsi, rosar_interp interp, const void* grad_image,

@@ -190,6 +190,17 @@ hipError_t launch_tables_t(const SparseArgs& a, const FcLayout& L, char* tabs, i
 
 }  // namespace
 
+bool fc_tap_layout(const SparseArgs& a, FcLayout* out) {
+  const int rows = sparse::staged_rows_bound(a.g, a.g.n_range, a.window, a.interp, a.y.l_count);
+  if (rows > kFcMaxRows) return false;
+  const int nsub = a.interp == ROSAR_LINEAR ? 2 : 1;
+  out->ne = a.k * nsub;
+  out->row_bytes = 16 * (1 + out->ne);
+  out->rows_cap = kFcMaxRows;
+  out->cos_hw = cos((a.window / 2) * a.g.step);
+  return true;
+}
+
 bool fc_layout(const SparseArgs& a, FcLayout* out) {
   const int n = a.g.n;
   if (n < 2 || n > kFftMaxN) return false;
@@ -204,14 +215,8 @@ bool fc_layout(const SparseArgs& a, FcLayout* out) {
     }
   }
   if (rem != 1) return false;
-  const int rows = sparse::staged_rows_bound(a.g, a.g.n_range, a.window, a.interp, a.y.l_count);
-  if (rows > kFcMaxRows) return false;
-  const int nsub = a.interp == ROSAR_LINEAR ? 2 : 1;
+  if (!fc_tap_layout(a, out)) return false;
   out->f = f;
-  out->ne = a.k * nsub;
-  out->row_bytes = 16 * (1 + out->ne);
-  out->rows_cap = kFcMaxRows;
-  out->cos_hw = cos((a.window / 2) * a.g.step);
   out->lds_bytes = (size_t)n * sizeof(float2) + sizeof(mfft::Twiddles);
   return true;
 }

@@ -103,6 +103,13 @@ struct FcLayout {
   size_t lds_bytes;
 };
 bool fc_layout(const SparseArgs& a, FcLayout* out);
+bool fc_tap_layout(const SparseArgs& a, FcLayout* out);   // tap-list fields only (any N)
+
+// Adjoint of the plain sparse filter with respect to the band (per band row, a gather over the
+// range rows whose taps read it): tap lists in the workspace, then the gather.
+size_t adjoint_band_workspace_bytes(const FcLayout& L, int32_t n_range);
+hipError_t launch_adjoint_band(const SparseArgs& a, const FcLayout& L, const float2* grad_image, float2* grad_band,
+                               void* ws, hipStream_t s);
 size_t fc_spectrum_bytes(const SparseArgs& a);
 int fc_twiddle_count(int n);
 void fc_twiddles(int n, float2* host_tw);   // fc_twiddle_count(n) entries

@@ -298,3 +298,31 @@ def test_fastconv_plan_rejections(lib):
         st, _ = plan_create(lib, g=g, grid=grid, view=view, tile=L.Tile(3, 0, 0, 0))
         assert st == L.ROSAR_ERR_UNSUPPORTED, n
         assert "2^a 3^b 5^c" in lib.rosar_last_error().decode()
+
+
+def test_adjoint_band_validation(lib):
+    g, grid = geom(), L.PolarGrid(8, 360, 1.0, 0.05)
+    view = L.RcView(0x20000, L.C64, 0, 64, 32, 424, 1.0, 0)
+    sset = L.SparseSet(32, 64, 0x30000, 0x40000, L.C64, 0)
+    n = C.c_size_t(0)
+    assert lib.rosar_sparse_filter_adjoint_band_workspace_size(C.byref(g), C.byref(grid), C.byref(view),
+                                                               C.byref(sset), L.NEAREST, C.byref(n)) == L.ROSAR_OK
+    assert n.value >= 8 * (16 + 32 * 16)      # one tap list per range row
+    m = C.c_size_t(0)
+    assert lib.rosar_sparse_filter_adjoint_band_workspace_size(C.byref(g), C.byref(grid), C.byref(view),
+                                                               C.byref(sset), L.LINEAR, C.byref(m)) == L.ROSAR_OK
+    assert m.value > n.value                  # LINEAR taps touch two bins
+    assert lib.rosar_sparse_filter_adjoint_band_workspace_size(C.byref(g), C.byref(grid), C.byref(view),
+                                                               C.byref(sset), L.NEAREST, None) == L.ROSAR_ERR_INVALID_ARG
+
+    def call(gimg=FAKE, gband=FAKE, ws=FAKE, nb=None, interp=L.NEAREST):
+        return lib.rosar_sparse_filter_adjoint_band(C.byref(g), C.byref(grid), C.byref(view), C.byref(sset), interp,
+                                                    gimg, gband, ws, n.value if nb is None else nb, None)
+
+    assert call(gimg=None) == L.ROSAR_ERR_INVALID_ARG
+    assert call(gband=None) == L.ROSAR_ERR_INVALID_ARG
+    assert call(gband=C.c_void_p(0x10004)) == L.ROSAR_ERR_INVALID_ARG
+    assert call(interp=9) == L.ROSAR_ERR_INVALID_ARG
+    for ws, nb in [(None, n.value), (C.c_void_p(0x10010), n.value), (FAKE, n.value - 1)]:
+        assert call(ws=ws, nb=nb) == L.ROSAR_ERR_WORKSPACE
+        assert lib.rosar_last_error().decode() != ""

@@ -327,6 +327,24 @@ def test_adjoint_band_identity(interp, corrected):
 
 
 @pytest.mark.parametrize("interp", ["nearest", "linear"])
+def test_adjoint_band_identity_narrow_band(interp):
+    """The identity with a band narrower than the bins the taps read (those taps contribute
+    nothing to either side)."""
+    w = synth.small()
+    x = synth.make_inputs(w)
+    g, grid = w.geometry, w.grid
+    lo, cnt = x.l_lo + 20, 15
+    yb = synth.random_complex((g.n_pulses, cnt), 31).astype(np.complex128)
+    gimg = synth.random_complex((grid.n_range, grid.n_az), 32).astype(np.complex128)
+    img = oracle.sparse_filter(yb, lo, g, grid, x.offsets, x.weights, interp=interp)
+    gy = oracle.sparse_filter_adjoint_band(cnt, lo, g, grid, x.offsets, x.weights, gimg, interp=interp)
+    assert np.count_nonzero(img) < img.size            # some rows read nothing
+    lhs = np.sum(np.conj(gimg) * img)
+    rhs = np.sum(np.conj(gy) * yb)
+    assert abs(lhs - rhs) < 1e-12 * (abs(lhs) + 1)
+
+
+@pytest.mark.parametrize("interp", ["nearest", "linear"])
 def test_adjoint_band_brute_force(interp):
     """Tiny case: the matrix of sparse_filter built column by column from unit band inputs;
     the adjoint equals conj(A)^T g."""
