@@ -325,7 +325,14 @@ def extras(torch, rs, synth, w, x, dev, rc, off, wts, timed, reps):
                                           workspace=ws, out=grads)
     b()
     out["adjoint_us"] = 1000 * timed(b, 3, inner=2, out=lambda: grads[0])
-    print(f"[bench] corrected forward {out['corrected_forward_us']:.1f} us, adjoint {out['adjoint_us']:.1f} us",
+    # adjoint with respect to the band (plain filter, NEAREST): per band row a gather
+    gband = torch.empty((x.l_count, n), dtype=torch.complex64, device=dev)
+    wsb = torch.empty(1 << 22, dtype=torch.uint8, device=dev)
+    ab = lambda: rs.sparse_filter_adjoint_band(g, grid, rc, off, wts, w.sparse.window, gimg, out=gband, workspace=wsb)
+    ab()
+    out["adjoint_band_us"] = 1000 * timed(ab, 3, inner=5, out=lambda: gband)
+    print(f"[bench] corrected forward {out['corrected_forward_us']:.1f} us, adjoint {out['adjoint_us']:.1f} us, "
+          f"adjoint w.r.t. the band {out['adjoint_band_us']:.1f} us",
           file=sys.stderr, flush=True)
 
     # sparse-plan variants on the same rotation: the direct sum with LINEAR sampling, and the
