@@ -9,7 +9,13 @@
 // expression as the forward filter's tables) are written to the caller's workspace first; then
 // one workgroup per (band row, pulse tile) marks the contributing range rows in an LDS bitmask
 // and walks them in increasing order, so the sum order is fixed and results are reproducible.
+// The staged form copies, batch by batch, the gradient rows of the contributing range rows over
+// the columns the tile's taps reach ([n0 - W/2, n0 + T + W/2], modulo N) into LDS; the direct
+// form (kept for windows too wide for one staged row) reads them from global memory.  Both add
+// the same terms in the same order.
 #include <hip/hip_runtime.h>
+
+#include <algorithm>
 
 #include "rosar_device.hpp"
 
@@ -75,6 +81,132 @@ __global__ __launch_bounds__(kAdjThreads) void adjoint_band_kernel(int n, int n_
   }
 }
 
+constexpr int kAdjMaxRows = 8;            // staged gradient rows per batch
+constexpr size_t kAdjLdsBudget = 40 * 1024;
+constexpr int kAdjWaves = kAdjThreads / kWave;
+
+__host__ __device__ constexpr int rows_words(int n_range) { return ((n_range + 31) / 32 + 3) & ~3; }
+
+// Staged form.  Dynamic LDS: the row mask (rows_words words), then cap * ne compacted taps
+// {LDS offset of the tap's first sample, coef.x, coef.y, 0}, then cap staged gradient rows.
+__global__ __launch_bounds__(kAdjThreads) void adjoint_band_staged_kernel(int n, int n_range, int tiles, int half_w,
+                                                                          int cap, int ne, const char* __restrict__ tabs,
+                                                                          int row_bytes,
+                                                                          const float2* __restrict__ grad_image,
+                                                                          float2* __restrict__ grad_band) {
+  extern __shared__ uint32_t s_rows[];
+  __shared__ int s_list[kAdjMaxRows];
+  __shared__ int s_rel[kAdjMaxRows];
+  __shared__ int s_wcnt[kAdjWaves];
+  __shared__ int s_cnt, s_cur_w, s_ntaps;
+  __shared__ unsigned s_cur_m;
+  const int l = blockIdx.x / tiles;
+  const int n0 = (blockIdx.x % tiles) * kAdjTile;
+  const int tid = threadIdx.x;
+  const int lane = tid & (kWave - 1);
+  const int wave = tid / kWave;
+  const int words = (n_range + 31) / 32;
+  const int width = kAdjTile + 2 * half_w + 1;   // staged columns n0 - half_w + [0, width)
+  int4* taps = reinterpret_cast<int4*>(s_rows + rows_words(n_range));
+  float2* stage = reinterpret_cast<float2*>(taps + cap * ne);
+  for (int i = tid; i < words; i += kAdjThreads) s_rows[i] = 0u;
+  __syncthreads();
+  for (int r = tid; r < n_range; r += kAdjThreads) {
+    const int4 h = *reinterpret_cast<const int4*>(tabs + (size_t)r * row_bytes);
+    const int rel = l - h.x;
+    if (rel >= 0 && rel < 32 && ((unsigned)h.y >> rel) & 1u) atomicOr(&s_rows[r >> 5], 1u << (r & 31));
+  }
+  __syncthreads();
+  if (tid == 0) {
+    s_cur_w = 0;
+    s_cur_m = s_rows[0];
+  }
+
+  float2 acc[kAdjP];
+#pragma unroll
+  for (int p = 0; p < kAdjP; ++p) acc[p] = make_float2(0.f, 0.f);
+  while (true) {
+    // the next batch of contributing rows, in increasing order (thread 0 advances the cursor)
+    if (tid == 0) {
+      int cnt = 0, w_ = s_cur_w;
+      unsigned m_ = s_cur_m;
+      while (cnt < cap) {
+        while (m_ == 0u && w_ + 1 < words) m_ = s_rows[++w_];
+        if (m_ == 0u) break;
+        const int r = w_ * 32 + __builtin_ctz(m_);
+        s_list[cnt] = r;
+        s_rel[cnt] = l - reinterpret_cast<const int4*>(tabs + (size_t)r * row_bytes)->x;
+        ++cnt;
+        m_ &= m_ - 1u;
+      }
+      s_cnt = cnt;
+      s_cur_w = w_;
+      s_cur_m = m_;
+      s_ntaps = 0;
+    }
+    __syncthreads();
+    const int cnt = s_cnt;
+    if (cnt == 0) break;
+    // stage the gradient rows
+    for (int slot = 0; slot < cnt; ++slot) {
+      const float2* grow = grad_image + (size_t)s_list[slot] * n;
+      for (int i = tid; i < width; i += kAdjThreads) stage[slot * width + i] = grow[(n0 - half_w + i + n) % n];
+    }
+    // compact the batch's taps on band row l, in (row, entry) order: a ballot per wave, the
+    // waves' counts added in wave order
+    const int total = cnt * ne;
+    for (int base = 0; base < total; base += kAdjThreads) {
+      const int idx = base + tid;
+      int4 t = make_int4(0, -1, 0, 0);
+      int slot = 0;
+      if (idx < total) {
+        slot = idx / ne;
+        t = reinterpret_cast<const int4*>(tabs + (size_t)s_list[slot] * row_bytes)[1 + idx - slot * ne];
+      }
+      const bool match = idx < total && t.y == s_rel[slot];
+      const uint64_t bal = __ballot(match);
+      const int before = __popcll(bal & ((1ull << lane) - 1ull));
+      if (lane == 0) s_wcnt[wave] = __popcll(bal);
+      __syncthreads();
+      int off = s_ntaps;
+      for (int w2 = 0; w2 < wave; ++w2) off += s_wcnt[w2];
+      if (match) {
+        const int o = t.x < half_w ? t.x : t.x - n;   // tap offset in [-W/2, W/2)
+        // the table holds conj(w) c; the adjoint applies w c
+        taps[off + before] = make_int4(slot * width + half_w - o, t.z, __float_as_int(-__int_as_float(t.w)), 0);
+      }
+      __syncthreads();
+      if (tid == 0) {
+        int sum = 0;
+        for (int w2 = 0; w2 < kAdjWaves; ++w2) sum += s_wcnt[w2];
+        s_ntaps += sum;
+      }
+      __syncthreads();
+    }
+    const int ntaps = s_ntaps;
+    for (int e = 0; e < ntaps; ++e) {
+      const int4 t = taps[e];
+      const float cx = __int_as_float(t.y), cy = __int_as_float(t.z);
+#pragma unroll
+      for (int p = 0; p < kAdjP; ++p) {
+        const int np = n0 + tid + p * kAdjThreads;
+        if (np < n) {
+          const float2 gv = stage[t.x + tid + p * kAdjThreads];
+          acc[p].x = fmaf(cx, gv.x, fmaf(-cy, gv.y, acc[p].x));
+          acc[p].y = fmaf(cx, gv.y, fmaf(cy, gv.x, acc[p].y));
+        }
+      }
+    }
+    __syncthreads();   // the next batch overwrites the stage, the taps and the list
+  }
+  float2* out = grad_band + (size_t)l * n;
+#pragma unroll
+  for (int p = 0; p < kAdjP; ++p) {
+    const int np = n0 + tid + p * kAdjThreads;
+    if (np < n) out[np] = acc[p];
+  }
+}
+
 }  // namespace
 
 size_t adjoint_band_workspace_bytes(const FcLayout& L, int32_t n_range) {
@@ -88,9 +220,17 @@ hipError_t launch_adjoint_band(const SparseArgs& a, const FcLayout& L, const flo
   hipError_t e = launch_fc_tables(a, L, tabs, bad, s);
   if (e != hipSuccess) return e;
   const int tiles = (a.g.n + kAdjTile - 1) / kAdjTile;
-  const size_t lds = (size_t)((a.g.n_range + 31) / 32) * sizeof(uint32_t);
-  adjoint_band_kernel<<<a.y.l_count * tiles, kAdjThreads, lds, s>>>(a.g.n, a.g.n_range, tiles, tabs, L.row_bytes,
-                                                                    grad_image, grad_band);
+  const int half_w = a.window / 2;
+  const size_t mask_bytes = (size_t)rows_words(a.g.n_range) * sizeof(uint32_t);
+  const size_t per_row = (size_t)(kAdjTile + 2 * half_w + 1) * sizeof(float2) + (size_t)L.ne * sizeof(int4);
+  const int cap = mask_bytes >= kAdjLdsBudget ? 0 : (int)std::min<size_t>(kAdjMaxRows, (kAdjLdsBudget - mask_bytes) / per_row);
+  if (cap >= 1) {
+    adjoint_band_staged_kernel<<<a.y.l_count * tiles, kAdjThreads, mask_bytes + (size_t)cap * per_row, s>>>(
+        a.g.n, a.g.n_range, tiles, half_w, cap, L.ne, tabs, L.row_bytes, grad_image, grad_band);
+  } else {
+    adjoint_band_kernel<<<a.y.l_count * tiles, kAdjThreads, mask_bytes, s>>>(a.g.n, a.g.n_range, tiles, tabs,
+                                                                             L.row_bytes, grad_image, grad_band);
+  }
   return hipGetLastError();
 }
 
