@@ -4,10 +4,11 @@ C ABI of librosar.so (include/rosar.h)."""
 from ._lib import RosarError, LIB_PATH, lib
 from .api import (BatchPlan, RangeCompressed, Rotation, SparseFilterFn, SparsePlan, autotune_sparse_filter,
                   backward_workspace_bytes, batch_autotune, bp_full, bp_workspace_bytes, empty_rc, range_compress,
-                  sparse_filter, sparse_filter_adjoint_band, sparse_filter_backward, sparse_filter_diff,
+                  sparse_filter, sparse_filter_adjoint_band, sparse_filter_backward, sparse_filter_band_diff,
+                  sparse_filter_diff,
                   sparse_plan_autotune, weights_f16)
 
 __all__ = ["RosarError", "LIB_PATH", "lib", "BatchPlan", "RangeCompressed", "Rotation", "SparseFilterFn",
            "SparsePlan", "autotune_sparse_filter", "backward_workspace_bytes", "batch_autotune", "bp_full",
-           "bp_workspace_bytes", "empty_rc", "range_compress", "sparse_filter", "sparse_filter_adjoint_band", "sparse_filter_backward",
+           "bp_workspace_bytes", "empty_rc", "range_compress", "sparse_filter", "sparse_filter_adjoint_band", "sparse_filter_backward", "sparse_filter_band_diff",
            "sparse_filter_diff", "sparse_plan_autotune", "weights_f16"]

@@ -216,6 +216,38 @@ def sparse_filter_diff(geom, grid, rc, offsets, weights, window, dphi, dpsi, int
     return SparseFilterFn.apply(weights, dphi, dpsi, geom, grid, rc, offsets, window, interp)
 
 
+class SparseFilterBandFn(torch.autograd.Function):
+    """image = sparse_filter(band) for the plain filter, differentiable with respect to the
+    range-compressed band [l_count, N] (complex64); backward is the band adjoint A^H g.  The
+    weights and offsets are constants here."""
+
+    @staticmethod
+    def forward(ctx, band, geom, grid, l_lo, offsets, weights, window, interp):
+        n = geom.n_pulses
+        halo = window // 2
+        rc = empty_rc(n, l_lo, band.shape[0], halo=halo, device=band.device)
+        b = band.detach().contiguous()
+        # the filter reads the band in its stored layout: pulses with circular halo copies
+        rc.data[:, halo:halo + n].copy_(b)
+        if halo:
+            rc.data[:, :halo].copy_(b[:, n - halo:])
+            rc.data[:, halo + n:].copy_(b[:, :halo])
+        img = sparse_filter(geom, grid, rc, offsets, weights, window, interp=interp)
+        ctx.cfg = (geom, grid, rc, offsets, weights, window, interp)
+        return img
+
+    @staticmethod
+    def backward(ctx, grad_img):
+        geom, grid, rc, offsets, weights, window, interp = ctx.cfg
+        gb = sparse_filter_adjoint_band(geom, grid, rc, offsets, weights, window, grad_img.contiguous(), interp=interp)
+        return gb, None, None, None, None, None, None, None
+
+
+def sparse_filter_band_diff(geom, grid, band, l_lo, offsets, weights, window, interp="nearest"):
+    """Plain sparse filter differentiable with respect to the band [l_count, N] (complex64)."""
+    return SparseFilterBandFn.apply(band, geom, grid, l_lo, offsets, weights, window, interp)
+
+
 def autotune_sparse_filter(geom, grid, rc: RangeCompressed, offsets, weights, window, reps: int = 20,
                            out: torch.Tensor | None = None):
     """Time every launch shape of the plain sparse filter; returns ((variant, ppl, waves), microseconds)."""

@@ -91,3 +91,24 @@ def test_adjoint_band_identity_with_gpu_forward(interp):
     lhs = np.sum(np.conj(gimg.astype(np.complex128)) * img.astype(np.complex128))
     rhs = np.sum(np.conj(gy) * band)
     assert abs(lhs - rhs) <= 1e-5 * abs(lhs)
+
+
+@pytest.mark.parametrize("interp", ["nearest", "linear"])
+def test_band_autograd(interp):
+    """torch.autograd through the plain filter with respect to the band: for
+    L = Re(sum conj(c) I), dL/dRe(I) + j dL/dIm(I) = c, so band.grad = A^H c (oracle)."""
+    rs = need_gpu()
+    w, x = inputs("small")
+    yb = oracle_band("small")
+    band = to_dev(yb.T.astype(np.complex64)).requires_grad_(True)        # [l_count, N]
+    c = synth.random_complex((w.grid.n_range, w.grid.n_az), 78).astype(np.complex64)
+    log(f"band autograd {interp}")
+    img = rs.sparse_filter_band_diff(w.geometry, w.grid, band, x.l_lo, to_dev(x.offsets),
+                                     to_dev(x.weights.astype(np.complex64)), w.sparse.window, interp=interp)
+    ref_img = oracle.sparse_filter(yb, x.l_lo, w.geometry, w.grid, x.offsets, x.weights, interp=interp)
+    assert rel_l2(img.detach().cpu().numpy(), ref_img) <= 1e-4
+    loss = torch.real(torch.sum(torch.conj(to_dev(c)) * img))
+    loss.backward()
+    want = oracle.sparse_filter_adjoint_band(x.l_count, x.l_lo, w.geometry, w.grid, x.offsets, x.weights, c,
+                                             interp=interp)
+    assert rel_l2(band.grad.cpu().numpy(), want.T) <= TOL_GRAD
