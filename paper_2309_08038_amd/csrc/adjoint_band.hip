@@ -84,12 +84,14 @@ __global__ __launch_bounds__(kAdjThreads) void adjoint_band_kernel(int n, int n_
 constexpr int kAdjMaxRows = 8;            // staged gradient rows per batch
 constexpr size_t kAdjLdsBudget = 40 * 1024;
 constexpr int kAdjWaves = kAdjThreads / kWave;
+constexpr int kAdjTilesPer = 1;           // pulse tiles of one band row per workgroup (4: 190 us, too few workgroups)
 
 __host__ __device__ constexpr int rows_words(int n_range) { return ((n_range + 31) / 32 + 3) & ~3; }
 
 // Staged form.  Dynamic LDS: the row mask (rows_words words), then cap * ne compacted taps
 // {LDS offset of the tap's first sample, coef.x, coef.y, 0}, then cap staged gradient rows.
-__global__ __launch_bounds__(kAdjThreads) void adjoint_band_staged_kernel(int n, int n_range, int tiles, int half_w,
+__global__ __launch_bounds__(kAdjThreads) void adjoint_band_staged_kernel(int n, int n_range, int tiles, int groups,
+                                                                          int half_w,
                                                                           int cap, int ne, const char* __restrict__ tabs,
                                                                           int row_bytes,
                                                                           const float2* __restrict__ grad_image,
@@ -100,13 +102,13 @@ __global__ __launch_bounds__(kAdjThreads) void adjoint_band_staged_kernel(int n,
   __shared__ int s_wcnt[kAdjWaves];
   __shared__ int s_cnt, s_cur_w, s_ntaps;
   __shared__ unsigned s_cur_m;
-  const int l = blockIdx.x / tiles;
-  const int n0 = (blockIdx.x % tiles) * kAdjTile;
+  const int l = blockIdx.x / groups;
+  const int tile0 = (blockIdx.x % groups) * kAdjTilesPer;   // this workgroup's tiles: tile0 + [0, kAdjTilesPer)
   const int tid = threadIdx.x;
   const int lane = tid & (kWave - 1);
   const int wave = tid / kWave;
   const int words = (n_range + 31) / 32;
-  const int width = kAdjTile + 2 * half_w + 1;   // staged columns n0 - half_w + [0, width)
+  const int width = kAdjTile + 2 * half_w + 1;   // staged columns of a tile: n0 - half_w + [0, width)
   int4* taps = reinterpret_cast<int4*>(s_rows + rows_words(n_range));
   float2* stage = reinterpret_cast<float2*>(taps + cap * ne);
   for (int i = tid; i < words; i += kAdjThreads) s_rows[i] = 0u;
@@ -122,9 +124,11 @@ __global__ __launch_bounds__(kAdjThreads) void adjoint_band_staged_kernel(int n,
     s_cur_m = s_rows[0];
   }
 
-  float2 acc[kAdjP];
+  float2 acc[kAdjTilesPer][kAdjP];
 #pragma unroll
-  for (int p = 0; p < kAdjP; ++p) acc[p] = make_float2(0.f, 0.f);
+  for (int tt = 0; tt < kAdjTilesPer; ++tt)
+#pragma unroll
+    for (int p = 0; p < kAdjP; ++p) acc[tt][p] = make_float2(0.f, 0.f);
   while (true) {
     // the next batch of contributing rows, in increasing order (thread 0 advances the cursor)
     if (tid == 0) {
@@ -147,11 +151,6 @@ __global__ __launch_bounds__(kAdjThreads) void adjoint_band_staged_kernel(int n,
     __syncthreads();
     const int cnt = s_cnt;
     if (cnt == 0) break;
-    // stage the gradient rows
-    for (int slot = 0; slot < cnt; ++slot) {
-      const float2* grow = grad_image + (size_t)s_list[slot] * n;
-      for (int i = tid; i < width; i += kAdjThreads) stage[slot * width + i] = grow[(n0 - half_w + i + n) % n];
-    }
     // compact the batch's taps on band row l, in (row, entry) order: a ballot per wave, the
     // waves' counts added in wave order
     const int total = cnt * ne;
@@ -184,26 +183,41 @@ __global__ __launch_bounds__(kAdjThreads) void adjoint_band_staged_kernel(int n,
       __syncthreads();
     }
     const int ntaps = s_ntaps;
-    for (int e = 0; e < ntaps; ++e) {
-      const int4 t = taps[e];
-      const float cx = __int_as_float(t.y), cy = __int_as_float(t.z);
+    // the batch's taps applied to each tile: stage the rows' gradient columns, then accumulate
 #pragma unroll
-      for (int p = 0; p < kAdjP; ++p) {
-        const int np = n0 + tid + p * kAdjThreads;
-        if (np < n) {
-          const float2 gv = stage[t.x + tid + p * kAdjThreads];
-          acc[p].x = fmaf(cx, gv.x, fmaf(-cy, gv.y, acc[p].x));
-          acc[p].y = fmaf(cx, gv.y, fmaf(cy, gv.x, acc[p].y));
+    for (int tt = 0; tt < kAdjTilesPer; ++tt) {
+      const int tile = tile0 + tt;
+      if (tile >= tiles) break;   // block-uniform
+      const int n0 = tile * kAdjTile;
+      for (int slot = 0; slot < cnt; ++slot) {
+        const float2* grow = grad_image + (size_t)s_list[slot] * n;
+        for (int i = tid; i < width; i += kAdjThreads) stage[slot * width + i] = grow[(n0 - half_w + i + n) % n];
+      }
+      __syncthreads();
+      for (int e = 0; e < ntaps; ++e) {
+        const int4 t = taps[e];
+        const float cx = __int_as_float(t.y), cy = __int_as_float(t.z);
+#pragma unroll
+        for (int p = 0; p < kAdjP; ++p) {
+          const int np = n0 + tid + p * kAdjThreads;
+          if (np < n) {
+            const float2 gv = stage[t.x + tid + p * kAdjThreads];
+            acc[tt][p].x = fmaf(cx, gv.x, fmaf(-cy, gv.y, acc[tt][p].x));
+            acc[tt][p].y = fmaf(cx, gv.y, fmaf(cy, gv.x, acc[tt][p].y));
+          }
         }
       }
+      __syncthreads();   // the next tile or batch overwrites the stage (and the taps and list)
     }
-    __syncthreads();   // the next batch overwrites the stage, the taps and the list
   }
   float2* out = grad_band + (size_t)l * n;
 #pragma unroll
-  for (int p = 0; p < kAdjP; ++p) {
-    const int np = n0 + tid + p * kAdjThreads;
-    if (np < n) out[np] = acc[p];
+  for (int tt = 0; tt < kAdjTilesPer; ++tt) {
+#pragma unroll
+    for (int p = 0; p < kAdjP; ++p) {
+      const int np = (tile0 + tt) * kAdjTile + tid + p * kAdjThreads;
+      if (tile0 + tt < tiles && np < n) out[np] = acc[tt][p];
+    }
   }
 }
 
@@ -225,8 +239,9 @@ hipError_t launch_adjoint_band(const SparseArgs& a, const FcLayout& L, const flo
   const size_t per_row = (size_t)(kAdjTile + 2 * half_w + 1) * sizeof(float2) + (size_t)L.ne * sizeof(int4);
   const int cap = mask_bytes >= kAdjLdsBudget ? 0 : (int)std::min<size_t>(kAdjMaxRows, (kAdjLdsBudget - mask_bytes) / per_row);
   if (cap >= 1) {
-    adjoint_band_staged_kernel<<<a.y.l_count * tiles, kAdjThreads, mask_bytes + (size_t)cap * per_row, s>>>(
-        a.g.n, a.g.n_range, tiles, half_w, cap, L.ne, tabs, L.row_bytes, grad_image, grad_band);
+    const int groups = (tiles + kAdjTilesPer - 1) / kAdjTilesPer;
+    adjoint_band_staged_kernel<<<a.y.l_count * groups, kAdjThreads, mask_bytes + (size_t)cap * per_row, s>>>(
+        a.g.n, a.g.n_range, tiles, groups, half_w, cap, L.ne, tabs, L.row_bytes, grad_image, grad_band);
   } else {
     adjoint_band_kernel<<<a.y.l_count * tiles, kAdjThreads, mask_bytes, s>>>(a.g.n, a.g.n_range, tiles, tabs,
                                                                              L.row_bytes, grad_image, grad_band);
