@@ -66,8 +66,10 @@ typedef enum rosar_dtype {
 
 typedef enum rosar_interp { ROSAR_NEAREST = 0, ROSAR_LINEAR = 1 } rosar_interp;
 
-/* Radar and rotation (paper Table I/II notation).  n_fft (L) must be a power of two in
- * [64, 2048] with L >= n_fast (M); zero padding when L > M (eq. 38). */
+/* Radar and rotation (paper Table I/II notation).  n_fft (L) >= n_fast (M); zero padding when
+ * L > M (eq. 38).  rosar_range_compress takes L a power of two in [64, 2048] (wave-per-pulse
+ * kernels) or any L = 2^a 3^b 5^c <= 8192 (a workgroup per pulse, e.g. M = L = 225); batches
+ * take powers of two in [64, 2048]. */
 typedef struct rosar_geometry {
   int32_t n_pulses;   /* N: pulses per rotation, >= 2 */
   int32_t n_fast;     /* M: fast-time samples per pulse, >= 1 */

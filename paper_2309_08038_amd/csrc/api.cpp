@@ -67,9 +67,18 @@ rosar_status check_geometry(const rosar_geometry* g) {
   return ROSAR_OK;
 }
 
+// Batched range compression: power-of-two FFT lengths in [64, 2048].
 rosar_status check_fft(const rosar_geometry* g) {
   if (!pow2(g->n_fft) || g->n_fft < 64 || g->n_fft > 2048)
     return fail(ROSAR_ERR_UNSUPPORTED, "n_fft must be a power of two in [64, 2048] (got %d)", g->n_fft);
+  return ROSAR_OK;
+}
+
+// Single-rotation range compression: also any 2^a 3^b 5^c <= 8192 (mixed-radix path).
+rosar_status check_fft_single(const rosar_geometry* g) {
+  if (!rosar::range_compress_length_supported(g->n_fft))
+    return fail(ROSAR_ERR_UNSUPPORTED,
+                "n_fft must be a power of two in [64, 2048] or 2^a 3^b 5^c <= 8192 (got %d)", g->n_fft);
   return ROSAR_OK;
 }
 
@@ -227,7 +236,7 @@ rosar_status rosar_range_compress(const rosar_geometry* geom, const void* raw, c
                                   int32_t l_lo, int32_t l_count, int32_t halo, rosar_dtype out_dtype,
                                   float out_scale, void* y_t, int64_t ld, rosar_stream stream) {
   ROSAR_TRY(check_geometry(geom));
-  ROSAR_TRY(check_fft(geom));
+  ROSAR_TRY(check_fft_single(geom));
   if (!raw || !aligned(raw, 8)) return fail(ROSAR_ERR_INVALID_ARG, "raw NULL or misaligned");
   if (window && !aligned(window, 4)) return fail(ROSAR_ERR_INVALID_ARG, "window misaligned");
   if (!dtype_valid(out_dtype)) return fail(ROSAR_ERR_INVALID_ARG, "out_dtype %d is not a rosar_dtype", (int)out_dtype);

@@ -201,8 +201,7 @@ bool fc_tap_layout(const SparseArgs& a, FcLayout* out) {
   return true;
 }
 
-bool fc_layout(const SparseArgs& a, FcLayout* out) {
-  const int n = a.g.n;
+bool fft_factors(int n, FftFactors* out) {
   if (n < 2 || n > kFftMaxN) return false;
   FftFactors f{};
   f.n = n;
@@ -215,9 +214,16 @@ bool fc_layout(const SparseArgs& a, FcLayout* out) {
     }
   }
   if (rem != 1) return false;
+  *out = f;
+  return true;
+}
+
+bool fc_layout(const SparseArgs& a, FcLayout* out) {
+  FftFactors f{};
+  if (!fft_factors(a.g.n, &f)) return false;
   if (!fc_tap_layout(a, out)) return false;
   out->f = f;
-  out->lds_bytes = (size_t)n * sizeof(float2) + sizeof(mfft::Twiddles);
+  out->lds_bytes = (size_t)a.g.n * sizeof(float2) + sizeof(mfft::Twiddles);
   return true;
 }
 

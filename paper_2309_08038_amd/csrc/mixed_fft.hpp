@@ -41,6 +41,19 @@ __device__ __forceinline__ void load_twiddles(Twiddles& t, const float2* __restr
   }
 }
 
+// The same tables evaluated in the kernel (float32 sincospi of the exact ratio t / N), for
+// callers without a host-built table.
+__device__ __forceinline__ void make_twiddles(Twiddles& t, int n, int tid) {
+  const int cnt = twiddle_count(n);
+  for (int i = tid; i < cnt; i += kFftThreads) {
+    const int tt = i < kTwLo ? i : (i - kTwLo) * kTwLo;
+    float sn, cs;
+    sincospif(-2.0f * (float)tt / (float)n, &sn, &cs);
+    if (i < kTwLo) t.lo[i] = make_float2(cs, sn);
+    else t.hi[i - kTwLo] = make_float2(cs, sn);
+  }
+}
+
 // j * z for DIR = +1, -j * z for DIR = -1.
 template <int DIR>
 __device__ __forceinline__ float2 rot90(float2 z) {

@@ -57,6 +57,9 @@ struct Tile {
 };
 
 // Launchers (kernels live in the .hip files).  Each returns hipGetLastError() after launching.
+// Range compression: power-of-two L in [64, 2048] by the radix-8/4/2 wave kernels, any other
+// 2^a 3^b 5^c <= 8192 by the mixed-radix workgroup kernel.
+bool range_compress_length_supported(int32_t l);
 hipError_t launch_range_compress(const RcArgs& a, hipStream_t s);
 hipError_t launch_sparse_plain(const SparseArgs& a, const Tile& t, hipStream_t s);
 hipError_t launch_sparse_corrected(const SparseArgs& a, hipStream_t s);
@@ -102,6 +105,7 @@ struct FcLayout {
   double cos_hw;
   size_t lds_bytes;
 };
+bool fft_factors(int n, FftFactors* out);   // n = 2^a 3^b 5^c <= 8192 (radix 8, 4, 2, 5, 3 passes)
 bool fc_layout(const SparseArgs& a, FcLayout* out);
 bool fc_tap_layout(const SparseArgs& a, FcLayout* out);   // tap-list fields only (any N)
 

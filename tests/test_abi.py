@@ -80,8 +80,8 @@ def rc_call(lib, g, **kw):
 
 @pytest.mark.parametrize("kw,status", [
     (dict(n_pulses=1), L.ROSAR_ERR_INVALID_ARG),
-    (dict(n_fft=100, n_fast=100), L.ROSAR_ERR_UNSUPPORTED),
-    (dict(n_fft=4096, n_fast=4096), L.ROSAR_ERR_UNSUPPORTED),
+    (dict(n_fft=98, n_fast=98), L.ROSAR_ERR_UNSUPPORTED),      # 2 x 7^2: no mixed-radix path
+    (dict(n_fft=9000, n_fast=9000), L.ROSAR_ERR_UNSUPPORTED),  # over the 8192-point workgroup FFT
     (dict(n_fft=128, n_fast=256), L.ROSAR_ERR_INVALID_ARG),
     (dict(radius_m=float("nan")), L.ROSAR_ERR_INVALID_ARG),
     (dict(radius_m=-1.0), L.ROSAR_ERR_INVALID_ARG),

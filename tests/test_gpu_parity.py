@@ -52,9 +52,12 @@ def test_range_compress_small(dtype):
     assert torch.equal(d[:, :32], d[:, n:n + 32]) and torch.equal(d[:, n + 32:n + 64], d[:, 32:64])
 
 
-@pytest.mark.parametrize("n,m,l", [(100, 200, 256), (70, 64, 64), (64, 2048, 2048), (129, 1000, 1024)])
+@pytest.mark.parametrize("n,m,l", [(100, 200, 256), (70, 64, 64), (64, 2048, 2048), (129, 1000, 1024),
+                                   # mixed-radix path: the paper's M = L = 225, other 2^a 3^b 5^c, 4096
+                                   (800, 225, 225), (37, 90, 100), (40, 3000, 4096), (20, 7000, 7200)])
 def test_range_compress_shapes(n, m, l):
-    """Zero padding (M < L), the smallest and largest FFT, ragged pulse counts."""
+    """Zero padding (M < L), the smallest and largest FFT, ragged pulse counts, and lengths of
+    the mixed-radix path."""
     rs = need_gpu()
     log(f"range_compress N={n} M={m} L={l}")
     g = synth.Geometry(n, m, l, 0.25, 77e9, 4e9 * 1e7 / m, 1e7)
@@ -69,6 +72,46 @@ def test_range_compress_shapes(n, m, l):
     rc2 = rs.range_compress(g, to_dev(raw), None, 0, l, halo=0)
     torch.cuda.synchronize()
     assert rel_l2(rc2.pulses(n).cpu().numpy().T, oracle.range_compress(raw, None, l)) <= 1e-5
+
+
+def test_range_compress_mixed_f16():
+    """Mixed-radix path with FP16 storage and a power-of-two scale."""
+    rs = need_gpu()
+    n, m, l = 64, 225, 225
+    g = synth.Geometry(n, m, l, 0.145, 60e9, 4e9 * 1e7 / m, 1e7)
+    raw = synth.random_complex((n, m), seed=5)
+    win = synth.hann(m)
+    log("range_compress mixed f16")
+    rc = rs.range_compress(g, to_dev(raw), to_dev(win), 10, 150, halo=8, dtype="f16", scale=2.0 ** -4)
+    torch.cuda.synchronize()
+    got = rc.pulses(n).cpu().numpy().T
+    ref = oracle.range_compress(raw, win, l)[:, 10:160]
+    assert rel_l2(got, ref) <= 1e-3
+
+
+def test_paper_radar_end_to_end():
+    """The paper's radar (N = 800, M = L = 225 through the mixed-radix range FFT, r = 0.145 m,
+    60 GHz, T_Start = 7 us) on a polar grid: range compression + sparse filter (both
+    interpolations) and BPA against the FP64 oracle."""
+    import dataclasses
+    rs = need_gpu()
+    w = custom_workload("paper_radar", 77, 800, 225, 24, 0.5, 2.5, 32, 64, radius=0.145)
+    g = dataclasses.replace(w.geometry, fc_hz=60e9, t_start_s=7e-6)
+    w = dataclasses.replace(w, geometry=g)
+    x = synth.make_inputs(w)
+    yb = oracle.range_compress(x.raw, x.window, g.n_fft)[:, x.l_lo:x.l_lo + x.l_count]
+    rc = rs.range_compress(g, to_dev(x.raw), to_dev(x.window), x.l_lo, x.l_count, halo=32)
+    torch.cuda.synchronize()
+    assert rel_l2(rc.pulses(g.n_pulses).cpu().numpy().T, yb) <= 1e-5
+    off, wts = to_dev(x.offsets), to_dev(x.weights.astype(np.complex64))
+    for interp in ("nearest", "linear"):
+        log(f"paper radar sparse filter {interp}")
+        img = rs.sparse_filter(g, w.grid, rc, off, wts, w.sparse.window, interp=interp).cpu().numpy()
+        ref = oracle.sparse_filter(yb, x.l_lo, g, w.grid, x.offsets, x.weights, interp=interp)
+        assert rel_l2(img, ref) <= TOL, interp
+    log("paper radar BPA")
+    bpa = rs.bp_full(g, w.grid, rc).cpu().numpy()
+    assert rel_l2(bpa, oracle.bp_full(yb, x.l_lo, g, w.grid)) <= TOL
 
 
 # ------------------------------------------------------------------ sparse filter
