@@ -270,6 +270,32 @@ def bp_full_at(yb, l_lo, geom, grid, rows, azs, pulse_angles=None, interp="neare
 
 
 # ----------------------------------------------------------------------- adjoint
+def bp_time_domain_at(raw, window, geom, grid, rows, azs, pulse_angles=None) -> np.ndarray:
+    """Conventional time-domain BPA (the W_BP Hadamard sum of Sec. II-C, before range
+    compression), pixel by pixel at (rows[i], azs[i]):
+        I = sum over visible n of alpha_n exp(-j 2 k R_n) sum_m h[m] y[n, m] exp(-j 2 pi tau_n K m t_s)
+    with tau_n = 2 R_n / c, t_s = 1 / F_s, visibility and alpha as in bp_full (eqs. 3-5, 8,
+    15), h the range window (rect if None).  The fast-time ramp uses the exact beat frequency,
+    where FFT+BPA reads the nearest FFT bin."""
+    n_p, m_s = raw.shape
+    h = np.ones(m_s) if window is None else np.asarray(window, dtype=np.float64)
+    hy = raw.astype(np.complex128) * h[None, :]
+    k = wavenumber(geom)
+    angles = _angles(geom, pulse_angles)
+    m = np.arange(m_s)
+    out = np.zeros(len(rows), dtype=np.complex128)
+    for i, (row, a) in enumerate(zip(rows, azs)):
+        phi_a = geom.phi0_rad + TWO_PI * a / grid.n_az
+        vis, rn, alpha = bp_terms(geom, grid, row, phi_a, angles)
+        vis, rn, alpha = vis[0], rn[0], alpha[0]
+        nv = np.nonzero(vis)[0]
+        tau = 2.0 * rn[nv] / geom.c_m_s
+        ramp = np.exp(-2j * np.pi * np.outer(tau * geom.slope_hz_s / geom.fs_hz, m))   # [visible, M]
+        d = np.sum(ramp * hy[nv], axis=1)
+        out[i] = np.sum(alpha[nv] * np.exp(-2j * k * rn[nv]) * d)
+    return out
+
+
 def sparse_filter_grad(yb, l_lo, geom, grid, offsets, weights, grad_image, dphi=None, dpsi=None,
                        interp="linear"):
     """Exact derivatives of sparse_filter for a real loss, in the convention

@@ -269,6 +269,46 @@ def test_time_domain_bpa_brute_force():
     np.testing.assert_allclose(got, ref, atol=1e-10 * np.abs(ref).max())
 
 
+def test_time_domain_bpa_equals_fft_bpa_on_bins():
+    """Radius -> 0 and range rows on FFT-bin centres: every tau_n K t_s lands on a bin, so the
+    conventional BPA equals range FFT + BPA (NEAREST) for any window."""
+    import dataclasses
+    g0 = small_geom(32, 32, 1e-9)
+    beta = oracle.bins_per_metre(g0)
+    grid = synth.PolarGrid(4, 32, 6.0 / beta, 1.0 / beta)            # rows at bins 6..9
+    raw = synth.random_complex((32, 32), seed=23).astype(np.complex128)
+    win = synth.hann(32)
+    yb = oracle.range_compress(raw, win, 32)
+    rows = np.repeat(np.arange(4), 8)
+    azs = np.tile(np.arange(0, 32, 4), 4)
+    td = oracle.bp_time_domain_at(raw, win, g0, grid, rows, azs)
+    ff = oracle.bp_full_at(yb, 0, g0, grid, rows, azs)
+    np.testing.assert_allclose(td, ff, atol=1e-6 * np.abs(ff).max())
+    assert dataclasses.is_dataclass(g0)
+
+
+def test_time_domain_bpa_zero_padding_limit():
+    """With r > 0 the beat frequencies fall between bins; range FFTs zero-padded to 1024 M bins
+    read the nearest of a grid 1024 times finer, and FFT+BPA converges to the conventional
+    BPA (phase error of the nearest-bin ramp over M samples <= pi M / L')."""
+    import dataclasses
+    g = small_geom(16, 16, 0.05)
+    grid = synth.PolarGrid(3, 16, 0.2, 0.1)     # slant ranges within the 16-bin unambiguous range
+    raw = synth.random_complex((16, 16), seed=24).astype(np.complex128)
+    win = synth.hann(16)
+    lp = 16 * 1024
+    gp = dataclasses.replace(g, n_fft=lp)
+    yb = oracle.range_compress(raw, win, lp)
+    rows = np.repeat(np.arange(3), 16)
+    azs = np.tile(np.arange(16), 3)
+    td = oracle.bp_time_domain_at(raw, win, g, grid, rows, azs)
+    ff = oracle.bp_full_at(yb, 0, gp, grid, rows, azs)
+    assert metrics.rel_l2(ff, td) <= 2e-3
+    # at the plain FFT length the nearest-bin reading is visibly different
+    ff16 = oracle.bp_full_at(oracle.range_compress(raw, win, 16), 0, g, grid, rows, azs)
+    assert metrics.rel_l2(ff16, td) > 1e-2
+
+
 # --------------------------------------------------------------------------- P9
 def test_linearity():
     w = synth.small()
