@@ -608,6 +608,20 @@ def main():
     }
     if not a.no_extras:
         out["rows"] = extras(torch, rs, synth, w, x, dev, rc, off, wts, timed, a.steps)
+        # conventional time-domain BPA (raw samples, exact beat frequency): the paper's timing
+        # comparator; its cost is pixels x visible pulses x M, so 8 rows of the grid are timed
+        first, count = grid.n_range // 2, 8
+        td_img = torch.empty((count, grid.n_az), dtype=torch.complex64, device=dev)
+        td = lambda: rs.bp_time_domain(g, grid, raw, win, angles=ang, rows=(first, count), out=td_img)
+        td()
+        ms_td = timed(td, 2, out=lambda: td_img)
+        td_px_s = count * grid.n_az / (ms_td * 1e-3)
+        out["rows"]["time_domain_bpa"] = {
+            "rows": [first, count], "ms": ms_td, "pixels_per_s": td_px_s,
+            "fft_sas_vs_td_bpa": out["value"] / td_px_s, "fft_bpa_vs_td_bpa": out["fft_bpa_pixels_per_s"] / td_px_s,
+            "note": "true angles, Hann window; pixels/s on 8 middle rows of the grid"}
+        print(f"[bench] time-domain BPA: {ms_td:.2f} ms for {count} rows ({td_px_s:.3g} px/s); FFT+SAS is "
+              f"{out['value'] / td_px_s:.0f}x faster", file=sys.stderr, flush=True)
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, x)
         out["cpu_baseline"]["all_cores"] = cpu_baseline_all_cores(w, x)

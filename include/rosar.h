@@ -208,6 +208,22 @@ rosar_status rosar_sparse_filter_backward(const rosar_geometry* geom, const rosa
                                           void* workspace, size_t workspace_bytes,
                                           rosar_stream stream);
 
+/* ---------------------------------------------------------------- time-domain BPA
+ * Conventional back-projection on the raw fast-time samples (the W_BP Hadamard sum of
+ * Sec. II-C), the comparator of the paper's timing tables:
+ *   I(R, phi_a) = sum over visible n of alpha_n exp(-j 2 k R_n)
+ *                 sum_m h[m] y[n, m] exp(-j 2 pi tau_n K m t_s),   tau_n = 2 R_n / c,
+ * with the exact beat frequency per (pixel, pulse), visibility and alpha as rosar_bp_full.
+ * raw [n_pulses][n_fast] C64 (8-byte aligned); window [n_fast] float or NULL (rect);
+ * pulse_angle_rad [n_pulses] or NULL (nominal); computes grid rows [row_first, row_first +
+ * row_count) into image [row_count][n_az] C64 (8-byte aligned, overwritten).  Its cost is
+ * pixels x visible pulses x n_fast, so callers time it on a few rows.
+ * Errors: INVALID_ARG for pointers, alignment or a row range outside the grid; UNSUPPORTED for
+ * n_fast > 2048 or n_az != n_pulses. */
+rosar_status rosar_bp_time_domain(const rosar_geometry* geom, const rosar_polar_grid* grid, const void* raw,
+                                  const float* window, const double* pulse_angle_rad, int32_t row_first,
+                                  int32_t row_count, void* image, rosar_stream stream);
+
 /* ---------------------------------------------------------------- adjoint w.r.t. the band
  * The plain sparse filter (Algorithm 2 with eq. 43, no angle or phase errors) is linear in the
  * range-compressed band: I[r, a] = sum_k conj(w[r, k]) c Y[l_k, (a + o_k) mod N], c = 1 for

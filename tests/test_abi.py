@@ -326,3 +326,21 @@ def test_adjoint_band_validation(lib):
     for ws, nb in [(None, n.value), (C.c_void_p(0x10010), n.value), (FAKE, n.value - 1)]:
         assert call(ws=ws, nb=nb) == L.ROSAR_ERR_WORKSPACE
         assert lib.rosar_last_error().decode() != ""
+
+
+def test_bp_time_domain_validation(lib):
+    g, grid = geom(), L.PolarGrid(8, 360, 1.0, 0.05)
+
+    def call(raw=FAKE, window=None, angles=None, first=0, count=8, image=FAKE, gg=None):
+        return lib.rosar_bp_time_domain(C.byref(gg or g), C.byref(grid), raw, window, angles, first, count, image,
+                                        None)
+
+    assert call(raw=None) == L.ROSAR_ERR_INVALID_ARG
+    assert call(raw=C.c_void_p(0x10004)) == L.ROSAR_ERR_INVALID_ARG
+    assert call(window=C.c_void_p(0x10002)) == L.ROSAR_ERR_INVALID_ARG
+    assert call(angles=C.c_void_p(0x10004)) == L.ROSAR_ERR_INVALID_ARG
+    for first, count in ((-1, 2), (0, 0), (5, 4), (8, 1)):
+        assert call(first=first, count=count) == L.ROSAR_ERR_INVALID_ARG, (first, count)
+    assert call(image=None) == L.ROSAR_ERR_INVALID_ARG
+    assert call(gg=geom(n_fast=4096, n_fft=4096)) == L.ROSAR_ERR_UNSUPPORTED
+    assert lib.rosar_last_error().decode() != ""
