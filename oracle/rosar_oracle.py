@@ -270,6 +270,29 @@ def bp_full_at(yb, l_lo, geom, grid, rows, azs, pulse_angles=None, interp="neare
 
 
 # ----------------------------------------------------------------------- adjoint
+def sas_time_domain_at(raw, window, geom, grid, offsets, weights, rows, azs) -> np.ndarray:
+    """Sparse-aperture filter on the raw samples (the W_SA compensation of Sec. II-C followed by
+    the weights, before range compression), pixel by pixel at (rows[i], azs[i]):
+        I = sum_k conj(w[r, k]) sum_m h[m] y[n_k, m] exp(-j 2 pi tau_k K m t_s),
+    n_k = (a + o_k) mod N, tau_k = 2 R(o_k 2 pi / N) / c (eq. 2), h the range window.  The
+    weights carry the carrier phase and the pattern; the ramp uses the exact beat frequency,
+    where FFT+SAS reads the nearest FFT bin (eq. 40)."""
+    n_p, m_s = raw.shape
+    h = np.ones(m_s) if window is None else np.asarray(window, dtype=np.float64)
+    hy = raw.astype(np.complex128) * h[None, :]
+    m = np.arange(m_s)
+    out = np.zeros(len(rows), dtype=np.complex128)
+    for i, (row, a) in enumerate(zip(rows, azs)):
+        rr = grid.r0_m + row * grid.dr_m
+        o = offsets[row].astype(np.int64)
+        n = (a + o) % n_p
+        r_hat = slant_range(rr, geom.radius_m, o * TWO_PI / n_p)
+        f = 2.0 * r_hat / geom.c_m_s * geom.slope_hz_s / geom.fs_hz
+        d = np.sum(np.exp(-2j * np.pi * np.outer(f, m)) * hy[n], axis=1)
+        out[i] = np.sum(np.conj(weights[row]) * d)
+    return out
+
+
 def bp_time_domain_at(raw, window, geom, grid, rows, azs, pulse_angles=None) -> np.ndarray:
     """Conventional time-domain BPA (the W_BP Hadamard sum of Sec. II-C, before range
     compression), pixel by pixel at (rows[i], azs[i]):

@@ -309,6 +309,47 @@ def test_time_domain_bpa_zero_padding_limit():
     assert metrics.rel_l2(ff16, td) > 1e-2
 
 
+def _sas_case(n, m, r, r0, dr, rows, k, w, seed):
+    g = small_geom(n, m, r)
+    grid = synth.PolarGrid(rows, n, r0, dr)
+    wl = synth.Workload("tdsas", seed, g, grid, synth.SceneSpec(0, "unit", 1, 2), synth.SparseSpec(k, w, False))
+    offs = synth.make_support(wl)
+    wts = synth.random_complex((rows, k), seed + 1).astype(np.complex128)
+    raw = synth.random_complex((n, m), seed + 2).astype(np.complex128)
+    return g, grid, offs, wts, raw
+
+
+def test_time_domain_sas_equals_fft_sas_on_bins():
+    """Radius -> 0 and range rows on bin centres: the sparse filter on raw samples equals range
+    FFT + sparse filter (NEAREST) for any window."""
+    g0 = small_geom(32, 32, 1e-9)
+    beta = oracle.bins_per_metre(g0)
+    g, grid, offs, wts, raw = _sas_case(32, 32, 1e-9, 6.0 / beta, 1.0 / beta, 4, 5, 8, 61)
+    win = synth.hann(32)
+    rows = np.repeat(np.arange(4), 32)
+    azs = np.tile(np.arange(32), 4)
+    td = oracle.sas_time_domain_at(raw, win, g, grid, offs, wts, rows, azs)
+    ff = oracle.sparse_filter(oracle.range_compress(raw, win, 32), 0, g, grid, offs, wts).ravel()
+    np.testing.assert_allclose(td, ff, atol=1e-6 * np.abs(ff).max())
+
+
+def test_time_domain_sas_zero_padding_limit():
+    """r > 0: FFT + sparse filter on range FFTs zero-padded to 1024 M bins converges to the
+    sparse filter on raw samples; at the plain length the nearest-bin reading differs."""
+    import dataclasses
+    g, grid, offs, wts, raw = _sas_case(16, 16, 0.05, 0.2, 0.1, 3, 5, 8, 71)
+    win = synth.hann(16)
+    rows = np.repeat(np.arange(3), 16)
+    azs = np.tile(np.arange(16), 3)
+    td = oracle.sas_time_domain_at(raw, win, g, grid, offs, wts, rows, azs)
+    lp = 16 * 1024
+    gp = dataclasses.replace(g, n_fft=lp)
+    ff = oracle.sparse_filter(oracle.range_compress(raw, win, lp), 0, gp, grid, offs, wts).ravel()
+    assert metrics.rel_l2(ff, td) <= 2e-3
+    ff16 = oracle.sparse_filter(oracle.range_compress(raw, win, 16), 0, g, grid, offs, wts).ravel()
+    assert metrics.rel_l2(ff16, td) > 1e-2
+
+
 # --------------------------------------------------------------------------- P9
 def test_linearity():
     w = synth.small()
