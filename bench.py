@@ -622,6 +622,17 @@ def main():
             "note": "true angles, Hann window; pixels/s on 8 middle rows of the grid"}
         print(f"[bench] time-domain BPA: {ms_td:.2f} ms for {count} rows ({td_px_s:.3g} px/s); FFT+SAS is "
               f"{out['value'] / td_px_s:.0f}x faster", file=sys.stderr, flush=True)
+        # the sparse filter on the raw samples (SAS without the range FFT), same rows
+        ts = lambda: rs.sas_time_domain(g, grid, raw, off, wts, w.sparse.window, window=win, rows=(first, count),
+                                        out=td_img)
+        ts()
+        ms_ts = timed(ts, 3, out=lambda: td_img)
+        ts_px_s = count * grid.n_az / (ms_ts * 1e-3)
+        out["rows"]["time_domain_sas"] = {
+            "rows": [first, count], "ms": ms_ts, "pixels_per_s": ts_px_s, "td_sas_vs_td_bpa": ts_px_s / td_px_s,
+            "fft_sas_vs_td_sas": out["value"] / ts_px_s, "note": "Hann window; 8 middle rows"}
+        print(f"[bench] time-domain SAS: {ms_ts:.3f} ms for {count} rows ({ts_px_s:.3g} px/s)", file=sys.stderr,
+              flush=True)
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, x)
         out["cpu_baseline"]["all_cores"] = cpu_baseline_all_cores(w, x)

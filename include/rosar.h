@@ -224,6 +224,18 @@ rosar_status rosar_bp_time_domain(const rosar_geometry* geom, const rosar_polar_
                                   const float* window, const double* pulse_angle_rad, int32_t row_first,
                                   int32_t row_count, void* image, rosar_stream stream);
 
+/* Sparse-aperture filter on the raw samples (the W_SA compensation of Sec. II-C followed by
+ * the weights, before range compression):
+ *   I[r, a] = sum_k conj(w[r, k]) sum_m h[m] y[(a + o_k) mod N, m] exp(-j 2 pi tau_k K m t_s),
+ * tau_k = 2 R(o_k 2 pi / N) / c (eq. 2), the exact beat frequency where rosar_sparse_filter
+ * reads the nearest FFT bin of the range-compressed data.  set as for rosar_sparse_filter
+ * (ROSAR_C64 weights); raw, window, row range and image as rosar_bp_time_domain.
+ * Errors: as rosar_bp_time_domain and the set checks of rosar_sparse_filter; UNSUPPORTED for
+ * FP16 weights. */
+rosar_status rosar_sas_time_domain(const rosar_geometry* geom, const rosar_polar_grid* grid, const void* raw,
+                                   const float* window, const rosar_sparse_set* set, int32_t row_first,
+                                   int32_t row_count, void* image, rosar_stream stream);
+
 /* ---------------------------------------------------------------- adjoint w.r.t. the band
  * The plain sparse filter (Algorithm 2 with eq. 43, no angle or phase errors) is linear in the
  * range-compressed band: I[r, a] = sum_k conj(w[r, k]) c Y[l_k, (a + o_k) mod N], c = 1 for

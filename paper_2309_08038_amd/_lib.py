@@ -85,6 +85,8 @@ PROTOTYPES = [
     ("rosar_sparse_plan_destroy", None, [C.c_void_p]),
     ("rosar_bp_time_domain", C.c_int, [_P(Geometry), _P(PolarGrid), C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32,
                                       C.c_int32, C.c_void_p, C.c_void_p]),
+    ("rosar_sas_time_domain", C.c_int, [_P(Geometry), _P(PolarGrid), C.c_void_p, C.c_void_p, _P(SparseSet),
+                                       C.c_int32, C.c_int32, C.c_void_p, C.c_void_p]),
     ("rosar_sparse_filter_adjoint_band_workspace_size", C.c_int, [_P(Geometry), _P(PolarGrid), _P(RcView),
                                                                   _P(SparseSet), C.c_int, _P(C.c_size_t)]),
     ("rosar_sparse_filter_adjoint_band", C.c_int, [_P(Geometry), _P(PolarGrid), _P(RcView), _P(SparseSet), C.c_int,

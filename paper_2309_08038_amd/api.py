@@ -334,6 +334,23 @@ def bp_time_domain(geom, grid, raw: torch.Tensor, window: torch.Tensor | None = 
     return out
 
 
+def sas_time_domain(geom, grid, raw: torch.Tensor, offsets, weights, window_w, window: torch.Tensor | None = None,
+                    rows: tuple[int, int] | None = None, out: torch.Tensor | None = None) -> torch.Tensor:
+    """Sparse-aperture filter on the raw samples (exact beat frequency per tap) for grid rows
+    [first, first + count) (all rows if None); returns [count, n_az]."""
+    _need_gpu(raw)
+    first, count = (0, grid.n_range) if rows is None else rows
+    if out is None:
+        out = torch.empty((count, grid.n_az), dtype=torch.complex64, device=raw.device)
+    s = _set(offsets, weights, window_w)
+    g, p = L.geometry(geom), L.polar_grid(grid)
+    raw = raw.contiguous()
+    L.check(L.lib().rosar_sas_time_domain(C.byref(g), C.byref(p), _ptr(raw),
+                                          None if window is None else _ptr(window.contiguous()), C.byref(s), first,
+                                          count, _ptr(out), _stream(raw.device)), "rosar_sas_time_domain")
+    return out
+
+
 def sparse_filter_adjoint_band(geom, grid, layout: RangeCompressed, offsets, weights, window, grad_image,
                                interp: str = "nearest", out: torch.Tensor | None = None,
                                workspace: torch.Tensor | None = None) -> torch.Tensor:

@@ -375,6 +375,30 @@ rosar_status rosar_bp_time_domain(const rosar_geometry* geom, const rosar_polar_
                   "time-domain BPA launch");
 }
 
+rosar_status rosar_sas_time_domain(const rosar_geometry* geom, const rosar_polar_grid* grid, const void* raw,
+                                   const float* window, const rosar_sparse_set* set, int32_t row_first,
+                                   int32_t row_count, void* image, rosar_stream stream) {
+  ROSAR_TRY(check_geometry(geom));
+  ROSAR_TRY(check_grid(geom, grid));
+  ROSAR_TRY(check_set(geom, set));
+  if (set->w_dtype != ROSAR_C64) return fail(ROSAR_ERR_UNSUPPORTED, "the raw-sample filter needs ROSAR_C64 weights");
+  if (geom->n_fast > 2048) return fail(ROSAR_ERR_UNSUPPORTED, "n_fast must be <= 2048 (got %d)", geom->n_fast);
+  if (!raw || !aligned(raw, 8)) return fail(ROSAR_ERR_INVALID_ARG, "raw NULL or misaligned");
+  if (window && !aligned(window, 4)) return fail(ROSAR_ERR_INVALID_ARG, "window misaligned");
+  if (row_first < 0 || row_count < 1 || row_count > grid->n_range - row_first)
+    return fail(ROSAR_ERR_INVALID_ARG, "rows [%d, %d + %d) outside the grid's %d rows", row_first, row_first, row_count,
+                grid->n_range);
+  ROSAR_TRY(check_image(image, "image"));
+  if (inject_launch_fault()) return fail(ROSAR_ERR_HIP, "injected launch failure (ROSAR_FAULT_INJECT)");
+  const rosar::Geo g = make_geo(geom, grid);
+  const double cyc_per_m = 2.0 * geom->slope_hz_s / (geom->c_m_s * geom->fs_hz);
+  return from_hip(rosar::launch_sas_time_domain(g, geom->n_fast, cyc_per_m, static_cast<const float2*>(raw), window,
+                                                set->offsets, static_cast<const float2*>(set->weights), set->k,
+                                                set->window, row_first, row_count, static_cast<float2*>(image),
+                                                reinterpret_cast<hipStream_t>(stream)),
+                  "raw-sample sparse filter launch");
+}
+
 rosar_status rosar_sparse_filter_adjoint_band_workspace_size(const rosar_geometry* geom,
                                                              const rosar_polar_grid* grid, const rosar_rc_view* rc,
                                                              const rosar_sparse_set* set, rosar_interp interp,

@@ -344,3 +344,19 @@ def test_bp_time_domain_validation(lib):
     assert call(image=None) == L.ROSAR_ERR_INVALID_ARG
     assert call(gg=geom(n_fast=4096, n_fft=4096)) == L.ROSAR_ERR_UNSUPPORTED
     assert lib.rosar_last_error().decode() != ""
+
+
+def test_sas_time_domain_validation(lib):
+    g, grid = geom(), L.PolarGrid(8, 360, 1.0, 0.05)
+    sset = L.SparseSet(32, 64, 0x30000, 0x40000, L.C64, 0)
+
+    def call(raw=FAKE, first=0, count=8, image=FAKE, s=None, gg=None):
+        return lib.rosar_sas_time_domain(C.byref(gg or g), C.byref(grid), raw, None, C.byref(s or sset), first,
+                                         count, image, None)
+
+    assert call(raw=None) == L.ROSAR_ERR_INVALID_ARG
+    assert call(first=7, count=2) == L.ROSAR_ERR_INVALID_ARG
+    assert call(image=C.c_void_p(0x10004)) == L.ROSAR_ERR_INVALID_ARG
+    assert call(s=L.SparseSet(65, 64, 0x30000, 0x40000, L.C64, 0)) == L.ROSAR_ERR_INVALID_ARG
+    assert call(s=L.SparseSet(32, 64, 0x30000, 0x40000, L.C16_F16, 0)) == L.ROSAR_ERR_UNSUPPORTED
+    assert call(gg=geom(n_fast=4096, n_fft=4096)) == L.ROSAR_ERR_UNSUPPORTED

@@ -1,5 +1,6 @@
-"""GPU tests of the conventional time-domain BPA (raw samples, exact beat frequency) against the
-FP64 oracle: relative L2 <= 1e-4 (complex64 data, float32 accumulation)."""
+"""GPU tests of the raw-sample (time-domain) forms: the conventional BPA and the sparse-aperture
+filter with the exact beat frequency, against the FP64 oracle: relative L2 <= 1e-4 (complex64
+data, float32 accumulation)."""
 import numpy as np
 import pytest
 
@@ -53,4 +54,37 @@ def test_time_domain_bpa_rotation_rows():
     rl = rng.integers(0, count, 30)
     azs = rng.integers(0, w.grid.n_az, 30)
     ref = oracle.bp_time_domain_at(x.raw, x.window, w.geometry, w.grid, rl + first, azs, pulse_angles=x.angles)
+    assert rel_l2(img[rl, azs], ref) <= TOL
+
+
+@pytest.mark.parametrize("name", ["small", "edge"])
+def test_time_domain_sas(name):
+    rs = need_gpu()
+    if name == "small":
+        w, x = inputs("small")
+    else:
+        w = custom_workload("td_sas_edge", 91, 100, 128, 5, 0.6, 2.5, 5, 16)   # ragged N, K = 5
+        x = synth.make_inputs(w)
+    log(f"time-domain SAS {name}")
+    img = rs.sas_time_domain(w.geometry, w.grid, to_dev(x.raw), to_dev(x.offsets),
+                             to_dev(x.weights.astype(np.complex64)), w.sparse.window, window=to_dev(x.window)).cpu().numpy()
+    rng = np.random.default_rng(8)
+    rows = rng.integers(0, w.grid.n_range, 200)
+    azs = rng.integers(0, w.grid.n_az, 200)
+    ref = oracle.sas_time_domain_at(x.raw, x.window, w.geometry, w.grid, x.offsets, x.weights, rows, azs)
+    assert rel_l2(img[rows, azs], ref) <= TOL
+
+
+def test_time_domain_sas_rotation_rows():
+    rs = need_gpu()
+    w, x = inputs("rotation")
+    first, count = 300, 4
+    log("time-domain SAS rotation rows")
+    img = rs.sas_time_domain(w.geometry, w.grid, to_dev(x.raw), to_dev(x.offsets),
+                             to_dev(x.weights.astype(np.complex64)), w.sparse.window, window=to_dev(x.window),
+                             rows=(first, count)).cpu().numpy()
+    rng = np.random.default_rng(9)
+    rl = rng.integers(0, count, 60)
+    azs = rng.integers(0, w.grid.n_az, 60)
+    ref = oracle.sas_time_domain_at(x.raw, x.window, w.geometry, w.grid, x.offsets, x.weights, rl + first, azs)
     assert rel_l2(img[rl, azs], ref) <= TOL
