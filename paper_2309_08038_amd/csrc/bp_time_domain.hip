@@ -6,7 +6,7 @@
 // pixel; the workgroup walks the pulses in order, so every lane reads the same windowed samples:
 // blocks of kTdPulses pulses are staged in LDS and read as broadcasts, and only the ramp differs
 // per lane.  Geometry is float64 per (pixel, pulse); the ramp exp(-j 2 pi f m) (f = 2 K R_n /
-// (c F_s) cycles per sample) advances by float32 complex multiplies in four interleaved streams
+// (c F_s) cycles per sample) advances by float32 complex multiplies in eight interleaved streams
 // and restarts every 64 samples from its float64-reduced exact value.
 #include <hip/hip_runtime.h>
 
@@ -18,7 +18,7 @@ namespace {
 constexpr int kTdThreads = 256;
 constexpr int kTdPulses = 4;      // pulses staged per block
 constexpr int kTdReseed = 64;     // ramp restart interval (samples)
-constexpr int kTdStreams = 4;     // interleaved ramps per segment (kTdReseed is a multiple)
+constexpr int kTdStreams = 8;     // interleaved ramps per segment (kTdReseed is a multiple)
 
 __global__ __launch_bounds__(kTdThreads) void bp_time_domain_kernel(Geo g, int m_fast, double cyc_per_m,
                                                                     const float2* __restrict__ raw,
