@@ -152,6 +152,34 @@ def sparse_filter(yb: np.ndarray, l_lo: int, geom, grid, offsets: np.ndarray, we
     return out
 
 
+def sparse_filter_cartesian(yb: np.ndarray, l_lo: int, geom, grid, xs: np.ndarray, ys: np.ndarray,
+                            offsets: np.ndarray, weights: np.ndarray, interp: str = "nearest") -> np.ndarray:
+    """Algorithm 2 for targets at Cartesian positions (xs[i], ys[i]) (FFT+SAS form, eq. 43):
+    R_t = |(x, y)|, phi_t = atan2(y, x); the weights are those of the polar grid row nearest to
+    R_t (pixels farther than half a row spacing outside the rows read nothing); the central
+    phase centre is n_c = round((phi_t - phi0) / phi_Delta); tap k reads pulse
+    n = (n_c + o_k) mod N at the bin of the slant range from that pulse to the target (eq. 2,
+    eq. 40):  I = sum_k conj(w[row, k]) Y_1D[n, u(R(phi_t - phi_n))]."""
+    n_p = geom.n_pulses
+    step = TWO_PI / n_p
+    rt = np.hypot(xs, ys)
+    phi = np.arctan2(ys, xs)
+    nc = np.floor((phi - geom.phi0_rad) / step + 0.5).astype(np.int64)
+    row = np.floor((rt - grid.r0_m) / grid.dr_m + 0.5).astype(np.int64)
+    inside = (row >= 0) & (row < grid.n_range)
+    rowc = np.where(inside, row, 0)
+    beta = bins_per_metre(geom)
+    out = np.zeros(len(xs), dtype=np.complex128)
+    for kk in range(offsets.shape[1]):
+        o = offsets[rowc, kk].astype(np.int64)
+        nn = nc + o
+        d = phi - (geom.phi0_rad + nn * step)
+        u = beta * slant_range(rt, geom.radius_m, d)
+        s, _ = sample(yb, l_lo, nn % n_p, u, interp)
+        out += np.where(inside, np.conj(weights[rowc, kk]) * s, 0.0)
+    return out
+
+
 def sparse_filter_at(yb, l_lo, geom, grid, offsets, weights, rows, azs, dphi=None, dpsi=None,
                      interp="nearest") -> np.ndarray:
     """The same sum as sparse_filter, evaluated pixel by pixel at (rows[i], azs[i])."""

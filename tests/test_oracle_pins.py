@@ -350,6 +350,42 @@ def test_time_domain_sas_zero_padding_limit():
     assert metrics.rel_l2(ff16, td) > 1e-2
 
 
+@pytest.mark.parametrize("interp", ["nearest", "linear"])
+def test_cartesian_on_polar_pixels(interp):
+    """Cartesian targets on the four axes at the grid rows' radii coincide with polar pixels
+    (phi on a pulse, R on a row): the Cartesian filter equals the polar one there."""
+    w = synth.small()
+    x = synth.make_inputs(w)
+    g, grid = w.geometry, w.grid
+    y = oracle.range_compress(x.raw, x.window, g.n_fft)[:, x.l_lo:x.l_lo + x.l_count]
+    polar = oracle.sparse_filter(y, x.l_lo, g, grid, x.offsets, x.weights, interp=interp)
+    radii = grid.r0_m + np.arange(grid.n_range) * grid.dr_m
+    n = g.n_pulses
+    for q, (cx, cy) in enumerate(((1, 0), (0, 1), (-1, 0), (0, -1))):
+        got = oracle.sparse_filter_cartesian(y, x.l_lo, g, grid, cx * radii, cy * radii, x.offsets, x.weights, interp)
+        np.testing.assert_allclose(got, polar[:, q * n // 4], atol=1e-9 * np.abs(polar).max())
+
+
+def test_cartesian_rotation_invariance():
+    """Rotating the targets by j pulse steps and the data by j pulses leaves the Cartesian image
+    unchanged; the targets here sit between pulse angles (centre-pulse residual != 0)."""
+    w = synth.small()
+    x = synth.make_inputs(w)
+    g, grid = w.geometry, w.grid
+    y = oracle.range_compress(x.raw, x.window, g.n_fft)[:, x.l_lo:x.l_lo + x.l_count]
+    rng = np.random.default_rng(3)
+    rt = grid.r0_m + rng.uniform(0, grid.n_range - 1, 40) * grid.dr_m
+    phi = rng.uniform(0, 2 * np.pi, 40)
+    j = 7
+    base = oracle.sparse_filter_cartesian(y, x.l_lo, g, grid, rt * np.cos(phi), rt * np.sin(phi), x.offsets,
+                                          x.weights, "linear")
+    rot = phi + j * 2 * np.pi / g.n_pulses
+    moved = oracle.sparse_filter_cartesian(np.roll(y, j, axis=0), x.l_lo, g, grid, rt * np.cos(rot), rt * np.sin(rot),
+                                           x.offsets, x.weights, "linear")
+    np.testing.assert_allclose(moved, base, atol=1e-9 * np.abs(base).max())
+    assert np.count_nonzero(np.abs(base) > 1e-6) > 30
+
+
 # --------------------------------------------------------------------------- P9
 def test_linearity():
     w = synth.small()
