@@ -355,6 +355,18 @@ def extras(torch, rs, synth, w, x, dev, rc, off, wts, timed, reps):
                 fc[f"{name}_{interp}_error"] = str(e)
             p.close()
     out["plan_variants"] = fc
+
+    # Algorithm 2 on a Cartesian lattice (per-pixel geometry): 1024 x 1024 targets over the disc
+    from types import SimpleNamespace
+    r1 = grid.r0_m + (grid.n_range - 1) * grid.dr_m
+    cart = SimpleNamespace(nx=1024, ny=1024, x0_m=-r1, y0_m=-r1, dx_m=2 * r1 / 1023, dy_m=2 * r1 / 1023)
+    cimg = torch.empty((1024, 1024), dtype=torch.complex64, device=dev)
+    cf = lambda: rs.sparse_filter_cartesian(g, grid, cart, rc, off, wts, w.sparse.window, out=cimg)
+    cf()
+    ms_c = timed(cf, 3, inner=5, out=lambda: cimg)
+    out["cartesian"] = {"lattice": [1024, 1024], "extent_m": 2 * r1, "us": 1000 * ms_c,
+                        "pixels_per_s": 1024 * 1024 / (ms_c * 1e-3)}
+    print(f"[bench] Cartesian 1024 x 1024: {1000 * ms_c:.1f} us", file=sys.stderr, flush=True)
     print("[bench] plan variants: " + ", ".join(f"{k} {v}" for k, v in fc.items()), file=sys.stderr, flush=True)
 
     # batched stream: 64 rotations of uneven size, autotuned shape, replayed from a HIP graph

@@ -208,6 +208,27 @@ rosar_status rosar_sparse_filter_backward(const rosar_geometry* geom, const rosa
                                           void* workspace, size_t workspace_bytes,
                                           rosar_stream stream);
 
+/* ---------------------------------------------------------------- Cartesian targets
+ * Algorithm 2 for targets on a Cartesian lattice x = x0 + ix dx, y = y0 + iy dy (metres, the
+ * rotation centre at the origin, angles as phi0 + 2 pi n / N):
+ *   R_t = |(x, y)|, phi_t = atan2(y, x); weights of the polar grid row nearest to R_t (targets
+ *   more than half a row spacing outside [r0, r0 + (n_range - 1) dr] are 0); central phase
+ *   centre n_c = round((phi_t - phi0) / phi_Delta); tap k reads pulse (n_c + o_k) mod N at the
+ *   bin of the slant range from that pulse to the target (eq. 2, eq. 40);
+ *   I = sum_k conj(w[row, k]) Y[n, u]   (eq. 43).
+ * grid: the rows the weights were designed for (n_az must equal n_pulses); rc, set, interp as
+ * rosar_sparse_filter (no angle/phase errors); image [ny][nx] C64, 8-byte aligned, overwritten.
+ * Errors: as rosar_sparse_filter; INVALID_ARG for a NULL cart, nx outside [1, 2^24], ny
+ * outside [1, 65535], or a non-finite origin / non-positive spacing. */
+typedef struct rosar_cart_grid {
+  int32_t nx, ny;
+  double x0_m, y0_m, dx_m, dy_m;
+} rosar_cart_grid;
+rosar_status rosar_sparse_filter_cartesian(const rosar_geometry* geom, const rosar_polar_grid* grid,
+                                           const rosar_cart_grid* cart, const rosar_rc_view* rc,
+                                           const rosar_sparse_set* set, rosar_interp interp, void* image,
+                                           rosar_stream stream);
+
 /* ---------------------------------------------------------------- time-domain BPA
  * Conventional back-projection on the raw fast-time samples (the W_BP Hadamard sum of
  * Sec. II-C), the comparator of the paper's timing tables:

@@ -30,6 +30,11 @@ class PolarGrid(C.Structure):
     _fields_ = [("n_range", C.c_int32), ("n_az", C.c_int32), ("r0_m", C.c_double), ("dr_m", C.c_double)]
 
 
+class CartGrid(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("x0_m", C.c_double), ("y0_m", C.c_double),
+                ("dx_m", C.c_double), ("dy_m", C.c_double)]
+
+
 class RcView(C.Structure):
     _fields_ = [("data", C.c_void_p), ("dtype", C.c_int32), ("l_lo", C.c_int32), ("l_count", C.c_int32),
                 ("halo", C.c_int32), ("ld", C.c_int64), ("scale", C.c_float), ("reserved", C.c_int32)]
@@ -83,6 +88,8 @@ PROTOTYPES = [
                                           _P(Tile), C.c_void_p, _P(C.c_void_p)]),
     ("rosar_sparse_plan_run", C.c_int, [C.c_void_p, _P(RcView), C.c_void_p, C.c_void_p]),
     ("rosar_sparse_plan_destroy", None, [C.c_void_p]),
+    ("rosar_sparse_filter_cartesian", C.c_int, [_P(Geometry), _P(PolarGrid), _P(CartGrid), _P(RcView),
+                                               _P(SparseSet), C.c_int, C.c_void_p, C.c_void_p]),
     ("rosar_bp_time_domain", C.c_int, [_P(Geometry), _P(PolarGrid), C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32,
                                       C.c_int32, C.c_void_p, C.c_void_p]),
     ("rosar_sas_time_domain", C.c_int, [_P(Geometry), _P(PolarGrid), C.c_void_p, C.c_void_p, _P(SparseSet),

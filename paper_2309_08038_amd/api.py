@@ -317,6 +317,22 @@ def sparse_plan_autotune(geom, grid, rc: RangeCompressed, offsets, weights, wind
     return (best.pixels_per_lane, best.waves), float(us.value)
 
 
+def sparse_filter_cartesian(geom, grid, cart, rc: RangeCompressed, offsets, weights, window, interp: str = "nearest",
+                            out: torch.Tensor | None = None) -> torch.Tensor:
+    """Algorithm 2 for targets on the Cartesian lattice `cart` (nx, ny, x0_m, y0_m, dx_m, dy_m),
+    with the weights of the polar grid rows; returns [ny, nx] complex64."""
+    _need_gpu(rc.data)
+    s = _set(offsets, weights, window)
+    if out is None:
+        out = torch.empty((cart.ny, cart.nx), dtype=torch.complex64, device=rc.data.device)
+    g, p, v = L.geometry(geom), L.polar_grid(grid), rc.view()
+    c = L.CartGrid(int(cart.nx), int(cart.ny), float(cart.x0_m), float(cart.y0_m), float(cart.dx_m), float(cart.dy_m))
+    L.check(L.lib().rosar_sparse_filter_cartesian(C.byref(g), C.byref(p), C.byref(c), C.byref(v), C.byref(s),
+                                                  L.INTERP_CODES[interp], _ptr(out), _stream(rc.data.device)),
+            "rosar_sparse_filter_cartesian")
+    return out
+
+
 def bp_time_domain(geom, grid, raw: torch.Tensor, window: torch.Tensor | None = None, angles: torch.Tensor | None = None,
                    rows: tuple[int, int] | None = None, out: torch.Tensor | None = None) -> torch.Tensor:
     """Conventional time-domain BPA on the raw samples (exact beat frequency per pixel and

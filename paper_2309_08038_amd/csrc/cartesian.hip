@@ -1,0 +1,97 @@
+// Algorithm 2 for targets on a Cartesian lattice (FFT+SAS form, eq. 43).  For the target at
+// (x, y): R_t = |(x, y)|, phi_t = atan2(y, x); the weights are those of the polar grid row
+// nearest to R_t (targets more than half a row spacing outside the rows get zero); the central
+// phase centre is n_c = round((phi_t - phi0) / phi_Delta); tap k reads pulse (n_c + o_k) mod N
+// at the bin of the slant range from that pulse to the target (eq. 2, eq. 40).  Without the
+// rotation symmetry each pixel has its own tap geometry: a thread owns a pixel and evaluates it
+// in float64, reading the band samples from global memory.
+#include <hip/hip_runtime.h>
+
+#include "rosar_device.hpp"
+
+namespace rosar {
+namespace {
+
+constexpr int kCartThreads = 256;
+
+template <int DT, int WDT, int INTERP>
+__global__ __launch_bounds__(kCartThreads) void sparse_cartesian_kernel(Geo g, View y, CartGrid c, int32_t k,
+                                                                        int32_t half_w,
+                                                                        const int32_t* __restrict__ offsets,
+                                                                        const void* __restrict__ weights,
+                                                                        float2* __restrict__ image) {
+  const int ix = blockIdx.x * kCartThreads + threadIdx.x;
+  const int iy = blockIdx.y;
+  if (ix >= c.nx) return;   // no barrier in this kernel
+  const double x = c.x0 + ix * c.dx, yy = c.y0 + iy * c.dy;
+  const double rt = sqrt(x * x + yy * yy);
+  const double phi = atan2(yy, x);
+  const int nc = (int)floor((phi - g.phi0) / g.step + 0.5);
+  const int row = (int)floor((rt - g.r0) / g.dr + 0.5);
+  float2 acc = make_float2(0.f, 0.f);
+  if (row >= 0 && row < g.n_range) {
+    const double c1 = rt * rt + g.radius * g.radius;
+    const double c2 = 2.0 * rt * g.radius;
+    const char* yd = static_cast<const char*>(y.data);
+    for (int t = 0; t < k; ++t) {
+      const int o = offsets[(int64_t)row * k + t];
+      if (o < -half_w || o >= half_w) continue;   // outside the window: no contribution
+      const float2 w = load_w<WDT>(weights, (int64_t)row * k + t);
+      const int nn = nc + o;
+      const double d = phi - (g.phi0 + nn * g.step);
+      const double u = g.beta * sqrt(c1 - c2 * cos(d));
+      int n = nn % g.n;
+      n += n < 0 ? g.n : 0;
+      float2 s = make_float2(0.f, 0.f);
+      if constexpr (INTERP == ROSAR_NEAREST) {
+        const int l = (int)floor(u + 0.5) - y.l_lo;
+        if (l >= 0 && l < y.l_count) s = load_c<DT>(yd, (int64_t)l * y.ld + y.halo + n);
+      } else {
+        const double fl = floor(u);
+        const float f = (float)(u - fl);
+        const int l = (int)fl - y.l_lo;
+        if (l >= 0 && l < y.l_count) {
+          const float2 v = load_c<DT>(yd, (int64_t)l * y.ld + y.halo + n);
+          s.x += (1.f - f) * v.x;
+          s.y += (1.f - f) * v.y;
+        }
+        if (l + 1 >= 0 && l + 1 < y.l_count) {
+          const float2 v = load_c<DT>(yd, (int64_t)(l + 1) * y.ld + y.halo + n);
+          s.x += f * v.x;
+          s.y += f * v.y;
+        }
+      }
+      cmac_conj(acc, w, s);
+    }
+  }
+  image[(size_t)iy * c.nx + ix] = make_float2(acc.x * y.inv_scale, acc.y * y.inv_scale);
+}
+
+template <int DT, int WDT>
+hipError_t launch_wdt(const SparseArgs& a, const CartGrid& c, hipStream_t s) {
+  dim3 grid((c.nx + kCartThreads - 1) / kCartThreads, c.ny);
+  if (a.interp == ROSAR_LINEAR)
+    sparse_cartesian_kernel<DT, WDT, ROSAR_LINEAR><<<grid, kCartThreads, 0, s>>>(a.g, a.y, c, a.k, a.window / 2,
+                                                                                a.offsets, a.weights, a.image);
+  else
+    sparse_cartesian_kernel<DT, WDT, ROSAR_NEAREST><<<grid, kCartThreads, 0, s>>>(a.g, a.y, c, a.k, a.window / 2,
+                                                                                 a.offsets, a.weights, a.image);
+  return hipGetLastError();
+}
+
+template <int DT>
+hipError_t launch_dt(const SparseArgs& a, const CartGrid& c, hipStream_t s) {
+  return a.w_dtype == ROSAR_C64 ? launch_wdt<DT, 0>(a, c, s) : launch_wdt<DT, 1>(a, c, s);
+}
+
+}  // namespace
+
+hipError_t launch_sparse_cartesian(const SparseArgs& a, const CartGrid& c, hipStream_t s) {
+  switch (a.y.dtype) {
+    case ROSAR_C64: return launch_dt<0>(a, c, s);
+    case ROSAR_C16_F16: return launch_dt<1>(a, c, s);
+    default: return launch_dt<2>(a, c, s);
+  }
+}
+
+}  // namespace rosar

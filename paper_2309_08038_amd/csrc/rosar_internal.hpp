@@ -56,6 +56,12 @@ struct Tile {
   int variant, ppl, waves;
 };
 
+// Cartesian target lattice: x = x0 + ix dx, y = y0 + iy dy.
+struct CartGrid {
+  int32_t nx, ny;
+  double x0, y0, dx, dy;
+};
+
 // Launchers (kernels live in the .hip files).  Each returns hipGetLastError() after launching.
 // Range compression: power-of-two L in [64, 2048] by the radix-8/4/2 wave kernels, any other
 // 2^a 3^b 5^c <= 8192 by the mixed-radix workgroup kernel.
@@ -63,6 +69,7 @@ bool range_compress_length_supported(int32_t l);
 hipError_t launch_range_compress(const RcArgs& a, hipStream_t s);
 hipError_t launch_sparse_plain(const SparseArgs& a, const Tile& t, hipStream_t s);
 hipError_t launch_sparse_corrected(const SparseArgs& a, hipStream_t s);
+hipError_t launch_sparse_cartesian(const SparseArgs& a, const CartGrid& c, hipStream_t s);
 size_t bp_workspace_bytes(int32_t n);
 hipError_t launch_sas_time_domain(const Geo& g, int m_fast, double cyc_per_m, const float2* raw, const float* window,
                                   const int32_t* offsets, const float2* weights, int k, int window_w, int row_first,

@@ -43,7 +43,8 @@ def test_every_declared_symbol_is_exported(lib):
 def test_struct_layouts_match_c(tmp_path):
     """sizeof/offsetof of the C structs (gcc on the public header) equal the ctypes mirrors."""
     structs = {"rosar_geometry": L.Geometry, "rosar_polar_grid": L.PolarGrid, "rosar_rc_view": L.RcView,
-               "rosar_sparse_set": L.SparseSet, "rosar_tile": L.Tile, "rosar_rotation_desc": L.RotationDesc}
+               "rosar_sparse_set": L.SparseSet, "rosar_tile": L.Tile, "rosar_rotation_desc": L.RotationDesc,
+               "rosar_cart_grid": L.CartGrid}
     lines = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{HEADER}"', "int main(void){"]
     for cname, py in structs.items():
         lines.append(f'printf("{cname} %zu\\n", sizeof({cname}));')
@@ -360,3 +361,22 @@ def test_sas_time_domain_validation(lib):
     assert call(s=L.SparseSet(65, 64, 0x30000, 0x40000, L.C64, 0)) == L.ROSAR_ERR_INVALID_ARG
     assert call(s=L.SparseSet(32, 64, 0x30000, 0x40000, L.C16_F16, 0)) == L.ROSAR_ERR_UNSUPPORTED
     assert call(gg=geom(n_fast=4096, n_fft=4096)) == L.ROSAR_ERR_UNSUPPORTED
+
+
+def test_cartesian_validation(lib):
+    g, grid = geom(), L.PolarGrid(8, 360, 1.0, 0.05)
+    view = L.RcView(0x20000, L.C64, 0, 64, 32, 424, 1.0, 0)
+    sset = L.SparseSet(32, 64, 0x30000, 0x40000, L.C64, 0)
+
+    def call(cart, image=FAKE):
+        return lib.rosar_sparse_filter_cartesian(C.byref(g), C.byref(grid), C.byref(cart) if cart else None,
+                                                 C.byref(view), C.byref(sset), L.NEAREST, image, None)
+
+    good = L.CartGrid(16, 16, -1.0, -1.0, 0.1, 0.1)
+    assert call(None) == L.ROSAR_ERR_INVALID_ARG
+    assert call(good, image=None) == L.ROSAR_ERR_INVALID_ARG
+    for bad in (L.CartGrid(0, 16, 0, 0, 0.1, 0.1), L.CartGrid(16, 70000, 0, 0, 0.1, 0.1),
+                L.CartGrid(16, 16, float("nan"), 0, 0.1, 0.1), L.CartGrid(16, 16, 0, 0, 0.0, 0.1),
+                L.CartGrid(16, 16, 0, 0, 0.1, -1.0)):
+        assert call(bad) == L.ROSAR_ERR_INVALID_ARG, (bad.nx, bad.ny, bad.x0_m, bad.dx_m, bad.dy_m)
+        assert lib.rosar_last_error().decode() != ""
