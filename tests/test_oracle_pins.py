@@ -386,6 +386,55 @@ def test_cartesian_rotation_invariance():
     assert np.count_nonzero(np.abs(base) > 1e-6) > 30
 
 
+def _steering(geom, rr, d, k):
+    """eq. 16 evaluated directly with complex exponentials (test-side reference)."""
+    r = geom.radius_m
+    rn = np.sqrt(rr * rr + r * r - 2 * rr * r * np.cos(d))
+    return np.maximum(rr * np.cos(d) - r, 0.0) / rn * np.exp(1j * 2 * k * rn)
+
+
+def test_delta_r_direct_evaluation():
+    """At a carrier low enough for direct complex arithmetic to keep its digits, ||a^ - a|| from
+    explicit exponentials equals the oracle's cancellation-free form."""
+    import dataclasses
+    g = dataclasses.replace(small_geom(360, 64, 0.3), fc_hz=2e9)
+    grid = synth.PolarGrid(5, 360, 0.6, 0.4)
+    k = oracle.wavenumber(g)
+    rng = np.random.default_rng(11)
+    deltas = rng.normal(0, 2e-2, (50, 64))
+    got = oracle.delta_r_samples(g, grid, 64, deltas)
+    d0 = np.arange(-32, 32) * 2 * np.pi / 360
+    for row in range(5):
+        rr = grid.r0_m + row * grid.dr_m
+        want = np.linalg.norm(_steering(g, rr, d0[None, :] + deltas, k) - _steering(g, rr, d0, k)[None, :], axis=1)
+        np.testing.assert_allclose(got[row], want, rtol=1e-9)
+
+
+def test_delta_r_small_sigma_linearisation():
+    """Small sigma: E[Delta^2] -> sigma^2 sum_n |da_n/dphi|^2, the derivative taken by central
+    differences of the directly evaluated steering vector."""
+    g = small_geom(360, 64, 0.25)
+    grid = synth.PolarGrid(3, 360, 1.0, 0.5)
+    k = oracle.wavenumber(g)
+    sigma = 1e-6
+    rng = np.random.default_rng(12)
+    deltas = rng.normal(0, sigma, (20000, 64))
+    got = np.mean(oracle.delta_r_samples(g, grid, 64, deltas) ** 2, axis=1)
+    d0 = np.arange(-32, 32) * 2 * np.pi / 360
+    h = 1e-7
+    for row in range(3):
+        rr = grid.r0_m + row * grid.dr_m
+        da = (_steering(g, rr, d0 + h, k) - _steering(g, rr, d0 - h, k)) / (2 * h)
+        want = sigma ** 2 * np.sum(np.abs(da) ** 2)
+        assert abs(got[row] - want) <= 0.03 * want, (row, got[row], want)
+
+
+def test_delta_r_quantile():
+    samples = np.array([[5.0, 1.0, 3.0, 2.0, 4.0]])
+    assert oracle.delta_r(samples, 0.99)[0] == 5.0
+    assert oracle.delta_r(samples, 0.6)[0] == 3.0      # ceil(0.6 * 5) = 3rd smallest
+
+
 # --------------------------------------------------------------------------- P9
 def test_linearity():
     w = synth.small()
