@@ -229,6 +229,27 @@ rosar_status rosar_sparse_filter_cartesian(const rosar_geometry* geom, const ros
                                            const rosar_sparse_set* set, rosar_interp interp, void* image,
                                            rosar_stream stream);
 
+/* ---------------------------------------------------------------- rotation-jitter bound
+ * Delta_R of the robust weight design (Sec. III-C, parameter settings, eq. 37): the phase-centre
+ * directions of the W-element window around a target are perturbed by drawn angle errors, and
+ * for every range row R of the grid and every draw s
+ *   samples[R][s] = || a^(phi; R) - a(phi; R) ||,
+ * a_e = alpha_e exp(-j 2 k R_e) the steering vector of eq. 16 at D_e = (e - W/2) 2 pi / N
+ * (alpha as rosar_bp_full: max(R cos D - r, 0) / R_e), a^ the same at D_e + deltas[e][s].
+ * delta_r[R] is then the sample of rank ceil(quantile * n_samples) - 1 in ascending order (the
+ * quantile point of the empirical CDF; the paper takes 0.99).  The draws are inputs: the caller
+ * samples them (the paper: independent N(0, sigma) per element) and the same draws serve every
+ * row.  Evaluated in float64 without forming differences of nearly equal ranges or phases.
+ * window: even, in [2, N]; deltas [window][n_samples] float64 radians, draw-minor (device,
+ * 8-byte aligned, read only); samples [n_range][n_samples] float64 and delta_r [n_range]
+ * float64 (device, 8-byte aligned, overwritten).  Non-finite draws give unspecified but
+ * finite-time results.
+ * Errors: INVALID_ARG for pointers, alignment, window, n_samples outside [1, 2^24] or quantile
+ * outside (0, 1]; UNSUPPORTED for more than 524280 range rows. */
+rosar_status rosar_delta_r(const rosar_geometry* geom, const rosar_polar_grid* grid, int32_t window,
+                           const double* deltas, int32_t n_samples, double quantile, double* samples,
+                           double* delta_r, rosar_stream stream);
+
 /* ---------------------------------------------------------------- time-domain BPA
  * Conventional back-projection on the raw fast-time samples (the W_BP Hadamard sum of
  * Sec. II-C), the comparator of the paper's timing tables:

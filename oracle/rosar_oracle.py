@@ -22,6 +22,9 @@ Readings of the paper taken here (each also an explicit argument of the HIP entr
   * The residual Dirichlet phase after the range FFT (Remark 1) is not corrected.
   * Per-pulse angle errors delta_n (data taken at phi_n + delta_n, eq. 37) and phase errors
     psi_n enter the corrected sparse filter as s <- s exp(-j 2k (R^ - R_nom)) exp(-j psi_n).
+  * Delta_R (eq. 37): the steering vector spans the sparse set's W-element window; the angle
+    draws are inputs shared by every range row; the q point of the empirical CDF is the sample
+    of rank ceil(q S) - 1 in ascending order.
 """
 from __future__ import annotations
 
@@ -155,8 +158,9 @@ def sparse_filter(yb: np.ndarray, l_lo: int, geom, grid, offsets: np.ndarray, we
 def delta_r_samples(geom, grid, window: int, deltas: np.ndarray) -> np.ndarray:
     """Monte-Carlo samples of Delta^_R = ||a^(phi; R) - a(phi; R)|| (Sec. III-C parameter
     settings, eq. 37): a is the steering vector of the W phase centres around the target
-    direction (eq. 16: cos(theta'_n) exp(j 2 k R_n), cos(theta'_n) = max(R cos D_n - r, 0) / R_n
-    as in the field-of-view reading, D_n = o 2 pi / N for offsets o in [-W/2, W/2)), a^ the
+    direction (eq. 16: cos(theta'_n) exp(-j 2 k R_n), the sign immaterial to the norm;
+    cos(theta'_n) = max(R cos D_n - r, 0) / R_n as in the field-of-view reading;
+    D_n = o 2 pi / N for offsets o in [-W/2, W/2)), a^ the
     same with each angle perturbed by the given draw, D^_n = D_n + deltas[s, o + W/2].  Computed
     per element as |alpha^ e^{j psi} - alpha|^2 = (alpha^ - alpha)^2 + 4 alpha alpha^ sin^2(psi/2),
     psi = 2 k (R^ - R), R^ - R = (R^2^ - R^2) / (R^ + R).  Returns [n_range, S]."""

@@ -367,6 +367,28 @@ def sas_time_domain(geom, grid, raw: torch.Tensor, offsets, weights, window_w, w
     return out
 
 
+def delta_r(geom, grid, window: int, deltas: torch.Tensor, quantile: float = 0.99,
+            samples: torch.Tensor | None = None, out: torch.Tensor | None = None):
+    """Monte-Carlo Delta_R per range row (eq. 37): `deltas` [window, S] float64 angle errors (draw
+    minor), shared by every row.  Returns (delta_r [n_range], samples [n_range, S]), float64."""
+    _need_gpu(deltas)
+    if deltas.dtype != torch.float64 or deltas.dim() != 2 or deltas.shape[0] != window:
+        raise ValueError(f"deltas must be float64 [window={window}, S], got {tuple(deltas.shape)} {deltas.dtype}")
+    deltas = deltas.contiguous()
+    n_s = deltas.shape[1]
+    dev = deltas.device
+    if samples is None:
+        samples = torch.empty((grid.n_range, n_s), dtype=torch.float64, device=dev)
+    if out is None:
+        out = torch.empty(grid.n_range, dtype=torch.float64, device=dev)
+    if samples.shape != (grid.n_range, n_s) or out.shape != (grid.n_range,) or not samples.is_contiguous():
+        raise ValueError("samples must be contiguous [n_range, S] and out [n_range]")
+    g, p = L.geometry(geom), L.polar_grid(grid)
+    L.check(L.lib().rosar_delta_r(C.byref(g), C.byref(p), window, _ptr(deltas), n_s, float(quantile), _ptr(samples),
+                                  _ptr(out), _stream(dev)), "rosar_delta_r")
+    return out, samples
+
+
 def sparse_filter_adjoint_band(geom, grid, layout: RangeCompressed, offsets, weights, window, grad_image,
                                interp: str = "nearest", out: torch.Tensor | None = None,
                                workspace: torch.Tensor | None = None) -> torch.Tensor:

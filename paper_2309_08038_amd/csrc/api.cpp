@@ -393,6 +393,31 @@ rosar_status rosar_bp_time_domain(const rosar_geometry* geom, const rosar_polar_
                   "time-domain BPA launch");
 }
 
+rosar_status rosar_delta_r(const rosar_geometry* geom, const rosar_polar_grid* grid, int32_t window,
+                           const double* deltas, int32_t n_samples, double quantile, double* samples,
+                           double* delta_r, rosar_stream stream) {
+  ROSAR_TRY(check_geometry(geom));
+  ROSAR_TRY(check_grid(geom, grid));
+  if (window < 2 || (window & 1) || window > geom->n_pulses)
+    return fail(ROSAR_ERR_INVALID_ARG, "window must be even and in [2, N] (got %d)", window);
+  if (n_samples < 1 || n_samples > (1 << 24))
+    return fail(ROSAR_ERR_INVALID_ARG, "n_samples must be in [1, 2^24] (got %d)", n_samples);
+  if (!(quantile > 0.0 && quantile <= 1.0))
+    return fail(ROSAR_ERR_INVALID_ARG, "quantile must be in (0, 1] (got %g)", quantile);
+  if ((grid->n_range + rosar::delta_r_rows_per_block() - 1) / rosar::delta_r_rows_per_block() > 65535)
+    return fail(ROSAR_ERR_UNSUPPORTED, "n_range %d exceeds %d rows", grid->n_range,
+                65535 * rosar::delta_r_rows_per_block());
+  if (!deltas || !aligned(deltas, 8)) return fail(ROSAR_ERR_INVALID_ARG, "deltas NULL or misaligned");
+  if (!samples || !aligned(samples, 8)) return fail(ROSAR_ERR_INVALID_ARG, "samples NULL or misaligned");
+  if (!delta_r || !aligned(delta_r, 8)) return fail(ROSAR_ERR_INVALID_ARG, "delta_r NULL or misaligned");
+  if (inject_launch_fault()) return fail(ROSAR_ERR_HIP, "injected launch failure (ROSAR_FAULT_INJECT)");
+  // rank of the q point: the smallest sample whose empirical CDF reaches q
+  const int rank = (int)std::ceil(quantile * (double)n_samples) - 1;
+  return from_hip(rosar::launch_delta_r(make_geo(geom, grid), window, n_samples, deltas, rank, samples, delta_r,
+                                        reinterpret_cast<hipStream_t>(stream)),
+                  "Delta_R Monte-Carlo launch");
+}
+
 rosar_status rosar_sas_time_domain(const rosar_geometry* geom, const rosar_polar_grid* grid, const void* raw,
                                    const float* window, const rosar_sparse_set* set, int32_t row_first,
                                    int32_t row_count, void* image, rosar_stream stream) {

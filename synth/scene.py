@@ -64,6 +64,12 @@ def nominal_angles(geom: Geometry) -> np.ndarray:
     return geom.phi0_rad + 2.0 * math.pi * np.arange(geom.n_pulses) / geom.n_pulses
 
 
+def jitter_draws(seed: int, window: int, n_samples: int, sigma_rad: float) -> np.ndarray:
+    """Monte-Carlo angle errors for the Delta_R estimate (eq. 37): [window, n_samples] float64,
+    independent N(0, sigma^2) per phase centre and draw, draw-minor (the device layout)."""
+    return np.random.Generator(np.random.PCG64(seed)).normal(0.0, sigma_rad, (window, n_samples))
+
+
 def make_angles(w: Workload) -> np.ndarray:
     """True pulse angles: nominal 2*pi*n/N plus N(0, sigma^2) jitter (eq. 37)."""
     a = nominal_angles(w.geometry)

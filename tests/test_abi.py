@@ -347,6 +347,26 @@ def test_bp_time_domain_validation(lib):
     assert lib.rosar_last_error().decode() != ""
 
 
+def test_delta_r_validation(lib):
+    g, grid = geom(), L.PolarGrid(8, 360, 1.0, 0.05)
+
+    def call(window=64, deltas=FAKE, n_s=100, q=0.99, samples=FAKE, out=FAKE, gr=None):
+        return lib.rosar_delta_r(C.byref(g), C.byref(gr or grid), window, deltas, n_s, q, samples, out, None)
+
+    for window in (0, 1, 63, 362):
+        assert call(window=window) == L.ROSAR_ERR_INVALID_ARG, window
+    for n_s in (0, -1, (1 << 24) + 1):
+        assert call(n_s=n_s) == L.ROSAR_ERR_INVALID_ARG, n_s
+    for q in (0.0, -0.5, 1.0000001, float("nan"), float("inf")):
+        assert call(q=q) == L.ROSAR_ERR_INVALID_ARG, q
+    assert call(deltas=None) == L.ROSAR_ERR_INVALID_ARG
+    assert call(deltas=C.c_void_p(0x10004)) == L.ROSAR_ERR_INVALID_ARG
+    assert call(samples=None) == L.ROSAR_ERR_INVALID_ARG
+    assert call(out=C.c_void_p(0x10004)) == L.ROSAR_ERR_INVALID_ARG
+    assert call(gr=L.PolarGrid(600000, 360, 1.0, 0.05)) == L.ROSAR_ERR_UNSUPPORTED
+    assert "n_range" in lib.rosar_last_error().decode()
+
+
 def test_sas_time_domain_validation(lib):
     g, grid = geom(), L.PolarGrid(8, 360, 1.0, 0.05)
     sset = L.SparseSet(32, 64, 0x30000, 0x40000, L.C64, 0)
