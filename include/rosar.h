@@ -229,6 +229,19 @@ rosar_status rosar_sparse_filter_cartesian(const rosar_geometry* geom, const ros
                                            const rosar_sparse_set* set, rosar_interp interp, void* image,
                                            rosar_stream stream);
 
+/* Algorithm 2 on a polar grid whose azimuth-bin count A = grid->n_az need not equal N: pixel
+ * (i, a) is the target at R_i and phi_a = phi0 + 2 pi a / A; its central phase centre is
+ * n_c = round((phi_a - phi0) / phi_Delta) (floor(x + 1/2)), tap k reads pulse (n_c + o_k) mod N
+ * at the bin of the slant range from that pulse to the target (eq. 2, eq. 40), with the
+ * weights of row i; eq. 43.  A = N gives rosar_sparse_filter's image (float64 geometry per
+ * pixel, so not bit for bit).  rc, set, interp as rosar_sparse_filter; image [n_range][A] C64
+ * (8-byte aligned, overwritten).
+ * Errors: as rosar_sparse_filter for the rows, view and set; INVALID_ARG for A outside
+ * [1, 2^24]; UNSUPPORTED for more than 65535 rows or 2^31 pixels. */
+rosar_status rosar_sparse_filter_polar(const rosar_geometry* geom, const rosar_polar_grid* grid,
+                                       const rosar_rc_view* rc, const rosar_sparse_set* set, rosar_interp interp,
+                                       void* image, rosar_stream stream);
+
 /* ---------------------------------------------------------------- rotation-jitter bound
  * Delta_R of the robust weight design (Sec. III-C, parameter settings, eq. 37): the phase-centre
  * directions of the W-element window around a target are perturbed by drawn angle errors, and

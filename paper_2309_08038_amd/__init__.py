@@ -5,7 +5,7 @@ from ._lib import RosarError, LIB_PATH, lib
 from .api import (BatchPlan, RangeCompressed, Rotation, SparseFilterBandFn, SparseFilterFn, SparsePlan,
                   autotune_sparse_filter, backward_workspace_bytes, batch_autotune, bp_full, bp_time_domain,
                   bp_workspace_bytes, delta_r, empty_rc, range_compress, sas_time_domain, sparse_filter,
-                  sparse_filter_adjoint_band, sparse_filter_backward, sparse_filter_band_diff, sparse_filter_cartesian,
+                  sparse_filter_adjoint_band, sparse_filter_backward, sparse_filter_band_diff, sparse_filter_cartesian, sparse_filter_polar,
                   sparse_filter_diff, sparse_plan_autotune, weights_f16)
 
 __all__ = [
@@ -13,7 +13,7 @@ __all__ = [
     "BatchPlan", "RangeCompressed", "Rotation", "SparseFilterBandFn", "SparseFilterFn", "SparsePlan",
     "autotune_sparse_filter", "backward_workspace_bytes", "batch_autotune", "bp_full", "bp_time_domain",
     "bp_workspace_bytes", "delta_r", "empty_rc", "range_compress", "sas_time_domain", "sparse_filter",
-    "sparse_filter_adjoint_band", "sparse_filter_backward", "sparse_filter_band_diff", "sparse_filter_cartesian",
+    "sparse_filter_adjoint_band", "sparse_filter_backward", "sparse_filter_band_diff", "sparse_filter_cartesian", "sparse_filter_polar",
     "sparse_filter_diff",
     "sparse_plan_autotune", "weights_f16",
 ]

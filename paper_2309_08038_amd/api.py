@@ -333,6 +333,20 @@ def sparse_filter_cartesian(geom, grid, cart, rc: RangeCompressed, offsets, weig
     return out
 
 
+def sparse_filter_polar(geom, grid, rc: RangeCompressed, offsets, weights, window, interp: str = "nearest",
+                        out: torch.Tensor | None = None) -> torch.Tensor:
+    """Algorithm 2 on a polar grid of grid.n_az azimuth bins, which may differ from the pulse
+    count (per-pixel central phase centre); returns [n_range, n_az] complex64."""
+    _need_gpu(rc.data)
+    s = _set(offsets, weights, window)
+    if out is None:
+        out = torch.empty((grid.n_range, grid.n_az), dtype=torch.complex64, device=rc.data.device)
+    g, p, v = L.geometry(geom), L.polar_grid(grid), rc.view()
+    L.check(L.lib().rosar_sparse_filter_polar(C.byref(g), C.byref(p), C.byref(v), C.byref(s), L.INTERP_CODES[interp],
+                                              _ptr(out), _stream(rc.data.device)), "rosar_sparse_filter_polar")
+    return out
+
+
 def bp_time_domain(geom, grid, raw: torch.Tensor, window: torch.Tensor | None = None, angles: torch.Tensor | None = None,
                    rows: tuple[int, int] | None = None, out: torch.Tensor | None = None) -> torch.Tensor:
     """Conventional time-domain BPA on the raw samples (exact beat frequency per pixel and

@@ -371,6 +371,25 @@ rosar_status rosar_sparse_filter_cartesian(const rosar_geometry* geom, const ros
                   "Cartesian sparse filter launch");
 }
 
+rosar_status rosar_sparse_filter_polar(const rosar_geometry* geom, const rosar_polar_grid* grid,
+                                       const rosar_rc_view* rc, const rosar_sparse_set* set, rosar_interp interp,
+                                       void* image, rosar_stream stream) {
+  if (!geom) return fail(ROSAR_ERR_INVALID_ARG, "geometry is NULL");
+  if (!grid) return fail(ROSAR_ERR_INVALID_ARG, "grid is NULL");
+  rosar_polar_grid pulses = *grid;   // rows as given, azimuth on the pulse grid for the shared checks
+  pulses.n_az = geom->n_pulses;
+  rosar::SparseArgs a{};
+  ROSAR_TRY(sparse_common(geom, &pulses, rc, set, nullptr, nullptr, interp, image, &a));
+  if (grid->n_az < 1 || grid->n_az > (1 << 24))
+    return fail(ROSAR_ERR_INVALID_ARG, "n_az must be in [1, 2^24] (got %d)", grid->n_az);
+  if (grid->n_range > 65535) return fail(ROSAR_ERR_UNSUPPORTED, "n_range must be <= 65535 (got %d)", grid->n_range);
+  if ((int64_t)grid->n_range * grid->n_az > ((int64_t)1 << 31))
+    return fail(ROSAR_ERR_UNSUPPORTED, "image larger than 2^31 pixels");
+  if (inject_launch_fault()) return fail(ROSAR_ERR_HIP, "injected launch failure (ROSAR_FAULT_INJECT)");
+  return from_hip(rosar::launch_sparse_polar(a, grid->n_az, reinterpret_cast<hipStream_t>(stream)),
+                  "polar sparse filter launch");
+}
+
 rosar_status rosar_bp_time_domain(const rosar_geometry* geom, const rosar_polar_grid* grid, const void* raw,
                                   const float* window, const double* pulse_angle_rad, int32_t row_first,
                                   int32_t row_count, void* image, rosar_stream stream) {

@@ -5,6 +5,11 @@
 // at the bin of the slant range from that pulse to the target (eq. 2, eq. 40).  Without the
 // rotation symmetry each pixel has its own tap geometry: a thread owns a pixel and evaluates it
 // in float64, reading the band samples from global memory.
+//
+// POLAR: the targets are the pixels of a polar grid of A azimuth bins that need not equal N
+// (Algorithm 2's round(phi_t / phi_Delta) with phi_t = phi0 + 2 pi a / A): pixel (i, a) has
+// R_t = R_i, the weights of row i, and the same per-pixel tap geometry.  A = N gives the
+// plain sparse filter's image.
 #include <hip/hip_runtime.h>
 
 #include "rosar_device.hpp"
@@ -14,7 +19,7 @@ namespace {
 
 constexpr int kCartThreads = 256;
 
-template <int DT, int WDT, int INTERP>
+template <int DT, int WDT, int INTERP, bool POLAR>
 __global__ __launch_bounds__(kCartThreads) void sparse_cartesian_kernel(Geo g, View y, CartGrid c, int32_t k,
                                                                         int32_t half_w,
                                                                         const int32_t* __restrict__ offsets,
@@ -23,11 +28,19 @@ __global__ __launch_bounds__(kCartThreads) void sparse_cartesian_kernel(Geo g, V
   const int ix = blockIdx.x * kCartThreads + threadIdx.x;
   const int iy = blockIdx.y;
   if (ix >= c.nx) return;   // no barrier in this kernel
-  const double x = c.x0 + ix * c.dx, yy = c.y0 + iy * c.dy;
-  const double rt = sqrt(x * x + yy * yy);
-  const double phi = atan2(yy, x);
+  double rt, phi;
+  int row;
+  if constexpr (POLAR) {   // c.nx = A azimuth bins, c.ny = rows
+    rt = g.r0 + iy * g.dr;
+    phi = g.phi0 + ix * (6.283185307179586476925286766559 / c.nx);
+    row = iy;
+  } else {
+    const double x = c.x0 + ix * c.dx, yy = c.y0 + iy * c.dy;
+    rt = sqrt(x * x + yy * yy);
+    phi = atan2(yy, x);
+    row = (int)floor((rt - g.r0) / g.dr + 0.5);
+  }
   const int nc = (int)floor((phi - g.phi0) / g.step + 0.5);
-  const int row = (int)floor((rt - g.r0) / g.dr + 0.5);
   float2 acc = make_float2(0.f, 0.f);
   if (row >= 0 && row < g.n_range) {
     const double c1 = rt * rt + g.radius * g.radius;
@@ -67,31 +80,41 @@ __global__ __launch_bounds__(kCartThreads) void sparse_cartesian_kernel(Geo g, V
   image[(size_t)iy * c.nx + ix] = make_float2(acc.x * y.inv_scale, acc.y * y.inv_scale);
 }
 
-template <int DT, int WDT>
+template <int DT, int WDT, bool POLAR>
 hipError_t launch_wdt(const SparseArgs& a, const CartGrid& c, hipStream_t s) {
   dim3 grid((c.nx + kCartThreads - 1) / kCartThreads, c.ny);
   if (a.interp == ROSAR_LINEAR)
-    sparse_cartesian_kernel<DT, WDT, ROSAR_LINEAR><<<grid, kCartThreads, 0, s>>>(a.g, a.y, c, a.k, a.window / 2,
-                                                                                a.offsets, a.weights, a.image);
+    sparse_cartesian_kernel<DT, WDT, ROSAR_LINEAR, POLAR><<<grid, kCartThreads, 0, s>>>(
+        a.g, a.y, c, a.k, a.window / 2, a.offsets, a.weights, a.image);
   else
-    sparse_cartesian_kernel<DT, WDT, ROSAR_NEAREST><<<grid, kCartThreads, 0, s>>>(a.g, a.y, c, a.k, a.window / 2,
-                                                                                 a.offsets, a.weights, a.image);
+    sparse_cartesian_kernel<DT, WDT, ROSAR_NEAREST, POLAR><<<grid, kCartThreads, 0, s>>>(
+        a.g, a.y, c, a.k, a.window / 2, a.offsets, a.weights, a.image);
   return hipGetLastError();
 }
 
-template <int DT>
+template <int DT, bool POLAR>
 hipError_t launch_dt(const SparseArgs& a, const CartGrid& c, hipStream_t s) {
-  return a.w_dtype == ROSAR_C64 ? launch_wdt<DT, 0>(a, c, s) : launch_wdt<DT, 1>(a, c, s);
+  return a.w_dtype == ROSAR_C64 ? launch_wdt<DT, 0, POLAR>(a, c, s) : launch_wdt<DT, 1, POLAR>(a, c, s);
+}
+
+template <bool POLAR>
+hipError_t launch_any(const SparseArgs& a, const CartGrid& c, hipStream_t s) {
+  switch (a.y.dtype) {
+    case ROSAR_C64: return launch_dt<0, POLAR>(a, c, s);
+    case ROSAR_C16_F16: return launch_dt<1, POLAR>(a, c, s);
+    default: return launch_dt<2, POLAR>(a, c, s);
+  }
 }
 
 }  // namespace
 
 hipError_t launch_sparse_cartesian(const SparseArgs& a, const CartGrid& c, hipStream_t s) {
-  switch (a.y.dtype) {
-    case ROSAR_C64: return launch_dt<0>(a, c, s);
-    case ROSAR_C16_F16: return launch_dt<1>(a, c, s);
-    default: return launch_dt<2>(a, c, s);
-  }
+  return launch_any<false>(a, c, s);
+}
+
+hipError_t launch_sparse_polar(const SparseArgs& a, int32_t n_az, hipStream_t s) {
+  const CartGrid c{n_az, a.g.n_range, 0.0, 0.0, 0.0, 0.0};
+  return launch_any<true>(a, c, s);
 }
 
 }  // namespace rosar

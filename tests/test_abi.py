@@ -383,6 +383,25 @@ def test_sas_time_domain_validation(lib):
     assert call(gg=geom(n_fast=4096, n_fft=4096)) == L.ROSAR_ERR_UNSUPPORTED
 
 
+def test_polar_validation(lib):
+    g = geom()
+    view = L.RcView(0x20000, L.C64, 0, 64, 32, 424, 1.0, 0)
+    sset = L.SparseSet(32, 64, 0x30000, 0x40000, L.C64, 0)
+
+    def call(grid, image=FAKE):
+        return lib.rosar_sparse_filter_polar(C.byref(g), C.byref(grid) if grid else None, C.byref(view),
+                                             C.byref(sset), L.NEAREST, image, None)
+
+    assert call(None) == L.ROSAR_ERR_INVALID_ARG
+    assert call(L.PolarGrid(8, 500, 1.0, 0.05), image=None) == L.ROSAR_ERR_INVALID_ARG
+    for bad in (L.PolarGrid(8, 0, 1.0, 0.05), L.PolarGrid(8, (1 << 24) + 1, 1.0, 0.05),
+                L.PolarGrid(0, 500, 1.0, 0.05), L.PolarGrid(8, 500, -1.0, 0.05)):
+        assert call(bad) == L.ROSAR_ERR_INVALID_ARG, (bad.n_range, bad.n_az, bad.r0_m)
+    assert call(L.PolarGrid(70000, 500, 1.0, 0.05)) == L.ROSAR_ERR_UNSUPPORTED
+    assert call(L.PolarGrid(40000, 60000, 1.0, 0.0001)) == L.ROSAR_ERR_UNSUPPORTED
+    assert lib.rosar_last_error().decode() != ""
+
+
 def test_cartesian_validation(lib):
     g, grid = geom(), L.PolarGrid(8, 360, 1.0, 0.05)
     view = L.RcView(0x20000, L.C64, 0, 64, 32, 424, 1.0, 0)

@@ -88,3 +88,56 @@ def test_cartesian_paper_radar():
     ref = oracle.sparse_filter_cartesian(yb, x.l_lo, g, w.grid, xs, ys, x.offsets, x.weights,
                                          "linear").reshape(126, 126)
     assert rel_l2(img, ref) <= TOL
+
+
+def polar_positions(grid, n_az):
+    """Targets of a polar grid with n_az azimuth bins: R_i, phi0 + 2 pi a / n_az (phi0 = 0)."""
+    r = grid.r0_m + np.arange(grid.n_range) * grid.dr_m
+    phi = 2 * np.pi * np.arange(n_az) / n_az
+    return (r[:, None] * np.cos(phi)[None, :]).ravel(), (r[:, None] * np.sin(phi)[None, :]).ravel()
+
+
+@pytest.mark.parametrize("interp,n_az", [("nearest", 500), ("linear", 500), ("nearest", 250)])
+def test_polar_az_other_than_pulses(interp, n_az):
+    """A = 500 and 250 azimuth bins for N = 360 pulses (a N / A never falls halfway between two
+    pulses, so the central phase centre has no tie), against Algorithm 2 at those targets."""
+    rs = need_gpu()
+    w, x = inputs("small")
+    g = w.geometry
+    grid = dataclasses.replace(w.grid, n_az=n_az)
+    rc = rs.range_compress(g, to_dev(x.raw), to_dev(x.window), x.l_lo, x.l_count, halo=w.sparse.window // 2)
+    log(f"polar A={n_az} {interp}")
+    img = rs.sparse_filter_polar(g, grid, rc, to_dev(x.offsets), to_dev(x.weights.astype(np.complex64)),
+                                 w.sparse.window, interp=interp).cpu().numpy()
+    xs, ys = polar_positions(grid, n_az)
+    ref = oracle.sparse_filter_cartesian(oracle_band("small"), x.l_lo, g, w.grid, xs, ys, x.offsets, x.weights,
+                                         interp).reshape(grid.n_range, n_az)
+    assert img.shape == (grid.n_range, n_az)
+    assert rel_l2(img, ref) <= TOL
+
+
+def test_polar_az_equal_pulses_is_plain_filter():
+    rs = need_gpu()
+    w, x = inputs("small")
+    rc = rs.range_compress(w.geometry, to_dev(x.raw), to_dev(x.window), x.l_lo, x.l_count, halo=w.sparse.window // 2)
+    off, wts = to_dev(x.offsets), to_dev(x.weights.astype(np.complex64))
+    log("polar A=N")
+    a = rs.sparse_filter_polar(w.geometry, w.grid, rc, off, wts, w.sparse.window).cpu().numpy()
+    b = rs.sparse_filter(w.geometry, w.grid, rc, off, wts, w.sparse.window).cpu().numpy()
+    assert rel_l2(a, b) <= 1e-6
+
+
+def test_polar_az_f16():
+    rs = need_gpu()
+    w, x = inputs("small")
+    g = w.geometry
+    grid = dataclasses.replace(w.grid, n_az=500)
+    rc = rs.range_compress(g, to_dev(x.raw), to_dev(x.window), x.l_lo, x.l_count, halo=w.sparse.window // 2,
+                           dtype="f16", scale=2.0 ** -4)
+    log("polar A=500 f16")
+    img = rs.sparse_filter_polar(g, grid, rc, to_dev(x.offsets), to_dev(x.weights.astype(np.complex64)),
+                                 w.sparse.window).cpu().numpy()
+    xs, ys = polar_positions(grid, 500)
+    ref = oracle.sparse_filter_cartesian(oracle_band("small"), x.l_lo, g, w.grid, xs, ys, x.offsets, x.weights,
+                                         "nearest").reshape(grid.n_range, 500)
+    assert rel_l2(img, ref) <= 1e-2
