@@ -75,3 +75,32 @@ def test_delta_r_grows_with_sigma():
     assert bool((hi > lo).all())
     ratio = (hi / lo).cpu().numpy()
     np.testing.assert_allclose(ratio, 2.0, rtol=1e-3)   # linear in sigma to first order
+
+
+def test_delta_r_graph_replays():
+    """Captured in a HIP graph (no memset nodes), every replay equals the eager result bit for
+    bit, with eager work and synchronisations between replays; the samples buffer is reused."""
+    rs = need_gpu()
+    g = synth.radar(800, 64, 0.145)
+    grid = synth.PolarGrid(21, 800, 0.3, 0.2)
+    d = to_dev(synth.jitter_draws(26, 128, 1000, np.deg2rad(0.086)))
+    out = torch.empty(21, dtype=torch.float64, device="cuda")
+    smp = torch.empty((21, 1000), dtype=torch.float64, device="cuda")
+    log("delta_r graph replays")
+    rs.delta_r(g, grid, 128, d, samples=smp, out=out)
+    torch.cuda.synchronize()
+    ref_out, ref_smp = out.clone(), smp.clone()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(graph, stream=s):
+            rs.delta_r(g, grid, 128, d, samples=smp, out=out)
+    torch.cuda.current_stream().wait_stream(s)
+    for i in range(4):
+        out.fill_(-1.0)
+        smp.fill_(-1.0)
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(out, ref_out) and torch.equal(smp, ref_smp), i
