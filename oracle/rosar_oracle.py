@@ -192,6 +192,41 @@ def delta_r(samples: np.ndarray, q: float = 0.99) -> np.ndarray:
     return s[:, idx]
 
 
+def beampattern(geom, grid, offsets: np.ndarray, weights: np.ndarray, window: int,
+                angles: np.ndarray) -> np.ndarray:
+    """|w^H a(phi; R)| of each range row's sparse weights (Sec. III-A, eq. 16 and C1/C2 of
+    eq. 20): a target at angle phi from a pixel's direction is seen by tap k (pulse a + o_k) at
+    D_k = phi - o_k 2 pi / N, with a_k = alpha(D_k) exp(-j 2 k R(D_k)), R from eq. 2 and alpha
+    = max(R cos D - r, 0) / R(D) as in BPA.  Taps outside [-W/2, W/2) contribute nothing (the
+    filter's rule).  Returns [n_range, len(angles)]."""
+    k = wavenumber(geom)
+    r = geom.radius_m
+    step = TWO_PI / geom.n_pulses
+    out = np.zeros((grid.n_range, len(angles)))
+    half = window // 2
+    for row in range(grid.n_range):
+        rr = grid.r0_m + row * grid.dr_m
+        o = offsets[row].astype(np.int64)
+        keep = (o >= -half) & (o < half)
+        d = angles[:, None] - o[None, keep] * step                     # [A, K']
+        rn = slant_range(rr, r, d)
+        al = np.maximum(rr * np.cos(d) - r, 0.0) / rn
+        a = al * np.exp(-1j * 2.0 * k * rn)
+        out[row] = np.abs(a @ np.conj(weights[row, keep]))
+    return out
+
+
+def robust_summary(main: np.ndarray, side_max: np.ndarray, delta_r: np.ndarray) -> np.ndarray:
+    """Worst case over array errors of norm <= Delta_R for a unit-norm w (the Cauchy-Schwarz and
+    triangle bounds of Sec. III-A): main-lobe gain >= (|w^H a_m| - Delta_R)^2, side-lobe response
+    <= (|w^H a_s| + Delta_R)^2.  Returns their ratio per row (+inf when |w^H a_m| <= Delta_R);
+    a design meets C2 relative to C1 when it is <= eta."""
+    lo = main - delta_r
+    hi = side_max + delta_r
+    with np.errstate(divide="ignore"):
+        return np.where(lo > 0, hi * hi / np.where(lo > 0, lo * lo, 1.0), np.inf)
+
+
 def sparse_filter_cartesian(yb: np.ndarray, l_lo: int, geom, grid, xs: np.ndarray, ys: np.ndarray,
                             offsets: np.ndarray, weights: np.ndarray, interp: str = "nearest") -> np.ndarray:
     """Algorithm 2 for targets at Cartesian positions (xs[i], ys[i]) (FFT+SAS form, eq. 43):

@@ -435,6 +435,87 @@ def test_delta_r_quantile():
     assert oracle.delta_r(samples, 0.6)[0] == 3.0      # ceil(0.6 * 5) = 3rd smallest
 
 
+def _cartesian_steering(geom, rr, phi, offsets, k):
+    """Tap elements from explicit positions: phase centre of tap o on the circle at angle
+    o 2 pi / N, boresight radial; target at angle phi, range rr."""
+    th = offsets * 2 * np.pi / geom.n_pulses
+    px, py = geom.radius_m * np.cos(th), geom.radius_m * np.sin(th)
+    tx, ty = rr * np.cos(phi), rr * np.sin(phi)
+    dx, dy = tx - px, ty - py
+    dist = np.hypot(dx, dy)
+    cos_b = (dx * np.cos(th) + dy * np.sin(th)) / dist
+    return np.maximum(cos_b, 0.0) * np.exp(-1j * 2 * k * dist)
+
+
+def test_beampattern_matched_weights_cartesian():
+    """Weights matched to the main-lobe steering vector built from explicit Cartesian positions:
+    |w^H a(0)| = ||a(0)|| (Cauchy-Schwarz equality) and every other direction is <= it."""
+    g = small_geom(360, 64, 0.25)
+    grid = synth.PolarGrid(3, 360, 0.8, 0.9)
+    k = oracle.wavenumber(g)
+    rng = np.random.default_rng(31)
+    offs = np.stack([np.sort(rng.choice(np.arange(-32, 32), 24, replace=False)) for _ in range(3)]).astype(np.int32)
+    w = np.zeros((3, 24), complex)
+    for i in range(3):
+        rr = grid.r0_m + i * grid.dr_m
+        a0 = _cartesian_steering(g, rr, 0.0, offs[i], k)
+        w[i] = a0 / np.linalg.norm(a0)
+    ang = np.concatenate([[0.0], np.linspace(-0.3, 0.3, 61)])
+    pat = oracle.beampattern(g, grid, offs, w, 64, ang)
+    for i in range(3):
+        rr = grid.r0_m + i * grid.dr_m
+        np.testing.assert_allclose(pat[i, 0], np.linalg.norm(_cartesian_steering(g, rr, 0.0, offs[i], k)), rtol=1e-12)
+        for j, phi in enumerate(ang):
+            want = abs(np.vdot(w[i], _cartesian_steering(g, rr, phi, offs[i], k)))
+            np.testing.assert_allclose(pat[i, j], want, rtol=1e-9, atol=1e-12)
+        assert pat[i, 1:].max() <= pat[i, 0] * (1 + 1e-12)
+
+
+def test_beampattern_offset_shift_invariance():
+    """Shifting every offset by one pulse and the direction by one pulse step leaves D_k, hence
+    the pattern, unchanged; taps shifted out of the window drop out."""
+    g = small_geom(360, 64, 0.25)
+    grid = synth.PolarGrid(2, 360, 1.0, 0.5)
+    rng = np.random.default_rng(32)
+    offs = np.stack([np.sort(rng.choice(np.arange(-30, 30), 16, replace=False)) for _ in range(2)]).astype(np.int32)
+    w = rng.normal(size=(2, 16)) + 1j * rng.normal(size=(2, 16))
+    ang = np.linspace(-0.2, 0.2, 41)
+    a = oracle.beampattern(g, grid, offs, w, 64, ang)
+    b = oracle.beampattern(g, grid, offs + 1, w, 64, ang + 2 * np.pi / 360)
+    np.testing.assert_allclose(a, b, rtol=1e-9)
+    offs2 = offs.copy()
+    offs2[:, 0] = 40                      # outside [-32, 32): contributes nothing
+    w2 = w.copy()
+    w2[:, 0] = 0
+    np.testing.assert_allclose(oracle.beampattern(g, grid, offs2, w, 64, ang),
+                               oracle.beampattern(g, grid, offs, w2, 64, ang), rtol=1e-12)
+
+
+def test_robust_summary_bounds_random_errors():
+    """For unit-norm w and errors of norm <= Delta_R, |w^H (a + e)|^2 stays within the bounds the
+    summary's ratio is built from, and the bound is reached by e along a (equality case)."""
+    rng = np.random.default_rng(33)
+    n = 40
+    w = rng.normal(size=n) + 1j * rng.normal(size=n)
+    w /= np.linalg.norm(w)
+    am = rng.normal(size=n) + 1j * rng.normal(size=n)
+    as_ = 0.2 * (rng.normal(size=n) + 1j * rng.normal(size=n))
+    dr = 0.3
+    main, side = abs(np.vdot(w, am)), abs(np.vdot(w, as_))
+    ratio = oracle.robust_summary(np.array([main]), np.array([side]), np.array([dr]))[0]
+    worst_m, worst_s = np.inf, 0.0
+    for _ in range(2000):
+        e = rng.normal(size=n) + 1j * rng.normal(size=n)
+        e *= dr * rng.uniform() ** (1 / (2 * n)) / np.linalg.norm(e)
+        worst_m = min(worst_m, abs(np.vdot(w, am + e)) ** 2)
+        worst_s = max(worst_s, abs(np.vdot(w, as_ + e)) ** 2)
+    assert worst_m >= (main - dr) ** 2 - 1e-12 and worst_s <= (side + dr) ** 2 + 1e-12
+    assert worst_s / worst_m <= ratio
+    e_eq = -dr * w * np.exp(1j * np.angle(np.vdot(w, am)))     # aligned with w, against w^H a_m
+    np.testing.assert_allclose(abs(np.vdot(w, am + e_eq)), main - dr, rtol=1e-12)
+    assert np.isinf(oracle.robust_summary(np.array([0.1]), np.array([0.0]), np.array([0.2]))[0])
+
+
 # --------------------------------------------------------------------------- P9
 def test_linearity():
     w = synth.small()
