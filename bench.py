@@ -663,6 +663,27 @@ def main():
             "note": "samples kernel (float64 error norms) + per-row radix selection of the 99 % point"}
         print(f"[bench] Delta_R Monte-Carlo: {ms_dr:.3f} ms ({evals / (ms_dr * 1e-3):.3g} element evaluations/s)",
               file=sys.stderr, flush=True)
+        # beampattern of the weights over the window's angular span and the worst-case check
+        # (C1/C2 worst-case forms) with that Delta_R
+        bp_ang = torch.from_numpy(np.concatenate([[0.0], np.linspace(-np.pi * w.sparse.window / g.n_pulses,
+                                                                     np.pi * w.sparse.window / g.n_pulses,
+                                                                     2048)])).to(dev)
+        bp_pat = torch.empty((grid.n_range, bp_ang.numel()), dtype=torch.float64, device=dev)
+        bp_sum = torch.empty((grid.n_range, 3), dtype=torch.float64, device=dev)
+        bpat = lambda: rs.beampattern(g, grid, off, wts, w.sparse.window, bp_ang, delta_r=dr_out, pattern=bp_pat,
+                                      summary=bp_sum)
+        bpat()
+        ms_bpat = timed(bpat, 3, out=lambda: bp_sum)
+        terms = grid.n_range * bp_ang.numel() * k
+        ratio = bp_sum[:, 2].cpu().numpy()
+        out["rows"]["beampattern"] = {
+            "ms": ms_bpat, "angles": int(bp_ang.numel()), "rows": grid.n_range, "taps": k,
+            "tap_terms_per_s": terms / (ms_bpat * 1e-3),
+            "worst_case_ratio_db_median": float(10 * np.log10(np.median(ratio))) if np.isfinite(ratio).any() else None,
+            "rows_with_main_below_delta_r": int(np.count_nonzero(~np.isfinite(ratio))),
+            "note": "float64 |w^H a(phi; R)| at 2049 angles per row + per-row worst-case summary with the Delta_R above"}
+        print(f"[bench] beampattern + robust check: {ms_bpat:.3f} ms ({terms / (ms_bpat * 1e-3):.3g} tap terms/s)",
+              file=sys.stderr, flush=True)
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, x)
         out["cpu_baseline"]["all_cores"] = cpu_baseline_all_cores(w, x)

@@ -263,6 +263,27 @@ rosar_status rosar_delta_r(const rosar_geometry* geom, const rosar_polar_grid* g
                            const double* deltas, int32_t n_samples, double quantile, double* samples,
                            double* delta_r, rosar_stream stream);
 
+/* Beampattern of the sparse weights and the worst-case robust check of a weight design
+ * (Sec. III-A: eq. 16, C1 and C2 of eq. 20 and their worst-case forms under array errors of
+ * norm <= Delta_R).  For every range row R and every angle phi_j (radians, relative to the
+ * pixel's direction):
+ *   pattern[R][j] = | sum_k conj(w[R, k]) alpha(D_k) exp(-j 2 k R(D_k)) |,  D_k = phi_j - o_k 2 pi / N,
+ * R(D) from eq. 2, alpha = max(R cos D - r, 0) / R(D); taps outside [-W/2, W/2) contribute
+ * nothing.  angles[0] is the main-lobe direction (normally 0) and the others side-lobe
+ * directions; per row summary[R] = {pattern[R][0], max over j >= 1 of pattern[R][j] (0 when
+ * n_angles = 1), (max side + Delta_R)^2 / (main - Delta_R)^2}, the last +inf when
+ * main <= Delta_R: for unit-norm weights the design meets the side-lobe level eta in the worst
+ * case when it is <= eta.  Float64 throughout.
+ * set: ROSAR_C64 weights (offsets and weights as rosar_sparse_filter); angles [n_angles] float64
+ * (device, 8-byte aligned); delta_r [n_range] float64 or NULL (Delta_R = 0), e.g. from
+ * rosar_delta_r; pattern [n_range][n_angles] and summary [n_range][3] float64 (device, 8-byte
+ * aligned, overwritten).
+ * Errors: INVALID_ARG for pointers, alignment, the set, n_angles outside [1, 2^24];
+ * UNSUPPORTED for FP16 weights or more than 65535 rows. */
+rosar_status rosar_beampattern(const rosar_geometry* geom, const rosar_polar_grid* grid, const rosar_sparse_set* set,
+                               const double* angles, int32_t n_angles, const double* delta_r, double* pattern,
+                               double* summary, rosar_stream stream);
+
 /* ---------------------------------------------------------------- time-domain BPA
  * Conventional back-projection on the raw fast-time samples (the W_BP Hadamard sum of
  * Sec. II-C), the comparator of the paper's timing tables:

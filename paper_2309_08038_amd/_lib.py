@@ -94,6 +94,8 @@ PROTOTYPES = [
                                       C.c_int32, C.c_void_p, C.c_void_p]),
     ("rosar_sparse_filter_polar", C.c_int, [_P(Geometry), _P(PolarGrid), _P(RcView), _P(SparseSet), C.c_int,
                                             C.c_void_p, C.c_void_p]),
+    ("rosar_beampattern", C.c_int, [_P(Geometry), _P(PolarGrid), _P(SparseSet), C.c_void_p, C.c_int32, C.c_void_p,
+                                    C.c_void_p, C.c_void_p, C.c_void_p]),
     ("rosar_delta_r", C.c_int, [_P(Geometry), _P(PolarGrid), C.c_int32, C.c_void_p, C.c_int32, C.c_double,
                                 C.c_void_p, C.c_void_p, C.c_void_p]),
     ("rosar_sas_time_domain", C.c_int, [_P(Geometry), _P(PolarGrid), C.c_void_p, C.c_void_p, _P(SparseSet),

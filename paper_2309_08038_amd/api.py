@@ -403,6 +403,33 @@ def delta_r(geom, grid, window: int, deltas: torch.Tensor, quantile: float = 0.9
     return out, samples
 
 
+def beampattern(geom, grid, offsets, weights, window: int, angles: torch.Tensor,
+                delta_r: torch.Tensor | None = None, pattern: torch.Tensor | None = None,
+                summary: torch.Tensor | None = None):
+    """|w^H a(phi; R)| of each row's sparse weights at `angles` (float64 radians from the pixel's
+    direction; angles[0] the main lobe) and the per-row worst-case summary {main, max side,
+    (side + Delta_R)^2 / (main - Delta_R)^2}.  Returns (pattern [n_range, A], summary [n_range, 3])."""
+    _need_gpu(angles)
+    if angles.dtype != torch.float64 or angles.dim() != 1:
+        raise ValueError("angles must be a float64 vector")
+    angles = angles.contiguous()
+    dev = angles.device
+    s = _set(offsets, weights, window)
+    if pattern is None:
+        pattern = torch.empty((grid.n_range, angles.numel()), dtype=torch.float64, device=dev)
+    if summary is None:
+        summary = torch.empty((grid.n_range, 3), dtype=torch.float64, device=dev)
+    if delta_r is not None:
+        delta_r = delta_r.contiguous()
+        if delta_r.dtype != torch.float64 or delta_r.shape != (grid.n_range,):
+            raise ValueError("delta_r must be float64 [n_range]")
+    g, p = L.geometry(geom), L.polar_grid(grid)
+    L.check(L.lib().rosar_beampattern(C.byref(g), C.byref(p), C.byref(s), _ptr(angles), angles.numel(),
+                                      None if delta_r is None else _ptr(delta_r), _ptr(pattern), _ptr(summary),
+                                      _stream(dev)), "rosar_beampattern")
+    return pattern, summary
+
+
 def sparse_filter_adjoint_band(geom, grid, layout: RangeCompressed, offsets, weights, window, grad_image,
                                interp: str = "nearest", out: torch.Tensor | None = None,
                                workspace: torch.Tensor | None = None) -> torch.Tensor:

@@ -17,7 +17,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "librosar.so")
-SOURCES = ["range_compress.hip", "sparse_filter.hip", "fastconv.hip", "adjoint_band.hip", "bp_full.hip", "bp_time_domain.hip", "cartesian.hip", "delta_r.hip", "backward.hip",
+SOURCES = ["range_compress.hip", "sparse_filter.hip", "fastconv.hip", "adjoint_band.hip", "bp_full.hip", "bp_time_domain.hip", "cartesian.hip", "delta_r.hip", "beampattern.hip", "backward.hip",
            "batch.hip", "api.cpp"]
 ARCH = "gfx950"
 

@@ -437,6 +437,27 @@ rosar_status rosar_delta_r(const rosar_geometry* geom, const rosar_polar_grid* g
                   "Delta_R Monte-Carlo launch");
 }
 
+rosar_status rosar_beampattern(const rosar_geometry* geom, const rosar_polar_grid* grid, const rosar_sparse_set* set,
+                               const double* angles, int32_t n_angles, const double* delta_r, double* pattern,
+                               double* summary, rosar_stream stream) {
+  ROSAR_TRY(check_geometry(geom));
+  ROSAR_TRY(check_grid(geom, grid));
+  ROSAR_TRY(check_set(geom, set));
+  if (set->w_dtype != ROSAR_C64) return fail(ROSAR_ERR_UNSUPPORTED, "the beampattern needs ROSAR_C64 weights");
+  if (n_angles < 1 || n_angles > (1 << 24))
+    return fail(ROSAR_ERR_INVALID_ARG, "n_angles must be in [1, 2^24] (got %d)", n_angles);
+  if (grid->n_range > 65535) return fail(ROSAR_ERR_UNSUPPORTED, "n_range must be <= 65535 (got %d)", grid->n_range);
+  if (!angles || !aligned(angles, 8)) return fail(ROSAR_ERR_INVALID_ARG, "angles NULL or misaligned");
+  if (delta_r && !aligned(delta_r, 8)) return fail(ROSAR_ERR_INVALID_ARG, "delta_r misaligned");
+  if (!pattern || !aligned(pattern, 8)) return fail(ROSAR_ERR_INVALID_ARG, "pattern NULL or misaligned");
+  if (!summary || !aligned(summary, 8)) return fail(ROSAR_ERR_INVALID_ARG, "summary NULL or misaligned");
+  if (inject_launch_fault()) return fail(ROSAR_ERR_HIP, "injected launch failure (ROSAR_FAULT_INJECT)");
+  return from_hip(rosar::launch_beampattern(make_geo(geom, grid), set->k, set->window, set->offsets,
+                                            static_cast<const float2*>(set->weights), angles, n_angles, delta_r,
+                                            pattern, summary, reinterpret_cast<hipStream_t>(stream)),
+                  "beampattern launch");
+}
+
 rosar_status rosar_sas_time_domain(const rosar_geometry* geom, const rosar_polar_grid* grid, const void* raw,
                                    const float* window, const rosar_sparse_set* set, int32_t row_first,
                                    int32_t row_count, void* image, rosar_stream stream) {

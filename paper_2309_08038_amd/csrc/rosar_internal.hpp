@@ -78,6 +78,9 @@ hipError_t launch_sas_time_domain(const Geo& g, int m_fast, double cyc_per_m, co
 hipError_t launch_delta_r(const Geo& g, int window, int n_samples, const double* deltas, int rank, double* samples,
                           double* delta_r, hipStream_t s);
 int delta_r_rows_per_block();
+hipError_t launch_beampattern(const Geo& g, int k, int window, const int32_t* offsets, const float2* weights,
+                              const double* angles, int n_ang, const double* delta_r, double* pattern,
+                              double* summary, hipStream_t s);
 hipError_t launch_bp_time_domain(const Geo& g, int m_fast, double cyc_per_m, const float2* raw, const float* window,
                                  const double* angles, int row_first, int row_count, float2* image, hipStream_t s);
 hipError_t launch_bp_full(const Geo& g, const View& y, const double* angles, int32_t interp,

@@ -383,6 +383,27 @@ def test_sas_time_domain_validation(lib):
     assert call(gg=geom(n_fast=4096, n_fft=4096)) == L.ROSAR_ERR_UNSUPPORTED
 
 
+def test_beampattern_validation(lib):
+    g, grid = geom(), L.PolarGrid(8, 360, 1.0, 0.05)
+    sset = L.SparseSet(32, 64, 0x30000, 0x40000, L.C64, 0)
+
+    def call(s=None, angles=FAKE, n=100, dr=None, pattern=FAKE, summary=FAKE, gr=None):
+        return lib.rosar_beampattern(C.byref(g), C.byref(gr or grid), C.byref(s or sset), angles, n, dr, pattern,
+                                     summary, None)
+
+    assert call(s=L.SparseSet(32, 64, 0x30000, 0x40000, L.C16_F16, 0)) == L.ROSAR_ERR_UNSUPPORTED
+    assert call(s=L.SparseSet(32, 63, 0x30000, 0x40000, L.C64, 0)) == L.ROSAR_ERR_INVALID_ARG
+    for n in (0, -3, (1 << 24) + 1):
+        assert call(n=n) == L.ROSAR_ERR_INVALID_ARG, n
+    assert call(angles=None) == L.ROSAR_ERR_INVALID_ARG
+    assert call(angles=C.c_void_p(0x10004)) == L.ROSAR_ERR_INVALID_ARG
+    assert call(dr=C.c_void_p(0x10004)) == L.ROSAR_ERR_INVALID_ARG
+    assert call(pattern=None) == L.ROSAR_ERR_INVALID_ARG
+    assert call(summary=C.c_void_p(0x10002)) == L.ROSAR_ERR_INVALID_ARG
+    assert call(gr=L.PolarGrid(70000, 360, 1.0, 0.05)) == L.ROSAR_ERR_UNSUPPORTED
+    assert lib.rosar_last_error().decode() != ""
+
+
 def test_polar_validation(lib):
     g = geom()
     view = L.RcView(0x20000, L.C64, 0, 64, 32, 424, 1.0, 0)
