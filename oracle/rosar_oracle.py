@@ -158,7 +158,7 @@ def sparse_filter(yb: np.ndarray, l_lo: int, geom, grid, offsets: np.ndarray, we
 def delta_r_samples(geom, grid, window: int, deltas: np.ndarray) -> np.ndarray:
     """Monte-Carlo samples of Delta^_R = ||a^(phi; R) - a(phi; R)|| (Sec. III-C parameter
     settings, eq. 37): a is the steering vector of the W phase centres around the target
-    direction (eq. 16: cos(theta'_n) exp(-j 2 k R_n), the sign immaterial to the norm;
+    direction (eq. 16: cos(theta'_n) exp(+j 2 k R_n);
     cos(theta'_n) = max(R cos D_n - r, 0) / R_n as in the field-of-view reading;
     D_n = o 2 pi / N for offsets o in [-W/2, W/2)), a^ the
     same with each angle perturbed by the given draw, D^_n = D_n + deltas[s, o + W/2].  Computed
@@ -196,7 +196,8 @@ def beampattern(geom, grid, offsets: np.ndarray, weights: np.ndarray, window: in
                 angles: np.ndarray) -> np.ndarray:
     """|w^H a(phi; R)| of each range row's sparse weights (Sec. III-A, eq. 16 and C1/C2 of
     eq. 20): a target at angle phi from a pixel's direction is seen by tap k (pulse a + o_k) at
-    D_k = phi - o_k 2 pi / N, with a_k = alpha(D_k) exp(-j 2 k R(D_k)), R from eq. 2 and alpha
+    D_k = phi - o_k 2 pi / N, with a_k = alpha(D_k) exp(+j 2 k R(D_k)) (eq. 16's sign, the data's
+    carrier phase; the filter applies conj(w)), R from eq. 2 and alpha
     = max(R cos D - r, 0) / R(D) as in BPA.  Taps outside [-W/2, W/2) contribute nothing (the
     filter's rule).  Returns [n_range, len(angles)]."""
     k = wavenumber(geom)
@@ -211,7 +212,7 @@ def beampattern(geom, grid, offsets: np.ndarray, weights: np.ndarray, window: in
         d = angles[:, None] - o[None, keep] * step                     # [A, K']
         rn = slant_range(rr, r, d)
         al = np.maximum(rr * np.cos(d) - r, 0.0) / rn
-        a = al * np.exp(-1j * 2.0 * k * rn)
+        a = al * np.exp(1j * 2.0 * k * rn)
         out[row] = np.abs(a @ np.conj(weights[row, keep]))
     return out
 

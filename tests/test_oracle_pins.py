@@ -444,7 +444,7 @@ def _cartesian_steering(geom, rr, phi, offsets, k):
     dx, dy = tx - px, ty - py
     dist = np.hypot(dx, dy)
     cos_b = (dx * np.cos(th) + dy * np.sin(th)) / dist
-    return np.maximum(cos_b, 0.0) * np.exp(-1j * 2 * k * dist)
+    return np.maximum(cos_b, 0.0) * np.exp(1j * 2 * k * dist)
 
 
 def test_beampattern_matched_weights_cartesian():
@@ -469,6 +469,34 @@ def test_beampattern_matched_weights_cartesian():
             want = abs(np.vdot(w[i], _cartesian_steering(g, rr, phi, offs[i], k)))
             np.testing.assert_allclose(pat[i, j], want, rtol=1e-9, atol=1e-12)
         assert pat[i, 1:].max() <= pat[i, 0] * (1 + 1e-12)
+
+
+def test_beampattern_main_lobe_is_filter_response():
+    """A unit scatterer at pixel (row, a0) whose data at each tap's bin is alpha e^{+j 2kR} (the
+    carrier phase of the data model, amplitude the cosine pattern from Cartesian positions):
+    the sparse filter's output there has the magnitude of the beampattern's main lobe, for
+    arbitrary complex weights (so the steering vector's sign and conjugation are fixed)."""
+    g = small_geom(180, 128, 0.25)
+    w = synth.Workload("p14", 47, g, synth.PolarGrid(6, 180, 1.3, 0.11),
+                       synth.SceneSpec(0, "unit", 1, 2), synth.SparseSpec(24, 64, False))
+    offs = synth.make_support(w)
+    rng = np.random.default_rng(34)
+    wts = rng.normal(size=offs.shape) + 1j * rng.normal(size=offs.shape)
+    l_lo, l_count = synth.band_for(g, w.grid)
+    row, a0 = 3, 17
+    yb = _bin_exact_scene(g, w.grid, offs, row, a0, l_lo, l_count)
+    r_t = w.grid.r0_m + row * w.grid.dr_m
+    phi_t = 2 * np.pi * a0 / 180
+    for o in offs[row]:
+        n = (a0 + int(o)) % 180
+        ang = 2 * np.pi * n / 180
+        px, py = g.radius_m * np.cos(ang), g.radius_m * np.sin(ang)
+        dx, dy = r_t * np.cos(phi_t) - px, r_t * np.sin(phi_t) - py
+        yb[n] *= (dx * np.cos(ang) + dy * np.sin(ang)) / np.hypot(dx, dy)
+    img = oracle.sparse_filter_at(yb, l_lo, g, w.grid, offs, wts, np.array([row]), np.array([a0]))[0]
+    sub = synth.PolarGrid(1, 180, r_t, 0.11)
+    pat = oracle.beampattern(g, sub, offs[row:row + 1], wts[row:row + 1], 64, np.array([0.0]))[0, 0]
+    np.testing.assert_allclose(abs(img), pat, rtol=1e-9)
 
 
 def test_beampattern_offset_shift_invariance():
