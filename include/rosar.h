@@ -247,7 +247,7 @@ rosar_status rosar_sparse_filter_polar(const rosar_geometry* geom, const rosar_p
  * directions of the W-element window around a target are perturbed by drawn angle errors, and
  * for every range row R of the grid and every draw s
  *   samples[R][s] = || a^(phi; R) - a(phi; R) ||,
- * a_e = alpha_e exp(-j 2 k R_e) the steering vector of eq. 16 at D_e = (e - W/2) 2 pi / N
+ * a_e = alpha_e exp(+j 2 k R_e) the steering vector of eq. 16 at D_e = (e - W/2) 2 pi / N
  * (alpha as rosar_bp_full: max(R cos D - r, 0) / R_e), a^ the same at D_e + deltas[e][s].
  * delta_r[R] is then the sample of rank ceil(quantile * n_samples) - 1 in ascending order (the
  * quantile point of the empirical CDF; the paper takes 0.99).  The draws are inputs: the caller
@@ -267,7 +267,7 @@ rosar_status rosar_delta_r(const rosar_geometry* geom, const rosar_polar_grid* g
  * (Sec. III-A: eq. 16, C1 and C2 of eq. 20 and their worst-case forms under array errors of
  * norm <= Delta_R).  For every range row R and every angle phi_j (radians, relative to the
  * pixel's direction):
- *   pattern[R][j] = | sum_k conj(w[R, k]) alpha(D_k) exp(-j 2 k R(D_k)) |,  D_k = phi_j - o_k 2 pi / N,
+ *   pattern[R][j] = | sum_k conj(w[R, k]) alpha(D_k) exp(+j 2 k R(D_k)) |,  D_k = phi_j - o_k 2 pi / N,
  * R(D) from eq. 2, alpha = max(R cos D - r, 0) / R(D); taps outside [-W/2, W/2) contribute
  * nothing.  angles[0] is the main-lobe direction (normally 0) and the others side-lobe
  * directions; per row summary[R] = {pattern[R][0], max over j >= 1 of pattern[R][j] (0 when

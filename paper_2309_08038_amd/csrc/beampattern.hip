@@ -2,7 +2,7 @@
 // (Sec. III-A: eq. 16, the constraints C1 and C2 of eq. 20 and their worst-case forms): for range
 // row R and a target at angle phi from the pixel's direction, tap k (pulse a + o_k) sees it at
 // D_k = phi - o_k phi_Delta, so
-//   P(R, phi) = | sum_k conj(w_k) alpha(D_k) exp(-j 2 k R(D_k)) | = |w^H a(phi; R)|,
+//   P(R, phi) = | sum_k conj(w_k) alpha(D_k) exp(+j 2 k R(D_k)) | = |w^H a(phi; R)|,
 // R(D) from eq. 2 and alpha = max(R cos D - r, 0) / R(D).  Taps outside the window contribute
 // nothing, as in the filter.  A thread owns one (row, angle) and sums the taps in float64, with
 // the carrier phase reduced in revolutions before its sine and cosine.  The summary takes angle
@@ -38,9 +38,9 @@ __global__ __launch_bounds__(kBpatThreads) void beampattern_kernel(Geo g, int k,
     const double cd = cos(phi - o * g.step);
     const double rn = sqrt(c1 - c2 * cd);
     const double al = fmax(rr * cd - g.radius, 0.0) / rn;
-    const double rev = rn * g.k_over_pi;   // exp(-j 2 k R) in revolutions
+    const double rev = rn * g.k_over_pi;   // exp(+j 2 k R) (eq. 16) in revolutions
     double s, c;
-    sincospi(-2.0 * (rev - rint(rev)), &s, &c);
+    sincospi(2.0 * (rev - rint(rev)), &s, &c);
     const double ex = al * c, ey = al * s;
     // conj(w) * a
     ax += (double)w.x * ex + (double)w.y * ey;

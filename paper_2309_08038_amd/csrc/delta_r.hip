@@ -1,7 +1,7 @@
 // Monte-Carlo bound of the steering-vector error under rotation jitter (Sec. III-C, parameter
 // settings, eq. 37): for every range row R and every draw s of the phase-centre angle errors,
 //   D^_e = D_e + delta[e, s],  D_e = (e - W/2) 2 pi / N,
-//   Delta^_R[s] = || a^(phi; R) - a(phi; R) ||,  a_e = alpha_e exp(-j 2 k R_e)  (eq. 16),
+//   Delta^_R[s] = || a^(phi; R) - a(phi; R) ||,  a_e = alpha_e exp(+j 2 k R_e)  (eq. 16),
 // and Delta_R is the order statistic of rank ceil(q S) - 1 of those S values (the 99 % point of
 // their CDF for q = 0.99).  Each element adds (alpha^ - alpha)^2 + 4 alpha alpha^ sin^2(psi / 2),
 // psi = 2 k (R^ - R), with R^ - R = 2 R r (cos D - cos D^) / (R^ + R): no difference of two
