@@ -448,7 +448,7 @@ def main():
     a = parse()
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); the imaging path has no multi-GPU "
-              "code: sharding by azimuth sector or rotation is described in DESIGN.md", file=sys.stderr)
+              "code (it would shard by azimuth sector with a W/2-pulse halo, or by rotation)", file=sys.stderr)
         sys.exit(2)
     import torch
     import synth
