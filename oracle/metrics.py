@@ -114,3 +114,29 @@ def pslr_db(img: np.ndarray, rows, azs, half_window: int, exclude: np.ndarray | 
         if side and cut[pa] > 0:
             out[i] = 10 * np.log10(max(side) / cut[pa])
     return (out, ext, pks) if return_lobes else out
+
+
+def pisr_db(img: np.ndarray, rows, azs, half_window: int, exclude: np.ndarray | None = None,
+            search: int = 3, lobes=None, peaks=None):
+    """Peak-to-integral sidelobe ratio (eq. 44) in dB, |I(phi_m, R)|^2 / sum_s |I(phi_s, R)|^2, on
+    the circular azimuth cut through each scatterer's peak.  The peak and the main lobe are those
+    of pslr_db (same `search`, `lobes`, `peaks`); the side-lobe directions phi_s are the bins
+    within +-half_window of the peak outside the main lobe and outside `exclude`.  Higher is
+    better.  One value per scatterer (nan where undefined)."""
+    _, ext, pks = pslr_db(img, rows, azs, half_window, exclude, search, lobes, True, peaks)
+    n_a = img.shape[1]
+    mag = np.abs(img.astype(np.complex128)) ** 2
+    out = np.full(len(rows), np.nan)
+    for i, ((lo, hi), (pr, pa)) in enumerate(zip(ext, pks)):
+        if pr < 0:
+            continue
+        side = 0.0
+        for d in range(-half_window, half_window + 1):
+            a = (pa + d) % n_a
+            if -lo <= d <= hi or (exclude is not None and exclude[pr, a]):
+                continue
+            side += mag[pr, a]
+        if side > 0 and mag[pr, pa] > 0:
+            out[i] = 10 * np.log10(mag[pr, pa] / side)
+    return out
+

@@ -71,6 +71,14 @@ def test_reduced_precision_nmse_pslr(precision_case, dtype, scale):
         f"scatterers (PSLR median {np.median(p_ref[ok]):.1f} dB); vs complex64 worst {d_64.max():.3f} dB; "
         f"with each image's own main-lobe extent: worst {d_own.max():.3f} dB (scatterer {worst}: lobes "
         f"ref {lobes[worst]} vs {own_lobes[worst]}, PSLR {p_ref[worst]:.2f} vs {p_own[worst]:.2f} dB)")
+    # PISR (eq. 44) over the same peaks and main lobes
+    i_ref = metrics.pisr_db(ref, rows, azs, half, excl, lobes=lobes, peaks=pk)
+    i_img = metrics.pisr_db(img, rows, azs, half, excl, lobes=lobes, peaks=pk)
+    oki = ~np.isnan(i_ref)
+    di = np.abs(i_img - i_ref)[oki]
+    log(f"precision {dtype}: |dPISR| vs FP64 median {np.median(di):.4f} dB worst {di.max():.4f} dB "
+        f"(PISR median {np.median(i_ref[oki]):.2f} dB)")
     assert e_ref <= 1e-2
     assert d_ref.max() <= 0.5
     assert d_64.max() <= 0.5
+    assert di.max() <= 0.5

@@ -718,6 +718,18 @@ def test_point_target_focus():
 
 
 # --------------------------------------------------------------------------- metrics
+@pytest.mark.parametrize("m", [16, 64, 250])
+def test_pisr_rect_aperture_closed_form(m):
+    """Rectangular aperture of M (even) samples, transformed with 2M points (a circular cut):
+    even bins are nulls, odd bin j has |X|^2 = csc^2(pi j / 2M), and the odd-bin sum is M^2, so
+    with the main lobe {-2..2} (out to the first nulls) PISR = M^2 / (M^2 - 2 csc^2(pi / 2M))."""
+    cut = np.fft.fft(np.ones(m), 2 * m)
+    want = 10 * np.log10(m * m / (m * m - 2 / np.sin(np.pi / (2 * m)) ** 2))
+    got = metrics.pisr_db(cut[None, :], [0], [0], m - 1)[0]
+    assert got == pytest.approx(want, abs=1e-9)
+    assert 7.0 < got < 7.5            # tends to -10 log10(1 - 8 / pi^2) = 7.24 dB
+
+
 def test_entropy_closed_forms():
     assert metrics.image_entropy(np.ones((4, 8))) == pytest.approx(math.log(32), abs=1e-12)
     z = np.zeros((5, 5), complex); z[2, 3] = 3 - 4j
