@@ -444,6 +444,20 @@ def extras(torch, rs, synth, w, x, dev, rc, off, wts, timed, reps):
     return out
 
 
+class Phase:
+    """A roctx range around one phase of the run (shown by rocprofv3 --marker-trace)."""
+
+    def __init__(self, torch, name):
+        self.torch, self.name = torch, name
+
+    def __enter__(self):
+        self.torch.cuda.nvtx.range_push(self.name)
+
+    def __exit__(self, *exc):
+        self.torch.cuda.nvtx.range_pop()
+        return False
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -520,7 +534,8 @@ def main():
     # compression of step i + 1 on a second stream overlapping the sparse filter of step i
     # (double-buffered band); every step still runs its whole path over its input
     t0 = time.perf_counter()
-    ms_step, last = pipelined_steps(torch, rs, g, grid, x, raw, win, w.sparse.window, sf, a.steps)
+    with Phase(torch, "timed steps (two streams)"):
+        ms_step, last = pipelined_steps(torch, rs, g, grid, x, raw, win, w.sparse.window, sf, a.steps)
     wall = time.perf_counter() - t0
     if not torch.equal(last, ref):
         raise RuntimeError("pipelined steps differ from the serial result")
@@ -619,7 +634,8 @@ def main():
                   "kernel_ms.sparse_filter_single_call is the entry point that builds them in every workgroup",
     }
     if not a.no_extras:
-        out["rows"] = extras(torch, rs, synth, w, x, dev, rc, off, wts, timed, a.steps)
+        with Phase(torch, "extras"):
+            out["rows"] = extras(torch, rs, synth, w, x, dev, rc, off, wts, timed, a.steps)
         # conventional time-domain BPA (raw samples, exact beat frequency): the paper's timing
         # comparator; its cost is pixels x visible pulses x M, so 8 rows of the grid are timed
         first, count = grid.n_range // 2, 8
@@ -685,8 +701,9 @@ def main():
         print(f"[bench] beampattern + robust check: {ms_bpat:.3f} ms ({terms / (ms_bpat * 1e-3):.3g} tap terms/s)",
               file=sys.stderr, flush=True)
     if not a.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(w, x)
-        out["cpu_baseline"]["all_cores"] = cpu_baseline_all_cores(w, x)
+        with Phase(torch, "cpu baseline"):
+            out["cpu_baseline"] = cpu_baseline(w, x)
+            out["cpu_baseline"]["all_cores"] = cpu_baseline_all_cores(w, x)
     print(json.dumps(out))
 
 

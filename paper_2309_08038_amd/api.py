@@ -7,6 +7,8 @@ are float16 / bfloat16 tensors with a trailing dimension of 2 (re, im).
 from __future__ import annotations
 
 import ctypes as C
+import json
+import os
 from dataclasses import dataclass
 
 import torch
@@ -294,15 +296,62 @@ def _descs(rotations):
     return arr
 
 
+def autotune_cache_key(arch: str, geom, grid, rc_dtype: str, l_count: int, k: int, window: int, w_dtype: int,
+                       interp: str, methods: str) -> str:
+    """Key of a plan-autotune result: the GPU architecture and the shape class that decides the
+    launch shape (pulses, rows, band rows, taps, window, storage and weight types, interpolation)."""
+    return (f"{arch}|plan|N={geom.n_pulses}|rows={grid.n_range}|band={l_count}|K={k}|W={window}|dt={rc_dtype}"
+            f"|wdt={w_dtype}|{interp}|{methods}")
+
+
+def autotune_cache_get(path: str, key: str):
+    """Cached (tile, microseconds) for `key`, or None (missing or unreadable file, no entry)."""
+    try:
+        with open(path) as f:
+            e = json.load(f).get(key)
+    except (OSError, ValueError):
+        return None
+    if not e:
+        return None
+    tile = e["tile"] if isinstance(e["tile"], str) else tuple(e["tile"])
+    return tile, float(e["us"])
+
+
+def autotune_cache_put(path: str, key: str, tile, us: float) -> None:
+    """Store a result, keeping the other entries; written to a temporary file and renamed, so a
+    reader never sees a partial file."""
+    try:
+        with open(path) as f:
+            d = json.load(f)
+    except (OSError, ValueError):
+        d = {}
+    d[key] = {"tile": tile if isinstance(tile, str) else list(tile), "us": us}
+    tmp = f"{path}.{os.getpid()}.tmp"
+    with open(tmp, "w") as f:
+        json.dump(d, f, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+
+
 def sparse_plan_autotune(geom, grid, rc: RangeCompressed, offsets, weights, window, interp: str = "nearest",
-                         reps: int = 20, out: torch.Tensor | None = None, methods: str = "all"):
+                         reps: int = 20, out: torch.Tensor | None = None, methods: str = "all",
+                         cache: str | None = None):
     """Time every plan launch shape on `rc`, and the azimuth fast convolution where the layout
     admits it; returns (tile, microseconds) with tile = (pixels_per_lane, waves) or "fastconv",
-    to pass as SparsePlan(tile=...).  methods: "all", "direct" or "fastconv"."""
+    to pass as SparsePlan(tile=...).  methods: "all", "direct" or "fastconv".  cache: a JSON file
+    of earlier results keyed by GPU architecture and shape class (default: the
+    ROSAR_AUTOTUNE_CACHE environment variable; none when unset); a hit skips the timing."""
     variants = {"all": 0, "direct": L.PLAN_DIRECT, "fastconv": L.PLAN_FASTCONV}[methods]
     _need_gpu(rc.data)
     s = _set(offsets, weights, window)
     dev = rc.data.device
+    cache = cache if cache is not None else os.environ.get("ROSAR_AUTOTUNE_CACHE")
+    key = None
+    if cache:
+        key = autotune_cache_key(torch.cuda.get_device_properties(dev).gcnArchName, geom, grid, rc.dtype,
+                                 rc.l_count, s.k, window, s.w_dtype, interp, methods)
+        hit = autotune_cache_get(cache, key)
+        if hit is not None:
+            return hit
     if out is None:
         out = torch.empty((grid.n_range, grid.n_az), dtype=torch.complex64, device=dev)
     g, p, v = L.geometry(geom), L.polar_grid(grid), rc.view()
@@ -312,9 +361,10 @@ def sparse_plan_autotune(geom, grid, rc: RangeCompressed, offsets, weights, wind
                                                L.INTERP_CODES[interp], _ptr(out), variants, reps, C.byref(best),
                                                C.byref(us),
                                                _stream(dev)), "rosar_sparse_plan_autotune")
-    if best.variant == 3:
-        return "fastconv", float(us.value)
-    return (best.pixels_per_lane, best.waves), float(us.value)
+    res = ("fastconv" if best.variant == 3 else (best.pixels_per_lane, best.waves)), float(us.value)
+    if cache:
+        autotune_cache_put(cache, key, *res)
+    return res
 
 
 def sparse_filter_cartesian(geom, grid, cart, rc: RangeCompressed, offsets, weights, window, interp: str = "nearest",

@@ -440,3 +440,25 @@ def test_cartesian_validation(lib):
                 L.CartGrid(16, 16, 0, 0, 0.1, -1.0)):
         assert call(bad) == L.ROSAR_ERR_INVALID_ARG, (bad.nx, bad.ny, bad.x0_m, bad.dx_m, bad.dy_m)
         assert lib.rosar_last_error().decode() != ""
+
+
+def test_autotune_cache_helpers(tmp_path):
+    """Plan-autotune cache: round trip of tuple and "fastconv" tiles, other keys kept, missing
+    or corrupt files read as empty."""
+    import paper_2309_08038_amd as rs
+    path = str(tmp_path / "tune.json")
+    assert rs.autotune_cache_get(path, "k1") is None
+    rs.autotune_cache_put(path, "k1", (4, 8), 35.5)
+    rs.autotune_cache_put(path, "k2", "fastconv", 57.0)
+    assert rs.autotune_cache_get(path, "k1") == ((4, 8), 35.5)
+    assert rs.autotune_cache_get(path, "k2") == ("fastconv", 57.0)
+    assert rs.autotune_cache_get(path, "k3") is None
+    (tmp_path / "bad.json").write_text("{not json")
+    assert rs.autotune_cache_get(str(tmp_path / "bad.json"), "k1") is None
+    rs.autotune_cache_put(str(tmp_path / "bad.json"), "k1", (2, 4), 1.0)
+    assert rs.autotune_cache_get(str(tmp_path / "bad.json"), "k1") == ((2, 4), 1.0)
+    g, grid = geom(), L.PolarGrid(8, 360, 1.0, 0.05)
+    a = rs.autotune_cache_key("gfx950", g, grid, "c64", 64, 32, 64, L.C64, "nearest", "all")
+    b = rs.autotune_cache_key("gfx950", g, grid, "f16", 64, 32, 64, L.C64, "nearest", "all")
+    assert a != b and a.startswith("gfx950|")
+

@@ -2,6 +2,8 @@
 a plan's run equals rosar_sparse_filter_tiled with the same launch shape bit for bit, for every
 planned shape, both interpolations and all storage types; it follows the oracle; it is reusable
 across rotations and replays correctly from a captured HIP graph."""
+import json
+
 import numpy as np
 import pytest
 
@@ -142,6 +144,25 @@ def test_plan_autotune(dtype):
         single = rs.sparse_filter(w.geometry, w.grid, rc, off, wts, w.sparse.window, tile=(2,) + shape).cpu()
         assert torch.equal(img, single)
     plan.close()
+
+
+def test_plan_autotune_cache(tmp_path):
+    """With a cache file the first autotune stores its result under the GPU's architecture and
+    shape class; an entry found there is returned without timing (an edited entry comes back)."""
+    rs = need_gpu()
+    w, x = inputs("small")
+    rc, off, wts = upload(rs, w, x)
+    path = str(tmp_path / "tune.json")
+    log("plan autotune cache")
+    first = rs.sparse_plan_autotune(w.geometry, w.grid, rc, off, wts, w.sparse.window, reps=2, cache=path)
+    d = json.loads(open(path).read())
+    (key, entry), = d.items()
+    arch = torch.cuda.get_device_properties(0).gcnArchName
+    assert key.startswith(arch + "|plan|") and rs.autotune_cache_get(path, key) == first
+    d[key] = {"tile": [2, 4], "us": 1.25}
+    open(path, "w").write(json.dumps(d))
+    assert rs.sparse_plan_autotune(w.geometry, w.grid, rc, off, wts, w.sparse.window, reps=2, cache=path) == \
+        ((2, 4), 1.25)
 
 
 def test_plan_layout_mismatch_rejected():
