@@ -358,6 +358,27 @@ def bp_full(yb, l_lo, geom, grid, pulse_angles=None, interp="nearest", rows=None
     return out
 
 
+def bp_cartesian_at(yb, l_lo, geom, xs, ys, pulse_angles=None, interp="nearest") -> np.ndarray:
+    """Full-aperture back-projection for targets at Cartesian positions (xs[i], ys[i]) (eq. 43
+    with the BPA weights, as bp_full for a polar pixel): R_t = |(x, y)|, phi_t = atan2(y, x),
+    D = phi_t - phi^_n, visible iff R_t cos D - r > 0 (eqs. 4-5), and
+    I = sum over visible n of alpha_n exp(-j 2 k R_n) Y_1D[n, u(R_n)]."""
+    ang = _angles(geom, pulse_angles)
+    beta = bins_per_metre(geom)
+    k = wavenumber(geom)
+    r = geom.radius_m
+    n_idx = np.arange(geom.n_pulses)
+    out = np.zeros(len(xs), dtype=np.complex128)
+    for i, (x, y) in enumerate(zip(xs, ys)):
+        rt, phi = math.hypot(x, y), math.atan2(y, x)
+        d = phi - ang
+        v = rt * np.cos(d) - r
+        rn = slant_range(rt, r, d)
+        s, _ = sample(yb, l_lo, n_idx, beta * rn, interp)
+        out[i] = np.where(v > 0, v / rn * np.exp(-1j * 2.0 * k * rn) * s, 0.0).sum()
+    return out
+
+
 def bp_full_at(yb, l_lo, geom, grid, rows, azs, pulse_angles=None, interp="nearest") -> np.ndarray:
     """bp_full evaluated pixel by pixel at (rows[i], azs[i])."""
     ang = _angles(geom, pulse_angles)

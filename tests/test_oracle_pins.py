@@ -5,6 +5,7 @@ a closed form derived independently (Cartesian geometry and the physical beat fr
 rather than the law-of-cosines/eq. 40 code paths the oracle uses), a brute-force sum on tiny
 inputs, an invariant, or a library special case.
 """
+import dataclasses
 import json
 import math
 import os
@@ -445,6 +446,28 @@ def _cartesian_steering(geom, rr, phi, offsets, k):
     dist = np.hypot(dx, dy)
     cos_b = (dx * np.cos(th) + dy * np.sin(th)) / dist
     return np.maximum(cos_b, 0.0) * np.exp(1j * 2 * k * dist)
+
+
+@pytest.mark.parametrize("jitter", [False, True])
+def test_bp_cartesian_on_polar_pixels(jitter):
+    """Back-projection for Cartesian targets placed on polar pixels equals the polar BPA there
+    (nominal and jittered pulse angles, both interpolations)."""
+    w = synth.small()
+    if jitter:
+        w = dataclasses.replace(w, scene=dataclasses.replace(w.scene, jitter_sigma_rad=np.deg2rad(0.05)))
+    x = synth.make_inputs(w)
+    g, grid = w.geometry, w.grid
+    yb = oracle.range_compress(x.raw, x.window, g.n_fft)[:, x.l_lo:x.l_lo + x.l_count]
+    ang = x.angles if jitter else None
+    rng = np.random.default_rng(35)
+    rows, azs = rng.integers(0, grid.n_range, 40), rng.integers(0, grid.n_az, 40)
+    r = grid.r0_m + rows * grid.dr_m
+    phi = g.phi0_rad + 2 * np.pi * azs / grid.n_az
+    for interp in ("nearest", "linear"):
+        want = oracle.bp_full_at(yb, x.l_lo, g, grid, rows, azs, pulse_angles=ang, interp=interp)
+        got = oracle.bp_cartesian_at(yb, x.l_lo, g, r * np.cos(phi), r * np.sin(phi), pulse_angles=ang,
+                                     interp=interp)
+        np.testing.assert_allclose(got, want, rtol=1e-9, atol=1e-9 * np.abs(want).max())
 
 
 def test_beampattern_matched_weights_cartesian():
