@@ -364,9 +364,16 @@ def extras(torch, rs, synth, w, x, dev, rc, off, wts, timed, reps):
     cf = lambda: rs.sparse_filter_cartesian(g, grid, cart, rc, off, wts, w.sparse.window, out=cimg)
     cf()
     ms_c = timed(cf, 3, inner=5, out=lambda: cimg)
+    # the comparator on the same lattice: full-aperture back-projection with the true angles
+    cang = torch.from_numpy(x.angles).to(dev)
+    bf = lambda: rs.bp_cartesian(g, cart, rc, angles=cang, out=cimg)
+    bf()
+    ms_cb = timed(bf, 2, out=lambda: cimg)
     out["cartesian"] = {"lattice": [1024, 1024], "extent_m": 2 * r1, "us": 1000 * ms_c,
-                        "pixels_per_s": 1024 * 1024 / (ms_c * 1e-3)}
-    print(f"[bench] Cartesian 1024 x 1024: {1000 * ms_c:.1f} us", file=sys.stderr, flush=True)
+                        "pixels_per_s": 1024 * 1024 / (ms_c * 1e-3), "bpa_us": 1000 * ms_cb,
+                        "sparse_vs_bpa": ms_cb / ms_c}
+    print(f"[bench] Cartesian 1024 x 1024: {1000 * ms_c:.1f} us; BPA {1000 * ms_cb:.0f} us (true angles)",
+          file=sys.stderr, flush=True)
     print("[bench] plan variants: " + ", ".join(f"{k} {v}" for k, v in fc.items()), file=sys.stderr, flush=True)
 
     # batched stream: 64 rotations of uneven size, autotuned shape, replayed from a HIP graph

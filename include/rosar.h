@@ -229,6 +229,20 @@ rosar_status rosar_sparse_filter_cartesian(const rosar_geometry* geom, const ros
                                            const rosar_sparse_set* set, rosar_interp interp, void* image,
                                            rosar_stream stream);
 
+/* Full-aperture back-projection (the comparator, eq. 43 with the BPA weights, eqs. 2-5, 8) for
+ * targets on the Cartesian lattice `cart`: for the target at (x, y), R_t = |(x, y)|,
+ * phi_t = atan2(y, x), D = phi_t - phi_n, and
+ *   I = sum over n with R_t cos D - r > 0 of (v / R_n) exp(-j 2 k R_n) Y(n, u(R_n)),
+ * u = beta R_n (eq. 40; NEAREST or LINEAR as rosar_sparse_filter).  pulse_angle_rad [n_pulses]
+ * float64 (device, 8-byte aligned) or NULL for the nominal phi0 + 2 pi n / N.  rc as
+ * rosar_sparse_filter; image [ny][nx] C64 (8-byte aligned, overwritten).  Float64 geometry per
+ * (pixel, pulse), float32 accumulation.
+ * Errors: INVALID_ARG for pointers, alignment, the view, interp or the lattice (as
+ * rosar_sparse_filter_cartesian). */
+rosar_status rosar_bp_cartesian(const rosar_geometry* geom, const rosar_cart_grid* cart, const rosar_rc_view* rc,
+                                const double* pulse_angle_rad, rosar_interp interp, void* image,
+                                rosar_stream stream);
+
 /* Algorithm 2 on a polar grid whose azimuth-bin count A = grid->n_az need not equal N: pixel
  * (i, a) is the target at R_i and phi_a = phi0 + 2 pi a / A; its central phase centre is
  * n_c = round((phi_a - phi0) / phi_Delta) (floor(x + 1/2)), tap k reads pulse (n_c + o_k) mod N

@@ -92,6 +92,8 @@ PROTOTYPES = [
                                                _P(SparseSet), C.c_int, C.c_void_p, C.c_void_p]),
     ("rosar_bp_time_domain", C.c_int, [_P(Geometry), _P(PolarGrid), C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32,
                                       C.c_int32, C.c_void_p, C.c_void_p]),
+    ("rosar_bp_cartesian", C.c_int, [_P(Geometry), _P(CartGrid), _P(RcView), C.c_void_p, C.c_int, C.c_void_p,
+                                     C.c_void_p]),
     ("rosar_sparse_filter_polar", C.c_int, [_P(Geometry), _P(PolarGrid), _P(RcView), _P(SparseSet), C.c_int,
                                             C.c_void_p, C.c_void_p]),
     ("rosar_beampattern", C.c_int, [_P(Geometry), _P(PolarGrid), _P(SparseSet), C.c_void_p, C.c_int32, C.c_void_p,

@@ -383,6 +383,25 @@ def sparse_filter_cartesian(geom, grid, cart, rc: RangeCompressed, offsets, weig
     return out
 
 
+def bp_cartesian(geom, cart, rc: RangeCompressed, angles: torch.Tensor | None = None, interp: str = "nearest",
+                 out: torch.Tensor | None = None) -> torch.Tensor:
+    """Full-aperture back-projection for targets on the Cartesian lattice `cart` (nx, ny, x0_m,
+    y0_m, dx_m, dy_m), with the given pulse angles (nominal if None); returns [ny, nx] complex64."""
+    _need_gpu(rc.data)
+    if out is None:
+        out = torch.empty((cart.ny, cart.nx), dtype=torch.complex64, device=rc.data.device)
+    g, v = L.geometry(geom), rc.view()
+    c = L.CartGrid(int(cart.nx), int(cart.ny), float(cart.x0_m), float(cart.y0_m), float(cart.dx_m), float(cart.dy_m))
+    if angles is not None:
+        angles = angles.contiguous()
+        if angles.dtype != torch.float64 or angles.numel() != geom.n_pulses:
+            raise ValueError("angles must be float64 [n_pulses]")
+    L.check(L.lib().rosar_bp_cartesian(C.byref(g), C.byref(c), C.byref(v), None if angles is None else _ptr(angles),
+                                       L.INTERP_CODES[interp], _ptr(out), _stream(rc.data.device)),
+            "rosar_bp_cartesian")
+    return out
+
+
 def sparse_filter_polar(geom, grid, rc: RangeCompressed, offsets, weights, window, interp: str = "nearest",
                         out: torch.Tensor | None = None) -> torch.Tensor:
     """Algorithm 2 on a polar grid of grid.n_az azimuth bins, which may differ from the pulse

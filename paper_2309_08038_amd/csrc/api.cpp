@@ -353,22 +353,45 @@ rosar_status rosar_sparse_filter_backward_workspace_size(const rosar_geometry* g
   return ok();
 }
 
-rosar_status rosar_sparse_filter_cartesian(const rosar_geometry* geom, const rosar_polar_grid* grid,
-                                           const rosar_cart_grid* cart, const rosar_rc_view* rc,
-                                           const rosar_sparse_set* set, rosar_interp interp, void* image,
-                                           rosar_stream stream) {
-  rosar::SparseArgs a{};
-  ROSAR_TRY(sparse_common(geom, grid, rc, set, nullptr, nullptr, interp, image, &a));
+static rosar_status check_cart(const rosar_cart_grid* cart) {
   if (!cart) return fail(ROSAR_ERR_INVALID_ARG, "cart is NULL");
   if (cart->nx < 1 || cart->ny < 1 || cart->ny > 65535 || cart->nx > (1 << 24))
     return fail(ROSAR_ERR_INVALID_ARG, "cart lattice %d x %d outside [1, 2^24] x [1, 65535]", cart->nx, cart->ny);
   if (!std::isfinite(cart->x0_m) || !std::isfinite(cart->y0_m) || !(cart->dx_m > 0.0) || !(cart->dy_m > 0.0) ||
       !std::isfinite(cart->dx_m) || !std::isfinite(cart->dy_m))
     return fail(ROSAR_ERR_INVALID_ARG, "cart origin must be finite and its spacings positive");
+  return ROSAR_OK;
+}
+
+rosar_status rosar_sparse_filter_cartesian(const rosar_geometry* geom, const rosar_polar_grid* grid,
+                                           const rosar_cart_grid* cart, const rosar_rc_view* rc,
+                                           const rosar_sparse_set* set, rosar_interp interp, void* image,
+                                           rosar_stream stream) {
+  rosar::SparseArgs a{};
+  ROSAR_TRY(sparse_common(geom, grid, rc, set, nullptr, nullptr, interp, image, &a));
+  ROSAR_TRY(check_cart(cart));
   if (inject_launch_fault()) return fail(ROSAR_ERR_HIP, "injected launch failure (ROSAR_FAULT_INJECT)");
   const rosar::CartGrid c{cart->nx, cart->ny, cart->x0_m, cart->y0_m, cart->dx_m, cart->dy_m};
   return from_hip(rosar::launch_sparse_cartesian(a, c, reinterpret_cast<hipStream_t>(stream)),
                   "Cartesian sparse filter launch");
+}
+
+rosar_status rosar_bp_cartesian(const rosar_geometry* geom, const rosar_cart_grid* cart, const rosar_rc_view* rc,
+                                const double* pulse_angle_rad, rosar_interp interp, void* image,
+                                rosar_stream stream) {
+  ROSAR_TRY(check_geometry(geom));
+  ROSAR_TRY(check_view(geom, rc));
+  if (interp != ROSAR_NEAREST && interp != ROSAR_LINEAR)
+    return fail(ROSAR_ERR_INVALID_ARG, "interp must be ROSAR_NEAREST or ROSAR_LINEAR");
+  ROSAR_TRY(check_cart(cart));
+  if (pulse_angle_rad && !aligned(pulse_angle_rad, 8))
+    return fail(ROSAR_ERR_INVALID_ARG, "pulse_angle_rad misaligned");
+  ROSAR_TRY(check_image(image, "image"));
+  if (inject_launch_fault()) return fail(ROSAR_ERR_HIP, "injected launch failure (ROSAR_FAULT_INJECT)");
+  const rosar::CartGrid c{cart->nx, cart->ny, cart->x0_m, cart->y0_m, cart->dx_m, cart->dy_m};
+  return from_hip(rosar::launch_bp_cartesian(make_geo(geom, nullptr), make_view(rc), c, pulse_angle_rad, interp,
+                                             static_cast<float2*>(image), reinterpret_cast<hipStream_t>(stream)),
+                  "Cartesian back-projection launch");
 }
 
 rosar_status rosar_sparse_filter_polar(const rosar_geometry* geom, const rosar_polar_grid* grid,

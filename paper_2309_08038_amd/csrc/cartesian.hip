@@ -80,6 +80,89 @@ __global__ __launch_bounds__(kCartThreads) void sparse_cartesian_kernel(Geo g, V
   image[(size_t)iy * c.nx + ix] = make_float2(acc.x * y.inv_scale, acc.y * y.inv_scale);
 }
 
+// Full-aperture back-projection for the same Cartesian targets (eq. 43 with the BPA weights,
+// eqs. 2-5, 8): I = sum over visible n of alpha_n exp(-j 2 k R_n) Y(n, u(R_n)), D = phi_t - phi_n,
+// visible iff R_t cos D - r > 0.  A thread owns a pixel.  With nominal pulse angles it walks
+// only the pulses within acos(r / R_t) of the target's direction (the others are invisible);
+// with given angles it walks all N.  Geometry in float64, the carrier phase reduced in
+// revolutions, float32 accumulation.
+template <int DT, int INTERP>
+__global__ __launch_bounds__(kCartThreads) void bp_cartesian_kernel(Geo g, View y, CartGrid c,
+                                                                    const double* __restrict__ angles,
+                                                                    float2* __restrict__ image) {
+  const int ix = blockIdx.x * kCartThreads + threadIdx.x;
+  const int iy = blockIdx.y;
+  if (ix >= c.nx) return;   // no barrier in this kernel
+  const double x = c.x0 + ix * c.dx, yy = c.y0 + iy * c.dy;
+  const double rt = sqrt(x * x + yy * yy);
+  const double phi = atan2(yy, x);
+  const double c1 = rt * rt + g.radius * g.radius;
+  const double c2 = 2.0 * rt * g.radius;
+  const char* yd = static_cast<const char*>(y.data);
+  float2 acc = make_float2(0.f, 0.f);
+  // target angle from pulse 0, reduced to [0, 2 pi): the span indices stay within about
+  // [-N/4, 5N/4] for any phi0
+  const double two_pi = 6.283185307179586476925286766559;
+  double rel = phi - g.phi0;
+  rel -= two_pi * floor(rel / two_pi);
+  int m0 = 0, m1 = g.n - 1;   // pulse indices m: pulse m mod N, nominally at phi0 + m phi_Delta
+  if (!angles) {
+    if (rt <= g.radius) m1 = -1;   // R cos D - r <= R - r <= 0: nothing visible
+    else {
+      const double half = acos(g.radius / rt);   // < pi / 2
+      m0 = (int)floor((rel - half) / g.step);
+      m1 = (int)ceil((rel + half) / g.step);
+    }
+  }
+  for (int m = m0; m <= m1; ++m) {
+    int n = m % g.n;
+    n += n < 0 ? g.n : 0;
+    const double cd = angles ? cos(phi - angles[n]) : cos(rel - m * g.step);
+    const double v = rt * cd - g.radius;
+    if (v <= 0.0) continue;   // outside the field of view (eqs. 4-5)
+    const double rn = sqrt(c1 - c2 * cd);
+    const double u = g.beta * rn;
+    float2 s = make_float2(0.f, 0.f);
+    if constexpr (INTERP == ROSAR_NEAREST) {
+      const int l = (int)floor(u + 0.5) - y.l_lo;
+      if (l >= 0 && l < y.l_count) s = load_c<DT>(yd, (int64_t)l * y.ld + y.halo + n);
+    } else {
+      const double fl = floor(u);
+      const float f = (float)(u - fl);
+      const int l = (int)fl - y.l_lo;
+      if (l >= 0 && l < y.l_count) {
+        const float2 a = load_c<DT>(yd, (int64_t)l * y.ld + y.halo + n);
+        s.x += (1.f - f) * a.x;
+        s.y += (1.f - f) * a.y;
+      }
+      if (l + 1 >= 0 && l + 1 < y.l_count) {
+        const float2 a = load_c<DT>(yd, (int64_t)(l + 1) * y.ld + y.halo + n);
+        s.x += f * a.x;
+        s.y += f * a.y;
+      }
+    }
+    const double rev = rn * g.k_over_pi;   // exp(-j 2 k R_n) in revolutions
+    float ss, cs;
+    sincospif(-2.0f * (float)(rev - rint(rev)), &ss, &cs);
+    const float al = (float)(v / rn);
+    const float ex = al * cs, ey = al * ss;
+    acc.x += ex * s.x - ey * s.y;
+    acc.y += ex * s.y + ey * s.x;
+  }
+  image[(size_t)iy * c.nx + ix] = make_float2(acc.x * y.inv_scale, acc.y * y.inv_scale);
+}
+
+template <int DT>
+hipError_t launch_bp_dt(const Geo& g, const View& y, const CartGrid& c, const double* angles, int32_t interp,
+                        float2* image, hipStream_t s) {
+  dim3 grid((c.nx + kCartThreads - 1) / kCartThreads, c.ny);
+  if (interp == ROSAR_LINEAR)
+    bp_cartesian_kernel<DT, ROSAR_LINEAR><<<grid, kCartThreads, 0, s>>>(g, y, c, angles, image);
+  else
+    bp_cartesian_kernel<DT, ROSAR_NEAREST><<<grid, kCartThreads, 0, s>>>(g, y, c, angles, image);
+  return hipGetLastError();
+}
+
 template <int DT, int WDT, bool POLAR>
 hipError_t launch_wdt(const SparseArgs& a, const CartGrid& c, hipStream_t s) {
   dim3 grid((c.nx + kCartThreads - 1) / kCartThreads, c.ny);
@@ -110,6 +193,15 @@ hipError_t launch_any(const SparseArgs& a, const CartGrid& c, hipStream_t s) {
 
 hipError_t launch_sparse_cartesian(const SparseArgs& a, const CartGrid& c, hipStream_t s) {
   return launch_any<false>(a, c, s);
+}
+
+hipError_t launch_bp_cartesian(const Geo& g, const View& y, const CartGrid& c, const double* angles, int32_t interp,
+                               float2* image, hipStream_t s) {
+  switch (y.dtype) {
+    case ROSAR_C64: return launch_bp_dt<0>(g, y, c, angles, interp, image, s);
+    case ROSAR_C16_F16: return launch_bp_dt<1>(g, y, c, angles, interp, image, s);
+    default: return launch_bp_dt<2>(g, y, c, angles, interp, image, s);
+  }
 }
 
 hipError_t launch_sparse_polar(const SparseArgs& a, int32_t n_az, hipStream_t s) {

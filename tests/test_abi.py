@@ -423,6 +423,25 @@ def test_polar_validation(lib):
     assert lib.rosar_last_error().decode() != ""
 
 
+def test_bp_cartesian_validation(lib):
+    g = geom()
+    view = L.RcView(0x20000, L.C64, 0, 64, 32, 424, 1.0, 0)
+    good = L.CartGrid(16, 16, -1.0, -1.0, 0.1, 0.1)
+
+    def call(cart=good, angles=None, interp=L.NEAREST, image=FAKE, v=None):
+        return lib.rosar_bp_cartesian(C.byref(g), C.byref(cart) if cart else None, C.byref(v or view), angles,
+                                      interp, image, None)
+
+    assert call(cart=None) == L.ROSAR_ERR_INVALID_ARG
+    assert call(cart=L.CartGrid(16, 0, 0, 0, 0.1, 0.1)) == L.ROSAR_ERR_INVALID_ARG
+    assert call(cart=L.CartGrid(16, 16, 0, 0, float("inf"), 0.1)) == L.ROSAR_ERR_INVALID_ARG
+    assert call(angles=C.c_void_p(0x10004)) == L.ROSAR_ERR_INVALID_ARG
+    assert call(interp=7) == L.ROSAR_ERR_INVALID_ARG
+    assert call(image=None) == L.ROSAR_ERR_INVALID_ARG
+    assert call(v=L.RcView(0x20000, L.C64, 0, 64, 32, 100, 1.0, 0)) == L.ROSAR_ERR_INVALID_ARG   # ld too small
+    assert lib.rosar_last_error().decode() != ""
+
+
 def test_cartesian_validation(lib):
     g, grid = geom(), L.PolarGrid(8, 360, 1.0, 0.05)
     view = L.RcView(0x20000, L.C64, 0, 64, 32, 424, 1.0, 0)
