@@ -82,17 +82,33 @@ __global__ __launch_bounds__(kCartThreads) void sparse_cartesian_kernel(Geo g, V
 
 // Full-aperture back-projection for the same Cartesian targets (eq. 43 with the BPA weights,
 // eqs. 2-5, 8): I = sum over visible n of alpha_n exp(-j 2 k R_n) Y(n, u(R_n)), D = phi_t - phi_n,
-// visible iff R_t cos D - r > 0.  A thread owns a pixel.  With nominal pulse angles it walks
-// only the pulses within acos(r / R_t) of the target's direction (the others are invisible);
-// with given angles it walks all N.  Geometry in float64, the carrier phase reduced in
-// revolutions, float32 accumulation.
+// visible iff R_t cos D - r > 0.  A thread owns a pixel and walks only the pulses whose nominal
+// angle lies within acos(r / R_t) + max |delta| of the target's direction (delta: given angle
+// minus nominal, its maximum reduced by each workgroup); the others cannot be visible.
+// Geometry in float64, the carrier phase reduced in revolutions, float32 accumulation.
 template <int DT, int INTERP>
 __global__ __launch_bounds__(kCartThreads) void bp_cartesian_kernel(Geo g, View y, CartGrid c,
                                                                     const double* __restrict__ angles,
                                                                     float2* __restrict__ image) {
+  __shared__ double s_dmax[kCartThreads / kWave];
+  const double two_pi = 6.283185307179586476925286766559;
+  // largest deviation of the given pulse angles from the nominal ones (every thread takes part
+  // before any leaves)
+  double dmax = 0.0;
+  if (angles) {
+    for (int n = threadIdx.x; n < g.n; n += kCartThreads) {
+      double d = angles[n] - (g.phi0 + n * g.step);
+      d -= two_pi * rint(d / two_pi);
+      dmax = fmax(dmax, fabs(d));
+    }
+    for (int off = kWave / 2; off > 0; off >>= 1) dmax = fmax(dmax, __shfl_xor(dmax, off));
+    if ((threadIdx.x & (kWave - 1)) == 0) s_dmax[threadIdx.x / kWave] = dmax;
+    __syncthreads();
+    for (int i = 0; i < kCartThreads / kWave; ++i) dmax = fmax(dmax, s_dmax[i]);
+  }
   const int ix = blockIdx.x * kCartThreads + threadIdx.x;
   const int iy = blockIdx.y;
-  if (ix >= c.nx) return;   // no barrier in this kernel
+  if (ix >= c.nx) return;   // no barrier below
   const double x = c.x0 + ix * c.dx, yy = c.y0 + iy * c.dy;
   const double rt = sqrt(x * x + yy * yy);
   const double phi = atan2(yy, x);
@@ -101,15 +117,15 @@ __global__ __launch_bounds__(kCartThreads) void bp_cartesian_kernel(Geo g, View 
   const char* yd = static_cast<const char*>(y.data);
   float2 acc = make_float2(0.f, 0.f);
   // target angle from pulse 0, reduced to [0, 2 pi): the span indices stay within about
-  // [-N/4, 5N/4] for any phi0
-  const double two_pi = 6.283185307179586476925286766559;
+  // [-N/2, 3N/2] for any phi0
   double rel = phi - g.phi0;
   rel -= two_pi * floor(rel / two_pi);
   int m0 = 0, m1 = g.n - 1;   // pulse indices m: pulse m mod N, nominally at phi0 + m phi_Delta
-  if (!angles) {
-    if (rt <= g.radius) m1 = -1;   // R cos D - r <= R - r <= 0: nothing visible
-    else {
-      const double half = acos(g.radius / rt);   // < pi / 2
+  if (rt <= g.radius) {
+    m1 = -1;   // R cos D - r <= R - r <= 0: nothing visible
+  } else {
+    const double half = acos(g.radius / rt) + dmax;   // acos < pi / 2
+    if (half < 0.5 * two_pi - g.step) {
       m0 = (int)floor((rel - half) / g.step);
       m1 = (int)ceil((rel + half) / g.step);
     }
