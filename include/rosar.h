@@ -423,7 +423,8 @@ typedef struct rosar_sparse_plan rosar_sparse_plan;
  * LDS-staged kernel cannot take (halo < W/2, rows not 16-byte aligned, one staged row over the
  * LDS budget), or for variant 3 an N with another prime factor, N > 8192 or more than 32 bin
  * rows per range row; NO_MEMORY if the table allocation ((K or 2K) x 24 bytes + 16 per row, rounded
- * to 16) fails. */
+ * to 16) fails; INVALID_ARG, before any allocation, when `stream` is capturing a graph (the
+ * capture stays valid). */
 rosar_status rosar_sparse_plan_create(const rosar_geometry* geom, const rosar_polar_grid* grid,
                                       const rosar_rc_view* rc, const rosar_sparse_set* set,
                                       rosar_interp interp, const rosar_tile* tile, rosar_stream stream,
@@ -444,7 +445,8 @@ void rosar_sparse_plan_destroy(rosar_sparse_plan* plan);
  * candidates to a mask of ROSAR_PLAN_DIRECT (the LDS-staged shapes) and ROSAR_PLAN_FASTCONV
  * (0 = both).  Synchronises `stream`.
  * Errors: as rosar_sparse_plan_create (UNSUPPORTED if no candidate admits the layout);
- * INVALID_ARG for NULL best/best_us, reps outside [1, 10000] or unknown variant bits. */
+ * INVALID_ARG for NULL best/best_us, reps outside [1, 10000] or unknown variant bits, or when
+ * `stream` is capturing a graph. */
 enum { ROSAR_PLAN_DIRECT = 1, ROSAR_PLAN_FASTCONV = 2 };
 rosar_status rosar_sparse_plan_autotune(const rosar_geometry* geom, const rosar_polar_grid* grid,
                                         const rosar_rc_view* rc, const rosar_sparse_set* set,
@@ -454,7 +456,7 @@ rosar_status rosar_sparse_plan_autotune(const rosar_geometry* geom, const rosar_
 /* ---------------------------------------------------------------- autotuning
  * Times every supported launch shape of rosar_sparse_filter on the given inputs (the image is
  * overwritten), `reps` timed launches each, and returns the fastest in *best with its mean
- * time in microseconds.  Synchronises `stream`. */
+ * time in microseconds.  Synchronises `stream`; refuses a capturing stream (INVALID_ARG). */
 rosar_status rosar_autotune_sparse_filter(const rosar_geometry* geom, const rosar_polar_grid* grid,
                                           const rosar_rc_view* rc, const rosar_sparse_set* set,
                                           void* image, int32_t reps, rosar_tile* best,

@@ -353,6 +353,17 @@ rosar_status rosar_sparse_filter_backward_workspace_size(const rosar_geometry* g
   return ok();
 }
 
+// Entry points that allocate, synchronise or time refuse a capturing stream before any of that:
+// the capture stays valid and the caller gets an error instead of a broken graph.
+static rosar_status check_not_capturing(rosar_stream stream, const char* what) {
+  hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(reinterpret_cast<hipStream_t>(stream), &st) != hipSuccess)
+    return fail(ROSAR_ERR_HIP, "%s: cannot query the stream's capture status", what);
+  if (st != hipStreamCaptureStatusNone)
+    return fail(ROSAR_ERR_INVALID_ARG, "%s allocates and synchronises: it cannot run under stream capture", what);
+  return ROSAR_OK;
+}
+
 static rosar_status check_cart(const rosar_cart_grid* cart) {
   if (!cart) return fail(ROSAR_ERR_INVALID_ARG, "cart is NULL");
   if (cart->nx < 1 || cart->ny < 1 || cart->ny > 65535 || cart->nx > (1 << 24))
@@ -666,6 +677,7 @@ rosar_status rosar_sparse_plan_create(const rosar_geometry* geom, const rosar_po
     if (!rosar::fc_layout(a, &fc))
       return fail(ROSAR_ERR_UNSUPPORTED,
                   "the azimuth fast convolution needs N = 2^a 3^b 5^c <= 8192 and at most 32 bin rows per range row");
+    ROSAR_TRY(check_not_capturing(stream, "rosar_sparse_plan_create"));
     int dev = -1;
     if (hipGetDevice(&dev) != hipSuccess) return fail(ROSAR_ERR_HIP, "cannot query the current device");
     auto* p = new (std::nothrow) rosar_sparse_plan();
@@ -705,6 +717,7 @@ rosar_status rosar_sparse_plan_create(const rosar_geometry* geom, const rosar_po
     return fail(ROSAR_ERR_UNSUPPORTED,
                 "this band layout cannot use the LDS-staged kernel (halo < W/2, rows not 16-byte aligned, or a "
                 "staged row over the LDS budget)");
+  ROSAR_TRY(check_not_capturing(stream, "rosar_sparse_plan_create"));
   int dev = -1;
   if (hipGetDevice(&dev) != hipSuccess) return fail(ROSAR_ERR_HIP, "cannot query the current device");
   auto* p = new (std::nothrow) rosar_sparse_plan();
@@ -795,6 +808,7 @@ rosar_status rosar_sparse_plan_autotune(const rosar_geometry* geom, const rosar_
   if (!any && !fc_ok)
     return fail(ROSAR_ERR_UNSUPPORTED, "no plan variant admits this layout (direct: halo >= W/2, 16-byte aligned rows, "
                                        "a staged row within the LDS budget; fast convolution: N = 2^a 3^b 5^c <= 8192)");
+  ROSAR_TRY(check_not_capturing(stream, "rosar_sparse_plan_autotune"));
   if (inject_launch_fault()) return fail(ROSAR_ERR_HIP, "injected launch failure (ROSAR_FAULT_INJECT)");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   char* tabs = nullptr;   // row blocks do not depend on the shape: one buffer serves every shape
@@ -867,6 +881,7 @@ rosar_status rosar_autotune_sparse_filter(const rosar_geometry* geom, const rosa
   ROSAR_TRY(sparse_common(geom, grid, rc, set, nullptr, nullptr, ROSAR_NEAREST, image, &a));
   if (!best || !best_us) return fail(ROSAR_ERR_INVALID_ARG, "best / best_us is NULL");
   if (reps < 1 || reps > 10000) return fail(ROSAR_ERR_INVALID_ARG, "reps must be in [1, 10000]");
+  ROSAR_TRY(check_not_capturing(stream, "rosar_autotune_sparse_filter"));
   if (inject_launch_fault()) return fail(ROSAR_ERR_HIP, "injected launch failure (ROSAR_FAULT_INJECT)");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   hipEvent_t e0, e1;

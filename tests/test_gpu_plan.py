@@ -350,3 +350,33 @@ def test_plan_runs_deterministic(variant):
         torch.cuda.synchronize()
         assert torch.equal(img, ref), ("replay", rep)
     plan.close()
+
+
+def test_plan_create_refused_under_capture():
+    """Plan creation and the plan autotuner allocate and synchronise: on a capturing stream they
+    return an error before touching the capture, which stays valid; a capturable call in the
+    same capture replays to the eager result."""
+    rs = need_gpu()
+    w, x = inputs("small")
+    rc, off, wts = upload(rs, w, x)
+    eager = rs.sparse_filter(w.geometry, w.grid, rc, off, wts, w.sparse.window)
+    torch.cuda.synchronize()
+    img = torch.empty_like(eager)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    graph = torch.cuda.CUDAGraph()
+    log("plan create under capture")
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(graph, stream=s):
+            with pytest.raises(rs.RosarError, match="capture"):
+                rs.SparsePlan(w.geometry, w.grid, rc, off, wts, w.sparse.window)
+            with pytest.raises(rs.RosarError, match="capture"):
+                rs.sparse_plan_autotune(w.geometry, w.grid, rc, off, wts, w.sparse.window, reps=1)
+            rs.sparse_filter(w.geometry, w.grid, rc, off, wts, w.sparse.window, out=img)
+    torch.cuda.current_stream().wait_stream(s)
+    for _ in range(2):
+        img.zero_()
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(img, eager)
