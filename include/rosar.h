@@ -375,7 +375,9 @@ typedef struct rosar_batch_plan rosar_batch_plan;
  * 8x2, 4x8}; NULL = 4x8).  Every descriptor obeys the rules of rosar_range_compress and
  * rosar_sparse_filter (C64 data and weights); the halo should cover half the window (staging
  * falls back to element copies otherwise).  y_t is written by the run (range compression) and
- * read by its sparse filter; images are overwritten.  Errors name the offending rotation. */
+ * read by its sparse filter; images are overwritten.  Errors name the offending rotation.
+ * It allocates and copies synchronously and takes no stream: do not call it while a graph is
+ * being captured. */
 rosar_status rosar_batch_plan_create(const rosar_rotation_desc* descs, int32_t n,
                                      const rosar_tile* tile, rosar_batch_plan** out);
 /* Enqueues counter reset + range compression (one launch per FFT length) + the persistent
@@ -387,7 +389,8 @@ rosar_status rosar_batch_plan_info(const rosar_batch_plan* plan, int64_t* pixels
 void rosar_batch_plan_destroy(rosar_batch_plan* plan);
 /* Project autotuner for batches: builds a plan for every supported sparse-filter launch shape,
  * times `reps` runs of each on `stream` (outputs are overwritten) and returns the fastest
- * shape in *best with its mean run time in microseconds.  Synchronises `stream`. */
+ * shape in *best with its mean run time in microseconds.  Synchronises `stream`; refuses a
+ * capturing stream (INVALID_ARG, the capture stays valid). */
 rosar_status rosar_batch_autotune(const rosar_rotation_desc* descs, int32_t n, int32_t reps,
                                   rosar_tile* best, float* best_us, rosar_stream stream);
 

@@ -374,6 +374,13 @@ rosar_status rosar_batch_autotune(const rosar_rotation_desc* descs, int32_t n, i
   if (!best || !best_us) return bfail(ROSAR_ERR_INVALID_ARG, "best / best_us is NULL");
   if (reps < 1 || reps > 1000) return bfail(ROSAR_ERR_INVALID_ARG, "reps must be in [1, 1000]");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  // it allocates, synchronises and times: refused on a capturing stream, which stays valid
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s, &cap) != hipSuccess)
+    return bfail(ROSAR_ERR_HIP, "rosar_batch_autotune: cannot query the stream's capture status");
+  if (cap != hipStreamCaptureStatusNone)
+    return bfail(ROSAR_ERR_INVALID_ARG, "rosar_batch_autotune allocates and synchronises: it cannot run under "
+                                        "stream capture");
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess) return bfail(ROSAR_ERR_HIP, "hipEventCreate failed");
   if (hipEventCreate(&e1) != hipSuccess) {

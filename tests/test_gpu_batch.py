@@ -115,3 +115,32 @@ def test_batch_full_stream_autotuned():
         if i % 16 == 0:
             assert oracle_sampled(w, x, r.image.cpu().numpy(), n=20, seed=i) <= 1e-4, w.name
     plan.close()
+
+
+def test_batch_autotune_refused_under_capture():
+    """The batch autotuner allocates, synchronises and times: on a capturing stream it returns an
+    error before touching the capture, which then ends normally and replays a batch run."""
+    rs = need_gpu()
+    ws = synth.scaled_batch(3, seed=7)
+    xs = [synth.make_inputs(w) for w in ws]
+    rots = rotations(rs, ws, xs)
+    plan = rs.BatchPlan(rots, tile=(4, 4))
+    plan.run()
+    torch.cuda.synchronize()
+    ref = [r.image.clone() for r in rots]
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    graph = torch.cuda.CUDAGraph()
+    log("batch autotune under capture")
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(graph, stream=s):
+            with pytest.raises(rs.RosarError, match="capture"):
+                rs.batch_autotune(rots, reps=1)
+            plan.run()
+    torch.cuda.current_stream().wait_stream(s)
+    for r in rots:
+        r.image.zero_()
+    torch.cuda.synchronize()
+    graph.replay()
+    torch.cuda.synchronize()
+    assert all(torch.equal(r.image, e) for r, e in zip(rots, ref))

@@ -197,3 +197,19 @@ def test_bp_cartesian_axis_matches_polar_bpa():
     cart = rs.bp_cartesian(g, c, rc).cpu().numpy()[0]
     polar = rs.bp_full(g, grid, rc).cpu().numpy()[:, 0]
     assert rel_l2(cart, polar) <= 1e-5
+
+
+@pytest.mark.parametrize("dtype,scale", [("f16", 2.0 ** -4), ("bf16", 1.0)])
+def test_bp_cartesian_reduced_precision(dtype, scale):
+    """Back-projection on the lattice from FP16 / BF16 storage (float32 accumulation)."""
+    rs = need_gpu()
+    w, x = inputs("small")
+    g, grid = w.geometry, w.grid
+    r1 = grid.r0_m + (grid.n_range - 1) * grid.dr_m
+    c, xs, ys = lattice(64, 64, -r1 - 0.00917, -r1 + 0.00431, 2 * r1 / 63, 2 * r1 / 63)
+    rc = rs.range_compress(g, to_dev(x.raw), to_dev(x.window), x.l_lo, x.l_count, halo=w.sparse.window // 2,
+                           dtype=dtype, scale=scale)
+    log(f"bp cartesian {dtype}")
+    img = rs.bp_cartesian(g, c, rc).cpu().numpy()
+    ref = oracle.bp_cartesian_at(oracle_band("small"), x.l_lo, g, xs, ys).reshape(64, 64)
+    assert rel_l2(img, ref) <= 1e-2
