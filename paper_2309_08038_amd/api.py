@@ -26,6 +26,19 @@ def _ptr(t) -> C.c_void_p | None:
     return None if t is None else C.c_void_p(t.data_ptr())
 
 
+def _out(t, shape, dtype, device):
+    """The caller's output buffer, checked against what the kernel writes (device, dtype, shape,
+    contiguity), or a new one."""
+    shape = tuple(shape) if isinstance(shape, (tuple, list)) else (shape,)
+    if t is None:
+        return torch.empty(shape, dtype=dtype, device=device)
+    if (t.device != torch.device(device) or t.dtype != dtype or tuple(t.shape) != shape
+            or not t.is_contiguous()):
+        raise ValueError(f"output buffer must be a contiguous {dtype} tensor of shape {shape} on {device} "
+                         f"(got {t.dtype} {tuple(t.shape)} on {t.device}, contiguous={t.is_contiguous()})")
+    return t
+
+
 def _need_gpu(*tensors):
     for t in tensors:
         if t is not None and not t.is_cuda:
@@ -111,8 +124,7 @@ def sparse_filter(geom, grid, rc: RangeCompressed, offsets: torch.Tensor, weight
     """Sparse-aperture azimuth filter (Algorithm 2 / eq. 43) -> complex64 image [n_range, n_az]."""
     s = _set(offsets, weights, window)
     _need_gpu(dphi, dpsi, rc.data)
-    if out is None:
-        out = torch.empty((grid.n_range, grid.n_az), dtype=torch.complex64, device=rc.data.device)
+    out = _out(out, (grid.n_range, grid.n_az), torch.complex64, rc.data.device)
     g, p, v = L.geometry(geom), L.polar_grid(grid), rc.view()
     t = None if tile is None else L.Tile(tile[0], tile[1], tile[2], 0)
     L.check(L.lib().rosar_sparse_filter_tiled(C.byref(g), C.byref(p), C.byref(v), C.byref(s), _ptr(dphi), _ptr(dpsi),
@@ -135,11 +147,11 @@ def bp_full(geom, grid, rc: RangeCompressed, angles: torch.Tensor | None = None,
     if angles is not None and angles.dtype != torch.float64:
         raise TypeError("angles must be float64 [N]")
     dev = rc.data.device
-    if out is None:
-        out = torch.empty((grid.n_range, grid.n_az), dtype=torch.complex64, device=dev)
+    out = _out(out, (grid.n_range, grid.n_az), torch.complex64, dev)
     nbytes = bp_workspace_bytes(geom)
     if workspace is None:
         workspace = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    _need_gpu(workspace)   # its size is checked by the library
     g, p, v = L.geometry(geom), L.polar_grid(grid), rc.view()
     L.check(L.lib().rosar_bp_full(C.byref(g), C.byref(p), C.byref(v), _ptr(angles), L.INTERP_CODES[interp],
                                   _ptr(out), _ptr(workspace), workspace.numel() * workspace.element_size(),
@@ -255,8 +267,7 @@ def autotune_sparse_filter(geom, grid, rc: RangeCompressed, offsets, weights, wi
     """Time every launch shape of the plain sparse filter; returns ((variant, ppl, waves), microseconds)."""
     s = _set(offsets, weights, window)
     dev = rc.data.device
-    if out is None:
-        out = torch.empty((grid.n_range, grid.n_az), dtype=torch.complex64, device=dev)
+    out = _out(out, (grid.n_range, grid.n_az), torch.complex64, dev)
     g, p, v = L.geometry(geom), L.polar_grid(grid), rc.view()
     best = L.Tile()
     us = C.c_float(0)
@@ -352,8 +363,7 @@ def sparse_plan_autotune(geom, grid, rc: RangeCompressed, offsets, weights, wind
         hit = autotune_cache_get(cache, key)
         if hit is not None:
             return hit
-    if out is None:
-        out = torch.empty((grid.n_range, grid.n_az), dtype=torch.complex64, device=dev)
+    out = _out(out, (grid.n_range, grid.n_az), torch.complex64, dev)
     g, p, v = L.geometry(geom), L.polar_grid(grid), rc.view()
     best = L.Tile()
     us = C.c_float(0)
@@ -373,8 +383,7 @@ def sparse_filter_cartesian(geom, grid, cart, rc: RangeCompressed, offsets, weig
     with the weights of the polar grid rows; returns [ny, nx] complex64."""
     _need_gpu(rc.data)
     s = _set(offsets, weights, window)
-    if out is None:
-        out = torch.empty((cart.ny, cart.nx), dtype=torch.complex64, device=rc.data.device)
+    out = _out(out, (cart.ny, cart.nx), torch.complex64, rc.data.device)
     g, p, v = L.geometry(geom), L.polar_grid(grid), rc.view()
     c = L.CartGrid(int(cart.nx), int(cart.ny), float(cart.x0_m), float(cart.y0_m), float(cart.dx_m), float(cart.dy_m))
     L.check(L.lib().rosar_sparse_filter_cartesian(C.byref(g), C.byref(p), C.byref(c), C.byref(v), C.byref(s),
@@ -388,8 +397,7 @@ def bp_cartesian(geom, cart, rc: RangeCompressed, angles: torch.Tensor | None = 
     """Full-aperture back-projection for targets on the Cartesian lattice `cart` (nx, ny, x0_m,
     y0_m, dx_m, dy_m), with the given pulse angles (nominal if None); returns [ny, nx] complex64."""
     _need_gpu(rc.data)
-    if out is None:
-        out = torch.empty((cart.ny, cart.nx), dtype=torch.complex64, device=rc.data.device)
+    out = _out(out, (cart.ny, cart.nx), torch.complex64, rc.data.device)
     g, v = L.geometry(geom), rc.view()
     c = L.CartGrid(int(cart.nx), int(cart.ny), float(cart.x0_m), float(cart.y0_m), float(cart.dx_m), float(cart.dy_m))
     if angles is not None:
@@ -408,8 +416,7 @@ def sparse_filter_polar(geom, grid, rc: RangeCompressed, offsets, weights, windo
     count (per-pixel central phase centre); returns [n_range, n_az] complex64."""
     _need_gpu(rc.data)
     s = _set(offsets, weights, window)
-    if out is None:
-        out = torch.empty((grid.n_range, grid.n_az), dtype=torch.complex64, device=rc.data.device)
+    out = _out(out, (grid.n_range, grid.n_az), torch.complex64, rc.data.device)
     g, p, v = L.geometry(geom), L.polar_grid(grid), rc.view()
     L.check(L.lib().rosar_sparse_filter_polar(C.byref(g), C.byref(p), C.byref(v), C.byref(s), L.INTERP_CODES[interp],
                                               _ptr(out), _stream(rc.data.device)), "rosar_sparse_filter_polar")
@@ -422,8 +429,7 @@ def bp_time_domain(geom, grid, raw: torch.Tensor, window: torch.Tensor | None = 
     pulse) for grid rows [first, first + count) (all rows if None); returns [count, n_az]."""
     _need_gpu(raw)
     first, count = (0, grid.n_range) if rows is None else rows
-    if out is None:
-        out = torch.empty((count, grid.n_az), dtype=torch.complex64, device=raw.device)
+    out = _out(out, (count, grid.n_az), torch.complex64, raw.device)
     g, p = L.geometry(geom), L.polar_grid(grid)
     raw = raw.contiguous()
     L.check(L.lib().rosar_bp_time_domain(C.byref(g), C.byref(p), _ptr(raw),
@@ -439,8 +445,7 @@ def sas_time_domain(geom, grid, raw: torch.Tensor, offsets, weights, window_w, w
     [first, first + count) (all rows if None); returns [count, n_az]."""
     _need_gpu(raw)
     first, count = (0, grid.n_range) if rows is None else rows
-    if out is None:
-        out = torch.empty((count, grid.n_az), dtype=torch.complex64, device=raw.device)
+    out = _out(out, (count, grid.n_az), torch.complex64, raw.device)
     s = _set(offsets, weights, window_w)
     g, p = L.geometry(geom), L.polar_grid(grid)
     raw = raw.contiguous()
@@ -460,12 +465,8 @@ def delta_r(geom, grid, window: int, deltas: torch.Tensor, quantile: float = 0.9
     deltas = deltas.contiguous()
     n_s = deltas.shape[1]
     dev = deltas.device
-    if samples is None:
-        samples = torch.empty((grid.n_range, n_s), dtype=torch.float64, device=dev)
-    if out is None:
-        out = torch.empty(grid.n_range, dtype=torch.float64, device=dev)
-    if samples.shape != (grid.n_range, n_s) or out.shape != (grid.n_range,) or not samples.is_contiguous():
-        raise ValueError("samples must be contiguous [n_range, S] and out [n_range]")
+    samples = _out(samples, (grid.n_range, n_s), torch.float64, dev)
+    out = _out(out, grid.n_range, torch.float64, dev)
     g, p = L.geometry(geom), L.polar_grid(grid)
     L.check(L.lib().rosar_delta_r(C.byref(g), C.byref(p), window, _ptr(deltas), n_s, float(quantile), _ptr(samples),
                                   _ptr(out), _stream(dev)), "rosar_delta_r")
@@ -484,10 +485,8 @@ def beampattern(geom, grid, offsets, weights, window: int, angles: torch.Tensor,
     angles = angles.contiguous()
     dev = angles.device
     s = _set(offsets, weights, window)
-    if pattern is None:
-        pattern = torch.empty((grid.n_range, angles.numel()), dtype=torch.float64, device=dev)
-    if summary is None:
-        summary = torch.empty((grid.n_range, 3), dtype=torch.float64, device=dev)
+    pattern = _out(pattern, (grid.n_range, angles.numel()), torch.float64, dev)
+    summary = _out(summary, (grid.n_range, 3), torch.float64, dev)
     if delta_r is not None:
         delta_r = delta_r.contiguous()
         if delta_r.dtype != torch.float64 or delta_r.shape != (grid.n_range,):
@@ -509,14 +508,14 @@ def sparse_filter_adjoint_band(geom, grid, layout: RangeCompressed, offsets, wei
     s = _set(offsets, weights, window)
     g, p, v = L.geometry(geom), L.polar_grid(grid), layout.view()
     dev = grad_image.device
-    if out is None:
-        out = torch.empty((layout.l_count, geom.n_pulses), dtype=torch.complex64, device=dev)
+    out = _out(out, (layout.l_count, geom.n_pulses), torch.complex64, dev)
     need = C.c_size_t(0)
     L.check(L.lib().rosar_sparse_filter_adjoint_band_workspace_size(C.byref(g), C.byref(p), C.byref(v), C.byref(s),
                                                                     L.INTERP_CODES[interp], C.byref(need)),
             "rosar_sparse_filter_adjoint_band_workspace_size")
     if workspace is None:
         workspace = torch.empty(int(need.value), dtype=torch.uint8, device=dev)
+    _need_gpu(workspace)   # its size is checked by the library
     L.check(L.lib().rosar_sparse_filter_adjoint_band(C.byref(g), C.byref(p), C.byref(v), C.byref(s),
                                                      L.INTERP_CODES[interp], _ptr(grad_image.contiguous()), _ptr(out),
                                                      _ptr(workspace), workspace.numel(), _stream(dev)),
@@ -555,8 +554,7 @@ class SparsePlan:
 
     def run(self, rc: RangeCompressed, out: torch.Tensor | None = None) -> torch.Tensor:
         _need_gpu(rc.data)
-        if out is None:
-            out = torch.empty((self.grid.n_range, self.grid.n_az), dtype=torch.complex64, device=rc.data.device)
+        out = _out(out, (self.grid.n_range, self.grid.n_az), torch.complex64, rc.data.device)
         v = rc.view()
         L.check(L.lib().rosar_sparse_plan_run(self._h, C.byref(v), _ptr(out), _stream(rc.data.device)),
                 "rosar_sparse_plan_run")

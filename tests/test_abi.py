@@ -481,3 +481,16 @@ def test_autotune_cache_helpers(tmp_path):
     b = rs.autotune_cache_key("gfx950", g, grid, "f16", 64, 32, 64, L.C64, "nearest", "all")
     assert a != b and a.startswith("gfx950|")
 
+
+
+def test_output_buffer_checks():
+    """A caller's output buffer must match what the kernel writes; None allocates one."""
+    import torch
+    from paper_2309_08038_amd.api import _out
+    t = torch.empty((4, 6), dtype=torch.complex64)
+    assert _out(t, (4, 6), torch.complex64, "cpu") is t
+    assert tuple(_out(None, 5, torch.float64, "cpu").shape) == (5,)
+    for bad in (torch.empty((4, 7), dtype=torch.complex64), torch.empty((4, 6), dtype=torch.complex128),
+                torch.empty((6, 4), dtype=torch.complex64).t()):
+        with pytest.raises(ValueError):
+            _out(bad, (4, 6), torch.complex64, "cpu")
