@@ -39,6 +39,13 @@ def _out(t, shape, dtype, device):
     return t
 
 
+def _shape(t, shape, name):
+    """Raises unless tensor t (if given) has exactly `shape`: the kernels read and write by the
+    sizes the geometry and grid give, so a smaller tensor would be overrun."""
+    if t is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)} (got {tuple(t.shape)})")
+
+
 def _need_gpu(*tensors):
     for t in tensors:
         if t is not None and not t.is_cuda:
@@ -59,6 +66,11 @@ class RangeCompressed:
     scale: float = 1.0
 
     def view(self) -> L.RcView:
+        _need_gpu(self.data)
+        need = self.l_count * self.ld * (8 if self.dtype == "c64" else 4)
+        if self.data.numel() * self.data.element_size() < need:
+            raise ValueError(f"band tensor holds {self.data.numel() * self.data.element_size()} bytes, "
+                             f"its layout ({self.l_count} rows x ld {self.ld}) needs {need}")
         return L.RcView(self.data.data_ptr(), L.DTYPE_CODES[self.dtype], self.l_lo, self.l_count, self.halo,
                         self.ld, float(self.scale), 0)
 
@@ -89,17 +101,24 @@ def range_compress(geom, raw: torch.Tensor, window: torch.Tensor | None, l_lo: i
         raise TypeError("raw must be complex64 [N, M]")
     if window is not None and window.dtype != torch.float32:
         raise TypeError("window must be float32 [M]")
+    _shape(raw, (geom.n_pulses, geom.n_fast), "raw")
+    _shape(window, (geom.n_fast,), "window")
     if out is None:
         out = empty_rc(geom.n_pulses, l_lo, l_count, halo, dtype, scale, raw.device)
+    elif out.l_lo != l_lo or out.l_count != l_count:
+        raise ValueError("out's band (l_lo, l_count) differs from the requested one")
     g = L.geometry(geom)
+    out.view()   # size check of the band tensor against its layout
     L.check(L.lib().rosar_range_compress(C.byref(g), _ptr(raw), _ptr(window), l_lo, l_count, out.halo,
                                          L.DTYPE_CODES[out.dtype], float(out.scale), _ptr(out.data), out.ld,
                                          _stream(raw.device)), "rosar_range_compress")
     return out
 
 
-def _set(offsets: torch.Tensor, weights: torch.Tensor, window: int) -> L.SparseSet:
+def _set(offsets: torch.Tensor, weights: torch.Tensor, window: int, rows: int | None = None) -> L.SparseSet:
     _need_gpu(offsets, weights)
+    if rows is not None and offsets.dim() == 2 and offsets.shape[0] != rows:
+        raise ValueError(f"offsets and weights need one row per range row ({rows}, got {offsets.shape[0]})")
     if offsets.dtype != torch.int32 or offsets.dim() != 2:
         raise TypeError("offsets must be int32 [n_range, K]")
     if weights.dtype == torch.complex64:
@@ -122,8 +141,10 @@ def sparse_filter(geom, grid, rc: RangeCompressed, offsets: torch.Tensor, weight
                   dphi: torch.Tensor | None = None, dpsi: torch.Tensor | None = None, interp: str = "nearest",
                   out: torch.Tensor | None = None, tile: tuple[int, int, int] | None = None) -> torch.Tensor:
     """Sparse-aperture azimuth filter (Algorithm 2 / eq. 43) -> complex64 image [n_range, n_az]."""
-    s = _set(offsets, weights, window)
+    s = _set(offsets, weights, window, grid.n_range)
     _need_gpu(dphi, dpsi, rc.data)
+    _shape(dphi, (geom.n_pulses,), "dphi")
+    _shape(dpsi, (geom.n_pulses,), "dpsi")
     out = _out(out, (grid.n_range, grid.n_az), torch.complex64, rc.data.device)
     g, p, v = L.geometry(geom), L.polar_grid(grid), rc.view()
     t = None if tile is None else L.Tile(tile[0], tile[1], tile[2], 0)
@@ -146,6 +167,7 @@ def bp_full(geom, grid, rc: RangeCompressed, angles: torch.Tensor | None = None,
     _need_gpu(angles, rc.data)
     if angles is not None and angles.dtype != torch.float64:
         raise TypeError("angles must be float64 [N]")
+    _shape(angles, (geom.n_pulses,), "angles")
     dev = rc.data.device
     out = _out(out, (grid.n_range, grid.n_az), torch.complex64, dev)
     nbytes = bp_workspace_bytes(geom)
@@ -160,7 +182,7 @@ def bp_full(geom, grid, rc: RangeCompressed, angles: torch.Tensor | None = None,
 
 
 def backward_workspace_bytes(geom, grid, offsets, weights, window) -> int:
-    g, p, s = L.geometry(geom), L.polar_grid(grid), _set(offsets, weights, window)
+    g, p, s = L.geometry(geom), L.polar_grid(grid), _set(offsets, weights, window, grid.n_range)
     n = C.c_size_t(0)
     L.check(L.lib().rosar_sparse_filter_backward_workspace_size(C.byref(g), C.byref(p), C.byref(s), C.byref(n)),
             "rosar_sparse_filter_backward_workspace_size")
@@ -173,8 +195,11 @@ def sparse_filter_backward(geom, grid, rc: RangeCompressed, offsets, weights, wi
     """Adjoint of sparse_filter -> (grad_weights c64 [n_range, K] | None, grad_dphi f32 [N] | None,
     grad_dpsi f32 [N] | None) for grad_image = dL/dRe(I) + j dL/dIm(I).  `out` may supply the three
     output tensors (entries None for gradients not wanted)."""
-    s = _set(offsets, weights, window)
+    s = _set(offsets, weights, window, grid.n_range)
     _need_gpu(grad_image, dphi, dpsi)
+    _shape(grad_image, (grid.n_range, grid.n_az), "grad_image")
+    _shape(dphi, (geom.n_pulses,), "dphi")
+    _shape(dpsi, (geom.n_pulses,), "dpsi")
     dev = grad_image.device
     if out is not None:
         gw, gd, gp = out
@@ -265,7 +290,7 @@ def sparse_filter_band_diff(geom, grid, band, l_lo, offsets, weights, window, in
 def autotune_sparse_filter(geom, grid, rc: RangeCompressed, offsets, weights, window, reps: int = 20,
                            out: torch.Tensor | None = None):
     """Time every launch shape of the plain sparse filter; returns ((variant, ppl, waves), microseconds)."""
-    s = _set(offsets, weights, window)
+    s = _set(offsets, weights, window, grid.n_range)
     dev = rc.data.device
     out = _out(out, (grid.n_range, grid.n_az), torch.complex64, dev)
     g, p, v = L.geometry(geom), L.polar_grid(grid), rc.view()
@@ -292,12 +317,17 @@ class Rotation:
 
     def desc(self) -> L.RotationDesc:
         _need_gpu(self.raw, self.window, self.offsets, self.weights, self.image, self.rc.data)
+        _shape(self.raw, (self.geom.n_pulses, self.geom.n_fast), "raw")
+        _shape(self.window, (self.geom.n_fast,), "window")
+        _shape(self.image, (self.grid.n_range, self.grid.n_az), "image")
+        self.rc.view()   # band size check
         if self.rc.dtype != "c64" or self.weights.dtype != torch.complex64:
             raise TypeError("batched rotations use complex64 data and weights")
         return L.RotationDesc(L.geometry(self.geom), L.polar_grid(self.grid), self.raw.data_ptr(),
                               None if self.window is None else self.window.data_ptr(), self.rc.data.data_ptr(),
                               self.rc.l_lo, self.rc.l_count, self.rc.halo, 0, self.rc.ld,
-                              _set(self.offsets, self.weights, self.sparse_window), self.image.data_ptr())
+                              _set(self.offsets, self.weights, self.sparse_window, self.grid.n_range),
+                              self.image.data_ptr())
 
 
 def _descs(rotations):
@@ -353,7 +383,7 @@ def sparse_plan_autotune(geom, grid, rc: RangeCompressed, offsets, weights, wind
     ROSAR_AUTOTUNE_CACHE environment variable; none when unset); a hit skips the timing."""
     variants = {"all": 0, "direct": L.PLAN_DIRECT, "fastconv": L.PLAN_FASTCONV}[methods]
     _need_gpu(rc.data)
-    s = _set(offsets, weights, window)
+    s = _set(offsets, weights, window, grid.n_range)
     dev = rc.data.device
     cache = cache if cache is not None else os.environ.get("ROSAR_AUTOTUNE_CACHE")
     key = None
@@ -382,7 +412,7 @@ def sparse_filter_cartesian(geom, grid, cart, rc: RangeCompressed, offsets, weig
     """Algorithm 2 for targets on the Cartesian lattice `cart` (nx, ny, x0_m, y0_m, dx_m, dy_m),
     with the weights of the polar grid rows; returns [ny, nx] complex64."""
     _need_gpu(rc.data)
-    s = _set(offsets, weights, window)
+    s = _set(offsets, weights, window, grid.n_range)
     out = _out(out, (cart.ny, cart.nx), torch.complex64, rc.data.device)
     g, p, v = L.geometry(geom), L.polar_grid(grid), rc.view()
     c = L.CartGrid(int(cart.nx), int(cart.ny), float(cart.x0_m), float(cart.y0_m), float(cart.dx_m), float(cart.dy_m))
@@ -415,7 +445,7 @@ def sparse_filter_polar(geom, grid, rc: RangeCompressed, offsets, weights, windo
     """Algorithm 2 on a polar grid of grid.n_az azimuth bins, which may differ from the pulse
     count (per-pixel central phase centre); returns [n_range, n_az] complex64."""
     _need_gpu(rc.data)
-    s = _set(offsets, weights, window)
+    s = _set(offsets, weights, window, grid.n_range)
     out = _out(out, (grid.n_range, grid.n_az), torch.complex64, rc.data.device)
     g, p, v = L.geometry(geom), L.polar_grid(grid), rc.view()
     L.check(L.lib().rosar_sparse_filter_polar(C.byref(g), C.byref(p), C.byref(v), C.byref(s), L.INTERP_CODES[interp],
@@ -427,7 +457,11 @@ def bp_time_domain(geom, grid, raw: torch.Tensor, window: torch.Tensor | None = 
                    rows: tuple[int, int] | None = None, out: torch.Tensor | None = None) -> torch.Tensor:
     """Conventional time-domain BPA on the raw samples (exact beat frequency per pixel and
     pulse) for grid rows [first, first + count) (all rows if None); returns [count, n_az]."""
-    _need_gpu(raw)
+    _need_gpu(raw, window)
+    _shape(raw, (geom.n_pulses, geom.n_fast), "raw")
+    _shape(window, (geom.n_fast,), "window")
+    if angles is not None and (angles.dtype != torch.float64 or tuple(angles.shape) != (geom.n_pulses,)):
+        raise ValueError("angles must be float64 [n_pulses]")
     first, count = (0, grid.n_range) if rows is None else rows
     out = _out(out, (count, grid.n_az), torch.complex64, raw.device)
     g, p = L.geometry(geom), L.polar_grid(grid)
@@ -443,10 +477,12 @@ def sas_time_domain(geom, grid, raw: torch.Tensor, offsets, weights, window_w, w
                     rows: tuple[int, int] | None = None, out: torch.Tensor | None = None) -> torch.Tensor:
     """Sparse-aperture filter on the raw samples (exact beat frequency per tap) for grid rows
     [first, first + count) (all rows if None); returns [count, n_az]."""
-    _need_gpu(raw)
+    _need_gpu(raw, window)
+    _shape(raw, (geom.n_pulses, geom.n_fast), "raw")
+    _shape(window, (geom.n_fast,), "window")
     first, count = (0, grid.n_range) if rows is None else rows
     out = _out(out, (count, grid.n_az), torch.complex64, raw.device)
-    s = _set(offsets, weights, window_w)
+    s = _set(offsets, weights, window_w, grid.n_range)
     g, p = L.geometry(geom), L.polar_grid(grid)
     raw = raw.contiguous()
     L.check(L.lib().rosar_sas_time_domain(C.byref(g), C.byref(p), _ptr(raw),
@@ -484,7 +520,7 @@ def beampattern(geom, grid, offsets, weights, window: int, angles: torch.Tensor,
         raise ValueError("angles must be a float64 vector")
     angles = angles.contiguous()
     dev = angles.device
-    s = _set(offsets, weights, window)
+    s = _set(offsets, weights, window, grid.n_range)
     pattern = _out(pattern, (grid.n_range, angles.numel()), torch.float64, dev)
     summary = _out(summary, (grid.n_range, 3), torch.float64, dev)
     if delta_r is not None:
@@ -505,7 +541,8 @@ def sparse_filter_adjoint_band(geom, grid, layout: RangeCompressed, offsets, wei
     A^H grad_image (grad_image = dL/dRe(I) + j dL/dIm(I)).  `layout` gives the band rows; returns
     [l_count, n_pulses] complex64 (the band without its halo copies)."""
     _need_gpu(grad_image)
-    s = _set(offsets, weights, window)
+    _shape(grad_image, (grid.n_range, grid.n_az), "grad_image")
+    s = _set(offsets, weights, window, grid.n_range)
     g, p, v = L.geometry(geom), L.polar_grid(grid), layout.view()
     dev = grad_image.device
     out = _out(out, (layout.l_count, geom.n_pulses), torch.complex64, dev)
@@ -537,7 +574,7 @@ class SparsePlan:
     def __init__(self, geom, grid, layout: RangeCompressed, offsets, weights, window, interp: str = "nearest",
                  tile: tuple[int, int] | str | None = None):
         _need_gpu(layout.data)
-        s = _set(offsets, weights, window)
+        s = _set(offsets, weights, window, grid.n_range)
         g, p, v = L.geometry(geom), L.polar_grid(grid), layout.view()
         if tile == "fastconv":
             t = L.Tile(3, 0, 0, 0)
