@@ -155,32 +155,31 @@ def sparse_filter(yb: np.ndarray, l_lo: int, geom, grid, offsets: np.ndarray, we
     return out
 
 
-def delta_r_samples(geom, grid, window: int, deltas: np.ndarray) -> np.ndarray:
-    """Monte-Carlo samples of Delta^_R = ||a^(phi; R) - a(phi; R)|| (Sec. III-C parameter
-    settings, eq. 37): a is the steering vector of the W phase centres around the target
-    direction (eq. 16: cos(theta'_n) exp(+j 2 k R_n);
-    cos(theta'_n) = max(R cos D_n - r, 0) / R_n as in the field-of-view reading;
-    D_n = o 2 pi / N for offsets o in [-W/2, W/2)), a^ the
-    same with each angle perturbed by the given draw, D^_n = D_n + deltas[s, o + W/2].  Computed
-    per element as |alpha^ e^{j psi} - alpha|^2 = (alpha^ - alpha)^2 + 4 alpha alpha^ sin^2(psi/2),
-    psi = 2 k (R^ - R), R^ - R = (R^2^ - R^2) / (R^ + R).  Returns [n_range, S]."""
+def steering_vector(geom, rr: float, d):
+    """Element a_n of the steering vector (eq. 16) of a target at range rr seen from a phase
+    centre whose angle differs from the target's by d: cos(theta'_n) exp(+j 2 k R_n), with R_n
+    from eq. 2 and cos(theta'_n) = max(R cos D - r, 0) / R_n (the field-of-view reading)."""
     k = wavenumber(geom)
     r = geom.radius_m
+    rn = slant_range(rr, r, d)
+    return np.maximum(rr * np.cos(d) - r, 0.0) / rn * np.exp(1j * 2.0 * k * rn)
+
+
+def delta_r_samples(geom, grid, window: int, deltas: np.ndarray) -> np.ndarray:
+    """Monte-Carlo samples of Delta^_R = ||a^(phi; R) - a(phi; R)|| (Sec. III-C parameter
+    settings, eq. 37), straight from the definition: a is the steering vector (eq. 16) of the W
+    phase centres around the target direction, D_n = o 2 pi / N for offsets o in [-W/2, W/2);
+    a^ is the same vector with each angle perturbed by the given draw,
+    D^_n = D_n + deltas[s, o + W/2].  Both vectors are evaluated as complex exponentials in
+    float64 and subtracted.  Returns [n_range, S]."""
     o = np.arange(-(window // 2), window // 2)
     d0 = o * TWO_PI / geom.n_pulses
     out = np.zeros((grid.n_range, deltas.shape[0]))
     for row in range(grid.n_range):
         rr = grid.r0_m + row * grid.dr_m
-        rn = slant_range(rr, r, d0)
-        al = np.maximum(rr * np.cos(d0) - r, 0.0) / rn
-        d1 = d0[None, :] + deltas
-        rh = slant_range(rr, r, d1)
-        alh = np.maximum(rr * np.cos(d1) - r, 0.0) / rh
-        # R^2^ - R^2 = 2 R r (cos D - cos D^) = 4 R r sin((D + D^)/2) sin((D^ - D)/2)
-        dsq = 4.0 * rr * r * np.sin((d0[None, :] + d1) / 2.0) * np.sin(deltas / 2.0)
-        psi = 2.0 * k * dsq / (rh + rn[None, :])
-        e2 = (alh - al[None, :]) ** 2 + 4.0 * al[None, :] * alh * np.sin(psi / 2.0) ** 2
-        out[row] = np.sqrt(np.sum(e2, axis=1))
+        a = steering_vector(geom, rr, d0)
+        a_hat = steering_vector(geom, rr, d0[None, :] + deltas)
+        out[row] = np.linalg.norm(a_hat - a[None, :], axis=1)
     return out
 
 

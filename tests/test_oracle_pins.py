@@ -159,6 +159,183 @@ def test_sum_abs_weights_closed_form(t_start):
     assert others.max() < peak * (1 - 1e-6)
 
 
+# --------------------------------------------------------------------------- P4, corrected
+def _recorded_point(g, grid, offsets, row, a0, l_lo, l_count, delta=None, psi=None, spread=False):
+    """Band of a unit point at pixel (row, a0) as recorded by phase centres that really sat at
+    phi0 + 2 pi n / N + delta_n (positions in x/y), with a per-pulse phase error e^{+j psi_n} in
+    the data: value e^{+j carrier phase} at the bin of the true beat frequency (NEAREST), or at
+    both bins around it (spread, so LINEAR reads the same value)."""
+    n_p = g.n_pulses
+    delta = np.zeros(n_p) if delta is None else delta
+    psi = np.zeros(n_p) if psi is None else psi
+    yb = np.zeros((n_p, l_count), dtype=np.complex128)
+    r_t = grid.r0_m + row * grid.dr_m
+    phi_t = g.phi0_rad + 2 * np.pi * a0 / grid.n_az
+    for o in offsets[row]:
+        n = (a0 + int(o)) % n_p
+        ang = g.phi0_rad + 2 * np.pi * n / n_p + delta[n]
+        rn = cart_range(g, ang, r_t, phi_t)
+        u = beat_bin(g, rn)
+        assert abs(u - np.floor(u) - 0.5) > 1e-6          # no rounding tie
+        val = np.exp(1j * (carrier_phase(g, rn) + psi[n]))
+        if spread:
+            lb = int(np.floor(u)) - l_lo
+            yb[n, lb] = yb[n, lb + 1] = val
+        else:
+            yb[n, int(np.floor(u + 0.5)) - l_lo] = val
+    return yb
+
+
+def _p4_case(seed):
+    g = small_geom(180, 128, 0.25)
+    w = synth.Workload("p4c", 48, g, synth.PolarGrid(6, 180, 1.3, 0.11),
+                       synth.SceneSpec(0, "unit", 1, 2), synth.SparseSpec(24, 64, False))
+    offs = synth.make_support(w)
+    wts = synth.phase_matched_weights(g, w.grid, offs, synth.taylor_taper(64, 4, 30))
+    l_lo, l_count = synth.band_for(g, w.grid)
+    rng = np.random.default_rng(seed)
+    return g, w.grid, offs, wts, l_lo, l_count, rng
+
+
+@pytest.mark.parametrize("interp", ["nearest", "linear"])
+def test_corrected_filter_angle_error_physical(interp):
+    """Data recorded at true angles 2 pi n / N + delta_n (eq. 37), with the bin and the carrier
+    phase of the true x/y range: the corrected filter given dphi = delta refocuses the point to
+    sum_k |w_k| exactly (weights matched to the nominal geometry); dphi = -delta, or no
+    correction, does not.  This fixes the sign convention of delta relative to the offsets."""
+    g, grid, offs, wts, l_lo, l_count, rng = _p4_case(61)
+    row, a0 = 3, 17
+    delta = rng.normal(0, 3e-3, g.n_pulses)
+    yb = _recorded_point(g, grid, offs, row, a0, l_lo, l_count, delta=delta, spread=interp == "linear")
+    peak = np.sum(np.abs(wts[row]))
+    at = lambda d, p=None: oracle.sparse_filter_at(yb, l_lo, g, grid, offs, wts, [row], [a0], d, p, interp)[0]
+    got = at(delta)
+    assert abs(got - peak) < 1e-9 * peak
+    assert abs(at(-delta)) < 0.9 * peak
+    assert abs(at(np.zeros(g.n_pulses))) < 0.9 * peak
+    assert abs(oracle.sparse_filter_at(yb, l_lo, g, grid, offs, wts, [row], [a0], interp=interp)[0]) < 0.9 * peak
+
+
+def test_corrected_filter_phase_error_physical():
+    """Data carrying a per-pulse phase error e^{+j psi_n}: the corrected filter given dpsi = psi
+    refocuses the point to sum_k |w_k|; dpsi = -psi does not."""
+    g, grid, offs, wts, l_lo, l_count, rng = _p4_case(62)
+    row, a0 = 2, 100
+    psi = rng.uniform(-np.pi, np.pi, g.n_pulses)
+    yb = _recorded_point(g, grid, offs, row, a0, l_lo, l_count, psi=psi)
+    peak = np.sum(np.abs(wts[row]))
+    at = lambda p: oracle.sparse_filter_at(yb, l_lo, g, grid, offs, wts, [row], [a0], None, p)[0]
+    assert abs(at(psi) - peak) < 1e-9 * peak
+    assert abs(at(-psi)) < 0.9 * peak
+
+
+@pytest.mark.parametrize("which", ["delta", "psi"])
+def test_calibration_gradient_points_to_truth(which):
+    """L = -|I(pixel)|^2 of the recorded point: its gradient vanishes at the true errors (the
+    refocused maximum) and, one pulse's estimate moved by eps from the truth, has the sign of
+    eps, so a gradient step moves the estimate back (LINEAR, derivatives of the corrected
+    model)."""
+    g, grid, offs, wts, l_lo, l_count, rng = _p4_case(63)
+    row, a0 = 4, 60
+    true = rng.normal(0, 3e-3, g.n_pulses) if which == "delta" else rng.uniform(-1, 1, g.n_pulses)
+    kw = {which: true}
+    yb = _recorded_point(g, grid, offs, row, a0, l_lo, l_count, spread=True, **kw)
+    sub = synth.PolarGrid(grid.n_range, grid.n_az, grid.r0_m, grid.dr_m)
+
+    def grad(est):
+        dphi, dpsi = (est, None) if which == "delta" else (None, est)
+        img = oracle.sparse_filter(yb, l_lo, g, sub, offs, wts, dphi, dpsi, "linear", rows=range(grid.n_range))
+        gimg = np.zeros_like(img)
+        gimg[row, a0] = -2.0 * img[row, a0]           # dL/dRe I + j dL/dIm I of L = -|I|^2
+        _, gd, gp = oracle.sparse_filter_grad(yb, l_lo, g, sub, offs, wts, gimg,
+                                              dphi if dphi is not None else np.zeros(g.n_pulses),
+                                              dpsi if dpsi is not None else np.zeros(g.n_pulses), "linear")
+        return gd if which == "delta" else gp
+
+    at_truth = grad(true)
+    pulses = (a0 + offs[row][[2, 9, 20]]) % g.n_pulses
+    scale = np.sum(np.abs(wts[row])) ** 2
+    assert np.max(np.abs(at_truth)) < 1e-9 * scale * (1e3 if which == "delta" else 1)
+    eps = 2e-4 if which == "delta" else 0.05
+    for n, sgn in zip(pulses, (1, -1, 1)):
+        est = true.copy()
+        est[n] += sgn * eps
+        gn = grad(est)[n]
+        assert np.sign(gn) == sgn and abs(gn) > 1e-6 * scale, (n, sgn, gn)
+
+
+# --------------------------------------------------------------------------- LINEAR closed form
+def _quadratic_band(g, l_lo, l_count, rng):
+    """Y[n, l] = c0_n + c1_n l + c2_n l^2 in the absolute bin index l, complex coefficients."""
+    c = rng.normal(size=(3, g.n_pulses)) + 1j * rng.normal(size=(3, g.n_pulses))
+    c[2] *= 1e-2
+    l = np.arange(l_lo, l_lo + l_count, dtype=np.float64)
+    return c[0][:, None] + c[1][:, None] * l[None, :] + c[2][:, None] * l[None, :] ** 2, c
+
+
+def _quadratic_read(c, n, u, interp):
+    """What a sampler must return on the quadratic band at fractional bin u: NEAREST reads
+    l = floor(u + 1/2); LINEAR is the chord between floor(u) and floor(u) + 1, which lies
+    f (1 - f) (f = u - floor(u)) above the parabola l^2 (half its second difference, 2)."""
+    if interp == "nearest":
+        l = np.floor(u + 0.5)
+        return c[0][n] + c[1][n] * l + c[2][n] * l * l
+    f = u - np.floor(u)
+    return c[0][n] + c[1][n] * u + c[2][n] * (u * u + f * (1.0 - f))
+
+
+@pytest.mark.parametrize("interp", ["nearest", "linear"])
+@pytest.mark.parametrize("corrected", [False, True])
+def test_sparse_filter_quadratic_band_closed_form(interp, corrected):
+    """The sparse filter on a band quadratic in the bin index equals
+    sum_k conj(w_k) rot_k Q_n(u_k), u_k the beat bin of the x/y range from the phase centre
+    (at its jittered angle when corrected) and rot_k = e^{-j 2k (R^ - R_nom)} e^{-j psi_n}.
+    An extrapolating LINEAR index (ceil), swapped weights or a wrong bin fail it."""
+    g, grid, offs, _, l_lo, l_count, rng = _p4_case(64 + corrected)
+    yb, c = _quadratic_band(g, l_lo, l_count, rng)
+    wts = rng.normal(size=offs.shape) + 1j * rng.normal(size=offs.shape)
+    delta = rng.normal(0, 3e-3, g.n_pulses) if corrected else None
+    psi = rng.uniform(-1, 1, g.n_pulses) if corrected else None
+    k = oracle.wavenumber(g)
+    rows, azs = rng.integers(0, grid.n_range, 12), rng.integers(0, grid.n_az, 12)
+    got = oracle.sparse_filter_at(yb, l_lo, g, grid, offs, wts, rows, azs, delta, psi, interp)
+    for i, (row, a) in enumerate(zip(rows, azs)):
+        r_t, phi_t = grid.r0_m + row * grid.dr_m, g.phi0_rad + 2 * np.pi * a / grid.n_az
+        want = 0j
+        for kk, o in enumerate(offs[row]):
+            n = (a + int(o)) % g.n_pulses
+            nominal = g.phi0_rad + 2 * np.pi * n / g.n_pulses
+            r_nom = cart_range(g, nominal, r_t, phi_t)
+            r_hat = cart_range(g, nominal + (delta[n] if corrected else 0.0), r_t, phi_t)
+            u = beat_bin(g, r_hat)
+            assert l_lo + 1 <= u < l_lo + l_count - 2
+            rot = np.exp(-2j * k * (r_hat - r_nom) - 1j * psi[n]) if corrected else 1.0
+            want += np.conj(wts[row, kk]) * rot * _quadratic_read(c, n, u, interp)
+        assert abs(got[i] - want) <= 1e-9 * abs(want), (row, a, got[i], want)
+
+
+@pytest.mark.parametrize("interp", ["nearest", "linear"])
+def test_bp_quadratic_band_closed_form(interp):
+    """Back-projection on the quadratic band with jittered pulse angles equals
+    sum over visible n of cos(theta_n) e^{-j 2k R_n} Q_n(u_n), with R_n, the bore-sight cosine
+    and u_n from x/y positions."""
+    g, grid, _, _, l_lo, l_count, rng = _p4_case(66)
+    yb, c = _quadratic_band(g, l_lo, l_count, rng)
+    ang = synth.nominal_angles(g) + rng.normal(0, 3e-3, g.n_pulses)
+    k = oracle.wavenumber(g)
+    rows, azs = rng.integers(0, grid.n_range, 6), rng.integers(0, grid.n_az, 6)
+    got = oracle.bp_full_at(yb, l_lo, g, grid, rows, azs, pulse_angles=ang, interp=interp)
+    for i, (row, a) in enumerate(zip(rows, azs)):
+        r_t, phi_t = grid.r0_m + row * grid.dr_m, g.phi0_rad + 2 * np.pi * a / grid.n_az
+        rn = cart_range(g, ang, r_t, phi_t)
+        cb = boresight_cos(g, ang, r_t, phi_t)
+        vis = cb > 0
+        u = beat_bin(g, rn[vis])
+        n = np.nonzero(vis)[0]
+        want = np.sum(cb[vis] * np.exp(-2j * k * rn[vis]) * _quadratic_read(c, n, u, interp))
+        assert abs(got[i] - want) <= 1e-9 * abs(want), (row, a)
+
+
 # --------------------------------------------------------------------------- P5
 def test_raw_domain_closed_form():
     """O1 then O2 on a simulated scatterer equals sum_k conj(w_k) alpha_k e^{j2kR_k} H(u_k - l_k)
@@ -387,27 +564,54 @@ def test_cartesian_rotation_invariance():
     assert np.count_nonzero(np.abs(base) > 1e-6) > 30
 
 
-def _steering(geom, rr, d, k):
-    """eq. 16 evaluated directly with complex exponentials (test-side reference)."""
-    r = geom.radius_m
-    rn = np.sqrt(rr * rr + r * r - 2 * rr * r * np.cos(d))
-    return np.maximum(rr * np.cos(d) - r, 0.0) / rn * np.exp(1j * 2 * k * rn)
+def _steering_xy(geom, rr, phi_t, d):
+    """eq. 16 element from explicit x/y positions: the phase centre at angle phi_t + d on the
+    circle (bore-sight radial), the target at (rr, phi_t)."""
+    k = oracle.wavenumber(geom)
+    ang = phi_t + d
+    dist = cart_range(geom, ang, rr, phi_t)
+    return np.maximum(boresight_cos(geom, ang, rr, phi_t), 0.0) * np.exp(1j * 2 * k * dist)
 
 
-def test_delta_r_direct_evaluation():
-    """At a carrier low enough for direct complex arithmetic to keep its digits, ||a^ - a|| from
-    explicit exponentials equals the oracle's cancellation-free form."""
-    import dataclasses
-    g = dataclasses.replace(small_geom(360, 64, 0.3), fc_hz=2e9)
-    grid = synth.PolarGrid(5, 360, 0.6, 0.4)
-    k = oracle.wavenumber(g)
+def test_delta_r_cartesian_positions():
+    """||a^ - a|| with both steering vectors built from perturbed and nominal x/y positions of the
+    W phase centres (77 GHz, metres of range)."""
+    g = small_geom(360, 64, 0.3)
+    grid = synth.PolarGrid(5, 360, 0.6, 3.1)
     rng = np.random.default_rng(11)
-    deltas = rng.normal(0, 2e-2, (50, 64))
+    deltas = rng.normal(0, 2e-3, (50, 64))
     got = oracle.delta_r_samples(g, grid, 64, deltas)
     d0 = np.arange(-32, 32) * 2 * np.pi / 360
     for row in range(5):
         rr = grid.r0_m + row * grid.dr_m
-        want = np.linalg.norm(_steering(g, rr, d0[None, :] + deltas, k) - _steering(g, rr, d0, k)[None, :], axis=1)
+        phi_t = 0.7
+        want = np.linalg.norm(_steering_xy(g, rr, phi_t, d0[None, :] + deltas) - _steering_xy(g, rr, phi_t, d0)[None, :],
+                              axis=1)
+        np.testing.assert_allclose(got[row], want, rtol=1e-9)
+
+
+def test_delta_r_cancellation_free_form():
+    """The form the device evaluates, |alpha^ e^{j psi} - alpha|^2 = (alpha^ - alpha)^2
+    + 4 alpha alpha^ sin^2(psi/2) with psi = 2k (R^2^ - R^2)/(R^ + R) and R^2^ - R^2 =
+    4 R r sin((D + D^)/2) sin((D^ - D)/2), equals the oracle's direct difference of complex
+    exponentials to 1e-9 at 77 GHz over 0.5-15 m."""
+    g = small_geom(3600, 64, 0.3)
+    grid = synth.PolarGrid(4, 3600, 0.5, 4.8)
+    k = oracle.wavenumber(g)
+    r = g.radius_m
+    rng = np.random.default_rng(13)
+    deltas = rng.normal(0, np.deg2rad(0.05), (40, 256))
+    got = oracle.delta_r_samples(g, grid, 256, deltas)
+    d0 = np.arange(-128, 128) * 2 * np.pi / 3600
+    for row in range(4):
+        rr = grid.r0_m + row * grid.dr_m
+        d1 = d0[None, :] + deltas
+        rn = np.sqrt(rr * rr + r * r - 2 * rr * r * np.cos(d0))
+        rh = np.sqrt(rr * rr + r * r - 2 * rr * r * np.cos(d1))
+        al = np.maximum(rr * np.cos(d0) - r, 0) / rn
+        alh = np.maximum(rr * np.cos(d1) - r, 0) / rh
+        psi = 2 * k * 4 * rr * r * np.sin((d0[None, :] + d1) / 2) * np.sin(deltas / 2) / (rh + rn[None, :])
+        want = np.sqrt(np.sum((alh - al[None, :]) ** 2 + 4 * al[None, :] * alh * np.sin(psi / 2) ** 2, axis=1))
         np.testing.assert_allclose(got[row], want, rtol=1e-9)
 
 
@@ -425,7 +629,7 @@ def test_delta_r_small_sigma_linearisation():
     h = 1e-7
     for row in range(3):
         rr = grid.r0_m + row * grid.dr_m
-        da = (_steering(g, rr, d0 + h, k) - _steering(g, rr, d0 - h, k)) / (2 * h)
+        da = (_steering_xy(g, rr, 0.3, d0 + h) - _steering_xy(g, rr, 0.3, d0 - h)) / (2 * h)
         want = sigma ** 2 * np.sum(np.abs(da) ** 2)
         assert abs(got[row] - want) <= 0.03 * want, (row, got[row], want)
 
