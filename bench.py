@@ -27,12 +27,12 @@ sys.path.insert(0, ROOT)
 import numpy as np  # noqa: E402
 
 PEAK_HBM_GBPS = 8000.0
-# 256 CUs x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz: FP32 FMA issued one per lane per cycle
-# (packed FP32 disabled in this build); FP64 vector runs at the same rate.
-PEAK_FP32_VALU_TFLOPS = 78.6
-# the published vector FP32 figure counts packed FMAs (two per lane per cycle), which this build
-# does not emit; reported beside the fraction for reference
-PEAK_FP32_PACKED_TFLOPS = 157.3
+# MI355X's published vector FP32 peak (it counts packed FMAs, two per lane per cycle): the
+# roofline line's peak
+PEAK_FP32_TFLOPS = 157.3
+# 256 CUs x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz: one FP32 FMA per lane per cycle, the most this
+# build can issue (packed FP32 instructions are disabled); reported beside the fraction
+PEAK_FP32_UNPACKED_TFLOPS = 78.6
 PROFILE_DIR = os.path.join(ROOT, "profiles")
 
 
@@ -224,6 +224,25 @@ def copy_bandwidth(torch, nbytes=1 << 30, reps=5):
     return 2 * nbytes / (ms * 1e-3) / 1e9
 
 
+class ReplayMismatch(RuntimeError):
+    """A graph replay whose output differs from the eager run's bits."""
+
+
+def bits_differ(torch, got, ref):
+    """None if the two tensors hold the same bits (NaN-safe), else a short description of where
+    and how much they differ."""
+    a, b = got.contiguous().view(torch.uint8), ref.contiguous().view(torch.uint8)
+    if torch.equal(a, b):
+        return None
+    g, r = got.reshape(-1), ref.reshape(-1)
+    neq = (g.view(torch.uint8).reshape(g.numel(), -1) != r.view(torch.uint8).reshape(r.numel(), -1)).any(dim=1)
+    idx = torch.nonzero(neq).flatten()
+    diff = (g[idx].to(torch.complex128) - r[idx].to(torch.complex128)).abs()
+    return (f"{idx.numel()} of {g.numel()} elements differ (first at flat index {int(idx[0])}, "
+            f"last at {int(idx[-1])}); max |diff| {float(diff.max()):.3e} against max |ref| "
+            f"{float(r.abs().max()):.3e}; NaN in replay {int(torch.isnan(g).sum())}, in eager {int(torch.isnan(r).sum())}")
+
+
 def graph_timer(torch):
     """ms per call of fn, from HIP-graph replays: `inner` calls captured into one graph (no host
     work per launch: a Python/ctypes call costs about as much as a short kernel), the graph
@@ -243,8 +262,10 @@ def graph_timer(torch):
                     fn()
             g.replay()
             torch.cuda.synchronize()
-            if ref is not None and not torch.equal(out(), ref):
-                raise RuntimeError("graph replay differs from the eager result")
+            if ref is not None:
+                why = bits_differ(torch, out(), ref)
+                if why is not None:
+                    raise ReplayMismatch(f"graph replay differs from the eager result: {why}")
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             e0.record(s)
             for _ in range(reps):
@@ -350,9 +371,10 @@ def extras(torch, rs, synth, w, x, dev, rc, off, wts, timed, reps):
             fp()
             try:
                 fc[f"{name}_{interp}_us"] = 1000 * timed(fp, max(3, reps // 10), inner=10, out=lambda: img)
-            except RuntimeError as e:   # a replay that differs from the eager run is reported, not timed
+            except ReplayMismatch as e:
+                # recorded with the elements that differ; the run then exits non-zero
                 fc[f"{name}_{interp}_us"] = None
-                fc[f"{name}_{interp}_error"] = str(e)
+                FAILURES.append(f"plan variant {name} {interp}: {e}")
             p.close()
     out["plan_variants"] = fc
 
@@ -451,6 +473,9 @@ def extras(torch, rs, synth, w, x, dev, rc, off, wts, timed, reps):
     return out
 
 
+FAILURES: list = []
+
+
 class Phase:
     """A roctx range around one phase of the run (shown by rocprofv3 --marker-trace)."""
 
@@ -544,8 +569,9 @@ def main():
     with Phase(torch, "timed steps (two streams)"):
         ms_step, last = pipelined_steps(torch, rs, g, grid, x, raw, win, w.sparse.window, sf, a.steps)
     wall = time.perf_counter() - t0
-    if not torch.equal(last, ref):
-        raise RuntimeError("pipelined steps differ from the serial result")
+    why = bits_differ(torch, last, ref)
+    if why is not None:
+        raise RuntimeError(f"pipelined steps differ from the serial result: {why}")
     print(f"[bench] {a.steps} steps: {ms_step:.4f} ms/step pipelined, {ms_step_serial:.4f} ms/step serial "
           f"(wall {wall:.3f} s)", file=sys.stderr, flush=True)
 
@@ -561,8 +587,9 @@ def main():
     ms_sf = timed(lambda: sf(rc, img), kreps, inner=20, out=lambda: img)
     sf_ref = img.clone()
     ms_sf_other = timed(lambda: (planned if a.single_call else single)(rc, img), kreps, inner=20, out=lambda: img)
-    if not torch.equal(img, sf_ref):
-        raise RuntimeError("planned and single-call sparse filters differ")
+    why = bits_differ(torch, img, sf_ref)
+    if why is not None:
+        raise RuntimeError(f"planned and single-call sparse filters differ: {why}")
     ms_sf_plan, ms_sf_single = (ms_sf_other, ms_sf) if a.single_call else (ms_sf, ms_sf_other)
     rs.bp_full(g, grid, rc, angles=ang, out=bimg, workspace=bws)
     ms_bp = timed(lambda: rs.bp_full(g, grid, rc, angles=ang, out=bimg, workspace=bws), a.bpa_reps,
@@ -587,10 +614,13 @@ def main():
     traffic = None if a.single_call else load_traffic("sparse_filter", digest, a.workload,
                                                        f"{plan_shape[0]}x{plan_shape[1]}")
     achieved_tf = sf_flops / (ms_sf * 1e-3) / 1e12
-    roofline = {"bound": "alu", "achieved": round(achieved_tf, 3), "peak": PEAK_FP32_VALU_TFLOPS,
-                "unit": "TFLOP/s", "frac": round(achieved_tf / PEAK_FP32_VALU_TFLOPS, 4),
-                "peak_with_packed_fp32": PEAK_FP32_PACKED_TFLOPS,
-                "frac_of_packed_peak": round(achieved_tf / PEAK_FP32_PACKED_TFLOPS, 4),
+    roofline = {"bound": "alu", "achieved": round(achieved_tf, 3), "peak": PEAK_FP32_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(achieved_tf / PEAK_FP32_TFLOPS, 4),
+                "peak_unpacked_fp32": PEAK_FP32_UNPACKED_TFLOPS,
+                "frac_of_unpacked_peak": round(achieved_tf / PEAK_FP32_UNPACKED_TFLOPS, 4),
+                "peak_note": ("peak = MI355X's published FP32 vector rate (packed FMAs); this build issues "
+                              "unpacked FMAs only, whose ceiling is 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz "
+                              "= 78.6 TFLOP/s"),
                 "traffic": traffic,
                 "kernel": ("sparse_lds_kernel (single call, default launch shape)" if a.single_call else
                            f"sparse_lds_kernel<0, 0, 0, {plan_shape[0]}, {plan_shape[1]}, true> (planned tap "
@@ -711,7 +741,12 @@ def main():
         with Phase(torch, "cpu baseline"):
             out["cpu_baseline"] = cpu_baseline(w, x)
             out["cpu_baseline"]["all_cores"] = cpu_baseline_all_cores(w, x)
+    if FAILURES:
+        out["failures"] = FAILURES
     print(json.dumps(out))
+    if FAILURES:
+        print("[bench] FAILED: " + "; ".join(FAILURES), file=sys.stderr, flush=True)
+        sys.exit(1)
 
 
 if __name__ == "__main__":

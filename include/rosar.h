@@ -409,8 +409,10 @@ rosar_status rosar_batch_autotune(const rosar_rotation_desc* descs, int32_t n, i
  * sparse kernel, multiplies and accumulates, and transforms back (mixed-radix FFTs of length N
  * in LDS, float32).  It equals the direct sum up to float32 rounding, not bit for bit.  It
  * needs N = 2^a 3^b 5^c <= 8192 and the taps of a range row on at most 32 bin rows.  The plan
- * owns the band-row spectra (l_count x N x 8 bytes), a twiddle table and per-row tap lists, so
- * runs of one such plan must not overlap (runs on one stream are ordered). */
+ * owns the band-row spectra (l_count x N x 8 bytes), a twiddle table and per-row tap lists.  Every
+ * rosar_sparse_plan_run writes the band-row spectra into that one buffer, so runs of one
+ * fast-convolution plan through rosar_sparse_plan_run must not overlap (runs on one stream are
+ * ordered); rosar_sparse_plan_run_workspace gives each run its own spectrum buffer. */
 typedef struct rosar_sparse_plan rosar_sparse_plan;
 
 /* Validates the arguments as rosar_sparse_filter does and enqueues the table kernel on
@@ -437,6 +439,19 @@ rosar_status rosar_sparse_plan_create(const rosar_geometry* geom, const rosar_po
  * must be used on the device it was created on.  Safe to capture in a HIP graph. */
 rosar_status rosar_sparse_plan_run(const rosar_sparse_plan* plan, const rosar_rc_view* rc, void* image,
                                    rosar_stream stream);
+/* Device workspace, in bytes, that one rosar_sparse_plan_run_workspace call of `plan` uses:
+ * the band-row spectra (l_count x N x 8) for the fast convolution, 0 for the direct variant.
+ * Errors: INVALID_ARG for NULL arguments. */
+rosar_status rosar_sparse_plan_workspace_size(const rosar_sparse_plan* plan, size_t* bytes);
+/* rosar_sparse_plan_run with the band-row spectra in a caller-owned workspace (at least
+ * rosar_sparse_plan_workspace_size bytes, 256-byte aligned, contents undefined on entry and
+ * exit) instead of the plan's own buffer.  Runs of one fast-convolution plan that use distinct
+ * workspaces may overlap (several streams, parallel branches of a graph): the plan's other
+ * buffers are only read by a run.  workspace NULL uses the plan's buffer, as
+ * rosar_sparse_plan_run does; the direct variant ignores the workspace.
+ * Errors: as rosar_sparse_plan_run; ROSAR_ERR_WORKSPACE for a misaligned or short workspace. */
+rosar_status rosar_sparse_plan_run_workspace(const rosar_sparse_plan* plan, const rosar_rc_view* rc, void* image,
+                                             void* workspace, size_t workspace_bytes, rosar_stream stream);
 /* Frees the plan's tables (NULL is a no-op).  No run of the plan may be pending. */
 void rosar_sparse_plan_destroy(rosar_sparse_plan* plan);
 /* Project autotuner for plans: for every plan launch shape the layout admits, builds the tap

@@ -88,6 +88,9 @@ PROTOTYPES = [
                                           _P(Tile), C.c_void_p, _P(C.c_void_p)]),
     ("rosar_sparse_plan_run", C.c_int, [C.c_void_p, _P(RcView), C.c_void_p, C.c_void_p]),
     ("rosar_sparse_plan_destroy", None, [C.c_void_p]),
+    ("rosar_sparse_plan_workspace_size", C.c_int, [C.c_void_p, _P(C.c_size_t)]),
+    ("rosar_sparse_plan_run_workspace", C.c_int, [C.c_void_p, _P(RcView), C.c_void_p, C.c_void_p, C.c_size_t,
+                                                 C.c_void_p]),
     ("rosar_sparse_filter_cartesian", C.c_int, [_P(Geometry), _P(PolarGrid), _P(CartGrid), _P(RcView),
                                                _P(SparseSet), C.c_int, C.c_void_p, C.c_void_p]),
     ("rosar_bp_time_domain", C.c_int, [_P(Geometry), _P(PolarGrid), C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32,

@@ -39,19 +39,38 @@ def _out(t, shape, dtype, device):
     return t
 
 
-def _shape(t, shape, name):
-    """Raises unless tensor t (if given) has exactly `shape`: the kernels read and write by the
-    sizes the geometry and grid give, so a smaller tensor would be overrun."""
-    if t is not None and tuple(t.shape) != tuple(shape):
-        raise ValueError(f"{name} must have shape {tuple(shape)} (got {tuple(t.shape)})")
+def _is_gpu(t) -> bool:
+    return t.is_cuda
 
 
 def _need_gpu(*tensors):
     for t in tensors:
-        if t is not None and not t.is_cuda:
+        if t is not None and not _is_gpu(t):
             raise ValueError("librosar operates on GPU tensors only (got a CPU tensor)")
         if t is not None and not t.is_contiguous():
             raise ValueError("librosar needs contiguous tensors")
+
+
+def _arg(t, name, dtype, shape=None, copy=False):
+    """Checks an input tensor before any launch, since the C ABI sees only its pointer: element
+    type and shape as the kernel reads them, then that it lives on a GPU (a host pointer would
+    fault the kernel), then contiguity (copy=True makes a contiguous copy instead).  None passes
+    through."""
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor (got {type(t).__name__})")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype} (got {t.dtype})")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)} (got {tuple(t.shape)})")
+    if not _is_gpu(t):
+        raise ValueError(f"{name} must be a GPU tensor (got one on {t.device})")
+    if copy:
+        return t.contiguous()
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return t
 
 
 @dataclass
@@ -66,6 +85,13 @@ class RangeCompressed:
     scale: float = 1.0
 
     def view(self) -> L.RcView:
+        want = {"c64": torch.complex64, "f16": torch.float16, "bf16": torch.bfloat16}.get(self.dtype)
+        if want is None:
+            raise ValueError(f"unknown band storage type {self.dtype!r}")
+        if self.data.dtype != want or (self.dtype != "c64" and self.data.shape[-1] != 2):
+            raise TypeError(f"a {self.dtype} band needs a {want} tensor"
+                            f"{'' if self.dtype == 'c64' else ' with a trailing (re, im) dimension'}"
+                            f" (got {self.data.dtype} {tuple(self.data.shape)})")
         _need_gpu(self.data)
         need = self.l_count * self.ld * (8 if self.dtype == "c64" else 4)
         if self.data.numel() * self.data.element_size() < need:
@@ -96,13 +122,8 @@ def range_compress(geom, raw: torch.Tensor, window: torch.Tensor | None, l_lo: i
                    halo: int = 0, dtype: str = "c64", scale: float = 1.0,
                    out: RangeCompressed | None = None) -> RangeCompressed:
     """Windowed range FFT of every pulse (eq. 38), band [l_lo, l_lo+l_count) stored transposed."""
-    _need_gpu(raw, window)
-    if raw.dtype != torch.complex64:
-        raise TypeError("raw must be complex64 [N, M]")
-    if window is not None and window.dtype != torch.float32:
-        raise TypeError("window must be float32 [M]")
-    _shape(raw, (geom.n_pulses, geom.n_fast), "raw")
-    _shape(window, (geom.n_fast,), "window")
+    _arg(raw, "raw", torch.complex64, (geom.n_pulses, geom.n_fast))
+    _arg(window, "window", torch.float32, (geom.n_fast,))
     if out is None:
         out = empty_rc(geom.n_pulses, l_lo, l_count, halo, dtype, scale, raw.device)
     elif out.l_lo != l_lo or out.l_count != l_count:
@@ -116,19 +137,19 @@ def range_compress(geom, raw: torch.Tensor, window: torch.Tensor | None, l_lo: i
 
 
 def _set(offsets: torch.Tensor, weights: torch.Tensor, window: int, rows: int | None = None) -> L.SparseSet:
-    _need_gpu(offsets, weights)
-    if rows is not None and offsets.dim() == 2 and offsets.shape[0] != rows:
-        raise ValueError(f"offsets and weights need one row per range row ({rows}, got {offsets.shape[0]})")
     if offsets.dtype != torch.int32 or offsets.dim() != 2:
         raise TypeError("offsets must be int32 [n_range, K]")
-    if weights.dtype == torch.complex64:
+    if rows is not None and offsets.shape[0] != rows:
+        raise ValueError(f"offsets and weights need one row per range row ({rows}, got {offsets.shape[0]})")
+    if weights.dtype == torch.complex64 and weights.dim() == 2:
         wdt = L.C64
-    elif weights.dtype == torch.float16 and weights.shape[-1] == 2:
+    elif weights.dtype == torch.float16 and weights.dim() == 3 and weights.shape[-1] == 2:
         wdt = L.C16_F16
     else:
         raise TypeError("weights must be complex64 [n_range, K] or float16 [n_range, K, 2]")
     if tuple(weights.shape[:2]) != tuple(offsets.shape):
         raise ValueError("weights and offsets shapes differ")
+    _need_gpu(offsets, weights)
     return L.SparseSet(int(offsets.shape[1]), int(window), offsets.data_ptr(), weights.data_ptr(), wdt, 0)
 
 
@@ -142,9 +163,9 @@ def sparse_filter(geom, grid, rc: RangeCompressed, offsets: torch.Tensor, weight
                   out: torch.Tensor | None = None, tile: tuple[int, int, int] | None = None) -> torch.Tensor:
     """Sparse-aperture azimuth filter (Algorithm 2 / eq. 43) -> complex64 image [n_range, n_az]."""
     s = _set(offsets, weights, window, grid.n_range)
-    _need_gpu(dphi, dpsi, rc.data)
-    _shape(dphi, (geom.n_pulses,), "dphi")
-    _shape(dpsi, (geom.n_pulses,), "dpsi")
+    _arg(dphi, "dphi", torch.float32, (geom.n_pulses,))
+    _arg(dpsi, "dpsi", torch.float32, (geom.n_pulses,))
+    _need_gpu(rc.data)
     out = _out(out, (grid.n_range, grid.n_az), torch.complex64, rc.data.device)
     g, p, v = L.geometry(geom), L.polar_grid(grid), rc.view()
     t = None if tile is None else L.Tile(tile[0], tile[1], tile[2], 0)
@@ -164,10 +185,8 @@ def bp_workspace_bytes(geom) -> int:
 def bp_full(geom, grid, rc: RangeCompressed, angles: torch.Tensor | None = None, interp: str = "nearest",
             out: torch.Tensor | None = None, workspace: torch.Tensor | None = None) -> torch.Tensor:
     """Full-aperture back-projection (FFT+BPA) -> complex64 image [n_range, n_az]."""
-    _need_gpu(angles, rc.data)
-    if angles is not None and angles.dtype != torch.float64:
-        raise TypeError("angles must be float64 [N]")
-    _shape(angles, (geom.n_pulses,), "angles")
+    _arg(angles, "angles", torch.float64, (geom.n_pulses,))
+    _need_gpu(rc.data)
     dev = rc.data.device
     out = _out(out, (grid.n_range, grid.n_az), torch.complex64, dev)
     nbytes = bp_workspace_bytes(geom)
@@ -196,10 +215,10 @@ def sparse_filter_backward(geom, grid, rc: RangeCompressed, offsets, weights, wi
     grad_dpsi f32 [N] | None) for grad_image = dL/dRe(I) + j dL/dIm(I).  `out` may supply the three
     output tensors (entries None for gradients not wanted)."""
     s = _set(offsets, weights, window, grid.n_range)
-    _need_gpu(grad_image, dphi, dpsi)
-    _shape(grad_image, (grid.n_range, grid.n_az), "grad_image")
-    _shape(dphi, (geom.n_pulses,), "dphi")
-    _shape(dpsi, (geom.n_pulses,), "dpsi")
+    _arg(grad_image, "grad_image", torch.complex64, (grid.n_range, grid.n_az))
+    _arg(dphi, "dphi", torch.float32, (geom.n_pulses,))
+    _arg(dpsi, "dpsi", torch.float32, (geom.n_pulses,))
+    _need_gpu(rc.data)
     dev = grad_image.device
     if out is not None:
         gw, gd, gp = out
@@ -263,6 +282,9 @@ class SparseFilterBandFn(torch.autograd.Function):
     @staticmethod
     def forward(ctx, band, geom, grid, l_lo, offsets, weights, window, interp):
         n = geom.n_pulses
+        if band.dim() != 2:
+            raise ValueError("band must be complex64 [l_count, N]")
+        _arg(band, "band", torch.complex64, (band.shape[0], n), copy=True)
         halo = window // 2
         rc = empty_rc(n, l_lo, band.shape[0], halo=halo, device=band.device)
         b = band.detach().contiguous()
@@ -316,10 +338,10 @@ class Rotation:
     image: torch.Tensor
 
     def desc(self) -> L.RotationDesc:
-        _need_gpu(self.raw, self.window, self.offsets, self.weights, self.image, self.rc.data)
-        _shape(self.raw, (self.geom.n_pulses, self.geom.n_fast), "raw")
-        _shape(self.window, (self.geom.n_fast,), "window")
-        _shape(self.image, (self.grid.n_range, self.grid.n_az), "image")
+        _arg(self.raw, "raw", torch.complex64, (self.geom.n_pulses, self.geom.n_fast))
+        _arg(self.window, "window", torch.float32, (self.geom.n_fast,))
+        _arg(self.image, "image", torch.complex64, (self.grid.n_range, self.grid.n_az))
+        _need_gpu(self.offsets, self.weights, self.rc.data)
         self.rc.view()   # band size check
         if self.rc.dtype != "c64" or self.weights.dtype != torch.complex64:
             raise TypeError("batched rotations use complex64 data and weights")
@@ -426,14 +448,11 @@ def bp_cartesian(geom, cart, rc: RangeCompressed, angles: torch.Tensor | None = 
                  out: torch.Tensor | None = None) -> torch.Tensor:
     """Full-aperture back-projection for targets on the Cartesian lattice `cart` (nx, ny, x0_m,
     y0_m, dx_m, dy_m), with the given pulse angles (nominal if None); returns [ny, nx] complex64."""
+    angles = _arg(angles, "angles", torch.float64, (geom.n_pulses,), copy=True)
     _need_gpu(rc.data)
     out = _out(out, (cart.ny, cart.nx), torch.complex64, rc.data.device)
     g, v = L.geometry(geom), rc.view()
     c = L.CartGrid(int(cart.nx), int(cart.ny), float(cart.x0_m), float(cart.y0_m), float(cart.dx_m), float(cart.dy_m))
-    if angles is not None:
-        angles = angles.contiguous()
-        if angles.dtype != torch.float64 or angles.numel() != geom.n_pulses:
-            raise ValueError("angles must be float64 [n_pulses]")
     L.check(L.lib().rosar_bp_cartesian(C.byref(g), C.byref(c), C.byref(v), None if angles is None else _ptr(angles),
                                        L.INTERP_CODES[interp], _ptr(out), _stream(rc.data.device)),
             "rosar_bp_cartesian")
@@ -457,18 +476,13 @@ def bp_time_domain(geom, grid, raw: torch.Tensor, window: torch.Tensor | None = 
                    rows: tuple[int, int] | None = None, out: torch.Tensor | None = None) -> torch.Tensor:
     """Conventional time-domain BPA on the raw samples (exact beat frequency per pixel and
     pulse) for grid rows [first, first + count) (all rows if None); returns [count, n_az]."""
-    _need_gpu(raw, window)
-    _shape(raw, (geom.n_pulses, geom.n_fast), "raw")
-    _shape(window, (geom.n_fast,), "window")
-    if angles is not None and (angles.dtype != torch.float64 or tuple(angles.shape) != (geom.n_pulses,)):
-        raise ValueError("angles must be float64 [n_pulses]")
+    raw = _arg(raw, "raw", torch.complex64, (geom.n_pulses, geom.n_fast), copy=True)
+    window = _arg(window, "window", torch.float32, (geom.n_fast,), copy=True)
+    angles = _arg(angles, "angles", torch.float64, (geom.n_pulses,), copy=True)
     first, count = (0, grid.n_range) if rows is None else rows
     out = _out(out, (count, grid.n_az), torch.complex64, raw.device)
     g, p = L.geometry(geom), L.polar_grid(grid)
-    raw = raw.contiguous()
-    L.check(L.lib().rosar_bp_time_domain(C.byref(g), C.byref(p), _ptr(raw),
-                                         None if window is None else _ptr(window.contiguous()),
-                                         None if angles is None else _ptr(angles.contiguous()), first, count,
+    L.check(L.lib().rosar_bp_time_domain(C.byref(g), C.byref(p), _ptr(raw), _ptr(window), _ptr(angles), first, count,
                                          _ptr(out), _stream(raw.device)), "rosar_bp_time_domain")
     return out
 
@@ -477,16 +491,13 @@ def sas_time_domain(geom, grid, raw: torch.Tensor, offsets, weights, window_w, w
                     rows: tuple[int, int] | None = None, out: torch.Tensor | None = None) -> torch.Tensor:
     """Sparse-aperture filter on the raw samples (exact beat frequency per tap) for grid rows
     [first, first + count) (all rows if None); returns [count, n_az]."""
-    _need_gpu(raw, window)
-    _shape(raw, (geom.n_pulses, geom.n_fast), "raw")
-    _shape(window, (geom.n_fast,), "window")
+    raw = _arg(raw, "raw", torch.complex64, (geom.n_pulses, geom.n_fast), copy=True)
+    window = _arg(window, "window", torch.float32, (geom.n_fast,), copy=True)
     first, count = (0, grid.n_range) if rows is None else rows
     out = _out(out, (count, grid.n_az), torch.complex64, raw.device)
     s = _set(offsets, weights, window_w, grid.n_range)
     g, p = L.geometry(geom), L.polar_grid(grid)
-    raw = raw.contiguous()
-    L.check(L.lib().rosar_sas_time_domain(C.byref(g), C.byref(p), _ptr(raw),
-                                          None if window is None else _ptr(window.contiguous()), C.byref(s), first,
+    L.check(L.lib().rosar_sas_time_domain(C.byref(g), C.byref(p), _ptr(raw), _ptr(window), C.byref(s), first,
                                           count, _ptr(out), _stream(raw.device)), "rosar_sas_time_domain")
     return out
 
@@ -495,10 +506,9 @@ def delta_r(geom, grid, window: int, deltas: torch.Tensor, quantile: float = 0.9
             samples: torch.Tensor | None = None, out: torch.Tensor | None = None):
     """Monte-Carlo Delta_R per range row (eq. 37): `deltas` [window, S] float64 angle errors (draw
     minor), shared by every row.  Returns (delta_r [n_range], samples [n_range, S]), float64."""
-    _need_gpu(deltas)
-    if deltas.dtype != torch.float64 or deltas.dim() != 2 or deltas.shape[0] != window:
-        raise ValueError(f"deltas must be float64 [window={window}, S], got {tuple(deltas.shape)} {deltas.dtype}")
-    deltas = deltas.contiguous()
+    if not isinstance(deltas, torch.Tensor) or deltas.dim() != 2:
+        raise ValueError("deltas must be a float64 [window, S] tensor")
+    deltas = _arg(deltas, "deltas", torch.float64, (window, deltas.shape[1]), copy=True)
     n_s = deltas.shape[1]
     dev = deltas.device
     samples = _out(samples, (grid.n_range, n_s), torch.float64, dev)
@@ -515,18 +525,14 @@ def beampattern(geom, grid, offsets, weights, window: int, angles: torch.Tensor,
     """|w^H a(phi; R)| of each row's sparse weights at `angles` (float64 radians from the pixel's
     direction; angles[0] the main lobe) and the per-row worst-case summary {main, max side,
     (side + Delta_R)^2 / (main - Delta_R)^2}.  Returns (pattern [n_range, A], summary [n_range, 3])."""
-    _need_gpu(angles)
-    if angles.dtype != torch.float64 or angles.dim() != 1:
+    if not isinstance(angles, torch.Tensor) or angles.dim() != 1:
         raise ValueError("angles must be a float64 vector")
-    angles = angles.contiguous()
+    angles = _arg(angles, "angles", torch.float64, copy=True)
+    delta_r = _arg(delta_r, "delta_r", torch.float64, (grid.n_range,), copy=True)
     dev = angles.device
     s = _set(offsets, weights, window, grid.n_range)
     pattern = _out(pattern, (grid.n_range, angles.numel()), torch.float64, dev)
     summary = _out(summary, (grid.n_range, 3), torch.float64, dev)
-    if delta_r is not None:
-        delta_r = delta_r.contiguous()
-        if delta_r.dtype != torch.float64 or delta_r.shape != (grid.n_range,):
-            raise ValueError("delta_r must be float64 [n_range]")
     g, p = L.geometry(geom), L.polar_grid(grid)
     L.check(L.lib().rosar_beampattern(C.byref(g), C.byref(p), C.byref(s), _ptr(angles), angles.numel(),
                                       None if delta_r is None else _ptr(delta_r), _ptr(pattern), _ptr(summary),
@@ -540,8 +546,7 @@ def sparse_filter_adjoint_band(geom, grid, layout: RangeCompressed, offsets, wei
     """Gradient of a real loss with respect to the band read by the plain sparse filter,
     A^H grad_image (grad_image = dL/dRe(I) + j dL/dIm(I)).  `layout` gives the band rows; returns
     [l_count, n_pulses] complex64 (the band without its halo copies)."""
-    _need_gpu(grad_image)
-    _shape(grad_image, (grid.n_range, grid.n_az), "grad_image")
+    grad_image = _arg(grad_image, "grad_image", torch.complex64, (grid.n_range, grid.n_az), copy=True)
     s = _set(offsets, weights, window, grid.n_range)
     g, p, v = L.geometry(geom), L.polar_grid(grid), layout.view()
     dev = grad_image.device
@@ -554,7 +559,7 @@ def sparse_filter_adjoint_band(geom, grid, layout: RangeCompressed, offsets, wei
         workspace = torch.empty(int(need.value), dtype=torch.uint8, device=dev)
     _need_gpu(workspace)   # its size is checked by the library
     L.check(L.lib().rosar_sparse_filter_adjoint_band(C.byref(g), C.byref(p), C.byref(v), C.byref(s),
-                                                     L.INTERP_CODES[interp], _ptr(grad_image.contiguous()), _ptr(out),
+                                                     L.INTERP_CODES[interp], _ptr(grad_image), _ptr(out),
                                                      _ptr(workspace), workspace.numel(), _stream(dev)),
             "rosar_sparse_filter_adjoint_band")
     return out
@@ -569,7 +574,8 @@ class SparsePlan:
     and each run() computes the image rosar_sparse_filter gives with that launch shape, bit for
     bit.  tile = "fastconv": the same sum as an azimuth fast convolution (FFTs of the band rows
     and of each row's sparse kernels); equal to the direct sum up to float32 rounding.  Runs of
-    one fast-convolution plan share its spectrum buffer: do not overlap them."""
+    one fast-convolution plan without a workspace share the plan's spectrum buffer: do not
+    overlap them; give overlapping runs a workspace each (run(..., workspace=))."""
 
     def __init__(self, geom, grid, layout: RangeCompressed, offsets, weights, window, interp: str = "nearest",
                  tile: tuple[int, int] | str | None = None):
@@ -589,12 +595,27 @@ class SparsePlan:
         self.device = layout.data.device
         self._keep = (offsets, weights)
 
-    def run(self, rc: RangeCompressed, out: torch.Tensor | None = None) -> torch.Tensor:
-        _need_gpu(rc.data)
+    def workspace_bytes(self) -> int:
+        """Bytes of the per-run workspace run(..., workspace=) takes (0 for the direct variant)."""
+        n = C.c_size_t(0)
+        L.check(L.lib().rosar_sparse_plan_workspace_size(self._h, C.byref(n)), "rosar_sparse_plan_workspace_size")
+        return int(n.value)
+
+    def run(self, rc: RangeCompressed, out: torch.Tensor | None = None,
+            workspace: torch.Tensor | None = None) -> torch.Tensor:
+        """The plan's image of `rc`.  workspace: a device buffer of workspace_bytes() for the
+        fast convolution's band-row spectra, so that runs with distinct workspaces may overlap;
+        None uses the plan's own buffer (runs must then not overlap)."""
+        _need_gpu(rc.data, workspace)
         out = _out(out, (self.grid.n_range, self.grid.n_az), torch.complex64, rc.data.device)
         v = rc.view()
-        L.check(L.lib().rosar_sparse_plan_run(self._h, C.byref(v), _ptr(out), _stream(rc.data.device)),
-                "rosar_sparse_plan_run")
+        if workspace is None:
+            L.check(L.lib().rosar_sparse_plan_run(self._h, C.byref(v), _ptr(out), _stream(rc.data.device)),
+                    "rosar_sparse_plan_run")
+        else:
+            L.check(L.lib().rosar_sparse_plan_run_workspace(self._h, C.byref(v), _ptr(out), _ptr(workspace),
+                                                            workspace.numel() * workspace.element_size(),
+                                                            _stream(rc.data.device)), "rosar_sparse_plan_run_workspace")
         return out
 
     def close(self):

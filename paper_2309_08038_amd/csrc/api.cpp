@@ -751,10 +751,14 @@ rosar_status rosar_sparse_plan_create(const rosar_geometry* geom, const rosar_po
   return ROSAR_OK;
 }
 
-rosar_status rosar_sparse_plan_run(const rosar_sparse_plan* plan, const rosar_rc_view* rc, void* image,
-                                   rosar_stream stream) {
-  rosar::clear_error();
-  if (!plan) return fail(ROSAR_ERR_INVALID_ARG, "plan is NULL");
+}  // extern "C"
+
+namespace {
+
+// A run of the plan; for the fast convolution `spec` is the band-row spectrum buffer (NULL: the
+// plan's own).
+rosar_status plan_run(const rosar_sparse_plan* plan, const rosar_rc_view* rc, void* image, float2* spec,
+                      rosar_stream stream) {
   if (!rc) return fail(ROSAR_ERR_INVALID_ARG, "rc view is NULL");
   const rosar_rc_view& v = plan->view;
   if (rc->dtype != v.dtype || rc->l_lo != v.l_lo || rc->l_count != v.l_count || rc->halo != v.halo ||
@@ -771,9 +775,41 @@ rosar_status rosar_sparse_plan_run(const rosar_sparse_plan* plan, const rosar_rc
   a.image = reinterpret_cast<float2*>(image);
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   if (plan->variant == 3)
-    return from_hip(rosar::launch_fc_run(a, plan->fc, plan->tabs, plan->tw, plan->spec, plan->gspec, s),
+    return from_hip(rosar::launch_fc_run(a, plan->fc, plan->tabs, plan->tw, spec ? spec : plan->spec, plan->gspec, s),
                     "fast convolution launch");
   return from_hip(rosar::launch_sparse_planned(a, plan->layout, plan->tabs, s), "sparse plan launch");
+}
+
+}  // namespace
+
+extern "C" {
+
+rosar_status rosar_sparse_plan_run(const rosar_sparse_plan* plan, const rosar_rc_view* rc, void* image,
+                                   rosar_stream stream) {
+  rosar::clear_error();
+  if (!plan) return fail(ROSAR_ERR_INVALID_ARG, "plan is NULL");
+  return plan_run(plan, rc, image, nullptr, stream);
+}
+
+rosar_status rosar_sparse_plan_workspace_size(const rosar_sparse_plan* plan, size_t* bytes) {
+  rosar::clear_error();
+  if (!plan || !bytes) return fail(ROSAR_ERR_INVALID_ARG, "plan or bytes is NULL");
+  *bytes = plan->variant == 3 ? rosar::fc_spectrum_bytes(plan->a) : 0;
+  return ROSAR_OK;
+}
+
+rosar_status rosar_sparse_plan_run_workspace(const rosar_sparse_plan* plan, const rosar_rc_view* rc, void* image,
+                                             void* workspace, size_t workspace_bytes, rosar_stream stream) {
+  rosar::clear_error();
+  if (!plan) return fail(ROSAR_ERR_INVALID_ARG, "plan is NULL");
+  if (workspace && plan->variant == 3) {
+    const size_t need = rosar::fc_spectrum_bytes(plan->a);
+    if (!aligned(workspace, 256) || workspace_bytes < need)
+      return fail(ROSAR_ERR_WORKSPACE, "workspace must be 256-byte aligned and >= %zu bytes (got %zu)", need,
+                  workspace_bytes);
+  }
+  return plan_run(plan, rc, image, plan->variant == 3 && workspace ? reinterpret_cast<float2*>(workspace) : nullptr,
+                  stream);
 }
 
 void rosar_sparse_plan_destroy(rosar_sparse_plan* plan) { free_plan(plan); }

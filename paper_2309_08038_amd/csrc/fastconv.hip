@@ -104,7 +104,9 @@ __global__ __launch_bounds__(kFftThreads) void fc_spectrum_kernel(View y, FftFac
 
 // G of one (range row, bin row) pair: the row's entries on that bin row scattered into a
 // zeroed LDS row (entries that share an azimuth index add up, as in the direct sum), then the
-// unnormalised inverse-direction transform.
+// unnormalised inverse-direction transform.  One thread adds the entries in table order, so a
+// repeated azimuth index sums in a fixed order and every plan build gives the same bits (the
+// scatter is K or 2K additions, once per plan).
 __global__ __launch_bounds__(kFftThreads) void fc_kernel_spectra_kernel(FftFactors f, const char* __restrict__ tabs,
                                                                         int row_bytes, const int2* __restrict__ pairs,
                                                                         const float2* __restrict__ tw,
@@ -118,14 +120,15 @@ __global__ __launch_bounds__(kFftThreads) void fc_kernel_spectra_kernel(FftFacto
   mfft::load_twiddles(s_tw, tw, n, tid);
   const int4* blk = reinterpret_cast<const int4*>(tabs + (size_t)pr.x * row_bytes);
   const int ne = blk[0].z;
-  float* bufs = reinterpret_cast<float*>(buf);
   for (int i = tid; i < n; i += kFftThreads) buf[i] = make_float2(0.f, 0.f);
   __syncthreads();
-  for (int e = tid; e < ne; e += kFftThreads) {
-    const int4 t = blk[1 + e];
-    if (t.y == pr.y) {
-      atomicAdd(&bufs[2 * t.x], __int_as_float(t.z));
-      atomicAdd(&bufs[2 * t.x + 1], __int_as_float(t.w));
+  if (tid == 0) {
+    for (int e = 0; e < ne; ++e) {
+      const int4 t = blk[1 + e];
+      if (t.y == pr.y) {
+        buf[t.x].x += __int_as_float(t.z);
+        buf[t.x].y += __int_as_float(t.w);
+      }
     }
   }
   __syncthreads();

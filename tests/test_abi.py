@@ -494,3 +494,170 @@ def test_output_buffer_checks():
                 torch.empty((6, 4), dtype=torch.complex64).t()):
         with pytest.raises(ValueError):
             _out(bad, (4, 6), torch.complex64, "cpu")
+
+
+# ----------------------------------------------------------------- binding argument checks
+def test_arg_checks():
+    """_arg: element type (TypeError), shape, device and contiguity (ValueError); None passes."""
+    import torch
+    from paper_2309_08038_amd.api import _arg
+    assert _arg(None, "x", torch.float32, (3,)) is None
+    with pytest.raises(TypeError):
+        _arg(torch.zeros(3, dtype=torch.float64), "x", torch.float32, (3,))
+    with pytest.raises(ValueError, match="shape"):
+        _arg(torch.zeros(4, dtype=torch.float32), "x", torch.float32, (3,))
+    with pytest.raises(ValueError, match="GPU"):
+        _arg(torch.zeros(3, dtype=torch.float32), "x", torch.float32, (3,))
+    with pytest.raises(TypeError):
+        _arg([0.0, 1.0], "x", torch.float32)
+
+
+class _Case:
+    """Host tensors of the small workload's shapes, standing in for device tensors."""
+
+    def __init__(self):
+        import torch
+        import synth
+        import paper_2309_08038_amd as rs
+        w = synth.small()
+        self.g, self.grid, self.win = w.geometry, w.grid, w.sparse.window
+        n, m, rows, k = self.g.n_pulses, self.g.n_fast, self.grid.n_range, w.sparse.k
+        self.raw = torch.zeros((n, m), dtype=torch.complex64)
+        self.window = torch.ones(m, dtype=torch.float32)
+        self.rc = rs.RangeCompressed(torch.zeros((16, n + self.win), dtype=torch.complex64), "c64", 10, 16,
+                                     self.win // 2, n + self.win)
+        self.offsets = torch.zeros((rows, k), dtype=torch.int32)
+        self.weights = torch.zeros((rows, k), dtype=torch.complex64)
+        self.pulse_f32 = torch.zeros(n, dtype=torch.float32)
+        self.pulse_f64 = torch.zeros(n, dtype=torch.float64)
+        self.image = torch.zeros((rows, self.grid.n_az), dtype=torch.complex64)
+
+
+def _no_launch(monkeypatch, host=()):
+    """Every tensor counts as a device tensor except those in `host`, and any library call fails
+    the test: each rejection must come from the binding, before a launch."""
+    from paper_2309_08038_amd import api
+    ids = {id(t) for t in host}
+    monkeypatch.setattr(api, "_is_gpu", lambda t: id(t) not in ids)
+
+    def launched():
+        raise AssertionError("the library was called")
+    monkeypatch.setattr(L, "lib", launched)
+
+
+def test_binding_rejects_wrong_dtypes_before_launch(monkeypatch):
+    """Per-pulse arrays, gradient images and raw cubes of the wrong element type raise TypeError
+    (a float64 dphi would be read as float32 pairs; a float32 gradient image is half the bytes
+    the kernel reads)."""
+    import torch
+    import paper_2309_08038_amd as rs
+    c = _Case()
+    _no_launch(monkeypatch)
+    n = c.g.n_pulses
+    with pytest.raises(TypeError, match="dphi"):
+        rs.sparse_filter(c.g, c.grid, c.rc, c.offsets, c.weights, c.win, dphi=c.pulse_f64)
+    with pytest.raises(TypeError, match="dpsi"):
+        rs.sparse_filter(c.g, c.grid, c.rc, c.offsets, c.weights, c.win, dpsi=torch.zeros(n, dtype=torch.float16))
+    with pytest.raises(TypeError, match="grad_image"):
+        rs.sparse_filter_backward(c.g, c.grid, c.rc, c.offsets, c.weights, c.win, c.image.real.contiguous())
+    with pytest.raises(TypeError, match="dphi"):
+        rs.sparse_filter_backward(c.g, c.grid, c.rc, c.offsets, c.weights, c.win, c.image, dphi=c.pulse_f64)
+    with pytest.raises(TypeError, match="grad_image"):
+        rs.sparse_filter_adjoint_band(c.g, c.grid, c.rc, c.offsets, c.weights, c.win, c.image.real.contiguous())
+    with pytest.raises(TypeError, match="raw"):
+        rs.bp_time_domain(c.g, c.grid, c.raw.to(torch.complex128))
+    with pytest.raises(TypeError, match="raw"):
+        rs.sas_time_domain(c.g, c.grid, torch.zeros(c.raw.shape, dtype=torch.float32), c.offsets, c.weights, c.win)
+    with pytest.raises(TypeError, match="raw"):
+        rs.range_compress(c.g, c.raw.to(torch.complex128), c.window, 10, 16)
+    with pytest.raises(TypeError, match="angles"):
+        rs.bp_full(c.g, c.grid, c.rc, angles=c.pulse_f32)
+    with pytest.raises(TypeError, match="angles"):
+        rs.bp_time_domain(c.g, c.grid, c.raw, angles=c.pulse_f32)
+    with pytest.raises(TypeError, match="delta_r"):
+        rs.beampattern(c.g, c.grid, c.offsets, c.weights, c.win, torch.zeros(5, dtype=torch.float64),
+                       delta_r=torch.zeros(c.grid.n_range, dtype=torch.float32))
+    with pytest.raises(TypeError, match="band"):
+        bad = rs.RangeCompressed(c.rc.data.real.contiguous(), "c64", 10, 16, c.rc.halo, c.rc.ld)
+        rs.sparse_filter(c.g, c.grid, bad, c.offsets, c.weights, c.win)
+    with pytest.raises(TypeError, match="offsets"):
+        rs.sparse_filter(c.g, c.grid, c.rc, c.offsets.long(), c.weights, c.win)
+    with pytest.raises(TypeError, match="weights"):
+        rs.sparse_filter(c.g, c.grid, c.rc, c.offsets, c.weights.to(torch.complex128), c.win)
+
+
+def test_binding_rejects_wrong_shapes_before_launch(monkeypatch):
+    import torch
+    import paper_2309_08038_amd as rs
+    c = _Case()
+    _no_launch(monkeypatch)
+    n = c.g.n_pulses
+    with pytest.raises(ValueError, match="dphi"):
+        rs.sparse_filter(c.g, c.grid, c.rc, c.offsets, c.weights, c.win, dphi=torch.zeros(n - 1))
+    with pytest.raises(ValueError, match="grad_image"):
+        rs.sparse_filter_backward(c.g, c.grid, c.rc, c.offsets, c.weights, c.win, c.image[:-1].contiguous())
+    with pytest.raises(ValueError, match="raw"):
+        rs.range_compress(c.g, c.raw[:-1].contiguous(), c.window, 10, 16)
+    with pytest.raises(ValueError, match="window"):
+        rs.range_compress(c.g, c.raw, c.window[:-1].contiguous(), 10, 16)
+    with pytest.raises(ValueError, match="angles"):
+        rs.bp_cartesian(c.g, rs_cart(), c.rc, angles=torch.zeros(n + 1, dtype=torch.float64))
+    with pytest.raises(ValueError, match="one row per range row"):
+        rs.sparse_filter(c.g, c.grid, c.rc, c.offsets[:-1].contiguous(), c.weights[:-1].contiguous(), c.win)
+
+
+def rs_cart():
+    from types import SimpleNamespace
+    return SimpleNamespace(nx=8, ny=8, x0_m=0.0, y0_m=0.0, dx_m=0.1, dy_m=0.1)
+
+
+@pytest.mark.parametrize("entry", ["bp_full", "bp_cartesian", "bp_time_domain", "sparse_filter",
+                                   "sparse_filter_backward", "beampattern"])
+def test_binding_rejects_host_per_pulse_arrays(monkeypatch, entry):
+    """A per-pulse (or per-row) array left in host memory raises ValueError in the binding, every
+    other argument being a device tensor; nothing is launched."""
+    import torch
+    import paper_2309_08038_amd as rs
+    c = _Case()
+    host = {"bp_full": c.pulse_f64, "bp_cartesian": c.pulse_f64, "bp_time_domain": c.pulse_f64,
+            "sparse_filter": c.pulse_f32, "sparse_filter_backward": c.pulse_f32,
+            "beampattern": torch.zeros(c.grid.n_range, dtype=torch.float64)}[entry]
+    _no_launch(monkeypatch, host=[host])
+    call = {
+        "bp_full": lambda: rs.bp_full(c.g, c.grid, c.rc, angles=host),
+        "bp_cartesian": lambda: rs.bp_cartesian(c.g, rs_cart(), c.rc, angles=host),
+        "bp_time_domain": lambda: rs.bp_time_domain(c.g, c.grid, c.raw, angles=host),
+        "sparse_filter": lambda: rs.sparse_filter(c.g, c.grid, c.rc, c.offsets, c.weights, c.win, dphi=host),
+        "sparse_filter_backward": lambda: rs.sparse_filter_backward(c.g, c.grid, c.rc, c.offsets, c.weights, c.win,
+                                                                    c.image, dpsi=host),
+        "beampattern": lambda: rs.beampattern(c.g, c.grid, c.offsets, c.weights, c.win,
+                                              torch.zeros(5, dtype=torch.float64), delta_r=host),
+    }[entry]
+    with pytest.raises(ValueError, match="GPU"):
+        call()
+
+
+def test_binding_reaches_the_library_with_valid_arguments(monkeypatch):
+    """The same calls with every argument valid get past the binding's checks (to the patched
+    library), so the rejections above are the checks under test, not some other failure."""
+    import torch
+    import paper_2309_08038_amd as rs
+    c = _Case()
+    _no_launch(monkeypatch)
+    for call in (lambda: rs.sparse_filter(c.g, c.grid, c.rc, c.offsets, c.weights, c.win, dphi=c.pulse_f32),
+                 lambda: rs.bp_full(c.g, c.grid, c.rc, angles=c.pulse_f64),
+                 lambda: rs.bp_time_domain(c.g, c.grid, c.raw, angles=c.pulse_f64),
+                 lambda: rs.sparse_filter_adjoint_band(c.g, c.grid, c.rc, c.offsets, c.weights, c.win, c.image),
+                 lambda: rs.beampattern(c.g, c.grid, c.offsets, c.weights, c.win, torch.zeros(5, dtype=torch.float64),
+                                        delta_r=torch.zeros(c.grid.n_range, dtype=torch.float64))):
+        with pytest.raises(AssertionError, match="library was called"):
+            call()
+
+
+def test_plan_workspace_entry_points_validate(lib):
+    """The workspace queries and runs of a plan reject NULL arguments before any device work."""
+    n = C.c_size_t(7)
+    assert lib.rosar_sparse_plan_workspace_size(None, C.byref(n)) == L.ROSAR_ERR_INVALID_ARG
+    v = L.RcView(0x10000, L.C64, 0, 16, 0, 360, 1.0, 0)
+    assert lib.rosar_sparse_plan_run_workspace(None, C.byref(v), FAKE, FAKE, 1 << 20, None) == L.ROSAR_ERR_INVALID_ARG
+    assert "NULL" in lib.rosar_last_error().decode()

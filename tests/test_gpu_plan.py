@@ -317,6 +317,70 @@ def test_fastconv_graph_replay():
     plan.close()
 
 
+@pytest.mark.parametrize("interp", ["nearest", "linear"])
+def test_fastconv_parallel_runs_own_workspaces(interp):
+    """Rotation size: two runs of one fast-convolution plan on two different rotations, captured
+    on two streams as parallel branches of one graph, each with its own spectrum workspace: every
+    replay equals the eager images bit for bit (the runs share only what a run reads)."""
+    rs = need_gpu()
+    w, x = inputs("rotation")
+    rc1, off, wts = upload(rs, w, x)
+    x2 = synth.Inputs(**{**x.__dict__, "raw": np.roll(x.raw, 7, axis=0) * np.complex64(0.5 - 0.25j)})
+    rc2, _, _ = upload(rs, w, x2)
+    plan = rs.SparsePlan(w.geometry, w.grid, rc1, off, wts, w.sparse.window, interp=interp, tile="fastconv")
+    nbytes = plan.workspace_bytes()
+    assert nbytes == x.l_count * w.geometry.n_pulses * 8
+    ws = [torch.empty(nbytes, dtype=torch.uint8, device=rc1.data.device) for _ in range(2)]
+    log(f"fastconv parallel runs {interp}: eager references")
+    ref1, ref2 = plan.run(rc1), plan.run(rc2)
+    torch.cuda.synchronize()
+    ref1, ref2 = ref1.clone(), ref2.clone()
+    assert not torch.equal(ref1, ref2)
+    img1, img2 = torch.empty_like(ref1), torch.empty_like(ref2)
+    s, sa, sb = torch.cuda.Stream(), torch.cuda.Stream(), torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(graph, stream=s):
+            sa.wait_stream(s)
+            sb.wait_stream(s)
+            with torch.cuda.stream(sa):
+                plan.run(rc1, out=img1, workspace=ws[0])
+            with torch.cuda.stream(sb):
+                plan.run(rc2, out=img2, workspace=ws[1])
+            s.wait_stream(sa)
+            s.wait_stream(sb)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    for rep in range(3):
+        log(f"fastconv parallel runs {interp}: replay {rep}")
+        img1.zero_()
+        img2.zero_()
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(img1, ref1), ("first branch", rep)
+        assert torch.equal(img2, ref2), ("second branch", rep)
+        plan.run(rc2, out=img1)          # eager work between replays, on the plan's own buffer
+        torch.cuda.synchronize()
+    plan.close()
+
+
+def test_fastconv_plan_builds_identical():
+    """Two builds of the same fast-convolution plan give the same image bits (the kernel spectra
+    are accumulated in a fixed order)."""
+    rs = need_gpu()
+    w, x = inputs("small")
+    rc, off, wts = upload(rs, w, x)
+    imgs = []
+    for i in range(2):
+        log(f"fastconv plan build {i}")
+        plan = rs.SparsePlan(w.geometry, w.grid, rc, off, wts, w.sparse.window, interp="linear", tile="fastconv")
+        imgs.append(plan.run(rc).cpu())
+        plan.close()
+    assert torch.equal(imgs[0], imgs[1])
+
+
 @pytest.mark.parametrize("variant", ["fastconv-nearest", "fastconv-linear", "direct-linear", "direct-nearest"])
 def test_plan_runs_deterministic(variant):
     """Rotation size: repeated eager runs and graph replays of one plan give identical bits."""
