@@ -480,6 +480,74 @@ rosar_status rosar_autotune_sparse_filter(const rosar_geometry* geom, const rosa
                                           void* image, int32_t reps, rosar_tile* best,
                                           float* best_us, rosar_stream stream);
 
+/* ---------------------------------------------------------------- robust weight design
+ * Offline design of the sparse weights (Sec. III-A/B, Algorithm 1: FPP-SCA).  For every row i of
+ * `grid` (range R_i = r0 + i dr; n_az is not used) the candidates are the phase centres that
+ * see a target at the row's azimuth (eqs. 4-5): offsets o in [-h, h] with R cos(o 2 pi / N) > r.
+ * Steering vectors follow eq. 16 with the cosine pattern max(R cos D - r, 0) / R(D); the main
+ * lobe is the target direction, the side-lobe directions are spaced by d_angle over
+ * [D_min, -phi_mw] and [phi_mw, D_max].  From w_(0) = 1/sqrt(n), U'_(0) = |w_(0)^H a_m|, each of
+ * `iters` iterations solves the convex sub-problem of eq. 36 around the previous iterate
+ * (linearised C1, C2, C4 of eqs. 33-35; C3; C5 with U'_min = sqrt(u_min); slacks b, b1, b2 >= 0
+ * weighted by lambda_b) with the barrier method: Newton steps with a backtracking line search
+ * (ls_alpha, ls_beta; a step below ls_min ends a centring), at most max_newton per centring,
+ * centring stops at a Newton decrement^2 / 2 <= newton_tol, tau from tau0 multiplied by mu until
+ * the duality-gap bound m / tau < eps.  Entries with |w_k| < th are set to zero. */
+typedef struct {
+  int32_t iters, max_newton;
+  double th, phi_mw, d_angle, lam_b, eta, u_min, b_min;
+  double eps, mu, tau0, newton_tol, ls_alpha, ls_beta, ls_min;
+} rosar_sas_params;
+
+/* Workspace bytes of rosar_sas_design, and the largest candidate count of any row (the
+ * `window` the outputs need).  Errors: INVALID_ARG for NULL arguments, a bad geometry or grid,
+ * or parameters out of range (iters in [1, 1000], max_newton in [1, 1000], angles, eta, mu > 1,
+ * tau0 > 0, 0 < ls_alpha < 0.5, 0 < ls_beta < 1, eps > 0). */
+rosar_status rosar_sas_design_workspace_size(const rosar_geometry* geom, const rosar_polar_grid* grid,
+                                             const rosar_sas_params* params, size_t* bytes,
+                                             int32_t* max_candidates);
+/* Designs every row on the device, one workgroup per row, all iterations in one launch.
+ *   delta_r  [n_range] float64 (device): Delta_R of each row (eq. 37; rosar_delta_r).
+ *   offsets  [n_range][window] int32, weights [n_range][window] C64 (device, written): each
+ *            row's nonzero taps first, in candidate order (offset relative to the target's
+ *            pulse, weight applied conjugated as in eq. 43), zero-weight padding after them.
+ *   count    [n_range] int32 (device, written): nonzero taps per row.
+ *   history  [n_range][iters][6] float64 (device) or NULL: per iteration the objective
+ *            J = ||w||_1 + lambda_b (b + b1 + b2), U', b, b1, b2 and the Newton steps taken.
+ * A row whose taps are not all accepted (b + b1 + b2 >= b_min in the last iteration) still
+ * gets its weights; the caller checks the history.
+ * Errors: as the workspace query; INVALID_ARG for window below the largest candidate count,
+ * NULL or misaligned pointers; ROSAR_ERR_WORKSPACE for a short or misaligned workspace. */
+rosar_status rosar_sas_design(const rosar_geometry* geom, const rosar_polar_grid* grid,
+                              const rosar_sas_params* params, const double* delta_r, int32_t window,
+                              int32_t* offsets, void* weights, int32_t* count, double* history,
+                              void* workspace, size_t workspace_bytes, rosar_stream stream);
+
+/* ---------------------------------------------------------------- autotune cache
+ * The autotuners above (rosar_autotune_sparse_filter, rosar_sparse_plan_autotune,
+ * rosar_batch_autotune) first look their key up in the library's autotune cache and return a
+ * hit without timing anything; a miss is timed and stored.  A key is the device's architecture
+ * name (e.g. "gfx950") and the shape class that decides the winning launch shape: pulses, rows
+ * and their spacing, band layout and storage type, taps, window, weight type, interpolation
+ * (plans also the candidate mask; batches a hash of every rotation's sizes).  The cache is
+ * process-wide, behind one mutex, and mirrored to a JSON file:
+ * {"<key>": {"variant": v, "pixels_per_lane": p, "waves": w, "us": t}, ...}.  A store rereads
+ * the file, adds its entry and replaces the file through a temporary file and a rename, so
+ * processes sharing a file keep each other's entries and readers never see a partial file.
+ *
+ * rosar_autotune selects the cache file (NULL: no file, entries kept in memory only) and loads
+ * its entries; a missing or unparsable file reads as empty.  Without a call, the first cache
+ * use takes the file named by the ROSAR_AUTOTUNE_CACHE environment variable, if set.  Host
+ * only (no device work).  Errors: none (always ROSAR_OK). */
+rosar_status rosar_autotune(const char* cache_path);
+/* Looks `key` up: *found = 1 and the stored shape and time, or *found = 0.
+ * Errors: INVALID_ARG for a NULL argument. */
+rosar_status rosar_autotune_lookup(const char* key, rosar_tile* tile, float* us, int32_t* found);
+/* Stores a result under `key` (and in the file, if one is selected).
+ * Errors: INVALID_ARG for an empty or NULL key, a NULL tile, us < 0, or a file that cannot be
+ * written (the entry is still kept in memory). */
+rosar_status rosar_autotune_store(const char* key, const rosar_tile* tile, float us);
+
 #ifdef __cplusplus
 }
 #endif

@@ -50,6 +50,13 @@ class Tile(C.Structure):
                 ("reserved", C.c_int32)]
 
 
+class SasParams(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("max_newton", C.c_int32), ("th", C.c_double), ("phi_mw", C.c_double),
+                ("d_angle", C.c_double), ("lam_b", C.c_double), ("eta", C.c_double), ("u_min", C.c_double),
+                ("b_min", C.c_double), ("eps", C.c_double), ("mu", C.c_double), ("tau0", C.c_double),
+                ("newton_tol", C.c_double), ("ls_alpha", C.c_double), ("ls_beta", C.c_double), ("ls_min", C.c_double)]
+
+
 class RotationDesc(C.Structure):
     _fields_ = [("geom", Geometry), ("grid", PolarGrid), ("raw", C.c_void_p), ("window", C.c_void_p),
                 ("y_t", C.c_void_p), ("l_lo", C.c_int32), ("l_count", C.c_int32), ("halo", C.c_int32),
@@ -71,6 +78,10 @@ PROTOTYPES = [
     ("rosar_bp_full_workspace_size", C.c_int, [_P(Geometry), _P(C.c_size_t)]),
     ("rosar_bp_full", C.c_int, [_P(Geometry), _P(PolarGrid), _P(RcView), C.c_void_p, C.c_int, C.c_void_p,
                                C.c_void_p, C.c_size_t, C.c_void_p]),
+    ("rosar_sas_design_workspace_size", C.c_int, [_P(Geometry), _P(PolarGrid), _P(SasParams), _P(C.c_size_t),
+                                                  _P(C.c_int32)]),
+    ("rosar_sas_design", C.c_int, [_P(Geometry), _P(PolarGrid), _P(SasParams), C.c_void_p, C.c_int32, C.c_void_p,
+                                   C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),
     ("rosar_sparse_filter_backward_workspace_size", C.c_int, [_P(Geometry), _P(PolarGrid), _P(SparseSet),
                                                              _P(C.c_size_t)]),
     ("rosar_sparse_filter_backward", C.c_int, [_P(Geometry), _P(PolarGrid), _P(RcView), _P(SparseSet),
@@ -109,6 +120,9 @@ PROTOTYPES = [
                                                                   _P(SparseSet), C.c_int, _P(C.c_size_t)]),
     ("rosar_sparse_filter_adjoint_band", C.c_int, [_P(Geometry), _P(PolarGrid), _P(RcView), _P(SparseSet), C.c_int,
                                                   C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),
+    ("rosar_autotune", C.c_int, [C.c_char_p]),
+    ("rosar_autotune_lookup", C.c_int, [C.c_char_p, _P(Tile), _P(C.c_float), _P(C.c_int32)]),
+    ("rosar_autotune_store", C.c_int, [C.c_char_p, _P(Tile), C.c_float]),
     ("rosar_sparse_plan_autotune", C.c_int, [_P(Geometry), _P(PolarGrid), _P(RcView), _P(SparseSet), C.c_int,
                                             C.c_void_p, C.c_int32, C.c_int32, _P(Tile), _P(C.c_float),
                                             C.c_void_p]),

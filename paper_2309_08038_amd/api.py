@@ -7,7 +7,6 @@ are float16 / bfloat16 tensors with a trailing dimension of 2 (re, im).
 from __future__ import annotations
 
 import ctypes as C
-import json
 import os
 from dataclasses import dataclass
 
@@ -200,6 +199,55 @@ def bp_full(geom, grid, rc: RangeCompressed, angles: torch.Tensor | None = None,
     return out
 
 
+@dataclass
+class SasDesign:
+    """Result of the robust sparse-array synthesis (Algorithm 1) for every row of a polar grid:
+    offsets [rows, window] int32 and weights [rows, window] complex64 with each row's nonzero
+    taps first, count [rows] int32 of nonzero taps, history [rows, iters, 6] float64 (J, U',
+    b, b1, b2, Newton steps per iteration)."""
+    offsets: torch.Tensor
+    weights: torch.Tensor
+    count: torch.Tensor
+    history: torch.Tensor
+
+    def sparse_set(self):
+        """(offsets, weights) cut to the largest nonzero count K of any row (zero-weight
+        padding beyond a row's own count), contiguous, for sparse_filter / SparsePlan."""
+        k = max(int(self.count.max().item()), 1)
+        return self.offsets[:, :k].contiguous(), self.weights[:, :k].contiguous()
+
+
+def sas_params(iters=50, max_newton=50, th=1e-3, phi_mw=0.017453292519943295, d_angle=0.008726646259971648,
+               lam_b=50.0, eta=0.0005, u_min=5.0, b_min=1e-5, eps=1e-6, mu=8.0, tau0=1.0, newton_tol=1e-8,
+               ls_alpha=0.01, ls_beta=0.5, ls_min=1e-10) -> L.SasParams:
+    """Design parameters (defaults: the paper's Table V; barrier-method settings)."""
+    return L.SasParams(int(iters), int(max_newton), th, phi_mw, d_angle, lam_b, eta, u_min, b_min, eps, mu, tau0,
+                       newton_tol, ls_alpha, ls_beta, ls_min)
+
+
+def sas_design(geom, grid, delta_r: torch.Tensor, params: L.SasParams | None = None,
+               window: int | None = None) -> SasDesign:
+    """Robust sparse-array synthesis of every row of `grid` on the GPU (Algorithm 1 with eq. 36);
+    delta_r [rows] float64 on the device (rosar_delta_r)."""
+    params = sas_params() if params is None else params
+    _arg(delta_r, "delta_r", torch.float64, (grid.n_range,))
+    dev = delta_r.device
+    g, p = L.geometry(geom), L.polar_grid(grid)
+    nbytes, ncand = C.c_size_t(0), C.c_int32(0)
+    L.check(L.lib().rosar_sas_design_workspace_size(C.byref(g), C.byref(p), C.byref(params), C.byref(nbytes),
+                                                    C.byref(ncand)), "rosar_sas_design_workspace_size")
+    window = max(int(ncand.value), 1) if window is None else int(window)
+    offsets = torch.empty((grid.n_range, window), dtype=torch.int32, device=dev)
+    weights = torch.empty((grid.n_range, window), dtype=torch.complex64, device=dev)
+    count = torch.empty(grid.n_range, dtype=torch.int32, device=dev)
+    hist = torch.empty((grid.n_range, params.iters, 6), dtype=torch.float64, device=dev)
+    ws = torch.empty(max(int(nbytes.value), 1), dtype=torch.uint8, device=dev)
+    L.check(L.lib().rosar_sas_design(C.byref(g), C.byref(p), C.byref(params), _ptr(delta_r), window, _ptr(offsets),
+                                     _ptr(weights), _ptr(count), _ptr(hist), _ptr(ws), ws.numel(), _stream(dev)),
+            "rosar_sas_design")
+    return SasDesign(offsets, weights, count, hist)
+
+
 def backward_workspace_bytes(geom, grid, offsets, weights, window) -> int:
     g, p, s = L.geometry(geom), L.polar_grid(grid), _set(offsets, weights, window, grid.n_range)
     n = C.c_size_t(0)
@@ -359,40 +407,25 @@ def _descs(rotations):
     return arr
 
 
-def autotune_cache_key(arch: str, geom, grid, rc_dtype: str, l_count: int, k: int, window: int, w_dtype: int,
-                       interp: str, methods: str) -> str:
-    """Key of a plan-autotune result: the GPU architecture and the shape class that decides the
-    launch shape (pulses, rows, band rows, taps, window, storage and weight types, interpolation)."""
-    return (f"{arch}|plan|N={geom.n_pulses}|rows={grid.n_range}|band={l_count}|K={k}|W={window}|dt={rc_dtype}"
-            f"|wdt={w_dtype}|{interp}|{methods}")
+def autotune_cache(path: str | None) -> None:
+    """Selects the library's autotune cache file (None: no file; results then stay in memory for
+    the process).  The library's autotuners look their shape class up there before timing and
+    store what they time; without a call, the ROSAR_AUTOTUNE_CACHE environment variable names
+    the file."""
+    L.check(L.lib().rosar_autotune(None if path is None else os.fsencode(path)), "rosar_autotune")
 
 
-def autotune_cache_get(path: str, key: str):
-    """Cached (tile, microseconds) for `key`, or None (missing or unreadable file, no entry)."""
-    try:
-        with open(path) as f:
-            e = json.load(f).get(key)
-    except (OSError, ValueError):
-        return None
-    if not e:
-        return None
-    tile = e["tile"] if isinstance(e["tile"], str) else tuple(e["tile"])
-    return tile, float(e["us"])
+def autotune_lookup(key: str):
+    """(variant, pixels_per_lane, waves, microseconds) stored under `key`, or None."""
+    t, us, found = L.Tile(), C.c_float(0), C.c_int32(0)
+    L.check(L.lib().rosar_autotune_lookup(key.encode(), C.byref(t), C.byref(us), C.byref(found)),
+            "rosar_autotune_lookup")
+    return (t.variant, t.pixels_per_lane, t.waves, float(us.value)) if found.value else None
 
 
-def autotune_cache_put(path: str, key: str, tile, us: float) -> None:
-    """Store a result, keeping the other entries; written to a temporary file and renamed, so a
-    reader never sees a partial file."""
-    try:
-        with open(path) as f:
-            d = json.load(f)
-    except (OSError, ValueError):
-        d = {}
-    d[key] = {"tile": tile if isinstance(tile, str) else list(tile), "us": us}
-    tmp = f"{path}.{os.getpid()}.tmp"
-    with open(tmp, "w") as f:
-        json.dump(d, f, indent=1, sort_keys=True)
-    os.replace(tmp, path)
+def autotune_store(key: str, variant: int, pixels_per_lane: int, waves: int, us: float) -> None:
+    t = L.Tile(int(variant), int(pixels_per_lane), int(waves), 0)
+    L.check(L.lib().rosar_autotune_store(key.encode(), C.byref(t), float(us)), "rosar_autotune_store")
 
 
 def sparse_plan_autotune(geom, grid, rc: RangeCompressed, offsets, weights, window, interp: str = "nearest",
@@ -400,21 +433,15 @@ def sparse_plan_autotune(geom, grid, rc: RangeCompressed, offsets, weights, wind
                          cache: str | None = None):
     """Time every plan launch shape on `rc`, and the azimuth fast convolution where the layout
     admits it; returns (tile, microseconds) with tile = (pixels_per_lane, waves) or "fastconv",
-    to pass as SparsePlan(tile=...).  methods: "all", "direct" or "fastconv".  cache: a JSON file
-    of earlier results keyed by GPU architecture and shape class (default: the
-    ROSAR_AUTOTUNE_CACHE environment variable; none when unset); a hit skips the timing."""
+    to pass as SparsePlan(tile=...).  methods: "all", "direct" or "fastconv".  cache: selects the
+    library's autotune cache file first (autotune_cache); a result cached for this GPU
+    architecture and shape class is returned without timing."""
     variants = {"all": 0, "direct": L.PLAN_DIRECT, "fastconv": L.PLAN_FASTCONV}[methods]
     _need_gpu(rc.data)
     s = _set(offsets, weights, window, grid.n_range)
     dev = rc.data.device
-    cache = cache if cache is not None else os.environ.get("ROSAR_AUTOTUNE_CACHE")
-    key = None
-    if cache:
-        key = autotune_cache_key(torch.cuda.get_device_properties(dev).gcnArchName, geom, grid, rc.dtype,
-                                 rc.l_count, s.k, window, s.w_dtype, interp, methods)
-        hit = autotune_cache_get(cache, key)
-        if hit is not None:
-            return hit
+    if cache is not None:
+        autotune_cache(cache)
     out = _out(out, (grid.n_range, grid.n_az), torch.complex64, dev)
     g, p, v = L.geometry(geom), L.polar_grid(grid), rc.view()
     best = L.Tile()
@@ -423,10 +450,7 @@ def sparse_plan_autotune(geom, grid, rc: RangeCompressed, offsets, weights, wind
                                                L.INTERP_CODES[interp], _ptr(out), variants, reps, C.byref(best),
                                                C.byref(us),
                                                _stream(dev)), "rosar_sparse_plan_autotune")
-    res = ("fastconv" if best.variant == 3 else (best.pixels_per_lane, best.waves)), float(us.value)
-    if cache:
-        autotune_cache_put(cache, key, *res)
-    return res
+    return ("fastconv" if best.variant == 3 else (best.pixels_per_lane, best.waves)), float(us.value)
 
 
 def sparse_filter_cartesian(geom, grid, cart, rc: RangeCompressed, offsets, weights, window, interp: str = "nearest",

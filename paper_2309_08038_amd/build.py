@@ -17,8 +17,8 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "librosar.so")
-SOURCES = ["range_compress.hip", "sparse_filter.hip", "fastconv.hip", "adjoint_band.hip", "bp_full.hip", "bp_time_domain.hip", "cartesian.hip", "delta_r.hip", "beampattern.hip", "backward.hip",
-           "batch.hip", "api.cpp"]
+SOURCES = ["range_compress.hip", "sparse_filter.hip", "fastconv.hip", "adjoint_band.hip", "bp_full.hip", "bp_time_domain.hip", "cartesian.hip", "sas_design.hip", "delta_r.hip", "beampattern.hip", "backward.hip",
+           "batch.hip", "api.cpp", "autotune_cache.cpp"]
 ARCH = "gfx950"
 
 # Packed FP32 instructions stay off: the compiler would otherwise form v_pk_fma_f32 and

@@ -343,6 +343,56 @@ rosar_status rosar_bp_full(const rosar_geometry* geom, const rosar_polar_grid* g
                   "bp_full launch");
 }
 
+static rosar_status check_sas(const rosar_geometry* geom, const rosar_polar_grid* grid, const rosar_sas_params* p) {
+  ROSAR_TRY(check_geometry(geom));
+  if (!grid) return fail(ROSAR_ERR_INVALID_ARG, "grid is NULL");
+  if (grid->n_range < 1 || grid->n_range > 65536) return fail(ROSAR_ERR_INVALID_ARG, "n_range must be in [1, 65536]");
+  if (!(grid->r0_m > 0) || !std::isfinite(grid->r0_m) || !(grid->dr_m >= 0) || !std::isfinite(grid->dr_m))
+    return fail(ROSAR_ERR_INVALID_ARG, "r0_m must be > 0 and dr_m >= 0, both finite");
+  if (!p) return fail(ROSAR_ERR_INVALID_ARG, "params is NULL");
+  if (p->iters < 1 || p->iters > 1000 || p->max_newton < 1 || p->max_newton > 1000)
+    return fail(ROSAR_ERR_INVALID_ARG, "iters and max_newton must be in [1, 1000]");
+  if (!(p->phi_mw >= 0) || !(p->d_angle > 0) || !(p->eta > 0) || !(p->u_min >= 0) || !(p->lam_b > 0) ||
+      !(p->th >= 0) || !(p->eps > 0) || !(p->mu > 1) || !(p->tau0 > 0) || !(p->newton_tol > 0) ||
+      !(p->ls_alpha > 0 && p->ls_alpha < 0.5) || !(p->ls_beta > 0 && p->ls_beta < 1) || !(p->ls_min > 0))
+    return fail(ROSAR_ERR_INVALID_ARG, "design parameters out of range");
+  return ROSAR_OK;
+}
+
+rosar_status rosar_sas_design_workspace_size(const rosar_geometry* geom, const rosar_polar_grid* grid,
+                                             const rosar_sas_params* params, size_t* bytes,
+                                             int32_t* max_candidates) {
+  ROSAR_TRY(check_sas(geom, grid, params));
+  if (!bytes || !max_candidates) return fail(ROSAR_ERR_INVALID_ARG, "bytes or max_candidates is NULL");
+  const rosar::SasSizes z = rosar::sas_sizes(make_geo(geom, grid), *params);
+  *bytes = z.bytes;
+  *max_candidates = z.n_max;
+  return ok();
+}
+
+rosar_status rosar_sas_design(const rosar_geometry* geom, const rosar_polar_grid* grid,
+                              const rosar_sas_params* params, const double* delta_r, int32_t window,
+                              int32_t* offsets, void* weights, int32_t* count, double* history,
+                              void* workspace, size_t workspace_bytes, rosar_stream stream) {
+  ROSAR_TRY(check_sas(geom, grid, params));
+  const rosar::Geo g = make_geo(geom, grid);
+  const rosar::SasSizes z = rosar::sas_sizes(g, *params);
+  if (window < std::max(z.n_max, 1)) return fail(ROSAR_ERR_INVALID_ARG, "window %d below the largest candidate count %d", window, z.n_max);
+  if (!delta_r || !aligned(delta_r, 8)) return fail(ROSAR_ERR_INVALID_ARG, "delta_r NULL or misaligned");
+  if (!offsets || !aligned(offsets, 4) || !count || !aligned(count, 4))
+    return fail(ROSAR_ERR_INVALID_ARG, "offsets or count NULL or misaligned");
+  ROSAR_TRY(check_image(weights, "weights"));
+  if (history && !aligned(history, 8)) return fail(ROSAR_ERR_INVALID_ARG, "history misaligned");
+  if (!workspace || !aligned(workspace, 256) || workspace_bytes < z.bytes)
+    return fail(ROSAR_ERR_WORKSPACE, "workspace must be 256-byte aligned and >= %zu bytes (got %zu)", z.bytes,
+                workspace_bytes);
+  if (inject_launch_fault()) return fail(ROSAR_ERR_HIP, "injected launch failure (ROSAR_FAULT_INJECT)");
+  return from_hip(rosar::launch_sas_design(g, *params, delta_r, z, workspace, window, offsets,
+                                           reinterpret_cast<float2*>(weights), count, history,
+                                           reinterpret_cast<hipStream_t>(stream)),
+                  "sas_design launch");
+}
+
 rosar_status rosar_sparse_filter_backward_workspace_size(const rosar_geometry* geom, const rosar_polar_grid* grid,
                                                          const rosar_sparse_set* set, size_t* bytes) {
   ROSAR_TRY(check_geometry(geom));
@@ -577,6 +627,21 @@ rosar_status rosar_sparse_filter_backward(const rosar_geometry* geom, const rosa
 }
 
 }  // extern "C"
+
+namespace {
+
+// Autotune cache key: GPU architecture and everything that decides which launch shape wins
+// (pulses, rows and their spacing, band layout and storage, taps, window, weight type,
+// interpolation).
+std::string tune_key(const char* kind, const rosar::SparseArgs& a, const rosar_rc_view* rc, rosar_interp interp) {
+  char buf[512];
+  snprintf(buf, sizeof(buf), "%s|%s|N=%d|rows=%d|r0=%.17g|dr=%.17g|band=%d+%d|halo=%d|ld=%lld|dt=%d|K=%d|W=%d|wdt=%d|interp=%d",
+           rosar::tune_arch().c_str(), kind, a.g.n, a.g.n_range, a.g.r0, a.g.dr, rc->l_lo, rc->l_count, rc->halo,
+           (long long)rc->ld, rc->dtype, a.k, a.window, a.w_dtype, (int)interp);
+  return buf;
+}
+
+}  // namespace
 
 struct rosar_sparse_plan {
   rosar::SparseArgs a{};      // geometry, band layout (data NULL), set, interp
@@ -844,6 +909,8 @@ rosar_status rosar_sparse_plan_autotune(const rosar_geometry* geom, const rosar_
   if (!any && !fc_ok)
     return fail(ROSAR_ERR_UNSUPPORTED, "no plan variant admits this layout (direct: halo >= W/2, 16-byte aligned rows, "
                                        "a staged row within the LDS budget; fast convolution: N = 2^a 3^b 5^c <= 8192)");
+  const std::string key = tune_key("plan", a, rc, interp) + "|variants=" + std::to_string(variants);
+  if (rosar::tune_cache_get(key, best, best_us)) return ok();
   ROSAR_TRY(check_not_capturing(stream, "rosar_sparse_plan_autotune"));
   if (inject_launch_fault()) return fail(ROSAR_ERR_HIP, "injected launch failure (ROSAR_FAULT_INJECT)");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
@@ -907,6 +974,7 @@ rosar_status rosar_sparse_plan_autotune(const rosar_geometry* geom, const rosar_
   best->waves = best_tile.waves;
   best->reserved = 0;
   *best_us = best_t;
+  if (!rosar::tune_cache_put(key, *best, best_t)) return fail(ROSAR_ERR_INVALID_ARG, "cannot write the autotune cache file");
   return ok();
 }
 
@@ -917,6 +985,8 @@ rosar_status rosar_autotune_sparse_filter(const rosar_geometry* geom, const rosa
   ROSAR_TRY(sparse_common(geom, grid, rc, set, nullptr, nullptr, ROSAR_NEAREST, image, &a));
   if (!best || !best_us) return fail(ROSAR_ERR_INVALID_ARG, "best / best_us is NULL");
   if (reps < 1 || reps > 10000) return fail(ROSAR_ERR_INVALID_ARG, "reps must be in [1, 10000]");
+  const std::string key = tune_key("single", a, rc, ROSAR_NEAREST);
+  if (rosar::tune_cache_get(key, best, best_us)) return ok();
   ROSAR_TRY(check_not_capturing(stream, "rosar_autotune_sparse_filter"));
   if (inject_launch_fault()) return fail(ROSAR_ERR_HIP, "injected launch failure (ROSAR_FAULT_INJECT)");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
@@ -958,6 +1028,7 @@ rosar_status rosar_autotune_sparse_filter(const rosar_geometry* geom, const rosa
   best->waves = best_tile.waves;
   best->reserved = 0;
   *best_us = best_t;
+  if (!rosar::tune_cache_put(key, *best, best_t)) return fail(ROSAR_ERR_INVALID_ARG, "cannot write the autotune cache file");
   return ok();
 }
 

@@ -32,7 +32,7 @@ constexpr int kRedGroups = 32;         // row groups of the first reduction stag
 
 // Nominal geometry and weight of one tap, 48 bytes.
 struct alignas(16) BwTap {
-  double u;       // band-relative bin beta * R_nom - l_lo (+ 1/2 for NEAREST)
+  SplitBin u;     // band-relative bin beta * R_nom - l_lo (+ 1/2 for NEAREST), split
   float r2;       // R_nom^2
   float rnom;     // R_nom
   float sd, cd;   // sin, cos of D0
@@ -109,7 +109,7 @@ __global__ __launch_bounds__(kBwThreads) void backward_row_kernel(
         const double rn = sqrt(r2);
         const float2 w = weights[wrow + t];
         BwTap e;
-        e.u = g.beta * rn + u_shift;
+        e.u = split_bin(g.beta * rn + u_shift);
         e.r2 = (float)r2;
         e.rnom = (float)rn;
         e.sd = (float)sd;
@@ -139,26 +139,32 @@ __global__ __launch_bounds__(kBwThreads) void backward_row_kernel(
           const float rs = __builtin_amdgcn_rsqf(r2);
           const float rh = r2 * rs;
           const float diff = dd * __builtin_amdgcn_rcpf(rh + tp.rnom);   // R^ - R_nom
-          const double u = tp.u + (double)(beta * diff);
+          const float corr = beta * diff;
+          float fr;
+          bool tie;
+          int l = corr_bin(tp.u, corr, &fr, &tie);
           float2 yv, dy = make_float2(0.f, 0.f);
           if constexpr (INTERP == ROSAR_NEAREST) {
-            const int l = min(max((int)floor(u), -1), y.l_count);
+            if (__builtin_expect(tie, 0)) {
+              // plain float64 bin at the angle (o 2 pi) / N + delta_n of the oracle's definition
+              const double d = (double)tp.o * g.step + (dphi ? (double)dphi[min(pn, n - 1)] : 0.0);
+              l = (int)floor(plain_bin_half(rr, g.radius, d, g.beta)) - y.l_lo;
+            }
+            l = min(max(l, -1), y.l_count);
             yv = buf_load<DT>(rsrc, (uint32_t)(__mul24(l, ld_es) + cb[j]), 0u);
           } else {
-            const double fl = floor(u);
-            const float f = (float)(u - fl);
-            const int l = min(max((int)fl, -2), y.l_count);
+            l = min(max(l, -2), y.l_count);
             const uint32_t off0 = (uint32_t)(__mul24(l, ld_es) + cb[j]);
             const float2 y0 = buf_load<DT>(rsrc, off0, 0u);
             const float2 y1 = buf_load<DT>(rsrc, off0 + (uint32_t)ld_es, 0u);
             dy = make_float2((y1.x - y0.x) * isc, (y1.y - y0.y) * isc);
-            yv = make_float2(fmaf(f, y1.x - y0.x, y0.x), fmaf(f, y1.y - y0.y, y0.y));
+            yv = make_float2(fmaf(fr, y1.x - y0.x, y0.x), fmaf(fr, y1.y - y0.y, y0.y));
           }
           yv.x *= isc;
           yv.y *= isc;
-          float fr = fmaf(kpi, diff, pr[j]);
-          fr -= floorf(fr);
-          const float2 rot = make_float2(cos_rev(fr), -sin_rev(fr));
+          float rev = fmaf(kpi, diff, pr[j]);
+          rev -= floorf(rev);
+          const float2 rot = make_float2(cos_rev(rev), -sin_rev(rev));
           const float2 s = cmul(yv, rot);
           // conj(g) s
           gw.x = fmaf(gv.x, s.x, fmaf(gv.y, s.y, gw.x));

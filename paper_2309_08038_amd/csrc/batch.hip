@@ -373,6 +373,27 @@ rosar_status rosar_batch_autotune(const rosar_rotation_desc* descs, int32_t n, i
   clear_error();
   if (!best || !best_us) return bfail(ROSAR_ERR_INVALID_ARG, "best / best_us is NULL");
   if (reps < 1 || reps > 1000) return bfail(ROSAR_ERR_INVALID_ARG, "reps must be in [1, 1000]");
+  if (!descs || n < 1) return bfail(ROSAR_ERR_INVALID_ARG, "descs NULL or n < 1");
+  // cache key: the shapes of every rotation (FNV-1a over their sizes, band layouts and sets)
+  uint64_t h = 1469598103934665603ull;
+  auto mix = [&h](const void* p, size_t bytes) {
+    const unsigned char* c = static_cast<const unsigned char*>(p);
+    for (size_t i = 0; i < bytes; ++i) h = (h ^ c[i]) * 1099511628211ull;
+  };
+  for (int32_t i = 0; i < n; ++i) {
+    const rosar_status vs = validate_rotation(descs[i], i);
+    if (vs != ROSAR_OK) return vs;
+    const rosar_rotation_desc& d = descs[i];
+    const int64_t f[] = {d.geom.n_pulses, d.geom.n_fast, d.geom.n_fft, d.grid.n_range, d.grid.n_az, d.l_lo,
+                         d.l_count, d.halo, d.ld, d.set.k, d.set.window, d.set.w_dtype};
+    mix(f, sizeof(f));
+    const double r[] = {d.geom.radius_m, d.grid.r0_m, d.grid.dr_m};
+    mix(r, sizeof(r));
+  }
+  char kb[160];
+  snprintf(kb, sizeof(kb), "%s|batch|n=%d|shapes=%016llx", tune_arch().c_str(), n, (unsigned long long)h);
+  const std::string key = kb;
+  if (tune_cache_get(key, best, best_us)) return ROSAR_OK;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   // it allocates, synchronises and times: refused on a capturing stream, which stays valid
   hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
@@ -427,6 +448,7 @@ rosar_status rosar_batch_autotune(const rosar_rotation_desc* descs, int32_t n, i
   if (!have) return bfail(ROSAR_ERR_UNSUPPORTED, "no batch launch shape holds these windows");
   *best = bt;
   *best_us = best_t;
+  if (!tune_cache_put(key, bt, best_t)) return bfail(ROSAR_ERR_INVALID_ARG, "cannot write the autotune cache file");
   clear_error();
   return ROSAR_OK;
 }

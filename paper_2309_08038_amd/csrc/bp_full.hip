@@ -17,6 +17,7 @@
 // the bin is beta R_nom + beta (R_n - R_nom) in float64, the phase adds 2 k (R_n - R_nom), and
 // v = R cos D - r = (R^2 - r^2 - R_n^2) / (2 r) gives alpha = max(v, 0) / R_n (eqs. 3, 8, 15).
 // Neighbouring lanes read neighbouring columns of the same bin row: coalesced loads.
+
 #include "rosar_device.hpp"
 
 namespace rosar {
@@ -30,12 +31,12 @@ constexpr size_t kBpHeader = 256;                // bytes before the per-pulse t
 
 // Nominal geometry of one offset o (no angle error), 32 bytes.
 struct alignas(16) BpTap {
-  double u;       // beta * R_nom (FFT bin, eq. 40)
+  SplitBin u;     // beta * R_nom - l_lo (+ 1/2 for NEAREST): FFT bin of eq. 40, split
   float r2;       // R_nom^2
   float rnom;     // R_nom
   float sd, cd;   // sin, cos of D0 = 2 pi o / N
   float ph;       // frac(k R_nom / pi): revolutions of exp(j 2 k R_nom)
-  int32_t pad;
+  int32_t near;   // NEAREST: a correction of this offset can bring the bin near a rounding tie
 };
 
 __global__ __launch_bounds__(1024) void bp_prep_kernel(int32_t n, double phi0, double step,
@@ -68,6 +69,7 @@ __global__ __launch_bounds__(1024) void bp_prep_kernel(int32_t n, double phi0, d
 template <int DT, int INTERP>
 __global__ __launch_bounds__(kBpThreads) void bp_kernel(Geo g, View y, int tiles_per_row, int nblocks,
                                                        const double* __restrict__ ws,
+                                                       const double* __restrict__ angles,
                                                        const char* __restrict__ ydata,
                                                        float2* __restrict__ image) {
   __shared__ BpTap s_tap[kBpChunk];
@@ -127,13 +129,16 @@ __global__ __launch_bounds__(kBpThreads) void bp_kernel(Geo g, View y, int tiles
         const double rn = sqrt(r2);
         const double ph = g.k_over_pi * rn;
         BpTap t;
-        t.u = g.beta * rn + u_shift;   // band-relative bin (+ 1/2 for rounding to nearest)
+        t.u = split_bin(g.beta * rn + u_shift);   // band-relative bin (+ 1/2 for rounding to nearest)
         t.r2 = (float)r2;
         t.rnom = (float)rn;
         t.sd = (float)s;
         t.cd = (float)c;
         t.ph = (float)(ph - floor(ph));
-        t.pad = 0;
+        // |R_n - R_nom| is at most the chord r |d| between the nominal and the true phase centre,
+        // so the corrected fraction stays within beta r max|d| of the nominal one
+        const float fmax_corr = (float)(g.beta * r * dmax) * 1.0001f + 0x1p-17f;
+        t.near = (t.u.f < fmax_corr || t.u.f > 1.f - fmax_corr) ? 1 : 0;
         s_tap[threadIdx.x] = t;
       }
       for (int j = threadIdx.x; j < cnt - 1 + kBpTile; j += kBpThreads) {
@@ -161,29 +166,37 @@ __global__ __launch_bounds__(kBpThreads) void bp_kernel(Geo g, View y, int tiles
           const float rn = r2 * rs;
           const float diff = dd * __builtin_amdgcn_rcpf(rn + tp.rnom);   // R_n - R_nom
           const float alpha = fmaxf((k1 - r2) * inv2r, 0.f) * rs;
-          const double u = tp.u + (double)(beta * diff);
+          const float corr = beta * diff;
+          float fr;
+          bool tie;
+          int l = corr_bin(tp.u, corr, &fr, &tie);
           int pn = pc[p] + t;
           pn -= (pn >= n) ? n : 0;
           const int cb = (pn + y.halo) * ES;   // byte offset of the column within a row
           // rows clamped to just outside either band edge: an out-of-band sample reads zero
           float2 smp;
           if constexpr (INTERP == ROSAR_NEAREST) {
-            const int l = min(max((int)floor(u), -1), y.l_count);
+            if (tp.near && tie) {
+              // plain float64 bin at D = phi_a - phi^_n (the step 2 pi / N multiplied, not divided:
+              // the angles may differ from the definition's in the last bit)
+              const double phi_a = g.phi0 + (double)acol[p] * g.step;
+              const double phi_n = angles ? angles[pn] : g.phi0 + (double)pn * g.step;
+              l = (int)floor(plain_bin_half(rr, r, phi_a - phi_n, g.beta)) - y.l_lo;
+            }
+            l = min(max(l, -1), y.l_count);
             smp = buf_load<DT>(rsrc, (uint32_t)(__mul24(l, ld_es) + cb), 0u);
           } else {
-            const double fl = floor(u);
-            const float f = (float)(u - fl);
-            const int l = min(max((int)fl, -2), y.l_count);
+            l = min(max(l, -2), y.l_count);
             const uint32_t off0 = (uint32_t)(__mul24(l, ld_es) + cb);
             const float2 y0 = buf_load<DT>(rsrc, off0, 0u);
             const float2 y1 = buf_load<DT>(rsrc, off0 + (uint32_t)ld_es, 0u);
-            smp = make_float2(fmaf(f, y1.x - y0.x, y0.x), fmaf(f, y1.y - y0.y, y0.y));
+            smp = make_float2(fmaf(fr, y1.x - y0.x, y0.x), fmaf(fr, y1.y - y0.y, y0.y));
           }
-          float fr = tp.ph + kpi * diff;
-          fr -= floorf(fr);
+          float rev = tp.ph + kpi * diff;
+          rev -= floorf(rev);
           // coefficient alpha exp(-j 2 k R_n); acc += coef * smp
-          const float cr = alpha * cos_rev(fr);
-          const float ci = -alpha * sin_rev(fr);
+          const float cr = alpha * cos_rev(rev);
+          const float ci = -alpha * sin_rev(rev);
           acc[p].x = fmaf(cr, smp.x, acc[p].x);
           acc[p].x = fmaf(-ci, smp.y, acc[p].x);
           acc[p].y = fmaf(cr, smp.y, acc[p].y);
@@ -203,14 +216,14 @@ __global__ __launch_bounds__(kBpThreads) void bp_kernel(Geo g, View y, int tiles
 
 template <int DT>
 hipError_t launch_dt(const Geo& g, const View& y, int32_t interp, float2* image, const double* ws,
-                     hipStream_t s) {
+                     const double* angles, hipStream_t s) {
   const int tiles = (g.n + kBpTile - 1) / kBpTile;
   const int nblocks = tiles * g.n_range;
   const char* yd = reinterpret_cast<const char*>(y.data);
   if (interp == ROSAR_LINEAR)
-    bp_kernel<DT, ROSAR_LINEAR><<<nblocks, kBpThreads, 0, s>>>(g, y, tiles, nblocks, ws, yd, image);
+    bp_kernel<DT, ROSAR_LINEAR><<<nblocks, kBpThreads, 0, s>>>(g, y, tiles, nblocks, ws, angles, yd, image);
   else
-    bp_kernel<DT, ROSAR_NEAREST><<<nblocks, kBpThreads, 0, s>>>(g, y, tiles, nblocks, ws, yd, image);
+    bp_kernel<DT, ROSAR_NEAREST><<<nblocks, kBpThreads, 0, s>>>(g, y, tiles, nblocks, ws, angles, yd, image);
   return hipGetLastError();
 }
 
@@ -225,9 +238,9 @@ hipError_t launch_bp_full(const Geo& g, const View& y, const double* angles, int
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   switch (y.dtype) {
-    case ROSAR_C64: return launch_dt<0>(g, y, interp, image, w, s);
-    case ROSAR_C16_F16: return launch_dt<1>(g, y, interp, image, w, s);
-    default: return launch_dt<2>(g, y, interp, image, w, s);
+    case ROSAR_C64: return launch_dt<0>(g, y, interp, image, w, angles, s);
+    case ROSAR_C16_F16: return launch_dt<1>(g, y, interp, image, w, angles, s);
+    default: return launch_dt<2>(g, y, interp, image, w, angles, s);
   }
 }
 

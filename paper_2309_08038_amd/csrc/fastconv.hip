@@ -60,7 +60,7 @@ __global__ __launch_bounds__(256) void fc_table_kernel(Geo g, View y, int32_t k,
     float f = 0.f;
     if (inwin) {
       const double u = g.beta * sqrt(c1 - c2 * cos(o * g.step));
-      l = sparse::bin_of<INTERP>(u) - y.l_lo;
+      l = sparse::tap_bin<INTERP>(u, g, rr, o) - y.l_lo;
       if constexpr (INTERP == ROSAR_LINEAR) f = (float)(u - floor(u));
     }
     const int pos = inwin ? (o < 0 ? o + g.n : o) : 0;

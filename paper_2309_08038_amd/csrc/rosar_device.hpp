@@ -134,6 +134,92 @@ __device__ __forceinline__ float2 buf_load(__amdgpu_buffer_rsrc_t r, uint32_t vo
 // Workgroups are dispatched round-robin over the 8 XCDs (block b runs on XCD b % 8).  Map
 // the hardware block index to a logical one so that each XCD receives a contiguous range of
 // logical blocks (neighbouring range rows share Y rows in that XCD's L2).
+// ---------------------------------------------------------------- eq. 40 rounding ties
+// NEAREST takes the bin floor(u + 1/2) of u = beta R (eq. 40, eq. 2).  The kernels evaluate u
+// in a fast way whose error is bounded (float64 with fused operations, or a float64 nominal
+// bin plus a float32 correction); where floor could then differ from the plain evaluation,
+// i.e. within that bound of a rounding boundary, they recompute u the plain way below.
+
+constexpr double kTwoPiD = 6.283185307179586476925286766559;
+
+// cos x in float64 for |x| < 2^20 (angles of a rotation and their errors): Cody-Waite
+// reduction by pi (a 33 + 33 + 53-bit split of pi, so q P1 and q P2 are exact for |q| < 2^20),
+// cos x = (-1)^q cos r with |r| <= pi/2, and the Taylor series of cos r to the r^24 term
+// (remainder below 4e-22).  About 1 ulp of absolute error; one polynomial, so few registers in
+// the rarely taken branches that call it.
+__device__ __forceinline__ double cos_reduced(double x) {
+  constexpr double kInvPi = 0.31830988618379067154;
+  constexpr double kP1 = 0x1.921fb54400000p+1;
+  constexpr double kP2 = 0x1.0b4611a600000p-33;
+  constexpr double kP3 = 0x1.3198a2e037073p-68;
+  const double q = rint(x * kInvPi);
+  const double r = ((x - q * kP1) - q * kP2) - q * kP3;
+  const double z = r * r;
+  double c = 1.0 / 620448401733239439360000.0;   // 1/24!
+  c = c * z - 1.0 / 1124000727777607680000.0;    // 1/22!
+  c = c * z + 1.0 / 2432902008176640000.0;       // 1/20!
+  c = c * z - 1.0 / 6402373705728000.0;          // 1/18!
+  c = c * z + 1.0 / 20922789888000.0;            // 1/16!
+  c = c * z - 1.0 / 87178291200.0;               // 1/14!
+  c = c * z + 1.0 / 479001600.0;                 // 1/12!
+  c = c * z - 1.0 / 3628800.0;                   // 1/10!
+  c = c * z + 1.0 / 40320.0;                     // 1/8!
+  c = c * z - 1.0 / 720.0;                       // 1/6!
+  c = c * z + 1.0 / 24.0;
+  c = c * z - 0.5;
+  c = c * z + 1.0;
+  return ((int64_t)q & 1) ? -c : c;
+}
+
+// u + 1/2 of a point at range rr seen from a phase centre at angle d from it, with every
+// operation rounded on its own in the order eq. 2 writes it:
+// beta sqrt((rr rr + r r) - ((2 r) rr) cos d) + 1/2.
+__device__ __attribute__((noinline)) double plain_bin_half(double rr, double radius, double d, double beta) {
+#pragma clang fp contract(off)
+  const double cd = cos_reduced(d);
+  const double c1 = rr * rr + radius * radius;
+  const double c2 = 2.0 * radius * rr;
+  const double rn = sqrt(c1 - c2 * cd);
+  return beta * rn + 0.5;
+}
+
+// True when floor(u) may differ from the plain evaluation's: u lies within `err` of an
+// integer.
+__device__ __forceinline__ bool near_bin_tie(double u, double err) {
+  const double t = u - floor(u);
+  return t < err || t > 1.0 - err;
+}
+
+// Bound on the error of a float64 bin evaluated with fused operations and a different but
+// equivalent angle expression (a few ulps of u < 2^20): far below it.
+constexpr double kBinErr64 = 0x1p-30;
+
+// A float64 nominal bin split as floor(u) and its fraction in float32, so the per-pair work of
+// the corrected paths (nominal bin plus a float32 correction) stays in float32.
+struct SplitBin {
+  int32_t i;
+  float f;
+};
+__device__ __forceinline__ SplitBin split_bin(double u) {
+  const double fl = floor(u);
+  return SplitBin{(int32_t)fl, (float)(u - fl)};
+}
+
+// floor(i + f + corr) of a split nominal bin plus a float32 correction `corr` (in bins), and
+// whether that sum lies near a rounding boundary: within the bound of its error, a few float32
+// ulps relative to corr (hardware reciprocal square root and reciprocal) plus an absolute error
+// below 2^-18 bins (the float32 geometry terms, sin and cos of the half angle error, and the
+// float32 fraction).  The fraction of the sum comes out in *frac.
+__device__ __forceinline__ int corr_bin(SplitBin nb, float corr, float* frac, bool* tie) {
+  const float x = nb.f + corr;
+  const float fl = floorf(x);
+  const float fr = x - fl;
+  const float err = 0x1p-18f + fabsf(corr) * 0x1p-12f;
+  *frac = fr;
+  *tie = fr < err || fr > 1.f - err;
+  return nb.i + (int)fl;
+}
+
 __device__ __forceinline__ int xcd_logical_block(int b, int nblocks) {
   int per = nblocks / kXcds, rem = nblocks % kXcds;
   int xcd = b % kXcds, local = b / kXcds;

@@ -148,4 +148,22 @@ hipError_t launch_fc_run(const SparseArgs& a, const FcLayout& L, const char* tab
 Tile default_tile(int32_t n, int32_t y_dtype);
 bool tile_supported(const Tile& t);
 
+// Robust sparse-array synthesis (Algorithm 1): per-bin candidate and side-lobe counts decide
+// the workspace layout (a uniform stride per bin).
+using SasDesignParams = rosar_sas_params;
+struct SasSizes {
+  int n_max, s_max;     // most candidates / side-lobe directions of any bin
+  size_t stride, bytes; // workspace bytes per bin and in all
+};
+SasSizes sas_sizes(const Geo& g, const SasDesignParams& p);
+hipError_t launch_sas_design(const Geo& g, const SasDesignParams& p, const double* delta_r, const SasSizes& z,
+                             void* ws, int32_t window, int32_t* offsets, float2* weights, int32_t* count,
+                             double* hist, hipStream_t s);
+
+// Autotune cache (rosar_autotune): results keyed by GPU architecture and shape class, behind one
+// mutex, mirrored to the selected JSON file.  put returns false if the file cannot be written.
+bool tune_cache_get(const std::string& key, rosar_tile* tile, float* us);
+bool tune_cache_put(const std::string& key, const rosar_tile& tile, float us);
+std::string tune_arch();   // the current device's architecture name, e.g. "gfx950"
+
 }  // namespace rosar

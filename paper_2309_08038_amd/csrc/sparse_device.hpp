@@ -155,6 +155,21 @@ __device__ __forceinline__ int bin_of(double u) {
   return INTERP == ROSAR_NEAREST ? (int)floor(u + 0.5) : (int)floor(u);
 }
 
+// Bin of tap offset o of range row rr (eq. 2, eq. 40) from the float64 u = beta R(o 2 pi / N)
+// the caller evaluated: NEAREST near a rounding boundary is settled by the plain evaluation at
+// angle (o 2 pi) / N.  LINEAR is continuous across its bin boundaries and takes floor(u).
+template <int INTERP>
+__device__ __forceinline__ int tap_bin(double u, const Geo& g, double rr, int o) {
+  if constexpr (INTERP == ROSAR_NEAREST) {
+    const double uh = u + 0.5;
+    if (near_bin_tie(uh, kBinErr64))
+      return (int)floor(plain_bin_half(rr, g.radius, (double)o * g.step, g.beta));
+    return (int)floor(uh);
+  } else {
+    return (int)floor(u);
+  }
+}
+
 // Bin rows [lfirst, lfirst + nrows) of the staged window of one range row, from the geometry
 // alone: the slant range of a tap grows with |offset| (|R - r| at offset 0, at most that of
 // offset W/2, whose cosine is cos_hw).  Uniform across the workgroup.
@@ -270,7 +285,7 @@ __device__ __forceinline__ bool build_taps(const Geo& g, const View& y, int k, i
     float f = 0.f;
     if (inwin) {
       const double u = g.beta * sqrt(c1 - c2 * cos(o * g.step));
-      l = bin_of<INTERP>(u) - y.l_lo;
+      l = tap_bin<INTERP>(u, g, rr, o) - y.l_lo;
       if constexpr (INTERP == ROSAR_LINEAR) f = (float)(u - floor(u));
     }
 #pragma unroll

@@ -111,7 +111,7 @@ __global__ __launch_bounds__(kWave* NW) void sparse_plain_kernel(
         const double u = g.beta * rn;
         int l;
         if constexpr (INTERP == ROSAR_NEAREST) {
-          l = (int)floor(u + 0.5) - y.l_lo;
+          l = sparse::tap_bin<INTERP>(u, g, rr, ofs) - y.l_lo;
         } else {
           const double fl = floor(u);
           const float f = (float)(u - fl);
@@ -182,7 +182,7 @@ constexpr int kCorrMaxCols = 4096;                 // largest per-pulse table he
 
 // Nominal geometry and weight of one tap (no angle error), 48 bytes.
 struct alignas(16) CorrTap {
-  double u;       // band-relative bin beta * R_nom - l_lo (+ 1/2 for NEAREST)
+  SplitBin u;     // band-relative bin beta * R_nom - l_lo (+ 1/2 for NEAREST), split
   float r2;       // R_nom^2
   float rnom;     // R_nom
   float sd, cd;   // sin, cos of D0 = 2 pi o / N
@@ -262,7 +262,7 @@ __global__ __launch_bounds__(kCorrThreads) void sparse_corrected_kernel(
       const double r2 = c1 - c2 * cd;
       const double rn = sqrt(r2);
       CorrTap e;
-      e.u = g.beta * rn + u_shift;
+      e.u = split_bin(g.beta * rn + u_shift);
       e.r2 = (float)r2;
       e.rnom = (float)rn;
       e.sd = (float)sd;
@@ -305,24 +305,33 @@ __global__ __launch_bounds__(kCorrThreads) void sparse_corrected_kernel(
         const float r2 = fmaxf(tp.r2 + dd, 1e-30f);
         const float rn = r2 * __builtin_amdgcn_rsqf(r2);
         const float diff = dd * __builtin_amdgcn_rcpf(rn + tp.rnom);   // R^ - R_nom
-        const double u = tp.u + (double)(beta * diff);
+        const float corr = beta * diff;
+        float fr;
+        bool tie;
+        int l = corr_bin(tp.u, corr, &fr, &tie);
         float2 smp;
         if constexpr (INTERP == ROSAR_NEAREST) {
-          const int l = min(max((int)floor(u), -1), y.l_count);
+          if (__builtin_expect(tie, 0)) {
+            // plain float64 bin at the angle (o 2 pi) / N + delta_n of the oracle's definition
+            int pn = acol[p] + tp.o;
+            pn += (pn < 0) ? n : 0;
+            pn -= (pn >= n) ? n : 0;
+            const double d = (double)tp.o * g.step + (dphi ? (double)dphi[pn] : 0.0);
+            l = (int)floor(plain_bin_half(rr, g.radius, d, g.beta)) - y.l_lo;
+          }
+          l = min(max(l, -1), y.l_count);
           smp = buf_load<DT>(rsrc, (uint32_t)(__mul24(l, ld_es) + cb), 0u);
         } else {
-          const double fl = floor(u);
-          const float f = (float)(u - fl);
-          const int l = min(max((int)fl, -2), y.l_count);
+          l = min(max(l, -2), y.l_count);
           const uint32_t off0 = (uint32_t)(__mul24(l, ld_es) + cb);
           const float2 y0 = buf_load<DT>(rsrc, off0, 0u);
           const float2 y1 = buf_load<DT>(rsrc, off0 + (uint32_t)ld_es, 0u);
-          smp = make_float2(fmaf(f, y1.x - y0.x, y0.x), fmaf(f, y1.y - y0.y, y0.y));
+          smp = make_float2(fmaf(fr, y1.x - y0.x, y0.x), fmaf(fr, y1.y - y0.y, y0.y));
         }
         // exp(-j (2 k (R^ - R_nom) + psi)) in revolutions
-        float fr = fmaf(kpi, diff, pr);
-        fr -= floorf(fr);
-        const float2 rot = make_float2(cos_rev(fr), -sin_rev(fr));
+        float rev = fmaf(kpi, diff, pr);
+        rev -= floorf(rev);
+        const float2 rot = make_float2(cos_rev(rev), -sin_rev(rev));
         cmac_conj(acc[p], w, cmul(smp, rot));
       }
     }

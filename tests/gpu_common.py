@@ -57,3 +57,16 @@ def custom_workload(name, cfg_id, n, m, rg, r0, r1, k, win, radius=0.25, shared=
 
 def rel_l2(a, b):
     return oracle.metrics.rel_l2(np.asarray(a), np.asarray(b))
+
+
+def assert_image(got, ref, tol, what=""):
+    """Relative L2 <= tol over the image, and no pixel off by more than tol times the image's
+    largest magnitude: a handful of wrong pixels (a wrong bin, a wrong pulse) fails the second
+    bar even where it hides under the first."""
+    got, ref = np.asarray(got), np.asarray(ref)
+    e = rel_l2(got, ref)
+    assert e <= tol, (what, "relative L2", e)
+    scale = np.abs(ref).max()
+    worst = np.abs(got - ref).max()
+    assert worst <= tol * scale, (what, "largest pixel error", worst, "of max", scale,
+                                  "at", np.unravel_index(np.argmax(np.abs(got - ref)), ref.shape))

@@ -461,26 +461,49 @@ def test_cartesian_validation(lib):
         assert lib.rosar_last_error().decode() != ""
 
 
-def test_autotune_cache_helpers(tmp_path):
-    """Plan-autotune cache: round trip of tuple and "fastconv" tiles, other keys kept, missing
-    or corrupt files read as empty."""
+def test_autotune_cache_in_library(tmp_path, lib):
+    """The library's autotune cache: entries round-trip through its JSON file (stores merge with
+    what the file holds, reloads see them), a missing or corrupt file reads as empty, NULL
+    arguments are rejected, and no file keeps entries in memory only."""
+    import json
     import paper_2309_08038_amd as rs
     path = str(tmp_path / "tune.json")
-    assert rs.autotune_cache_get(path, "k1") is None
-    rs.autotune_cache_put(path, "k1", (4, 8), 35.5)
-    rs.autotune_cache_put(path, "k2", "fastconv", 57.0)
-    assert rs.autotune_cache_get(path, "k1") == ((4, 8), 35.5)
-    assert rs.autotune_cache_get(path, "k2") == ("fastconv", 57.0)
-    assert rs.autotune_cache_get(path, "k3") is None
-    (tmp_path / "bad.json").write_text("{not json")
-    assert rs.autotune_cache_get(str(tmp_path / "bad.json"), "k1") is None
-    rs.autotune_cache_put(str(tmp_path / "bad.json"), "k1", (2, 4), 1.0)
-    assert rs.autotune_cache_get(str(tmp_path / "bad.json"), "k1") == ((2, 4), 1.0)
-    g, grid = geom(), L.PolarGrid(8, 360, 1.0, 0.05)
-    a = rs.autotune_cache_key("gfx950", g, grid, "c64", 64, 32, 64, L.C64, "nearest", "all")
-    b = rs.autotune_cache_key("gfx950", g, grid, "f16", 64, 32, 64, L.C64, "nearest", "all")
-    assert a != b and a.startswith("gfx950|")
-
+    try:
+        rs.autotune_cache(path)
+        assert rs.autotune_lookup("gfx950|plan|k1") is None
+        rs.autotune_store("gfx950|plan|k1", 2, 4, 8, 35.5)
+        rs.autotune_store('gfx950|odd "key" \\ |k2', 3, 0, 0, 57.0)
+        assert rs.autotune_lookup("gfx950|plan|k1") == (2, 4, 8, 35.5)
+        d = json.loads(open(path).read())
+        assert d["gfx950|plan|k1"] == {"variant": 2, "pixels_per_lane": 4, "waves": 8, "us": 35.5}
+        assert d['gfx950|odd "key" \\ |k2']["variant"] == 3
+        # another writer adds an entry to the file; the next store keeps it
+        d["other|k3"] = {"variant": 1, "pixels_per_lane": 2, "waves": 2, "us": 3.0}
+        open(path, "w").write(json.dumps(d))
+        rs.autotune_store("gfx950|plan|k4", 2, 8, 4, 10.0)
+        assert set(json.loads(open(path).read())) == {"gfx950|plan|k1", 'gfx950|odd "key" \\ |k2', "other|k3",
+                                                      "gfx950|plan|k4"}
+        rs.autotune_cache(path)   # reload
+        assert rs.autotune_lookup("other|k3") == (1, 2, 2, 3.0)
+        bad = tmp_path / "bad.json"
+        bad.write_text("{not json")
+        rs.autotune_cache(str(bad))
+        assert rs.autotune_lookup("gfx950|plan|k1") is None
+        rs.autotune_store("gfx950|plan|k1", 2, 2, 4, 1.0)
+        assert json.loads(bad.read_text()) == {"gfx950|plan|k1": {"variant": 2, "pixels_per_lane": 2, "waves": 4,
+                                                                  "us": 1.0}}
+        rs.autotune_cache(str(tmp_path / "missing.json"))
+        assert rs.autotune_lookup("gfx950|plan|k1") is None
+        rs.autotune_cache(None)
+        rs.autotune_store("mem|only", 2, 2, 2, 2.0)
+        assert rs.autotune_lookup("mem|only") == (2, 2, 2, 2.0)
+        assert not (tmp_path / "mem").exists()
+        t, us, found = L.Tile(), C.c_float(0), C.c_int32(0)
+        assert lib.rosar_autotune_lookup(None, C.byref(t), C.byref(us), C.byref(found)) == L.ROSAR_ERR_INVALID_ARG
+        assert lib.rosar_autotune_store(b"", C.byref(t), 1.0) == L.ROSAR_ERR_INVALID_ARG
+        assert lib.rosar_autotune_store(b"k", C.byref(t), -1.0) == L.ROSAR_ERR_INVALID_ARG
+    finally:
+        rs.autotune_cache(None)
 
 
 def test_output_buffer_checks():
@@ -661,3 +684,26 @@ def test_plan_workspace_entry_points_validate(lib):
     v = L.RcView(0x10000, L.C64, 0, 16, 0, 360, 1.0, 0)
     assert lib.rosar_sparse_plan_run_workspace(None, C.byref(v), FAKE, FAKE, 1 << 20, None) == L.ROSAR_ERR_INVALID_ARG
     assert "NULL" in lib.rosar_last_error().decode()
+
+
+def test_sas_design_validation(lib):
+    """Design parameters, window and workspace are checked before any device work."""
+    g = geom(n_pulses=160, n_fast=225, n_fft=225, radius_m=0.145, fc_hz=60e9, slope_hz_s=6.8e13, fs_hz=4.5e6,
+             t_start_s=7e-6)
+    grid = L.PolarGrid(3, 160, 1.2, 0.3)
+    import paper_2309_08038_amd as rs
+    from oracle import fppsca as F
+    p = rs.sas_params(iters=5)
+    nb, nc = C.c_size_t(0), C.c_int32(0)
+    assert lib.rosar_sas_design_workspace_size(C.byref(g), C.byref(grid), C.byref(p), C.byref(nb),
+                                               C.byref(nc)) == L.ROSAR_OK
+    assert nc.value == len(F.candidates(g, 1.8)) and nb.value > 0      # the farthest row sees the most
+    call = lambda pp, window=nc.value, ws=FAKE, wsb=nb.value: lib.rosar_sas_design(
+        C.byref(g), C.byref(grid), C.byref(pp), FAKE, window, FAKE, FAKE, FAKE, None, ws, wsb, None)
+    for bad in (dict(iters=0), dict(mu=1.0), dict(eta=0.0), dict(ls_alpha=0.6), dict(tau0=-1.0), dict(d_angle=0.0)):
+        assert call(rs.sas_params(**{"iters": 5, **bad})) == L.ROSAR_ERR_INVALID_ARG, bad
+    assert call(p, window=nc.value - 1) == L.ROSAR_ERR_INVALID_ARG
+    assert call(p, wsb=nb.value - 1) == L.ROSAR_ERR_WORKSPACE
+    assert call(p, ws=C.c_void_p(0x10010)) == L.ROSAR_ERR_WORKSPACE
+
+

@@ -8,7 +8,7 @@ import pytest
 
 import oracle
 import synth
-from gpu_common import custom_workload, dev, inputs, log, need_gpu, oracle_band, rel_l2, to_dev, torch
+from gpu_common import assert_image, custom_workload, dev, inputs, log, need_gpu, oracle_band, rel_l2, to_dev, torch
 
 pytestmark = pytest.mark.gpu
 
@@ -108,10 +108,10 @@ def test_paper_radar_end_to_end():
         log(f"paper radar sparse filter {interp}")
         img = rs.sparse_filter(g, w.grid, rc, off, wts, w.sparse.window, interp=interp).cpu().numpy()
         ref = oracle.sparse_filter(yb, x.l_lo, g, w.grid, x.offsets, x.weights, interp=interp)
-        assert rel_l2(img, ref) <= TOL, interp
+        assert_image(img, ref, TOL, interp)
     log("paper radar BPA")
     bpa = rs.bp_full(g, w.grid, rc).cpu().numpy()
-    assert rel_l2(bpa, oracle.bp_full(yb, x.l_lo, g, w.grid)) <= TOL
+    assert_image(bpa, oracle.bp_full(yb, x.l_lo, g, w.grid), TOL)
 
 
 # ------------------------------------------------------------------ sparse filter
@@ -123,7 +123,7 @@ def test_sparse_filter_small_end_to_end():
     img = rs.sparse_filter(w.geometry, w.grid, rc, off, wts, w.sparse.window)
     torch.cuda.synchronize()
     ref = oracle.sparse_filter(oracle_band("small"), x.l_lo, w.geometry, w.grid, x.offsets, x.weights)
-    assert rel_l2(img.cpu().numpy(), ref) <= TOL
+    assert_image(img.cpu().numpy(), ref, TOL)
 
 
 SHAPES = [(v, p, nw) for v in (1, 2) for p in (1, 2, 4, 8) for nw in (1, 2, 4, 8) if not (p == 8 and nw == 8)]
@@ -141,7 +141,7 @@ def test_sparse_filter_launch_shapes_bit_identical():
     for t in SHAPES:
         log(f"sparse_filter tile={t}")
         img = rs.sparse_filter(w.geometry, w.grid, rc, off, wts, w.sparse.window, tile=t).cpu()
-        assert rel_l2(img.numpy(), ref) <= TOL, t
+        assert_image(img.numpy(), ref, TOL, t)
         if first is None:
             first = img
         assert torch.equal(img, first), t
@@ -160,7 +160,7 @@ def test_sparse_filter_halo_and_wrap(interp):
         log(f"sparse_filter halo={halo} interp={interp}")
         rc = rc_from_band(rs, w, yb, x.l_lo, halo)
         img = rs.sparse_filter(w.geometry, w.grid, rc, off, wts, w.sparse.window, interp=interp).cpu().numpy()
-        assert rel_l2(img, ref) <= TOL, halo
+        assert_image(img, ref, TOL, halo)
         outs.append(img)
     np.testing.assert_allclose(outs[0], outs[2], rtol=0, atol=1e-6 * np.abs(ref).max())
 
@@ -188,7 +188,7 @@ def test_sparse_filter_edge_cases(case, interp):
     rc = rs.range_compress(w.geometry, to_dev(x.raw), to_dev(x.window), x.l_lo, x.l_count, halo=win // 2)
     img = rs.sparse_filter(w.geometry, w.grid, rc, to_dev(x.offsets), to_dev(x.weights.astype(np.complex64)),
                            win, interp=interp).cpu().numpy()
-    assert rel_l2(img, ref) <= TOL
+    assert_image(img, ref, TOL)
 
 
 def test_sparse_filter_narrow_band():
@@ -203,7 +203,7 @@ def test_sparse_filter_narrow_band():
     rc = rs.range_compress(w.geometry, to_dev(x.raw), to_dev(x.window), lo, cnt, halo=32)
     img = rs.sparse_filter(w.geometry, w.grid, rc, to_dev(x.offsets), to_dev(x.weights.astype(np.complex64)),
                            w.sparse.window).cpu().numpy()
-    assert rel_l2(img, ref) <= TOL
+    assert_image(img, ref, TOL)
     assert np.count_nonzero(img) < img.size     # rows far outside the band are exactly zero
 
 
@@ -225,7 +225,7 @@ def test_sparse_filter_corrected(interp, which):
     img = rs.sparse_filter(w.geometry, w.grid, rc, to_dev(x.offsets), to_dev(x.weights.astype(np.complex64)),
                            w.sparse.window, dphi=None if dphi is None else to_dev(dphi),
                            dpsi=None if dpsi is None else to_dev(dpsi), interp=interp).cpu().numpy()
-    assert rel_l2(img, ref) <= TOL
+    assert_image(img, ref, TOL)
 
 
 @pytest.mark.parametrize("interp", ["nearest", "linear"])
@@ -249,7 +249,7 @@ def test_sparse_filter_corrected_wide_window(interp, halo_half):
                            halo=win // 2 if halo_half else 0)
     img = rs.sparse_filter(w.geometry, w.grid, rc, to_dev(x.offsets), to_dev(x.weights.astype(np.complex64)),
                            win, dphi=to_dev(dphi), dpsi=to_dev(dpsi), interp=interp).cpu().numpy()
-    assert rel_l2(img, ref) <= TOL
+    assert_image(img, ref, TOL)
 
 
 def test_sparse_filter_rotation_invariance_bitwise():
@@ -272,7 +272,7 @@ def test_sparse_filter_rotation_full():
     rc, off, wts = upload(w, x, rs=rs)
     img = rs.sparse_filter(w.geometry, w.grid, rc, off, wts, w.sparse.window).cpu().numpy()
     ref = oracle.sparse_filter(oracle_band("rotation"), x.l_lo, w.geometry, w.grid, x.offsets, x.weights)
-    assert rel_l2(img, ref) <= TOL
+    assert_image(img, ref, TOL)
 
 
 # ------------------------------------------------------------------ back-projection
@@ -284,7 +284,7 @@ def test_bp_full_small(interp):
     rc, _, _ = upload(w, x, rs=rs)
     img = rs.bp_full(w.geometry, w.grid, rc, interp=interp).cpu().numpy()
     ref = oracle.bp_full(oracle_band("small"), x.l_lo, w.geometry, w.grid, interp=interp)
-    assert rel_l2(img, ref) <= TOL
+    assert_image(img, ref, TOL)
 
 
 def test_bp_full_jittered_angles_small():
@@ -295,7 +295,7 @@ def test_bp_full_jittered_angles_small():
     rc, _, _ = upload(w, x, rs=rs)
     img = rs.bp_full(w.geometry, w.grid, rc, angles=to_dev(ang)).cpu().numpy()
     ref = oracle.bp_full(oracle_band("small"), x.l_lo, w.geometry, w.grid, pulse_angles=ang)
-    assert rel_l2(img, ref) <= TOL
+    assert_image(img, ref, TOL)
 
 
 def test_bp_full_rotation_sampled():
@@ -312,7 +312,7 @@ def test_bp_full_rotation_sampled():
     rows[:4] = [0, 0, w.grid.n_range - 1, w.grid.n_range - 1]
     azs[:4] = [0, w.grid.n_az - 1, 0, w.grid.n_az - 1]
     ref = oracle.bp_full_at(oracle_band("rotation"), x.l_lo, w.geometry, w.grid, rows, azs, pulse_angles=x.angles)
-    assert rel_l2(img[rows, azs], ref) <= TOL
+    assert_image(img[rows, azs], ref, TOL)
 
 
 @pytest.mark.parametrize("interp", ["nearest", "linear"])
@@ -330,7 +330,7 @@ def test_bp_full_narrow_band(interp):
     ref = oracle.bp_full(y[:, lo:lo + cnt], lo, w.geometry, w.grid, pulse_angles=ang, interp=interp)
     rc = rs.range_compress(w.geometry, to_dev(x.raw), to_dev(x.window), lo, cnt, halo=0)
     img = rs.bp_full(w.geometry, w.grid, rc, angles=to_dev(ang), interp=interp).cpu().numpy()
-    assert rel_l2(img, ref) <= TOL
+    assert_image(img, ref, TOL)
     assert np.count_nonzero(img) < img.size
 
 
@@ -344,7 +344,7 @@ def test_bp_full_rows_inside_radius():
     ref = oracle.bp_full(yb, x.l_lo, w.geometry, w.grid)
     rc = rs.range_compress(w.geometry, to_dev(x.raw), to_dev(x.window), x.l_lo, x.l_count, halo=8)
     img = rs.bp_full(w.geometry, w.grid, rc).cpu().numpy()
-    assert rel_l2(img, ref) <= TOL
+    assert_image(img, ref, TOL)
     inside = w.grid.r0_m + np.arange(w.grid.n_range) * w.grid.dr_m <= w.geometry.radius_m
     assert inside.any() and not np.any(img[inside])
 
@@ -378,8 +378,8 @@ def test_bpa_equals_dense_sparse_filter_gpu():
     rc = rc_from_band(rs, w, yb, l_lo, n // 2)
     a = rs.sparse_filter(g, grid, rc, to_dev(offs), to_dev(wts.astype(np.complex64)), n).cpu().numpy()
     b = rs.bp_full(g, grid, rc).cpu().numpy()
-    assert rel_l2(a, b) <= TOL
-    assert rel_l2(b, oracle.bp_full(yb, l_lo, g, grid)) <= TOL
+    assert_image(a, b, TOL)
+    assert_image(b, oracle.bp_full(yb, l_lo, g, grid), TOL)
 
 
 # ------------------------------------------------------------------ adjoint
@@ -428,13 +428,13 @@ def test_max_taps_forward_corrected_and_adjoint(interp):
     log(f"max taps plain {interp}")
     ref = oracle.sparse_filter(yb, x.l_lo, w.geometry, w.grid, x.offsets, x.weights, interp=interp)
     img = rs.sparse_filter(w.geometry, w.grid, rc, off, wts, n, interp=interp).cpu().numpy()
-    assert rel_l2(img, ref) <= TOL
+    assert_image(img, ref, TOL)
     log(f"max taps corrected {interp}")
     ref = oracle.sparse_filter(yb, x.l_lo, w.geometry, w.grid, x.offsets, x.weights, dphi=dphi.astype(np.float64),
                                dpsi=dpsi.astype(np.float64), interp=interp)
     img = rs.sparse_filter(w.geometry, w.grid, rc, off, wts, n, dphi=to_dev(dphi), dpsi=to_dev(dpsi),
                            interp=interp).cpu().numpy()
-    assert rel_l2(img, ref) <= TOL
+    assert_image(img, ref, TOL)
     log(f"max taps adjoint {interp}")
     gimg = synth.random_complex((w.grid.n_range, n), seed=37)
     gw_r, gd_r, gp_r = oracle.sparse_filter_grad(yb, x.l_lo, w.geometry, w.grid, x.offsets, x.weights,

@@ -148,21 +148,32 @@ def test_plan_autotune(dtype):
 
 def test_plan_autotune_cache(tmp_path):
     """With a cache file the first autotune stores its result under the GPU's architecture and
-    shape class; an entry found there is returned without timing (an edited entry comes back)."""
+    shape class (in the library, which writes the file); an entry found there is returned
+    without timing (an edited entry comes back, also after the file is reloaded)."""
     rs = need_gpu()
     w, x = inputs("small")
     rc, off, wts = upload(rs, w, x)
     path = str(tmp_path / "tune.json")
     log("plan autotune cache")
-    first = rs.sparse_plan_autotune(w.geometry, w.grid, rc, off, wts, w.sparse.window, reps=2, cache=path)
-    d = json.loads(open(path).read())
-    (key, entry), = d.items()
-    arch = torch.cuda.get_device_properties(0).gcnArchName
-    assert key.startswith(arch + "|plan|") and rs.autotune_cache_get(path, key) == first
-    d[key] = {"tile": [2, 4], "us": 1.25}
-    open(path, "w").write(json.dumps(d))
-    assert rs.sparse_plan_autotune(w.geometry, w.grid, rc, off, wts, w.sparse.window, reps=2, cache=path) == \
-        ((2, 4), 1.25)
+    try:
+        first = rs.sparse_plan_autotune(w.geometry, w.grid, rc, off, wts, w.sparse.window, reps=2, cache=path)
+        d = json.loads(open(path).read())
+        (key, entry), = d.items()
+        arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+        assert key.startswith(arch + "|plan|"), key
+        tile = "fastconv" if entry["variant"] == 3 else (entry["pixels_per_lane"], entry["waves"])
+        assert (tile, pytest.approx(entry["us"], rel=1e-6)) == first
+        d[key] = {"variant": 2, "pixels_per_lane": 2, "waves": 4, "us": 1.25}
+        open(path, "w").write(json.dumps(d))
+        rs.autotune_cache(path)     # reload the edited file
+        assert rs.sparse_plan_autotune(w.geometry, w.grid, rc, off, wts, w.sparse.window, reps=2) == ((2, 4), 1.25)
+        # the single-call autotuner caches under its own key
+        t1 = rs.autotune_sparse_filter(w.geometry, w.grid, rc, off, wts, w.sparse.window, reps=2)
+        keys = json.loads(open(path).read()).keys()
+        assert len(keys) == 2 and any("|single|" in k for k in keys)
+        assert rs.autotune_sparse_filter(w.geometry, w.grid, rc, off, wts, w.sparse.window, reps=2) == t1
+    finally:
+        rs.autotune_cache(None)
 
 
 def test_plan_layout_mismatch_rejected():
