@@ -168,6 +168,19 @@ rosar_status rosar_sparse_filter_tiled(const rosar_geometry* geom, const rosar_p
                                        const float* dphi, const float* dpsi, rosar_interp interp,
                                        void* image, const rosar_tile* tile, rosar_stream stream);
 
+/* rosar_bp_full for callers that cannot allocate (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): the same kernels and the same image, with
+ * the per-pulse table in a file-scope device array of the library (256 B + 8 B per pulse for
+ * at most 65536 pulses, 512.25 KiB per GPU, held until the process ends) instead of a caller
+ * workspace.  It calls no allocating routine.  Every call on one GPU shares that GPU's array,
+ * which holds the last call's table: calls that overlap on one GPU (several streams, parallel
+ * graph branches) race and must not be issued; calls on one stream are ordered.  The first call
+ * on a device looks the array's address up (hipGetSymbolAddress) with that device current.
+ * Errors: as rosar_bp_full without the workspace checks; INVALID_ARG for n_pulses > 65536. */
+rosar_status rosar_bp_full_noalloc(const rosar_geometry* geom, const rosar_polar_grid* grid,
+                                   const rosar_rc_view* rc, const double* pulse_angle_rad,
+                                   rosar_interp interp, void* image, rosar_stream stream);
+
 /* Device workspace (bytes) needed by rosar_bp_full for this geometry. */
 rosar_status rosar_bp_full_workspace_size(const rosar_geometry* geom, size_t* bytes);
 

@@ -78,6 +78,8 @@ PROTOTYPES = [
     ("rosar_bp_full_workspace_size", C.c_int, [_P(Geometry), _P(C.c_size_t)]),
     ("rosar_bp_full", C.c_int, [_P(Geometry), _P(PolarGrid), _P(RcView), C.c_void_p, C.c_int, C.c_void_p,
                                C.c_void_p, C.c_size_t, C.c_void_p]),
+    ("rosar_bp_full_noalloc", C.c_int, [_P(Geometry), _P(PolarGrid), _P(RcView), C.c_void_p, C.c_int, C.c_void_p,
+                                       C.c_void_p]),
     ("rosar_sas_design_workspace_size", C.c_int, [_P(Geometry), _P(PolarGrid), _P(SasParams), _P(C.c_size_t),
                                                   _P(C.c_int32)]),
     ("rosar_sas_design", C.c_int, [_P(Geometry), _P(PolarGrid), _P(SasParams), C.c_void_p, C.c_int32, C.c_void_p,

@@ -199,6 +199,20 @@ def bp_full(geom, grid, rc: RangeCompressed, angles: torch.Tensor | None = None,
     return out
 
 
+def bp_full_noalloc(geom, grid, rc: RangeCompressed, angles: torch.Tensor | None = None, interp: str = "nearest",
+                    out: torch.Tensor | None = None) -> torch.Tensor:
+    """bp_full without a workspace: the per-pulse table lives in the library's device array (at
+    most 65536 pulses); calls that overlap on one GPU must not be issued."""
+    _arg(angles, "angles", torch.float64, (geom.n_pulses,))
+    _need_gpu(rc.data)
+    dev = rc.data.device
+    out = _out(out, (grid.n_range, grid.n_az), torch.complex64, dev)
+    g, p, v = L.geometry(geom), L.polar_grid(grid), rc.view()
+    L.check(L.lib().rosar_bp_full_noalloc(C.byref(g), C.byref(p), C.byref(v), _ptr(angles), L.INTERP_CODES[interp],
+                                          _ptr(out), _stream(dev)), "rosar_bp_full_noalloc")
+    return out
+
+
 @dataclass
 class SasDesign:
     """Result of the robust sparse-array synthesis (Algorithm 1) for every row of a polar grid:

@@ -343,6 +343,27 @@ rosar_status rosar_bp_full(const rosar_geometry* geom, const rosar_polar_grid* g
                   "bp_full launch");
 }
 
+rosar_status rosar_bp_full_noalloc(const rosar_geometry* geom, const rosar_polar_grid* grid, const rosar_rc_view* rc,
+                                   const double* pulse_angle_rad, rosar_interp interp, void* image,
+                                   rosar_stream stream) {
+  ROSAR_TRY(check_geometry(geom));
+  ROSAR_TRY(check_grid(geom, grid));
+  ROSAR_TRY(check_view(geom, rc));
+  if (interp != ROSAR_NEAREST && interp != ROSAR_LINEAR)
+    return fail(ROSAR_ERR_INVALID_ARG, "interp must be ROSAR_NEAREST or ROSAR_LINEAR");
+  if (pulse_angle_rad && !aligned(pulse_angle_rad, 8)) return fail(ROSAR_ERR_INVALID_ARG, "pulse_angle_rad misaligned");
+  ROSAR_TRY(check_image(image, "image"));
+  if (geom->n_pulses > rosar::kBpNoAllocMaxPulses)
+    return fail(ROSAR_ERR_INVALID_ARG, "rosar_bp_full_noalloc takes at most %d pulses (got %d): use rosar_bp_full",
+                rosar::kBpNoAllocMaxPulses, geom->n_pulses);
+  if (inject_launch_fault()) return fail(ROSAR_ERR_HIP, "injected launch failure (ROSAR_FAULT_INJECT)");
+  void* ws = nullptr;
+  ROSAR_TRY(from_hip(rosar::bp_scratch(&ws), "bp_full_noalloc scratch address"));
+  return from_hip(rosar::launch_bp_full(make_geo(geom, grid), make_view(rc), pulse_angle_rad, interp,
+                                        reinterpret_cast<float2*>(image), ws, reinterpret_cast<hipStream_t>(stream)),
+                  "bp_full_noalloc launch");
+}
+
 static rosar_status check_sas(const rosar_geometry* geom, const rosar_polar_grid* grid, const rosar_sas_params* p) {
   ROSAR_TRY(check_geometry(geom));
   if (!grid) return fail(ROSAR_ERR_INVALID_ARG, "grid is NULL");

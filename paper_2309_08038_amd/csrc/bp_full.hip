@@ -17,6 +17,7 @@
 // the bin is beta R_nom + beta (R_n - R_nom) in float64, the phase adds 2 k (R_n - R_nom), and
 // v = R cos D - r = (R^2 - r^2 - R_n^2) / (2 r) gives alpha = max(v, 0) / R_n (eqs. 3, 8, 15).
 // Neighbouring lanes read neighbouring columns of the same bin row: coalesced loads.
+#include <mutex>
 
 #include "rosar_device.hpp"
 
@@ -230,6 +231,34 @@ hipError_t launch_dt(const Geo& g, const View& y, int32_t interp, float2* image,
 }  // namespace
 
 size_t bp_workspace_bytes(int32_t n) { return kBpHeader + (size_t)n * sizeof(float2); }
+
+// The allocation-free entry point's per-pulse table lives in this file-scope device array, one
+// copy per GPU (the largest angle error, then (sin(d_n/2), cos(d_n/2)) per pulse).  Host code
+// never passes the array's name to a kernel: it takes the device address from
+// hipGetSymbolAddress, once per device, with that device current.
+static __device__ __align__(256) unsigned char scratch[kBpHeader + (size_t)kBpNoAllocMaxPulses * sizeof(float2)];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+hipError_t bp_scratch(void** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
 
 hipError_t launch_bp_full(const Geo& g, const View& y, const double* angles, int32_t interp,
                           float2* image, void* ws, hipStream_t s) {

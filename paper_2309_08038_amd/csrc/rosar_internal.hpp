@@ -74,6 +74,10 @@ hipError_t launch_sparse_polar(const SparseArgs& a, int32_t n_az, hipStream_t s)
 hipError_t launch_bp_cartesian(const Geo& g, const View& y, const CartGrid& c, const double* angles, int32_t interp,
                                float2* image, hipStream_t s);
 size_t bp_workspace_bytes(int32_t n);
+// Allocation-free back-projection: the workspace is a file-scope device array sized for at most
+// kBpNoAllocMaxPulses pulses; bp_scratch gives its address on the current device.
+constexpr int32_t kBpNoAllocMaxPulses = 1 << 16;
+hipError_t bp_scratch(void** out);
 hipError_t launch_sas_time_domain(const Geo& g, int m_fast, double cyc_per_m, const float2* raw, const float* window,
                                   const int32_t* offsets, const float2* weights, int k, int window_w, int row_first,
                                   int row_count, float2* image, hipStream_t s);

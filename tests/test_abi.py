@@ -707,3 +707,17 @@ def test_sas_design_validation(lib):
     assert call(p, ws=C.c_void_p(0x10010)) == L.ROSAR_ERR_WORKSPACE
 
 
+def test_bp_full_noalloc_validation(lib):
+    """The allocation-free back-projection rejects more pulses than its device array holds, and
+    bad views or angles, before any device work."""
+    grid = L.PolarGrid(8, 360, 1.0, 0.05)
+    view = L.RcView(0x20000, L.C64, 0, 64, 32, 424, 1.0, 0)
+    g = geom()
+    assert lib.rosar_bp_full_noalloc(C.byref(g), C.byref(grid), C.byref(view), C.c_void_p(0x10004), L.NEAREST,
+                                     FAKE, None) == L.ROSAR_ERR_INVALID_ARG
+    big = geom(n_pulses=65537)
+    bgrid = L.PolarGrid(8, 65537, 1.0, 0.05)
+    bview = L.RcView(0x20000, L.C64, 0, 64, 0, 65537, 1.0, 0)
+    assert lib.rosar_bp_full_noalloc(C.byref(big), C.byref(bgrid), C.byref(bview), None, L.NEAREST, FAKE,
+                                     None) == L.ROSAR_ERR_INVALID_ARG
+    assert "65536" in lib.rosar_last_error().decode()
