@@ -51,6 +51,9 @@ def parse():
                     help="time the steps with the single-call sparse filter instead of a plan")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the corrected-forward, adjoint, batch and precision timings")
+    ap.add_argument("--only", default=None, choices=sorted(ONLY_ROWS),
+                    help="launch one kernel of the path --steps times on the workload and print its mean time "
+                         "(a short program for rocprofv3 kernel-trace and counter runs); no other timing")
     return ap.parse_args()
 
 
@@ -324,20 +327,33 @@ def pipelined_steps(torch, rs, g, grid, x, raw, win, window, sf, steps):
     return e0.elapsed_time(e1) / steps, imgs[(steps - 1) % 2]
 
 
+def pulse_errors(torch, synth, w, x, dev):
+    """Per-pulse angle errors (the workload's own jitter: true minus nominal angles) and phase
+    errors (seeded N(0, 0.1 rad)) for the corrected forward and its adjoint, float32."""
+    dphi = torch.from_numpy((x.angles - synth.nominal_angles(w.geometry)).astype(np.float32)).to(dev)
+    rng = np.random.default_rng(1000 * w.cfg_id + 9)
+    dpsi = torch.from_numpy(rng.normal(0.0, 0.1, w.geometry.n_pulses).astype(np.float32)).to(dev)
+    return dphi, dpsi
+
+
 def extras(torch, rs, synth, w, x, dev, rc, off, wts, timed, reps):
     """Timings of the other rows of the path on the same rotation, plus the batched stream and
     the precision workload."""
     g, grid = w.geometry, w.grid
     n = g.n_pulses
     out = {}
-    # corrected forward (per-pulse angle and phase errors, LINEAR) and its adjoint
-    dphi = torch.zeros(n, dtype=torch.float32, device=dev)
-    dpsi = torch.zeros(n, dtype=torch.float32, device=dev)
+    # corrected forward with the workload's angle errors and random phase errors (LINEAR, then
+    # NEAREST with its tie guard) and its adjoint
+    dphi, dpsi = pulse_errors(torch, synth, w, x, dev)
     img = torch.empty((grid.n_range, grid.n_az), dtype=torch.complex64, device=dev)
     f = lambda: rs.sparse_filter(g, grid, rc, off, wts, w.sparse.window, dphi=dphi, dpsi=dpsi, interp="linear",
                                  out=img)
     f()
     out["corrected_forward_us"] = 1000 * timed(f, max(3, reps // 5), inner=5, out=lambda: img)
+    fn = lambda: rs.sparse_filter(g, grid, rc, off, wts, w.sparse.window, dphi=dphi, dpsi=dpsi, interp="nearest",
+                                  out=img)
+    fn()
+    out["corrected_forward_nearest_us"] = 1000 * timed(fn, max(3, reps // 5), inner=5, out=lambda: img)
     gimg = torch.randn((grid.n_range, grid.n_az), dtype=torch.complex64, device=dev)
     ws = torch.empty(rs.backward_workspace_bytes(g, grid, off, wts, w.sparse.window), dtype=torch.uint8, device=dev)
     grads = (torch.empty(tuple(off.shape), dtype=torch.complex64, device=dev),
@@ -352,7 +368,8 @@ def extras(torch, rs, synth, w, x, dev, rc, off, wts, timed, reps):
     ab = lambda: rs.sparse_filter_adjoint_band(g, grid, rc, off, wts, w.sparse.window, gimg, out=gband, workspace=wsb)
     ab()
     out["adjoint_band_us"] = 1000 * timed(ab, 3, inner=5, out=lambda: gband)
-    print(f"[bench] corrected forward {out['corrected_forward_us']:.1f} us, adjoint {out['adjoint_us']:.1f} us, "
+    print(f"[bench] corrected forward {out['corrected_forward_us']:.1f} us (LINEAR), "
+          f"{out['corrected_forward_nearest_us']:.1f} us (NEAREST), adjoint {out['adjoint_us']:.1f} us, "
           f"adjoint w.r.t. the band {out['adjoint_band_us']:.1f} us",
           file=sys.stderr, flush=True)
 
@@ -475,6 +492,50 @@ def extras(torch, rs, synth, w, x, dev, rc, off, wts, timed, reps):
 
 FAILURES: list = []
 
+# --only: one kernel of the path, launched on its own
+ONLY_ROWS = ("range_compress", "sparse_filter", "corrected_linear", "corrected_nearest", "adjoint", "bp_full")
+
+
+def only_row(torch, rs, synth, a, w, x, dev, raw, win, rc, off, wts, ang, img, bws):
+    """Launch one kernel --steps times (after --warmup launches) and print its mean time from
+    events around the launches: a short program whose profile holds little else."""
+    g, grid = w.geometry, w.grid
+    dphi, dpsi = pulse_errors(torch, synth, w, x, dev)
+    if a.only == "range_compress":
+        fn = lambda: rs.range_compress(g, raw, win, x.l_lo, x.l_count, out=rc)
+    elif a.only == "sparse_filter":
+        plan = rs.SparsePlan(g, grid, rc, off, wts, w.sparse.window,
+                             tile=tuple(int(v) for v in a.tile.split(",")[1:]) if a.tile else (4, 4))
+        fn = lambda: plan.run(rc, out=img)
+    elif a.only in ("corrected_linear", "corrected_nearest"):
+        interp = a.only.split("_")[1]
+        fn = lambda: rs.sparse_filter(g, grid, rc, off, wts, w.sparse.window, dphi=dphi, dpsi=dpsi, interp=interp,
+                                      out=img)
+    elif a.only == "adjoint":
+        gimg = torch.randn((grid.n_range, grid.n_az), dtype=torch.complex64, device=dev)
+        ws = torch.empty(rs.backward_workspace_bytes(g, grid, off, wts, w.sparse.window), dtype=torch.uint8,
+                         device=dev)
+        grads = (torch.empty(tuple(off.shape), dtype=torch.complex64, device=dev),
+                 torch.empty(g.n_pulses, dtype=torch.float32, device=dev),
+                 torch.empty(g.n_pulses, dtype=torch.float32, device=dev))
+        fn = lambda: rs.sparse_filter_backward(g, grid, rc, off, wts, w.sparse.window, gimg, dphi, dpsi, "linear",
+                                               workspace=ws, out=grads)
+    else:
+        fn = lambda: rs.bp_full(g, grid, rc, angles=ang, out=img, workspace=bws)
+    for _ in range(a.warmup):
+        fn()
+    torch.cuda.synchronize()
+    s = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for _ in range(a.steps):
+        fn()
+    e1.record(s)
+    torch.cuda.synchronize()
+    print(json.dumps({"only": a.only, "workload": w.name, "launches": a.steps,
+                      "ms_per_launch": e0.elapsed_time(e1) / a.steps,
+                      "note": "events around eager launches (host launch cost included for short kernels)"}))
+
 
 class Phase:
     """A roctx range around one phase of the run (shown by rocprofv3 --marker-trace)."""
@@ -518,6 +579,10 @@ def main():
     bimg = torch.empty_like(img)
     bws = torch.empty(rs.bp_workspace_bytes(g), dtype=torch.uint8, device=dev)
     tile = tuple(int(v) for v in a.tile.split(",")) if a.tile else None
+    if a.only:
+        rs.range_compress(g, raw, win, x.l_lo, x.l_count, out=rc)
+        only_row(torch, rs, synth, a, w, x, dev, raw, win, rc, off, wts, ang, img, bws)
+        return
     # one filter design for every rotation: the tap tables of its range rows are built once,
     # outside the timed steps (the plan equals the single call with the same shape bit for bit)
     rs.range_compress(g, raw, win, x.l_lo, x.l_count, out=rc)

@@ -12,8 +12,11 @@ recipe and the sparse-aperture recipe.  Five workloads are defined:
              FP16/BF16 range-compressed storage and FP16 weights.
   batch      64 rotations of uneven size (see synth.batch).
   calib      `rotation` sizes with LINEAR interpolation for gradient-based calibration.
+  testbed    the paper's radar (Table II chirp, N=800, M=L=225, r=0.145 m) and its 9.8756 m
+             square image area on a 0.04 m Cartesian lattice (247 x 247 targets), 155 polar
+             weight rows one FFT bin apart, K=157 of a 400-pulse window.
 
-Radar common to all: f_c = 77 GHz, B = 4 GHz swept over the M samples, F_s = 10 MHz,
+Radar common to all but `testbed`: f_c = 77 GHz, B = 4 GHz swept over the M samples, F_s = 10 MHz,
 K_s = B*F_s/M, T_Start = 0, c = 299 792 458 m/s.  With L = M one FFT bin is c/(2B) m.
 """
 from __future__ import annotations
@@ -158,4 +161,63 @@ def scaled(w: Workload, n_pulses: int, n_fast: int, n_range: int, k: int | None 
                      grid=grid, scene=sc, sparse=sp)
 
 
-WORKLOADS = {"small": small, "rotation": rotation, "precision": precision, "calib": calib}
+# The paper's radar (Sec. IV-B, Table II): chirp from 60 GHz with slope K = 6.8e13 Hz/s, sampled
+# at F_s = 4.5 MHz from T_Start = 7 us, M = L = 225 samples, r = 0.145 m, N = 800 pulses per
+# rotation.  One FFT bin spans c F_s / (2 K L) = 0.04409 m, so the 225 bins reach 9.8756 m: the
+# side of the testbed's square image area (Sec. IV-F).
+PAPER_FC_HZ = 60e9
+PAPER_SLOPE_HZ_S = 6.8e13
+PAPER_FS_HZ = 4.5e6
+PAPER_T_START_S = 7e-6
+PAPER_AREA_M = 9.8756
+PAPER_CELL_M = 0.04
+# the wheel encoder's angle spread (Sec. IV-B), read in degrees
+PAPER_SIGMA_RAD = math.radians(0.086)
+
+
+def paper_radar(n_pulses: int = 800) -> Geometry:
+    return Geometry(n_pulses=n_pulses, n_fast=225, n_fft=225, radius_m=0.145, fc_hz=PAPER_FC_HZ,
+                    slope_hz_s=PAPER_SLOPE_HZ_S, fs_hz=PAPER_FS_HZ, t_start_s=PAPER_T_START_S)
+
+
+@dataclass(frozen=True)
+class CartLattice:
+    """Cartesian targets x0 + i dx, y0 + j dy (i < nx, j < ny), row-major [ny][nx]."""
+    nx: int
+    ny: int
+    x0_m: float
+    y0_m: float
+    dx_m: float
+    dy_m: float
+
+    def positions(self):
+        import numpy as np
+        xs = (self.x0_m + np.arange(self.nx) * self.dx_m)[None, :].repeat(self.ny, 0)
+        ys = (self.y0_m + np.arange(self.ny) * self.dy_m)[:, None].repeat(self.nx, 1)
+        return xs.ravel(), ys.ravel()
+
+
+def paper_lattice() -> CartLattice:
+    """The testbed's image area (Sec. IV-F): a 9.8756 m square centred on the rotation centre,
+    cut into 0.04 m cells; the targets are the 247 x 247 cell centres."""
+    n = int(math.ceil(PAPER_AREA_M / PAPER_CELL_M))
+    x0 = -PAPER_AREA_M / 2 + PAPER_CELL_M / 2
+    return CartLattice(n, n, x0, x0, PAPER_CELL_M, PAPER_CELL_M)
+
+
+def testbed() -> Workload:
+    """The paper's radar and image area: polar weight rows one FFT bin apart from 0.2 m out to
+    the area's corners (7.0 m), 20 Rayleigh scatterers inside the area plus white noise, the
+    encoder's angle jitter, K = 157 taps (Table IV's robust count) of a 400-pulse window."""
+    g = paper_radar(800)
+    b = bin_size_m(g)
+    r_hi = math.hypot(PAPER_AREA_M / 2, PAPER_AREA_M / 2)
+    n_rows = int(math.ceil((r_hi - 0.2) / b)) + 1
+    grid = PolarGrid(n_range=n_rows, n_az=800, r0_m=0.2, dr_m=b)
+    return Workload("testbed", 6, g, grid,
+                    SceneSpec(20, "rayleigh", 0.5, PAPER_AREA_M / 2, noise_power=1e-3,
+                              jitter_sigma_rad=PAPER_SIGMA_RAD),
+                    SparseSpec(157, 400, shared_support=False))
+
+
+WORKLOADS = {"small": small, "rotation": rotation, "precision": precision, "calib": calib, "testbed": testbed}

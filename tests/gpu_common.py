@@ -37,7 +37,7 @@ def to_dev(a):
 
 @functools.lru_cache(maxsize=8)
 def inputs(name: str):
-    w = {"small": synth.small, "rotation": synth.rotation, "calib": synth.calib}[name]()
+    w = {"small": synth.small, "rotation": synth.rotation, "calib": synth.calib, "testbed": synth.testbed}[name]()
     return w, synth.make_inputs(w)
 
 
