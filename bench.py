@@ -490,6 +490,155 @@ def extras(torch, rs, synth, w, x, dev, rc, off, wts, timed, reps):
     return out
 
 
+def sidelobe_grid(geom, rr, phi_mw, d_angle):
+    """Side-lobe directions of a design row (input of the worst-case check): from phi_MW outwards
+    in steps of the angle interval to the extreme candidates' angles, on both sides; candidates
+    are the phase centres that see the row's target (R cos D > r)."""
+    n = geom.n_pulses
+    o = np.arange(-(n // 2), n - n // 2)
+    o = o[rr * np.cos(o * 2 * np.pi / n) - geom.radius_m > 0]
+    d_min, d_max = o.min() * 2 * np.pi / n, o.max() * 2 * np.pi / n
+    left = -phi_mw - d_angle * np.arange(int(np.floor((-phi_mw - d_min) / d_angle)) + 1)
+    right = phi_mw + d_angle * np.arange(int(np.floor((d_max - phi_mw) / d_angle)) + 1)
+    return np.concatenate([left[::-1], right]), d_min, d_max
+
+
+def sas_design_row(torch, rs, synth, dev):
+    """Robust sparse-array synthesis (Algorithm 1, FPP-SCA) on the GPU, then the worst-case check
+    of the designed weights with the GPU beampattern.
+
+    Design: the paper's radar (Table II chirp, r = 0.145 m) at N = 160 pulses, 16 rows over
+    [1, 4] m, Delta_R = 0.035 x (2 m / R) (the paper's 0.035 at R = 2 m, falling with range),
+    40 iterations, eta = -20 dB, phi_MW = 4 deg, 2 deg side-lobe interval, U_min = 2,
+    lambda_b = 200.  At N = 160 the paper's Table V values (-33 dB, 1 deg, 0.5 deg) are
+    infeasible (the C2 slack stays near 0.5: the phase centres are 5.7 mm apart, more than half
+    the 5 mm wavelength), so relaxed ones are used; the paper's N = 800 is timed for one
+    iteration of its 155 testbed rows.
+    The kernel runs with Th = 0, so it returns every candidate's final weight; the check is
+    (max side + Delta_R)^2 / (main - Delta_R)^2 per row on the design's side-lobe grid (the
+    constraint as posed, eq. 32).  The paper's thresholding (Th = 1e-3) is then applied to those
+    weights and the same check repeated on the sparse set, and a 0.05 deg grid over the same span
+    shows the pattern between the grid points."""
+    import math
+    g = synth.paper_radar(160)
+    grid = synth.PolarGrid(16, 160, 1.0, 0.2)
+    ranges = grid.ranges()
+    dr = torch.tensor([0.035 * 2.0 / r for r in ranges], dtype=torch.float64, device=dev)
+    th_paper = 1e-3
+    prm = rs.sas_params(iters=40, d_angle=math.radians(2.0), phi_mw=math.radians(4.0), eta=0.01, u_min=2.0,
+                        lam_b=200.0, th=0.0)
+    rs.sas_design(g, grid, dr, rs.sas_params(iters=1, d_angle=prm.d_angle, phi_mw=prm.phi_mw, eta=prm.eta,
+                                             u_min=prm.u_min, lam_b=prm.lam_b))
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    d = rs.sas_design(g, grid, dr, prm)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    hist = d.history.cpu().numpy()
+    cnt = d.count.cpu().numpy()
+    wts_all = d.weights.cpu()
+    off_all = d.offsets.cpu()
+
+    def ratio_of(row, off, w, angs):
+        a = torch.from_numpy(np.concatenate([[0.0], angs])).to(dev)
+        sub = synth.PolarGrid(1, g.n_pulses, ranges[row], 0.1)
+        _, summ = rs.beampattern(g, sub, off.to(dev), w.to(dev), g.n_pulses, a, delta_r=dr[row:row + 1].contiguous())
+        return float(summ.cpu().numpy()[0][2])
+
+    design, sparse, fine, nnz = [], [], [], []
+    for row, rr in enumerate(ranges):
+        side, d_min, d_max = sidelobe_grid(g, rr, prm.phi_mw, prm.d_angle)
+        fine_grid = np.concatenate([np.arange(d_min, -prm.phi_mw, math.radians(0.05)),
+                                    np.arange(prm.phi_mw, d_max, math.radians(0.05))])
+        c = int(cnt[row])
+        off, w = off_all[row:row + 1, :c].contiguous(), wts_all[row:row + 1, :c].contiguous()
+        design.append(ratio_of(row, off, w, side))
+        keep = (w.abs() >= th_paper)[0]
+        ks = max(int(keep.sum()), 1)
+        nnz.append(int(keep.sum()))
+        off_s, w_s = off[:, keep][:, :ks].contiguous(), w[:, keep][:, :ks].contiguous()
+        sparse.append(ratio_of(row, off_s, w_s, side))
+        fine.append(ratio_of(row, off_s, w_s, fine_grid))
+    design, sparse, fine, nnz = np.array(design), np.array(sparse), np.array(fine), np.array(nnz)
+    slack = hist[:, -1, 2] + hist[:, -1, 3] + hist[:, -1, 4]
+    db = lambda v: float(10 * np.log10(v))
+    res = {"radar": "Table II chirp, r = 0.145 m, N = 160", "rows": grid.n_range, "range_m": [ranges[0], ranges[-1]],
+           "iterations": prm.iters, "eta_db": db(prm.eta), "phi_mw_deg": 4.0, "interval_deg": 2.0,
+           "u_min": prm.u_min, "lambda_b": prm.lam_b, "ms": ms,
+           "newton_steps_total": int(hist[:, :, 5].sum()),
+           "c1_c2_slack_max": float(max(hist[:, -1, 3].max(), hist[:, -1, 4].max())),
+           "norm_slack_b_max": float(hist[:, -1, 2].max()),
+           "rows_accepted": int(np.count_nonzero(slack < prm.b_min)),
+           "candidates_min_max": [int(cnt.min()), int(cnt.max())],
+           "worst_case_ratio_db_max": db(design.max()),
+           "worst_case_ratio_over_eta_max": float(design.max() / prm.eta),
+           "worst_case_ratio_below_eta": bool(np.all(design <= prm.eta * (1 + 1e-3))),
+           "thresholded": {"th": th_paper, "nonzeros_min_median_max": [int(nnz.min()), int(np.median(nnz)),
+                                                                        int(nnz.max())],
+                           "worst_case_ratio_db_max": db(sparse.max()),
+                           "worst_case_ratio_db_max_fine_grid": db(fine.max())},
+           "note": "float64 GPU design (one workgroup per row) returning every candidate's weight (Th = 0), checked "
+                   "by rosar_beampattern with the same Delta_R on the design's side-lobe grid (below_eta allows 1e-3 "
+                   "relative); then thresholded at the paper's Th = 1e-3 and checked again, also on a 0.05 deg grid "
+                   "(at N = 160 the design grid does not bound the pattern between its points). rows_accepted is the "
+                   "paper's b + b1 + b2 < 1e-5, which the norm slack b of C3/C4 reaches only slowly"}
+    # the paper's size: one FPP-SCA iteration for the 155 testbed rows at N = 800
+    tw = synth.testbed()
+    drp = torch.tensor([0.035 * 2.0 / max(r, 0.5) for r in tw.grid.ranges()], dtype=torch.float64, device=dev)
+    e0.record()
+    dp = rs.sas_design(tw.geometry, tw.grid, drp, rs.sas_params(iters=1))
+    e1.record()
+    torch.cuda.synchronize()
+    hp = dp.history.cpu().numpy()
+    res["paper_size_one_iteration"] = {"rows": tw.grid.n_range, "pulses": 800, "ms": e0.elapsed_time(e1),
+                                       "newton_steps_max_row": int(hp[:, 0, 5].max()),
+                                       "params": "Table V (-33 dB, 1 deg, 0.5 deg interval, U_min 5, lambda_b 50)"}
+    print(f"[bench] FPP-SCA design: {grid.n_range} rows x {prm.iters} iterations at N = 160 in {ms:.0f} ms, "
+          f"worst-case ratio max {res['worst_case_ratio_db_max']:.3f} dB (eta {res['eta_db']:.0f} dB), "
+          f"{res['thresholded']['worst_case_ratio_db_max']:.3f} dB after thresholding; N = 800, 155 rows, one "
+          f"iteration: {res['paper_size_one_iteration']['ms']:.0f} ms", file=sys.stderr, flush=True)
+    return res
+
+
+def testbed_row(torch, rs, synth, dev, timed):
+    """The paper's own instance: Table II radar (N = 800, M = L = 225), the 9.8756 m square area on
+    the 0.04 m lattice (247 x 247 targets): range compression + Algorithm 2 (K = 157) against
+    range compression + back-projection with the true angles, per image."""
+    w = synth.testbed()
+    x = synth.make_inputs(w)
+    g = w.geometry
+    lat = synth.paper_lattice()
+    raw = torch.from_numpy(x.raw).to(dev)
+    win = torch.from_numpy(x.window).to(dev)
+    off = torch.from_numpy(x.offsets).to(dev)
+    wts = torch.from_numpy(x.weights.astype(np.complex64)).to(dev)
+    ang = torch.from_numpy(x.angles).to(dev)
+    rc = rs.range_compress(g, raw, win, x.l_lo, x.l_count, halo=w.sparse.window // 2)
+    img = torch.empty((lat.ny, lat.nx), dtype=torch.complex64, device=dev)
+    t_rc = timed(lambda: rs.range_compress(g, raw, win, x.l_lo, x.l_count, out=rc), 3, inner=10,
+                 out=lambda: rc.data)
+    sf = lambda: rs.sparse_filter_cartesian(g, w.grid, lat, rc, off, wts, w.sparse.window, out=img)
+    sf()
+    t_sf = timed(sf, 3, inner=10, out=lambda: img)
+    bp = lambda: rs.bp_cartesian(g, lat, rc, angles=ang, out=img)
+    bp()
+    t_bp = timed(bp, 3, inner=5, out=lambda: img)
+    px = lat.nx * lat.ny
+    res = {"radar": "Table II: N = 800, M = L = 225 (mixed-radix FFT), r = 0.145 m, 60 GHz, K = 6.8e13 Hz/s, "
+                    "F_s = 4.5 MHz, T_Start = 7 us",
+           "lattice": [lat.ny, lat.nx], "cell_m": lat.dx_m, "area_m": 9.8756, "taps": w.sparse.k,
+           "window": w.sparse.window, "range_compress_us": 1000 * t_rc, "sparse_filter_us": 1000 * t_sf,
+           "bpa_us": 1000 * t_bp, "fft_sas_pixels_per_s": px / ((t_rc + t_sf) * 1e-3),
+           "fft_bpa_pixels_per_s": px / ((t_rc + t_bp) * 1e-3), "fft_sas_vs_fft_bpa": (t_rc + t_bp) / (t_rc + t_sf),
+           "note": "per image; the paper's MATLAB times for this area (Tables VII-VIII) are context only"}
+    print(f"[bench] testbed 247 x 247: range compression {1000 * t_rc:.1f} us, Algorithm 2 {1000 * t_sf:.1f} us, "
+          f"BPA {1000 * t_bp:.1f} us; FFT+SAS {res['fft_sas_vs_fft_bpa']:.1f}x faster than FFT+BPA",
+          file=sys.stderr, flush=True)
+    return res
+
+
 FAILURES: list = []
 
 # --only: one kernel of the path, launched on its own
@@ -802,6 +951,8 @@ def main():
             "note": "float64 |w^H a(phi; R)| at 2049 angles per row + per-row worst-case summary with the Delta_R above"}
         print(f"[bench] beampattern + robust check: {ms_bpat:.3f} ms ({terms / (ms_bpat * 1e-3):.3g} tap terms/s)",
               file=sys.stderr, flush=True)
+        out["rows"]["sas_design"] = sas_design_row(torch, rs, synth, dev)
+        out["rows"]["testbed"] = testbed_row(torch, rs, synth, dev, timed)
     if not a.no_cpu_baseline:
         with Phase(torch, "cpu baseline"):
             out["cpu_baseline"] = cpu_baseline(w, x)

@@ -16,6 +16,8 @@
 //
 // Corrected path (per-pulse angle error dphi and phase error psi): see
 // sparse_corrected_kernel.
+#include <type_traits>
+
 #include "sparse_device.hpp"
 
 namespace rosar {
@@ -182,25 +184,31 @@ constexpr int kCorrMaxCols = 4096;                 // largest per-pulse table he
 
 // Nominal geometry and weight of one tap (no angle error), 48 bytes.
 struct alignas(16) CorrTap {
-  SplitBin u;     // band-relative bin beta * R_nom - l_lo (+ 1/2 for NEAREST), split
-  float r2;       // R_nom^2
-  float rnom;     // R_nom
-  float sd, cd;   // sin, cos of D0 = 2 pi o / N
-  float wr, wi;   // weight (zero for an offset outside the window)
-  int32_t o;      // offset
-  int32_t pad;
+  SplitBin u;       // band-relative bin beta * R_nom - l_lo (+ 1/2 for NEAREST), split
+  float r2;         // R_nom^2
+  float rnom;       // R_nom
+  float sd, cd;     // sin, cos of D0 = 2 pi o / N
+  float wr, wi;     // weight (zero for an offset outside the window)
+  float q1, q2, q3; // Taylor coefficients at D0: R(D0 + d) - R_nom = d (q1 + d (q2 + d q3)) + O(d^4)
+  int32_t o;        // offset
 };
 
 // Corrected path: the angle error d_n and phase error psi_n of pulse n move the slant range of
-// every (pixel, tap) pair: R^ = R(D0 + d_n).  The workgroup (one row, kCorrTile pixels)
-// computes the taps' nominal geometry in float64 into LDS and stages, per column of pulses
-// [a0 - W/2, a0 + T + W/2), (sin(d/2), cos(d/2), psi / 2 pi).  Per pair only the correction is
-// evaluated, in float32 and without cancellation:
-//   R^2 - R_nom^2 = 4 R r sin(D0 + d/2) sin(d/2),  R^ - R_nom = (R^2 - R_nom^2) / (R^ + R_nom),
-// the bin is the float64 nominal bin plus beta (R^ - R_nom), the sample comes through buffer
-// loads (out-of-band rows read zero), and the phase factor exp(-j (2 k (R^ - R_nom) + psi))
-// runs on the hardware sine/cosine in revolutions.  TABLE = false (window too wide for the
-// LDS table) evaluates the per-pulse values for every pair from global memory.
+// every (pixel, tap) pair: R^ = R(D0 + d_n), R(D) = sqrt(R^2 + r^2 - 2 R r cos D).  The
+// workgroup (one row, kCorrTile pixels) computes the taps' nominal geometry in float64 into LDS
+// and stages, per column of pulses [a0 - W/2, a0 + T + W/2), (sin(d/2), cos(d/2), psi / 2 pi,
+// d).  Per pair only the correction R^ - R_nom is evaluated, in float32, one of two ways:
+//  - series: the cubic Taylor polynomial of R(D0 + d) - R(D0) in d, with float64 coefficients
+//    per tap.  Its remainder is at most max|R''''| d^4 / 24, and |R''''| peaks at D = 0 with
+//    c/(2 rho) + 3 c^2 / (4 rho^3) (c = 2 R r, rho = R - r).  The workgroup takes this path when
+//    twice that bound at the largest |d| of its pulse table is below 1e-6 rad of carrier phase
+//    and 2^-20 bins (the workloads' angle errors of a few milliradians are far inside it);
+//  - exact otherwise: R^2 - R_nom^2 = 4 R r sin(D0 + d/2) sin(d/2) and
+//    R^ - R_nom = (R^2 - R_nom^2) / (R^ + R_nom), without cancellation.
+// The bin is the float64 nominal bin plus beta (R^ - R_nom), the sample comes through buffer
+// loads (out-of-band rows read zero), and the phase factor exp(-j (2 k (R^ - R_nom) + psi)) runs
+// on the hardware sine/cosine in revolutions.  TABLE = false (window too wide for the LDS table)
+// evaluates the per-pulse values for every pair from global memory, on the exact path.
 template <int DT, int WDT, int INTERP, bool TABLE>
 __global__ __launch_bounds__(kCorrThreads) void sparse_corrected_kernel(
     Geo g, View y, int32_t k, int32_t window, int tiles_per_row, int nblocks,
@@ -210,6 +218,7 @@ __global__ __launch_bounds__(kCorrThreads) void sparse_corrected_kernel(
   constexpr int ES = Elem<DT>::bytes;
   constexpr float kInv2Pi = 0.15915494309189533577f;
   __shared__ CorrTap s_tap[kCorrChunk];
+  __shared__ float s_red[kCorrThreads / kWave];
   extern __shared__ float4 s_pul[];   // TABLE: kCorrTile + window entries
   const int blk = xcd_logical_block(blockIdx.x, nblocks);
   const int row = blk / tiles_per_row;
@@ -220,18 +229,38 @@ __global__ __launch_bounds__(kCorrThreads) void sparse_corrected_kernel(
   const int lane = threadIdx.x & (kWave - 1);
   const int wave = threadIdx.x / kWave;
   const int i_wave = wave * kWave * kCorrP;
+  const double rr = g.r0 + row * g.dr;
 
+  bool series = false;
   if constexpr (TABLE) {
+    float dmax = 0.f;
     for (int c = threadIdx.x; c < kCorrTile + window; c += kCorrThreads) {
       int pn = (a0 - half_w + c) % n;
       pn += pn < 0 ? n : 0;
-      float sh = 0.f, ch = 1.f;
-      if (dphi) sincosf(0.5f * dphi[pn], &sh, &ch);
-      s_pul[c] = make_float4(sh, ch, dpsi ? dpsi[pn] * kInv2Pi : 0.f, 0.f);
+      float sh = 0.f, ch = 1.f, d = 0.f;
+      if (dphi) {
+        d = dphi[pn];
+        sincosf(0.5f * d, &sh, &ch);
+      }
+      dmax = fmaxf(dmax, fabsf(d));
+      s_pul[c] = make_float4(sh, ch, dpsi ? dpsi[pn] * kInv2Pi : 0.f, d);
+    }
+    for (int off = kWave / 2; off > 0; off >>= 1) dmax = fmaxf(dmax, __shfl_xor(dmax, off));
+    if (lane == 0) s_red[wave] = dmax;
+    __syncthreads();
+    dmax = s_red[0];
+#pragma unroll
+    for (int w = 1; w < kCorrThreads / kWave; ++w) dmax = fmaxf(dmax, s_red[w]);
+    const double rho = rr - g.radius;
+    if (rho > 0.0 && dmax == dmax) {
+      const double c = 2.0 * rr * g.radius;
+      const double m4 = 2.0 * (c / (2.0 * rho) + 0.75 * c * c / (rho * rho * rho));
+      const double d2 = (double)dmax * (double)dmax;
+      const double rem = m4 * d2 * d2 / 24.0;   // metres
+      series = rem * (kTwoPiD * g.k_over_pi) <= 1e-6 && rem * g.beta <= 0x1p-20;
     }
   }
 
-  const double rr = g.r0 + row * g.dr;
   const double c1 = rr * rr + g.radius * g.radius;
   const double c2 = 2.0 * rr * g.radius;
   const float c4 = (float)(2.0 * c2);   // 4 R r
@@ -250,93 +279,111 @@ __global__ __launch_bounds__(kCorrThreads) void sparse_corrected_kernel(
     acc[p] = make_float2(0.f, 0.f);
   }
 
-  for (int c0 = 0; c0 < k; c0 += kCorrChunk) {
-    const int cnt = min(kCorrChunk, k - c0);
-    if ((int)threadIdx.x < cnt) {
-      const int t = c0 + (int)threadIdx.x;
-      const int o = offsets[wrow + t];
-      const float2 w = load_w<WDT>(weights, wrow + t);
-      const bool inwin = o >= -half_w && o < half_w;
-      double sd, cd;
-      sincos(o * g.step, &sd, &cd);
-      const double r2 = c1 - c2 * cd;
-      const double rn = sqrt(r2);
-      CorrTap e;
-      e.u = split_bin(g.beta * rn + u_shift);
-      e.r2 = (float)r2;
-      e.rnom = (float)rn;
-      e.sd = (float)sd;
-      e.cd = (float)cd;
-      e.wr = inwin ? w.x : 0.f;
-      e.wi = inwin ? w.y : 0.f;
-      e.o = inwin ? o : 0;
-      e.pad = 0;
-      s_tap[threadIdx.x] = e;
-    }
-    __syncthreads();
-    for (int t = 0; t < cnt; ++t) {
-      const CorrTap tp = s_tap[t];
-      const float2 w = make_float2(tp.wr, tp.wi);
+  // the tap loop, with the series (SERIES = true) or the exact correction
+  auto taps = [&](auto series_tag) {
+    constexpr bool SERIES = decltype(series_tag)::value;
+    for (int c0 = 0; c0 < k; c0 += kCorrChunk) {
+      const int cnt = min(kCorrChunk, k - c0);
+      if ((int)threadIdx.x < cnt) {
+        const int t = c0 + (int)threadIdx.x;
+        const int o = offsets[wrow + t];
+        const float2 w = load_w<WDT>(weights, wrow + t);
+        const bool inwin = o >= -half_w && o < half_w;
+        double sd, cd;
+        sincos(o * g.step, &sd, &cd);
+        const double r2 = c1 - c2 * cd;
+        const double rn = sqrt(r2);
+        CorrTap e;
+        e.u = split_bin(g.beta * rn + u_shift);
+        e.r2 = (float)r2;
+        e.rnom = (float)rn;
+        e.sd = (float)sd;
+        e.cd = (float)cd;
+        e.wr = inwin ? w.x : 0.f;
+        e.wi = inwin ? w.y : 0.f;
+        // derivatives of R(D) = sqrt(S), S = c1 - c2 cos D, at D0 (S' = c2 sin D0, S'' = c2 cos D0)
+        const double s1 = c2 * sd, s2 = c2 * cd;
+        const double ir = 1.0 / rn, ir3 = ir * ir * ir, ir5 = ir3 * ir * ir;
+        e.q1 = (float)(0.5 * s1 * ir);
+        e.q2 = (float)(0.5 * (0.5 * s2 * ir - 0.25 * s1 * s1 * ir3));
+        e.q3 = (float)((-0.5 * s1 * ir - 0.75 * s1 * s2 * ir3 + 0.375 * s1 * s1 * s1 * ir5) / 6.0);
+        e.o = inwin ? o : 0;
+        s_tap[threadIdx.x] = e;
+      }
+      __syncthreads();
+      for (int t = 0; t < cnt; ++t) {
+        const CorrTap tp = s_tap[t];
+        const float2 w = make_float2(tp.wr, tp.wi);
 #pragma unroll
-      for (int p = 0; p < kCorrP; ++p) {
-        float sh, ch, pr;
-        int col = acol[p] + tp.o;
-        if constexpr (TABLE) {
-          const float4 q = s_pul[i_wave + lane + kWave * p + tp.o + half_w];
-          sh = q.x;
-          ch = q.y;
-          pr = q.z;
-        } else {
-          int pn = col;
-          pn += (pn < 0) ? n : 0;
-          pn -= (pn >= n) ? n : 0;
-          sh = 0.f;
-          ch = 1.f;
-          if (dphi) sincosf(0.5f * dphi[pn], &sh, &ch);
-          pr = dpsi ? dpsi[pn] * kInv2Pi : 0.f;
-        }
-        if (!direct) {
-          col += (col < 0) ? n : 0;
-          col -= (col >= n) ? n : 0;
-        }
-        const int cb = (col + y.halo) * ES;
-        const float s_mid = fmaf(tp.sd, ch, tp.cd * sh);   // sin(D0 + d/2)
-        const float dd = c4 * s_mid * sh;                    // R^2 - R_nom^2
-        const float r2 = fmaxf(tp.r2 + dd, 1e-30f);
-        const float rn = r2 * __builtin_amdgcn_rsqf(r2);
-        const float diff = dd * __builtin_amdgcn_rcpf(rn + tp.rnom);   // R^ - R_nom
-        const float corr = beta * diff;
-        float fr;
-        bool tie;
-        int l = corr_bin(tp.u, corr, &fr, &tie);
-        float2 smp;
-        if constexpr (INTERP == ROSAR_NEAREST) {
-          if (__builtin_expect(tie, 0)) {
-            // plain float64 bin at the angle (o 2 pi) / N + delta_n of the oracle's definition
-            int pn = acol[p] + tp.o;
+        for (int p = 0; p < kCorrP; ++p) {
+          float sh = 0.f, ch = 1.f, pr, dn = 0.f;
+          int col = acol[p] + tp.o;
+          if constexpr (TABLE) {
+            const float4 q = s_pul[i_wave + lane + kWave * p + tp.o + half_w];
+            sh = q.x;
+            ch = q.y;
+            pr = q.z;
+            dn = q.w;
+          } else {
+            int pn = col;
             pn += (pn < 0) ? n : 0;
             pn -= (pn >= n) ? n : 0;
-            const double d = (double)tp.o * g.step + (dphi ? (double)dphi[pn] : 0.0);
-            l = (int)floor(plain_bin_half(rr, g.radius, d, g.beta)) - y.l_lo;
+            if (dphi) sincosf(0.5f * dphi[pn], &sh, &ch);
+            pr = dpsi ? dpsi[pn] * kInv2Pi : 0.f;
           }
-          l = min(max(l, -1), y.l_count);
-          smp = buf_load<DT>(rsrc, (uint32_t)(__mul24(l, ld_es) + cb), 0u);
-        } else {
-          l = min(max(l, -2), y.l_count);
-          const uint32_t off0 = (uint32_t)(__mul24(l, ld_es) + cb);
-          const float2 y0 = buf_load<DT>(rsrc, off0, 0u);
-          const float2 y1 = buf_load<DT>(rsrc, off0 + (uint32_t)ld_es, 0u);
-          smp = make_float2(fmaf(fr, y1.x - y0.x, y0.x), fmaf(fr, y1.y - y0.y, y0.y));
+          if (!direct) {
+            col += (col < 0) ? n : 0;
+            col -= (col >= n) ? n : 0;
+          }
+          const int cb = (col + y.halo) * ES;
+          float diff;   // R^ - R_nom
+          if constexpr (SERIES) {
+            diff = dn * fmaf(dn, fmaf(dn, tp.q3, tp.q2), tp.q1);
+          } else {
+            const float s_mid = fmaf(tp.sd, ch, tp.cd * sh);   // sin(D0 + d/2)
+            const float dd = c4 * s_mid * sh;                    // R^2 - R_nom^2
+            const float r2 = fmaxf(tp.r2 + dd, 1e-30f);
+            const float rn = r2 * __builtin_amdgcn_rsqf(r2);
+            diff = dd * __builtin_amdgcn_rcpf(rn + tp.rnom);
+          }
+          const float corr = beta * diff;
+          float fr;
+          bool tie;
+          int l = corr_bin(tp.u, corr, &fr, &tie);
+          float2 smp;
+          if constexpr (INTERP == ROSAR_NEAREST) {
+            if (__builtin_expect(tie, 0)) {
+              // plain float64 bin at the angle (o 2 pi) / N + delta_n of the oracle's definition
+              int pn = acol[p] + tp.o;
+              pn += (pn < 0) ? n : 0;
+              pn -= (pn >= n) ? n : 0;
+              const double d = (double)tp.o * g.step + (dphi ? (double)dphi[pn] : 0.0);
+              l = (int)floor(plain_bin_half(rr, g.radius, d, g.beta)) - y.l_lo;
+            }
+            l = min(max(l, -1), y.l_count);
+            smp = buf_load<DT>(rsrc, (uint32_t)(__mul24(l, ld_es) + cb), 0u);
+          } else {
+            l = min(max(l, -2), y.l_count);
+            const uint32_t off0 = (uint32_t)(__mul24(l, ld_es) + cb);
+            const float2 y0 = buf_load<DT>(rsrc, off0, 0u);
+            const float2 y1 = buf_load<DT>(rsrc, off0 + (uint32_t)ld_es, 0u);
+            smp = make_float2(fmaf(fr, y1.x - y0.x, y0.x), fmaf(fr, y1.y - y0.y, y0.y));
+          }
+          // exp(-j (2 k (R^ - R_nom) + psi)) in revolutions
+          float rev = fmaf(kpi, diff, pr);
+          rev -= floorf(rev);
+          const float2 rot = make_float2(cos_rev(rev), -sin_rev(rev));
+          cmac_conj(acc[p], w, cmul(smp, rot));
         }
-        // exp(-j (2 k (R^ - R_nom) + psi)) in revolutions
-        float rev = fmaf(kpi, diff, pr);
-        rev -= floorf(rev);
-        const float2 rot = make_float2(cos_rev(rev), -sin_rev(rev));
-        cmac_conj(acc[p], w, cmul(smp, rot));
       }
+      __syncthreads();
     }
-    __syncthreads();
-  }
+  };
+  if (series)
+    taps(std::true_type{});
+  else
+    taps(std::false_type{});
+
   float2* out = image + (int64_t)row * n;
 #pragma unroll
   for (int p = 0; p < kCorrP; ++p) {
