@@ -14,11 +14,16 @@
 // feeds conj(g) s into a per-tap partial reduced across the wavefront and then across the
 // waves in a fixed order.  The taps' nominal geometry (float64 bin of R_nom, R_nom, sin/cos of
 // D0 = 2 pi o / N) and weights sit in an LDS table; per (pulse, tap) only the angle-error
-// correction is evaluated, in float32 without cancellation:
+// correction is evaluated in float32.  As in the corrected forward it is either the cubic
+// Taylor polynomial of R(D0 + d) - R(D0) in d (and its derivative for dR^/dd), taken when the
+// workgroup's fourth-derivative remainder bound at the rotation's largest |d| is below 1e-6 rad
+// of carrier phase and 2^-20 bins, or otherwise the exact form without cancellation:
 //   R^2 - R_nom^2 = 4 R r sin(D0 + d/2) sin(d/2),   R^ - R_nom = (R^2 - R_nom^2)/(R^ + R_nom),
 // with the bin formed in float64 and the samples read through buffer loads (out-of-band rows
 // read zero).  Row partials of grad_dphi/grad_dpsi go to the workspace; a two-stage reduction
 // sums them over rows in a fixed order (groups of rows, then the groups).
+#include <type_traits>
+
 #include "rosar_device.hpp"
 
 namespace rosar {
@@ -30,7 +35,7 @@ constexpr int kBwPpt = 8;      // pulses per thread per pass
 constexpr int kBwChunk = kBwThreads;   // taps per LDS table chunk
 constexpr int kRedGroups = 32;         // row groups of the first reduction stage
 
-// Nominal geometry and weight of one tap, 48 bytes.
+// Nominal geometry and weight of one tap, 80 bytes.
 struct alignas(16) BwTap {
   SplitBin u;     // band-relative bin beta * R_nom - l_lo (+ 1/2 for NEAREST), split
   float r2;       // R_nom^2
@@ -39,6 +44,8 @@ struct alignas(16) BwTap {
   float wr, wi;   // weight
   int32_t o;      // offset
   int32_t valid;  // offset inside the window
+  float q1, q2, q3;   // Taylor coefficients at D0: R(D0 + d) - R_nom = d (q1 + d (q2 + d q3))
+  float p2, p3;       // 2 q2, 3 q3: dR^/dd = q1 + d (p2 + d p3)
 };
 
 __device__ __forceinline__ float2 wave_sum(float2 v) {
@@ -60,6 +67,7 @@ __global__ __launch_bounds__(kBwThreads) void backward_row_kernel(
   constexpr float kInv2Pi = 0.15915494309189533577f;
   extern __shared__ float2 s_gw[];   // [kBwWaves][k]: per-wave grad_w partials
   __shared__ BwTap s_tap[kBwChunk];
+  __shared__ float s_red[kBwWaves];
   const int lane = threadIdx.x & (kWave - 1);
   const int wave = threadIdx.x / kWave;
   const int row = xcd_logical_block(blockIdx.x, nblocks);
@@ -69,6 +77,28 @@ __global__ __launch_bounds__(kBwThreads) void backward_row_kernel(
     for (int w = 0; w < kBwWaves; ++w) s_gw[w * k + t] = make_float2(0.f, 0.f);
 
   const double rr = g.r0 + row * g.dr;
+  // the series path when the remainder bound (see the corrected forward) holds at max |d|
+  bool series = false;
+  {
+    float dmax = 0.f;
+    if (dphi)
+      for (int pn = threadIdx.x; pn < n; pn += kBwThreads) dmax = fmaxf(dmax, fabsf(dphi[pn]));
+    for (int off = kWave / 2; off > 0; off >>= 1) dmax = fmaxf(dmax, __shfl_xor(dmax, off));
+    if (lane == 0) s_red[wave] = dmax;
+    __syncthreads();
+    dmax = s_red[0];
+#pragma unroll
+    for (int w = 1; w < kBwWaves; ++w) dmax = fmaxf(dmax, s_red[w]);
+    const double rho = rr - g.radius;
+    if (rho > 0.0 && dmax == dmax) {
+      const double c = 2.0 * rr * g.radius;
+      const double m4 = 2.0 * (c / (2.0 * rho) + 0.75 * c * c / (rho * rho * rho));
+      const double d2 = (double)dmax * (double)dmax;
+      const double rem = m4 * d2 * d2 / 24.0;   // metres
+      series = rem * (kTwoPiD * g.k_over_pi) <= 1e-6 && rem * g.beta <= 0x1p-20 &&
+               g.beta * g.radius * (double)dmax < 0.5 && g.k_over_pi * g.radius * (double)dmax < 64.0;
+    }
+  }
   const double c1 = rr * rr + g.radius * g.radius;
   const double c2 = 2.0 * rr * g.radius;
   const float c4 = (float)(2.0 * c2);          // 4 R r
@@ -83,16 +113,20 @@ __global__ __launch_bounds__(kBwThreads) void backward_row_kernel(
   const int64_t wrow = (int64_t)row * k;
   const float2* grow = gimg + (int64_t)row * n;
 
+  auto passes = [&](auto series_tag) {
+  constexpr bool SERIES = decltype(series_tag)::value;
   for (int base = 0; base < n; base += kBwThreads * kBwPpt) {
-    float sh[kBwPpt], ch[kBwPpt], pr[kBwPpt], gd[kBwPpt], gp[kBwPpt];
+    float sh[kBwPpt], ch[kBwPpt], pr[kBwPpt], dn[kBwPpt], gd[kBwPpt], gp[kBwPpt];
     int cb[kBwPpt];   // byte offset of the pulse's column within a row
 #pragma unroll
     for (int j = 0; j < kBwPpt; ++j) {
       const int pn = min(base + (int)threadIdx.x + kBwThreads * j, n - 1);
       sh[j] = 0.f;
       ch[j] = 1.f;
-      if (dphi) sincosf(0.5f * dphi[pn], &sh[j], &ch[j]);
+      dn[j] = dphi ? dphi[pn] : 0.f;
+      if (dphi) sincosf(0.5f * dn[j], &sh[j], &ch[j]);
       pr[j] = dpsi ? dpsi[pn] * kInv2Pi : 0.f;
+      pr[j] -= rintf(pr[j]);
       cb[j] = (pn + y.halo) * ES;
       gd[j] = 0.f;
       gp[j] = 0.f;
@@ -110,6 +144,18 @@ __global__ __launch_bounds__(kBwThreads) void backward_row_kernel(
         const float2 w = weights[wrow + t];
         BwTap e;
         e.u = split_bin(g.beta * rn + u_shift);
+        if constexpr (SERIES) e.u.i = min(max(e.u.i, -3), y.l_count + 2);
+        // derivatives of R(D) = sqrt(S), S = c1 - c2 cos D, at D0 (S' = c2 sin D0, S'' = c2 cos D0)
+        const double s1 = c2 * sd, s2 = c2 * cd;
+        const double ir = 1.0 / rn, ir3 = ir * ir * ir, ir5 = ir3 * ir * ir;
+        const double q1 = 0.5 * s1 * ir;
+        const double q2 = 0.5 * (0.5 * s2 * ir - 0.25 * s1 * s1 * ir3);
+        const double q3 = (-0.5 * s1 * ir - 0.75 * s1 * s2 * ir3 + 0.375 * s1 * s1 * s1 * ir5) / 6.0;
+        e.q1 = (float)q1;
+        e.q2 = (float)q2;
+        e.q3 = (float)q3;
+        e.p2 = (float)(2.0 * q2);
+        e.p3 = (float)(3.0 * q3);
         e.r2 = (float)r2;
         e.rnom = (float)rn;
         e.sd = (float)sd;
@@ -133,12 +179,22 @@ __global__ __launch_bounds__(kBwThreads) void backward_row_kernel(
           ap -= (ap >= n) ? n : 0;
           // pulses past N (last pass) take a zero gradient sample: they add nothing
           const float2 gv = pn < n ? grow[ap] : make_float2(0.f, 0.f);
-          const float s_mid = fmaf(tp.sd, ch[j], tp.cd * sh[j]);   // sin(D0 + d/2)
-          const float dd = c4 * s_mid * sh[j];                      // R^2 - R_nom^2
-          const float r2 = fmaxf(tp.r2 + dd, 1e-30f);
-          const float rs = __builtin_amdgcn_rsqf(r2);
-          const float rh = r2 * rs;
-          const float diff = dd * __builtin_amdgcn_rcpf(rh + tp.rnom);   // R^ - R_nom
+          float diff, dr;   // R^ - R_nom and dR^/dd
+          if constexpr (SERIES) {
+            diff = dn[j] * fmaf(dn[j], fmaf(dn[j], tp.q3, tp.q2), tp.q1);
+            dr = fmaf(dn[j], fmaf(dn[j], tp.p3, tp.p2), tp.q1);
+          } else {
+            const float s_mid = fmaf(tp.sd, ch[j], tp.cd * sh[j]);   // sin(D0 + d/2)
+            const float dd = c4 * s_mid * sh[j];                      // R^2 - R_nom^2
+            const float r2 = fmaxf(tp.r2 + dd, 1e-30f);
+            const float rs = __builtin_amdgcn_rsqf(r2);
+            const float rh = r2 * rs;
+            diff = dd * __builtin_amdgcn_rcpf(rh + tp.rnom);
+            // dR^/dd = R r sin(D) / R^,  D = D0 + d:
+            // sin D = sin D0 (1 - 2 sin^2(d/2)) + cos D0 2 sin(d/2) cos(d/2)
+            const float sind = fmaf(tp.sd, fmaf(-2.f * sh[j], sh[j], 1.f), tp.cd * 2.f * sh[j] * ch[j]);
+            dr = rrr * sind * rs;
+          }
           const float corr = beta * diff;
           float fr;
           bool tie;
@@ -149,11 +205,12 @@ __global__ __launch_bounds__(kBwThreads) void backward_row_kernel(
               // plain float64 bin at the angle (o 2 pi) / N + delta_n of the oracle's definition
               const double d = (double)tp.o * g.step + (dphi ? (double)dphi[min(pn, n - 1)] : 0.0);
               l = (int)floor(plain_bin_half(rr, g.radius, d, g.beta)) - y.l_lo;
+              l = min(max(l, -1), y.l_count);
             }
-            l = min(max(l, -1), y.l_count);
+            if constexpr (!SERIES) l = min(max(l, -1), y.l_count);
             yv = buf_load<DT>(rsrc, (uint32_t)(__mul24(l, ld_es) + cb[j]), 0u);
           } else {
-            l = min(max(l, -2), y.l_count);
+            if constexpr (!SERIES) l = min(max(l, -2), y.l_count);
             const uint32_t off0 = (uint32_t)(__mul24(l, ld_es) + cb[j]);
             const float2 y0 = buf_load<DT>(rsrc, off0, 0u);
             const float2 y1 = buf_load<DT>(rsrc, off0 + (uint32_t)ld_es, 0u);
@@ -163,16 +220,13 @@ __global__ __launch_bounds__(kBwThreads) void backward_row_kernel(
           yv.x *= isc;
           yv.y *= isc;
           float rev = fmaf(kpi, diff, pr[j]);
-          rev -= floorf(rev);
+          if constexpr (!SERIES) rev -= floorf(rev);
           const float2 rot = make_float2(cos_rev(rev), -sin_rev(rev));
           const float2 s = cmul(yv, rot);
           // conj(g) s
           gw.x = fmaf(gv.x, s.x, fmaf(gv.y, s.y, gw.x));
           gw.y = fmaf(gv.x, s.y, fmaf(-gv.y, s.x, gw.y));
-          // ds/d dphi = rot (beta dY/du - j 2k Y) R r sin(D) / R^,  D = D0 + d:
-          // sin D = sin D0 (1 - 2 sin^2(d/2)) + cos D0 2 sin(d/2) cos(d/2)
-          const float sind = fmaf(tp.sd, fmaf(-2.f * sh[j], sh[j], 1.f), tp.cd * 2.f * sh[j] * ch[j]);
-          const float dr = rrr * sind * rs;
+          // ds/d dphi = rot (beta dY/du - j 2k Y) dR^/dd
           const float2 inner = make_float2(beta * dy.x + two_k * yv.y, beta * dy.y - two_k * yv.x);
           const float2 dsd = cmul(rot, inner);
           // z = conj(g) conj(w) = conj(g w)
@@ -199,6 +253,11 @@ __global__ __launch_bounds__(kBwThreads) void backward_row_kernel(
       }
     }
   }
+  };
+  if (series)
+    passes(std::true_type{});
+  else
+    passes(std::false_type{});
   __syncthreads();
   if (grad_w) {
     for (int t = threadIdx.x; t < k; t += kBwThreads) {

@@ -202,7 +202,12 @@ struct alignas(16) CorrTap {
 //    per tap.  Its remainder is at most max|R''''| d^4 / 24, and |R''''| peaks at D = 0 with
 //    c/(2 rho) + 3 c^2 / (4 rho^3) (c = 2 R r, rho = R - r).  The workgroup takes this path when
 //    twice that bound at the largest |d| of its pulse table is below 1e-6 rad of carrier phase
-//    and 2^-20 bins (the workloads' angle errors of a few milliradians are far inside it);
+//    and 2^-20 bins, and when beta r |d| < 1/2 (|dR/dD| <= r, so the correction moves a bin by
+//    less than one): the workloads' angle errors of a few milliradians are far inside it.  The
+//    nominal bin is then clamped once per tap to [-3, l_count + 2], so every sampled row stays
+//    out of the band when the nominal one is (zero by the buffer's range check) and no per-pair
+//    clamp is needed; the phase (psi / 2 pi reduced to [-1/2, 1/2] in the table) stays within
+//    the hardware sine's input range without a floor;
 //  - exact otherwise: R^2 - R_nom^2 = 4 R r sin(D0 + d/2) sin(d/2) and
 //    R^ - R_nom = (R^2 - R_nom^2) / (R^ + R_nom), without cancellation.
 // The bin is the float64 nominal bin plus beta (R^ - R_nom), the sample comes through buffer
@@ -243,7 +248,9 @@ __global__ __launch_bounds__(kCorrThreads) void sparse_corrected_kernel(
         sincosf(0.5f * d, &sh, &ch);
       }
       dmax = fmaxf(dmax, fabsf(d));
-      s_pul[c] = make_float4(sh, ch, dpsi ? dpsi[pn] * kInv2Pi : 0.f, d);
+      float pr = dpsi ? dpsi[pn] * kInv2Pi : 0.f;
+      pr -= rintf(pr);
+      s_pul[c] = make_float4(sh, ch, pr, d);
     }
     for (int off = kWave / 2; off > 0; off >>= 1) dmax = fmaxf(dmax, __shfl_xor(dmax, off));
     if (lane == 0) s_red[wave] = dmax;
@@ -257,7 +264,8 @@ __global__ __launch_bounds__(kCorrThreads) void sparse_corrected_kernel(
       const double m4 = 2.0 * (c / (2.0 * rho) + 0.75 * c * c / (rho * rho * rho));
       const double d2 = (double)dmax * (double)dmax;
       const double rem = m4 * d2 * d2 / 24.0;   // metres
-      series = rem * (kTwoPiD * g.k_over_pi) <= 1e-6 && rem * g.beta <= 0x1p-20;
+      series = rem * (kTwoPiD * g.k_over_pi) <= 1e-6 && rem * g.beta <= 0x1p-20 &&
+               g.beta * g.radius * (double)dmax < 0.5 && g.k_over_pi * g.radius * (double)dmax < 64.0;
     }
   }
 
@@ -269,7 +277,6 @@ __global__ __launch_bounds__(kCorrThreads) void sparse_corrected_kernel(
   const double u_shift = INTERP == ROSAR_NEAREST ? 0.5 - y.l_lo : -(double)y.l_lo;
   const __amdgpu_buffer_rsrc_t rsrc = make_rsrc(ydata, (uint32_t)((int64_t)y.l_count * y.ld * ES));
   const int ld_es = (int)(y.ld * ES);
-  const bool direct = y.halo >= half_w;   // the halo holds every column a + o (no wrap)
   const int64_t wrow = (int64_t)row * k;
   int acol[kCorrP];   // pixel column, clamped into the rotation for padding lanes
   float2 acc[kCorrP];
@@ -279,9 +286,11 @@ __global__ __launch_bounds__(kCorrThreads) void sparse_corrected_kernel(
     acc[p] = make_float2(0.f, 0.f);
   }
 
-  // the tap loop, with the series (SERIES = true) or the exact correction
-  auto taps = [&](auto series_tag) {
+  // the tap loop, with the series (SERIES = true) or the exact correction; DIRECT: the halo
+  // holds every column a + o (no wrap)
+  auto taps = [&](auto series_tag, auto direct_tag) {
     constexpr bool SERIES = decltype(series_tag)::value;
+    constexpr bool DIRECT = decltype(direct_tag)::value;
     for (int c0 = 0; c0 < k; c0 += kCorrChunk) {
       const int cnt = min(kCorrChunk, k - c0);
       if ((int)threadIdx.x < cnt) {
@@ -295,6 +304,7 @@ __global__ __launch_bounds__(kCorrThreads) void sparse_corrected_kernel(
         const double rn = sqrt(r2);
         CorrTap e;
         e.u = split_bin(g.beta * rn + u_shift);
+        if constexpr (SERIES) e.u.i = min(max(e.u.i, -3), y.l_count + 2);
         e.r2 = (float)r2;
         e.rnom = (float)rn;
         e.sd = (float)sd;
@@ -331,7 +341,7 @@ __global__ __launch_bounds__(kCorrThreads) void sparse_corrected_kernel(
             if (dphi) sincosf(0.5f * dphi[pn], &sh, &ch);
             pr = dpsi ? dpsi[pn] * kInv2Pi : 0.f;
           }
-          if (!direct) {
+          if constexpr (!DIRECT) {
             col += (col < 0) ? n : 0;
             col -= (col >= n) ? n : 0;
           }
@@ -359,11 +369,12 @@ __global__ __launch_bounds__(kCorrThreads) void sparse_corrected_kernel(
               pn -= (pn >= n) ? n : 0;
               const double d = (double)tp.o * g.step + (dphi ? (double)dphi[pn] : 0.0);
               l = (int)floor(plain_bin_half(rr, g.radius, d, g.beta)) - y.l_lo;
+              l = min(max(l, -1), y.l_count);
             }
-            l = min(max(l, -1), y.l_count);
+            if constexpr (!SERIES) l = min(max(l, -1), y.l_count);
             smp = buf_load<DT>(rsrc, (uint32_t)(__mul24(l, ld_es) + cb), 0u);
           } else {
-            l = min(max(l, -2), y.l_count);
+            if constexpr (!SERIES) l = min(max(l, -2), y.l_count);
             const uint32_t off0 = (uint32_t)(__mul24(l, ld_es) + cb);
             const float2 y0 = buf_load<DT>(rsrc, off0, 0u);
             const float2 y1 = buf_load<DT>(rsrc, off0 + (uint32_t)ld_es, 0u);
@@ -371,7 +382,7 @@ __global__ __launch_bounds__(kCorrThreads) void sparse_corrected_kernel(
           }
           // exp(-j (2 k (R^ - R_nom) + psi)) in revolutions
           float rev = fmaf(kpi, diff, pr);
-          rev -= floorf(rev);
+          if constexpr (!SERIES) rev -= floorf(rev);
           const float2 rot = make_float2(cos_rev(rev), -sin_rev(rev));
           cmac_conj(acc[p], w, cmul(smp, rot));
         }
@@ -379,10 +390,18 @@ __global__ __launch_bounds__(kCorrThreads) void sparse_corrected_kernel(
       __syncthreads();
     }
   };
-  if (series)
-    taps(std::true_type{});
-  else
-    taps(std::false_type{});
+  const bool direct = y.halo >= half_w;
+  if (series) {
+    if (direct)
+      taps(std::true_type{}, std::true_type{});
+    else
+      taps(std::true_type{}, std::false_type{});
+  } else {
+    if (direct)
+      taps(std::false_type{}, std::true_type{});
+    else
+      taps(std::false_type{}, std::false_type{});
+  }
 
   float2* out = image + (int64_t)row * n;
 #pragma unroll
