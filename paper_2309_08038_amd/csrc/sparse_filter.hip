@@ -196,8 +196,9 @@ struct alignas(16) CorrTap {
 // Corrected path: the angle error d_n and phase error psi_n of pulse n move the slant range of
 // every (pixel, tap) pair: R^ = R(D0 + d_n), R(D) = sqrt(R^2 + r^2 - 2 R r cos D).  The
 // workgroup (one row, kCorrTile pixels) computes the taps' nominal geometry in float64 into LDS
-// and stages, per column of pulses [a0 - W/2, a0 + T + W/2), (sin(d/2), cos(d/2), psi / 2 pi,
-// d).  Per pair only the correction R^ - R_nom is evaluated, in float32, one of two ways:
+// and stages, per column of pulses [a0 - W/2, a0 + T + W/2), (psi / 2 pi, d) and
+// (sin(d/2), cos(d/2)) as two float2 tables (the series path reads only the first, with
+// conflict-free 8-byte loads).  Per pair only the correction R^ - R_nom is evaluated, in float32, one of two ways:
 //  - series: the cubic Taylor polynomial of R(D0 + d) - R(D0) in d, with float64 coefficients
 //    per tap.  Its remainder is at most max|R''''| d^4 / 24, and |R''''| peaks at D = 0 with
 //    c/(2 rho) + 3 c^2 / (4 rho^3) (c = 2 R r, rho = R - r).  The workgroup takes this path when
@@ -224,7 +225,7 @@ __global__ __launch_bounds__(kCorrThreads) void sparse_corrected_kernel(
   constexpr float kInv2Pi = 0.15915494309189533577f;
   __shared__ CorrTap s_tap[kCorrChunk];
   __shared__ float s_red[kCorrThreads / kWave];
-  extern __shared__ float4 s_pul[];   // TABLE: kCorrTile + window entries
+  extern __shared__ float2 s_pul[];   // TABLE: (psi / 2 pi, d) then (sin(d/2), cos(d/2)), kCorrTile + window each
   const int blk = xcd_logical_block(blockIdx.x, nblocks);
   const int row = blk / tiles_per_row;
   const int tile = blk - row * tiles_per_row;
@@ -250,7 +251,8 @@ __global__ __launch_bounds__(kCorrThreads) void sparse_corrected_kernel(
       dmax = fmaxf(dmax, fabsf(d));
       float pr = dpsi ? dpsi[pn] * kInv2Pi : 0.f;
       pr -= rintf(pr);
-      s_pul[c] = make_float4(sh, ch, pr, d);
+      s_pul[c] = make_float2(pr, d);
+      s_pul[kCorrTile + window + c] = make_float2(sh, ch);
     }
     for (int off = kWave / 2; off > 0; off >>= 1) dmax = fmaxf(dmax, __shfl_xor(dmax, off));
     if (lane == 0) s_red[wave] = dmax;
@@ -329,11 +331,15 @@ __global__ __launch_bounds__(kCorrThreads) void sparse_corrected_kernel(
           float sh = 0.f, ch = 1.f, pr, dn = 0.f;
           int col = acol[p] + tp.o;
           if constexpr (TABLE) {
-            const float4 q = s_pul[i_wave + lane + kWave * p + tp.o + half_w];
-            sh = q.x;
-            ch = q.y;
-            pr = q.z;
-            dn = q.w;
+            const int c = i_wave + lane + kWave * p + tp.o + half_w;
+            const float2 q = s_pul[c];
+            pr = q.x;
+            dn = q.y;
+            if constexpr (!SERIES) {
+              const float2 h = s_pul[kCorrTile + window + c];
+              sh = h.x;
+              ch = h.y;
+            }
           } else {
             int pn = col;
             pn += (pn < 0) ? n : 0;
@@ -488,7 +494,7 @@ hipError_t launch_corr_t(const SparseArgs& a, hipStream_t s) {
   const int nblocks = tiles * a.g.n_range;
   const char* yd = reinterpret_cast<const char*>(a.y.data);
   if (kCorrTile + a.window <= kCorrMaxCols) {
-    const size_t lds = (size_t)(kCorrTile + a.window) * sizeof(float4);
+    const size_t lds = (size_t)(kCorrTile + a.window) * 2 * sizeof(float2);
     sparse_corrected_kernel<DT, WDT, INTERP, true><<<nblocks, kCorrThreads, lds, s>>>(
         a.g, a.y, a.k, a.window, tiles, nblocks, a.offsets, a.weights, a.dphi, a.dpsi, yd, a.image);
   } else {
