@@ -15,9 +15,13 @@
 //
 // Newton system: the epigraph variables t couple only with their own (Re w_k, Im w_k), so they
 // are eliminated per cone (a 2 x 2 Schur update); the reduced system over
-// y = [Re w, Im w, U', b, b1, b2] (ny = 2n + 4) is assembled in float64 in global memory
-// (side-lobe terms as a rank-3S update, tiled through LDS), factored by a blocked Cholesky
-// (16-column panels staged in LDS) and solved by forward and backward substitution.
+// y = [Re w, Im w, U', b, b1, b2] (ny = 2n + 4) is assembled in float64 in global memory,
+// factored by a blocked Cholesky (16-column panels staged in LDS) and solved by forward and
+// backward substitution.  The side-lobe terms are a rank-3S update G G^T: the columns of G
+// (2n x 3S, written once per Newton step) are sqrt(2/(-f_s)) times the real forms of a_s and
+// j a_s and 2/|f_s| times that of a_s (a_s^H w); G G^T runs on the float64 matrix cores
+// (16 x 16 x 4 MFMA), 64 x 64 output blocks per pass, 16 columns of G staged in LDS at a time
+// while the next 16 are loaded.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -32,6 +36,14 @@ constexpr int kSasWaves = kSasThreads / kWave;
 constexpr int kChol = 16;          // Cholesky panel width
 constexpr int kTile = 32;          // Hessian assembly output tile
 constexpr int kSChunk = 16;        // side-lobe rows staged per assembly step
+constexpr int kMB = 64;            // G G^T output block (rows and columns) per pass
+constexpr int kKC = 16;            // columns of G staged in LDS per step (four MFMA k-steps)
+
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+// Rows of G (2n, padded to whole output blocks) and columns (3S, padded to whole stages).
+__host__ __device__ inline int g_rows(int n) { return (2 * n + kMB - 1) / kMB * kMB; }
+__host__ __device__ inline int g_cols(int s) { return (3 * s + kKC - 1) / kKC * kKC; }
 
 struct SasBuffers {
   double2* a_s;     // [s_max][n_max]
@@ -46,6 +58,8 @@ struct SasBuffers {
   double* grad;     // [3 n_max + 4]
   double* rhs;      // [2 n_max + 4]
   double* H;        // [ny_max][ny_max]
+  double2* cs;      // [s_max]  (sqrt(2/(-f_s)), 2/|f_s|)
+  double* G;        // [g_cols(s_max)][g_rows(n_max)]  side-lobe factor, column-major
 };
 
 __host__ __device__ inline size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
@@ -53,7 +67,8 @@ __host__ __device__ inline size_t align256(size_t b) { return (b + 255) & ~(size
 __host__ __device__ inline size_t bin_bytes(int n_max, int s_max) {
   const size_t nv = 3 * (size_t)n_max + 4, ny = 2 * (size_t)n_max + 4;
   return align256((size_t)s_max * n_max * 16) + 3 * align256((size_t)n_max * 16) + align256((size_t)s_max * 16) +
-         align256((size_t)s_max * 8) + 4 * align256(nv * 8) + align256(ny * 8) + align256(ny * ny * 8);
+         align256((size_t)s_max * 8) + 4 * align256(nv * 8) + align256(ny * 8) + align256(ny * ny * 8) +
+         align256((size_t)s_max * 16) + align256((size_t)g_cols(s_max) * g_rows(n_max) * 8);
 }
 
 __device__ inline SasBuffers carve(char* base, int n_max, int s_max) {
@@ -77,6 +92,8 @@ __device__ inline SasBuffers carve(char* base, int n_max, int s_max) {
   b.grad = reinterpret_cast<double*>(take(nv * 8));
   b.rhs = reinterpret_cast<double*>(take(ny * 8));
   b.H = reinterpret_cast<double*>(take(ny * ny * 8));
+  b.cs = reinterpret_cast<double2*>(take((size_t)s_max * 16));
+  b.G = reinterpret_cast<double*>(take((size_t)g_cols(s_max) * g_rows(n_max) * 8));
   return b;
 }
 
@@ -238,75 +255,89 @@ __device__ void assemble(const SasBuffers& B, const double* x, int n, int n_max,
   }
   __syncthreads();
 
-  // ---- Hessian, w-w block: sum_s [c_s (P P^T + Q Q^T) + d_s V V^T] over the lower tiles
+  // ---- Hessian, w-w block: sum_s [c_s (P P^T + Q Q^T) + d_s V V^T] = G G^T
   // (P = (Re a, Im a), Q = (-Im a, Re a), V = (Re(a z), Im(a z)), c = 2/(-f), d = 4/f^2)
-  double* sP = lds;                               // [kSChunk][kTile] row factors of the tile rows
-  double* sQ = sP + kSChunk * kTile;
-  double* sV = sQ + kSChunk * kTile;
-  double* cP = sV + kSChunk * kTile;              // same for the tile columns
-  double* cQ = cP + kSChunk * kTile;
-  double* cV = cQ + kSChunk * kTile;
-  double* sc = cV + kSChunk * kTile;              // [kSChunk] c_s
-  double* sd = sc + kSChunk;                      // [kSChunk] d_s
   const int nw = 2 * n;
-  const int tiles = (nw + kTile - 1) / kTile;
-  // thread layout inside a 32 x 32 tile: 256 threads, 4 elements each (rows ty, ty+8, ty+16, ty+24)
-  const int tx = threadIdx.x % kTile, ty = threadIdx.x / kTile;
-  for (int ti = 0; ti < tiles; ++ti) {
-    for (int tj = 0; tj <= ti; ++tj) {
-      double acc[4] = {0.0, 0.0, 0.0, 0.0};
-      for (int s0 = 0; s0 < s_cnt; s0 += kSChunk) {
-        const int sn = min(kSChunk, s_cnt - s0);
-        __syncthreads();
-        for (int e = threadIdx.x; e < kSChunk * kTile * 2; e += kSasThreads) {
-          const int side = e / (kSChunk * kTile);   // 0: tile rows, 1: tile columns
-          const int r = (e % (kSChunk * kTile)) / kTile, col = e % kTile;
-          const int idx = (side == 0 ? ti : tj) * kTile + col;
-          double p = 0.0, q = 0.0, v = 0.0;
-          if (r < sn && idx < nw) {
-            const int s = s0 + r;
-            const int k = idx < n ? idx : idx - n;
-            const double2 a = B.a_s[(size_t)s * n_max + k];
-            const double2 z = B.z[s];
-            const double azr = a.x * z.x - a.y * z.y, azi = a.x * z.y + a.y * z.x;
-            if (idx < n) {
-              p = a.x;
-              q = -a.y;
-              v = azr;
-            } else {
-              p = a.y;
-              q = a.x;
-              v = azi;
-            }
-          }
-          double* dstP = side == 0 ? sP : cP;
-          double* dstQ = side == 0 ? sQ : cQ;
-          double* dstV = side == 0 ? sV : cV;
-          dstP[r * kTile + col] = p;
-          dstQ[r * kTile + col] = q;
-          dstV[r * kTile + col] = v;
-        }
-        if (threadIdx.x < kSChunk) {
-          const int s = s0 + threadIdx.x;
-          const double f = s < s_cnt ? B.fs[s] : -1.0;
-          sc[threadIdx.x] = s < s_cnt ? 2.0 / (-f) : 0.0;
-          sd[threadIdx.x] = s < s_cnt ? 4.0 / (f * f) : 0.0;
-        }
-        __syncthreads();
-        for (int r = 0; r < sn; ++r) {
-          const double cs = sc[r], ds = sd[r];
-          const double pj = cP[r * kTile + tx], qj = cQ[r * kTile + tx], vj = cV[r * kTile + tx];
-#pragma unroll
-          for (int m = 0; m < 4; ++m) {
-            const int row = ty + 8 * m;
-            acc[m] += cs * (sP[r * kTile + row] * pj + sQ[r * kTile + row] * qj) + ds * sV[r * kTile + row] * vj;
-          }
+  for (int si = threadIdx.x; si < s_cnt; si += kSasThreads) {
+    const double f = B.fs[si];
+    B.cs[si] = make_double2(sqrt(2.0 / (-f)), 2.0 / fabs(f));
+  }
+  __syncthreads();
+  const int gr = g_rows(n_max), gc = g_cols(s_cnt);
+  for (int c = 0; c < gc; ++c) {
+    const int si = c / 3, t = c - 3 * si;
+    for (int row = threadIdx.x; row < gr; row += kSasThreads) {
+      double v = 0.0;
+      if (row < nw && si < s_cnt) {
+        const int k = row < n ? row : row - n;
+        const double2 a = B.a_s[(size_t)si * n_max + k];
+        const double2 sc = B.cs[si];
+        if (t == 0) {
+          v = sc.x * (row < n ? a.x : a.y);
+        } else if (t == 1) {
+          v = sc.x * (row < n ? -a.y : a.x);
+        } else {
+          const double2 z = B.z[si];
+          v = sc.y * (row < n ? a.x * z.x - a.y * z.y : a.x * z.y + a.y * z.x);
         }
       }
+      B.G[(size_t)c * gr + row] = v;
+    }
+  }
+  __syncthreads();
+  {
+    // G G^T on the matrix cores: per 64 x 64 block of the lower triangle, wave w owns block
+    // rows [16 w, 16 w + 16) and four 16-column tiles.  v_mfma_f64_16x16x4f64 lane l takes
+    // A[l % 16][l / 16] and B[l / 16][l % 16] and holds D[l / 16 + 4 r][l % 16] in register r.
+    double* sI = lds;                 // [kKC][kMB] block rows' columns of G
+    double* sJ = lds + kKC * kMB;     // [kKC][kMB] block columns'
+    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+    const int nb = (nw + kMB - 1) / kMB;
+    constexpr int kPer = 2 * kKC * kMB / kSasThreads;   // staged entries per thread
+    for (int bi = 0; bi < nb; ++bi) {
+      for (int bj = 0; bj <= bi; ++bj) {
+        dbl4 acc[4];
 #pragma unroll
-      for (int m = 0; m < 4; ++m) {
-        const int i = ti * kTile + ty + 8 * m, j = tj * kTile + tx;
-        if (i < nw && j < nw && j <= i) B.H[(size_t)i * ny + j] = acc[m];
+        for (int t = 0; t < 4; ++t) acc[t] = dbl4{0.0, 0.0, 0.0, 0.0};
+        double pre[kPer];
+        auto fetch = [&](int k0) {
+#pragma unroll
+          for (int m = 0; m < kPer; ++m) {
+            const int e = threadIdx.x + kSasThreads * m;
+            const int side = e / (kKC * kMB), rem = e % (kKC * kMB);
+            const int c = rem / kMB, r = rem % kMB;
+            pre[m] = B.G[(size_t)(k0 + c) * gr + (side ? bj : bi) * kMB + r];
+          }
+        };
+        fetch(0);
+        for (int k0 = 0; k0 < gc; k0 += kKC) {
+          __syncthreads();
+#pragma unroll
+          for (int m = 0; m < kPer; ++m) {
+            const int e = threadIdx.x + kSasThreads * m;
+            const int side = e / (kKC * kMB), rem = e % (kKC * kMB);
+            (side ? sJ : sI)[rem] = pre[m];
+          }
+          __syncthreads();
+          if (k0 + kKC < gc) fetch(k0 + kKC);
+#pragma unroll
+          for (int kk = 0; kk < kKC; kk += 4) {
+            const double a = sI[(kk + lane / 16) * kMB + wave * 16 + lane % 16];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+              const double b = sJ[(kk + lane / 16) * kMB + t * 16 + lane % 16];
+              acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[t], 0, 0, 0);
+            }
+          }
+        }
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int i = bi * kMB + wave * 16 + lane / 16 + 4 * r;
+            const int j = bj * kMB + t * 16 + lane % 16;
+            if (i < nw && j <= i) B.H[(size_t)i * ny + j] = acc[t][r];
+          }
       }
     }
   }

@@ -64,25 +64,44 @@ def test_sas_design_matches_oracle_per_iteration():
 
 def test_sas_design_meets_worst_case_with_gpu_beampattern():
     """32 iterations: the C1 and C2 slacks vanish, and the GPU beampattern's worst-case ratio
-    (side + Delta_R)^2 / (main - Delta_R)^2 of each designed row is at most eta."""
+    (side + Delta_R)^2 / (main - Delta_R)^2 of each row's design is at most eta, as eqs. 31-32
+    require of the sub-problem's solution (the kernel runs with Th = 0 and returns every
+    candidate's weight).  The thresholding of Sec. III-C (|w_k| < Th set to zero) then moves
+    each pattern value by at most eps = sum of the removed |w_k| (|a_k| <= 1), so the sparse
+    set's ratio stays within ((side + Delta_R + eps) / (main - Delta_R - eps))^2."""
     rs = need_gpu()
     g, grid, p = small_case(32)
+    p_all = dataclasses.replace(p, th=0.0)
     deltas = torch.tensor([0.03, 0.02, 0.015], dtype=torch.float64, device=dev())
     log("sas design: 3 rows x 32 iterations, then the beampattern check")
-    d = rs.sas_design(g, grid, deltas, gpu_params(rs, p))
+    d = rs.sas_design(g, grid, deltas, gpu_params(rs, p_all))
     torch.cuda.synchronize()
     hist = d.history.cpu().numpy()
     assert np.all(hist[:, -1, 3] < 1e-8) and np.all(hist[:, -1, 4] < 1e-8), hist[:, -1]
-    off, w = d.sparse_set()
+    cnt = d.count.cpu().numpy()
     for row in range(grid.n_range):
         rr = grid.r0_m + row * grid.dr_m
+        assert cnt[row] == len(F.candidates(g, rr))            # Th = 0 keeps every candidate
         sub = synth.PolarGrid(1, g.n_pulses, rr, 0.1)
         ph = F.sidelobe_angles(F.candidates(g, rr), g.n_pulses, p.phi_mw, p.d_angle)
         a = torch.from_numpy(np.concatenate([[0.0], ph])).to(dev())
-        _, summ = rs.beampattern(g, sub, off[row:row + 1].contiguous(), w[row:row + 1].contiguous(), g.n_pulses, a,
-                                 delta_r=deltas[row:row + 1].contiguous())
+        dr = deltas[row:row + 1].contiguous()
+        off = d.offsets[row:row + 1, :cnt[row]].contiguous()
+        w = d.weights[row:row + 1, :cnt[row]].contiguous()
+        _, summ = rs.beampattern(g, sub, off, w, g.n_pulses, a, delta_r=dr)
         main, side, ratio = summ.cpu().numpy()[0]
         u2 = hist[row, -1, 1] ** 2
-        log(f"  row {row}: main {main:.5f} side {side:.5f} ratio {ratio:.3e} eta {p.eta}")
+        log(f"  row {row}: main {main:.5f} side {side:.5f} ratio {ratio:.4e} eta {p.eta}")
         assert ratio <= p.eta * (1 + 1e-3), (row, ratio)
         assert (main - deltas[row].item()) ** 2 >= u2 * (1 - 1e-3)
+        # the paper's thresholding
+        keep = (w.abs() >= p.th)[0]
+        eps = float(w[0, ~keep].abs().sum())
+        _, summ_t = rs.beampattern(g, sub, off[:, keep].contiguous(), w[:, keep].contiguous(), g.n_pulses, a,
+                                   delta_r=dr)
+        ratio_t = summ_t.cpu().numpy()[0][2]
+        dl = deltas[row].item()
+        bound = ((side + dl + eps) / (main - dl - eps)) ** 2
+        log(f"    thresholded at {p.th}: {int(keep.sum())} of {cnt[row]} kept, ratio {ratio_t:.4e} <= {bound:.4e}")
+        assert 0 < keep.sum() < cnt[row]
+        assert ratio_t <= bound * (1 + 1e-9), (row, ratio_t, bound)
