@@ -16,12 +16,12 @@
 // Newton system: the epigraph variables t couple only with their own (Re w_k, Im w_k), so they
 // are eliminated per cone (a 2 x 2 Schur update); the reduced system over
 // y = [Re w, Im w, U', b, b1, b2] (ny = 2n + 4) is assembled in float64 in global memory,
-// factored by a blocked Cholesky (16-column panels staged in LDS) and solved by forward and
-// backward substitution.  The side-lobe terms are a rank-3S update G G^T: the columns of G
+// factored by a blocked Cholesky (32-column panels, the trailing updates on the matrix cores)
+// and solved by forward and backward substitution.  The side-lobe terms are a rank-3S update G G^T: the columns of G
 // (2n x 3S, written once per Newton step) are sqrt(2/(-f_s)) times the real forms of a_s and
 // j a_s and 2/|f_s| times that of a_s (a_s^H w); G G^T runs on the float64 matrix cores
-// (16 x 16 x 4 MFMA), 64 x 64 output blocks per pass, 16 columns of G staged in LDS at a time
-// while the next 16 are loaded.
+// (16 x 16 x 4 MFMA), 64 x 64 output blocks per pass, 32 columns of G staged in LDS at a time
+// while the next 32 are loaded.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -33,11 +33,9 @@ namespace {
 
 constexpr int kSasThreads = 256;
 constexpr int kSasWaves = kSasThreads / kWave;
-constexpr int kChol = 16;          // Cholesky panel width
-constexpr int kTile = 32;          // Hessian assembly output tile
-constexpr int kSChunk = 16;        // side-lobe rows staged per assembly step
 constexpr int kMB = 64;            // G G^T output block (rows and columns) per pass
-constexpr int kKC = 16;            // columns of G staged in LDS per step (four MFMA k-steps)
+constexpr int kKC = 32;            // columns of G staged in LDS per step (eight MFMA k-steps)
+constexpr int kCP = 32;            // Cholesky panel width
 
 typedef double dbl4 __attribute__((ext_vector_type(4)));
 
@@ -418,91 +416,108 @@ __device__ void assemble(const SasBuffers& B, const double* x, int n, int n_max,
   __syncthreads();
 }
 
-// In-place Cholesky of the lower triangle of H (ny x ny, row stride ny): right-looking with
-// kChol-column panels; the trailing update runs over 32 x 32 tiles of the lower triangle with
-// the two panel slices staged in LDS.  Returns false (all threads) if a pivot is not positive.
+// In-place Cholesky of the lower triangle of H (ny x ny, row stride ny), right-looking with
+// kCP-column panels: the diagonal block is factored in LDS column by column by the whole
+// workgroup, the panel below by forward substitution (one row per thread, held in LDS), and the trailing
+// update A22 -= L21 L21^T runs on the float64 matrix cores over 64 x 64 blocks of the lower
+// triangle (the panel's 32 columns of the block rows and columns staged in LDS).  Returns false
+// (all threads) if a pivot is not positive.
 __device__ bool cholesky(double* H, int ny, double* lds, double* red) {
-  double* L11 = lds;                       // [kChol][kChol]
-  double* Lr = lds + kChol * kChol;        // [kTile][kChol] panel rows of a tile's rows
-  double* Lc = Lr + kTile * kChol;         // [kTile][kChol] panel rows of a tile's columns
-  const int tx = threadIdx.x % kTile, ty = threadIdx.x / kTile;
-  for (int k0 = 0; k0 < ny; k0 += kChol) {
-    const int kb = min(kChol, ny - k0);
+  (void)red;
+  constexpr int LP = kCP + 1;              // padded row of the diagonal block
+  constexpr int SL = kMB + 1;              // padded column of the staged panels
+  double* L11 = lds;                       // [kCP][LP]
+  double* dinv = L11 + kCP * LP;           // [kCP] 1 / L11[j][j]
+  double* sI = dinv + kCP;                 // [kCP][SL] panel columns of the block rows
+  double* sJ = sI + kCP * SL;              // [kCP][SL] panel columns of the block columns
+  double* vL = sJ + kCP * SL;              // [kSasThreads][LP] one panel row per thread
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+  for (int k0 = 0; k0 < ny; k0 += kCP) {
+    const int kb = min(kCP, ny - k0);
     __syncthreads();
-    for (int e = threadIdx.x; e < kb * kb; e += kSasThreads) {
-      const int i = e / kb, j = e % kb;
-      L11[i * kChol + j] = j <= i ? H[(size_t)(k0 + i) * ny + k0 + j] : 0.0;
+    for (int e = threadIdx.x; e < kCP * kCP; e += kSasThreads) {
+      const int i = e / kCP, j = e % kCP;
+      L11[i * LP + j] = (i < kb && j <= i) ? H[(size_t)(k0 + i) * ny + k0 + j] : 0.0;
     }
     __syncthreads();
-    // unblocked factor of the diagonal block by one thread (kChol^3 / 6 operations)
-    double bad = 0.0;
-    if (threadIdx.x == 0) {
-      for (int j = 0; j < kb; ++j) {
-        double d = L11[j * kChol + j];
-        for (int q = 0; q < j; ++q) d -= L11[j * kChol + q] * L11[j * kChol + q];
-        if (!(d > 0.0)) {
-          bad = 1.0;
-          d = 1.0;
-        }
-        const double ljj = sqrt(d);
-        L11[j * kChol + j] = ljj;
-        for (int i = j + 1; i < kb; ++i) {
-          double v = L11[i * kChol + j];
-          for (int q = 0; q < j; ++q) v -= L11[i * kChol + q] * L11[j * kChol + q];
-          L11[i * kChol + j] = v / ljj;
-        }
+    // the diagonal block, column by column (every thread reads the same pivots, so the
+    // positivity test is uniform)
+    for (int j = 0; j < kb; ++j) {
+      const double d = L11[j * LP + j];
+      if (!(d > 0.0)) return false;
+      const double ljj = sqrt(d);
+      __syncthreads();   // every thread has read the pivot
+      for (int i = j + 1 + (int)threadIdx.x; i < kb; i += kSasThreads) L11[i * LP + j] /= ljj;
+      if (threadIdx.x == 0) {
+        L11[j * LP + j] = ljj;
+        dinv[j] = 1.0 / ljj;
       }
+      __syncthreads();
+      const int rem = kb - j - 1;
+      for (int e = threadIdx.x; e < rem * rem; e += kSasThreads) {
+        const int i = j + 1 + e / rem, m = j + 1 + e % rem;
+        if (m <= i) L11[i * LP + m] -= L11[i * LP + j] * L11[m * LP + j];
+      }
+      __syncthreads();
     }
-    if (block_max(bad, red) > 0.0) return false;
     for (int e = threadIdx.x; e < kb * kb; e += kSasThreads) {
       const int i = e / kb, j = e % kb;
-      if (j <= i) H[(size_t)(k0 + i) * ny + k0 + j] = L11[i * kChol + j];
+      if (j <= i) H[(size_t)(k0 + i) * ny + k0 + j] = L11[i * LP + j];
     }
-    // panel below: L21 = A21 L11^{-T}, one row per thread
+    // panel below: L21 = A21 L11^{-T}, one row per thread, the row held in LDS
     const int rows = ny - k0 - kb;
+    double* vr = vL + threadIdx.x * LP;
     for (int r = threadIdx.x; r < rows; r += kSasThreads) {
       double* hrow = H + (size_t)(k0 + kb + r) * ny + k0;
-      double v[kChol];
-#pragma unroll
-      for (int j = 0; j < kChol; ++j) v[j] = j < kb ? hrow[j] : 0.0;
-#pragma unroll
-      for (int j = 0; j < kChol; ++j) {
-        if (j < kb) {
-          double sum = v[j];
-#pragma unroll
-          for (int q = 0; q < j; ++q) sum -= v[q] * L11[j * kChol + q];
-          v[j] = sum / L11[j * kChol + j];
-        }
+      for (int j = 0; j < kb; ++j) vr[j] = hrow[j];
+      for (int j = 0; j < kb; ++j) {
+        double sum = vr[j];
+        for (int q = 0; q < j; ++q) sum -= vr[q] * L11[j * LP + q];
+        vr[j] = sum * dinv[j];
       }
-#pragma unroll
-      for (int j = 0; j < kChol; ++j)
-        if (j < kb) hrow[j] = v[j];
+      for (int j = 0; j < kb; ++j) hrow[j] = vr[j];
     }
     __syncthreads();
-    // trailing update A22 -= L21 L21^T over the lower tiles of A22
+    // trailing update A22 -= L21 L21^T on the matrix cores (lane layout as in the assembly)
     const int base = k0 + kb;
-    const int tiles = (rows + kTile - 1) / kTile;
-    for (int ti = 0; ti < tiles; ++ti) {
-      for (int tj = 0; tj <= ti; ++tj) {
+    const int nb = (rows + kMB - 1) / kMB;
+    for (int bi = 0; bi < nb; ++bi) {
+      for (int bj = 0; bj <= bi; ++bj) {
         __syncthreads();
-        for (int e = threadIdx.x; e < 2 * kTile * kChol; e += kSasThreads) {
-          const int side = e / (kTile * kChol), rr = (e % (kTile * kChol)) / kChol, j = e % kChol;
-          const int row = (side == 0 ? ti : tj) * kTile + rr;
-          const double v = (row < rows && j < kb) ? H[(size_t)(base + row) * ny + k0 + j] : 0.0;
-          (side == 0 ? Lr : Lc)[rr * kChol + j] = v;
+        for (int e = threadIdx.x; e < 2 * kMB * kCP; e += kSasThreads) {
+          const int side = e / (kMB * kCP), rem = e % (kMB * kCP);
+          const int r = rem / kCP, c = rem % kCP;
+          const int row = (side ? bj : bi) * kMB + r;
+          const double v = (row < rows && c < kb) ? H[(size_t)(base + row) * ny + k0 + c] : 0.0;
+          (side ? sJ : sI)[c * SL + r] = v;
         }
         __syncthreads();
-        const int jc = tj * kTile + tx;
+        dbl4 acc[4];
 #pragma unroll
-        for (int m = 0; m < 4; ++m) {
-          const int ic = ti * kTile + ty + 8 * m;
-          if (ic < rows && jc <= ic) {
-            double sum = 0.0;
+        for (int t = 0; t < 4; ++t)
 #pragma unroll
-            for (int j = 0; j < kChol; ++j) sum += Lr[(ty + 8 * m) * kChol + j] * Lc[tx * kChol + j];
-            H[(size_t)(base + ic) * ny + base + jc] -= sum;
+          for (int q = 0; q < 4; ++q) {
+            const int i = bi * kMB + wave * 16 + lane / 16 + 4 * q;
+            const int j = bj * kMB + t * 16 + lane % 16;
+            acc[t][q] = (i < rows && j <= i) ? H[(size_t)(base + i) * ny + base + j] : 0.0;
+          }
+#pragma unroll
+        for (int kk = 0; kk < kCP; kk += 4) {
+          const double a = -sI[(kk + lane / 16) * SL + wave * 16 + lane % 16];
+#pragma unroll
+          for (int t = 0; t < 4; ++t) {
+            const double b = sJ[(kk + lane / 16) * SL + t * 16 + lane % 16];
+            acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[t], 0, 0, 0);
           }
         }
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int i = bi * kMB + wave * 16 + lane / 16 + 4 * q;
+            const int j = bj * kMB + t * 16 + lane % 16;
+            if (i < rows && j <= i) H[(size_t)(base + i) * ny + base + j] = acc[t][q];
+          }
       }
     }
   }
@@ -535,8 +550,8 @@ __global__ __launch_bounds__(kSasThreads) void sas_design_kernel(Geo g, SasDesig
                                                                  float2* __restrict__ weights, int32_t* __restrict__ count,
                                                                  double* __restrict__ hist) {
   __shared__ double red[kSasWaves];
-  constexpr int kAsmLds = 6 * kSChunk * kTile + 2 * kSChunk;
-  constexpr int kCholLds = kChol * kChol + 2 * kTile * kChol;
+  constexpr int kAsmLds = 2 * kKC * kMB;
+  constexpr int kCholLds = kCP * (kCP + 1) + kCP + 2 * kCP * (kMB + 1) + kSasThreads * (kCP + 1);
   __shared__ double lds[kAsmLds > kCholLds ? kAsmLds : kCholLds];
   const int bin = blockIdx.x;
   const SasBuffers B = carve(ws + (size_t)bin * stride, n_max, s_max);
