@@ -231,7 +231,7 @@ hipError_t launch_adjoint_band(const SparseArgs& a, const FcLayout& L, const flo
                                void* ws, hipStream_t s) {
   char* tabs = static_cast<char*>(ws);
   int* bad = reinterpret_cast<int*>(tabs + (size_t)L.row_bytes * a.g.n_range);   // set only past the host bound
-  hipError_t e = launch_fc_tables(a, L, tabs, bad, s);
+  hipError_t e = launch_fc_tables(a, L, tabs, bad, nullptr, s);
   if (e != hipSuccess) return e;
   const int tiles = (a.g.n + kAdjTile - 1) / kAdjTile;
   const int half_w = a.window / 2;

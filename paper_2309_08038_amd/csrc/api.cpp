@@ -674,6 +674,7 @@ struct rosar_sparse_plan {
   float2* tw = nullptr;       // fast convolution: twiddle table [N]
   float2* spec = nullptr;     // fast convolution: band-row spectra [l_count][N]
   float2* gspec = nullptr;    // fast convolution: kernel spectra [pairs][N]
+  int* first = nullptr;       // fast convolution: each range row's first kernel spectrum [n_range]
   int device = -1;
 };
 
@@ -685,56 +686,87 @@ void free_plan(rosar_sparse_plan* p) {
   (void)hipFree(p->tw);
   (void)hipFree(p->spec);
   (void)hipFree(p->gspec);
+  (void)hipFree(p->first);
   delete p;
 }
 
-// Device memory of a fast-convolution plan: tables (+ a flag word), twiddles, band-row spectra
-// and the kernel spectra of every (range row, bin row) pair.  Uploads the twiddles, builds the
-// tap lists, numbers the pairs on the host (row by row, bin rows in mask order; the header's
-// last word gets the row's first pair) and builds their spectra, all on `s`, which it
-// synchronises.  UNSUPPORTED if a range row's taps span more bin rows than the row mask holds.
+// Pinned host staging and device temporaries of fc_prepare, freed on every path.
+struct PinnedTmp {
+  void* p = nullptr;
+  ~PinnedTmp() {
+    if (p) (void)hipHostFree(p);
+  }
+};
+struct DeviceTmp {
+  void* p = nullptr;
+  ~DeviceTmp() {
+    if (p) (void)hipFree(p);
+  }
+};
+
+// Device memory of a fast-convolution plan: tables (+ a flag word), twiddles, band-row spectra,
+// the kernel spectra of every (range row, bin row) pair and each row's first pair index.
+// Uploads the twiddles, builds the tap lists, reads the rows' headers back, numbers the pairs on
+// the host (row by row, bin rows in mask order) and builds their spectra, all on `s`, which it
+// synchronises.  Every host buffer of a copy is pinned and every copy is one-dimensional, and
+// the headers the device wrote are not rewritten: the first pair indices go to an array of their
+// own.  UNSUPPORTED if a range row's taps span more bin rows than the row mask holds.
 rosar_status fc_prepare(const rosar::SparseArgs& a, const rosar::FcLayout& fc, hipStream_t s, char** tabs, float2** tw,
-                        float2** spec, float2** gspec) {
+                        float2** spec, float2** gspec, int** first) {
   const int n_range = a.g.n_range;
   const size_t tab_bytes = (size_t)fc.row_bytes * (size_t)n_range;
-  const size_t tw_bytes = (size_t)rosar::fc_twiddle_count(a.g.n) * sizeof(float2);
+  const int n_tw = rosar::fc_twiddle_count(a.g.n);
+  const size_t tw_bytes = (size_t)n_tw * sizeof(float2);
   const size_t row_spec_bytes = (size_t)a.g.n * sizeof(float2);
   if (hipMalloc(tabs, tab_bytes + 256) != hipSuccess || hipMalloc(tw, tw_bytes) != hipSuccess ||
-      hipMalloc(spec, rosar::fc_spectrum_bytes(a)) != hipSuccess)
+      hipMalloc(spec, rosar::fc_spectrum_bytes(a)) != hipSuccess ||
+      hipMalloc(first, (size_t)n_range * sizeof(int)) != hipSuccess)
     return fail(ROSAR_ERR_NO_MEMORY, "device allocation of the fast-convolution plan failed");
-  std::vector<float2> host_tw(rosar::fc_twiddle_count(a.g.n));
-  rosar::fc_twiddles(a.g.n, host_tw.data());
+  PinnedTmp h_tw, h_bad, h_hdr, h_first;
+  DeviceTmp d_hdr;
+  if (hipHostMalloc(&h_tw.p, tw_bytes) != hipSuccess || hipHostMalloc(&h_bad.p, sizeof(int)) != hipSuccess ||
+      hipHostMalloc(&h_hdr.p, (size_t)n_range * sizeof(int4)) != hipSuccess ||
+      hipHostMalloc(&h_first.p, (size_t)n_range * sizeof(int)) != hipSuccess ||
+      hipMalloc(&d_hdr.p, (size_t)n_range * sizeof(int4)) != hipSuccess)
+    return fail(ROSAR_ERR_NO_MEMORY, "staging allocation of the fast-convolution plan failed");
+  rosar::fc_twiddles(a.g.n, static_cast<float2*>(h_tw.p));
+  int* bad_host = static_cast<int*>(h_bad.p);
+  int4* hdr = static_cast<int4*>(h_hdr.p);
+  int* first_host = static_cast<int*>(h_first.p);
+  *bad_host = 0;
   int* bad = reinterpret_cast<int*>(*tabs + tab_bytes);
-  int bad_host = 0;
-  std::vector<int4> hdr(n_range);
-  hipError_t e = hipMemcpyAsync(*tw, host_tw.data(), tw_bytes, hipMemcpyHostToDevice, s);
-  if (e == hipSuccess) e = hipMemcpyAsync(bad, &bad_host, sizeof(int), hipMemcpyHostToDevice, s);
-  if (e == hipSuccess) e = rosar::launch_fc_tables(a, fc, *tabs, bad, s);
-  if (e == hipSuccess) e = hipMemcpyAsync(&bad_host, bad, sizeof(int), hipMemcpyDeviceToHost, s);
+  hipError_t e = hipMemcpyAsync(*tw, h_tw.p, tw_bytes, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(bad, bad_host, sizeof(int), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = rosar::launch_fc_tables(a, fc, *tabs, bad, static_cast<int4*>(d_hdr.p), s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);   // the tables are complete before any read-back
+  if (e == hipSuccess) e = hipMemcpyAsync(bad_host, bad, sizeof(int), hipMemcpyDeviceToHost, s);
   if (e == hipSuccess)
-    e = hipMemcpy2DAsync(hdr.data(), sizeof(int4), *tabs, fc.row_bytes, sizeof(int4), n_range, hipMemcpyDeviceToHost, s);
+    e = hipMemcpyAsync(hdr, d_hdr.p, (size_t)n_range * sizeof(int4), hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) return from_hip(e, "fast-convolution plan set-up");
-  if (bad_host)
+  if (*bad_host)
     return fail(ROSAR_ERR_UNSUPPORTED, "a range row's taps span more bin rows than the fast convolution handles (32)");
-  std::vector<int2> pairs;
+  size_t n_pairs = 0;
   for (int r = 0; r < n_range; ++r) {
-    hdr[r].w = (int)pairs.size();
-    for (unsigned m = (unsigned)hdr[r].y; m; m &= m - 1u) pairs.push_back(make_int2(r, __builtin_ctz(m)));
+    first_host[r] = (int)n_pairs;
+    n_pairs += (size_t)__builtin_popcount((unsigned)hdr[r].y);
   }
-  const size_t n_pairs = pairs.size();
-  int2* d_pairs = nullptr;
+  PinnedTmp h_pairs;
+  DeviceTmp d_pairs;
   if (hipMalloc(gspec, std::max<size_t>(n_pairs, 1) * row_spec_bytes) != hipSuccess ||
-      hipMalloc(&d_pairs, std::max<size_t>(n_pairs, 1) * sizeof(int2)) != hipSuccess) {
-    (void)hipFree(d_pairs);
+      hipMalloc(&d_pairs.p, std::max<size_t>(n_pairs, 1) * sizeof(int2)) != hipSuccess ||
+      hipHostMalloc(&h_pairs.p, std::max<size_t>(n_pairs, 1) * sizeof(int2)) != hipSuccess)
     return fail(ROSAR_ERR_NO_MEMORY, "device allocation of the kernel spectra (%zu pairs) failed", n_pairs);
-  }
-  e = hipMemcpy2DAsync(*tabs, fc.row_bytes, hdr.data(), sizeof(int4), sizeof(int4), n_range, hipMemcpyHostToDevice, s);
+  int2* pairs = static_cast<int2*>(h_pairs.p);
+  size_t q = 0;
+  for (int r = 0; r < n_range; ++r)
+    for (unsigned m = (unsigned)hdr[r].y; m; m &= m - 1u) pairs[q++] = make_int2(r, __builtin_ctz(m));
+  e = hipMemcpyAsync(*first, first_host, (size_t)n_range * sizeof(int), hipMemcpyHostToDevice, s);
   if (e == hipSuccess && n_pairs)
-    e = hipMemcpyAsync(d_pairs, pairs.data(), n_pairs * sizeof(int2), hipMemcpyHostToDevice, s);
-  if (e == hipSuccess) e = rosar::launch_fc_kernel_spectra(fc, *tabs, d_pairs, (int)n_pairs, *tw, *gspec, s);
+    e = hipMemcpyAsync(d_pairs.p, pairs, n_pairs * sizeof(int2), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess)
+    e = rosar::launch_fc_kernel_spectra(fc, *tabs, static_cast<const int2*>(d_pairs.p), (int)n_pairs, *tw, *gspec, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
-  (void)hipFree(d_pairs);
   if (e != hipSuccess) return from_hip(e, "fast-convolution kernel spectra");
   return ROSAR_OK;
 }
@@ -779,7 +811,7 @@ rosar_status rosar_sparse_plan_create(const rosar_geometry* geom, const rosar_po
       return fail(ROSAR_ERR_HIP, "injected launch failure (ROSAR_FAULT_INJECT)");
     }
     const rosar_status st =
-        fc_prepare(a, fc, reinterpret_cast<hipStream_t>(stream), &p->tabs, &p->tw, &p->spec, &p->gspec);
+        fc_prepare(a, fc, reinterpret_cast<hipStream_t>(stream), &p->tabs, &p->tw, &p->spec, &p->gspec, &p->first);
     if (st != ROSAR_OK) {
       free_plan(p);
       return st;
@@ -861,7 +893,8 @@ rosar_status plan_run(const rosar_sparse_plan* plan, const rosar_rc_view* rc, vo
   a.image = reinterpret_cast<float2*>(image);
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   if (plan->variant == 3)
-    return from_hip(rosar::launch_fc_run(a, plan->fc, plan->tabs, plan->tw, spec ? spec : plan->spec, plan->gspec, s),
+    return from_hip(rosar::launch_fc_run(a, plan->fc, plan->tabs, plan->first, plan->tw, spec ? spec : plan->spec,
+                                         plan->gspec, s),
                     "fast convolution launch");
   return from_hip(rosar::launch_sparse_planned(a, plan->layout, plan->tabs, s), "sparse plan launch");
 }
@@ -967,10 +1000,12 @@ rosar_status rosar_sparse_plan_autotune(const rosar_geometry* geom, const rosar_
     float2* tw = nullptr;
     float2* spec = nullptr;
     float2* gspec = nullptr;
-    const rosar_status fst = fc_prepare(a, fc, s, &ftabs, &tw, &spec, &gspec);
+    int* first = nullptr;
+    const rosar_status fst = fc_prepare(a, fc, s, &ftabs, &tw, &spec, &gspec, &first);
     if (fst == ROSAR_OK) {
       float us = 0.f;
-      e = time_launches([&] { return rosar::launch_fc_run(a, fc, ftabs, tw, spec, gspec, s); }, reps, s, e0, e1, &us);
+      e = time_launches([&] { return rosar::launch_fc_run(a, fc, ftabs, first, tw, spec, gspec, s); }, reps, s, e0, e1,
+                        &us);
       if (e == hipSuccess) e = hipStreamSynchronize(s);
       if (e != hipSuccess) {
         st = from_hip(e, "plan autotune");
@@ -986,6 +1021,7 @@ rosar_status rosar_sparse_plan_autotune(const rosar_geometry* geom, const rosar_
     (void)hipFree(tw);
     (void)hipFree(spec);
     (void)hipFree(gspec);
+    (void)hipFree(first);
   }
   if (e0) (void)hipEventDestroy(e0);
   if (e1) (void)hipEventDestroy(e1);

@@ -28,14 +28,15 @@ using mfft::kFftThreads;
 constexpr int kFcMaxRows = 32;   // bin rows one range row may touch (a 32-bit mask)
 constexpr int kFcMaxQ = (kFftMaxN + kFftThreads - 1) / kFftThreads;
 
-// Row block: int4 header {lfirst, bin mask, ne, first pair}, then ne entries
+// Row block: int4 header {lfirst, bin mask, ne, 0}, then ne entries
 // int4 {azimuth index (o mod N), bin row - lfirst (-1: no contribution), coef.x, coef.y}.  The
-// first pair index (the row's G spectra, one per mask bit in bit order) is filled in by the host.
+// header also goes to hdr_out[row] (when given) for the host, which numbers the row's G spectra
+// (one per mask bit in bit order) and uploads each row's first pair index as an array of its own.
 template <int WDT, int INTERP>
 __global__ __launch_bounds__(256) void fc_table_kernel(Geo g, View y, int32_t k, int32_t window, int rows_cap,
                                                        double cos_hw, const int32_t* __restrict__ offsets,
                                                        const void* __restrict__ weights, char* __restrict__ tabs,
-                                                       int row_bytes, int* __restrict__ bad) {
+                                                       int row_bytes, int* __restrict__ bad, int4* __restrict__ hdr_out) {
   constexpr int NSUB = INTERP == ROSAR_LINEAR ? 2 : 1;
   const int row = blockIdx.x;
   const int half_w = window / 2;
@@ -80,6 +81,7 @@ __global__ __launch_bounds__(256) void fc_table_kernel(Geo g, View y, int32_t k,
   __syncthreads();
   if (threadIdx.x == 0) {
     blk[0] = make_int4(sp.lfirst, (int)s_mask, k * NSUB, 0);
+    if (hdr_out) hdr_out[row] = blk[0];
     if (s_bad) atomicOr(bad, 1);
   }
 }
@@ -139,7 +141,8 @@ __global__ __launch_bounds__(kFftThreads) void fc_kernel_spectra_kernel(FftFacto
 
 // One range row: I[r, .] = IDFT(sum over the row's bin rows of G_{r,l} * Yhat_l).
 __global__ __launch_bounds__(kFftThreads) void fc_rows_kernel(FftFactors f, int n_range, const char* __restrict__ tabs,
-                                                              int row_bytes, const float2* __restrict__ tw,
+                                                              int row_bytes, const int* __restrict__ first_pair,
+                                                              const float2* __restrict__ tw,
                                                               const float2* __restrict__ spec,
                                                               const float2* __restrict__ gspec, float inv_scale,
                                                               float2* __restrict__ image) {
@@ -152,7 +155,7 @@ __global__ __launch_bounds__(kFftThreads) void fc_rows_kernel(FftFactors f, int 
   const int4 hdr = reinterpret_cast<const int4*>(tabs + (size_t)row * row_bytes)[0];
   const int lfirst = hdr.x;
   unsigned mask = (unsigned)hdr.y;
-  const float2* gp = gspec + (size_t)hdr.w * n;
+  const float2* gp = gspec + (size_t)first_pair[row] * n;
 
   float2 acc[kFcMaxQ];
 #pragma unroll
@@ -185,9 +188,9 @@ __global__ __launch_bounds__(kFftThreads) void fc_rows_kernel(FftFactors f, int 
 }
 
 template <int WDT, int INTERP>
-hipError_t launch_tables_t(const SparseArgs& a, const FcLayout& L, char* tabs, int* bad, hipStream_t s) {
+hipError_t launch_tables_t(const SparseArgs& a, const FcLayout& L, char* tabs, int* bad, int4* hdr_out, hipStream_t s) {
   fc_table_kernel<WDT, INTERP><<<a.g.n_range, 256, 0, s>>>(a.g, a.y, a.k, a.window, L.rows_cap, L.cos_hw, a.offsets,
-                                                          a.weights, tabs, L.row_bytes, bad);
+                                                          a.weights, tabs, L.row_bytes, bad, hdr_out);
   return hipGetLastError();
 }
 
@@ -244,11 +247,13 @@ void fc_twiddles(int n, float2* host_tw) {
   }
 }
 
-hipError_t launch_fc_tables(const SparseArgs& a, const FcLayout& L, char* tabs, int* bad, hipStream_t s) {
+hipError_t launch_fc_tables(const SparseArgs& a, const FcLayout& L, char* tabs, int* bad, int4* hdr_out, hipStream_t s) {
   const bool lin = a.interp == ROSAR_LINEAR;
   if (a.w_dtype == ROSAR_C64)
-    return lin ? launch_tables_t<0, ROSAR_LINEAR>(a, L, tabs, bad, s) : launch_tables_t<0, ROSAR_NEAREST>(a, L, tabs, bad, s);
-  return lin ? launch_tables_t<1, ROSAR_LINEAR>(a, L, tabs, bad, s) : launch_tables_t<1, ROSAR_NEAREST>(a, L, tabs, bad, s);
+    return lin ? launch_tables_t<0, ROSAR_LINEAR>(a, L, tabs, bad, hdr_out, s)
+               : launch_tables_t<0, ROSAR_NEAREST>(a, L, tabs, bad, hdr_out, s);
+  return lin ? launch_tables_t<1, ROSAR_LINEAR>(a, L, tabs, bad, hdr_out, s)
+             : launch_tables_t<1, ROSAR_NEAREST>(a, L, tabs, bad, hdr_out, s);
 }
 
 hipError_t launch_fc_kernel_spectra(const FcLayout& L, const char* tabs, const int2* pairs, int n_pairs,
@@ -258,8 +263,8 @@ hipError_t launch_fc_kernel_spectra(const FcLayout& L, const char* tabs, const i
   return hipGetLastError();
 }
 
-hipError_t launch_fc_run(const SparseArgs& a, const FcLayout& L, const char* tabs, const float2* tw, float2* spec,
-                         const float2* gspec, hipStream_t s) {
+hipError_t launch_fc_run(const SparseArgs& a, const FcLayout& L, const char* tabs, const int* first_pair,
+                         const float2* tw, float2* spec, const float2* gspec, hipStream_t s) {
   switch (a.y.dtype) {
     case ROSAR_C64: fc_spectrum_kernel<0><<<a.y.l_count, kFftThreads, L.lds_bytes, s>>>(a.y, L.f, tw, spec); break;
     case ROSAR_C16_F16: fc_spectrum_kernel<1><<<a.y.l_count, kFftThreads, L.lds_bytes, s>>>(a.y, L.f, tw, spec); break;
@@ -267,8 +272,8 @@ hipError_t launch_fc_run(const SparseArgs& a, const FcLayout& L, const char* tab
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  fc_rows_kernel<<<a.g.n_range, kFftThreads, L.lds_bytes, s>>>(L.f, a.g.n_range, tabs, L.row_bytes, tw, spec,
-                                                                gspec, a.y.inv_scale, a.image);
+  fc_rows_kernel<<<a.g.n_range, kFftThreads, L.lds_bytes, s>>>(L.f, a.g.n_range, tabs, L.row_bytes, first_pair, tw,
+                                                                spec, gspec, a.y.inv_scale, a.image);
   return hipGetLastError();
 }
 

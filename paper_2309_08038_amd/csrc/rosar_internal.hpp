@@ -142,11 +142,13 @@ hipError_t launch_adjoint_band(const SparseArgs& a, const FcLayout& L, const flo
 size_t fc_spectrum_bytes(const SparseArgs& a);
 int fc_twiddle_count(int n);
 void fc_twiddles(int n, float2* host_tw);   // fc_twiddle_count(n) entries
-hipError_t launch_fc_tables(const SparseArgs& a, const FcLayout& L, char* tabs, int* bad, hipStream_t s);
+// hdr_out (may be NULL): each row's header {lfirst, bin mask, ne, 0}, for the host
+hipError_t launch_fc_tables(const SparseArgs& a, const FcLayout& L, char* tabs, int* bad, int4* hdr_out, hipStream_t s);
 hipError_t launch_fc_kernel_spectra(const FcLayout& L, const char* tabs, const int2* pairs, int n_pairs,
                                    const float2* tw, float2* gspec, hipStream_t s);
-hipError_t launch_fc_run(const SparseArgs& a, const FcLayout& L, const char* tabs, const float2* tw, float2* spec,
-                         const float2* gspec, hipStream_t s);
+// first_pair[row]: index of the row's first kernel spectrum in gspec
+hipError_t launch_fc_run(const SparseArgs& a, const FcLayout& L, const char* tabs, const int* first_pair,
+                         const float2* tw, float2* spec, const float2* gspec, hipStream_t s);
 
 // Tile chosen when the caller leaves it to the library.
 Tile default_tile(int32_t n, int32_t y_dtype);
