@@ -528,7 +528,8 @@ rosar_status rosar_sas_design_workspace_size(const rosar_geometry* geom, const r
  *   history  [n_range][iters][6] float64 (device) or NULL: per iteration the objective
  *            J = ||w||_1 + lambda_b (b + b1 + b2), U', b, b1, b2 and the Newton steps taken.
  * A row whose taps are not all accepted (b + b1 + b2 >= b_min in the last iteration) still
- * gets its weights; the caller checks the history.
+ * gets its weights; the caller checks the history.  A row that no phase centre sees (R <= r,
+ * eqs. 4-5) gets count 0, zero outputs and an all-zero history.
  * Errors: as the workspace query; INVALID_ARG for window below the largest candidate count,
  * NULL or misaligned pointers; ROSAR_ERR_WORKSPACE for a short or misaligned workspace. */
 rosar_status rosar_sas_design(const rosar_geometry* geom, const rosar_polar_grid* grid,

@@ -570,10 +570,13 @@ __global__ __launch_bounds__(kSasThreads) void sas_design_kernel(Geo g, SasDesig
   const int n_right = max((int)floor((d_max - p.phi_mw) / p.d_angle) + 1, 0);
   const int s_cnt = n_left + n_right;
   if (n == 0 || n > n_max || s_cnt > s_max) {
+    // no phase centre sees the row (R <= r): no taps and an all-zero history
     for (int k = threadIdx.x; k < window; k += kSasThreads) {
       offsets[(size_t)bin * window + k] = 0;
       weights[(size_t)bin * window + k] = make_float2(0.f, 0.f);
     }
+    if (hist_bin)
+      for (int e = threadIdx.x; e < p.iters * 6; e += kSasThreads) hist_bin[e] = 0.0;
     if (threadIdx.x == 0) count[bin] = 0;
     return;
   }

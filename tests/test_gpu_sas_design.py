@@ -105,3 +105,26 @@ def test_sas_design_meets_worst_case_with_gpu_beampattern():
         log(f"    thresholded at {p.th}: {int(keep.sum())} of {cnt[row]} kept, ratio {ratio_t:.4e} <= {bound:.4e}")
         assert 0 < keep.sum() < cnt[row]
         assert ratio_t <= bound * (1 + 1e-9), (row, ratio_t, bound)
+
+
+def test_sas_design_rows_without_candidates_and_ragged_rows():
+    """A grid whose first row lies inside the radius (no phase centre sees it, eqs. 4-5) next to
+    rows with different candidate counts: the first row gets count 0, zero taps and a zero
+    history; the others match the oracle per iteration."""
+    rs = need_gpu()
+    g, _, p = small_case(2)
+    grid = synth.PolarGrid(3, 160, 0.1, 0.85)          # R = 0.1 (< r = 0.145), 0.95, 1.8 m
+    deltas = np.array([0.05, 0.03, 0.015])
+    log("sas design: a row inside the radius and two ragged rows, 2 iterations")
+    d = rs.sas_design(g, grid, torch.from_numpy(deltas).to(dev()), gpu_params(rs, p))
+    torch.cuda.synchronize()
+    hist, cnt = d.history.cpu().numpy(), d.count.cpu().numpy()
+    assert cnt[0] == 0 and np.all(hist[0] == 0)
+    assert np.all(d.weights[0].cpu().numpy() == 0) and np.all(d.offsets[0].cpu().numpy() == 0)
+    for row in (1, 2):
+        rr = grid.r0_m + row * grid.dr_m
+        ref = F.design_bin(g, rr, deltas[row], p)
+        for it, h in enumerate(ref.history):
+            assert abs(hist[row, it, 0] - h["J"]) <= 1e-5 * abs(h["J"]), (row, it)
+            assert abs(hist[row, it, 1] - h["U"]) <= 1e-5 * abs(h["U"]), (row, it)
+        assert cnt[row] == np.count_nonzero(np.abs(ref.w) > 0)
