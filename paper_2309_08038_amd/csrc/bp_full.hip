@@ -12,12 +12,20 @@
 // 2-5 with the pixel centred on pulse a).  Per chunk of offsets the workgroup computes the
 // nominal geometry in float64 (R_nom = R(D0), beta R_nom of eq. 40, the phase 2 k R_nom in
 // revolutions) into LDS, and stages the pulse corrections of the columns the chunk touches.
-// Per (pixel, pulse) only the correction is evaluated, in float32 and without cancellation:
-//   R_n^2 - R_nom^2 = 4 R r sin(D0 + d/2) sin(d/2),  R_n - R_nom = (R_n^2 - R_nom^2)/(R_n + R_nom),
-// the bin is beta R_nom + beta (R_n - R_nom) in float64, the phase adds 2 k (R_n - R_nom), and
-// v = R cos D - r = (R^2 - r^2 - R_n^2) / (2 r) gives alpha = max(v, 0) / R_n (eqs. 3, 8, 15).
+// Per (pixel, pulse) only the correction is evaluated, in float32, one of two ways chosen per
+// workgroup (as in the corrected sparse filter):
+//  - series, when the fourth-derivative remainder bound at the largest |d| is below 1e-6 rad of
+//    carrier phase and 2^-20 bins (and beta r max|d| < 1/2): R_n - R_nom = d (q1 + d (q2 + d q3))
+//    and v = R cos D - r = v0 + d (v1 + d (v2 + d v3)) (Taylor coefficients at D0 in float64 per
+//    offset; the cosine's remainder R d^4 / 24 is required below 1e-8 m);
+//  - exact otherwise, without cancellation:
+//    R_n^2 - R_nom^2 = 4 R r sin(D0 + d/2) sin(d/2),  R_n - R_nom = (R_n^2 - R_nom^2)/(R_n + R_nom),
+//    v = (R^2 - r^2 - R_n^2) / (2 r).
+// The bin is beta R_nom + beta (R_n - R_nom) in float64, the phase adds 2 k (R_n - R_nom), and
+// alpha = max(v, 0) / R_n (eqs. 3, 8, 15).
 // Neighbouring lanes read neighbouring columns of the same bin row: coalesced loads.
 #include <mutex>
+#include <type_traits>
 
 #include "rosar_device.hpp"
 
@@ -30,14 +38,16 @@ constexpr int kBpTile = kBpThreads * kBpP;       // pixels per workgroup
 constexpr int kBpChunk = kBpThreads;             // offsets per chunk (one per thread)
 constexpr size_t kBpHeader = 256;                // bytes before the per-pulse table
 
-// Nominal geometry of one offset o (no angle error), 32 bytes.
+// Nominal geometry of one offset o (no angle error), 64 bytes.
 struct alignas(16) BpTap {
   SplitBin u;     // beta * R_nom - l_lo (+ 1/2 for NEAREST): FFT bin of eq. 40, split
   float r2;       // R_nom^2
   float rnom;     // R_nom
   float sd, cd;   // sin, cos of D0 = 2 pi o / N
-  float ph;       // frac(k R_nom / pi): revolutions of exp(j 2 k R_nom)
+  float ph;       // k R_nom / pi - rint(.): revolutions of exp(j 2 k R_nom), in [-1/2, 1/2]
   int32_t near;   // NEAREST: a correction of this offset can bring the bin near a rounding tie
+  float q1, q2, q3;   // R(D0 + d) - R_nom = d (q1 + d (q2 + d q3))
+  float v0, v1, v2, v3;   // R cos(D0 + d) - r = v0 + d (v1 + d (v2 + d v3))
 };
 
 __global__ __launch_bounds__(1024) void bp_prep_kernel(int32_t n, double phi0, double step,
@@ -75,6 +85,7 @@ __global__ __launch_bounds__(kBpThreads) void bp_kernel(Geo g, View y, int tiles
                                                        float2* __restrict__ image) {
   __shared__ BpTap s_tap[kBpChunk];
   __shared__ float2 s_del[kBpChunk + kBpTile];   // pulse corrections of columns a0 + c0 + j
+  __shared__ float s_d[kBpChunk + kBpTile];      // their angle errors d (series path)
   const int blk = xcd_logical_block(blockIdx.x, nblocks);
   const int row = blk / tiles_per_row;
   const int tile = blk - row * tiles_per_row;
@@ -94,6 +105,15 @@ __global__ __launch_bounds__(kBpThreads) void bp_kernel(Geo g, View y, int tiles
     const float2* del = reinterpret_cast<const float2*>(reinterpret_cast<const char*>(ws) + kBpHeader);
     const double dmax = ws[0];
     const double reach = (acos(r / rr) + dmax) / g.step;
+    bool series = false;
+    {
+      const double rho = rr - r;
+      const double c = 2.0 * rr * r;
+      const double m4 = 2.0 * (c / (2.0 * rho) + 0.75 * c * c / (rho * rho * rho));
+      const double rem = m4 * dmax * dmax * dmax * dmax / 24.0;   // metres
+      series = rem * (kTwoPiD * g.k_over_pi) <= 1e-6 && rem * g.beta <= 0x1p-20 && g.beta * r * dmax < 0.5 &&
+               rr * dmax * dmax * dmax * dmax / 24.0 <= 1e-8;
+    }
     const int span = reach >= (double)n ? n : (int)reach + 1;
     int o_lo, o_hi;   // inclusive offset range, each pulse at most once per pixel
     if (2 * span + 1 >= n) {
@@ -120,6 +140,8 @@ __global__ __launch_bounds__(kBpThreads) void bp_kernel(Geo g, View y, int tiles
 #pragma unroll
     for (int p = 0; p < kBpP; ++p) acol[p] = min(a0 + i_wave + lane + kWave * p, n - 1);
 
+    auto chunks = [&](auto series_tag) {
+    constexpr bool SERIES = decltype(series_tag)::value;
     for (int c0 = o_lo; c0 <= o_hi; c0 += kBpChunk) {
       const int cnt = min(kBpChunk, o_hi - c0 + 1);
       if ((int)threadIdx.x < cnt) {
@@ -135,17 +157,33 @@ __global__ __launch_bounds__(kBpThreads) void bp_kernel(Geo g, View y, int tiles
         t.rnom = (float)rn;
         t.sd = (float)s;
         t.cd = (float)c;
-        t.ph = (float)(ph - floor(ph));
+        t.ph = (float)(ph - rint(ph));
         // |R_n - R_nom| is at most the chord r |d| between the nominal and the true phase centre,
         // so the corrected fraction stays within beta r max|d| of the nominal one
         const float fmax_corr = (float)(g.beta * r * dmax) * 1.0001f + 0x1p-17f;
         t.near = (t.u.f < fmax_corr || t.u.f > 1.f - fmax_corr) ? 1 : 0;
+        // derivatives of R(D) = sqrt(S), S = c1 - c2 cos D, and of R cos D - r, at D0
+        const double s1 = c2 * s, s2 = c2 * c;
+        const double ir = 1.0 / rn, ir3 = ir * ir * ir, ir5 = ir3 * ir * ir;
+        t.q1 = (float)(0.5 * s1 * ir);
+        t.q2 = (float)(0.5 * (0.5 * s2 * ir - 0.25 * s1 * s1 * ir3));
+        t.q3 = (float)((-0.5 * s1 * ir - 0.75 * s1 * s2 * ir3 + 0.375 * s1 * s1 * s1 * ir5) / 6.0);
+        t.v0 = (float)(rr * c - r);
+        t.v1 = (float)(-rr * s);
+        t.v2 = (float)(-0.5 * rr * c);
+        t.v3 = (float)(rr * s / 6.0);
+        if constexpr (SERIES) t.u.i = min(max(t.u.i, -3), y.l_count + 2);
         s_tap[threadIdx.x] = t;
       }
       for (int j = threadIdx.x; j < cnt - 1 + kBpTile; j += kBpThreads) {
         int pn = (a0 + c0 + j) % n;
         pn += pn < 0 ? n : 0;
         s_del[j] = del[pn];
+        if constexpr (SERIES) {
+          // d = 2 atan2(sin(d/2), cos(d/2)) would cost; the angle error itself is recomputed
+          const double dn = angles ? angles[pn] - (g.phi0 + g.step * pn) : 0.0;
+          s_d[j] = (float)(dn - kTwoPiD * rint(dn / kTwoPiD));
+        }
       }
       __syncthreads();
       int pc[kBpP];   // pulse column of offset c0 for each pixel, in [0, N)
@@ -159,14 +197,22 @@ __global__ __launch_bounds__(kBpThreads) void bp_kernel(Geo g, View y, int tiles
         const BpTap tp = s_tap[t];
 #pragma unroll
         for (int p = 0; p < kBpP; ++p) {
-          const float2 dl = s_del[i_wave + lane + kWave * p + t];   // (sin(d/2), cos(d/2))
-          const float s_mid = fmaf(tp.sd, dl.y, tp.cd * dl.x);    // sin(D0 + d/2)
-          const float dd = c4 * s_mid * dl.x;                      // R_n^2 - R_nom^2
-          const float r2 = fmaxf(tp.r2 + dd, 1e-30f);
-          const float rs = __builtin_amdgcn_rsqf(r2);
-          const float rn = r2 * rs;
-          const float diff = dd * __builtin_amdgcn_rcpf(rn + tp.rnom);   // R_n - R_nom
-          const float alpha = fmaxf((k1 - r2) * inv2r, 0.f) * rs;
+          float diff, alpha;   // R_n - R_nom, max(v, 0) / R_n
+          if constexpr (SERIES) {
+            const float dn = s_d[i_wave + lane + kWave * p + t];
+            diff = dn * fmaf(dn, fmaf(dn, tp.q3, tp.q2), tp.q1);
+            const float v = fmaf(dn, fmaf(dn, fmaf(dn, tp.v3, tp.v2), tp.v1), tp.v0);
+            alpha = fmaxf(v, 0.f) * __builtin_amdgcn_rcpf(tp.rnom + diff);
+          } else {
+            const float2 dl = s_del[i_wave + lane + kWave * p + t];   // (sin(d/2), cos(d/2))
+            const float s_mid = fmaf(tp.sd, dl.y, tp.cd * dl.x);    // sin(D0 + d/2)
+            const float dd = c4 * s_mid * dl.x;                      // R_n^2 - R_nom^2
+            const float r2 = fmaxf(tp.r2 + dd, 1e-30f);
+            const float rs = __builtin_amdgcn_rsqf(r2);
+            const float rn = r2 * rs;
+            diff = dd * __builtin_amdgcn_rcpf(rn + tp.rnom);
+            alpha = fmaxf((k1 - r2) * inv2r, 0.f) * rs;
+          }
           const float corr = beta * diff;
           float fr;
           bool tie;
@@ -183,18 +229,19 @@ __global__ __launch_bounds__(kBpThreads) void bp_kernel(Geo g, View y, int tiles
               const double phi_a = g.phi0 + (double)acol[p] * g.step;
               const double phi_n = angles ? angles[pn] : g.phi0 + (double)pn * g.step;
               l = (int)floor(plain_bin_half(rr, r, phi_a - phi_n, g.beta)) - y.l_lo;
+              l = min(max(l, -1), y.l_count);
             }
-            l = min(max(l, -1), y.l_count);
+            if constexpr (!SERIES) l = min(max(l, -1), y.l_count);
             smp = buf_load<DT>(rsrc, (uint32_t)(__mul24(l, ld_es) + cb), 0u);
           } else {
-            l = min(max(l, -2), y.l_count);
+            if constexpr (!SERIES) l = min(max(l, -2), y.l_count);
             const uint32_t off0 = (uint32_t)(__mul24(l, ld_es) + cb);
             const float2 y0 = buf_load<DT>(rsrc, off0, 0u);
             const float2 y1 = buf_load<DT>(rsrc, off0 + (uint32_t)ld_es, 0u);
             smp = make_float2(fmaf(fr, y1.x - y0.x, y0.x), fmaf(fr, y1.y - y0.y, y0.y));
           }
-          float rev = tp.ph + kpi * diff;
-          rev -= floorf(rev);
+          float rev = fmaf(kpi, diff, tp.ph);
+          if constexpr (!SERIES) rev -= floorf(rev);
           // coefficient alpha exp(-j 2 k R_n); acc += coef * smp
           const float cr = alpha * cos_rev(rev);
           const float ci = -alpha * sin_rev(rev);
@@ -206,6 +253,11 @@ __global__ __launch_bounds__(kBpThreads) void bp_kernel(Geo g, View y, int tiles
       }
       __syncthreads();
     }
+    };
+    if (series)
+      chunks(std::true_type{});
+    else
+      chunks(std::false_type{});
   }
   float2* out = image + (int64_t)row * n;
 #pragma unroll
