@@ -4,7 +4,12 @@
 // phase centre is n_c = round((phi_t - phi0) / phi_Delta); tap k reads pulse (n_c + o_k) mod N
 // at the bin of the slant range from that pulse to the target (eq. 2, eq. 40).  Without the
 // rotation symmetry each pixel has its own tap geometry: a thread owns a pixel and evaluates it
-// in float64, reading the band samples from global memory.
+// in float64, reading the band samples from global memory.  The angle between the target and
+// pulse n_c + o is D = e - o 2 pi / N with e = phi_t - phi0 - n_c 2 pi / N, so
+// cos D = cos e cos(o 2 pi / N) + sin e sin(o 2 pi / N): cos e and sin e once per target, the
+// offsets' cosines and sines from an LDS table of the window (windows up to kCartTableMax
+// pulses; wider ones take cos D directly).  For NEAREST a bin within 1e-9 of a rounding tie is
+// recomputed from the plain cos(phi_t - phi_n).
 //
 // POLAR: the targets are the pixels of a polar grid of A azimuth bins that need not equal N
 // (Algorithm 2's round(phi_t / phi_Delta) with phi_t = phi0 + 2 pi a / A): pixel (i, a) has
@@ -18,16 +23,24 @@ namespace rosar {
 namespace {
 
 constexpr int kCartThreads = 256;
+constexpr int kCartTableMax = 4096;   // widest window whose (cos, sin) table goes to LDS (64 KB)
 
 template <int DT, int WDT, int INTERP, bool POLAR>
 __global__ __launch_bounds__(kCartThreads) void sparse_cartesian_kernel(Geo g, View y, CartGrid c, int32_t k,
-                                                                        int32_t half_w,
+                                                                        int32_t half_w, int use_table,
                                                                         const int32_t* __restrict__ offsets,
                                                                         const void* __restrict__ weights,
                                                                         float2* __restrict__ image) {
+  extern __shared__ double2 s_cs[];   // [2 half_w]: (cos, sin) of o 2 pi / N, o in [-half_w, half_w)
+  for (int j = threadIdx.x; use_table && j < 2 * half_w; j += kCartThreads) {
+    double sn, cs;
+    sincos((double)(j - half_w) * g.step, &sn, &cs);
+    s_cs[j] = make_double2(cs, sn);
+  }
+  __syncthreads();
   const int ix = blockIdx.x * kCartThreads + threadIdx.x;
   const int iy = blockIdx.y;
-  if (ix >= c.nx) return;   // no barrier in this kernel
+  if (ix >= c.nx) return;   // no barrier below
   double rt, phi;
   int row;
   if constexpr (POLAR) {   // c.nx = A azimuth bins, c.ny = rows
@@ -45,14 +58,25 @@ __global__ __launch_bounds__(kCartThreads) void sparse_cartesian_kernel(Geo g, V
   if (row >= 0 && row < g.n_range) {
     const double c1 = rt * rt + g.radius * g.radius;
     const double c2 = 2.0 * rt * g.radius;
+    double se, ce;
+    sincos(phi - (g.phi0 + nc * g.step), &se, &ce);
     const char* yd = static_cast<const char*>(y.data);
     for (int t = 0; t < k; ++t) {
       const int o = offsets[(int64_t)row * k + t];
       if (o < -half_w || o >= half_w) continue;   // outside the window: no contribution
       const float2 w = load_w<WDT>(weights, (int64_t)row * k + t);
       const int nn = nc + o;
-      const double d = phi - (g.phi0 + nn * g.step);
-      const double u = g.beta * sqrt(c1 - c2 * cos(d));
+      double cd;
+      if (use_table) {
+        const double2 cso = s_cs[o + half_w];
+        cd = fma(ce, cso.x, se * cso.y);
+      } else {
+        cd = cos(phi - (g.phi0 + nn * g.step));
+      }
+      double u = g.beta * sqrt(c1 - c2 * cd);
+      if constexpr (INTERP == ROSAR_NEAREST) {
+        if (near_bin_tie(u + 0.5, 1e-9)) u = g.beta * sqrt(c1 - c2 * cos(phi - (g.phi0 + nn * g.step)));
+      }
       int n = nn % g.n;
       n += n < 0 ? g.n : 0;
       float2 s = make_float2(0.f, 0.f);
@@ -182,12 +206,15 @@ hipError_t launch_bp_dt(const Geo& g, const View& y, const CartGrid& c, const do
 template <int DT, int WDT, bool POLAR>
 hipError_t launch_wdt(const SparseArgs& a, const CartGrid& c, hipStream_t s) {
   dim3 grid((c.nx + kCartThreads - 1) / kCartThreads, c.ny);
+  const int half_w = a.window / 2;
+  const int use_table = 2 * half_w <= kCartTableMax ? 1 : 0;
+  const size_t lds = use_table ? (size_t)2 * half_w * sizeof(double2) : 0;
   if (a.interp == ROSAR_LINEAR)
-    sparse_cartesian_kernel<DT, WDT, ROSAR_LINEAR, POLAR><<<grid, kCartThreads, 0, s>>>(
-        a.g, a.y, c, a.k, a.window / 2, a.offsets, a.weights, a.image);
+    sparse_cartesian_kernel<DT, WDT, ROSAR_LINEAR, POLAR><<<grid, kCartThreads, lds, s>>>(
+        a.g, a.y, c, a.k, half_w, use_table, a.offsets, a.weights, a.image);
   else
-    sparse_cartesian_kernel<DT, WDT, ROSAR_NEAREST, POLAR><<<grid, kCartThreads, 0, s>>>(
-        a.g, a.y, c, a.k, a.window / 2, a.offsets, a.weights, a.image);
+    sparse_cartesian_kernel<DT, WDT, ROSAR_NEAREST, POLAR><<<grid, kCartThreads, lds, s>>>(
+        a.g, a.y, c, a.k, half_w, use_table, a.offsets, a.weights, a.image);
   return hipGetLastError();
 }
 

@@ -213,3 +213,22 @@ def test_bp_cartesian_reduced_precision(dtype, scale):
     img = rs.bp_cartesian(g, c, rc).cpu().numpy()
     ref = oracle.bp_cartesian_at(oracle_band("small"), x.l_lo, g, xs, ys).reshape(64, 64)
     assert rel_l2(img, ref) <= 1e-2
+
+
+@pytest.mark.parametrize("interp", ["nearest", "linear"])
+def test_cartesian_window_wider_than_the_lds_table(interp):
+    """A 4400-pulse window (N = 5000): wider than the kernel's table of the offsets' cosines, so
+    the target-to-pulse angle takes its cosine directly; against the oracle."""
+    rs = need_gpu()
+    w = custom_workload("cart_wide", 83, 5000, 64, 8, 1.0, 2.0, 8, 4400, radius=0.25)
+    x = synth.make_inputs(w)
+    g = w.geometry
+    yb = oracle.range_compress(x.raw, x.window, g.n_fft)[:, x.l_lo:x.l_lo + x.l_count]
+    rc = rs.range_compress(g, to_dev(x.raw), to_dev(x.window), x.l_lo, x.l_count, halo=16)
+    c, xs, ys = lattice(24, 20, -2.0 + 0.00731, -2.0 + 0.00419, 4.0 / 23, 4.0 / 19)
+    log(f"cartesian, window 4400 of 5000, {interp}")
+    img = rs.sparse_filter_cartesian(g, w.grid, c, rc, to_dev(x.offsets), to_dev(x.weights.astype(np.complex64)),
+                                     w.sparse.window, interp=interp).cpu().numpy()
+    ref = oracle.sparse_filter_cartesian(yb, x.l_lo, g, w.grid, xs, ys, x.offsets, x.weights,
+                                         interp).reshape(20, 24)
+    assert rel_l2(img, ref) <= TOL
