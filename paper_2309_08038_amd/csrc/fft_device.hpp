@@ -24,6 +24,13 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// LDS layout of one pulse row: element i sits at i + i/32, so the strided Stockham writes (and
+// reads) of a pass spread over the banks instead of piling onto a few; the row pitch is odd so
+// that the transposed store, which reads one element from each of several rows, does not
+// conflict either.
+__device__ __forceinline__ constexpr int lds_idx(int i) { return i + (i >> 5); }
+constexpr int row_pitch(int l) { return l + l / 32 + 1; }
+
 constexpr int radix_of(int x) { return (x % 8 == 0) ? 8 : ((x % 4 == 0) ? 4 : 2); }
 constexpr int pass_count(int l) {
   int p = 0;
@@ -103,7 +110,7 @@ template <int L, int PPW, int PASS>
 __device__ __forceinline__ void pass_load(float2 (&v)[PPW][pass_bpl(L, PASS)][pass_radix(L, PASS)],
                                           const float2* buf, int wave, int lane, const RcArgs& a, int n0) {
   using S = PassShape<L, PASS>;
-  constexpr int LP = L + 1;
+  constexpr int LP = row_pitch(L);
 #pragma unroll
   for (int p = 0; p < PPW; ++p) {
     const int wp = wave * PPW + p;
@@ -118,7 +125,7 @@ __device__ __forceinline__ void pass_load(float2 (&v)[PPW][pass_bpl(L, PASS)][pa
         if constexpr (PASS == 0) {
           if (j < S::NB && n < a.n && idx < a.m) x = a.raw[(int64_t)n * a.m + idx];
         } else {
-          if (j < S::NB) x = buf[wp * LP + idx];
+          if (j < S::NB) x = buf[wp * LP + lds_idx(idx)];
         }
         v[p][b][r] = x;
       }
@@ -150,7 +157,7 @@ __device__ __forceinline__ void pass_compute(float2 (&v)[PPW][pass_bpl(L, PASS)]
                                              float2* buf, const float2* tw, int wave, int lane) {
   using S = PassShape<L, PASS>;
   constexpr int R = S::R, NS = S::NS, NB = S::NB;
-  constexpr int LP = L + 1;
+  constexpr int LP = row_pitch(L);
 #pragma unroll
   for (int p = 0; p < PPW; ++p) {
     const int wp = wave * PPW + p;
@@ -166,7 +173,7 @@ __device__ __forceinline__ void pass_compute(float2 (&v)[PPW][pass_bpl(L, PASS)]
         dft<R>(v[p][b]);
         const int base = (j - k) * R + k;
 #pragma unroll
-        for (int q = 0; q < R; ++q) buf[wp * LP + base + q * NS] = v[p][b][q];
+        for (int q = 0; q < R; ++q) buf[wp * LP + lds_idx(base + q * NS)] = v[p][b][q];
       }
     }
   }
@@ -189,7 +196,7 @@ __device__ __forceinline__ void fft_rest(float2* buf, const float2* tw, int wave
 
 // LDS float2 needed by rc_block<L, PPW, NW>: twiddle table, NW*PPW padded pulse rows and the
 // window (L floats).
-constexpr int rc_lds_elems(int l, int ppw, int nw) { return l + nw * ppw * (l + 1) + l / 2; }
+constexpr int rc_lds_elems(int l, int ppw, int nw) { return l + nw * ppw * row_pitch(l) + l / 2; }
 
 // Range-compress pulses [n0, n0 + NW*PPW) of one rotation: FFT each (wave w owns pulses
 // n0 + w*PPW ...), then store the band transposed with NW*PPW consecutive pulses per row
@@ -199,7 +206,7 @@ constexpr int rc_lds_elems(int l, int ppw, int nw) { return l + nw * ppw * (l + 
 template <int L, int PPW, int DT, int NW>
 __device__ __forceinline__ void rc_block(const RcArgs& a, int n0, float2* lds) {
   constexpr int PW = NW * PPW;
-  constexpr int LP = L + 1;
+  constexpr int LP = row_pitch(L);
   constexpr int NT = NW * kWave;
   float2* tw = lds;
   float2* buf = lds + L;
@@ -227,7 +234,7 @@ __device__ __forceinline__ void rc_block(const RcArgs& a, int n0, float2* lds) {
     const int lr = i / PW;
     const int n = n0 + pp;
     if (n >= a.n) continue;
-    float2 v2 = buf[pp * LP + a.l_lo + lr];
+    float2 v2 = buf[pp * LP + lds_idx(a.l_lo + lr)];
     v2.x *= a.scale;
     v2.y *= a.scale;
     const int64_t row = (int64_t)lr * a.ld;
