@@ -179,80 +179,149 @@ __global__ __launch_bounds__(kWave* NW) void sparse_plain_kernel(
 constexpr int kCorrThreads = 256;
 constexpr int kCorrP = 4;                          // pixels per lane (64 apart)
 constexpr int kCorrTile = kCorrThreads * kCorrP;   // pixels per workgroup
-constexpr int kCorrChunk = kCorrThreads;           // taps per chunk (one per thread)
+constexpr int kCorrChunk = 32;                     // taps per chunk (one per thread of wave 0)
 constexpr int kCorrMaxCols = 4096;                 // largest per-pulse table held in LDS (T + W)
+constexpr int kCorrStageCols = 2048;               // largest T + W whose band rows are staged in LDS
+constexpr int kCorrStageRowsN = 3;                 // NEAREST: band rows staged per workgroup
+constexpr int kCorrStageRowsL = 2;                 // LINEAR: (row, next row - row) pairs staged
+constexpr int kColBatch = 4;                       // columns per thread whose loads are issued together
+constexpr int kStageLoads = 3;                     // band rows loaded per staged column
+static_assert(kCorrStageRowsN <= kStageLoads && kCorrStageRowsL + 1 <= kStageLoads, "staging loads");
 
-// Nominal geometry and weight of one tap (no angle error), 48 bytes.
+// Nominal geometry and weight of one tap (no angle error), 64 bytes.
 struct alignas(16) CorrTap {
   SplitBin u;       // band-relative bin beta * R_nom - l_lo (+ 1/2 for NEAREST), split
   float r2;         // R_nom^2
   float rnom;       // R_nom
   float sd, cd;     // sin, cos of D0 = 2 pi o / N
-  float wr, wi;     // weight (zero for an offset outside the window)
-  float q1, q2, q3; // Taylor coefficients at D0: R(D0 + d) - R_nom = d (q1 + d (q2 + d q3)) + O(d^4)
-  int32_t o;        // offset
+  float wa, wt;     // weight as |w| (zero for an offset outside the window) and arg(w) / 2 pi
+  float q1, q2, q3; // series in e = beta d: R(D0 + d) - R_nom = d (q1 + e (q2 + e q3)) + O(d^4)
+  int32_t o;        // offset (zero outside the window)
+  int32_t ub;       // series paths: byte offset of the tap's nominal row and column (see below)
+  int32_t pad[3];
 };
+
+// floor(x) converted to int32 in one instruction (the compiler emits a floor and a convert).
+__device__ __forceinline__ int floor_to_int(float x) {
+  int r;
+  asm("v_cvt_flr_i32_f32 %0, %1" : "=v"(r) : "v"(x));
+  return r;
+}
 
 // Corrected path: the angle error d_n and phase error psi_n of pulse n move the slant range of
 // every (pixel, tap) pair: R^ = R(D0 + d_n), R(D) = sqrt(R^2 + r^2 - 2 R r cos D).  The
 // workgroup (one row, kCorrTile pixels) computes the taps' nominal geometry in float64 into LDS
-// and stages, per column of pulses [a0 - W/2, a0 + T + W/2), (psi / 2 pi, d) and
-// (sin(d/2), cos(d/2)) as two float2 tables (the series path reads only the first, with
-// conflict-free 8-byte loads).  Per pair only the correction R^ - R_nom is evaluated, in float32, one of two ways:
+// and per-pulse values for the columns [a0 - W/2, a0 + T + W/2).  Per pair only the correction
+// R^ - R_nom is evaluated, in float32, one of two ways:
 //  - series: the cubic Taylor polynomial of R(D0 + d) - R(D0) in d, with float64 coefficients
 //    per tap.  Its remainder is at most max|R''''| d^4 / 24, and |R''''| peaks at D = 0 with
 //    c/(2 rho) + 3 c^2 / (4 rho^3) (c = 2 R r, rho = R - r).  The workgroup takes this path when
-//    twice that bound at the largest |d| of its pulse table is below 1e-6 rad of carrier phase
-//    and 2^-20 bins, and when beta r |d| < 1/2 (|dR/dD| <= r, so the correction moves a bin by
-//    less than one): the workloads' angle errors of a few milliradians are far inside it.  The
-//    nominal bin is then clamped once per tap to [-3, l_count + 2], so every sampled row stays
-//    out of the band when the nominal one is (zero by the buffer's range check) and no per-pair
-//    clamp is needed; the phase (psi / 2 pi reduced to [-1/2, 1/2] in the table) stays within
-//    the hardware sine's input range without a floor;
+//    twice that bound at the largest |d| of its columns is below 1e-6 rad of carrier phase and
+//    2^-20 bins, and when beta r |d| < 1/2 (|dR/dD| <= r, so the correction moves a bin by less
+//    than one): the workloads' angle errors of a few milliradians are far inside it.  With
+//    e = beta d and s = q1 + e (q2 + e q3), the bin is u + e s and the phase (k / pi) d s.
+//    The pairs then reach only the rows floor(u +- beta r max|d|) of the row's taps; when those
+//    span at most `stage_rows` rows, the workgroup copies them over its columns into LDS, each
+//    sample already turned by exp(-j psi) of its pulse (zero outside the band), and the pairs
+//    gather from LDS: NEAREST one float2 per sample, LINEAR the float4 (y_l, y_l+1 - y_l) so
+//    that the interpolation is two FMAs on one 16-byte read.  Otherwise the pairs read the band in
+//    global memory through buffer loads (out-of-band rows read zero), with the nominal bin
+//    clamped once per tap to [-3, l_count + 2] and folded with the column into one offset;
 //  - exact otherwise: R^2 - R_nom^2 = 4 R r sin(D0 + d/2) sin(d/2) and
-//    R^ - R_nom = (R^2 - R_nom^2) / (R^ + R_nom), without cancellation.
-// The bin is the float64 nominal bin plus beta (R^ - R_nom), the sample comes through buffer
-// loads (out-of-band rows read zero), and the phase factor exp(-j (2 k (R^ - R_nom) + psi)) runs
-// on the hardware sine/cosine in revolutions.  TABLE = false (window too wide for the LDS table)
-// evaluates the per-pulse values for every pair from global memory, on the exact path.
+//    R^ - R_nom = (R^2 - R_nom^2) / (R^ + R_nom), without cancellation, gathering from global
+//    memory.
+// The bin is the float64 nominal bin plus beta (R^ - R_nom), and the phase factor
+// exp(-j (2 k (R^ - R_nom) + psi)) runs on the hardware sine/cosine in revolutions with the
+// weight folded in: conj(w) exp(-j 2 pi x) = |w| exp(-j 2 pi (x + arg(w) / 2 pi)).
+// TABLE = false (window too wide for the LDS tables) evaluates the per-pulse values for every
+// pair from global memory, on the exact path.  `stage_rows` is the number of staged rows the
+// dynamic LDS can hold (0: no staging).  Waves whose pixels all lie past the end of the
+// rotation (the last tile of a row) skip the tap loops.
 template <int DT, int WDT, int INTERP, bool TABLE>
 __global__ __launch_bounds__(kCorrThreads) void sparse_corrected_kernel(
-    Geo g, View y, int32_t k, int32_t window, int tiles_per_row, int nblocks,
+    Geo g, View y, int32_t k, int32_t window, int tiles_per_row, int nblocks, int stage_rows,
     const int32_t* __restrict__ offsets, const void* __restrict__ weights,
     const float* __restrict__ dphi, const float* __restrict__ dpsi,
     const char* __restrict__ ydata, float2* __restrict__ image) {
   constexpr int ES = Elem<DT>::bytes;
+  constexpr bool LIN = INTERP == ROSAR_LINEAR;
+  constexpr int EB = LIN ? 16 : 8;   // bytes per staged element
   constexpr float kInv2Pi = 0.15915494309189533577f;
   __shared__ CorrTap s_tap[kCorrChunk];
   __shared__ float s_red[kCorrThreads / kWave];
-  extern __shared__ float2 s_pul[];   // TABLE: (psi / 2 pi, d) then (sin(d/2), cos(d/2)), kCorrTile + window each
+  __shared__ int s_redi[2 * (kCorrThreads / kWave)];
+  // TABLE: global gathers: float4 per column; staged: stage_rows rows of float2 (NEAREST) or
+  // float4 (LINEAR), then (beta d, (k / pi) d) per column
+  extern __shared__ float4 s_dyn[];
   const int blk = xcd_logical_block(blockIdx.x, nblocks);
   const int row = blk / tiles_per_row;
   const int tile = blk - row * tiles_per_row;
   const int n = g.n;
   const int half_w = window / 2;
+  const int cols = kCorrTile + window;
   const int a0 = tile * kCorrTile;
   const int lane = threadIdx.x & (kWave - 1);
   const int wave = threadIdx.x / kWave;
   const int i_wave = wave * kWave * kCorrP;
   const double rr = g.r0 + row * g.dr;
+  const float kpi = (float)g.k_over_pi;
+  const float beta = (float)g.beta;
+  const double c1 = rr * rr + g.radius * g.radius;
+  const double c2 = 2.0 * rr * g.radius;
+  const float c4 = (float)(2.0 * c2);   // 4 R r
+  const double u_shift = INTERP == ROSAR_NEAREST ? 0.5 - y.l_lo : -(double)y.l_lo;
+  const __amdgpu_buffer_rsrc_t rsrc = make_rsrc(ydata, (uint32_t)((int64_t)y.l_count * y.ld * ES));
+  const int ld_es = (int)(y.ld * ES);
+  const int64_t wrow = (int64_t)row * k;
 
-  bool series = false;
+  // pulse of column c of the tables (columns wrap around the rotation)
+  auto pulse_of = [&](int c) {
+    int pn = a0 - half_w + c;
+    if (pn < 0 || pn >= n) pn = ((pn % n) + n) % n;
+    return pn;
+  };
+  // float64 nominal bin of offset o (eq. 2, eq. 40), with the sine and cosine of D0 and R_nom^2
+  auto nominal = [&](int o, double& sd, double& cd, double& r2) {
+    sincos(o * g.step, &sd, &cd);
+    r2 = c1 - c2 * cd;
+    return g.beta * sqrt(r2) + u_shift;
+  };
+
+  // offsets of the first taps and weights of the first tap chunk, requested before anything
+  // waits on memory
+  const int o_first = (int)threadIdx.x < k ? offsets[wrow + threadIdx.x] : 0;
+  int o_next = o_first;
+  float2 w_next = make_float2(0.f, 0.f);
+  if ((int)threadIdx.x < min(kCorrChunk, k)) w_next = load_w<WDT>(weights, wrow + threadIdx.x);
+
+  bool series = false, staged = false;
+  float tie_err = 0.f;   // series paths, NEAREST: bound on the error of the float32 bin sum
+  int lmin = 0, nrows = 0;
+  // (d, psi) of every column, in the dynamic LDS past the tables built from it
+  float2* dps = reinterpret_cast<float2*>(reinterpret_cast<char*>(s_dyn) + max(16, stage_rows * EB) * cols);
   if constexpr (TABLE) {
     float dmax = 0.f;
-    for (int c = threadIdx.x; c < kCorrTile + window; c += kCorrThreads) {
-      int pn = (a0 - half_w + c) % n;
-      pn += pn < 0 ? n : 0;
-      float sh = 0.f, ch = 1.f, d = 0.f;
-      if (dphi) {
-        d = dphi[pn];
-        sincosf(0.5f * d, &sh, &ch);
+    for (int cb = threadIdx.x; cb < cols; cb += kColBatch * kCorrThreads) {
+      float dv[kColBatch], pv[kColBatch];
+#pragma unroll
+      for (int j = 0; j < kColBatch; ++j) {
+        const int c = cb + j * kCorrThreads;
+        dv[j] = 0.f;
+        pv[j] = 0.f;
+        if (c < cols) {
+          const int pn = pulse_of(c);
+          if (dphi) dv[j] = dphi[pn];
+          if (dpsi) pv[j] = dpsi[pn];
+        }
       }
-      dmax = fmaxf(dmax, fabsf(d));
-      float pr = dpsi ? dpsi[pn] * kInv2Pi : 0.f;
-      pr -= rintf(pr);
-      s_pul[c] = make_float2(pr, d);
-      s_pul[kCorrTile + window + c] = make_float2(sh, ch);
+#pragma unroll
+      for (int j = 0; j < kColBatch; ++j) {
+        const int c = cb + j * kCorrThreads;
+        if (c < cols) {
+          dps[c] = make_float2(dv[j], pv[j]);
+          dmax = fmaxf(dmax, fabsf(dv[j]));
+        }
+      }
     }
     for (int off = kWave / 2; off > 0; off >>= 1) dmax = fmaxf(dmax, __shfl_xor(dmax, off));
     if (lane == 0) s_red[wave] = dmax;
@@ -261,6 +330,7 @@ __global__ __launch_bounds__(kCorrThreads) void sparse_corrected_kernel(
 #pragma unroll
     for (int w = 1; w < kCorrThreads / kWave; ++w) dmax = fmaxf(dmax, s_red[w]);
     const double rho = rr - g.radius;
+    double cmax = 0.0;   // bound on |beta (R^ - R_nom)| of the series path, in bins
     if (rho > 0.0 && dmax == dmax) {
       const double c = 2.0 * rr * g.radius;
       const double m4 = 2.0 * (c / (2.0 * rho) + 0.75 * c * c / (rho * rho * rho));
@@ -268,145 +338,329 @@ __global__ __launch_bounds__(kCorrThreads) void sparse_corrected_kernel(
       const double rem = m4 * d2 * d2 / 24.0;   // metres
       series = rem * (kTwoPiD * g.k_over_pi) <= 1e-6 && rem * g.beta <= 0x1p-20 &&
                g.beta * g.radius * (double)dmax < 0.5 && g.k_over_pi * g.radius * (double)dmax < 64.0;
+      cmax = g.beta * g.radius * (double)dmax + 0x1p-20;
+      // the sum's error bound as in corr_bin, with |correction| <= cmax
+      tie_err = (float)(0x1p-18 + cmax * 0x1p-12);
+    }
+    if (series && stage_rows > 0) {
+      // rows the pairs can reach: floor(u +- cmax) over the in-window taps, with a margin for
+      // the float32 evaluation of the sum
+      const double cm = cmax * (1.0 + 0x1p-10) + 0x1p-16;
+      int lo = INT_MAX, hi = INT_MIN;
+      for (int t = threadIdx.x; t < k; t += kCorrThreads) {
+        const int o = t == (int)threadIdx.x ? o_first : offsets[wrow + t];
+        if (o >= -half_w && o < half_w) {
+          double sd, cd, r2;
+          const double u = nominal(o, sd, cd, r2);
+          lo = min(lo, (int)floor(u - cm));
+          hi = max(hi, (int)floor(u + cm));
+        }
+      }
+      for (int off = kWave / 2; off > 0; off >>= 1) {
+        lo = min(lo, __shfl_xor(lo, off));
+        hi = max(hi, __shfl_xor(hi, off));
+      }
+      if (lane == 0) {
+        s_redi[2 * wave] = lo;
+        s_redi[2 * wave + 1] = hi;
+      }
+      __syncthreads();
+      lo = s_redi[0];
+      hi = s_redi[1];
+#pragma unroll
+      for (int w = 1; w < kCorrThreads / kWave; ++w) {
+        lo = min(lo, s_redi[2 * w]);
+        hi = max(hi, s_redi[2 * w + 1]);
+      }
+      if (hi < lo) lo = hi = 0;   // no tap inside the window
+      lmin = lo;
+      nrows = hi - lo + 1;
+      staged = nrows <= stage_rows;
+    }
+    if (staged) {
+      // band rows lmin .. lmin + nrows - 1 (LINEAR: and the next) over the columns, turned by
+      // exp(-j psi)
+      // (the (beta d, (k / pi) d) table takes the place of (d, psi), column by column)
+      float2* ek = dps;
+      const int nload = nrows + (LIN ? 1 : 0);   // at most kStageLoads
+      for (int cb = threadIdx.x; cb < cols; cb += kColBatch * kCorrThreads) {
+        float2 v[kColBatch][kStageLoads];
+#pragma unroll
+        for (int j = 0; j < kColBatch; ++j) {
+          const int c = cb + j * kCorrThreads;
+          const uint32_t colb = c < cols ? (uint32_t)((pulse_of(c) + y.halo) * ES) : 0u;
+#pragma unroll
+          for (int r = 0; r < kStageLoads; ++r) {
+            const int l = lmin + r;
+            v[j][r] = make_float2(0.f, 0.f);
+            if (c < cols && r < nload && l >= 0 && l < y.l_count)
+              v[j][r] = buf_load<DT>(rsrc, (uint32_t)__mul24(l, ld_es) + colb, 0u);
+          }
+        }
+#pragma unroll
+        for (int j = 0; j < kColBatch; ++j) {
+          const int c = cb + j * kCorrThreads;
+          if (c >= cols) continue;
+          const float2 dp = dps[c];
+          float sp = 0.f, cp = 1.f;
+          if (dpsi) sincosf(dp.y, &sp, &cp);
+          ek[c] = make_float2(beta * dp.x, kpi * dp.x);
+#pragma unroll
+          for (int r = 0; r < kStageLoads; ++r)
+            v[j][r] = make_float2(fmaf(v[j][r].x, cp, v[j][r].y * sp), fmaf(v[j][r].y, cp, -v[j][r].x * sp));
+#pragma unroll
+          for (int r = 0; r < kStageLoads - (LIN ? 1 : 0); ++r) {
+            if (r >= nrows) break;
+            if constexpr (LIN) {
+              reinterpret_cast<float4*>(s_dyn)[r * cols + c] =
+                  make_float4(v[j][r].x, v[j][r].y, v[j][r + 1].x - v[j][r].x, v[j][r + 1].y - v[j][r].y);
+            } else {
+              reinterpret_cast<float2*>(s_dyn)[r * cols + c] = v[j][r];
+            }
+          }
+        }
+      }
+    } else {
+      for (int c = threadIdx.x; c < cols; c += kCorrThreads) {
+        const float2 dp = dps[c];
+        const float d = dp.x;
+        float pr = dp.y * kInv2Pi;
+        pr -= rintf(pr);
+        if (series) {
+          s_dyn[c] = make_float4(pr, beta * d, kpi * d, 0.f);
+        } else {
+          float sh = 0.f, ch = 1.f;
+          if (dphi) sincosf(0.5f * d, &sh, &ch);
+          s_dyn[c] = make_float4(pr, d, sh, ch);
+        }
+      }
     }
   }
 
-  const double c1 = rr * rr + g.radius * g.radius;
-  const double c2 = 2.0 * rr * g.radius;
-  const float c4 = (float)(2.0 * c2);   // 4 R r
-  const float kpi = (float)g.k_over_pi;
-  const float beta = (float)g.beta;
-  const double u_shift = INTERP == ROSAR_NEAREST ? 0.5 - y.l_lo : -(double)y.l_lo;
-  const __amdgpu_buffer_rsrc_t rsrc = make_rsrc(ydata, (uint32_t)((int64_t)y.l_count * y.ld * ES));
-  const int ld_es = (int)(y.ld * ES);
-  const int64_t wrow = (int64_t)row * k;
-  int acol[kCorrP];   // pixel column, clamped into the rotation for padding lanes
+  const bool wave_live = a0 + i_wave < n;   // some pixel of this wave lies in the rotation
+  int acol[kCorrP];        // pixel column, clamped into the rotation for padding lanes
+  uint32_t acb[kCorrP];    // its byte offset in a band row
   float2 acc[kCorrP];
 #pragma unroll
   for (int p = 0; p < kCorrP; ++p) {
     acol[p] = min(a0 + i_wave + lane + kWave * p, n - 1);
+    acb[p] = (uint32_t)acol[p] * ES;
     acc[p] = make_float2(0.f, 0.f);
   }
 
-  // the tap loop, with the series (SERIES = true) or the exact correction; DIRECT: the halo
-  // holds every column a + o (no wrap)
-  auto taps = [&](auto series_tag, auto direct_tag) {
-    constexpr bool SERIES = decltype(series_tag)::value;
-    constexpr bool DIRECT = decltype(direct_tag)::value;
+  // tap table of taps [c0, c0 + cnt), one per thread of wave 0, from the offsets and weights
+  // loaded ahead; then the next chunk's are requested, to arrive during this chunk's pairs
+  auto build_taps = [&](int c0, int cnt, bool ser, bool stg) {
+    if ((int)threadIdx.x < cnt) {
+      const int o = o_next;
+      const float2 w = w_next;
+      const bool inwin = o >= -half_w && o < half_w;
+      double sd, cd, r2;
+      const double u = nominal(o, sd, cd, r2);
+      const double rn = sqrt(r2);
+      CorrTap e;
+      e.u = split_bin(u);
+      e.r2 = (float)r2;
+      e.rnom = (float)rn;
+      e.sd = (float)sd;
+      e.cd = (float)cd;
+      e.wa = inwin ? (float)sqrt((double)w.x * w.x + (double)w.y * w.y) : 0.f;
+      e.wt = atan2f(w.y, w.x) * (float)(1.0 / kTwoPiD);
+      // derivatives of R(D) = sqrt(S), S = c1 - c2 cos D, at D0 (S' = c2 sin D0, S'' = c2 cos D0);
+      // the quadratic and cubic coefficients are taken per power of e = beta d
+      const double s1 = c2 * sd, s2 = c2 * cd;
+      const double ir = 1.0 / rn, ir3 = ir * ir * ir, ir5 = ir3 * ir * ir;
+      const double ib = 1.0 / g.beta;
+      e.q1 = (float)(0.5 * s1 * ir);
+      e.q2 = (float)(0.5 * (0.5 * s2 * ir - 0.25 * s1 * s1 * ir3) * ib);
+      e.q3 = (float)((-0.5 * s1 * ir - 0.75 * s1 * s2 * ir3 + 0.375 * s1 * s1 * s1 * ir5) / 6.0 * ib * ib);
+      e.o = inwin ? o : 0;
+      if (stg) {
+        // byte offset of (row u.i - lmin, column o + W/2) in the staged rows; a tap outside
+        // the window (zero weight) reads row 0 with li = 0
+        if (!inwin) {
+          e.u.i = lmin;
+          e.u.f = 0.5f;
+        }
+        e.ub = (e.u.i - lmin) * (cols * EB) + (e.o + half_w) * EB;
+      } else if (ser) {
+        // byte offset of (row u.i, column o + halo) in the band, the row clamped so that every
+        // sampled row stays out of the band when the nominal one is
+        e.u.i = min(max(e.u.i, -3), y.l_count + 2);
+        e.ub = (int32_t)((uint32_t)e.u.i * (uint32_t)ld_es + (uint32_t)((e.o + y.halo) * ES));
+      } else {
+        e.ub = 0;
+      }
+      s_tap[threadIdx.x] = e;
+    }
+    const int c1 = c0 + kCorrChunk;
+    if ((int)threadIdx.x < min(kCorrChunk, k - c1)) {
+      o_next = offsets[wrow + c1 + threadIdx.x];
+      w_next = load_w<WDT>(weights, wrow + c1 + threadIdx.x);
+    }
+  };
+
+  // exp term and accumulation shared by every path: acc += |w| exp(-j 2 pi rev) smp, where rev
+  // already holds arg(w) / 2 pi
+  auto accumulate = [&](float2& ac, const CorrTap& tp, float rev, float2 smp) {
+    const float a = tp.wa * cos_rev(rev), b = tp.wa * sin_rev(rev);
+    ac.x = fmaf(smp.x, a, fmaf(smp.y, b, ac.x));
+    ac.y = fmaf(smp.y, a, fmaf(-smp.x, b, ac.y));
+  };
+
+  // NEAREST tie: the plain float64 bin at the angle (o 2 pi) / N + delta_n of the oracle's
+  // definition, sampled from the band in global memory
+  auto tie_sample = [&](int p, const CorrTap& tp, int& pn) {
+    pn = acol[p] + tp.o;
+    pn += (pn < 0) ? n : 0;
+    pn -= (pn >= n) ? n : 0;
+    const double d = (double)tp.o * g.step + (dphi ? (double)dphi[pn] : 0.0);
+    int l = (int)floor(plain_bin_half(rr, g.radius, d, g.beta)) - y.l_lo;
+    l = min(max(l, -1), y.l_count);
+    return buf_load<DT>(rsrc, (uint32_t)(__mul24(l, ld_es) + (pn + y.halo) * ES), 0u);
+  };
+
+  if (staged) {
+    // series path over the staged rows
+    const char* band = reinterpret_cast<const char*>(s_dyn);
+    const float2* ek = dps;
+    const int rowb = cols * EB;
+    const int laneb = (i_wave + lane) * EB;
     for (int c0 = 0; c0 < k; c0 += kCorrChunk) {
       const int cnt = min(kCorrChunk, k - c0);
-      if ((int)threadIdx.x < cnt) {
-        const int t = c0 + (int)threadIdx.x;
-        const int o = offsets[wrow + t];
-        const float2 w = load_w<WDT>(weights, wrow + t);
-        const bool inwin = o >= -half_w && o < half_w;
-        double sd, cd;
-        sincos(o * g.step, &sd, &cd);
-        const double r2 = c1 - c2 * cd;
-        const double rn = sqrt(r2);
-        CorrTap e;
-        e.u = split_bin(g.beta * rn + u_shift);
-        if constexpr (SERIES) e.u.i = min(max(e.u.i, -3), y.l_count + 2);
-        e.r2 = (float)r2;
-        e.rnom = (float)rn;
-        e.sd = (float)sd;
-        e.cd = (float)cd;
-        e.wr = inwin ? w.x : 0.f;
-        e.wi = inwin ? w.y : 0.f;
-        // derivatives of R(D) = sqrt(S), S = c1 - c2 cos D, at D0 (S' = c2 sin D0, S'' = c2 cos D0)
-        const double s1 = c2 * sd, s2 = c2 * cd;
-        const double ir = 1.0 / rn, ir3 = ir * ir * ir, ir5 = ir3 * ir * ir;
-        e.q1 = (float)(0.5 * s1 * ir);
-        e.q2 = (float)(0.5 * (0.5 * s2 * ir - 0.25 * s1 * s1 * ir3));
-        e.q3 = (float)((-0.5 * s1 * ir - 0.75 * s1 * s2 * ir3 + 0.375 * s1 * s1 * s1 * ir5) / 6.0);
-        e.o = inwin ? o : 0;
-        s_tap[threadIdx.x] = e;
-      }
+      build_taps(c0, cnt, true, true);
       __syncthreads();
-      for (int t = 0; t < cnt; ++t) {
+      for (int t = 0; t < (wave_live ? cnt : 0); ++t) {
         const CorrTap tp = s_tap[t];
-        const float2 w = make_float2(tp.wr, tp.wi);
+        const int base = tp.ub + laneb;
+        float2 smp[kCorrP];
+        float rev[kCorrP];
+        int ties = 0;   // NEAREST: bit p set when pixel p's bin sum lies near a rounding boundary
 #pragma unroll
         for (int p = 0; p < kCorrP; ++p) {
-          float sh = 0.f, ch = 1.f, pr, dn = 0.f;
-          int col = acol[p] + tp.o;
-          if constexpr (TABLE) {
-            const int c = i_wave + lane + kWave * p + tp.o + half_w;
-            const float2 q = s_pul[c];
-            pr = q.x;
-            dn = q.y;
-            if constexpr (!SERIES) {
-              const float2 h = s_pul[kCorrTile + window + c];
-              sh = h.x;
-              ch = h.y;
-            }
-          } else {
-            int pn = col;
-            pn += (pn < 0) ? n : 0;
-            pn -= (pn >= n) ? n : 0;
-            if (dphi) sincosf(0.5f * dphi[pn], &sh, &ch);
-            pr = dpsi ? dpsi[pn] * kInv2Pi : 0.f;
-          }
-          if constexpr (!DIRECT) {
-            col += (col < 0) ? n : 0;
-            col -= (col >= n) ? n : 0;
-          }
-          const int cb = (col + y.halo) * ES;
-          float diff;   // R^ - R_nom
-          if constexpr (SERIES) {
-            diff = dn * fmaf(dn, fmaf(dn, tp.q3, tp.q2), tp.q1);
-          } else {
-            const float s_mid = fmaf(tp.sd, ch, tp.cd * sh);   // sin(D0 + d/2)
-            const float dd = c4 * s_mid * sh;                    // R^2 - R_nom^2
-            const float r2 = fmaxf(tp.r2 + dd, 1e-30f);
-            const float rn = r2 * __builtin_amdgcn_rsqf(r2);
-            diff = dd * __builtin_amdgcn_rcpf(rn + tp.rnom);
-          }
-          const float corr = beta * diff;
-          float fr;
-          bool tie;
-          int l = corr_bin(tp.u, corr, &fr, &tie);
-          float2 smp;
+          const float2 q = ek[i_wave + lane + kWave * p + tp.o + half_w];
+          const float s = fmaf(q.x, fmaf(q.x, tp.q3, tp.q2), tp.q1);
+          const float x = fmaf(q.x, s, tp.u.f);
+          rev[p] = fmaf(q.y, s, tp.wt);
+          const float fr = __builtin_amdgcn_fractf(x);
+          const char* at = band + (__mul24(floor_to_int(x), rowb) + base) + kWave * EB * p;
           if constexpr (INTERP == ROSAR_NEAREST) {
-            if (__builtin_expect(tie, 0)) {
-              // plain float64 bin at the angle (o 2 pi) / N + delta_n of the oracle's definition
-              int pn = acol[p] + tp.o;
-              pn += (pn < 0) ? n : 0;
-              pn -= (pn >= n) ? n : 0;
-              const double d = (double)tp.o * g.step + (dphi ? (double)dphi[pn] : 0.0);
-              l = (int)floor(plain_bin_half(rr, g.radius, d, g.beta)) - y.l_lo;
-              l = min(max(l, -1), y.l_count);
-            }
-            if constexpr (!SERIES) l = min(max(l, -1), y.l_count);
-            smp = buf_load<DT>(rsrc, (uint32_t)(__mul24(l, ld_es) + cb), 0u);
+            smp[p] = *reinterpret_cast<const float2*>(at);
+            ties |= (fr < tie_err || fr > 1.f - tie_err) ? (1 << p) : 0;
           } else {
-            if constexpr (!SERIES) l = min(max(l, -2), y.l_count);
-            const uint32_t off0 = (uint32_t)(__mul24(l, ld_es) + cb);
-            const float2 y0 = buf_load<DT>(rsrc, off0, 0u);
-            const float2 y1 = buf_load<DT>(rsrc, off0 + (uint32_t)ld_es, 0u);
-            smp = make_float2(fmaf(fr, y1.x - y0.x, y0.x), fmaf(fr, y1.y - y0.y, y0.y));
+            const float4 v = *reinterpret_cast<const float4*>(at);
+            smp[p] = make_float2(fmaf(fr, v.z, v.x), fmaf(fr, v.w, v.y));
           }
-          // exp(-j (2 k (R^ - R_nom) + psi)) in revolutions
-          float rev = fmaf(kpi, diff, pr);
-          if constexpr (!SERIES) rev -= floorf(rev);
-          const float2 rot = make_float2(cos_rev(rev), -sin_rev(rev));
-          cmac_conj(acc[p], w, cmul(smp, rot));
         }
+        if constexpr (INTERP == ROSAR_NEAREST) {
+          if (__builtin_expect(__builtin_amdgcn_ballot_w64(ties != 0) != 0, 0)) {
+#pragma unroll
+            for (int p = 0; p < kCorrP; ++p) {
+              if (ties & (1 << p)) {
+                // the tie's sample comes from global memory, not yet turned by exp(-j psi)
+                int pn;
+                smp[p] = tie_sample(p, tp, pn);
+                float pr = dpsi ? dpsi[pn] * kInv2Pi : 0.f;
+                rev[p] += pr - rintf(pr);
+              }
+            }
+          }
+        }
+#pragma unroll
+        for (int p = 0; p < kCorrP; ++p) accumulate(acc[p], tp, rev[p], smp[p]);
       }
       __syncthreads();
     }
-  };
-  const bool direct = y.halo >= half_w;
-  if (series) {
-    if (direct)
-      taps(std::true_type{}, std::true_type{});
-    else
-      taps(std::true_type{}, std::false_type{});
   } else {
-    if (direct)
-      taps(std::false_type{}, std::true_type{});
-    else
-      taps(std::false_type{}, std::false_type{});
+    // gathers from global memory, with the series (SERIES = true) or the exact correction;
+    // DIRECT: the halo holds every column a + o (no wrap)
+    auto taps = [&](auto series_tag, auto direct_tag) {
+      constexpr bool SERIES = decltype(series_tag)::value;
+      constexpr bool DIRECT = decltype(direct_tag)::value;
+      for (int c0 = 0; c0 < k; c0 += kCorrChunk) {
+        const int cnt = min(kCorrChunk, k - c0);
+        build_taps(c0, cnt, SERIES, false);
+        __syncthreads();
+        for (int t = 0; t < (wave_live ? cnt : 0); ++t) {
+          const CorrTap tp = s_tap[t];
+#pragma unroll
+          for (int p = 0; p < kCorrP; ++p) {
+            float x, rev, err = tie_err;
+            if constexpr (SERIES) {
+              const float4 q = s_dyn[i_wave + lane + kWave * p + tp.o + half_w];
+              const float s = fmaf(q.y, fmaf(q.y, tp.q3, tp.q2), tp.q1);
+              x = fmaf(q.y, s, tp.u.f);
+              rev = fmaf(q.z, s, q.x);
+            } else {
+              float sh = 0.f, ch = 1.f, pr;
+              if constexpr (TABLE) {
+                const float4 q = s_dyn[i_wave + lane + kWave * p + tp.o + half_w];
+                pr = q.x;
+                sh = q.z;
+                ch = q.w;
+              } else {
+                int pn = acol[p] + tp.o;
+                pn += (pn < 0) ? n : 0;
+                pn -= (pn >= n) ? n : 0;
+                if (dphi) sincosf(0.5f * dphi[pn], &sh, &ch);
+                pr = dpsi ? dpsi[pn] * kInv2Pi : 0.f;
+              }
+              const float s_mid = fmaf(tp.sd, ch, tp.cd * sh);   // sin(D0 + d/2)
+              const float dd = c4 * s_mid * sh;                    // R^2 - R_nom^2
+              const float r2 = fmaxf(tp.r2 + dd, 1e-30f);
+              const float rn = r2 * __builtin_amdgcn_rsqf(r2);
+              const float diff = dd * __builtin_amdgcn_rcpf(rn + tp.rnom);   // R^ - R_nom
+              const float corr = beta * diff;
+              x = tp.u.f + corr;
+              err = 0x1p-18f + fabsf(corr) * 0x1p-12f;
+              rev = fmaf(kpi, diff, pr);
+              rev -= floorf(rev);
+            }
+            const float fr = __builtin_amdgcn_fractf(x);
+            const int li = floor_to_int(x);
+            uint32_t off0;
+            if constexpr (SERIES && DIRECT) {
+              off0 = (uint32_t)__mul24(li, ld_es) + (acb[p] + (uint32_t)tp.ub);
+            } else {
+              int col = acol[p] + tp.o;
+              if constexpr (!DIRECT) {
+                col += (col < 0) ? n : 0;
+                col -= (col >= n) ? n : 0;
+              }
+              int l = tp.u.i + li;
+              if constexpr (!SERIES) l = min(max(l, INTERP == ROSAR_NEAREST ? -1 : -2), y.l_count);
+              off0 = (uint32_t)(__mul24(l, ld_es) + (col + y.halo) * ES);
+            }
+            float2 smp;
+            if constexpr (INTERP == ROSAR_NEAREST) {
+              smp = buf_load<DT>(rsrc, off0, 0u);
+              if (__builtin_expect(fr < err || fr > 1.f - err, 0)) {
+                int pn;
+                smp = tie_sample(p, tp, pn);
+              }
+            } else {
+              const float2 y0 = buf_load<DT>(rsrc, off0, 0u);
+              const float2 y1 = buf_load<DT>(rsrc, off0 + (uint32_t)ld_es, 0u);
+              smp = make_float2(fmaf(fr, y1.x - y0.x, y0.x), fmaf(fr, y1.y - y0.y, y0.y));
+            }
+            accumulate(acc[p], tp, rev + tp.wt, smp);
+          }
+        }
+        __syncthreads();
+      }
+    };
+    const bool direct = y.halo >= half_w;
+    if (series) {
+      if (direct)
+        taps(std::true_type{}, std::true_type{});
+      else
+        taps(std::true_type{}, std::false_type{});
+    } else {
+      if (direct)
+        taps(std::false_type{}, std::true_type{});
+      else
+        taps(std::false_type{}, std::false_type{});
+    }
   }
 
   float2* out = image + (int64_t)row * n;
@@ -493,13 +747,17 @@ hipError_t launch_corr_t(const SparseArgs& a, hipStream_t s) {
   const int tiles = (a.g.n + kCorrTile - 1) / kCorrTile;
   const int nblocks = tiles * a.g.n_range;
   const char* yd = reinterpret_cast<const char*>(a.y.data);
-  if (kCorrTile + a.window <= kCorrMaxCols) {
-    const size_t lds = (size_t)(kCorrTile + a.window) * 2 * sizeof(float2);
+  const int cols = kCorrTile + a.window;
+  if (cols <= kCorrMaxCols) {
+    // dynamic LDS: the float4 column table or the staged band rows, then a float2 per column
+    const bool lin = INTERP == ROSAR_LINEAR;
+    const int stage = cols <= kCorrStageCols ? (lin ? kCorrStageRowsL : kCorrStageRowsN) : 0;
+    const size_t lds = (size_t)std::max(16, stage * (lin ? 16 : 8)) * cols + (size_t)cols * sizeof(float2);
     sparse_corrected_kernel<DT, WDT, INTERP, true><<<nblocks, kCorrThreads, lds, s>>>(
-        a.g, a.y, a.k, a.window, tiles, nblocks, a.offsets, a.weights, a.dphi, a.dpsi, yd, a.image);
+        a.g, a.y, a.k, a.window, tiles, nblocks, stage, a.offsets, a.weights, a.dphi, a.dpsi, yd, a.image);
   } else {
     sparse_corrected_kernel<DT, WDT, INTERP, false><<<nblocks, kCorrThreads, 0, s>>>(
-        a.g, a.y, a.k, a.window, tiles, nblocks, a.offsets, a.weights, a.dphi, a.dpsi, yd, a.image);
+        a.g, a.y, a.k, a.window, tiles, nblocks, 0, a.offsets, a.weights, a.dphi, a.dpsi, yd, a.image);
   }
   return hipGetLastError();
 }
