@@ -179,16 +179,17 @@ __global__ __launch_bounds__(kWave* NW) void sparse_plain_kernel(
 constexpr int kCorrThreads = 256;
 constexpr int kCorrP = 4;                          // pixels per lane (64 apart)
 constexpr int kCorrTile = kCorrThreads * kCorrP;   // pixels per workgroup
-constexpr int kCorrChunk = 32;                     // taps per chunk (one per thread of wave 0)
+constexpr int kCorrChunk = 32;                     // taps per chunk, global gathers (one per thread of wave 0)
+constexpr int kCorrChunkS = 64;                    // taps per chunk, staged path
 constexpr int kCorrMaxCols = 4096;                 // largest per-pulse table held in LDS (T + W)
 constexpr int kCorrStageCols = 2048;               // largest T + W whose band rows are staged in LDS
 constexpr int kCorrStageRowsN = 3;                 // NEAREST: band rows staged per workgroup
 constexpr int kCorrStageRowsL = 2;                 // LINEAR: (row, next row - row) pairs staged
-constexpr int kColBatch = 4;                       // columns per thread whose loads are issued together
+constexpr int kColBatch = 8;                       // columns per thread whose loads are issued together
 constexpr int kStageLoads = 3;                     // band rows loaded per staged column
 static_assert(kCorrStageRowsN <= kStageLoads && kCorrStageRowsL + 1 <= kStageLoads, "staging loads");
 
-// Nominal geometry and weight of one tap (no angle error), 64 bytes.
+// Nominal geometry and weight of one tap (no angle error), 64 bytes in LDS.
 struct alignas(16) CorrTap {
   SplitBin u;       // band-relative bin beta * R_nom - l_lo (+ 1/2 for NEAREST), split
   float r2;         // R_nom^2
@@ -197,9 +198,21 @@ struct alignas(16) CorrTap {
   float wa, wt;     // weight as |w| (zero for an offset outside the window) and arg(w) / 2 pi
   float q1, q2, q3; // series in e = beta d: R(D0 + d) - R_nom = d (q1 + e (q2 + e q3)) + O(d^4)
   int32_t o;        // offset (zero outside the window)
-  int32_t ub;       // series paths: byte offset of the tap's nominal row and column (see below)
-  int32_t pad[3];
+  int32_t ub;       // series path from global memory: byte offset of the clamped nominal row and column
+  int32_t inwin;    // offset inside the window
+  double u64;       // the float64 nominal bin (registers only)
 };
+
+// The staged series path's 32-byte entry of one tap.
+struct alignas(16) CorrTapS {
+  float uf;         // fraction of the nominal bin (1/2 outside the window)
+  float q1, q2, q3; // series coefficients as in CorrTap
+  float wa, wt;     // |w| and arg(w) / 2 pi
+  int32_t o;        // offset (zero outside the window)
+  int32_t ub;       // byte offset of (row u.i - lmin, column o + W/2) in the staged rows
+};
+constexpr size_t kTapBufBytes = std::max(kCorrChunk * sizeof(CorrTap), kCorrChunkS * sizeof(CorrTapS));
+static_assert(sizeof(CorrTap) == 64 && sizeof(CorrTapS) == 32, "tap entry sizes");
 
 // floor(x) converted to int32 in one instruction (the compiler emits a floor and a convert).
 __device__ __forceinline__ int floor_to_int(float x) {
@@ -247,9 +260,13 @@ __global__ __launch_bounds__(kCorrThreads) void sparse_corrected_kernel(
   constexpr bool LIN = INTERP == ROSAR_LINEAR;
   constexpr int EB = LIN ? 16 : 8;   // bytes per staged element
   constexpr float kInv2Pi = 0.15915494309189533577f;
-  __shared__ CorrTap s_tap[kCorrChunk];
+  // tap tables: kCorrChunk CorrTap (gathers from global memory) or kCorrChunkS CorrTapS (staged)
+  __shared__ float4 s_tapbuf[kTapBufBytes / sizeof(float4)];
+  CorrTap* s_tap = reinterpret_cast<CorrTap*>(s_tapbuf);
+  CorrTapS* s_tapS = reinterpret_cast<CorrTapS*>(s_tapbuf);
   __shared__ float s_red[kCorrThreads / kWave];
   __shared__ int s_redi[2 * (kCorrThreads / kWave)];
+  __shared__ int s_nfast;   // staged path: taps of the chunk on the fast path (listed first)
   // TABLE: global gathers: float4 per column; staged: stage_rows rows of float2 (NEAREST) or
   // float4 (LINEAR), then (beta d, (k / pi) d) per column
   extern __shared__ float4 s_dyn[];
@@ -290,13 +307,76 @@ __global__ __launch_bounds__(kCorrThreads) void sparse_corrected_kernel(
   // offsets of the first taps and weights of the first tap chunk, requested before anything
   // waits on memory
   const int o_first = (int)threadIdx.x < k ? offsets[wrow + threadIdx.x] : 0;
+  float2 w_first = make_float2(0.f, 0.f);
+  if ((int)threadIdx.x < min(kCorrChunkS, k)) w_first = load_w<WDT>(weights, wrow + threadIdx.x);
   int o_next = o_first;
-  float2 w_next = make_float2(0.f, 0.f);
-  if ((int)threadIdx.x < min(kCorrChunk, k)) w_next = load_w<WDT>(weights, wrow + threadIdx.x);
+  float2 w_next = w_first;
 
   bool series = false, staged = false;
   float tie_err = 0.f;   // series paths, NEAREST: bound on the error of the float32 bin sum
+  double cm = 0.0;       // series paths: bound on |x - u.f| of a pair, in bins
   int lmin = 0, nrows = 0;
+
+  // float64 nominal geometry, weight and series coefficients of one tap (ub left zero)
+  auto tap_geom = [&](int o, float2 w) {
+    const bool inwin = o >= -half_w && o < half_w;
+    double sd, cd, r2;
+    const double u = nominal(o, sd, cd, r2);
+    const double rn = sqrt(r2);
+    CorrTap e;
+    e.u = split_bin(u);
+    e.r2 = (float)r2;
+    e.rnom = (float)rn;
+    e.sd = (float)sd;
+    e.cd = (float)cd;
+    e.wa = inwin ? (float)sqrt((double)w.x * w.x + (double)w.y * w.y) : 0.f;
+    e.wt = atan2f(w.y, w.x) * (float)(1.0 / kTwoPiD);
+    // derivatives of R(D) = sqrt(S), S = c1 - c2 cos D, at D0 (S' = c2 sin D0, S'' = c2 cos D0);
+    // the quadratic and cubic coefficients are taken per power of e = beta d
+    const double s1 = c2 * sd, s2 = c2 * cd;
+    const double ir = 1.0 / rn, ir3 = ir * ir * ir, ir5 = ir3 * ir * ir;
+    const double ib = 1.0 / g.beta;
+    e.q1 = (float)(0.5 * s1 * ir);
+    e.q2 = (float)(0.5 * (0.5 * s2 * ir - 0.25 * s1 * s1 * ir3) * ib);
+    e.q3 = (float)((-0.5 * s1 * ir - 0.75 * s1 * s2 * ir3 + 0.375 * s1 * s1 * s1 * ir5) / 6.0 * ib * ib);
+    e.o = inwin ? o : 0;
+    e.ub = 0;
+    e.inwin = inwin;
+    e.u64 = u;
+    return e;
+  };
+  // staged-path entry: byte offset of (row u.i - lmin, column o + W/2) in the staged rows; a
+  // tap outside the window (zero weight) reads row 0 with li = 0
+  auto staged_entry = [&](const CorrTap& e) {
+    CorrTapS t;
+    t.uf = e.inwin ? e.u.f : 0.5f;
+    t.q1 = e.q1;
+    t.q2 = e.q2;
+    t.q3 = e.q3;
+    t.wa = e.wa;
+    t.wt = e.wt;
+    t.o = e.o;
+    t.ub = ((e.inwin ? e.u.i : lmin) - lmin) * (cols * EB) + (e.o + half_w) * EB;
+    return t;
+  };
+  // wave 0 files the staged entries of its lanes' taps (valid: the lane holds a tap): first the
+  // taps whose every pair has floor(x) = 0 (NEAREST: and no tie), so that they sample their
+  // nominal row without the bin arithmetic, then the others; s_nfast counts the first
+  auto file_staged = [&](const CorrTap& e, bool valid) {
+    const CorrTapS t = staged_entry(e);
+    const double margin = INTERP == ROSAR_NEAREST ? (double)tie_err : 0.0;
+    const bool fast = valid && (double)t.uf - cm >= margin && (double)t.uf + cm < 1.0 - margin;
+    const uint64_t fm = __builtin_amdgcn_ballot_w64(fast);
+    const uint64_t sm = __builtin_amdgcn_ballot_w64(valid && !fast);
+    const uint64_t below = (1ull << lane) - 1ull;
+    const int nf = __builtin_popcountll(fm);
+    if (valid) s_tapS[fast ? __builtin_popcountll(fm & below) : nf + __builtin_popcountll(sm & below)] = t;
+    if (lane == 0) s_nfast = nf;
+  };
+
+  // one tap table for all taps, built by wave 0 while the column loads are in flight
+  const bool fused = TABLE && stage_rows > 0 && k <= kCorrChunkS;
+  CorrTap tap0{};
   // (d, psi) of every column, in the dynamic LDS past the tables built from it
   float2* dps = reinterpret_cast<float2*>(reinterpret_cast<char*>(s_dyn) + max(16, stage_rows * EB) * cols);
   if constexpr (TABLE) {
@@ -314,6 +394,7 @@ __global__ __launch_bounds__(kCorrThreads) void sparse_corrected_kernel(
           if (dpsi) pv[j] = dpsi[pn];
         }
       }
+      if (fused && cb == (int)threadIdx.x && (int)threadIdx.x < k) tap0 = tap_geom(o_first, w_first);
 #pragma unroll
       for (int j = 0; j < kColBatch; ++j) {
         const int c = cb + j * kCorrThreads;
@@ -345,15 +426,22 @@ __global__ __launch_bounds__(kCorrThreads) void sparse_corrected_kernel(
     if (series && stage_rows > 0) {
       // rows the pairs can reach: floor(u +- cmax) over the in-window taps, with a margin for
       // the float32 evaluation of the sum
-      const double cm = cmax * (1.0 + 0x1p-10) + 0x1p-16;
+      cm = cmax * (1.0 + 0x1p-10) + 0x1p-16;
       int lo = INT_MAX, hi = INT_MIN;
-      for (int t = threadIdx.x; t < k; t += kCorrThreads) {
-        const int o = t == (int)threadIdx.x ? o_first : offsets[wrow + t];
-        if (o >= -half_w && o < half_w) {
-          double sd, cd, r2;
-          const double u = nominal(o, sd, cd, r2);
-          lo = min(lo, (int)floor(u - cm));
-          hi = max(hi, (int)floor(u + cm));
+      if (fused) {
+        if ((int)threadIdx.x < k && tap0.inwin) {
+          lo = (int)floor(tap0.u64 - cm);
+          hi = (int)floor(tap0.u64 + cm);
+        }
+      } else {
+        for (int t = threadIdx.x; t < k; t += kCorrThreads) {
+          const int o = t == (int)threadIdx.x ? o_first : offsets[wrow + t];
+          if (o >= -half_w && o < half_w) {
+            double sd, cd, r2;
+            const double u = nominal(o, sd, cd, r2);
+            lo = min(lo, (int)floor(u - cm));
+            hi = max(hi, (int)floor(u + cm));
+          }
         }
       }
       for (int off = kWave / 2; off > 0; off >>= 1) {
@@ -378,9 +466,10 @@ __global__ __launch_bounds__(kCorrThreads) void sparse_corrected_kernel(
       staged = nrows <= stage_rows;
     }
     if (staged) {
+      if (fused && wave == 0) file_staged(tap0, (int)threadIdx.x < k);
       // band rows lmin .. lmin + nrows - 1 (LINEAR: and the next) over the columns, turned by
-      // exp(-j psi)
-      // (the (beta d, (k / pi) d) table takes the place of (d, psi), column by column)
+      // exp(-j psi); the (beta d, (k / pi) d) table takes the place of (d, psi), column by
+      // column
       float2* ek = dps;
       const int nload = nrows + (LIN ? 1 : 0);   // at most kStageLoads
       for (int cb = threadIdx.x; cb < cols; cb += kColBatch * kCorrThreads) {
@@ -449,52 +538,27 @@ __global__ __launch_bounds__(kCorrThreads) void sparse_corrected_kernel(
   }
 
   // tap table of taps [c0, c0 + cnt), one per thread of wave 0, from the offsets and weights
-  // loaded ahead; then the next chunk's are requested, to arrive during this chunk's pairs
-  auto build_taps = [&](int c0, int cnt, bool ser, bool stg) {
-    if ((int)threadIdx.x < cnt) {
-      const int o = o_next;
-      const float2 w = w_next;
-      const bool inwin = o >= -half_w && o < half_w;
-      double sd, cd, r2;
-      const double u = nominal(o, sd, cd, r2);
-      const double rn = sqrt(r2);
-      CorrTap e;
-      e.u = split_bin(u);
-      e.r2 = (float)r2;
-      e.rnom = (float)rn;
-      e.sd = (float)sd;
-      e.cd = (float)cd;
-      e.wa = inwin ? (float)sqrt((double)w.x * w.x + (double)w.y * w.y) : 0.f;
-      e.wt = atan2f(w.y, w.x) * (float)(1.0 / kTwoPiD);
-      // derivatives of R(D) = sqrt(S), S = c1 - c2 cos D, at D0 (S' = c2 sin D0, S'' = c2 cos D0);
-      // the quadratic and cubic coefficients are taken per power of e = beta d
-      const double s1 = c2 * sd, s2 = c2 * cd;
-      const double ir = 1.0 / rn, ir3 = ir * ir * ir, ir5 = ir3 * ir * ir;
-      const double ib = 1.0 / g.beta;
-      e.q1 = (float)(0.5 * s1 * ir);
-      e.q2 = (float)(0.5 * (0.5 * s2 * ir - 0.25 * s1 * s1 * ir3) * ib);
-      e.q3 = (float)((-0.5 * s1 * ir - 0.75 * s1 * s2 * ir3 + 0.375 * s1 * s1 * s1 * ir5) / 6.0 * ib * ib);
-      e.o = inwin ? o : 0;
-      if (stg) {
-        // byte offset of (row u.i - lmin, column o + W/2) in the staged rows; a tap outside
-        // the window (zero weight) reads row 0 with li = 0
-        if (!inwin) {
-          e.u.i = lmin;
-          e.u.f = 0.5f;
-        }
-        e.ub = (e.u.i - lmin) * (cols * EB) + (e.o + half_w) * EB;
-      } else if (ser) {
+  // loaded ahead; then the next chunk's (of `chunk` taps) are requested, to arrive during this
+  // chunk's pairs
+  auto build_taps = [&](int c0, int cnt, int chunk, bool ser, bool stg) {
+    if (stg) {
+      if (wave == 0) {
+        CorrTap e{};
+        if ((int)threadIdx.x < cnt) e = tap_geom(o_next, w_next);
+        file_staged(e, (int)threadIdx.x < cnt);
+      }
+    } else if ((int)threadIdx.x < cnt) {
+      CorrTap e = tap_geom(o_next, w_next);
+      if (ser) {
         // byte offset of (row u.i, column o + halo) in the band, the row clamped so that every
         // sampled row stays out of the band when the nominal one is
         e.u.i = min(max(e.u.i, -3), y.l_count + 2);
         e.ub = (int32_t)((uint32_t)e.u.i * (uint32_t)ld_es + (uint32_t)((e.o + y.halo) * ES));
-      } else {
-        e.ub = 0;
       }
       s_tap[threadIdx.x] = e;
     }
-    const int c1 = c0 + kCorrChunk;
-    if ((int)threadIdx.x < min(kCorrChunk, k - c1)) {
+    const int c1 = c0 + chunk;
+    if ((int)threadIdx.x < min(chunk, k - c1)) {
       o_next = offsets[wrow + c1 + threadIdx.x];
       w_next = load_w<WDT>(weights, wrow + c1 + threadIdx.x);
     }
@@ -502,19 +566,19 @@ __global__ __launch_bounds__(kCorrThreads) void sparse_corrected_kernel(
 
   // exp term and accumulation shared by every path: acc += |w| exp(-j 2 pi rev) smp, where rev
   // already holds arg(w) / 2 pi
-  auto accumulate = [&](float2& ac, const CorrTap& tp, float rev, float2 smp) {
-    const float a = tp.wa * cos_rev(rev), b = tp.wa * sin_rev(rev);
+  auto accumulate = [&](float2& ac, float wa, float rev, float2 smp) {
+    const float a = wa * cos_rev(rev), b = wa * sin_rev(rev);
     ac.x = fmaf(smp.x, a, fmaf(smp.y, b, ac.x));
     ac.y = fmaf(smp.y, a, fmaf(-smp.x, b, ac.y));
   };
 
   // NEAREST tie: the plain float64 bin at the angle (o 2 pi) / N + delta_n of the oracle's
   // definition, sampled from the band in global memory
-  auto tie_sample = [&](int p, const CorrTap& tp, int& pn) {
-    pn = acol[p] + tp.o;
+  auto tie_sample = [&](int p, int o, int& pn) {
+    pn = acol[p] + o;
     pn += (pn < 0) ? n : 0;
     pn -= (pn >= n) ? n : 0;
-    const double d = (double)tp.o * g.step + (dphi ? (double)dphi[pn] : 0.0);
+    const double d = (double)o * g.step + (dphi ? (double)dphi[pn] : 0.0);
     int l = (int)floor(plain_bin_half(rr, g.radius, d, g.beta)) - y.l_lo;
     l = min(max(l, -1), y.l_count);
     return buf_load<DT>(rsrc, (uint32_t)(__mul24(l, ld_es) + (pn + y.halo) * ES), 0u);
@@ -526,13 +590,31 @@ __global__ __launch_bounds__(kCorrThreads) void sparse_corrected_kernel(
     const float2* ek = dps;
     const int rowb = cols * EB;
     const int laneb = (i_wave + lane) * EB;
-    for (int c0 = 0; c0 < k; c0 += kCorrChunk) {
-      const int cnt = min(kCorrChunk, k - c0);
-      build_taps(c0, cnt, true, true);
-      __syncthreads();
-      for (int t = 0; t < (wave_live ? cnt : 0); ++t) {
-        const CorrTap tp = s_tap[t];
-        const int base = tp.ub + laneb;
+    auto pairs = [&](int cnt) {
+      const int nfast = __builtin_amdgcn_readfirstlane(wave_live ? s_nfast : 0);
+      // taps whose pairs all sample their nominal row: x = u.f + e s lies in [0, 1)
+      for (int t = 0; t < nfast; ++t) {
+        const CorrTapS tp = s_tapS[t];
+        const char* bt = band + (tp.ub + laneb);
+#pragma unroll
+        for (int p = 0; p < kCorrP; ++p) {
+          const float2 q = ek[i_wave + lane + kWave * p + tp.o + half_w];
+          const float s = fmaf(q.x, fmaf(q.x, tp.q3, tp.q2), tp.q1);
+          const char* at = bt + kWave * EB * p;
+          float2 smp;
+          if constexpr (INTERP == ROSAR_NEAREST) {
+            smp = *reinterpret_cast<const float2*>(at);
+          } else {
+            const float x = fmaf(q.x, s, tp.uf);
+            const float4 v = *reinterpret_cast<const float4*>(at);
+            smp = make_float2(fmaf(x, v.z, v.x), fmaf(x, v.w, v.y));
+          }
+          accumulate(acc[p], tp.wa, fmaf(q.y, s, tp.wt), smp);
+        }
+      }
+      for (int t = nfast; t < (wave_live ? cnt : 0); ++t) {
+        const CorrTapS tp = s_tapS[t];
+        const char* bt = band + (tp.ub + laneb);
         float2 smp[kCorrP];
         float rev[kCorrP];
         int ties = 0;   // NEAREST: bit p set when pixel p's bin sum lies near a rounding boundary
@@ -540,10 +622,10 @@ __global__ __launch_bounds__(kCorrThreads) void sparse_corrected_kernel(
         for (int p = 0; p < kCorrP; ++p) {
           const float2 q = ek[i_wave + lane + kWave * p + tp.o + half_w];
           const float s = fmaf(q.x, fmaf(q.x, tp.q3, tp.q2), tp.q1);
-          const float x = fmaf(q.x, s, tp.u.f);
+          const float x = fmaf(q.x, s, tp.uf);
           rev[p] = fmaf(q.y, s, tp.wt);
           const float fr = __builtin_amdgcn_fractf(x);
-          const char* at = band + (__mul24(floor_to_int(x), rowb) + base) + kWave * EB * p;
+          const char* at = bt + __mul24(floor_to_int(x), rowb) + kWave * EB * p;
           if constexpr (INTERP == ROSAR_NEAREST) {
             smp[p] = *reinterpret_cast<const float2*>(at);
             ties |= (fr < tie_err || fr > 1.f - tie_err) ? (1 << p) : 0;
@@ -559,7 +641,7 @@ __global__ __launch_bounds__(kCorrThreads) void sparse_corrected_kernel(
               if (ties & (1 << p)) {
                 // the tie's sample comes from global memory, not yet turned by exp(-j psi)
                 int pn;
-                smp[p] = tie_sample(p, tp, pn);
+                smp[p] = tie_sample(p, tp.o, pn);
                 float pr = dpsi ? dpsi[pn] * kInv2Pi : 0.f;
                 rev[p] += pr - rintf(pr);
               }
@@ -567,9 +649,21 @@ __global__ __launch_bounds__(kCorrThreads) void sparse_corrected_kernel(
           }
         }
 #pragma unroll
-        for (int p = 0; p < kCorrP; ++p) accumulate(acc[p], tp, rev[p], smp[p]);
+        for (int p = 0; p < kCorrP; ++p) accumulate(acc[p], tp.wa, rev[p], smp[p]);
       }
+    };
+    if (fused) {
       __syncthreads();
+      pairs(k);
+    } else {
+      __syncthreads();
+      for (int c0 = 0; c0 < k; c0 += kCorrChunkS) {
+        const int cnt = min(kCorrChunkS, k - c0);
+        build_taps(c0, cnt, kCorrChunkS, true, true);
+        __syncthreads();
+        pairs(cnt);
+        __syncthreads();
+      }
     }
   } else {
     // gathers from global memory, with the series (SERIES = true) or the exact correction;
@@ -579,7 +673,7 @@ __global__ __launch_bounds__(kCorrThreads) void sparse_corrected_kernel(
       constexpr bool DIRECT = decltype(direct_tag)::value;
       for (int c0 = 0; c0 < k; c0 += kCorrChunk) {
         const int cnt = min(kCorrChunk, k - c0);
-        build_taps(c0, cnt, SERIES, false);
+        build_taps(c0, cnt, kCorrChunk, SERIES, false);
         __syncthreads();
         for (int t = 0; t < (wave_live ? cnt : 0); ++t) {
           const CorrTap tp = s_tap[t];
@@ -636,14 +730,14 @@ __global__ __launch_bounds__(kCorrThreads) void sparse_corrected_kernel(
               smp = buf_load<DT>(rsrc, off0, 0u);
               if (__builtin_expect(fr < err || fr > 1.f - err, 0)) {
                 int pn;
-                smp = tie_sample(p, tp, pn);
+                smp = tie_sample(p, tp.o, pn);
               }
             } else {
               const float2 y0 = buf_load<DT>(rsrc, off0, 0u);
               const float2 y1 = buf_load<DT>(rsrc, off0 + (uint32_t)ld_es, 0u);
               smp = make_float2(fmaf(fr, y1.x - y0.x, y0.x), fmaf(fr, y1.y - y0.y, y0.y));
             }
-            accumulate(acc[p], tp, rev + tp.wt, smp);
+            accumulate(acc[p], tp.wa, rev + tp.wt, smp);
           }
         }
         __syncthreads();
