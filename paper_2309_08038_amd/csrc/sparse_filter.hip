@@ -183,7 +183,7 @@ constexpr int kCorrChunk = 32;                     // taps per chunk, global gat
 constexpr int kCorrChunkS = 64;                    // taps per chunk, staged path
 constexpr int kCorrMaxCols = 4096;                 // largest per-pulse table held in LDS (T + W)
 constexpr int kCorrStageCols = 2048;               // largest T + W whose band rows are staged in LDS
-constexpr int kCorrStageRowsN = 3;                 // NEAREST: band rows staged per workgroup
+constexpr int kCorrStageRowsN = 2;                 // NEAREST: band rows staged per workgroup
 constexpr int kCorrStageRowsL = 2;                 // LINEAR: (row, next row - row) pairs staged
 constexpr int kColBatch = 8;                       // columns per thread whose loads are issued together
 constexpr int kStageLoads = 3;                     // band rows loaded per staged column
@@ -492,7 +492,13 @@ __global__ __launch_bounds__(kCorrThreads) void sparse_corrected_kernel(
           if (c >= cols) continue;
           const float2 dp = dps[c];
           float sp = 0.f, cp = 1.f;
-          if (dpsi) sincosf(dp.y, &sp, &cp);
+          if (dpsi) {
+            // exp(-j psi) on the hardware sine/cosine in revolutions, like the pairs' phase
+            float pr = dp.y * kInv2Pi;
+            pr -= rintf(pr);
+            sp = sin_rev(pr);
+            cp = cos_rev(pr);
+          }
           ek[c] = make_float2(beta * dp.x, kpi * dp.x);
 #pragma unroll
           for (int r = 0; r < kStageLoads; ++r)
