@@ -329,7 +329,7 @@ __device__ __forceinline__ int floor_to_int(float x) {
 // grad_w is reduced per tap across the wave and then across the waves in a fixed order into a
 // per-tile partial; the row partials of grad_dphi / grad_dpsi are one value per pulse.
 template <int DT, int INTERP>
-__global__ __launch_bounds__(kBtThreads) void backward_tile_kernel(
+__device__ __forceinline__ void backward_tile(
     Geo g, View y, int32_t k, int32_t window, int tiles, int nblocks, int stage_rows,
     const int32_t* __restrict__ offsets, const float2* __restrict__ weights,
     const float* __restrict__ dphi, const float* __restrict__ dpsi,
@@ -729,6 +729,29 @@ __global__ __launch_bounds__(kBtThreads) void backward_tile_kernel(
   }
 }
 
+#define ROSAR_BT_ARGS                                                                             \
+  Geo g, View y, int32_t k, int32_t window, int tiles, int nblocks, int stage_rows,              \
+      const int32_t *__restrict__ offsets, const float2 *__restrict__ weights,                   \
+      const float *__restrict__ dphi, const float *__restrict__ dpsi,                            \
+      const float2 *__restrict__ gimg, const char *__restrict__ ydata,                           \
+      float2 *__restrict__ gw_part, float *__restrict__ part_d, float *__restrict__ part_p
+#define ROSAR_BT_PASS g, y, k, window, tiles, nblocks, stage_rows, offsets, weights, dphi, dpsi, gimg, ydata, gw_part, part_d, part_p
+
+// LINEAR: the staged rows (48 KB of LDS) allow three workgroups per CU.
+template <int DT>
+__global__ __launch_bounds__(kBtThreads) void backward_tile_linear_kernel(ROSAR_BT_ARGS) {
+  backward_tile<DT, ROSAR_LINEAR>(ROSAR_BT_PASS);
+}
+// NEAREST stages half as much: four workgroups per CU once the registers fit 128 per lane (the
+// few spills sit in the table set-up and the tie branch, not in the pair loops).
+template <int DT>
+__global__ __launch_bounds__(kBtThreads) __attribute__((amdgpu_waves_per_eu(4))) void backward_tile_nearest_kernel(
+    ROSAR_BT_ARGS) {
+  backward_tile<DT, ROSAR_NEAREST>(ROSAR_BT_PASS);
+}
+#undef ROSAR_BT_ARGS
+#undef ROSAR_BT_PASS
+
 // grad_w[row, t]: the tiles' partials added in order.
 __global__ __launch_bounds__(256) void backward_reduce_w_kernel(int32_t k, int32_t n_range, int32_t tiles,
                                                                 const float2* __restrict__ gw_part,
@@ -794,10 +817,10 @@ hipError_t launch_dt(const SparseArgs& a, const float2* gimg, float2* grad_w, fl
     const int stage = cols <= kBtStageCols ? kBtStageRows : 0;
     const size_t lds = (((size_t)cols * sizeof(float2) + 15) & ~(size_t)15) + (size_t)stage * kBtTile * (lin ? 16 : 8);
     if (lin)
-      backward_tile_kernel<DT, ROSAR_LINEAR><<<nblocks, kBtThreads, lds, s>>>(
+      backward_tile_linear_kernel<DT><<<nblocks, kBtThreads, lds, s>>>(
           a.g, a.y, a.k, a.window, tiles, nblocks, stage, a.offsets, w, a.dphi, a.dpsi, gimg, yd, gwp, pd, pp);
     else
-      backward_tile_kernel<DT, ROSAR_NEAREST><<<nblocks, kBtThreads, lds, s>>>(
+      backward_tile_nearest_kernel<DT><<<nblocks, kBtThreads, lds, s>>>(
           a.g, a.y, a.k, a.window, tiles, nblocks, stage, a.offsets, w, a.dphi, a.dpsi, gimg, yd, gwp, pd, pp);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !grad_w) return e;
