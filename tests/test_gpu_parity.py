@@ -252,6 +252,51 @@ def test_sparse_filter_corrected_wide_window(interp, halo_half):
     assert_image(img, ref, TOL)
 
 
+PATH_CASES = [
+    # name, n, window, rows r0..r1, K, angle-error sigma; the paths these take (checked on the
+    # CPU from the kernels' series bound and the rows each range row's taps reach):
+    ("staged", 1024, 64, 0.6, 1.4, 32, 2e-3),          # rows 1-3 staged in LDS, row 0 exact
+    ("series_global", 2048, 1536, 0.6, 1.4, 32, 1e-3),  # series, tile + W past the staging limit
+    ("exact", 1024, 64, 0.6, 1.4, 32, 0.05),           # large errors: the exact correction
+    ("near_rows", 1024, 256, 0.27, 0.4, 32, 2e-4),      # series, taps spanning 5-6 bin rows
+]
+
+
+@pytest.mark.parametrize("interp", ["nearest", "linear"])
+@pytest.mark.parametrize("case", PATH_CASES, ids=[c[0] for c in PATH_CASES])
+def test_corrected_forward_and_adjoint_paths(case, interp):
+    """Corrected forward and adjoint against the oracle on shapes that take each path of the
+    kernels: staged series rows, series with gathers from global memory (the window too wide to
+    stage), the exact correction (errors beyond the series bound) and rows whose taps span many
+    bin rows.  The image and the three gradients each meet the bars of the small-workload tests."""
+    rs = need_gpu()
+    name, n, win, r0, r1, k, sig = case
+    w = custom_workload(f"path_{name}", 81 + PATH_CASES.index(case), n, 64, 4, r0, r1, k, win)
+    x = synth.make_inputs(w)
+    rng = np.random.default_rng(41)
+    dphi = rng.normal(0, sig, n).astype(np.float32)
+    dpsi = rng.normal(0, 0.3, n).astype(np.float32)
+    yb = oracle.range_compress(x.raw, x.window, 64)[:, x.l_lo:x.l_lo + x.l_count]
+    rc = rs.range_compress(w.geometry, to_dev(x.raw), to_dev(x.window), x.l_lo, x.l_count, halo=win // 2)
+    off, wts = to_dev(x.offsets), to_dev(x.weights.astype(np.complex64))
+    log(f"corrected forward path {name} {interp}")
+    ref = oracle.sparse_filter(yb, x.l_lo, w.geometry, w.grid, x.offsets, x.weights, dphi=dphi.astype(np.float64),
+                               dpsi=dpsi.astype(np.float64), interp=interp)
+    img = rs.sparse_filter(w.geometry, w.grid, rc, off, wts, win, dphi=to_dev(dphi), dpsi=to_dev(dpsi),
+                           interp=interp).cpu().numpy()
+    assert_image(img, ref, TOL, name)
+    log(f"adjoint path {name} {interp}")
+    gimg = synth.random_complex((w.grid.n_range, n), seed=43)
+    gw_r, gd_r, gp_r = oracle.sparse_filter_grad(yb, x.l_lo, w.geometry, w.grid, x.offsets, x.weights,
+                                                 gimg.astype(np.complex128), dphi.astype(np.float64),
+                                                 dpsi.astype(np.float64), interp)
+    gw, gd, gp = rs.sparse_filter_backward(w.geometry, w.grid, rc, off, wts, win, to_dev(gimg), to_dev(dphi),
+                                           to_dev(dpsi), interp)
+    assert rel_l2(gw.cpu().numpy(), gw_r) <= 1e-3, name
+    assert rel_l2(gd.cpu().numpy(), gd_r) <= 1e-3, name
+    assert rel_l2(gp.cpu().numpy(), gp_r) <= 1e-3, name
+
+
 def test_sparse_filter_rotation_invariance_bitwise():
     rs = need_gpu()
     w, x = inputs("small")
