@@ -278,6 +278,7 @@ constexpr int kBtMaxCols = 4096;               // largest T + W whose gradient c
 constexpr int kBtStageCols = 2048;             // largest T + W whose band rows are staged too
 constexpr int kBtStageRows = 2;                // band rows (LINEAR: (row, next - row) pairs) staged
 constexpr int kBtStageLoads = kBtStageRows + 1;
+constexpr int kGBatch = 8;                     // gradient columns per thread whose loads are issued together
 
 // Nominal geometry and weight of one tap, 64 bytes.
 struct alignas(16) BtTap {
@@ -385,11 +386,63 @@ __device__ __forceinline__ void backward_tile(
     dj[j] = dphi ? dphi[pc] : 0.f;
     psj[j] = dpsi ? dpsi[pc] : 0.f;
   }
-  // gradient columns: pixel p0 - W/2 + c, wrapped
-  for (int c = threadIdx.x; c < cols; c += kBtThreads) {
-    int a = p0 - half_w + c;
-    if (a < 0 || a >= n) a = ((a % n) + n) % n;
-    s_g[c] = grow[a];
+  // the float64 geometry of one tap (ub left zero); its nominal bin in *u64
+  auto nominal = [&](int o, double& sd, double& cd, double& r2) {
+    sincos(o * g.step, &sd, &cd);
+    r2 = c1 - c2 * cd;
+    return g.beta * sqrt(r2) + u_shift;
+  };
+  auto make_tap = [&](int o, float2 w, int idx, bool& inwin, double& u64) {
+    BtTap e{};
+    inwin = o >= -half_w && o < half_w;
+    double sd, cd, r2;
+    u64 = nominal(o, sd, cd, r2);
+    const double rn = sqrt(r2);
+    e.u = split_bin(u64);
+    e.r2 = (float)r2;
+    e.rnom = (float)rn;
+    e.sd = (float)sd;
+    e.cd = (float)cd;
+    const double s1 = c2 * sd, s2 = c2 * cd;
+    const double ir = 1.0 / rn, ir3 = ir * ir * ir, ir5 = ir3 * ir * ir;
+    const double ib = 1.0 / g.beta;
+    const double q1 = 0.5 * s1 * ir;
+    const double q2 = 0.5 * (0.5 * s2 * ir - 0.25 * s1 * s1 * ir3);
+    const double q3 = (-0.5 * s1 * ir - 0.75 * s1 * s2 * ir3 + 0.375 * s1 * s1 * s1 * ir5) / 6.0;
+    e.q1 = (float)q1;
+    e.q2 = (float)(q2 * ib);
+    e.q3 = (float)(q3 * ib * ib);
+    e.p2 = (float)(2.0 * q2 * ib);
+    e.p3 = (float)(3.0 * q3 * ib * ib);
+    e.wr = w.x;
+    e.wi = w.y;
+    e.o = inwin ? o : 0;
+    e.idx = idx;
+    return e;
+  };
+  // with at most one chunk of taps, wave 0 builds the table once, while the loads are in flight
+  // (parked in its LDS slot until the chunk loop files it)
+  const bool fused = k <= kBtChunk;
+  bool inwin0 = false;
+  double u0 = 0.0;
+  if (fused && wave == 0 && lane < k) s_tap[lane] = make_tap(o_next, w_next, lane, inwin0, u0);
+  // gradient columns: pixel p0 - W/2 + c, wrapped; the loads of a thread's columns issued together
+  for (int cb = threadIdx.x; cb < cols; cb += kGBatch * kBtThreads) {
+    float2 gv[kGBatch];
+#pragma unroll
+    for (int j = 0; j < kGBatch; ++j) {
+      const int c = cb + j * kBtThreads;
+      if (c < cols) {
+        int a = p0 - half_w + c;
+        if (a < 0 || a >= n) a = ((a % n) + n) % n;
+        gv[j] = grow[a];
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < kGBatch; ++j) {
+      const int c = cb + j * kBtThreads;
+      if (c < cols) s_g[c] = gv[j];
+    }
   }
   float dmax = 0.f;
 #pragma unroll
@@ -419,15 +472,16 @@ __device__ __forceinline__ void backward_tile(
     cm = cmax * (1.0 + 0x1p-10) + 0x1p-16;
     tie_err = (float)(0x1p-18 + cmax * 0x1p-12);
   }
-  auto nominal = [&](int o, double& sd, double& cd, double& r2) {
-    sincos(o * g.step, &sd, &cd);
-    r2 = c1 - c2 * cd;
-    return g.beta * sqrt(r2) + u_shift;
-  };
   if (series && stage_rows > 0) {
     // rows the pairs can reach: floor(u +- cm) over the in-window taps
     int lo = INT_MAX, hi = INT_MIN;
-    for (int t = threadIdx.x; t < k; t += kBtThreads) {
+    if (fused) {
+      if (wave == 0 && lane < k && inwin0) {
+        lo = (int)floor(u0 - cm);
+        hi = (int)floor(u0 + cm);
+      }
+    } else {
+     for (int t = threadIdx.x; t < k; t += kBtThreads) {
       const int o = t == (int)threadIdx.x && t < kBtChunk ? o_next : offsets[wrow + t];
       if (o >= -half_w && o < half_w) {
         double sd, cd, r2;
@@ -435,6 +489,7 @@ __device__ __forceinline__ void backward_tile(
         lo = min(lo, (int)floor(u - cm));
         hi = max(hi, (int)floor(u + cm));
       }
+     }
     }
     for (int off = kWave / 2; off > 0; off >>= 1) {
       lo = min(lo, __shfl_xor(lo, off));
@@ -548,32 +603,13 @@ __device__ __forceinline__ void backward_tile(
       BtTap e{};
       bool inwin = false;
       if (valid) {
-        const int o = o_next;
-        const float2 w = w_next;
-        inwin = o >= -half_w && o < half_w;
-        double sd, cd, r2;
-        const double u = nominal(o, sd, cd, r2);
-        const double rn = sqrt(r2);
-        e.u = split_bin(u);
-        e.r2 = (float)r2;
-        e.rnom = (float)rn;
-        e.sd = (float)sd;
-        e.cd = (float)cd;
-        const double s1 = c2 * sd, s2 = c2 * cd;
-        const double ir = 1.0 / rn, ir3 = ir * ir * ir, ir5 = ir3 * ir * ir;
-        const double ib = 1.0 / g.beta;
-        const double q1 = 0.5 * s1 * ir;
-        const double q2 = 0.5 * (0.5 * s2 * ir - 0.25 * s1 * s1 * ir3);
-        const double q3 = (-0.5 * s1 * ir - 0.75 * s1 * s2 * ir3 + 0.375 * s1 * s1 * s1 * ir5) / 6.0;
-        e.q1 = (float)q1;
-        e.q2 = (float)(q2 * ib);
-        e.q3 = (float)(q3 * ib * ib);
-        e.p2 = (float)(2.0 * q2 * ib);
-        e.p3 = (float)(3.0 * q3 * ib * ib);
-        e.wr = w.x;
-        e.wi = w.y;
-        e.o = inwin ? o : 0;
-        e.idx = lane;
+        double u;
+        if (fused) {
+          e = s_tap[lane];   // each lane reads its own slot before any lane files into the table
+          inwin = inwin0;
+        } else {
+          e = make_tap(o_next, w_next, lane, inwin, u);
+        }
         if (staged) {
           e.ub = (e.u.i - lmin) * rowb;
         } else if (series) {
