@@ -7,21 +7,24 @@
 // (Chain rule through eq. 2 and the eq.-40 bin position; dY/du is the LINEAR slope, zero for
 // NEAREST.)
 //
-// Gather formulation, deterministic without atomics: a workgroup owns one range row and each
-// thread owns pulses n (so the angle/phase terms of n stay in registers and the per-row
-// contribution to grad_dphi[n] accumulates in that thread).  For each tap the thread visits
-// pixel a = n - o_t, recomputes the sample and its derivative (indices are never stored), and
-// feeds conj(g) s into a per-tap partial reduced across the wavefront and then across the
-// waves in a fixed order.  The taps' nominal geometry (float64 bin of R_nom, R_nom, sin/cos of
-// D0 = 2 pi o / N) and weights sit in an LDS table; per (pulse, tap) only the angle-error
-// correction is evaluated in float32.  As in the corrected forward it is either the cubic
-// Taylor polynomial of R(D0 + d) - R(D0) in d (and its derivative for dR^/dd), taken when the
-// workgroup's fourth-derivative remainder bound at the rotation's largest |d| is below 1e-6 rad
-// of carrier phase and 2^-20 bins, or otherwise the exact form without cancellation:
-//   R^2 - R_nom^2 = 4 R r sin(D0 + d/2) sin(d/2),   R^ - R_nom = (R^2 - R_nom^2)/(R^ + R_nom),
-// with the bin formed in float64 and the samples read through buffer loads (out-of-band rows
-// read zero).  Row partials of grad_dphi/grad_dpsi go to the workspace; a two-stage reduction
-// sums them over rows in a fixed order (groups of rows, then the groups).
+// Gather formulation, deterministic without atomics: each thread owns pulses n (so the
+// angle/phase terms of n stay in registers and the row's contribution to grad_dphi[n]
+// accumulates in that thread).  For each tap the thread visits pixel a = n - o_t, recomputes the
+// sample and its derivative (indices are never stored), and feeds conj(g) s into a per-tap
+// partial reduced across the wavefront and then across the waves in a fixed order.  The taps'
+// nominal geometry (float64 bin of R_nom, R_nom, sin/cos of D0 = 2 pi o / N) and weights sit in
+// an LDS table; per (pulse, tap) only the angle-error correction is evaluated in float32.  As in
+// the corrected forward it is either the cubic Taylor polynomial of R(D0 + d) - R(D0) in d (and
+// its derivative for dR^/dd), taken when the fourth-derivative remainder bound at the largest
+// |d| is below 1e-6 rad of carrier phase and 2^-20 bins, or otherwise the exact form without
+// cancellation:
+//   R^2 - R_nom^2 = 4 R r sin(D0 + d/2) sin(d/2),   R^ - R_nom = (R^2 - R_nom^2)/(R^ + R_nom).
+// The main kernel works on tiles of one range row and kBtTile pulses, with the gradient columns
+// and, on the series path, the band rows in LDS (backward_tile); windows too wide for that keep
+// one workgroup per row reading the band through buffer loads (backward_row_kernel, out-of-band
+// rows read zero).  Row partials of grad_dphi/grad_dpsi go to the workspace and a two-stage
+// reduction sums them over rows in a fixed order (groups of rows, then the groups); the tiles'
+// grad_w partials are added in order by their own kernel.
 #include <climits>
 #include <type_traits>
 
