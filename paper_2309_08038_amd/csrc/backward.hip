@@ -585,18 +585,21 @@ __device__ __forceinline__ void backward_tile(
   // NEAREST tie: the plain float64 bin at the angle (o 2 pi) / N + delta_n of the oracle's
   // definition, sampled from the band in global memory (not turned, scaled)
   auto tie_sample = [&](int j, const BtTap& tp) {
-    const int pc = min(p0 + i_wave + lane + kWave * j, n - 1);
+    if (p0 + i_wave + lane + kWave * j >= n) return make_float2(0.f, 0.f);   // a pulse past N
+    const int pc = p0 + i_wave + lane + kWave * j;
     const double d = (double)tp.o * g.step + (double)dj[j];
     int l = (int)floor(plain_bin_half(rr, g.radius, d, g.beta)) - y.l_lo;
     l = min(max(l, -1), y.l_count);
     const float2 v = buf_load<DT>(rsrc, (uint32_t)(__mul24(l, ld_es) + (pc + y.halo) * ES), 0u);
     return make_float2(v.x * isc, v.y * isc);
   };
-  // gradient sample of pulse j's pixel n - o
+  // gradient sample of pulse j's pixel n - o; pulses past N add nothing (on the staged path
+  // their band columns are zero already, so their g needs no mask there)
   auto grad_at = [&](int j, int o) {
     const float2 v = s_g[i_wave + lane + kWave * j - o + half_w];
-    return p0 + i_wave + lane + kWave * j < n ? v : make_float2(0.f, 0.f);   // pulses past N add nothing
+    return p0 + i_wave + lane + kWave * j < n ? v : make_float2(0.f, 0.f);
   };
+  auto grad_at_staged = [&](int j, int o) { return s_g[i_wave + lane + kWave * j - o + half_w]; };
 
   for (int c0 = 0; c0 < k; c0 += kBtChunk) {
     const int cnt = min(kBtChunk, k - c0);
@@ -664,7 +667,7 @@ __device__ __forceinline__ void backward_tile(
           } else {
             Y = *reinterpret_cast<const float2*>(at);
           }
-          pair_tail(j, tp, grad_at(j, tp.o), kdj[j] * s, dr, Y, dY, gw);
+          pair_tail(j, tp, grad_at_staged(j, tp.o), kdj[j] * s, dr, Y, dY, gw);
         }
         gw = make_float2(wave_sum_to_63(gw.x), wave_sum_to_63(gw.y));
         if (lane == kWave - 1) s_gwc[wave][tp.idx] = gw;
@@ -694,7 +697,7 @@ __device__ __forceinline__ void backward_tile(
               rev += prj[j];
             }
           }
-          pair_tail(j, tp, grad_at(j, tp.o), rev, dr, Y, dY, gw);
+          pair_tail(j, tp, grad_at_staged(j, tp.o), rev, dr, Y, dY, gw);
         }
         gw = make_float2(wave_sum_to_63(gw.x), wave_sum_to_63(gw.y));
         if (lane == kWave - 1) s_gwc[wave][tp.idx] = gw;
