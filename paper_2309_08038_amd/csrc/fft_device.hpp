@@ -194,6 +194,71 @@ __device__ __forceinline__ void fft_rest(float2* buf, const float2* tw, int wave
 }
 
 
+// Two band elements of consecutive pulses (idx even) as one 16-byte (complex64) or 8-byte
+// (16-bit pairs) store.
+template <int DT>
+__device__ __forceinline__ void store_c2(void* base, int64_t idx, float2 v0, float2 v1) {
+  if constexpr (DT == 0) {
+    reinterpret_cast<float4*>(base)[idx >> 1] = make_float4(v0.x, v0.y, v1.x, v1.y);
+  } else if constexpr (DT == 1) {
+    const __half2 h0 = __floats2half2_rn(v0.x, v0.y), h1 = __floats2half2_rn(v1.x, v1.y);
+    uint2 u;
+    u.x = *reinterpret_cast<const uint32_t*>(&h0);
+    u.y = *reinterpret_cast<const uint32_t*>(&h1);
+    reinterpret_cast<uint2*>(base)[idx >> 1] = u;
+  } else {
+    uint2 u;
+    u.x = f32_to_bf16_rne(v0.x) | (f32_to_bf16_rne(v0.y) << 16);
+    u.y = f32_to_bf16_rne(v1.x) | (f32_to_bf16_rne(v1.y) << 16);
+    reinterpret_cast<uint2*>(base)[idx >> 1] = u;
+  }
+}
+
+// Transposed band store for even N, halo and row pitch (and an aligned band): each thread owns
+// pulses (2h, 2h + 1) of the block and writes them as one store per row, so a wave covers
+// 2 * kWave / PW rows with PW consecutive pulses each.  The LDS reads of two sweeps are issued
+// before their stores.  Pulse pairs never straddle N or a halo boundary, since all three are even.
+template <int L, int PPW, int DT, int NW>
+__device__ __forceinline__ void store_band_pairs(const RcArgs& a, int n0, const float2* buf) {
+  constexpr int PW = NW * PPW, LP = row_pitch(L), NT = NW * kWave;
+  constexpr int HP = PW / 2;          // threads per row segment
+  constexpr int RS = NT / HP;         // rows per sweep of the workgroup
+  constexpr int U = 2;                // sweeps whose reads go out together
+  static_assert(PW % 2 == 0, "pulse pairs");
+  const int tid = threadIdx.x;
+  const int pp = 2 * (tid % HP), r0 = tid / HP;
+  const int n = n0 + pp;
+  if (n >= a.n) return;
+  const bool h_lo = n < a.halo, h_hi = n >= a.n - a.halo;
+  const float2* s0 = buf + pp * LP;
+  const float2* s1 = s0 + LP;
+  for (int base = r0; base < a.l_count; base += RS * U) {
+    float2 v0[U], v1[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int lr = base + u * RS;
+      const bool in = lr < a.l_count;
+      v0[u] = in ? s0[lds_idx(a.l_lo + lr)] : make_float2(0.f, 0.f);
+      v1[u] = in ? s1[lds_idx(a.l_lo + lr)] : make_float2(0.f, 0.f);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int lr = base + u * RS;
+      if (lr < a.l_count) {
+        float2 w0 = v0[u], w1 = v1[u];
+        w0.x *= a.scale;
+        w0.y *= a.scale;
+        w1.x *= a.scale;
+        w1.y *= a.scale;
+        const int64_t at = (int64_t)lr * a.ld + n + a.halo;
+        store_c2<DT>(a.out, at, w0, w1);
+        if (h_lo) store_c2<DT>(a.out, at + a.n, w0, w1);
+        if (h_hi) store_c2<DT>(a.out, at - a.n, w0, w1);
+      }
+    }
+  }
+}
+
 // LDS float2 needed by rc_block<L, PPW, NW>: twiddle table, NW*PPW padded pulse rows and the
 // window (L floats).
 constexpr int rc_lds_elems(int l, int ppw, int nw) { return l + nw * ppw * row_pitch(l) + l / 2; }
@@ -214,7 +279,18 @@ __device__ __forceinline__ void rc_block(const RcArgs& a, int n0, float2* lds) {
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
   using S0 = PassShape<L, 0>;
   float2 v[PPW][S0::BPL][S0::R];
-  pass_load<L, PPW, 0>(v, buf, wave, lane, a, n0);
+  if (S0::NB % kWave == 0 && a.m >= L && n0 + (wave + 1) * PPW <= a.n) {
+    // whole pulses, every lane in range: plain loads at constant offsets, no per-element guard
+    const float2* src = a.raw + (int64_t)(n0 + wave * PPW) * a.m + lane;
+#pragma unroll
+    for (int p = 0; p < PPW; ++p)
+#pragma unroll
+      for (int b = 0; b < S0::BPL; ++b)
+#pragma unroll
+        for (int r = 0; r < S0::R; ++r) v[p][b][r] = src[(int64_t)p * a.m + kWave * b + r * S0::NB];
+  } else {
+    pass_load<L, PPW, 0>(v, buf, wave, lane, a, n0);
+  }
   for (int t = tid; t < L; t += NT) {
     float s, c;
     sincospif(-2.0f * (float)t / (float)L, &s, &c);
@@ -227,6 +303,10 @@ __device__ __forceinline__ void rc_block(const RcArgs& a, int n0, float2* lds) {
   fft_rest<L, PPW, 1>(buf, tw, wave, lane, a);
   __syncthreads();
 
+  if (((a.ld | a.halo | a.n) & 1) == 0 && ((uintptr_t)a.out & (DT == 0 ? 15 : 7)) == 0) {
+    store_band_pairs<L, PPW, DT, NW>(a, n0, buf);
+    return;
+  }
   // transposed store of the band: PW consecutive pulses form one contiguous row segment
   const int total = a.l_count * PW;
   for (int i = tid; i < total; i += NT) {

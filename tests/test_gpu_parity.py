@@ -57,18 +57,21 @@ def test_range_compress_small(dtype):
                                    (800, 225, 225), (37, 90, 100), (40, 3000, 4096), (20, 7000, 7200)])
 def test_range_compress_shapes(n, m, l):
     """Zero padding (M < L), the smallest and largest FFT, ragged pulse counts, and lengths of
-    the mixed-radix path."""
+    the mixed-radix path; odd and even halos."""
     rs = need_gpu()
     log(f"range_compress N={n} M={m} L={l}")
     g = synth.Geometry(n, m, l, 0.25, 77e9, 4e9 * 1e7 / m, 1e7)
     raw = synth.random_complex((n, m), seed=n + m)
     win = synth.hann(m)
     l_lo, l_cnt = 3, l - 7
-    rc = rs.range_compress(g, to_dev(raw), to_dev(win), l_lo, l_cnt, halo=5)
-    torch.cuda.synchronize()
-    got = rc.pulses(n).cpu().numpy().T
     ref = oracle.range_compress(raw, win, l)[:, l_lo:l_lo + l_cnt]
-    assert rel_l2(got, ref) <= 1e-5
+    # an odd halo takes the element-wise band store; an even one (with even N) the paired store
+    for halo in (5, 6):
+        rc = rs.range_compress(g, to_dev(raw), to_dev(win), l_lo, l_cnt, halo=halo)
+        torch.cuda.synchronize()
+        assert rel_l2(rc.pulses(n).cpu().numpy().T, ref) <= 1e-5, halo
+        d = rc.data.cpu()
+        assert torch.equal(d[:, :halo], d[:, n:n + halo]) and torch.equal(d[:, n + halo:], d[:, halo:2 * halo])
     rc2 = rs.range_compress(g, to_dev(raw), None, 0, l, halo=0)
     torch.cuda.synchronize()
     assert rel_l2(rc2.pulses(n).cpu().numpy().T, oracle.range_compress(raw, None, l)) <= 1e-5
