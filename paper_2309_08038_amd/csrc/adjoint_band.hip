@@ -84,6 +84,7 @@ __global__ __launch_bounds__(kAdjThreads) void adjoint_band_kernel(int n, int n_
 constexpr int kAdjMaxRows = 8;            // staged gradient rows per batch
 constexpr size_t kAdjLdsBudget = 40 * 1024;
 constexpr int kAdjWaves = kAdjThreads / kWave;
+constexpr int kAdjU = 4;                  // taps whose stage reads are issued together
 constexpr int kAdjTilesPer = 1;           // pulse tiles of one band row per workgroup (4: 190 us, too few workgroups)
 
 __host__ __device__ constexpr int rows_words(int n_range) { return ((n_range + 31) / 32 + 3) & ~3; }
@@ -194,17 +195,37 @@ __global__ __launch_bounds__(kAdjThreads) void adjoint_band_staged_kernel(int n,
         for (int i = tid; i < width; i += kAdjThreads) stage[slot * width + i] = grow[(n0 - half_w + i + n) % n];
       }
       __syncthreads();
-      for (int e = 0; e < ntaps; ++e) {
+      // Taps in groups of kAdjU: a group's samples are requested before its multiply-adds.
+      // Pulses past N accumulate values that are never stored; their stage reads stay inside
+      // the slot (t.x + tid + p * kAdjThreads < (slot + 1) * width for any offset in the window).
+      int e = 0;
+      for (; e + kAdjU <= ntaps; e += kAdjU) {
+        int4 t[kAdjU];
+        float2 gv[kAdjU][kAdjP];
+#pragma unroll
+        for (int u = 0; u < kAdjU; ++u) {
+          t[u] = taps[e + u];
+#pragma unroll
+          for (int p = 0; p < kAdjP; ++p) gv[u][p] = stage[t[u].x + tid + p * kAdjThreads];
+        }
+#pragma unroll
+        for (int u = 0; u < kAdjU; ++u) {
+          const float cx = __int_as_float(t[u].y), cy = __int_as_float(t[u].z);
+#pragma unroll
+          for (int p = 0; p < kAdjP; ++p) {
+            acc[tt][p].x = fmaf(cx, gv[u][p].x, fmaf(-cy, gv[u][p].y, acc[tt][p].x));
+            acc[tt][p].y = fmaf(cx, gv[u][p].y, fmaf(cy, gv[u][p].x, acc[tt][p].y));
+          }
+        }
+      }
+      for (; e < ntaps; ++e) {
         const int4 t = taps[e];
         const float cx = __int_as_float(t.y), cy = __int_as_float(t.z);
 #pragma unroll
         for (int p = 0; p < kAdjP; ++p) {
-          const int np = n0 + tid + p * kAdjThreads;
-          if (np < n) {
-            const float2 gv = stage[t.x + tid + p * kAdjThreads];
-            acc[tt][p].x = fmaf(cx, gv.x, fmaf(-cy, gv.y, acc[tt][p].x));
-            acc[tt][p].y = fmaf(cx, gv.y, fmaf(cy, gv.x, acc[tt][p].y));
-          }
+          const float2 gv = stage[t.x + tid + p * kAdjThreads];
+          acc[tt][p].x = fmaf(cx, gv.x, fmaf(-cy, gv.y, acc[tt][p].x));
+          acc[tt][p].y = fmaf(cx, gv.y, fmaf(cy, gv.x, acc[tt][p].y));
         }
       }
       __syncthreads();   // the next tile or batch overwrites the stage (and the taps and list)
