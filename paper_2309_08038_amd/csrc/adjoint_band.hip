@@ -7,8 +7,9 @@
 // Per band row this is a gather: only the range rows whose taps reach bin row l contribute, and a
 // range row's taps reach at most 32 consecutive bin rows.  The tap lists (float64 bins, the same
 // expression as the forward filter's tables) are written to the caller's workspace first; then
-// one workgroup per (band row, pulse tile) marks the contributing range rows in an LDS bitmask
-// and walks them in increasing order, so the sum order is fixed and results are reproducible.
+// one workgroup per (band row, pulse tile) finds the contributing range rows and walks them in
+// increasing order (the staged form lists them in LDS with an ordered ballot, the direct form
+// marks them in an LDS bitmask), so the sum order is fixed and results are reproducible.
 // The staged form copies, batch by batch, the gradient rows of the contributing range rows over
 // the columns the tile's taps reach ([n0 - W/2, n0 + T + W/2], modulo N) into LDS; the direct
 // form (kept for windows too wide for one staged row) reads them from global memory.  Both add
@@ -85,44 +86,64 @@ constexpr int kAdjMaxRows = 8;            // staged gradient rows per batch
 constexpr size_t kAdjLdsBudget = 40 * 1024;
 constexpr int kAdjWaves = kAdjThreads / kWave;
 constexpr int kAdjU = 4;                  // taps whose stage reads are issued together
+constexpr int kAdjRowsPer = 4;            // row headers per thread requested together
 constexpr int kAdjTilesPer = 1;           // pulse tiles of one band row per workgroup (4: 190 us, too few workgroups)
 
 __host__ __device__ constexpr int rows_words(int n_range) { return ((n_range + 31) / 32 + 3) & ~3; }
+__host__ __device__ constexpr int list_words(int n_range) { return (n_range + 3) & ~3; }
 
-// Staged form.  Dynamic LDS: the row mask (rows_words words), then cap * ne compacted taps
-// {LDS offset of the tap's first sample, coef.x, coef.y, 0}, then cap staged gradient rows.
+// Staged form.  Dynamic LDS: the list of contributing rows (list_words words, each
+// (row << 5) | bin offset, in increasing row order), then cap * ne compacted taps {LDS offset of
+// the tap's first sample, coef.x, coef.y, 0}, then cap staged gradient rows.
 __global__ __launch_bounds__(kAdjThreads) void adjoint_band_staged_kernel(int n, int n_range, int tiles, int groups,
                                                                           int half_w,
                                                                           int cap, int ne, const char* __restrict__ tabs,
                                                                           int row_bytes,
                                                                           const float2* __restrict__ grad_image,
                                                                           float2* __restrict__ grad_band) {
-  extern __shared__ uint32_t s_rows[];
-  __shared__ int s_list[kAdjMaxRows];
-  __shared__ int s_rel[kAdjMaxRows];
+  extern __shared__ int4 s_dyn[];   // int4: the tap table's 16-byte LDS reads need 16-byte alignment
   __shared__ int s_wcnt[kAdjWaves];
-  __shared__ int s_cnt, s_cur_w, s_ntaps;
-  __shared__ unsigned s_cur_m;
+  __shared__ int s_ntaps;
   const int l = blockIdx.x / groups;
   const int tile0 = (blockIdx.x % groups) * kAdjTilesPer;   // this workgroup's tiles: tile0 + [0, kAdjTilesPer)
   const int tid = threadIdx.x;
   const int lane = tid & (kWave - 1);
   const int wave = tid / kWave;
-  const int words = (n_range + 31) / 32;
   const int width = kAdjTile + 2 * half_w + 1;   // staged columns of a tile: n0 - half_w + [0, width)
-  int4* taps = reinterpret_cast<int4*>(s_rows + rows_words(n_range));
+  int* rows = reinterpret_cast<int*>(s_dyn);
+  int4* taps = s_dyn + list_words(n_range) / 4;
   float2* stage = reinterpret_cast<float2*>(taps + cap * ne);
-  for (int i = tid; i < words; i += kAdjThreads) s_rows[i] = 0u;
-  __syncthreads();
-  for (int r = tid; r < n_range; r += kAdjThreads) {
-    const int4 h = *reinterpret_cast<const int4*>(tabs + (size_t)r * row_bytes);
-    const int rel = l - h.x;
-    if (rel >= 0 && rel < 32 && ((unsigned)h.y >> rel) & 1u) atomicOr(&s_rows[r >> 5], 1u << (r & 31));
-  }
-  __syncthreads();
-  if (tid == 0) {
-    s_cur_w = 0;
-    s_cur_m = s_rows[0];
+
+  // The contributing range rows (a tap on band row l), listed in increasing order: the headers
+  // of kAdjRowsPer * kAdjThreads rows are requested together, then a ballot per wave and
+  // chunk, the waves' counts added in wave order.  Every thread tracks the same running count.
+  int nrows = 0;
+  for (int base = 0; base < n_range; base += kAdjRowsPer * kAdjThreads) {
+    int4 h[kAdjRowsPer];
+#pragma unroll
+    for (int q = 0; q < kAdjRowsPer; ++q) {
+      const int r = base + q * kAdjThreads + tid;
+      h[q] = r < n_range ? *reinterpret_cast<const int4*>(tabs + (size_t)r * row_bytes) : make_int4(0, 0, 0, 0);
+    }
+#pragma unroll
+    for (int q = 0; q < kAdjRowsPer; ++q) {
+      const int r = base + q * kAdjThreads + tid;
+      const int rel = l - h[q].x;
+      const bool match = r < n_range && rel >= 0 && rel < 32 && (((unsigned)h[q].y >> rel) & 1u);
+      const uint64_t bal = __ballot(match);
+      if (lane == 0) s_wcnt[wave] = __popcll(bal);
+      __syncthreads();
+      int off = nrows, tot = 0;
+#pragma unroll
+      for (int w2 = 0; w2 < kAdjWaves; ++w2) {
+        const int c = s_wcnt[w2];
+        off += w2 < wave ? c : 0;
+        tot += c;
+      }
+      if (match) rows[off + __popcll(bal & ((1ull << lane) - 1ull))] = (r << 5) | rel;
+      nrows += tot;
+      __syncthreads();   // s_wcnt is rewritten by the next chunk
+    }
   }
 
   float2 acc[kAdjTilesPer][kAdjP];
@@ -130,40 +151,25 @@ __global__ __launch_bounds__(kAdjThreads) void adjoint_band_staged_kernel(int n,
   for (int tt = 0; tt < kAdjTilesPer; ++tt)
 #pragma unroll
     for (int p = 0; p < kAdjP; ++p) acc[tt][p] = make_float2(0.f, 0.f);
-  while (true) {
-    // the next batch of contributing rows, in increasing order (thread 0 advances the cursor)
-    if (tid == 0) {
-      int cnt = 0, w_ = s_cur_w;
-      unsigned m_ = s_cur_m;
-      while (cnt < cap) {
-        while (m_ == 0u && w_ + 1 < words) m_ = s_rows[++w_];
-        if (m_ == 0u) break;
-        const int r = w_ * 32 + __builtin_ctz(m_);
-        s_list[cnt] = r;
-        s_rel[cnt] = l - reinterpret_cast<const int4*>(tabs + (size_t)r * row_bytes)->x;
-        ++cnt;
-        m_ &= m_ - 1u;
-      }
-      s_cnt = cnt;
-      s_cur_w = w_;
-      s_cur_m = m_;
-      s_ntaps = 0;
-    }
+  for (int b0 = 0; b0 < nrows; b0 += cap) {
+    // the batch rows[b0, b0 + cnt)
+    const int cnt = min(cap, nrows - b0);
+    if (tid == 0) s_ntaps = 0;
     __syncthreads();
-    const int cnt = s_cnt;
-    if (cnt == 0) break;
     // compact the batch's taps on band row l, in (row, entry) order: a ballot per wave, the
     // waves' counts added in wave order
     const int total = cnt * ne;
     for (int base = 0; base < total; base += kAdjThreads) {
       const int idx = base + tid;
       int4 t = make_int4(0, -1, 0, 0);
-      int slot = 0;
+      int slot = 0, rel = -2;
       if (idx < total) {
         slot = idx / ne;
-        t = reinterpret_cast<const int4*>(tabs + (size_t)s_list[slot] * row_bytes)[1 + idx - slot * ne];
+        const int re = rows[b0 + slot];
+        rel = re & 31;
+        t = reinterpret_cast<const int4*>(tabs + (size_t)(re >> 5) * row_bytes)[1 + idx - slot * ne];
       }
-      const bool match = idx < total && t.y == s_rel[slot];
+      const bool match = idx < total && t.y == rel;
       const uint64_t bal = __ballot(match);
       const int before = __popcll(bal & ((1ull << lane) - 1ull));
       if (lane == 0) s_wcnt[wave] = __popcll(bal);
@@ -191,7 +197,7 @@ __global__ __launch_bounds__(kAdjThreads) void adjoint_band_staged_kernel(int n,
       if (tile >= tiles) break;   // block-uniform
       const int n0 = tile * kAdjTile;
       for (int slot = 0; slot < cnt; ++slot) {
-        const float2* grow = grad_image + (size_t)s_list[slot] * n;
+        const float2* grow = grad_image + (size_t)(rows[b0 + slot] >> 5) * n;
         for (int i = tid; i < width; i += kAdjThreads) stage[slot * width + i] = grow[(n0 - half_w + i + n) % n];
       }
       __syncthreads();
@@ -258,10 +264,11 @@ hipError_t launch_adjoint_band(const SparseArgs& a, const FcLayout& L, const flo
   const int half_w = a.window / 2;
   const size_t mask_bytes = (size_t)rows_words(a.g.n_range) * sizeof(uint32_t);
   const size_t per_row = (size_t)(kAdjTile + 2 * half_w + 1) * sizeof(float2) + (size_t)L.ne * sizeof(int4);
-  const int cap = mask_bytes >= kAdjLdsBudget ? 0 : (int)std::min<size_t>(kAdjMaxRows, (kAdjLdsBudget - mask_bytes) / per_row);
+  const size_t list_bytes = (size_t)list_words(a.g.n_range) * sizeof(int);
+  const int cap = list_bytes >= kAdjLdsBudget ? 0 : (int)std::min<size_t>(kAdjMaxRows, (kAdjLdsBudget - list_bytes) / per_row);
   if (cap >= 1) {
     const int groups = (tiles + kAdjTilesPer - 1) / kAdjTilesPer;
-    adjoint_band_staged_kernel<<<a.y.l_count * groups, kAdjThreads, mask_bytes + (size_t)cap * per_row, s>>>(
+    adjoint_band_staged_kernel<<<a.y.l_count * groups, kAdjThreads, list_bytes + (size_t)cap * per_row, s>>>(
         a.g.n, a.g.n_range, tiles, groups, half_w, cap, L.ne, tabs, L.row_bytes, grad_image, grad_band);
   } else {
     adjoint_band_kernel<<<a.y.l_count * tiles, kAdjThreads, mask_bytes, s>>>(a.g.n, a.g.n_range, tiles, tabs,
