@@ -41,6 +41,8 @@ EDGE = [
     ("k1", 64, 64, 3, 0.5, 1.2, 1, 2),
     ("w_equals_n", 96, 64, 4, 0.5, 1.0, 40, 96),
     ("many_rows", 128, 64, 300, 0.4, 1.4, 12, 32),
+    # more than 2048 range rows: the staged form's row list takes 32-bit entries
+    ("rows_over_2048", 64, 64, 2100, 0.4, 1.4, 8, 16),
     # a window of the whole rotation: one staged gradient row would not fit the LDS budget, so
     # the global-gather form runs
     ("wide_window_gather", 4096, 64, 3, 0.6, 1.0, 50, 4096),
