@@ -203,8 +203,8 @@ __device__ __forceinline__ void store_c2(void* base, int64_t idx, float2 v0, flo
   } else if constexpr (DT == 1) {
     const __half2 h0 = __floats2half2_rn(v0.x, v0.y), h1 = __floats2half2_rn(v1.x, v1.y);
     uint2 u;
-    u.x = *reinterpret_cast<const uint32_t*>(&h0);
-    u.y = *reinterpret_cast<const uint32_t*>(&h1);
+    __builtin_memcpy(&u.x, &h0, sizeof(uint32_t));
+    __builtin_memcpy(&u.y, &h1, sizeof(uint32_t));
     reinterpret_cast<uint2*>(base)[idx >> 1] = u;
   } else {
     uint2 u;
