@@ -77,6 +77,31 @@ def test_range_compress_shapes(n, m, l):
     assert rel_l2(rc2.pulses(n).cpu().numpy().T, oracle.range_compress(raw, None, l)) <= 1e-5
 
 
+@pytest.mark.parametrize("name", ["rotation", "precision"])
+@pytest.mark.parametrize("dtype", ["c64", "f16"])
+def test_range_compress_full_size(name, dtype):
+    """The rotation (3600 x 512) and precision (7200 x 1024) workloads at full size: every band
+    element against the FP64 oracle's windowed FFT (whole-pulse loads and paired band stores),
+    and the halo columns as exact copies of the wrapped pulses."""
+    rs = need_gpu()
+    w = getattr(synth, name)()
+    x = synth.make_inputs(w)
+    g = w.geometry
+    n, halo = g.n_pulses, w.sparse.window // 2
+    scale = 2.0 ** -6 if dtype == "f16" else 1.0
+    log(f"range_compress full size {name} {dtype}")
+    rc = rs.range_compress(g, to_dev(x.raw), to_dev(x.window), x.l_lo, x.l_count, halo=halo, dtype=dtype,
+                           scale=scale)
+    torch.cuda.synchronize()
+    got = rc.pulses(n).cpu().numpy().T                                   # [N, l_count]
+    ref = oracle.range_compress(x.raw, x.window, g.n_fft)[:, x.l_lo:x.l_lo + x.l_count]
+    tol = 1e-5 if dtype == "c64" else 2e-3
+    assert rel_l2(got, ref) <= tol
+    assert np.abs(got - ref).max() <= 10 * tol * np.abs(ref).max()
+    d = rc.data.cpu()
+    assert torch.equal(d[:, :halo], d[:, n:n + halo]) and torch.equal(d[:, n + halo:], d[:, halo:2 * halo])
+
+
 def test_range_compress_mixed_f16():
     """Mixed-radix path with FP16 storage and a power-of-two scale."""
     rs = need_gpu()
