@@ -23,6 +23,7 @@ namespace rosar {
 namespace {
 
 constexpr int kCartThreads = 256;
+constexpr int kCartU = 4;   // taps whose sample gathers are issued together
 constexpr int kCartTableMax = 4096;   // widest window whose (cos, sin) table goes to LDS (64 KB)
 
 template <int DT, int WDT, int INTERP, bool POLAR>
@@ -61,44 +62,71 @@ __global__ __launch_bounds__(kCartThreads) void sparse_cartesian_kernel(Geo g, V
     double se, ce;
     sincos(phi - (g.phi0 + nc * g.step), &se, &ce);
     const char* yd = static_cast<const char*>(y.data);
-    for (int t = 0; t < k; ++t) {
-      const int o = offsets[(int64_t)row * k + t];
-      if (o < -half_w || o >= half_w) continue;   // outside the window: no contribution
-      const float2 w = load_w<WDT>(weights, (int64_t)row * k + t);
-      const int nn = nc + o;
-      double cd;
-      if (use_table) {
-        const double2 cso = s_cs[o + half_w];
-        cd = fma(ce, cso.x, se * cso.y);
-      } else {
-        cd = cos(phi - (g.phi0 + nn * g.step));
-      }
-      double u = g.beta * sqrt(c1 - c2 * cd);
-      if constexpr (INTERP == ROSAR_NEAREST) {
-        if (near_bin_tie(u + 0.5, 1e-9)) u = g.beta * sqrt(c1 - c2 * cos(phi - (g.phi0 + nn * g.step)));
-      }
-      int n = nn % g.n;
-      n += n < 0 ? g.n : 0;
-      float2 s = make_float2(0.f, 0.f);
-      if constexpr (INTERP == ROSAR_NEAREST) {
-        const int l = (int)floor(u + 0.5) - y.l_lo;
-        if (l >= 0 && l < y.l_count) s = load_c<DT>(yd, (int64_t)l * y.ld + y.halo + n);
-      } else {
-        const double fl = floor(u);
-        const float f = (float)(u - fl);
-        const int l = (int)fl - y.l_lo;
-        if (l >= 0 && l < y.l_count) {
-          const float2 v = load_c<DT>(yd, (int64_t)l * y.ld + y.halo + n);
-          s.x += (1.f - f) * v.x;
-          s.y += (1.f - f) * v.y;
+    // Taps in groups of kCartU: the group's geometry and sample gathers first, so that its
+    // loads are in flight together, then its multiply-adds in tap order (the sum order of
+    // one tap at a time).
+    for (int t0 = 0; t0 < k; t0 += kCartU) {
+      float2 wv[kCartU], v0[kCartU], v1[kCartU];
+      float fr[kCartU];
+      bool use[kCartU], in0[kCartU], in1[kCartU];
+#pragma unroll
+      for (int q = 0; q < kCartU; ++q) {
+        const int t = t0 + q;
+        use[q] = in0[q] = in1[q] = false;
+        wv[q] = v0[q] = v1[q] = make_float2(0.f, 0.f);
+        fr[q] = 0.f;
+        if (t >= k) continue;
+        const int o = offsets[(int64_t)row * k + t];
+        if (o < -half_w || o >= half_w) continue;   // outside the window: no contribution
+        use[q] = true;
+        wv[q] = load_w<WDT>(weights, (int64_t)row * k + t);
+        const int nn = nc + o;
+        double cd;
+        if (use_table) {
+          const double2 cso = s_cs[o + half_w];
+          cd = fma(ce, cso.x, se * cso.y);
+        } else {
+          cd = cos(phi - (g.phi0 + nn * g.step));
         }
-        if (l + 1 >= 0 && l + 1 < y.l_count) {
-          const float2 v = load_c<DT>(yd, (int64_t)(l + 1) * y.ld + y.halo + n);
-          s.x += f * v.x;
-          s.y += f * v.y;
+        double u = g.beta * sqrt(c1 - c2 * cd);
+        if constexpr (INTERP == ROSAR_NEAREST) {
+          if (near_bin_tie(u + 0.5, 1e-9)) u = g.beta * sqrt(c1 - c2 * cos(phi - (g.phi0 + nn * g.step)));
+        }
+        int n = nn % g.n;
+        n += n < 0 ? g.n : 0;
+        if constexpr (INTERP == ROSAR_NEAREST) {
+          const int l = (int)floor(u + 0.5) - y.l_lo;
+          in0[q] = l >= 0 && l < y.l_count;
+          if (in0[q]) v0[q] = load_c<DT>(yd, (int64_t)l * y.ld + y.halo + n);
+        } else {
+          const double fl = floor(u);
+          fr[q] = (float)(u - fl);
+          const int l = (int)fl - y.l_lo;
+          in0[q] = l >= 0 && l < y.l_count;
+          in1[q] = l + 1 >= 0 && l + 1 < y.l_count;
+          if (in0[q]) v0[q] = load_c<DT>(yd, (int64_t)l * y.ld + y.halo + n);
+          if (in1[q]) v1[q] = load_c<DT>(yd, (int64_t)(l + 1) * y.ld + y.halo + n);
         }
       }
-      cmac_conj(acc, w, s);
+#pragma unroll
+      for (int q = 0; q < kCartU; ++q) {
+        if (!use[q]) continue;
+        float2 s = make_float2(0.f, 0.f);
+        if constexpr (INTERP == ROSAR_NEAREST) {
+          if (in0[q]) s = v0[q];
+        } else {
+          const float f = fr[q];
+          if (in0[q]) {
+            s.x += (1.f - f) * v0[q].x;
+            s.y += (1.f - f) * v0[q].y;
+          }
+          if (in1[q]) {
+            s.x += f * v1[q].x;
+            s.y += f * v1[q].y;
+          }
+        }
+        cmac_conj(acc, wv[q], s);
+      }
     }
   }
   image[(size_t)iy * c.nx + ix] = make_float2(acc.x * y.inv_scale, acc.y * y.inv_scale);
