@@ -24,6 +24,9 @@ namespace {
 
 constexpr int kCartThreads = 256;
 constexpr int kCartU = 4;   // taps whose sample gathers are issued together
+// back-projection: the per-pulse (cos, sin) table in LDS up to this size (N <= 3840), else
+// cos(phi - theta_n) per pulse and pixel
+constexpr size_t kCartPulseTableBytes = 60 * 1024;
 constexpr int kCartTableMax = 4096;   // widest window whose (cos, sin) table goes to LDS (64 KB)
 
 template <int DT, int WDT, int INTERP, bool POLAR>
@@ -141,9 +144,18 @@ __global__ __launch_bounds__(kCartThreads) void sparse_cartesian_kernel(Geo g, V
 template <int DT, int INTERP>
 __global__ __launch_bounds__(kCartThreads) void bp_cartesian_kernel(Geo g, View y, CartGrid c,
                                                                     const double* __restrict__ angles,
-                                                                    float2* __restrict__ image) {
+                                                                    int use_table, float2* __restrict__ image) {
   __shared__ double s_dmax[kCartThreads / kWave];
+  // with use_table: (cos, sin) of every pulse angle theta_n (given, or phi0 + n phi_Delta), so
+  // that cos(phi - theta_n) = cos phi cos theta_n + sin phi sin theta_n costs two FMAs
+  extern __shared__ double2 s_pcs[];
   const double two_pi = 6.283185307179586476925286766559;
+  for (int n = threadIdx.x; use_table && n < g.n; n += kCartThreads) {
+    double sn, cs;
+    sincos(angles ? angles[n] : g.phi0 + n * g.step, &sn, &cs);
+    s_pcs[n] = make_double2(cs, sn);
+  }
+  if (use_table) __syncthreads();
   // largest deviation of the given pulse angles from the nominal ones (every thread takes part
   // before any leaves)
   double dmax = 0.0;
@@ -168,6 +180,8 @@ __global__ __launch_bounds__(kCartThreads) void bp_cartesian_kernel(Geo g, View 
   const double c2 = 2.0 * rt * g.radius;
   const char* yd = static_cast<const char*>(y.data);
   float2 acc = make_float2(0.f, 0.f);
+  double sphi = 0.0, cphi = 1.0;
+  if (use_table) sincos(phi, &sphi, &cphi);
   // target angle from pulse 0, reduced to [0, 2 pi): the span indices stay within about
   // [-N/2, 3N/2] for any phi0
   double rel = phi - g.phi0;
@@ -185,7 +199,13 @@ __global__ __launch_bounds__(kCartThreads) void bp_cartesian_kernel(Geo g, View 
   for (int m = m0; m <= m1; ++m) {
     int n = m % g.n;
     n += n < 0 ? g.n : 0;
-    const double cd = angles ? cos(phi - angles[n]) : cos(rel - m * g.step);
+    double cd;
+    if (use_table) {
+      const double2 t = s_pcs[n];
+      cd = fma(cphi, t.x, sphi * t.y);
+    } else {
+      cd = angles ? cos(phi - angles[n]) : cos(rel - m * g.step);
+    }
     const double v = rt * cd - g.radius;
     if (v <= 0.0) continue;   // outside the field of view (eqs. 4-5)
     const double rn = sqrt(c1 - c2 * cd);
@@ -224,10 +244,12 @@ template <int DT>
 hipError_t launch_bp_dt(const Geo& g, const View& y, const CartGrid& c, const double* angles, int32_t interp,
                         float2* image, hipStream_t s) {
   dim3 grid((c.nx + kCartThreads - 1) / kCartThreads, c.ny);
+  const int use_table = (size_t)g.n * sizeof(double2) <= kCartPulseTableBytes ? 1 : 0;
+  const size_t lds = use_table ? (size_t)g.n * sizeof(double2) : 0;
   if (interp == ROSAR_LINEAR)
-    bp_cartesian_kernel<DT, ROSAR_LINEAR><<<grid, kCartThreads, 0, s>>>(g, y, c, angles, image);
+    bp_cartesian_kernel<DT, ROSAR_LINEAR><<<grid, kCartThreads, lds, s>>>(g, y, c, angles, use_table, image);
   else
-    bp_cartesian_kernel<DT, ROSAR_NEAREST><<<grid, kCartThreads, 0, s>>>(g, y, c, angles, image);
+    bp_cartesian_kernel<DT, ROSAR_NEAREST><<<grid, kCartThreads, lds, s>>>(g, y, c, angles, use_table, image);
   return hipGetLastError();
 }
 

@@ -186,6 +186,28 @@ def test_bp_cartesian_small(interp, jitter):
     assert rel_l2(img, ref) <= TOL
 
 
+@pytest.mark.parametrize("interp", ["nearest", "linear"])
+@pytest.mark.parametrize("jitter", [False, True])
+def test_bp_cartesian_pulses_past_the_lds_table(interp, jitter):
+    """N = 4000 pulses: more than the per-pulse (cos, sin) table holds in LDS, so every
+    cos(phi - theta_n) is evaluated directly; against the oracle."""
+    rs = need_gpu()
+    w = custom_workload("bp_cart_big_n", 91, 4000, 64, 6, 0.5, 1.5, 16, 32)
+    if jitter:
+        w = dataclasses.replace(w, scene=dataclasses.replace(w.scene, jitter_sigma_rad=np.deg2rad(0.05)))
+    x = synth.make_inputs(w)
+    g, grid = w.geometry, w.grid
+    r1 = grid.r0_m + (grid.n_range - 1) * grid.dr_m
+    c, xs, ys = lattice(17, 13, -r1 - 0.01234, -r1 * 0.9 + 0.00567, 2 * r1 / 16, 1.8 * r1 / 12)
+    rc = rs.range_compress(g, to_dev(x.raw), to_dev(x.window), x.l_lo, x.l_count, halo=w.sparse.window // 2)
+    log(f"bp cartesian N = 4000 {interp} jitter={jitter}")
+    img = rs.bp_cartesian(g, c, rc, angles=to_dev(x.angles) if jitter else None, interp=interp).cpu().numpy()
+    yb = oracle.range_compress(x.raw, x.window, g.n_fft)[:, x.l_lo:x.l_lo + x.l_count]
+    ref = oracle.bp_cartesian_at(yb, x.l_lo, g, xs, ys, pulse_angles=x.angles if jitter else None,
+                                 interp=interp).reshape(c.ny, c.nx)
+    assert rel_l2(img, ref) <= TOL
+
+
 def test_bp_cartesian_axis_matches_polar_bpa():
     """Targets on the positive x axis at the rows' radii are polar pixels of azimuth bin 0."""
     rs = need_gpu()
